@@ -1,0 +1,366 @@
+"""Seeded synthetic workloads shaped like the paper's test problems.
+
+Problem descriptions only: grids, parameters and exact cell averages of the
+initial data.  Nothing here computes any part of the ASE-DF method; both the
+CPU oracle and the GPU library consume what these generators return.
+
+Arrays use the state layout U[v, J, I] (v = conserved variable, J = row with
+ghosts, I = column with ghosts), float64, C-contiguous, with the row stride
+``grid.ld`` equal to the padded row length.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+BC_PERIODIC = 0
+BC_TRANSMISSIVE = 1
+BC_INFLOW_SLOT = 2
+
+
+@dataclasses.dataclass
+class Grid:
+    dim: int
+    nx: int
+    ny: int
+    ng: int
+    dx: float
+    dy: float
+    bc: Tuple[int, int, int, int] = (BC_TRANSMISSIVE,) * 4
+    y0: float = 0.0
+    inflow: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
+    slot_lo: float = 0.0
+    slot_hi: float = 0.0
+    ld: int = 0
+
+    def __post_init__(self):
+        if self.ld == 0:
+            self.ld = self.nx + 2 * self.ng
+        if self.dim == 1:
+            self.ny = 1
+
+    @property
+    def nvar(self) -> int:
+        return 3 if self.dim == 1 else 4
+
+    @property
+    def NX(self) -> int:
+        return self.nx + 2 * self.ng
+
+    @property
+    def NY(self) -> int:
+        return 1 if self.dim == 1 else self.ny + 2 * self.ng
+
+    def shape(self) -> Tuple[int, int, int]:
+        return (self.nvar, self.NY, self.ld)
+
+    def interior(self, a: np.ndarray) -> np.ndarray:
+        """View of the interior cells of a state-layout array."""
+        g = self.ng
+        if self.dim == 1:
+            return a[..., 0:1, g:g + self.nx]
+        return a[..., g:g + self.ny, g:g + self.nx]
+
+    def ncells(self) -> int:
+        return self.nx * (1 if self.dim == 1 else self.ny)
+
+
+@dataclasses.dataclass
+class Params:
+    order: int
+    gamma: float = 1.4
+    cfl: float = 0.5
+    sigma_thres: float = 2.0
+    eps: float = 1e-6
+    d_hi: float = 0.85
+    d_lo: float = 0.85
+    dt_cap: float = 0.0
+    positivity_fallback: int = 0
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    grid: Grid
+    params: Params
+    U: np.ndarray
+    nsteps: int
+    t_end: float = 0.0
+
+
+def ghosts_for(order: int) -> int:
+    return (order + 1) // 2 if order > 1 else 1
+
+
+def conservative(rho, u, v, p, gamma, dim):
+    """Conservative state (rho, rho u, [rho v], E) of primitive data."""
+    rho, u, v, p = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64) for a in (rho, u, v, p)))
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    if dim == 1:
+        return np.stack([rho, rho * u, E])
+    return np.stack([rho, rho * u, rho * v, E])
+
+
+def empty_state(grid: Grid) -> np.ndarray:
+    return np.zeros(grid.shape(), dtype=np.float64)
+
+
+def empty_sigma(grid: Grid) -> np.ndarray:
+    return np.zeros((grid.NY, grid.ld), dtype=np.float64)
+
+
+def _fill_interior(grid: Grid, U: np.ndarray, W: np.ndarray) -> None:
+    grid.interior(U)[...] = W.reshape(grid.interior(U).shape)
+
+
+# --------------------------------------------------------------------------
+# 1D problems
+# --------------------------------------------------------------------------
+
+def riemann_1d(n: int, left, right, order: int, x_split: float = 0.5, gamma: float = 1.4,
+               cfl: float = 0.5, name: str = "riemann1d", nsteps: int = 0, t_end: float = 0.0,
+               xlo: float = 0.0, xhi: float = 1.0) -> Workload:
+    """Two-state Riemann data (rho, u, p) on [xlo, xhi]; exact averages."""
+    dx = (xhi - xlo) / n
+    g = Grid(dim=1, nx=n, ny=1, ng=ghosts_for(order), dx=dx, dy=dx, bc=(BC_TRANSMISSIVE,) * 4)
+    xl = xlo + np.arange(n) * dx
+    xr = xl + dx
+    frac_left = np.clip((x_split - xl) / dx, 0.0, 1.0)
+    WL = conservative(left[0], left[1], 0.0, left[2], gamma, 1)
+    WR = conservative(right[0], right[1], 0.0, right[2], gamma, 1)
+    W = frac_left[None, :] * WL[:, None] + (1.0 - frac_left[None, :]) * WR[:, None]
+    U = empty_state(g)
+    _fill_interior(g, U, W)
+    return Workload(name, g, Params(order=order, gamma=gamma, cfl=cfl), U, nsteps, t_end)
+
+
+def sod(n: int = 200, order: int = 5) -> Workload:
+    """Sod shock tube: (1,0,1) | (0.125,0,0.1) at x=0.5, gamma 1.4, t=0.2."""
+    return riemann_1d(n, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), order, 0.5, 1.4, 0.5, "sod", 100000, 0.2)
+
+
+def density_wave_1d(n: int, order: int, seed: int = -1, amp: float = 1e-3, cfl: float = 0.5,
+                    t_end: float = 2.0) -> Workload:
+    """rho = 1 + 0.2 sin(pi x), u = 1, p = 1, periodic on [0,2] (exact averages).
+
+    seed >= 0 adds a seeded uniform perturbation of the density averages.
+    """
+    L = 2.0
+    dx = L / n
+    g = Grid(dim=1, nx=n, ny=1, ng=ghosts_for(order), dx=dx, dy=dx, bc=(BC_PERIODIC,) * 4)
+    xl = np.arange(n) * dx
+    xr = xl + dx
+    rho = 1.0 + 0.2 * (np.cos(math.pi * xl) - np.cos(math.pi * xr)) / (math.pi * dx)
+    if seed >= 0:
+        rng = np.random.default_rng(seed)
+        rho = rho + rng.uniform(-amp, amp, size=n)
+    gamma = 1.4
+    # u = 1 and p = 1 are constant, so rho u = rho and E = p/(gamma-1) + rho/2.
+    W = np.stack([rho, rho * 1.0, 1.0 / (gamma - 1.0) + 0.5 * rho])
+    U = empty_state(g)
+    _fill_interior(g, U, W)
+    return Workload("density_wave_1d", g, Params(order=order, gamma=gamma, cfl=cfl), U, 10 ** 9, t_end)
+
+
+def density_wave_exact_1d(n: int, t: float) -> np.ndarray:
+    """Exact cell averages of rho at time t for the 1D density wave."""
+    dx = 2.0 / n
+    xl = np.arange(n) * dx
+    xr = xl + dx
+    return 1.0 + 0.2 * (np.cos(math.pi * (xl - t)) - np.cos(math.pi * (xr - t))) / (math.pi * dx)
+
+
+# --------------------------------------------------------------------------
+# 2D problems
+# --------------------------------------------------------------------------
+
+def _avg_sin(lo, hi):
+    return (np.cos(math.pi * lo) - np.cos(math.pi * hi)) / (math.pi * (hi - lo))
+
+
+def density_wave_2d(n: int, order: int, seed: int = -1, amp: float = 1e-3, cfl: float = 0.5) -> Workload:
+    """rho = 1 + 0.2 sin(pi x) sin(pi y), u = v = 1, p = 1 on [0,2]^2, periodic."""
+    L = 2.0
+    dx = L / n
+    g = Grid(dim=2, nx=n, ny=n, ng=ghosts_for(order), dx=dx, dy=dx, bc=(BC_PERIODIC,) * 4)
+    e = np.arange(n + 1) * dx
+    sx = _avg_sin(e[:-1], e[1:])
+    rho = 1.0 + 0.2 * np.outer(sx, sx)          # [j, i]
+    if seed >= 0:
+        rng = np.random.default_rng(seed)
+        rho = rho + rng.uniform(-amp, amp, size=rho.shape)
+    gamma = 1.4
+    W = np.stack([rho, rho, rho, 1.0 / (gamma - 1.0) + rho])   # u = v = 1, p = 1
+    U = empty_state(g)
+    _fill_interior(g, U, W)
+    return Workload("density_wave_2d", g, Params(order=order, gamma=gamma, cfl=cfl), U, 10 ** 9, 0.0)
+
+
+# Configuration 3 of the paper's 2D Riemann tests, quadrant order NE, NW, SW, SE.
+CONFIG3_STATES = (
+    (1.5, 0.0, 0.0, 1.5),          # NE: x >= 0.7, y >= 0.7
+    (0.5323, 1.206, 0.0, 0.3),     # NW: x <  0.7, y >= 0.7
+    (0.138, 1.206, 1.206, 0.129),  # SW: x <  0.7, y <  0.7
+    (0.5323, 0.0, 1.206, 0.3),     # SE: x >= 0.7, y <  0.7
+)
+
+
+def quadrant_states(seed: int) -> Tuple[Tuple[float, float, float, float], ...]:
+    """Per-seed quadrant states (NE, NW, SW, SE): rho in [0.1,1.5], |u|,|v| <= 1.2,
+    p in [0.03,1.5]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(4):
+        rho = rng.uniform(0.1, 1.5)
+        u = rng.uniform(-1.2, 1.2)
+        v = rng.uniform(-1.2, 1.2)
+        p = rng.uniform(0.03, 1.5)
+        out.append((rho, u, v, p))
+    return tuple(out)
+
+
+def four_quadrant(n: int = 1024, order: int = 9, seed: int = 0, nsteps: int = 200, cfl: float = 0.4,
+                  states=None, split=(0.7, 0.7), ny: int = 0) -> Workload:
+    """2D four-quadrant Riemann problem on [0,1]^2 with area-fraction cut cells."""
+    nyy = ny if ny else n
+    dx = 1.0 / n
+    dy = 1.0 / nyy
+    gamma = 1.4
+    g = Grid(dim=2, nx=n, ny=nyy, ng=ghosts_for(order), dx=dx, dy=dy, bc=(BC_TRANSMISSIVE,) * 4)
+    if states is None:
+        states = quadrant_states(seed)
+    ex = np.arange(n) * dx
+    ey = np.arange(nyy) * dy
+    fx = np.clip((split[0] - ex) / dx, 0.0, 1.0)     # fraction left of the split
+    fy = np.clip((split[1] - ey) / dy, 0.0, 1.0)     # fraction below the split
+    Q = [conservative(s[0], s[1], s[2], s[3], gamma, 2) for s in states]
+    NE, NW, SW, SE = Q
+    FX = fx[None, None, :]
+    FY = fy[None, :, None]
+    W = (FX * FY * SW[:, None, None] + (1 - FX) * FY * SE[:, None, None]
+         + FX * (1 - FY) * NW[:, None, None] + (1 - FX) * (1 - FY) * NE[:, None, None])
+    U = empty_state(g)
+    _fill_interior(g, U, W)
+    return Workload(f"four_quadrant_{n}x{nyy}_r{order}_seed{seed}", g,
+                    Params(order=order, gamma=gamma, cfl=cfl), U, nsteps, 0.0)
+
+
+def jet(nx: int = 1600, ny: int = 800, order: int = 7, u_jet: float = 7400.0, nsteps: int = 500,
+        cfl: float = 0.25, positivity_fallback: int = 1) -> Workload:
+    """High-Mach jet on [0,1] x [-0.25,0.25], gamma 5/3: ambient (0.5,0,0,0.4127),
+    inflow (5, u_jet, 0, 0.4127) through |y| < 0.05 at x = 0, outflow elsewhere."""
+    gamma = 5.0 / 3.0
+    dx = 1.0 / nx
+    dy = 0.5 / ny
+    inflow = conservative(5.0, u_jet, 0.0, 0.4127, gamma, 2)
+    g = Grid(dim=2, nx=nx, ny=ny, ng=ghosts_for(order), dx=dx, dy=dy,
+             bc=(BC_INFLOW_SLOT, BC_TRANSMISSIVE, BC_TRANSMISSIVE, BC_TRANSMISSIVE), y0=-0.25,
+             inflow=tuple(float(x) for x in inflow), slot_lo=-0.05, slot_hi=0.05)
+    amb = conservative(0.5, 0.0, 0.0, 0.4127, gamma, 2)
+    W = np.broadcast_to(amb[:, None, None], (4, ny, nx)).copy()
+    U = empty_state(g)
+    _fill_interior(g, U, W)
+    return Workload(f"jet_{nx}x{ny}_r{order}", g,
+                    Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=positivity_fallback),
+                    U, nsteps, 0.0)
+
+
+# --------------------------------------------------------------------------
+# Batched 1D instances
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Batch:
+    ncells: np.ndarray        # int32 [ninst]
+    offsets: np.ndarray       # int64 [ninst]: first stored cell (ghosts incl.)
+    dx: np.ndarray            # float64 [ninst]
+    ng: int
+    U: np.ndarray             # float64 [3, total]
+    params: Params
+    bc: int
+    nsteps: int
+
+    @property
+    def ninst(self) -> int:
+        return int(self.ncells.shape[0])
+
+    @property
+    def total(self) -> int:
+        return int(self.U.shape[1])
+
+    def instance(self, k: int) -> np.ndarray:
+        o = int(self.offsets[k])
+        return self.U[:, o:o + int(self.ncells[k]) + 2 * self.ng]
+
+
+def _pack(ncells: Sequence[int], ng: int) -> Tuple[np.ndarray, np.ndarray, int]:
+    ncells = np.asarray(ncells, dtype=np.int32)
+    sizes = ncells.astype(np.int64) + 2 * ng
+    offsets = np.zeros(len(ncells), dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)[:-1]
+    return ncells, offsets, int(sizes.sum())
+
+
+def batched_riemann(ninst: int = 256, nmin: int = 64, nmax: int = 4096, order: int = 9, seed: int = 0,
+                    nsteps: int = 100, cfl: float = 0.5) -> Batch:
+    """Independent 1D Riemann problems on [0,1] split at 0.5, transmissive:
+    rho in [0.1,2], |u| <= 2, p in [0.05,2] per side; N uniform in [nmin, nmax]."""
+    rng = np.random.default_rng(seed)
+    n = rng.integers(nmin, nmax + 1, size=ninst)
+    ng = ghosts_for(order)
+    ncells, offsets, total = _pack(n, ng)
+    gamma = 1.4
+    U = np.zeros((3, total), dtype=np.float64)
+    dx = 1.0 / ncells.astype(np.float64)
+    for k in range(ninst):
+        rl, rr = rng.uniform(0.1, 2.0, size=2)
+        ul, ur = rng.uniform(-2.0, 2.0, size=2)
+        pl, pr = rng.uniform(0.05, 2.0, size=2)
+        N = int(ncells[k])
+        xl = np.arange(N) * dx[k]
+        frac = np.clip((0.5 - xl) / dx[k], 0.0, 1.0)
+        WL = conservative(rl, ul, 0.0, pl, gamma, 1)
+        WR = conservative(rr, ur, 0.0, pr, gamma, 1)
+        W = frac[None, :] * WL[:, None] + (1 - frac[None, :]) * WR[:, None]
+        o = int(offsets[k])
+        U[:, o + ng:o + ng + N] = W
+    return Batch(ncells, offsets, dx, ng, U, Params(order=order, gamma=gamma, cfl=cfl), BC_TRANSMISSIVE, nsteps)
+
+
+def batched_smooth(ninst: int = 16, nmin: int = 64, nmax: int = 512, order: int = 9, seed: int = 1,
+                   nsteps: int = 20, cfl: float = 0.5) -> Batch:
+    """Smooth periodic 1D instances: rho = 1 + 0.2 sin(2 pi x + phi),
+    u = 0.5 + 0.1 cos(2 pi x), p = 1 + 0.1 sin(2 pi x + psi) (point values at
+    five Gauss-Legendre nodes per cell averaged, i.e. 9th-order cell averages)."""
+    rng = np.random.default_rng(seed)
+    n = rng.integers(nmin, nmax + 1, size=ninst)
+    ng = ghosts_for(order)
+    ncells, offsets, total = _pack(n, ng)
+    gamma = 1.4
+    U = np.zeros((3, total), dtype=np.float64)
+    dx = 1.0 / ncells.astype(np.float64)
+    xg, wg = np.polynomial.legendre.leggauss(5)
+    for k in range(ninst):
+        phi, psi = rng.uniform(0, 2 * math.pi, size=2)
+        N = int(ncells[k])
+        xc = (np.arange(N) + 0.5) * dx[k]
+        acc = np.zeros((3, N))
+        for xq, wq in zip(xg, wg):
+            x = xc + 0.5 * dx[k] * xq
+            rho = 1 + 0.2 * np.sin(2 * math.pi * x + phi)
+            u = 0.5 + 0.1 * np.cos(2 * math.pi * x)
+            p = 1 + 0.1 * np.sin(2 * math.pi * x + psi)
+            acc += 0.5 * wq * conservative(rho, u, 0.0, p, gamma, 1)
+        o = int(offsets[k])
+        U[:, o + ng:o + ng + N] = acc
+    return Batch(ncells, offsets, dx, ng, U, Params(order=order, gamma=gamma, cfl=cfl), BC_PERIODIC, nsteps)
+
+
+def instance_grid(batch: Batch, k: int) -> Grid:
+    """The single-instance 1D grid of instance k of a batch."""
+    N = int(batch.ncells[k])
+    return Grid(dim=1, nx=N, ny=1, ng=batch.ng, dx=float(batch.dx[k]), dy=float(batch.dx[k]),
+                bc=(batch.bc,) * 4)
