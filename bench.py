@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Throughput of the 9th-order 2D ASE-DF step on one MI355X.
+
+Workload (default): 2D four-quadrant Riemann problem, 1024 x 1024 cells on
+[0,1]^2, order 9, gamma 1.4, CFL 0.4, transmissive boundaries, quadrant
+states drawn with seed 0 (rho in [0.1,1.5], |u|,|v| <= 1.2, p in [0.03,1.5]).
+A step is one full SSP-RK3 step of the whole grid (boundary fill, dt, three
+stages of reconstruction, DF strengths, LF flux and update) with the state
+resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--workload quad1024]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-updates/s, 9th-order 2D ASE step (FP64) + % HBM roofline; adjoint/fwd ratio"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+
+
+def alg_flops_per_cell_sweep(order: int, dim: int) -> float:
+    """Algorithmic FP64 operations per interior cell for one direction of one
+    stage on the top linear branch (every operation of the method counted once;
+    an FMA counts 2, a divide or square root 1).
+
+    2D, r = 2R+1, G = R Gauss points:
+      normal reconstruction   : DF sums (r-2 + ... adds) + 2 points x 4 vars x (2r-1)
+      tangential (two sides)  : 2 x (DF sums + G points x 4 vars x (2r-1))
+      per Gauss point         : primitives 2 x 12, strength 14, LF flux 33,
+                                quadrature 8, strength sum 1   -> 80
+      face strength mean      : 1
+      flux difference         : 4 vars x 2
+    """
+    R = (order - 1) // 2
+    sums = {1: 1, 2: 3, 3: 8, 4: 15}[R]
+    if dim == 1:
+        normal = sums + 2 * 3 * (2 * order - 1)
+        point = 2 * 9 + 9 + 26
+        return normal + point + 3 * 2
+    G = R
+    normal = sums + 2 * 4 * (2 * order - 1)
+    tang = 2 * (sums + G * 4 * (2 * order - 1))
+    return normal + tang + G * 80 + 1 + 8
+
+
+def alg_bytes_per_cell(kernel: str) -> float:
+    """Algorithmic HBM bytes per interior cell of one launch (FP64 words):
+    x sweep reads the stage state (4) and both strength planes (2), writes the
+    new x strengths (1) and the x residual (4); y sweep reads the stage state
+    (4), both strength planes (2), the x residual (4) and the step-start state
+    (4, stages 2-3), writes the stage output (4) and the new y strengths (1)."""
+    return {"sweep_x": 11 * 8.0, "sweep_y": (19 * 8.0 * 2 + 15 * 8.0) / 3.0}[kernel]
+
+
+def make_workload(name):
+    from paper_2410_05489_amd import workloads as WL
+    if name == "quad1024":
+        return WL.four_quadrant(1024, 9, seed=0, nsteps=200)
+    if name == "quad4096":
+        return WL.four_quadrant(4096, 9, seed=0, nsteps=200)
+    if name == "jet":
+        return WL.jet(1600, 800, 7, nsteps=500)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, seconds_hint=True):
+    """The oracle (single thread, as written) on one step of the same grid."""
+    from oracle import oracle as O
+    U = w.U.copy()
+    sx, sy = O.sigma_init(w.grid, w.params, U)
+    t0 = time.perf_counter()
+    O.step(w.grid, w.params, U, sx, sy, 0.0, 1)
+    el = time.perf_counter() - t0
+    n = w.grid.ncells()
+    return {"value": n / el / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 step of {w.name} ({n} cells) from its initial state, single-threaded C oracle, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="quad1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU domain decomposition is a design note, not implemented)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2410_05489_amd import ase
+
+    ase.lib()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    w = make_workload(args.workload)
+    g, p = w.grid, w.params
+    sim = ase.Simulation(g, p, w.U, device="cuda")
+    torch.cuda.synchronize()
+    if args.warmup:
+        sim.run(args.warmup)
+    torch.cuda.synchronize()
+
+    ase.profile_enable(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    sim.run(args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    kern = {k: ase.profile_read(k) for k in ("sweep_x", "sweep_y", "stage_1d", "bc", "cfl")}
+    ase.profile_enable(False)
+    U = sim.U.cpu().numpy()
+    finite = bool(torch.isfinite(sim.U).all().item())
+
+    ncell = g.ncells()
+    value = ncell * args.steps / (ms / 1e3) / 1e6
+    dom = max(("sweep_x", "sweep_y"), key=lambda k: kern[k][0])
+    tot, nl = kern[dom]
+    avg_s = tot / max(nl, 1) / 1e3
+    flops = alg_flops_per_cell_sweep(p.order, g.dim) + (4 + 56.0 / 3.0 if dom == "sweep_y" else 0.0)
+    achieved_tf = flops * ncell / avg_s / 1e12
+    bytes_launch = alg_bytes_per_cell(dom) * ncell
+    roof = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved_tf / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": f"k_sweep2d ({dom}), order {p.order}",
+            "avg_launch_ms": round(avg_s * 1e3, 4), "launches": nl,
+            "alg_flops_per_launch": flops * ncell, "alg_bytes_per_launch": bytes_launch,
+            "hbm_frac_alg": round(bytes_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+            "step_alg_bytes_per_cell": 352,
+            "step_hbm_frac_alg": round(value * 1e6 * 352 / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern.items() if v[1]}}
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Mcell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": w.name, "order": p.order, "nx": g.nx, "ny": g.ny,
+                                           "gamma": p.gamma, "cfl": p.cfl, "sigma_thres": p.sigma_thres},
+           "finite": finite, "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * ase.h -- C ABI of the MI355X (gfx950) ASE-DF library (libase.so).
+ *
+ * Adaptive-stencil-extension reconstruction driven by the discontinuity
+ * feedback factor (ASE-DF), Lax-Friedrichs interface flux and SSP-RK3
+ * update for the compressible Euler equations on uniform 1D/2D grids, after
+ * Zhang, Zhao, Ji & Xu, "An Adaptive Reconstruction Method for Arbitrary
+ * High-Order Accuracy Using Discontinuity Feedback" (arXiv 2410.05489).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers to float64 (int8 for levels)
+ *    owned by the caller; the library never allocates, frees or keeps them.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    asynchronous on that stream; results are ready once the caller
+ *    synchronises the stream.  Scalars such as dt and t live in device
+ *    memory so whole steps can run without a host round trip.
+ *  - Return value: ASE_OK (0) or a negative ASE_ERR_* code; the message of
+ *    the last failure on the calling host thread is ase_last_error().
+ *    Argument errors are detected before anything is launched.
+ *  - State layout (structure of arrays with ghost cells):
+ *      U[v*NY*ld + J*ld + I]   v = conserved variable, J row, I column
+ *    NX = nx + 2 ng columns, NY = ny + 2 ng rows (NY = 1 in 1D), row stride
+ *    ld >= NX; interior cell (i,j) is at I = i+ng, J = j+ng.  Variables are
+ *    (rho, rho u, E) in 1D and (rho, rho u, rho v, rho E) in 2D.
+ *  - Discontinuity strengths (the DF state) use one plane of the same shape:
+ *      sx[J*ld + I]  strength of the x-face between cells (I,J), (I+1,J)
+ *      sy[J*ld + I]  strength of the y-face between cells (I,J), (I,J+1)
+ *    The "flux faces" are x-faces i+1/2, i in [-1, nx-1], of interior rows
+ *    and y-faces j+1/2, j in [-1, ny-1], of interior columns.  A stage
+ *    writes the strengths of the flux faces; ase_bc_fill derives all other
+ *    stored faces from them (periodic wrap) or from the two adjacent
+ *    ghost-filled cell averages (first-order strength).
+ *  - Face arrays (compact numbering): x-face i+1/2 of row j has index
+ *    j*(nx+1) + (i+1); y-face j+1/2 of column i has index (j+1)*nx + i;
+ *    in 1D face i+1/2 has index i+1.  nfaces = (nx+1)*ny resp. nx*(ny+1).
+ *    Gauss-point states wl/wr are [v][k][face] with k over the G Gauss
+ *    points of the face (G = (order-1)/2 in 2D, 1 in 1D), ordered by
+ *    increasing coordinate; face fluxes F are [v][face] and already hold
+ *    the quadrature sum  sum_k eta_k F_k  (weights normalised to 1).
+ */
+#ifndef ASE_H
+#define ASE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ASE_OK = 0,
+    ASE_ERR_ARG = -1,       /* bad pointer, size, direction or stage     */
+    ASE_ERR_ORDER = -2,     /* order not in {3,5,7,9}                    */
+    ASE_ERR_GHOST = -3,     /* ng < (order+1)/2                          */
+    ASE_ERR_ALIGN = -4,     /* device pointer not 8-byte aligned         */
+    ASE_ERR_HIP = -5,       /* a HIP runtime call failed                 */
+    ASE_ERR_WORKSPACE = -6  /* workspace missing or too small            */
+};
+
+enum { ASE_BC_PERIODIC = 0, ASE_BC_TRANSMISSIVE = 1, ASE_BC_INFLOW_SLOT = 2 };
+
+/* Flags of ase_params_t. */
+enum {
+    /* A Gauss-point state with rho <= 0 or p <= 0 is replaced by the
+     * average of its own cell for the flux (its strength is +inf anyway). */
+    ASE_FLAG_POSITIVITY_FALLBACK = 1
+};
+
+/* Grid and boundary description (the problem statement of Sec. 2.1 and
+ * the test set-ups of Sec. 4). */
+typedef struct {
+    int32_t dim;        /* 1 or 2                                           */
+    int32_t nx, ny;     /* interior cells; ny = 1 in 1D                     */
+    int32_t ng;         /* ghost layers per side, >= (order+1)/2            */
+    int32_t ld;         /* row stride in elements, >= nx + 2 ng             */
+    int32_t bc[4];      /* x-lo, x-hi, y-lo, y-hi: ASE_BC_*.  Periodic must
+                           pair on both sides; INFLOW_SLOT only in x.       */
+    double dx, dy;      /* cell sizes                                        */
+    double y0;          /* lower edge of the domain (slot test)              */
+    double inflow[4];   /* conservative state of INFLOW_SLOT ghost cells     */
+    double slot_lo, slot_hi;  /* INFLOW_SLOT applies to ghost cells of rows
+                           whose centre y lies in (slot_lo, slot_hi); other
+                           rows of that side are transmissive.              */
+} ase_grid_t;
+
+/* Method parameters. */
+typedef struct {
+    int32_t order;      /* nominal order r: 3, 5, 7 or 9 (Sec. 3.2-3.4)     */
+    int32_t flags;      /* ASE_FLAG_*                                        */
+    double gamma;       /* ratio of specific heats                           */
+    double cfl;         /* CFL number                                        */
+    double sigma_thres; /* DF threshold (Remark 1; 2.0 in the paper)         */
+    double eps;         /* WENO-Z epsilon (1e-6)                             */
+    double d_hi, d_lo;  /* WENO-AO linear-weight parameters (0.85, 0.85)     */
+    double dt_cap;      /* > 0: dt = min(CFL dt, dt_cap)                     */
+} ase_params_t;
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *ase_last_error(void);
+
+/* Library ABI version (increments on any signature change). */
+int ase_version(void);
+
+/* Ghost cells and derived strengths (boundary conditions of Sec. 4).
+ * Fills every ghost cell of U (x first on interior rows, then y on every
+ * column, so corners take the y rule applied to x-filled values), then
+ * every stored strength that is not a flux-face strength: periodic faces
+ * take the wrapped flux-face value, the others the first-order strength of
+ * their two cells.  U: state layout, in/out.  sx, sy: in/out (sy unused in
+ * 1D, may be NULL). */
+int ase_bc_fill(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy,
+                void *stream);
+
+/* Initial DF state: fills the ghosts of U, then sets every stored strength
+ * to the first-order strength of its two adjacent cell averages (the DF of
+ * Sec. 3.1 applied to piecewise-constant states).  U in/out, sx/sy out. */
+int ase_sigma_init(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy,
+                   void *stream);
+
+/* Time step: dt = CFL / max over interior cells of (|u|+c)/dx [+ (|v|+c)/dy]
+ * (CFL number of Sec. 4), capped by dt_cap, clipped so that t + dt <= t_end
+ * when t_end > 0, and 0 once t >= t_end.  U: state (interior read).
+ * t: device scalar (in).  dt: device scalar (out).  ws: device workspace of
+ * at least ase_workspace_bytes() bytes. */
+int ase_cfl_dt(const ase_grid_t *g, const ase_params_t *p, const double *U, const double *t,
+               double t_end, double *dt, void *ws, size_t ws_bytes, void *stream);
+
+/* ASE-DF reconstruction along direction dir (0 = x-faces, 1 = y-faces):
+ * normal reconstruction of every cell with the DF factors of the faces in
+ * its stencil, then (2D) tangential reconstruction of the face values to
+ * the Gauss points with the strengths of the perpendicular faces of the
+ * side cell's column (Sec. 3.1 Remark 2, Sec. 3.2-3.4, Algorithm 1).
+ * U, sx, sy: state with ghosts already filled (ase_bc_fill).
+ * wl, wr: out, [v][k][face], left/right (lower/upper) states.
+ * level: optional out, [ny][nx] int8 level of the normal reconstruction of
+ * each interior cell: 9/7/5 linear order used, 2 = WENO-Z-AO(5,3) with DF,
+ * 3 = DF-damped centred polynomial (order 3).  May be NULL. */
+int ase_reconstruct(const ase_grid_t *g, const ase_params_t *p, int dir, const double *U,
+                    const double *sx, const double *sy, double *wl, double *wr, int8_t *level,
+                    void *stream);
+
+/* Discontinuity strength of every flux face of direction dir (Sec. 3.1):
+ * per Gauss point |pl-pr|/pl + |pl-pr|/pr + (Ma_n^l-Ma_n^r)^2 +
+ * (Ma_t^l-Ma_t^r)^2 (+inf if a side has rho <= 0 or p <= 0), averaged over
+ * the face's Gauss points.  wl, wr: in, [v][k][face].  sigma: out, the
+ * strength plane (sx for dir 0, sy for dir 1); only flux faces written. */
+int ase_df_compute(const ase_grid_t *g, const ase_params_t *p, int dir, const double *wl,
+                   const double *wr, double *sigma, void *stream);
+
+/* Lax-Friedrichs flux with local maximal signal speed at every Gauss point
+ * (Sec. 2.3), summed with the Gauss weights (Sec. 2.1).  wl, wr: in.
+ * F: out, [v][face]. */
+int ase_flux(const ase_grid_t *g, const ase_params_t *p, int dir, const double *wl, const double *wr,
+             double *F, void *stream);
+
+/* One SSP-RK3 stage (Eq. SSP-RK3) on interior cells with
+ * L = -(F_{i+1/2}-F_{i-1/2})/dx - (G_{j+1/2}-G_{j-1/2})/dy:
+ *   stage 1: Uout = Un + dt L;  stage 2: Uout = 3/4 Un + 1/4 Us + 1/4 dt L;
+ *   stage 3: Uout = 1/3 Un + 2/3 Us + 2/3 dt L.
+ * dt: device scalar.  F, G: face fluxes [v][face] (G ignored in 1D).
+ * Un, Us: state layout, in.  Uout: interior written (may alias Un). */
+int ase_stage_update(const ase_grid_t *g, const ase_params_t *p, int stage, const double *dt,
+                     const double *Un, const double *Us, const double *F, const double *G,
+                     double *Uout, void *stream);
+
+/* Bytes of device workspace that ase_step / ase_cfl_dt need for grid g. */
+size_t ase_workspace_bytes(const ase_grid_t *g, const ase_params_t *p);
+
+/* nsteps SSP-RK3 steps of the whole method with lagged discontinuity
+ * feedback: each stage computes the strengths of its flux faces from its
+ * own Gauss-point states, and the next stage's DF factors use them.
+ * Per step: boundary fill, dt, then three stages of reconstruction, flux,
+ * quadrature and update, all on device.  Steps stop advancing once t >=
+ * t_end (t_end > 0); remaining launches are no-ops.
+ * U, sx, sy: the state (U interior + flux-face strengths), in/out; the DF
+ * state must come from ase_sigma_init or a previous ase_step.
+ * t: device scalar, in/out.  dt_hist: optional device array [nsteps] of
+ * the dt of each step (0 for skipped steps).  ws: device workspace of
+ * ws_bytes >= ase_workspace_bytes(g, p). */
+int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, double *t,
+             double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes, void *stream);
+
+/* Per-kernel timing of ase_step, for benchmarks and profiling (not for
+ * production runs).  While enabled, ase_step brackets every launch of its
+ * reconstruction/flux/update kernels with HIP events on the call's stream
+ * (pool of 8192 launches; further launches go unrecorded).
+ * ase_profile_enable(1) clears and enables recording, (0) disables it.
+ * ase_profile_read waits for the recorded events, then returns the summed
+ * duration in milliseconds and the number of launches of one kernel class
+ * (ASE_KCLASS_*); it does not clear the record. */
+enum { ASE_KCLASS_SWEEP_X = 0, ASE_KCLASS_SWEEP_Y = 1, ASE_KCLASS_STAGE_1D = 2, ASE_KCLASS_BC = 3,
+       ASE_KCLASS_CFL = 4, ASE_KCLASS_COUNT = 5 };
+int ase_profile_enable(int on);
+int ase_profile_read(int kernel_class, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASE_H */

@@ -1,0 +1,226 @@
+"""Python binding of libase (the C ABI declared in include/ase.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels of libase.so.  PyTorch provides device memory (float64 tensors on
+the ROCm device) and the current stream.  There is no CPU fallback: if the
+library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+from .workloads import Grid, Params
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libase.so")
+_LIB = None
+
+FLAG_POSITIVITY_FALLBACK = 1
+
+
+class AseGrid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("ng", C.c_int32),
+                ("ld", C.c_int32), ("bc", C.c_int32 * 4), ("dx", C.c_double), ("dy", C.c_double),
+                ("y0", C.c_double), ("inflow", C.c_double * 4), ("slot_lo", C.c_double),
+                ("slot_hi", C.c_double)]
+
+
+class AseParams(C.Structure):
+    _fields_ = [("order", C.c_int32), ("flags", C.c_int32), ("gamma", C.c_double), ("cfl", C.c_double),
+                ("sigma_thres", C.c_double), ("eps", C.c_double), ("d_hi", C.c_double), ("d_lo", C.c_double),
+                ("dt_cap", C.c_double)]
+
+
+EXPORTS = ("ase_last_error", "ase_version", "ase_bc_fill", "ase_sigma_init", "ase_cfl_dt", "ase_reconstruct",
+           "ase_df_compute", "ase_flux", "ase_stage_update", "ase_workspace_bytes", "ase_step",
+           "ase_profile_enable", "ase_profile_read")
+
+KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4}
+
+
+class AseError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libase.so (built in-tree by paper_2410_05489_amd.build)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise AseError(f"{LIB_PATH} is missing: build it with paper_2410_05489_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.c_void_p, C.c_int
+    L.ase_last_error.restype = C.c_char_p
+    L.ase_last_error.argtypes = []
+    L.ase_version.restype = C.c_int
+    L.ase_bc_fill.argtypes = [vp, vp, dp, dp, dp, vp]
+    L.ase_sigma_init.argtypes = [vp, vp, dp, dp, dp, vp]
+    L.ase_cfl_dt.argtypes = [vp, vp, dp, dp, C.c_double, dp, vp, C.c_size_t, vp]
+    L.ase_reconstruct.argtypes = [vp, vp, ip, dp, dp, dp, dp, dp, vp, vp]
+    L.ase_df_compute.argtypes = [vp, vp, ip, dp, dp, dp, vp]
+    L.ase_flux.argtypes = [vp, vp, ip, dp, dp, dp, vp]
+    L.ase_stage_update.argtypes = [vp, vp, ip, dp, dp, dp, dp, dp, dp, vp]
+    L.ase_workspace_bytes.restype = C.c_size_t
+    L.ase_workspace_bytes.argtypes = [vp, vp]
+    L.ase_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, C.c_int32, C.c_double, vp, C.c_size_t, vp]
+    L.ase_profile_enable.argtypes = [C.c_int]
+    L.ase_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    for name in EXPORTS:
+        if not hasattr(L, name):
+            raise AseError(f"libase.so lacks {name}")
+    _LIB = L
+    return L
+
+
+def c_grid(g: Grid) -> AseGrid:
+    s = AseGrid()
+    s.dim, s.nx, s.ny, s.ng, s.ld = g.dim, g.nx, g.ny, g.ng, g.ld
+    for k in range(4):
+        s.bc[k] = int(g.bc[k])
+        s.inflow[k] = float(g.inflow[k])
+    s.dx, s.dy, s.y0, s.slot_lo, s.slot_hi = g.dx, g.dy, g.y0, g.slot_lo, g.slot_hi
+    return s
+
+
+def c_params(p: Params) -> AseParams:
+    s = AseParams()
+    s.order = int(p.order)
+    s.flags = FLAG_POSITIVITY_FALLBACK if p.positivity_fallback else 0
+    s.gamma, s.cfl, s.sigma_thres, s.eps = p.gamma, p.cfl, p.sigma_thres, p.eps
+    s.d_hi, s.d_lo, s.dt_cap = p.d_hi, p.d_lo, p.dt_cap
+    return s
+
+
+def _stream(stream=None) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _p(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise AseError("device tensor expected")
+    if not t.is_contiguous():
+        raise AseError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().ase_last_error().decode()
+        raise AseError(f"{what} failed ({rc}): {msg}")
+
+
+def _gp(g, p):
+    return C.byref(c_grid(g)), C.byref(c_params(p))
+
+
+def ngauss(g: Grid, order: int) -> int:
+    return 1 if g.dim == 1 else max(1, (order - 1) // 2)
+
+
+def face_count(g: Grid, d: int) -> int:
+    if g.dim == 1:
+        return g.nx + 1
+    return (g.nx + 1) * g.ny if d == 0 else g.nx * (g.ny + 1)
+
+
+def bc_fill(g, p, U, sx, sy=None, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_bc_fill(G, P, _p(U), _p(sx), _p(sy), _stream(stream)), "ase_bc_fill")
+
+
+def sigma_init(g, p, U, sx, sy=None, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_sigma_init(G, P, _p(U), _p(sx), _p(sy), _stream(stream)), "ase_sigma_init")
+
+
+def workspace_bytes(g, p) -> int:
+    G, P = _gp(g, p)
+    n = lib().ase_workspace_bytes(G, P)
+    if n == 0:
+        raise AseError("ase_workspace_bytes: " + lib().ase_last_error().decode())
+    return int(n)
+
+
+class Workspace:
+    """Device workspace (256-byte aligned) for ase_step / ase_cfl_dt."""
+
+    def __init__(self, nbytes: int, device="cuda"):
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        self.ptr = (base + 255) // 256 * 256
+        self.nbytes = nbytes
+
+
+def cfl_dt(g, p, U, t, t_end, dt, ws: Workspace, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_cfl_dt(G, P, _p(U), _p(t), float(t_end), _p(dt), ws.ptr, ws.nbytes, _stream(stream)),
+           "ase_cfl_dt")
+
+
+def reconstruct(g, p, d, U, sx, sy, wl, wr, level=None, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_reconstruct(G, P, d, _p(U), _p(sx), _p(sy), _p(wl), _p(wr), _p(level), _stream(stream)),
+           "ase_reconstruct")
+
+
+def df_compute(g, p, d, wl, wr, sigma, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_df_compute(G, P, d, _p(wl), _p(wr), _p(sigma), _stream(stream)), "ase_df_compute")
+
+
+def flux(g, p, d, wl, wr, F, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_flux(G, P, d, _p(wl), _p(wr), _p(F), _stream(stream)), "ase_flux")
+
+
+def stage_update(g, p, stage, dt, Un, Us, F, Gf, Uout, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_stage_update(G, P, stage, _p(dt), _p(Un), _p(Us), _p(F), _p(Gf), _p(Uout),
+                                  _stream(stream)), "ase_stage_update")
+
+
+def step(g, p, U, sx, sy, t, nsteps, t_end, ws: Workspace, dt_hist=None, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_step(G, P, _p(U), _p(sx), _p(sy), _p(t), _p(dt_hist), int(nsteps), float(t_end), ws.ptr,
+                          ws.nbytes, _stream(stream)), "ase_step")
+
+
+def profile_enable(on: bool):
+    _check(lib().ase_profile_enable(1 if on else 0), "ase_profile_enable")
+
+
+def profile_read(kclass: str):
+    """(total milliseconds, launches) of one kernel class recorded by ase_step."""
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    _check(lib().ase_profile_read(KCLASS[kclass], C.byref(ms), C.byref(n)), "ase_profile_read")
+    return ms.value, n.value
+
+
+class Simulation:
+    """Device state (U, sx, sy, t) plus workspace for one grid."""
+
+    def __init__(self, g: Grid, p: Params, U0, device="cuda", sx=None, sy=None, t: float = 0.0):
+        self.g, self.p = g, p
+        self.U = torch.as_tensor(U0, dtype=torch.float64).to(device).contiguous()
+        self.sx = torch.zeros((g.NY, g.ld), dtype=torch.float64, device=device)
+        self.sy = torch.zeros((g.NY, g.ld), dtype=torch.float64, device=device)
+        self.t = torch.full((1,), float(t), dtype=torch.float64, device=device)
+        self.ws = Workspace(workspace_bytes(g, p), device)
+        if sx is None:
+            sigma_init(g, p, self.U, self.sx, self.sy)
+        else:
+            self.sx.copy_(torch.as_tensor(sx))
+            self.sy.copy_(torch.as_tensor(sy))
+
+    def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None):
+        step(self.g, self.p, self.U, self.sx, self.sy, self.t, nsteps, t_end, self.ws, dt_hist)

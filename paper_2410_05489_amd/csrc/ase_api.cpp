@@ -1,0 +1,464 @@
+// C ABI of libase: validation, error reporting, workspace layout and the
+// orchestration of whole SSP-RK3 steps on device.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ase.h"
+#include "ase_device.h"
+#include "ase_host.h"
+
+namespace ase {
+
+namespace {
+thread_local std::string g_err;
+std::mutex g_tab_mu;
+bool g_tab_ok[64] = {false};
+constexpr size_t kAlign = 256;
+constexpr int kMaxParts = 1024;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool misaligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) != 0; }
+}  // namespace
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(ASE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int ensure_tables()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(ASE_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    if (g_tab_ok[dev]) return ASE_OK;
+    Tables t;
+    build_tables(&t);
+    e = upload_tables(t);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyToSymbol(tables)");
+    g_tab_ok[dev] = true;
+    return ASE_OK;
+}
+
+int validate(const ase_grid_t *g, const ase_params_t *p, Geo *geo)
+{
+    if (!g || !p) return fail(ASE_ERR_ARG, "null grid or params");
+    const int r = p->order;
+    if (r != 3 && r != 5 && r != 7 && r != 9) return fail(ASE_ERR_ORDER, "order must be 3, 5, 7 or 9");
+    if (g->dim != 1 && g->dim != 2) return fail(ASE_ERR_ARG, "dim must be 1 or 2");
+    if (g->nx < 1 || g->ny < 1) return fail(ASE_ERR_ARG, "nx, ny must be >= 1");
+    if (g->dim == 1 && g->ny != 1) return fail(ASE_ERR_ARG, "ny must be 1 in 1D");
+    if (g->ng < (r + 1) / 2) return fail(ASE_ERR_GHOST, "ng must be >= (order+1)/2");
+    if (g->ld < g->nx + 2 * g->ng) return fail(ASE_ERR_ARG, "ld must be >= nx + 2 ng");
+    if (!(g->dx > 0.0) || (g->dim == 2 && !(g->dy > 0.0))) return fail(ASE_ERR_ARG, "dx, dy must be > 0");
+    for (int k = 0; k < 4; ++k)
+        if (g->bc[k] < 0 || g->bc[k] > 2) return fail(ASE_ERR_ARG, "unknown boundary code");
+    if ((g->bc[0] == ASE_BC_PERIODIC) != (g->bc[1] == ASE_BC_PERIODIC))
+        return fail(ASE_ERR_ARG, "periodic x boundaries must pair");
+    if (g->dim == 2 && (g->bc[2] == ASE_BC_PERIODIC) != (g->bc[3] == ASE_BC_PERIODIC))
+        return fail(ASE_ERR_ARG, "periodic y boundaries must pair");
+    if (g->dim == 2 && (g->bc[2] == ASE_BC_INFLOW_SLOT || g->bc[3] == ASE_BC_INFLOW_SLOT))
+        return fail(ASE_ERR_ARG, "inflow slot is an x boundary only");
+    if (g->bc[0] == ASE_BC_PERIODIC && g->nx < g->ng) return fail(ASE_ERR_ARG, "periodic x needs nx >= ng");
+    if (g->dim == 2 && g->bc[2] == ASE_BC_PERIODIC && g->ny < g->ng)
+        return fail(ASE_ERR_ARG, "periodic y needs ny >= ng");
+    const long long NX = g->nx + 2LL * g->ng, NY = g->dim == 1 ? 1 : g->ny + 2LL * g->ng;
+    if (NY * (long long)g->ld > (1LL << 31) - 1 || (long long)(g->nx + 1) * (g->ny + 1) > (1LL << 31) - 1)
+        return fail(ASE_ERR_ARG, "grid too large");
+    if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->sigma_thres > 0.0) || !(p->eps > 0.0) ||
+        !(p->d_hi > 0.0 && p->d_hi < 1.0) || !(p->d_lo >= 0.0 && p->d_lo <= 1.0))
+        return fail(ASE_ERR_ARG, "invalid method parameters");
+    geo->dim = g->dim;
+    geo->nx = g->nx;
+    geo->ny = g->ny;
+    geo->ng = g->ng;
+    geo->ld = g->ld;
+    geo->NX = (int)NX;
+    geo->NY = (int)NY;
+    geo->nv = g->dim == 1 ? 3 : 4;
+    geo->plane = NY * g->ld;
+    geo->R = (r - 1) / 2;
+    geo->G = g->dim == 1 ? 1 : (r - 1) / 2;
+    geo->oi = (r - 3) / 2;
+    return ensure_tables();
+}
+
+MethodConst method_const(const ase_params_t *p)
+{
+    MethodConst m;
+    m.gamma = p->gamma;
+    m.gm1 = p->gamma - 1.0;
+    m.thr = p->sigma_thres;
+    m.eps = p->eps;
+    m.d5 = p->d_hi;
+    m.d3m = (1.0 - p->d_hi) * (1.0 - p->d_lo) / 2.0;
+    m.d30 = (1.0 - p->d_hi) * p->d_lo;
+    m.inv_d5 = 1.0 / m.d5;
+    m.r3m = m.d3m / m.d5;
+    m.r30 = m.d30 / m.d5;
+    m.order = p->order;
+    m.flags = p->flags;
+    return m;
+}
+
+static int nparts_for(const Geo &geo)
+{
+    const long long n = (long long)geo.nx * (geo.dim == 1 ? 1 : geo.ny);
+    long long b = (n + 255) / 256;
+    if (b > kMaxParts) b = kMaxParts;
+    return (int)(b < 1 ? 1 : b);
+}
+
+size_t workspace_bytes(const Geo &geo)
+{
+    const size_t state = align_up((size_t)geo.nv * (size_t)geo.plane * sizeof(double));
+    const size_t plane = align_up((size_t)geo.plane * sizeof(double));
+    return 3 * state + 2 * plane + align_up(4 * sizeof(double)) + align_up(kMaxParts * sizeof(double));
+}
+
+int carve_workspace(const Geo &geo, void *ws, size_t bytes, Workspace *w)
+{
+    if (!ws) return fail(ASE_ERR_WORKSPACE, "workspace is required");
+    if (bytes < workspace_bytes(geo)) return fail(ASE_ERR_WORKSPACE, "workspace too small");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(ASE_ERR_ALIGN, "workspace must be 256-byte aligned");
+    char *c = static_cast<char *>(ws);
+    const size_t state = align_up((size_t)geo.nv * (size_t)geo.plane * sizeof(double));
+    const size_t plane = align_up((size_t)geo.plane * sizeof(double));
+    w->U1 = reinterpret_cast<double *>(c); c += state;
+    w->U2 = reinterpret_cast<double *>(c); c += state;
+    w->Res = reinterpret_cast<double *>(c); c += state;
+    w->sxa = reinterpret_cast<double *>(c); c += plane;
+    w->sya = reinterpret_cast<double *>(c); c += plane;
+    w->scal = reinterpret_cast<double *>(c); c += align_up(4 * sizeof(double));
+    w->part = reinterpret_cast<double *>(c);
+    w->nparts = nparts_for(geo);
+    return ASE_OK;
+}
+
+static SweepArgs base_args(const ase_grid_t *g, const Geo &geo, const MethodConst &mc)
+{
+    SweepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = geo.nx; a.ny = geo.ny; a.ng = geo.ng; a.ld = geo.ld; a.NX = geo.NX; a.NY = geo.NY;
+    a.plane = geo.plane;
+    a.inv_dx = 1.0 / g->dx;
+    a.inv_dy = geo.dim == 2 ? 1.0 / g->dy : 0.0;
+    a.mc = mc;
+    return a;
+}
+
+// ---- per-kernel event timing (benchmarks) ---------------------------------
+namespace {
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+};
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<ProfRec> recs;
+    size_t next = 0;
+} g_prof;
+constexpr size_t kProfPool = 16384;
+}  // namespace
+
+struct ProfScope {
+    hipStream_t st;
+    ProfRec rec;
+    bool active = false;
+    ProfScope(int cls, hipStream_t s) : st(s)
+    {
+        if (!g_prof.on) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (g_prof.next + 2 > g_prof.pool.size()) return;
+        rec.cls = cls;
+        rec.a = g_prof.pool[g_prof.next++];
+        rec.b = g_prof.pool[g_prof.next++];
+        active = hipEventRecord(rec.a, st) == hipSuccess;
+    }
+    ~ProfScope()
+    {
+        if (!active) return;
+        if (hipEventRecord(rec.b, st) == hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_prof.mu);
+            g_prof.recs.push_back(rec);
+        }
+    }
+};
+
+static int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return ASE_OK;
+}
+
+}  // namespace ase
+
+using namespace ase;
+
+#define ASE_PTR(p, name)                                                        \
+    do {                                                                        \
+        if (!(p)) return fail(ASE_ERR_ARG, std::string("null pointer: ") + name); \
+        if (misaligned(p)) return fail(ASE_ERR_ALIGN, std::string("misaligned: ") + name); \
+    } while (0)
+
+extern "C" {
+
+const char *ase_last_error(void) { return g_err.c_str(); }
+
+int ase_version(void) { return 1; }
+
+int ase_bc_fill(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    ASE_PTR(U, "U");
+    ASE_PTR(sx, "sx");
+    if (geo.dim == 2) ASE_PTR(sy, "sy");
+    launch_bc_fill(*g, geo, method_const(p), U, sx, geo.dim == 2 ? sy : sx, (hipStream_t)stream);
+    return check_launch("ase_bc_fill");
+}
+
+int ase_sigma_init(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    ASE_PTR(U, "U");
+    ASE_PTR(sx, "sx");
+    if (geo.dim == 2) ASE_PTR(sy, "sy");
+    launch_sigma_init(*g, geo, method_const(p), U, sx, geo.dim == 2 ? sy : sx, (hipStream_t)stream);
+    return check_launch("ase_sigma_init");
+}
+
+size_t ase_workspace_bytes(const ase_grid_t *g, const ase_params_t *p)
+{
+    Geo geo;
+    if (validate(g, p, &geo)) return 0;
+    return workspace_bytes(geo);
+}
+
+int ase_cfl_dt(const ase_grid_t *g, const ase_params_t *p, const double *U, const double *t, double t_end,
+               double *dt, void *ws, size_t ws_bytes, void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    ASE_PTR(U, "U");
+    ASE_PTR(t, "t");
+    ASE_PTR(dt, "dt");
+    Workspace w;
+    rc = carve_workspace(geo, ws, ws_bytes, &w);
+    if (rc) return rc;
+    launch_cfl(*g, geo, *p, method_const(p), U, t, nullptr, t_end, dt, nullptr, nullptr, w.part, w.nparts,
+               (hipStream_t)stream);
+    return check_launch("ase_cfl_dt");
+}
+
+int ase_reconstruct(const ase_grid_t *g, const ase_params_t *p, int dir, const double *U, const double *sx,
+                    const double *sy, double *wl, double *wr, int8_t *level, void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    if (dir != 0 && !(dir == 1 && geo.dim == 2)) return fail(ASE_ERR_ARG, "dir must be 0 (or 1 in 2D)");
+    ASE_PTR(U, "U");
+    ASE_PTR(sx, "sx");
+    if (geo.dim == 2) ASE_PTR(sy, "sy");
+    ASE_PTR(wl, "wl");
+    ASE_PTR(wr, "wr");
+    SweepArgs a = base_args(g, geo, method_const(p));
+    a.U = U;
+    a.sx = sx;
+    a.sy = geo.dim == 2 ? sy : sx;
+    a.wl = wl;
+    a.wr = wr;
+    a.level = level;
+    a.nfaces = geo.dim == 1 ? geo.nx + 1 : (dir == 0 ? (geo.nx + 1) * geo.ny : geo.nx * (geo.ny + 1));
+    launch_sweep(geo, dir, MODE_RECON, a, (hipStream_t)stream);
+    return check_launch("ase_reconstruct");
+}
+
+int ase_df_compute(const ase_grid_t *g, const ase_params_t *p, int dir, const double *wl, const double *wr,
+                   double *sigma, void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    if (dir != 0 && !(dir == 1 && geo.dim == 2)) return fail(ASE_ERR_ARG, "dir must be 0 (or 1 in 2D)");
+    ASE_PTR(wl, "wl");
+    ASE_PTR(wr, "wr");
+    ASE_PTR(sigma, "sigma");
+    launch_df(geo, method_const(p), dir, wl, wr, sigma, (hipStream_t)stream);
+    return check_launch("ase_df_compute");
+}
+
+int ase_flux(const ase_grid_t *g, const ase_params_t *p, int dir, const double *wl, const double *wr, double *F,
+             void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    if (dir != 0 && !(dir == 1 && geo.dim == 2)) return fail(ASE_ERR_ARG, "dir must be 0 (or 1 in 2D)");
+    ASE_PTR(wl, "wl");
+    ASE_PTR(wr, "wr");
+    ASE_PTR(F, "F");
+    launch_flux(geo, method_const(p), dir, wl, wr, F, (hipStream_t)stream);
+    return check_launch("ase_flux");
+}
+
+int ase_stage_update(const ase_grid_t *g, const ase_params_t *p, int stage, const double *dt, const double *Un,
+                     const double *Us, const double *F, const double *G, double *Uout, void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    if (stage < 1 || stage > 3) return fail(ASE_ERR_ARG, "stage must be 1, 2 or 3");
+    ASE_PTR(dt, "dt");
+    ASE_PTR(Un, "Un");
+    ASE_PTR(Us, "Us");
+    ASE_PTR(F, "F");
+    if (geo.dim == 2) ASE_PTR(G, "G");
+    ASE_PTR(Uout, "Uout");
+    launch_stage_update(*g, geo, stage, dt, Un, Us, F, geo.dim == 2 ? G : F, Uout, (hipStream_t)stream);
+    return check_launch("ase_stage_update");
+}
+
+int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, double *t,
+             double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes, void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(ASE_ERR_ARG, "nsteps must be >= 0");
+    ASE_PTR(U, "U");
+    ASE_PTR(sx, "sx");
+    if (geo.dim == 2) ASE_PTR(sy, "sy");
+    ASE_PTR(t, "t");
+    if (dt_hist && misaligned(dt_hist)) return fail(ASE_ERR_ALIGN, "misaligned: dt_hist");
+    Workspace w;
+    rc = carve_workspace(geo, ws, ws_bytes, &w);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const MethodConst mc = method_const(p);
+    SweepArgs a = base_args(g, geo, mc);
+    a.dt = w.scal;
+    a.skip = w.scal + 1;
+    a.Res = w.Res;
+    a.Un = U;
+
+    double *sxs[2] = {sx, w.sxa};
+    double *sys[2] = {geo.dim == 2 ? sy : sx, w.sya};
+    int cur = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        double *sxc = sxs[cur], *syc = sys[cur], *sxn = sxs[cur ^ 1], *syn = sys[cur ^ 1];
+        {
+            ProfScope ps(ASE_KCLASS_BC, st);
+            launch_bc_fill(*g, geo, mc, U, sxc, syc, st);
+        }
+        {
+            ProfScope ps(ASE_KCLASS_CFL, st);
+            launch_cfl(*g, geo, *p, mc, U, t, t, t_end, w.scal, w.scal + 1, dt_hist ? dt_hist + s : nullptr,
+                       w.part, w.nparts, st);
+        }
+        double *in_st[3] = {U, w.U1, w.U2};
+        double *out_st[3] = {w.U1, w.U2, U};
+        double *sx_in[3] = {sxc, sxn, sxc}, *sy_in[3] = {syc, syn, syc};
+        double *sx_out[3] = {sxn, sxc, sxn}, *sy_out[3] = {syn, syc, syn};
+        for (int k = 0; k < 3; ++k) {
+            if (k > 0) {
+                ProfScope ps(ASE_KCLASS_BC, st);
+                launch_bc_fill(*g, geo, mc, in_st[k], sx_in[k], sy_in[k], st);
+            }
+            a.U = in_st[k];
+            a.sx = sx_in[k];
+            a.sy = sy_in[k];
+            a.stage = k + 1;
+            a.Uout = out_st[k];
+            if (geo.dim == 1) {
+                a.sig_out = sx_out[k];
+                ProfScope ps(ASE_KCLASS_STAGE_1D, st);
+                launch_sweep(geo, 0, MODE_FUSED_1D, a, st);
+            } else {
+                a.sig_out = sx_out[k];
+                {
+                    ProfScope ps(ASE_KCLASS_SWEEP_X, st);
+                    launch_sweep(geo, 0, MODE_FUSED_X, a, st);
+                }
+                a.sig_out = sy_out[k];
+                {
+                    ProfScope ps(ASE_KCLASS_SWEEP_Y, st);
+                    launch_sweep(geo, 1, MODE_FUSED_Y, a, st);
+                }
+            }
+        }
+        cur ^= 1;
+    }
+    if (cur == 1) {
+        hipError_t e = hipMemcpyAsync(sx, w.sxa, (size_t)geo.plane * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(sx)");
+        if (geo.dim == 2) {
+            e = hipMemcpyAsync(sy, w.sya, (size_t)geo.plane * sizeof(double), hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(sy)");
+        }
+    }
+    return check_launch("ase_step");
+}
+
+int ase_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (on && g_prof.pool.empty()) {
+        g_prof.pool.resize(kProfPool);
+        for (auto &e : g_prof.pool) {
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) {
+                g_prof.pool.clear();
+                return hip_fail(err, "hipEventCreate");
+            }
+        }
+    }
+    g_prof.recs.clear();
+    g_prof.next = 0;
+    g_prof.on = on != 0;
+    return ASE_OK;
+}
+
+int ase_profile_read(int kernel_class, double *total_ms, int64_t *launches)
+{
+    if (!total_ms || !launches) return fail(ASE_ERR_ARG, "null output");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    double tot = 0.0;
+    int64_t n = 0;
+    for (const ProfRec &r : g_prof.recs) {
+        if (r.cls != kernel_class) continue;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    return ASE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,303 @@
+// Device-side building blocks of the ASE-DF path for gfx950: the constant
+// tables, the discontinuity-feedback level rule, the per-cell reconstruction
+// (linear stencils and the WENO-Z-AO(5,3) fallback), Euler primitives, the
+// discontinuity strength and the Lax-Friedrichs flux.
+//
+// Everything is FP64.  Linear reconstructions are applied as precomputed
+// point-evaluation weights (the paper's zero-mean stencil coefficients
+// contracted with the basis at the evaluation point, built on the host by
+// ase_tables.cpp); the DF sums are formed left to right across the stencil.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ase {
+
+// Evaluation-point sets, per nominal order r in {3,5,7,9} (index r/2-1):
+// point 0 is the right face (xi = 0), point 1 the left face (xi = -1) and
+// points 2..2+G-1 the Gauss points xi = -1/2 + g_k of the face quadrature.
+constexpr int kMaxPts = 6;
+constexpr int kTaps = 9;  // stencil taps, centred on index 4
+
+struct Tables {
+    // lin[oi][li][q][t]: weight of tap t-4 for the linear stencil of level
+    // li (0: 3-cell S^{r3}_0, 1: 5, 2: 7, 3: 9 cells) at point q of order oi.
+    double lin[4][4][kMaxPts][kTaps];
+    // z[oi][q][k-1] = Z_k(xi_q), k = 1..4 (zero-mean basis on [-1,0]).
+    double z[4][kMaxPts][4];
+    // Gauss weights eta_k per order (normalised to 1).
+    double eta[4][4];
+};
+
+struct MethodConst {
+    double gamma, gm1;          // gamma, gamma - 1
+    double thr;                 // sigma_thres
+    double eps;
+    double d5, d3m, d30;        // linear weights d^5_0, d^3_{-1} (= d^3_1), d^3_0
+    double inv_d5, r3m, r30;    // 1/d5, d3m/d5, d30/d5
+    int order;
+    int flags;
+};
+
+#if defined(ASE_KERNEL_TU)
+// Device code below is compiled only into the kernel translation unit.
+extern __constant__ Tables c_tab;
+
+// ---------------------------------------------------------------------------
+// DF factor and level (Sec. 3.1 Eq. discontinuity strength; Algorithm 1 with
+// the text's rule at the nominal order).
+// ---------------------------------------------------------------------------
+constexpr int LVL_WENOAO = 2;
+constexpr int LVL_R3 = 3;
+
+__device__ __forceinline__ double df_alpha(double A, double thr) { return A < thr ? 1.0 : thr / A; }
+
+// Sum of face strengths s[lo..hi-1] in left-to-right order.
+template <int R>
+__device__ __forceinline__ double ssum(const double (&s)[2 * R], int lo, int hi)
+{
+    double A = 0.0;
+#pragma unroll
+    for (int m = -R; m < R; ++m)
+        if (m >= lo && m < hi) A += s[m + R];
+    return A;
+}
+
+// Level of the cell whose stencil face strengths are s[m+R], m = -R..R-1
+// (s[m+R] between cells m and m+1).  alpha(S) < 1  <=>  A(S) > thr.
+template <int R>
+__device__ __forceinline__ int select_level(const double (&s)[2 * R], double thr)
+{
+    if constexpr (R == 1) {
+        return LVL_R3;
+    } else {
+        if (ssum<R>(s, -2, 2) > thr) return LVL_WENOAO;
+        if constexpr (R == 2) {
+            return 5;
+        } else {
+            if (ssum<R>(s, -3, 3) > thr) return 5;
+            if constexpr (R == 3) {
+                return 7;
+            } else {
+                if (ssum<R>(s, -4, 4) > thr) return 7;
+                return 9;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell reconstruction of NV variables at NP points.
+//   W[v][m+R], m = -R..R : cell averages along the stencil (W_0 at index R)
+//   s[m+R]               : face strengths (used by r = 3 and the fallback)
+//   q0                   : first point of the table used (0 for the faces,
+//                          2 for the Gauss points)
+// ---------------------------------------------------------------------------
+template <int R, int NV, int NP, int H>
+__device__ __forceinline__ void eval_linear(const double (&W)[NV][2 * R + 1], int oi, int li, int q0,
+                                            double (&out)[NV][NP])
+{
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const double *w = c_tab.lin[oi][li][q0 + q];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double acc = w[4 - H] * W[v][R - H];
+#pragma unroll
+            for (int m = -H + 1; m <= H; ++m) acc = fma(w[4 + m], W[v][R + m], acc);
+            out[v][q] = acc;
+        }
+    }
+}
+
+// WENO-Z-AO(5,3) with DF factors (Sec. 3.2); one variable.
+template <int R, int NP>
+__device__ __forceinline__ void weno_ao53(const double *Wc /* W_0 */, const double al[4], const MethodConst &mc,
+                                          int oi, int q0, double (&out)[NP])
+{
+    const double Wm2 = Wc[-2], Wm1 = Wc[-1], W0 = Wc[0], W1 = Wc[1], W2 = Wc[2];
+    // sub-stencil coefficients (W_x1, W_x2)
+    const double am1 = 2.0 * W0 - 3.0 * Wm1 + Wm2, am2 = 0.5 * (Wm2 - 2.0 * Wm1 + W0);
+    const double a01 = W1 - W0, a02 = 0.5 * (Wm1 - 2.0 * W0 + W1);
+    const double ap1 = W1 - W0, ap2 = 0.5 * (W0 - 2.0 * W1 + W2);
+    // 5-cell coefficients
+    const double b1 = (-15.0 * W0 + Wm1 + 15.0 * W1 - W2) * (1.0 / 12.0);
+    const double b2 = (-8.0 * W0 + 6.0 * Wm1 - Wm2 + 2.0 * W1 + W2) * 0.125;
+    const double b3 = (3.0 * W0 - Wm1 - 3.0 * W1 + W2) * (1.0 / 6.0);
+    const double b4 = (6.0 * W0 - 4.0 * Wm1 + Wm2 - 4.0 * W1 + W2) * (1.0 / 24.0);
+    // smoothness indicators of the 3-cell polynomials on [-1,0]:
+    // int (P')^2 + int (P'')^2 = a1^2 - 2 a1 a2 + 16/3 a2^2
+    const double sm = am1 * am1 - 2.0 * am1 * am2 + (16.0 / 3.0) * am2 * am2;
+    const double s0 = a01 * a01 - 2.0 * a01 * a02 + (16.0 / 3.0) * a02 * a02;
+    const double sp = ap1 * ap1 - 2.0 * ap1 * ap2 + (16.0 / 3.0) * ap2 * ap2;
+    const double s5 = (sm + 4.0 * s0 + sp) * (1.0 / 6.0) + fabs(sm - sp);
+    const double tz = (fabs(s5 - sm) + fabs(s5 - s0) + fabs(s5 - sp)) * (1.0 / 3.0);
+    const double tz2 = tz * tz;
+    const double e5 = s5 + mc.eps, em = sm + mc.eps, e0 = s0 + mc.eps, ep = sp + mc.eps;
+    const double w5 = mc.d5 * (1.0 + tz2 / (e5 * e5));
+    const double wm = mc.d3m * (1.0 + tz2 / (em * em));
+    const double w0 = mc.d30 * (1.0 + tz2 / (e0 * e0));
+    const double wp = mc.d3m * (1.0 + tz2 / (ep * ep));
+    const double inv = 1.0 / (w5 + wm + w0 + wp);
+    const double o5 = w5 * inv, om = wm * inv, o0 = w0 * inv, op = wp * inv;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const double *z = c_tab.z[oi][q0 + q];
+        const double Pm = W0 + al[0] * (am1 * z[0] + am2 * z[1]);
+        const double P0 = W0 + al[1] * (a01 * z[0] + a02 * z[1]);
+        const double Pp = W0 + al[2] * (ap1 * z[0] + ap2 * z[1]);
+        const double P5 = W0 + al[3] * (b1 * z[0] + b2 * z[1] + b3 * z[2] + b4 * z[3]);
+        const double inner = P5 * mc.inv_d5 - mc.r3m * Pm - mc.r30 * P0 - mc.r3m * Pp;
+        out[q] = o5 * inner + om * Pm + o0 * P0 + op * Pp;
+    }
+}
+
+// Reconstruction of all NV variables of a cell at NP points of order r (oi).
+// Returns the level used.
+template <int R, int NV, int NP>
+__device__ __forceinline__ int reconstruct_cell(const double (&W)[NV][2 * R + 1], const double (&s)[2 * R],
+                                                const MethodConst &mc, int oi, int q0, double (&out)[NV][NP])
+{
+    const int lvl = select_level<R>(s, mc.thr);
+    if constexpr (R == 1) {
+        // DF-damped centred 3-cell polynomial.
+        const double al = df_alpha(s[0] + s[1], mc.thr);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double a1 = W[v][2] - W[v][1];
+            const double a2 = 0.5 * (W[v][0] - 2.0 * W[v][1] + W[v][2]);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const double *z = c_tab.z[oi][q0 + q];
+                out[v][q] = W[v][1] + al * (a1 * z[0] + a2 * z[1]);
+            }
+        }
+        return lvl;
+    } else {
+        if (lvl == 9) {
+            if constexpr (R >= 4) eval_linear<R, NV, NP, 4>(W, oi, 3, q0, out);
+        } else if (lvl == 7) {
+            if constexpr (R >= 3) eval_linear<R, NV, NP, 3>(W, oi, 2, q0, out);
+        } else if (lvl == 5) {
+            eval_linear<R, NV, NP, 2>(W, oi, 1, q0, out);
+        } else {
+            double al[4];
+            al[0] = df_alpha(ssum<R>(s, -2, 0), mc.thr);
+            al[1] = df_alpha(ssum<R>(s, -1, 1), mc.thr);
+            al[2] = df_alpha(ssum<R>(s, 0, 2), mc.thr);
+            al[3] = df_alpha(ssum<R>(s, -2, 2), mc.thr);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double o[NP];
+                weno_ao53<R, NP>(&W[v][R], al, mc, oi, q0, o);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) out[v][q] = o[q];
+            }
+        }
+        return lvl;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Euler equations (Sec. 2.3).
+// ---------------------------------------------------------------------------
+struct Prim {
+    double un, ut, p, c, ic;  // normal/tangential velocity, pressure, sound speed, 1/c
+    bool ok;
+};
+
+// dir 0: x-normal, 1: y-normal.  NV = 3 (1D) or 4 (2D).
+template <int NV>
+__device__ __forceinline__ Prim primitives(const double (&W)[NV], int dir, const MethodConst &mc)
+{
+    Prim q;
+    const double rho = W[0];
+    const double u = W[1] / rho;
+    double v = 0.0, ke;
+    if constexpr (NV == 4) {
+        v = W[2] / rho;
+        ke = rho * (u * u + v * v);
+    } else {
+        ke = rho * (u * u);
+    }
+    const double p = mc.gm1 * (W[NV - 1] - 0.5 * ke);
+    q.un = dir == 0 ? u : v;
+    q.ut = dir == 0 ? v : u;
+    q.p = p;
+    q.ok = (rho > 0.0) && (p > 0.0);
+    q.c = sqrt(mc.gamma * p / rho);
+    q.ic = 1.0 / q.c;
+    return q;
+}
+
+// Discontinuity strength of one Gauss point (Sec. 3.1); +inf if a side is
+// non-physical.
+__device__ __forceinline__ double sigma_point(const Prim &l, const Prim &r)
+{
+    if (!(l.ok && r.ok)) return __builtin_huge_val();
+    const double dp = fabs(l.p - r.p);
+    const double dn = l.un * l.ic - r.un * r.ic;
+    const double dt = l.ut * l.ic - r.ut * r.ic;
+    return dp / l.p + dp / r.p + dn * dn + dt * dt;
+}
+
+// Physical flux along dir.
+template <int NV>
+__device__ __forceinline__ void euler_flux(const double (&W)[NV], const Prim &q, int dir, double (&F)[NV])
+{
+    if constexpr (NV == 3) {
+        F[0] = W[1];
+        F[1] = W[1] * q.un + q.p;
+        F[2] = q.un * (W[2] + q.p);
+    } else {
+        F[0] = dir == 0 ? W[1] : W[2];
+        F[1] = W[1] * q.un + (dir == 0 ? q.p : 0.0);
+        F[2] = W[2] * q.un + (dir == 0 ? 0.0 : q.p);
+        F[3] = q.un * (W[3] + q.p);
+    }
+}
+
+// Lax-Friedrichs flux with the local maximal signal speed (Sec. 2.3).
+template <int NV>
+__device__ __forceinline__ void lf_flux(const double (&Wl)[NV], const Prim &ql, const double (&Wr)[NV],
+                                        const Prim &qr, int dir, double (&F)[NV])
+{
+    double Fl[NV], Fr[NV];
+    euler_flux<NV>(Wl, ql, dir, Fl);
+    euler_flux<NV>(Wr, qr, dir, Fr);
+    const double sl = fabs(ql.un) + ql.c, sr = fabs(qr.un) + qr.c;
+    const double hs = 0.5 * (sl > sr ? sl : sr);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = 0.5 * (Fl[v] + Fr[v]) - hs * (Wr[v] - Wl[v]);
+}
+
+// Strength and LF flux at one Gauss point, with the optional positivity
+// replacement of a non-physical side by its cell average.
+template <int NV>
+__device__ __forceinline__ double gauss_point(double (&Wl)[NV], double (&Wr)[NV], const double (&Cl)[NV],
+                                              const double (&Cr)[NV], int dir, const MethodConst &mc,
+                                              double (&F)[NV])
+{
+    Prim ql = primitives<NV>(Wl, dir, mc);
+    Prim qr = primitives<NV>(Wr, dir, mc);
+    const double sg = sigma_point(ql, qr);
+    if (mc.flags & 1) {
+        if (!ql.ok) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Wl[v] = Cl[v];
+            ql = primitives<NV>(Wl, dir, mc);
+        }
+        if (!qr.ok) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Wr[v] = Cr[v];
+            qr = primitives<NV>(Wr, dir, mc);
+        }
+    }
+    lf_flux<NV>(Wl, ql, Wr, qr, dir, F);
+    return sg;
+}
+
+#endif  // ASE_KERNEL_TU
+
+}  // namespace ase

@@ -1,0 +1,85 @@
+// Host-side internals of libase: argument validation, error reporting,
+// workspace layout and the kernel launchers shared by the entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/ase.h"
+#include "ase_device.h"
+
+namespace ase {
+
+void build_tables(Tables *t);
+hipError_t upload_tables(const Tables &t);
+
+// Thread-local error message; returns code.
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+// Tables uploaded once per device.
+int ensure_tables();
+
+struct Geo {
+    int dim, nx, ny, ng, ld, NX, NY, nv;
+    long long plane;   // NY * ld
+    int R, G, oi;      // stencil half width, Gauss points, order index
+};
+
+int validate(const ase_grid_t *g, const ase_params_t *p, Geo *geo);
+MethodConst method_const(const ase_params_t *p);
+
+// Workspace layout for ase_step / ase_cfl_dt.
+struct Workspace {
+    double *U1, *U2, *Res;     // stage states and x-sweep residual
+    double *sxa, *sya;         // ping-pong strengths
+    double *scal;              // [0] dt, [1] skip flag
+    double *part;              // per-block partial maxima
+    int nparts;
+};
+size_t workspace_bytes(const Geo &geo);
+int carve_workspace(const Geo &geo, void *ws, size_t bytes, Workspace *w);
+
+// Launchers (asynchronous on `st`).
+void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx, double *sy,
+                    hipStream_t st);
+void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
+                       double *sy, hipStream_t st);
+void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,
+                const double *t_in, double *t_out, double t_end, double *dt, double *skip, double *dt_hist,
+                double *part, int nparts, hipStream_t st);
+
+enum SweepMode { MODE_RECON = 0, MODE_FUSED_X = 1, MODE_FUSED_Y = 2, MODE_FUSED_1D = 3 };
+
+struct SweepArgs {
+    const double *U;       // stage input (ghosts filled)
+    const double *sx, *sy; // strengths read by this stage
+    double *sig_out;       // strengths written (flux faces of this direction)
+    double *wl, *wr;       // MODE_RECON outputs
+    int8_t *level;         // MODE_RECON optional output
+    double *Res;           // x residual (FUSED_X writes, FUSED_Y reads)
+    const double *Un;      // step start state (FUSED_Y / 1D)
+    double *Uout;          // stage output (FUSED_Y / 1D)
+    const double *dt;      // device dt
+    const double *skip;    // device skip flag (nullptr: never skip)
+    int stage;
+    int nx, ny, ng, ld, NX, NY;
+    long long plane;
+    int nfaces;
+    double inv_dx, inv_dy;
+    MethodConst mc;
+};
+
+void launch_sweep(const Geo &geo, int dir, int mode, const SweepArgs &a, hipStream_t st);
+
+void launch_df(const Geo &geo, const MethodConst &mc, int dir, const double *wl, const double *wr, double *sig,
+               hipStream_t st);
+void launch_flux(const Geo &geo, const MethodConst &mc, int dir, const double *wl, const double *wr, double *F,
+                 hipStream_t st);
+void launch_stage_update(const ase_grid_t &g, const Geo &geo, int stage, const double *dt, const double *Un,
+                         const double *Us, const double *F, const double *Gf, double *Uout, hipStream_t st);
+
+}  // namespace ase

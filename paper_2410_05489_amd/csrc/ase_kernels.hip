@@ -1,0 +1,740 @@
+// HIP kernels of the ASE-DF path for gfx950 (MI355X) and their launchers.
+//
+// Data layout: structure of arrays with ghost cells, U[v][J][I] (row stride
+// ld), one strength plane per face direction of the same shape.  One thread
+// per cell or face; reconstruction kernels stage a halo tile of the state and
+// of both strength planes in LDS, reconstruct every cell of the tile (and of
+// the halo rows the tangential stencils reach) once, keep the face traces in
+// LDS, and evaluate Gauss points, strengths and fluxes from there.
+#include <hip/hip_runtime.h>
+
+#include "ase_device.h"
+#include "ase_host.h"
+
+namespace ase {
+
+__constant__ Tables c_tab;
+
+hipError_t upload_tables(const Tables &t)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_tab), &t, sizeof(Tables), 0, hipMemcpyHostToDevice);
+}
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct BCInfo {
+    int dim, nx, ny, ng, ld, NX, NY;
+    int bc[4];
+    long long plane;
+    double y0, dy, slot_lo, slot_hi;
+    double inflow[4];
+};
+
+BCInfo make_bc(const ase_grid_t &g, const Geo &geo)
+{
+    BCInfo b;
+    b.dim = geo.dim; b.nx = geo.nx; b.ny = geo.ny; b.ng = geo.ng; b.ld = geo.ld; b.NX = geo.NX; b.NY = geo.NY;
+    for (int k = 0; k < 4; ++k) { b.bc[k] = g.bc[k]; b.inflow[k] = g.inflow[k]; }
+    b.plane = geo.plane;
+    b.y0 = g.y0; b.dy = g.dy; b.slot_lo = g.slot_lo; b.slot_hi = g.slot_hi;
+    return b;
+}
+
+__device__ __forceinline__ bool in_slot(const BCInfo &b, int J)
+{
+    if (b.dim == 1) return true;
+    const double y = b.y0 + ((double)(J - b.ng) + 0.5) * b.dy;
+    return y > b.slot_lo && y < b.slot_hi;
+}
+
+// Source of stored cell (I, J) under the boundary conditions: the row is
+// mapped by the y rule, then the column by the x rule within that row (so
+// corners are the y rule applied to x-filled values).  Returns false when
+// the cell takes the inflow state.
+__device__ __forceinline__ bool src_cell(const BCInfo &b, int I, int J, int &Is, int &Js)
+{
+    Js = J;
+    if (b.dim == 2) {
+        const int j = J - b.ng;
+        if (j < 0) Js = (b.bc[2] == ASE_BC_PERIODIC) ? J + b.ny : b.ng;
+        else if (j >= b.ny) Js = (b.bc[3] == ASE_BC_PERIODIC) ? J - b.ny : b.ng + b.ny - 1;
+    }
+    Is = I;
+    const int i = I - b.ng;
+    if (i < 0) {
+        if (b.bc[0] == ASE_BC_PERIODIC) Is = I + b.nx;
+        else if (b.bc[0] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return false;
+        else Is = b.ng;
+    } else if (i >= b.nx) {
+        if (b.bc[1] == ASE_BC_PERIODIC) Is = I - b.nx;
+        else if (b.bc[1] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return false;
+        else Is = b.ng + b.nx - 1;
+    }
+    return true;
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_bc_cells(BCInfo b, double *U)
+{
+    const long long n = (long long)b.NY * b.NX;
+    for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * kThreads) {
+        const int J = (int)(idx / b.NX), I = (int)(idx % b.NX);
+        const bool ghost = (I < b.ng || I >= b.ng + b.nx) || (b.dim == 2 && (J < b.ng || J >= b.ng + b.ny));
+        if (!ghost) continue;
+        int Is, Js;
+        const long long dst = (long long)J * b.ld + I;
+        if (src_cell(b, I, J, Is, Js)) {
+            const long long src = (long long)Js * b.ld + Is;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v * b.plane + dst] = U[v * b.plane + src];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v * b.plane + dst] = b.inflow[v];
+        }
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ double sigma_first_order(const double *U, long long plane, long long a, long long c,
+                                                    int dir, const MethodConst &mc)
+{
+    double Wa[NV], Wb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        Wa[v] = U[v * plane + a];
+        Wb[v] = U[v * plane + c];
+    }
+    const Prim qa = primitives<NV>(Wa, dir, mc);
+    const Prim qb = primitives<NV>(Wb, dir, mc);
+    return sigma_point(qa, qb);
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) { return ((i % n) + n) % n; }
+
+// Strengths of the stored faces that are not flux faces.  init = true sets
+// every stored face to its first-order strength.
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_bc_sigma(BCInfo b, MethodConst mc, const double *U, double *sx,
+                                                       double *sy, int init)
+{
+    const long long n = (long long)b.NY * b.NX;
+    const bool xper = b.bc[0] == ASE_BC_PERIODIC;
+    const bool yper = b.dim == 2 && b.bc[2] == ASE_BC_PERIODIC;
+    for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * kThreads) {
+        const int J = (int)(idx / b.NX), I = (int)(idx % b.NX);
+        const long long pos = (long long)J * b.ld + I;
+        // x-face between (I,J) and (I+1,J)
+        if (I + 1 < b.NX) {
+            const int f = I - b.ng, j = J - b.ng;
+            const bool row_ok = b.dim == 1 || (j >= 0 && j < b.ny);
+            const bool produced = row_ok && f >= -1 && f <= b.nx - 1;
+            if (init) {
+                sx[pos] = sigma_first_order<NV>(U, b.plane, pos, pos + 1, 0, mc);
+            } else if (!produced) {
+                const int fw = xper ? wrapi(f, b.nx) : f;
+                const int jw = yper ? wrapi(j, b.ny) : j;
+                const bool jw_ok = b.dim == 1 || (jw >= 0 && jw < b.ny);
+                if (jw_ok && fw >= -1 && fw <= b.nx - 1) {
+                    const int Jw = b.dim == 1 ? 0 : jw + b.ng;
+                    sx[pos] = sx[(long long)Jw * b.ld + fw + b.ng];
+                } else {
+                    sx[pos] = sigma_first_order<NV>(U, b.plane, pos, pos + 1, 0, mc);
+                }
+            }
+        }
+        if (b.dim == 2 && J + 1 < b.NY) {
+            const int f = J - b.ng, i = I - b.ng;
+            const bool produced = i >= 0 && i < b.nx && f >= -1 && f <= b.ny - 1;
+            if (init) {
+                sy[pos] = sigma_first_order<NV>(U, b.plane, pos, pos + b.ld, 1, mc);
+            } else if (!produced) {
+                const int fw = yper ? wrapi(f, b.ny) : f;
+                const int iw = xper ? wrapi(i, b.nx) : i;
+                if (iw >= 0 && iw < b.nx && fw >= -1 && fw <= b.ny - 1) {
+                    sy[pos] = sy[(long long)(fw + b.ng) * b.ld + iw + b.ng];
+                } else {
+                    sy[pos] = sigma_first_order<NV>(U, b.plane, pos, pos + b.ld, 1, mc);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Time step: per-block maxima of the signal-speed sum, then one block that
+// reduces them, clips against t_end and advances t.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double max_nan(double a, double b) { return (b > a || b != b) ? b : a; }
+
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_cfl_partial(BCInfo b, MethodConst mc, const double *U, double inv_dx,
+                                                          double inv_dy, double *part)
+{
+    __shared__ double red[kThreads];
+    const int ny = b.dim == 1 ? 1 : b.ny;
+    const long long n = (long long)ny * b.nx;
+    double lam = 0.0;
+    for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * kThreads) {
+        const int j = (int)(idx / b.nx), i = (int)(idx % b.nx);
+        const long long pos = (long long)(b.dim == 1 ? 0 : j + b.ng) * b.ld + i + b.ng;
+        double W[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + pos];
+        const Prim q = primitives<NV>(W, 0, mc);
+        double l = (fabs(q.un) + q.c) * inv_dx;
+        if constexpr (NV == 4) l = l + (fabs(q.ut) + q.c) * inv_dy;
+        lam = max_nan(lam, l);
+    }
+    red[threadIdx.x] = lam;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max_nan(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kThreads) k_cfl_final(const double *part, int nparts, double cfl, double dt_cap,
+                                                        const double *t_in, double *t_out, double t_end,
+                                                        double *dt_out, double *skip_out, double *dt_hist)
+{
+    __shared__ double red[kThreads];
+    double lam = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kThreads) lam = max_nan(lam, part[k]);
+    red[threadIdx.x] = lam;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max_nan(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double t = *t_in;
+        const bool skip = t_end > 0.0 && t >= t_end;
+        double dt = 0.0;
+        if (!skip) {
+            dt = cfl / red[0];
+            if (dt_cap > 0.0 && dt > dt_cap) dt = dt_cap;
+            if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
+        }
+        *dt_out = dt;
+        if (skip_out) *skip_out = skip ? 1.0 : 0.0;
+        if (t_out) *t_out = t + dt;
+        if (dt_hist) *dt_hist = dt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D sweep: one tile of T0 x T1 cells, faces of direction DIR.
+// ---------------------------------------------------------------------------
+template <int DIR, int R, int T0, int T1, int MODE>
+__global__ void __launch_bounds__(kThreads) k_sweep2d(SweepArgs a)
+{
+    constexpr int NV = 4, G = R, OI = R - 1;
+    constexpr int UX = (DIR == 0) ? T0 + 2 + 2 * R : T0 + 2 * R;
+    constexpr int UY = (DIR == 0) ? T1 + 2 * R : T1 + 2 + 2 * R;
+    constexpr int TX = (DIR == 0) ? T0 + 2 : T0 + 2 * R;
+    constexpr int TY = (DIR == 0) ? T1 + 2 * R : T1 + 2;
+    constexpr int FX = (DIR == 0) ? T0 + 1 : T0;
+    constexpr int FY = (DIR == 0) ? T1 : T1 + 1;
+    __shared__ double sU[NV][UY][UX];
+    __shared__ double sSX[UY][UX];
+    __shared__ double sSY[UY][UX];
+    __shared__ double sTR[NV][TY][TX];
+    __shared__ double sTL[NV][TY][TX];
+    __shared__ double sF[MODE == MODE_RECON ? 1 : NV][FY][FX];
+
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * T0, j0 = blockIdx.y * T1;
+    const int ox = (DIR == 0) ? i0 - 1 - R : i0 - R;
+    const int oy = (DIR == 0) ? j0 - R : j0 - 1 - R;
+    const MethodConst &mc = a.mc;
+
+    if (MODE != MODE_RECON && a.skip != nullptr && *a.skip != 0.0) {
+        // finished run: carry the strengths of the owned flux faces over
+        const double *sin = DIR == 0 ? a.sx : a.sy;
+        for (int it = tid; it < FX * FY; it += kThreads) {
+            const int fx = it % FX, fy = it / FX;
+            const int x = DIR == 0 ? i0 - 1 + fx : i0 + fx;
+            const int y = DIR == 0 ? j0 + fy : j0 - 1 + fy;
+            if (DIR == 0 ? (x > a.nx - 1 || y >= a.ny) : (x >= a.nx || y > a.ny - 1)) continue;
+            const bool own = DIR == 0 ? (fx > 0 || i0 == 0) : (fy > 0 || j0 == 0);
+            if (own) {
+                const long long pos = (long long)(y + a.ng) * a.ld + x + a.ng;
+                a.sig_out[pos] = sin[pos];
+            }
+        }
+        return;
+    }
+
+    // stage the halo tile
+    for (int it = tid; it < UX * UY; it += kThreads) {
+        const int lx = it % UX, ly = it / UX;
+        const int I = ox + lx + a.ng, J = oy + ly + a.ng;
+        const bool in = I < a.NX && J < a.NY;
+        const long long pos = (long long)J * a.ld + I;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sU[v][ly][lx] = in ? a.U[v * a.plane + pos] : 0.0;
+        sSX[ly][lx] = in ? a.sx[pos] : 0.0;
+        sSY[ly][lx] = in ? a.sy[pos] : 0.0;
+    }
+    __syncthreads();
+
+    // normal reconstruction: face traces of every cell the tile needs
+    for (int it = tid; it < TX * TY; it += kThreads) {
+        const int tx = it % TX, ty = it / TX;
+        const int lx = (DIR == 0) ? tx + R : tx;
+        const int ly = (DIR == 0) ? ty : ty + R;
+        const int x = ox + lx, y = oy + ly;
+        const bool need = (DIR == 0) ? (x <= a.nx && y < a.ny + R) : (x < a.nx + R && y <= a.ny);
+        if (!need) continue;
+        double s[2 * R];
+        double W[NV][2 * R + 1];
+#pragma unroll
+        for (int m = -R; m < R; ++m) s[m + R] = (DIR == 0) ? sSX[ly][lx + m] : sSY[ly + m][lx];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = -R; m <= R; ++m) W[v][m + R] = (DIR == 0) ? sU[v][ly][lx + m] : sU[v][ly + m][lx];
+        double out[NV][2];
+        const int lvl = reconstruct_cell<R, NV, 2>(W, s, mc, OI, 0, out);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            sTR[v][ty][tx] = out[v][0];
+            sTL[v][ty][tx] = out[v][1];
+        }
+        if (MODE == MODE_RECON && a.level != nullptr && x >= 0 && x < a.nx && y >= 0 && y < a.ny)
+            a.level[(long long)y * a.nx + x] = (int8_t)lvl;
+    }
+    __syncthreads();
+
+    // tangential reconstruction, strengths and fluxes at the Gauss points
+    for (int it = tid; it < FX * FY; it += kThreads) {
+        const int fx = it % FX, fy = it / FX;
+        const int x = DIR == 0 ? i0 - 1 + fx : i0 + fx;
+        const int y = DIR == 0 ? j0 + fy : j0 - 1 + fy;
+        if (DIR == 0 ? (x > a.nx - 1 || y >= a.ny) : (x >= a.nx || y > a.ny - 1)) continue;
+        double WL[NV][G], WR[NV][G];
+        {
+            double Wt[NV][2 * R + 1], s[2 * R];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int m = -R; m <= R; ++m)
+                    Wt[v][m + R] = (DIR == 0) ? sTR[v][fy + R + m][fx] : sTR[v][fy][fx + R + m];
+#pragma unroll
+            for (int m = -R; m < R; ++m) s[m + R] = (DIR == 0) ? sSY[fy + R + m][fx + R] : sSX[fy + R][fx + R + m];
+            reconstruct_cell<R, NV, G>(Wt, s, mc, OI, 2, WL);
+        }
+        {
+            double Wt[NV][2 * R + 1], s[2 * R];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int m = -R; m <= R; ++m)
+                    Wt[v][m + R] = (DIR == 0) ? sTL[v][fy + R + m][fx + 1] : sTL[v][fy + 1][fx + R + m];
+#pragma unroll
+            for (int m = -R; m < R; ++m)
+                s[m + R] = (DIR == 0) ? sSY[fy + R + m][fx + R + 1] : sSX[fy + R + 1][fx + R + m];
+            reconstruct_cell<R, NV, G>(Wt, s, mc, OI, 2, WR);
+        }
+        if constexpr (MODE == MODE_RECON) {
+            const long long fid = DIR == 0 ? (long long)y * (a.nx + 1) + (x + 1) : (long long)(y + 1) * a.nx + x;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    a.wl[(long long)(v * G + k) * a.nfaces + fid] = WL[v][k];
+                    a.wr[(long long)(v * G + k) * a.nfaces + fid] = WR[v][k];
+                }
+        } else {
+            double Cl[NV], Cr[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Cl[v] = sU[v][fy + R][fx + R];
+                Cr[v] = DIR == 0 ? sU[v][fy + R][fx + R + 1] : sU[v][fy + R + 1][fx + R];
+            }
+            double Fs[NV], ssum = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fs[v] = 0.0;
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                double Wl[NV], Wr[NV], Fk[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    Wl[v] = WL[v][k];
+                    Wr[v] = WR[v][k];
+                }
+                ssum += gauss_point<NV>(Wl, Wr, Cl, Cr, DIR, mc, Fk);
+                const double eta = c_tab.eta[OI][k];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Fs[v] += eta * Fk[v];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sF[v][fy][fx] = Fs[v];
+            const bool own = DIR == 0 ? (fx > 0 || i0 == 0) : (fy > 0 || j0 == 0);
+            if (own) a.sig_out[(long long)(y + a.ng) * a.ld + x + a.ng] = ssum / (double)G;
+        }
+    }
+    if constexpr (MODE == MODE_RECON) return;
+    __syncthreads();
+
+    // flux differences and (second sweep) the stage update
+    const double dt = (MODE == MODE_FUSED_Y) ? *a.dt : 0.0;
+    for (int it = tid; it < T0 * T1; it += kThreads) {
+        const int cx = it % T0, cy = it / T0;
+        const int x = i0 + cx, y = j0 + cy;
+        if (x >= a.nx || y >= a.ny) continue;
+        const long long pos = (long long)(y + a.ng) * a.ld + x + a.ng;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const long long e = v * a.plane + pos;
+            if constexpr (DIR == 0) {
+                const double d = -(sF[v][cy][cx + 1] - sF[v][cy][cx]) * a.inv_dx;
+                a.Res[e] = d;
+            } else {
+                const double d = -(sF[v][cy + 1][cx] - sF[v][cy][cx]) * a.inv_dy;
+                const double L = a.Res[e] + d;
+                double o;
+                if (a.stage == 1) o = a.Un[e] + dt * L;
+                else if (a.stage == 2) o = 0.75 * a.Un[e] + 0.25 * a.U[e] + 0.25 * dt * L;
+                else o = (1.0 / 3.0) * a.Un[e] + (2.0 / 3.0) * a.U[e] + (2.0 / 3.0) * dt * L;
+                a.Uout[e] = o;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1D stage: tile of T cells; reconstruction, strengths, LF flux and update
+// in one pass (MODE_FUSED_1D), or the face states only (MODE_RECON).
+// ---------------------------------------------------------------------------
+template <int R, int T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_stage1d(SweepArgs a)
+{
+    constexpr int NV = 3, OI = R - 1;
+    constexpr int UX = T + 2 + 2 * R;
+    __shared__ double sU[NV][UX];
+    __shared__ double sS[UX];
+    __shared__ double sTR[NV][T + 2];
+    __shared__ double sTL[NV][T + 2];
+    __shared__ double sF[NV][T + 1];
+
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * T;
+    const int ox = i0 - 1 - R;
+    const MethodConst &mc = a.mc;
+
+    if (MODE != MODE_RECON && a.skip != nullptr && *a.skip != 0.0) {
+        for (int fx = tid; fx < T + 1; fx += kThreads) {
+            const int x = i0 - 1 + fx;
+            if (x > a.nx - 1) continue;
+            if (fx > 0 || i0 == 0) a.sig_out[x + a.ng] = a.sx[x + a.ng];
+        }
+        return;
+    }
+
+    for (int lx = tid; lx < UX; lx += kThreads) {
+        const int I = ox + lx + a.ng;
+        const bool in = I < a.NX;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sU[v][lx] = in ? a.U[v * a.plane + I] : 0.0;
+        sS[lx] = in ? a.sx[I] : 0.0;
+    }
+    __syncthreads();
+
+    for (int tx = tid; tx < T + 2; tx += kThreads) {
+        const int lx = tx + R;
+        const int x = ox + lx;
+        if (x > a.nx) continue;
+        double s[2 * R];
+        double W[NV][2 * R + 1];
+#pragma unroll
+        for (int m = -R; m < R; ++m) s[m + R] = sS[lx + m];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = -R; m <= R; ++m) W[v][m + R] = sU[v][lx + m];
+        double out[NV][2];
+        const int lvl = reconstruct_cell<R, NV, 2>(W, s, mc, OI, 0, out);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            sTR[v][tx] = out[v][0];
+            sTL[v][tx] = out[v][1];
+        }
+        if (MODE == MODE_RECON && a.level != nullptr && x >= 0 && x < a.nx) a.level[x] = (int8_t)lvl;
+    }
+    __syncthreads();
+
+    for (int fx = tid; fx < T + 1; fx += kThreads) {
+        const int x = i0 - 1 + fx;   // face x + 1/2
+        if (x > a.nx - 1) continue;
+        double Wl[NV], Wr[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Wl[v] = sTR[v][fx];
+            Wr[v] = sTL[v][fx + 1];
+        }
+        if constexpr (MODE == MODE_RECON) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                a.wl[(long long)v * a.nfaces + x + 1] = Wl[v];
+                a.wr[(long long)v * a.nfaces + x + 1] = Wr[v];
+            }
+        } else {
+            double Cl[NV], Cr[NV], F[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Cl[v] = sU[v][fx + R];
+                Cr[v] = sU[v][fx + R + 1];
+            }
+            const double sg = gauss_point<NV>(Wl, Wr, Cl, Cr, 0, mc, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sF[v][fx] = F[v];
+            if (fx > 0 || i0 == 0) a.sig_out[x + a.ng] = sg;
+        }
+    }
+    if constexpr (MODE == MODE_RECON) return;
+    __syncthreads();
+
+    const double dt = *a.dt;
+    for (int cx = tid; cx < T; cx += kThreads) {
+        const int x = i0 + cx;
+        if (x >= a.nx) continue;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const long long e = v * a.plane + x + a.ng;
+            const double L = -(sF[v][cx + 1] - sF[v][cx]) * a.inv_dx;
+            double o;
+            if (a.stage == 1) o = a.Un[e] + dt * L;
+            else if (a.stage == 2) o = 0.75 * a.Un[e] + 0.25 * a.U[e] + 0.25 * dt * L;
+            else o = (1.0 / 3.0) * a.Un[e] + (2.0 / 3.0) * a.U[e] + (2.0 / 3.0) * dt * L;
+            a.Uout[e] = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Granular face kernels.
+// ---------------------------------------------------------------------------
+struct FaceGeo {
+    int dim, nx, ny, ng, ld, nfaces, G, oi;
+};
+
+__device__ __forceinline__ long long face_plane_pos(const FaceGeo &f, int dir, long long id)
+{
+    if (f.dim == 1) return id - 1 + f.ng;
+    if (dir == 0) {
+        const long long j = id / (f.nx + 1), i = id % (f.nx + 1) - 1;
+        return (j + f.ng) * f.ld + i + f.ng;
+    }
+    const long long j = id / f.nx - 1, i = id % f.nx;
+    return (j + f.ng) * f.ld + i + f.ng;
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_df(FaceGeo f, MethodConst mc, int dir, const double *wl,
+                                                 const double *wr, double *sig)
+{
+    const long long id = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (id >= f.nfaces) return;
+    double s = 0.0;
+    for (int k = 0; k < f.G; ++k) {
+        double Wl[NV], Wr[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Wl[v] = wl[(long long)(v * f.G + k) * f.nfaces + id];
+            Wr[v] = wr[(long long)(v * f.G + k) * f.nfaces + id];
+        }
+        s += sigma_point(primitives<NV>(Wl, dir, mc), primitives<NV>(Wr, dir, mc));
+    }
+    sig[face_plane_pos(f, dir, id)] = s / (double)f.G;
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_flux(FaceGeo f, MethodConst mc, int dir, const double *wl,
+                                                   const double *wr, double *F)
+{
+    const long long id = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (id >= f.nfaces) return;
+    double Fs[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fs[v] = 0.0;
+    for (int k = 0; k < f.G; ++k) {
+        double Wl[NV], Wr[NV], Fk[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Wl[v] = wl[(long long)(v * f.G + k) * f.nfaces + id];
+            Wr[v] = wr[(long long)(v * f.G + k) * f.nfaces + id];
+        }
+        lf_flux<NV>(Wl, primitives<NV>(Wl, dir, mc), Wr, primitives<NV>(Wr, dir, mc), dir, Fk);
+        const double eta = (f.dim == 1) ? 1.0 : c_tab.eta[f.oi][k];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fs[v] += eta * Fk[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[(long long)v * f.nfaces + id] = Fs[v];
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_stage_update(BCInfo b, int stage, const double *dtp, const double *Un,
+                                                           const double *Us, const double *F, const double *Gf,
+                                                           double inv_dx, double inv_dy, double *Uo)
+{
+    const int ny = b.dim == 1 ? 1 : b.ny;
+    const long long n = (long long)ny * b.nx;
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    const int j = (int)(idx / b.nx), i = (int)(idx % b.nx);
+    const long long pos = (long long)(b.dim == 1 ? 0 : j + b.ng) * b.ld + i + b.ng;
+    const long long nfx = b.dim == 1 ? b.nx + 1 : (long long)(b.nx + 1) * b.ny;
+    const long long nfy = (long long)b.nx * (b.ny + 1);
+    const double dt = *dtp;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const long long fx = (b.dim == 1) ? i + 1 : (long long)j * (b.nx + 1) + i + 1;
+        double L = -(F[v * nfx + fx] - F[v * nfx + fx - 1]) * inv_dx;
+        if constexpr (NV == 4) {
+            const long long fy = (long long)(j + 1) * b.nx + i;
+            L = L + -(Gf[v * nfy + fy] - Gf[v * nfy + fy - b.nx]) * inv_dy;
+        }
+        const long long e = v * b.plane + pos;
+        double o;
+        if (stage == 1) o = Un[e] + dt * L;
+        else if (stage == 2) o = 0.75 * Un[e] + 0.25 * Us[e] + 0.25 * dt * L;
+        else o = (1.0 / 3.0) * Un[e] + (2.0 / 3.0) * Us[e] + (2.0 / 3.0) * dt * L;
+        Uo[e] = o;
+    }
+}
+
+int grid_blocks(long long n)
+{
+    long long b = (n + kThreads - 1) / kThreads;
+    if (b > 65535LL * 16) b = 65535LL * 16;
+    return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx, double *sy,
+                    hipStream_t st)
+{
+    const BCInfo b = make_bc(g, geo);
+    const int nb = grid_blocks((long long)geo.NY * geo.NX);
+    if (geo.nv == 4) {
+        k_bc_cells<4><<<nb, kThreads, 0, st>>>(b, U);
+        k_bc_sigma<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
+    } else {
+        k_bc_cells<3><<<nb, kThreads, 0, st>>>(b, U);
+        k_bc_sigma<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
+    }
+}
+
+void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
+                       double *sy, hipStream_t st)
+{
+    const BCInfo b = make_bc(g, geo);
+    const int nb = grid_blocks((long long)geo.NY * geo.NX);
+    if (geo.nv == 4) {
+        k_bc_cells<4><<<nb, kThreads, 0, st>>>(b, U);
+        k_bc_sigma<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
+    } else {
+        k_bc_cells<3><<<nb, kThreads, 0, st>>>(b, U);
+        k_bc_sigma<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
+    }
+}
+
+void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,
+                const double *t_in, double *t_out, double t_end, double *dt, double *skip, double *dt_hist,
+                double *part, int nparts, hipStream_t st)
+{
+    const BCInfo b = make_bc(g, geo);
+    if (geo.nv == 4)
+        k_cfl_partial<4><<<nparts, kThreads, 0, st>>>(b, mc, U, 1.0 / g.dx, 1.0 / g.dy, part);
+    else
+        k_cfl_partial<3><<<nparts, kThreads, 0, st>>>(b, mc, U, 1.0 / g.dx, 1.0 / g.dy, part);
+    k_cfl_final<<<1, kThreads, 0, st>>>(part, nparts, p.cfl, p.dt_cap, t_in, t_out, t_end, dt, skip, dt_hist);
+}
+
+namespace {
+constexpr int kT0 = 16, kT1 = 16, kT1D = 256;
+
+template <int R>
+void sweep_r(const Geo &geo, int dir, int mode, const SweepArgs &a, hipStream_t st)
+{
+    if (geo.dim == 1) {
+        dim3 grid((geo.nx + kT1D - 1) / kT1D);
+        if (mode == MODE_RECON) k_stage1d<R, kT1D, MODE_RECON><<<grid, kThreads, 0, st>>>(a);
+        else k_stage1d<R, kT1D, MODE_FUSED_1D><<<grid, kThreads, 0, st>>>(a);
+        return;
+    }
+    dim3 grid((geo.nx + kT0 - 1) / kT0, (geo.ny + kT1 - 1) / kT1);
+    if (dir == 0) {
+        if (mode == MODE_RECON) k_sweep2d<0, R, kT0, kT1, MODE_RECON><<<grid, kThreads, 0, st>>>(a);
+        else k_sweep2d<0, R, kT0, kT1, MODE_FUSED_X><<<grid, kThreads, 0, st>>>(a);
+    } else {
+        if (mode == MODE_RECON) k_sweep2d<1, R, kT0, kT1, MODE_RECON><<<grid, kThreads, 0, st>>>(a);
+        else k_sweep2d<1, R, kT0, kT1, MODE_FUSED_Y><<<grid, kThreads, 0, st>>>(a);
+    }
+}
+}  // namespace
+
+void launch_sweep(const Geo &geo, int dir, int mode, const SweepArgs &a, hipStream_t st)
+{
+    switch (geo.R) {
+    case 1: sweep_r<1>(geo, dir, mode, a, st); break;
+    case 2: sweep_r<2>(geo, dir, mode, a, st); break;
+    case 3: sweep_r<3>(geo, dir, mode, a, st); break;
+    default: sweep_r<4>(geo, dir, mode, a, st); break;
+    }
+}
+
+static FaceGeo face_geo(const Geo &geo, int dir)
+{
+    FaceGeo f;
+    f.dim = geo.dim; f.nx = geo.nx; f.ny = geo.ny; f.ng = geo.ng; f.ld = geo.ld;
+    f.G = geo.G; f.oi = geo.oi;
+    if (geo.dim == 1) f.nfaces = geo.nx + 1;
+    else f.nfaces = dir == 0 ? (geo.nx + 1) * geo.ny : geo.nx * (geo.ny + 1);
+    return f;
+}
+
+void launch_df(const Geo &geo, const MethodConst &mc, int dir, const double *wl, const double *wr, double *sig,
+               hipStream_t st)
+{
+    const FaceGeo f = face_geo(geo, dir);
+    const int nb = (f.nfaces + kThreads - 1) / kThreads;
+    if (geo.nv == 4) k_df<4><<<nb, kThreads, 0, st>>>(f, mc, dir, wl, wr, sig);
+    else k_df<3><<<nb, kThreads, 0, st>>>(f, mc, dir, wl, wr, sig);
+}
+
+void launch_flux(const Geo &geo, const MethodConst &mc, int dir, const double *wl, const double *wr, double *F,
+                 hipStream_t st)
+{
+    const FaceGeo f = face_geo(geo, dir);
+    const int nb = (f.nfaces + kThreads - 1) / kThreads;
+    if (geo.nv == 4) k_flux<4><<<nb, kThreads, 0, st>>>(f, mc, dir, wl, wr, F);
+    else k_flux<3><<<nb, kThreads, 0, st>>>(f, mc, dir, wl, wr, F);
+}
+
+void launch_stage_update(const ase_grid_t &g, const Geo &geo, int stage, const double *dt, const double *Un,
+                         const double *Us, const double *F, const double *Gf, double *Uout, hipStream_t st)
+{
+    const BCInfo b = make_bc(g, geo);
+    const long long n = (long long)geo.nx * (geo.dim == 1 ? 1 : geo.ny);
+    const int nb = (int)((n + kThreads - 1) / kThreads);
+    if (geo.nv == 4)
+        k_stage_update<4><<<nb, kThreads, 0, st>>>(b, stage, dt, Un, Us, F, Gf, 1.0 / g.dx, 1.0 / g.dy, Uout);
+    else
+        k_stage_update<3><<<nb, kThreads, 0, st>>>(b, stage, dt, Un, Us, F, Gf, 1.0 / g.dx, 1.0 / g.dy, Uout);
+}
+
+}  // namespace ase

@@ -1,0 +1,256 @@
+"""GPU (libase, HIP) against the CPU oracle on seeded inputs.
+
+Every entry point of include/ase.h is compared element by element with the
+oracle on the same input.  Tolerances: per-step states to 1e-12 relative to
+the max-norm of each conserved variable, full runs to 1e-9; ghost copies and
+level selections bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2410_05489_amd import ase
+from paper_2410_05489_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def rel_err(a, b, g=None):
+    """max over variables of ||a_v - b_v||_inf / ||b_v||_inf."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    nv = a.shape[0]
+    a = a.reshape(nv, -1)
+    b = b.reshape(nv, -1)
+    den = np.maximum(np.abs(b).max(axis=1), 1e-300)
+    return float(np.max(np.abs(a - b).max(axis=1) / den))
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _case(name, order, ragged=True):
+    if name == "quad":
+        w = WL.four_quadrant(45 if ragged else 32, order, seed=3, ny=37 if ragged else 0)
+    elif name == "config3":
+        w = WL.four_quadrant(40, order, states=WL.CONFIG3_STATES)
+    elif name == "wave2d":
+        w = WL.density_wave_2d(24, order, seed=2, amp=1e-3)
+    elif name == "jet":
+        w = WL.jet(64, 32, order)
+    elif name == "sod":
+        w = WL.sod(203, order)
+    elif name == "wave1d":
+        w = WL.density_wave_1d(70, order, seed=1)
+    elif name == "riemann1d":
+        w = WL.riemann_1d(301, (1.3, 0.4, 2.0), (0.2, -0.3, 0.1), order, x_split=0.37)
+    else:
+        raise KeyError(name)
+    return w
+
+
+def _evolved(w, nsteps):
+    """Oracle state (U, sx, sy) after a few steps (non-trivial lagged strengths)."""
+    U = w.U.copy()
+    sx, sy = O.sigma_init(w.grid, w.params, U)
+    t = 0.0
+    if nsteps:
+        t, _ = O.step(w.grid, w.params, U, sx, sy, 0.0, nsteps)
+    return U, sx, sy, t
+
+
+CASES_2D = [("quad", 9), ("quad", 7), ("quad", 5), ("quad", 3), ("config3", 9), ("wave2d", 9), ("jet", 7)]
+CASES_1D = [("sod", 5), ("wave1d", 9), ("riemann1d", 9), ("riemann1d", 7), ("riemann1d", 3)]
+
+
+@pytest.mark.parametrize("name,order", CASES_2D + CASES_1D)
+def test_bc_fill_and_sigma_init(name, order):
+    w = _case(name, order)
+    g, p = w.grid, w.params
+    U, sx, sy, _ = _evolved(w, 2)
+    # ghost cells and derived strengths from identical interior + flux faces
+    Ug, sxg, syg = dev(U), dev(sx), dev(sy)
+    ase.bc_fill(g, p, Ug, sxg, syg)
+    Uo, sxo, syo = U.copy(), sx.copy(), sy.copy()
+    O.bc_fill(g, p, Uo, sxo, syo)
+    assert np.array_equal(host(Ug), Uo)
+    NX = g.NX
+    np.testing.assert_allclose(host(sxg)[:, :NX - 1], sxo[:, :NX - 1], rtol=1e-14, atol=0)
+    if g.dim == 2:
+        np.testing.assert_allclose(host(syg)[:g.NY - 1, :NX], syo[:g.NY - 1, :NX], rtol=1e-14, atol=0)
+    # first-order initialisation
+    U0 = w.U.copy()
+    Ug = dev(U0)
+    sxg = torch.zeros((g.NY, g.ld), dtype=torch.float64, device=DEV)
+    syg = torch.zeros_like(sxg)
+    ase.sigma_init(g, p, Ug, sxg, syg)
+    sxo, syo = O.sigma_init(g, p, U0)
+    np.testing.assert_allclose(host(sxg)[:, :NX - 1], sxo[:, :NX - 1], rtol=1e-14, atol=0)
+    if g.dim == 2:
+        np.testing.assert_allclose(host(syg)[:g.NY - 1, :NX], syo[:g.NY - 1, :NX], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("name,order", CASES_2D + CASES_1D)
+def test_cfl_dt(name, order):
+    w = _case(name, order)
+    g, p = w.grid, w.params
+    U, _, _, _ = _evolved(w, 1)
+    ws = ase.Workspace(ase.workspace_bytes(g, p), DEV)
+    t = torch.zeros(1, dtype=torch.float64, device=DEV)
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ase.cfl_dt(g, p, dev(U), t, 0.0, dt, ws)
+    ref = O.cfl_dt(g, p, U)
+    assert abs(host(dt)[0] - ref) <= 1e-14 * ref
+    # clipping against t_end and the finished state
+    t.fill_(0.3)
+    ase.cfl_dt(g, p, dev(U), t, 0.3 + 0.25 * ref, dt, ws)
+    assert abs(host(dt)[0] - O.cfl_dt(g, p, U, 0.3, 0.3 + 0.25 * ref)) <= 1e-15
+    ase.cfl_dt(g, p, dev(U), t, 0.3, dt, ws)
+    assert host(dt)[0] == 0.0
+
+
+def _recon_pair(w, d, nsteps=2):
+    g, p = w.grid, w.params
+    U, sx, sy, _ = _evolved(w, nsteps)
+    O.bc_fill(g, p, U, sx, sy)
+    wlo, wro, levo = O.reconstruct(g, p, d, U, sx, sy, want_level=True)
+    Gq = ase.ngauss(g, p.order)
+    nf = ase.face_count(g, d)
+    wlg = torch.zeros((g.nvar, Gq, nf), dtype=torch.float64, device=DEV)
+    wrg = torch.zeros_like(wlg)
+    levg = torch.zeros((g.ny, g.nx), dtype=torch.int8, device=DEV)
+    ase.reconstruct(g, p, d, dev(U), dev(sx), dev(sy), wlg, wrg, levg)
+    return (U, sx, sy), (wlo, wro, levo), (host(wlg), host(wrg), host(levg))
+
+
+@pytest.mark.parametrize("name,order", CASES_2D + CASES_1D)
+def test_reconstruct(name, order):
+    w = _case(name, order)
+    dirs = (0, 1) if w.grid.dim == 2 else (0,)
+    for d in dirs:
+        (U, _, _), (wlo, wro, levo), (wlg, wrg, levg) = _recon_pair(w, d)
+        assert np.array_equal(levg, levo), d
+        nv = w.grid.nvar
+        scale = np.abs(w.grid.interior(U)).reshape(nv, -1).max(axis=1)[:, None, None]
+        assert np.max(np.abs(wlg - wlo) / scale) < 1e-12, d
+        assert np.max(np.abs(wrg - wro) / scale) < 1e-12, d
+
+
+def test_reconstruct_exercises_every_level():
+    w = _case("config3", 9)
+    levels = set()
+    for d in (0, 1):
+        _, (_, _, levo), (_, _, levg) = _recon_pair(w, d, nsteps=6)
+        assert np.array_equal(levg, levo)
+        levels |= set(np.unique(levo).tolist())
+    assert levels >= {2, 5, 7, 9}, levels
+
+
+@pytest.mark.parametrize("name,order", [("quad", 9), ("jet", 7), ("sod", 5), ("riemann1d", 9)])
+def test_df_flux_and_stage_update(name, order):
+    w = _case(name, order)
+    g, p = w.grid, w.params
+    U, sx, sy, _ = _evolved(w, 2)
+    O.bc_fill(g, p, U, sx, sy)
+    dirs = (0, 1) if g.dim == 2 else (0,)
+    Fo, Fg = {}, {}
+    for d in dirs:
+        wl, wr = O.reconstruct(g, p, d, U, sx, sy)
+        # strengths
+        so = np.zeros((g.NY, g.ld))
+        O.df_compute(g, p, d, wl, wr, so)
+        sg = torch.zeros((g.NY, g.ld), dtype=torch.float64, device=DEV)
+        ase.df_compute(g, p, d, dev(wl), dev(wr), sg)
+        sg = host(sg)
+        fin = np.isfinite(so)
+        assert np.array_equal(fin, np.isfinite(sg))
+        assert np.all(np.abs(sg[fin] - so[fin]) <= 1e-13 * np.maximum(np.abs(so[fin]), 1.0))
+        # fluxes
+        Fo[d] = O.flux(g, p, d, wl, wr)
+        Fgd = torch.zeros((g.nvar, ase.face_count(g, d)), dtype=torch.float64, device=DEV)
+        ase.flux(g, p, d, dev(wl), dev(wr), Fgd)
+        Fg[d] = host(Fgd)
+        assert rel_err(Fg[d], Fo[d]) < 1e-13
+    # stage update from identical fluxes
+    dt = 0.37 * O.cfl_dt(g, p, U)
+    Us = U * (1.0 + 1e-3)
+    for stage in (1, 2, 3):
+        Uo = U.copy()
+        O.stage_update(g, p, stage, dt, U, Us, Fo[0], Fo.get(1, Fo[0]), Uo)
+        Ug = dev(U)
+        ase.stage_update(g, p, stage, torch.full((1,), dt, dtype=torch.float64, device=DEV), Ug, dev(Us),
+                         dev(Fo[0]), dev(Fo.get(1, Fo[0])), Ug)
+        assert rel_err(g.interior(host(Ug)), g.interior(Uo)) < 1e-14
+
+
+def _gpu_run(w, U, sx, sy, t, nsteps, t_end=0.0):
+    sim = ase.Simulation(w.grid, w.params, U, device=DEV, sx=sx, sy=sy, t=t)
+    hist = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=DEV)
+    sim.run(nsteps, t_end, hist)
+    return host(sim.U), host(sim.sx), host(sim.sy), float(host(sim.t)[0]), host(hist)[:nsteps]
+
+
+STEP_CASES = [("quad", 9), ("quad", 7), ("quad", 5), ("quad", 3), ("config3", 9), ("wave2d", 9), ("jet", 7),
+              ("sod", 5), ("wave1d", 9), ("riemann1d", 9), ("riemann1d", 3)]
+
+
+@pytest.mark.parametrize("name,order", STEP_CASES)
+def test_one_step(name, order):
+    """One full step (bc, dt, three stages) from an identical state: 1e-12."""
+    w = _case(name, order)
+    g, p = w.grid, w.params
+    U, sx, sy, t = _evolved(w, 3)
+    Ug, sxg, syg, tg, hg = _gpu_run(w, U, sx, sy, t, 1)
+    Uo, sxo, syo = U.copy(), sx.copy(), sy.copy()
+    to, ho = O.step(g, p, Uo, sxo, syo, t, 1)
+    assert abs(hg[0] - ho[0]) <= 1e-14 * ho[0]
+    assert abs(tg - to) <= 1e-15 * max(1.0, abs(to))
+    assert rel_err(g.interior(Ug), g.interior(Uo)) < 1e-12
+    # DF state on the flux faces
+    ng = g.ng
+    if g.dim == 1:
+        a, b = sxg[0, ng - 1:ng + g.nx], sxo[0, ng - 1:ng + g.nx]
+    else:
+        a = np.concatenate([sxg[ng:ng + g.ny, ng - 1:ng + g.nx].ravel(), syg[ng - 1:ng + g.ny, ng:ng + g.nx].ravel()])
+        b = np.concatenate([sxo[ng:ng + g.ny, ng - 1:ng + g.nx].ravel(), syo[ng - 1:ng + g.ny, ng:ng + g.nx].ravel()])
+    fin = np.isfinite(b)
+    assert np.array_equal(fin, np.isfinite(a))
+    assert np.all(np.abs(a[fin] - b[fin]) <= 1e-9 * np.maximum(np.abs(b[fin]), 1.0))
+
+
+@pytest.mark.parametrize("name,order,nsteps,t_end", [("sod", 5, 400, 0.2), ("riemann1d", 9, 150, 0.0),
+                                                     ("quad", 9, 60, 0.0), ("wave2d", 7, 40, 0.0),
+                                                     ("jet", 7, 60, 0.0)])
+def test_full_run(name, order, nsteps, t_end):
+    """Independent runs from the initial data: 1e-9 after the full run."""
+    w = _case(name, order)
+    g, p = w.grid, w.params
+    U0 = w.U.copy()
+    sx, sy = O.sigma_init(g, p, U0)
+    Ug, _, _, tg, hg = _gpu_run(w, U0, sx, sy, 0.0, nsteps, t_end)
+    Uo = U0.copy()
+    to, ho = O.step(g, p, Uo, sx.copy(), sy.copy(), 0.0, nsteps, t_end)
+    if t_end > 0:
+        assert abs(tg - t_end) < 1e-14 and abs(to - t_end) < 1e-14
+        assert np.all(hg[len(ho):] == 0.0)
+    assert rel_err(g.interior(Ug), g.interior(Uo)) < 1e-9
+
+
+def test_ragged_and_tiny_grids():
+    for nx, ny in ((1 + 9, 1 + 9), (17, 33), (33, 17), (5 + 16, 9)):
+        w = WL.four_quadrant(nx, 9, seed=7, ny=ny, split=(0.43, 0.61))
+        g, p = w.grid, w.params
+        U, sx, sy, t = _evolved(w, 2)
+        Ug, _, _, _, _ = _gpu_run(w, U, sx, sy, t, 2)
+        Uo = U.copy()
+        O.step(g, p, Uo, sx.copy(), sy.copy(), t, 2)
+        assert rel_err(g.interior(Ug), g.interior(Uo)) < 1e-12, (nx, ny)
