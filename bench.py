@@ -91,7 +91,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="quad1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU domain decomposition is a design note, not implemented)"}))
@@ -122,7 +134,6 @@ def main():
     ms = start.elapsed_time(stop)
     kern = {k: ase.profile_read(k) for k in ("sweep_x", "sweep_y", "stage_1d", "bc", "cfl")}
     ase.profile_enable(False)
-    U = sim.U.cpu().numpy()
     finite = bool(torch.isfinite(sim.U).all().item())
 
     ncell = g.ncells()

@@ -65,7 +65,15 @@ enum { ASE_BC_PERIODIC = 0, ASE_BC_TRANSMISSIVE = 1, ASE_BC_INFLOW_SLOT = 2 };
 enum {
     /* A Gauss-point state with rho <= 0 or p <= 0 is replaced by the
      * average of its own cell for the flux (its strength is +inf anyway). */
-    ASE_FLAG_POSITIVITY_FALLBACK = 1
+    ASE_FLAG_POSITIVITY_FALLBACK = 1,
+    /* Source of the interface states the DF strengths (Sec. 3.1) are
+     * computed from.  Clear (default, "lagged"): the Gauss-point states of
+     * the previous stage's reconstruction, so the strengths are part of the
+     * state and ase_bc_fill derives the non-flux faces.  Set ("first
+     * order"): the first-order states of the current stage input, i.e. the
+     * two cell averages beside each face; ase_bc_fill then recomputes every
+     * stored strength from the ghost-filled state. */
+    ASE_FLAG_DF_FIRST_ORDER = 2
 };
 
 /* Grid and boundary description (the problem statement of Sec. 2.1 and
@@ -105,11 +113,13 @@ int ase_version(void);
 
 /* Ghost cells and derived strengths (boundary conditions of Sec. 4).
  * Fills every ghost cell of U (x first on interior rows, then y on every
- * column, so corners take the y rule applied to x-filled values), then
- * every stored strength that is not a flux-face strength: periodic faces
- * take the wrapped flux-face value, the others the first-order strength of
- * their two cells.  U: state layout, in/out.  sx, sy: in/out (sy unused in
- * 1D, may be NULL). */
+ * column, so corners take the y rule applied to x-filled values), then the
+ * strengths a stage reads.  Lagged DF source: every stored strength that is
+ * not a flux-face strength -- periodic faces take the wrapped flux-face
+ * value, the others the first-order strength of their two cells.
+ * First-order DF source: every stored strength becomes the first-order
+ * strength of its two cells.  U: state layout, in/out.  sx, sy: in/out (sy
+ * unused in 1D, may be NULL). */
 int ase_bc_fill(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy,
                 void *stream);
 

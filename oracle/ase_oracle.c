@@ -51,9 +51,17 @@ typedef struct {
     double slot_lo, slot_hi;
 } orc_grid;
 
+/* Source of the interface states the DF strengths are computed from        */
+/* (reading R9): LAGGED -- the Gauss-point states of the previous stage's   */
+/* reconstruction; FIRST_ORDER -- the first-order (cell-average) states of  */
+/* the current stage input.                                                  */
+enum { ORC_DF_LAGGED = 0, ORC_DF_FIRST_ORDER = 1 };
+
 typedef struct {
     int32_t order;      /* 1 (first order, test aid), 3, 5, 7, 9 */
     int32_t positivity_fallback;
+    int32_t df_source;  /* ORC_DF_* */
+    int32_t pad_;
     double gamma, cfl, sigma_thres, eps, d_hi, d_lo;
     double dt_cap;      /* > 0: dt = min(dt_cfl, dt_cap) */
 } orc_params;
@@ -487,6 +495,24 @@ static double sigma_first_order(const orc_grid *g, const orc_params *p, const do
     return sigma_point(&qa, oka, &qb, okb);
 }
 
+/* First-order strength on every stored face (ghost cells already filled). */
+static void sigma_all_first_order(const orc_grid *g, const orc_params *p, const double *U, double *sx, double *sy)
+{
+    int NX = NXof(g), NY = NYof(g);
+    for (int J = 0; J < NY; ++J)
+        for (int I = 0; I + 1 < NX; ++I)
+            sx[(size_t)J * g->ld + I] = sigma_first_order(g, p, U, I, J, I + 1, J, 0);
+    if (g->dim == 2)
+        for (int J = 0; J + 1 < NY; ++J)
+            for (int I = 0; I < NX; ++I)
+                sy[(size_t)J * g->ld + I] = sigma_first_order(g, p, U, I, J, I, J + 1, 1);
+}
+
+/* Boundary step of a stage: ghost cells, then the strengths the stage's    */
+/* DF factors read -- derived non-flux faces (lagged source) or first-order */
+/* strengths of the stage input on every face (first-order source).        */
+static void stage_bc(const orc_grid *g, const orc_params *p, double *U, double *sx, double *sy);
+
 static int wrap(int i, int n) { return ((i % n) + n) % n; }
 
 /* Strength on faces the previous stage did not produce.  Flux faces are     */
@@ -532,6 +558,13 @@ static void bc_fill_sigma(const orc_grid *g, const orc_params *p, const double *
             }
         }
     }
+}
+
+static void stage_bc(const orc_grid *g, const orc_params *p, double *U, double *sx, double *sy)
+{
+    bc_fill_cells(g, U);
+    if (p->df_source == ORC_DF_FIRST_ORDER) sigma_all_first_order(g, p, U, sx, sy);
+    else bc_fill_sigma(g, p, U, sx, sy);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -709,8 +742,9 @@ static int residual(const orc_grid *g, const orc_params *p, const double *U, con
 }
 
 /* ------------------------------------------------------------------------ */
-/* Time step (reading R9): dt = CFL / max over interior cells of             */
-/* (|u|+c)/dx [+ (|v|+c)/dy], optionally capped, then clipped to t_end.      */
+/* Time step (reading R9): dt = CFL / max over interior cells (and the       */
+/* inflow state, when a boundary has one) of (|u|+c)/dx [+ (|v|+c)/dy],      */
+/* optionally capped, then clipped to t_end.                                 */
 /* ------------------------------------------------------------------------ */
 static double cfl_dt(const orc_grid *g, const orc_params *p, const double *U, double t, double t_end)
 {
@@ -730,6 +764,17 @@ static double cfl_dt(const orc_grid *g, const orc_params *p, const double *U, do
             }
             if (l > lam || l != l) lam = l;
         }
+    }
+    /* Inflow ghost states enter the domain: their signal speed counts too. */
+    if (g->bc[0] == ORC_BC_INFLOW_SLOT || g->bc[1] == ORC_BC_INFLOW_SLOT) {
+        prim_t qx, qy;
+        primitives(g, p, g->inflow, 0, &qx);
+        double l = (fabs(qx.un) + qx.c) / g->dx;
+        if (g->dim == 2) {
+            primitives(g, p, g->inflow, 1, &qy);
+            l = l + (fabs(qy.un) + qy.c) / g->dy;
+        }
+        if (l > lam || l != l) lam = l;
     }
     double dt = p->cfl / lam;
     if (p->dt_cap > 0.0 && dt > p->dt_cap) dt = p->dt_cap;
@@ -783,13 +828,13 @@ static int check_args(const orc_grid *g, const orc_params *p)
 /* Exported entry points (ctypes).                                           */
 /* ------------------------------------------------------------------------ */
 
-/* Ghost cells of U, then strengths of all non-flux faces. */
+/* Ghost cells of U, then the strengths a stage reads: all non-flux faces   */
+/* (lagged source) or every face at first order (first-order source).      */
 int orc_bc_fill(const orc_grid *g, const orc_params *p, double *U, double *sx, double *sy)
 {
     int e = check_args(g, p);
     if (e) return e;
-    bc_fill_cells(g, U);
-    bc_fill_sigma(g, p, U, sx, sy);
+    stage_bc(g, p, U, sx, sy);
     return 0;
 }
 
@@ -800,14 +845,7 @@ int orc_sigma_init(const orc_grid *g, const orc_params *p, double *U, double *sx
     int e = check_args(g, p);
     if (e) return e;
     bc_fill_cells(g, U);
-    int NX = NXof(g), NY = NYof(g);
-    for (int J = 0; J < NY; ++J)
-        for (int I = 0; I + 1 < NX; ++I)
-            sx[(size_t)J * g->ld + I] = sigma_first_order(g, p, U, I, J, I + 1, J, 0);
-    if (g->dim == 2)
-        for (int J = 0; J + 1 < NY; ++J)
-            for (int I = 0; I < NX; ++I)
-                sy[(size_t)J * g->ld + I] = sigma_first_order(g, p, U, I, J, I, J + 1, 1);
+    sigma_all_first_order(g, p, U, sx, sy);
     return 0;
 }
 
@@ -921,8 +959,7 @@ int orc_residual(const orc_grid *g, const orc_params *p, double *U, double *sx, 
 {
     int e = check_args(g, p);
     if (e) return e;
-    bc_fill_cells(g, U);
-    bc_fill_sigma(g, p, U, sx, sy);
+    stage_bc(g, p, U, sx, sy);
     size_t n = plane(g);
     double *tx = sx_new ? sx_new : malloc(n * sizeof(double));
     double *ty = (g->dim == 2) ? (sy_new ? sy_new : malloc(n * sizeof(double))) : NULL;
@@ -962,21 +999,18 @@ int orc_step(const orc_grid *g, const orc_params *p, double *U, double *sx, doub
         /* filled by the boundary step before they are read.                    */
         memcpy(U1, U, n * sizeof(double));
         memcpy(U2, U, n * sizeof(double));
-        bc_fill_cells(g, U);
-        bc_fill_sigma(g, p, U, sx, sy);
+        stage_bc(g, p, U, sx, sy);
         double dt = cfl_dt(g, p, U, *t, t_end);
         /* stage 1 */
         memcpy(sxa, sx, P * sizeof(double));
         memcpy(sya, sy ? sy : sx, P * sizeof(double));
         if (residual(g, p, U, sx, sy, L, sxa, g->dim == 2 ? sya : NULL)) goto fail;
         stage_combine(g, 1, dt, U, U, L, U1);
-        bc_fill_cells(g, U1);
-        bc_fill_sigma(g, p, U1, sxa, g->dim == 2 ? sya : NULL);
+        stage_bc(g, p, U1, sxa, g->dim == 2 ? sya : NULL);
         /* stage 2 */
         if (residual(g, p, U1, sxa, sya, L, sx, g->dim == 2 ? sy : NULL)) goto fail;
         stage_combine(g, 2, dt, U, U1, L, U2);
-        bc_fill_cells(g, U2);
-        bc_fill_sigma(g, p, U2, sx, g->dim == 2 ? sy : NULL);
+        stage_bc(g, p, U2, sx, g->dim == 2 ? sy : NULL);
         /* stage 3 */
         if (residual(g, p, U2, sx, sy, L, sxa, g->dim == 2 ? sya : NULL)) goto fail;
         stage_combine(g, 3, dt, U, U2, L, U);

@@ -28,7 +28,8 @@ class OrcGrid(C.Structure):
 
 
 class OrcParams(C.Structure):
-    _fields_ = [("order", C.c_int32), ("positivity_fallback", C.c_int32), ("gamma", C.c_double),
+    _fields_ = [("order", C.c_int32), ("positivity_fallback", C.c_int32), ("df_source", C.c_int32),
+                ("pad_", C.c_int32), ("gamma", C.c_double),
                 ("cfl", C.c_double), ("sigma_thres", C.c_double), ("eps", C.c_double),
                 ("d_hi", C.c_double), ("d_lo", C.c_double), ("dt_cap", C.c_double)]
 
@@ -92,6 +93,7 @@ def c_grid(g) -> OrcGrid:
 def c_params(p) -> OrcParams:
     s = OrcParams()
     s.order, s.positivity_fallback = int(p.order), int(p.positivity_fallback)
+    s.df_source = int(p.df_source)
     s.gamma, s.cfl, s.sigma_thres, s.eps = p.gamma, p.cfl, p.sigma_thres, p.eps
     s.d_hi, s.d_lo, s.dt_cap = p.d_hi, p.d_lo, p.dt_cap
     return s

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libase.so")
 _LIB = None
 
 FLAG_POSITIVITY_FALLBACK = 1
+FLAG_DF_FIRST_ORDER = 2
 
 
 class AseGrid(C.Structure):
@@ -90,7 +91,8 @@ def c_grid(g: Grid) -> AseGrid:
 def c_params(p: Params) -> AseParams:
     s = AseParams()
     s.order = int(p.order)
-    s.flags = FLAG_POSITIVITY_FALLBACK if p.positivity_fallback else 0
+    s.flags = (FLAG_POSITIVITY_FALLBACK if p.positivity_fallback else 0) | \
+        (FLAG_DF_FIRST_ORDER if p.df_source == 1 else 0)
     s.gamma, s.cfl, s.sigma_thres, s.eps = p.gamma, p.cfl, p.sigma_thres, p.eps
     s.d_hi, s.d_lo, s.dt_cap = p.d_hi, p.d_lo, p.dt_cap
     return s

@@ -231,7 +231,10 @@ int ase_bc_fill(const ase_grid_t *g, const ase_params_t *p, double *U, double *s
     ASE_PTR(U, "U");
     ASE_PTR(sx, "sx");
     if (geo.dim == 2) ASE_PTR(sy, "sy");
-    launch_bc_fill(*g, geo, method_const(p), U, sx, geo.dim == 2 ? sy : sx, (hipStream_t)stream);
+    if (p->flags & ASE_FLAG_DF_FIRST_ORDER)
+        launch_sigma_init(*g, geo, method_const(p), U, sx, geo.dim == 2 ? sy : sx, (hipStream_t)stream);
+    else
+        launch_bc_fill(*g, geo, method_const(p), U, sx, geo.dim == 2 ? sy : sx, (hipStream_t)stream);
     return check_launch("ase_bc_fill");
 }
 
@@ -363,6 +366,12 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
     a.Res = w.Res;
     a.Un = U;
 
+    // Ghost cells and the strengths the stage reads (lagged or first order).
+    const bool fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) != 0;
+    auto stage_bc = [&](double *Us, double *sxs_, double *sys_) {
+        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs_, sys_, st);
+        else launch_bc_fill(*g, geo, mc, Us, sxs_, sys_, st);
+    };
     double *sxs[2] = {sx, w.sxa};
     double *sys[2] = {geo.dim == 2 ? sy : sx, w.sya};
     int cur = 0;
@@ -370,7 +379,7 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
         double *sxc = sxs[cur], *syc = sys[cur], *sxn = sxs[cur ^ 1], *syn = sys[cur ^ 1];
         {
             ProfScope ps(ASE_KCLASS_BC, st);
-            launch_bc_fill(*g, geo, mc, U, sxc, syc, st);
+            stage_bc(U, sxc, syc);
         }
         {
             ProfScope ps(ASE_KCLASS_CFL, st);
@@ -384,7 +393,7 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
         for (int k = 0; k < 3; ++k) {
             if (k > 0) {
                 ProfScope ps(ASE_KCLASS_BC, st);
-                launch_bc_fill(*g, geo, mc, in_st[k], sx_in[k], sy_in[k], st);
+                stage_bc(in_st[k], sx_in[k], sy_in[k]);
             }
             a.U = in_st[k];
             a.sx = sx_in[k];

@@ -235,6 +235,8 @@ __device__ __forceinline__ Prim primitives(const double (&W)[NV], int dir, const
 // non-physical.
 __device__ __forceinline__ double sigma_point(const Prim &l, const Prim &r)
 {
+    // No contraction: equal states must give exactly zero.
+#pragma clang fp contract(off)
     if (!(l.ok && r.ok)) return __builtin_huge_val();
     const double dp = fabs(l.p - r.p);
     const double dn = l.un * l.ic - r.un * r.ic;

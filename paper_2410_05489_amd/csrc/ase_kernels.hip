@@ -199,12 +199,33 @@ __global__ void __launch_bounds__(kThreads) k_cfl_partial(BCInfo b, MethodConst 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+struct InflowSpeed {
+    int on, dim;
+    double W[4];
+    double inv_dx, inv_dy;
+};
+
 __global__ void __launch_bounds__(kThreads) k_cfl_final(const double *part, int nparts, double cfl, double dt_cap,
                                                         const double *t_in, double *t_out, double t_end,
-                                                        double *dt_out, double *skip_out, double *dt_hist)
+                                                        double *dt_out, double *skip_out, double *dt_hist,
+                                                        InflowSpeed inf, MethodConst mc)
 {
     __shared__ double red[kThreads];
     double lam = 0.0;
+    if (threadIdx.x == 0 && inf.on) {
+        // inflow ghost states enter the domain: their signal speed counts too
+        double l;
+        if (inf.dim == 2) {
+            const double W[4] = {inf.W[0], inf.W[1], inf.W[2], inf.W[3]};
+            const Prim q = primitives<4>(W, 0, mc);
+            l = (fabs(q.un) + q.c) * inf.inv_dx + (fabs(q.ut) + q.c) * inf.inv_dy;
+        } else {
+            const double W[3] = {inf.W[0], inf.W[1], inf.W[2]};
+            const Prim q = primitives<3>(W, 0, mc);
+            l = (fabs(q.un) + q.c) * inf.inv_dx;
+        }
+        lam = max_nan(lam, l);
+    }
     for (int k = threadIdx.x; k < nparts; k += kThreads) lam = max_nan(lam, part[k]);
     red[threadIdx.x] = lam;
     __syncthreads();
@@ -661,7 +682,14 @@ void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, cons
         k_cfl_partial<4><<<nparts, kThreads, 0, st>>>(b, mc, U, 1.0 / g.dx, 1.0 / g.dy, part);
     else
         k_cfl_partial<3><<<nparts, kThreads, 0, st>>>(b, mc, U, 1.0 / g.dx, 1.0 / g.dy, part);
-    k_cfl_final<<<1, kThreads, 0, st>>>(part, nparts, p.cfl, p.dt_cap, t_in, t_out, t_end, dt, skip, dt_hist);
+    InflowSpeed inf;
+    inf.on = (g.bc[0] == ASE_BC_INFLOW_SLOT || g.bc[1] == ASE_BC_INFLOW_SLOT) ? 1 : 0;
+    inf.dim = geo.dim;
+    for (int k = 0; k < 4; ++k) inf.W[k] = g.inflow[k];
+    inf.inv_dx = 1.0 / g.dx;
+    inf.inv_dy = geo.dim == 2 ? 1.0 / g.dy : 0.0;
+    k_cfl_final<<<1, kThreads, 0, st>>>(part, nparts, p.cfl, p.dt_cap, t_in, t_out, t_end, dt, skip, dt_hist, inf,
+                                        mc);
 }
 
 namespace {

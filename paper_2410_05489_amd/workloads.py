@@ -20,6 +20,11 @@ BC_PERIODIC = 0
 BC_TRANSMISSIVE = 1
 BC_INFLOW_SLOT = 2
 
+# Interface states the DF strengths come from: the previous stage's
+# Gauss-point states (lagged) or the current stage's cell averages.
+DF_LAGGED = 0
+DF_FIRST_ORDER = 1
+
 
 @dataclasses.dataclass
 class Grid:
@@ -79,6 +84,7 @@ class Params:
     d_lo: float = 0.85
     dt_cap: float = 0.0
     positivity_fallback: int = 0
+    df_source: int = 0          # DF_LAGGED or DF_FIRST_ORDER
 
 
 @dataclasses.dataclass
@@ -245,11 +251,11 @@ def four_quadrant(n: int = 1024, order: int = 9, seed: int = 0, nsteps: int = 20
     U = empty_state(g)
     _fill_interior(g, U, W)
     return Workload(f"four_quadrant_{n}x{nyy}_r{order}_seed{seed}", g,
-                    Params(order=order, gamma=gamma, cfl=cfl), U, nsteps, 0.0)
+                    Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=1), U, nsteps, 0.0)
 
 
 def jet(nx: int = 1600, ny: int = 800, order: int = 7, u_jet: float = 7400.0, nsteps: int = 500,
-        cfl: float = 0.25, positivity_fallback: int = 1) -> Workload:
+        cfl: float = 0.25, positivity_fallback: int = 1, df_source: int = DF_FIRST_ORDER) -> Workload:
     """High-Mach jet on [0,1] x [-0.25,0.25], gamma 5/3: ambient (0.5,0,0,0.4127),
     inflow (5, u_jet, 0, 0.4127) through |y| < 0.05 at x = 0, outflow elsewhere."""
     gamma = 5.0 / 3.0
@@ -264,8 +270,8 @@ def jet(nx: int = 1600, ny: int = 800, order: int = 7, u_jet: float = 7400.0, ns
     U = empty_state(g)
     _fill_interior(g, U, W)
     return Workload(f"jet_{nx}x{ny}_r{order}", g,
-                    Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=positivity_fallback),
-                    U, nsteps, 0.0)
+                    Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=positivity_fallback,
+                           df_source=df_source), U, nsteps, 0.0)
 
 
 # --------------------------------------------------------------------------
