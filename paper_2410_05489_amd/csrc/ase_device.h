@@ -89,34 +89,37 @@ __device__ __forceinline__ int select_level(const double (&s)[2 * R], double thr
 
 // ---------------------------------------------------------------------------
 // Per-cell reconstruction of NV variables at NP points.
-//   W[v][m+R], m = -R..R : cell averages along the stencil (W_0 at index R)
-//   s[m+R]               : face strengths (used by r = 3 and the fallback)
-//   q0                   : first point of the table used (0 for the faces,
-//                          2 for the Gauss points)
+//   ld(v, m), m = -R..R  : cell average of variable v at stencil offset m
+//                          (read on demand, one variable at a time)
+//   s[m+R], m = -R..R-1  : strength of the face between cells m and m+1
+//   q0                   : first evaluation point of the table (0 for the
+//                          two faces, 2 for the Gauss points)
 // ---------------------------------------------------------------------------
-template <int R, int NV, int NP, int H>
-__device__ __forceinline__ void eval_linear(const double (&W)[NV][2 * R + 1], int oi, int li, int q0,
-                                            double (&out)[NV][NP])
+template <int NV, int NP, int H, class LD>
+__device__ __forceinline__ void eval_linear(LD ld, int oi, int li, int q0, double (&out)[NV][NP])
 {
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-        const double *w = c_tab.lin[oi][li][q0 + q];
+    for (int v = 0; v < NV; ++v) {
+        double w[2 * H + 1];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double acc = w[4 - H] * W[v][R - H];
+        for (int m = -H; m <= H; ++m) w[m + H] = ld(v, m);
 #pragma unroll
-            for (int m = -H + 1; m <= H; ++m) acc = fma(w[4 + m], W[v][R + m], acc);
+        for (int q = 0; q < NP; ++q) {
+            const double *c = c_tab.lin[oi][li][q0 + q];
+            double acc = c[4 - H] * w[0];
+#pragma unroll
+            for (int m = -H + 1; m <= H; ++m) acc = fma(c[4 + m], w[m + H], acc);
             out[v][q] = acc;
         }
     }
 }
 
-// WENO-Z-AO(5,3) with DF factors (Sec. 3.2); one variable.
-template <int R, int NP>
-__device__ __forceinline__ void weno_ao53(const double *Wc /* W_0 */, const double al[4], const MethodConst &mc,
-                                          int oi, int q0, double (&out)[NP])
+// WENO-Z-AO(5,3) with DF factors (Sec. 3.2); one variable, W[0..4] = W_{-2..2}.
+template <int NP>
+__device__ __forceinline__ void weno_ao53(const double (&W)[5], const double al[4], const MethodConst &mc, int oi,
+                                          int q0, double (&out)[NP])
 {
-    const double Wm2 = Wc[-2], Wm1 = Wc[-1], W0 = Wc[0], W1 = Wc[1], W2 = Wc[2];
+    const double Wm2 = W[0], Wm1 = W[1], W0 = W[2], W1 = W[3], W2 = W[4];
     // sub-stencil coefficients (W_x1, W_x2)
     const double am1 = 2.0 * W0 - 3.0 * Wm1 + Wm2, am2 = 0.5 * (Wm2 - 2.0 * Wm1 + W0);
     const double a01 = W1 - W0, a02 = 0.5 * (Wm1 - 2.0 * W0 + W1);
@@ -155,9 +158,9 @@ __device__ __forceinline__ void weno_ao53(const double *Wc /* W_0 */, const doub
 
 // Reconstruction of all NV variables of a cell at NP points of order r (oi).
 // Returns the level used.
-template <int R, int NV, int NP>
-__device__ __forceinline__ int reconstruct_cell(const double (&W)[NV][2 * R + 1], const double (&s)[2 * R],
-                                                const MethodConst &mc, int oi, int q0, double (&out)[NV][NP])
+template <int R, int NV, int NP, class LD>
+__device__ __forceinline__ int reconstruct_cell(LD ld, const double (&s)[2 * R], const MethodConst &mc, int oi,
+                                                int q0, double (&out)[NV][NP])
 {
     const int lvl = select_level<R>(s, mc.thr);
     if constexpr (R == 1) {
@@ -165,22 +168,23 @@ __device__ __forceinline__ int reconstruct_cell(const double (&W)[NV][2 * R + 1]
         const double al = df_alpha(s[0] + s[1], mc.thr);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double a1 = W[v][2] - W[v][1];
-            const double a2 = 0.5 * (W[v][0] - 2.0 * W[v][1] + W[v][2]);
+            const double Wm = ld(v, -1), W0 = ld(v, 0), Wp = ld(v, 1);
+            const double a1 = Wp - W0;
+            const double a2 = 0.5 * (Wm - 2.0 * W0 + Wp);
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
                 const double *z = c_tab.z[oi][q0 + q];
-                out[v][q] = W[v][1] + al * (a1 * z[0] + a2 * z[1]);
+                out[v][q] = W0 + al * (a1 * z[0] + a2 * z[1]);
             }
         }
         return lvl;
     } else {
         if (lvl == 9) {
-            if constexpr (R >= 4) eval_linear<R, NV, NP, 4>(W, oi, 3, q0, out);
+            if constexpr (R >= 4) eval_linear<NV, NP, 4>(ld, oi, 3, q0, out);
         } else if (lvl == 7) {
-            if constexpr (R >= 3) eval_linear<R, NV, NP, 3>(W, oi, 2, q0, out);
+            if constexpr (R >= 3) eval_linear<NV, NP, 3>(ld, oi, 2, q0, out);
         } else if (lvl == 5) {
-            eval_linear<R, NV, NP, 2>(W, oi, 1, q0, out);
+            eval_linear<NV, NP, 2>(ld, oi, 1, q0, out);
         } else {
             double al[4];
             al[0] = df_alpha(ssum<R>(s, -2, 0), mc.thr);
@@ -189,8 +193,10 @@ __device__ __forceinline__ int reconstruct_cell(const double (&W)[NV][2 * R + 1]
             al[3] = df_alpha(ssum<R>(s, -2, 2), mc.thr);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                double o[NP];
-                weno_ao53<R, NP>(&W[v][R], al, mc, oi, q0, o);
+                double W[5], o[NP];
+#pragma unroll
+                for (int m = -2; m <= 2; ++m) W[m + 2] = ld(v, m);
+                weno_ao53<NP>(W, al, mc, oi, q0, o);
 #pragma unroll
                 for (int q = 0; q < NP; ++q) out[v][q] = o[q];
             }
@@ -202,6 +208,27 @@ __device__ __forceinline__ int reconstruct_cell(const double (&W)[NV][2 * R + 1]
 // ---------------------------------------------------------------------------
 // Euler equations (Sec. 2.3).
 // ---------------------------------------------------------------------------
+
+// Reciprocal and reciprocal square root: hardware estimate refined by two
+// Newton steps (error of a few ulp, far below the 1e-12 parity bound).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 struct Prim {
     double un, ut, p, c, ic;  // normal/tangential velocity, pressure, sound speed, 1/c
     bool ok;
@@ -213,26 +240,28 @@ __device__ __forceinline__ Prim primitives(const double (&W)[NV], int dir, const
 {
     Prim q;
     const double rho = W[0];
-    const double u = W[1] / rho;
+    const double ir = rcp_nr(rho);
+    const double u = W[1] * ir;
     double v = 0.0, ke;
     if constexpr (NV == 4) {
-        v = W[2] / rho;
-        ke = rho * (u * u + v * v);
+        v = W[2] * ir;
+        ke = W[1] * u + W[2] * v;   // rho (u^2 + v^2)
     } else {
-        ke = rho * (u * u);
+        ke = W[1] * u;
     }
     const double p = mc.gm1 * (W[NV - 1] - 0.5 * ke);
     q.un = dir == 0 ? u : v;
     q.ut = dir == 0 ? v : u;
     q.p = p;
     q.ok = (rho > 0.0) && (p > 0.0);
-    q.c = sqrt(mc.gamma * p / rho);
-    q.ic = 1.0 / q.c;
+    const double c2 = mc.gamma * p * ir;
+    q.ic = rsq_nr(c2);
+    q.c = c2 * q.ic;
     return q;
 }
 
 // Discontinuity strength of one Gauss point (Sec. 3.1); +inf if a side is
-// non-physical.
+// non-physical.  |pl-pr|/pl + |pl-pr|/pr is formed as |pl-pr| (pl+pr)/(pl pr).
 __device__ __forceinline__ double sigma_point(const Prim &l, const Prim &r)
 {
     // No contraction: equal states must give exactly zero.
@@ -241,7 +270,7 @@ __device__ __forceinline__ double sigma_point(const Prim &l, const Prim &r)
     const double dp = fabs(l.p - r.p);
     const double dn = l.un * l.ic - r.un * r.ic;
     const double dt = l.ut * l.ic - r.ut * r.ic;
-    return dp / l.p + dp / r.p + dn * dn + dt * dt;
+    return dp * (l.p + r.p) * rcp_nr(l.p * r.p) + dn * dn + dt * dt;
 }
 
 // Physical flux along dir.
@@ -275,11 +304,11 @@ __device__ __forceinline__ void lf_flux(const double (&Wl)[NV], const Prim &ql, 
 }
 
 // Strength and LF flux at one Gauss point, with the optional positivity
-// replacement of a non-physical side by its cell average.
-template <int NV>
-__device__ __forceinline__ double gauss_point(double (&Wl)[NV], double (&Wr)[NV], const double (&Cl)[NV],
-                                              const double (&Cr)[NV], int dir, const MethodConst &mc,
-                                              double (&F)[NV])
+// replacement of a non-physical side by its cell average (fetched lazily:
+// cl(v) / cr(v) return variable v of the left / right cell average).
+template <int NV, class CL, class CR>
+__device__ __forceinline__ double gauss_point(double (&Wl)[NV], double (&Wr)[NV], CL cl, CR cr, int dir,
+                                              const MethodConst &mc, double (&F)[NV])
 {
     Prim ql = primitives<NV>(Wl, dir, mc);
     Prim qr = primitives<NV>(Wr, dir, mc);
@@ -287,17 +316,27 @@ __device__ __forceinline__ double gauss_point(double (&Wl)[NV], double (&Wr)[NV]
     if (mc.flags & 1) {
         if (!ql.ok) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Wl[v] = Cl[v];
+            for (int v = 0; v < NV; ++v) Wl[v] = cl(v);
             ql = primitives<NV>(Wl, dir, mc);
         }
         if (!qr.ok) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Wr[v] = Cr[v];
+            for (int v = 0; v < NV; ++v) Wr[v] = cr(v);
             qr = primitives<NV>(Wr, dir, mc);
         }
     }
     lf_flux<NV>(Wl, ql, Wr, qr, dir, F);
     return sg;
+}
+
+// Exchange a double with the neighbouring lane (lane ^ 1) of a pair.  Both
+// lanes of the pair must be active.
+__device__ __forceinline__ double swap_pair(double x)
+{
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    const int lo2 = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+    const int hi2 = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(hi2, lo2);
 }
 
 #endif  // ASE_KERNEL_TU

@@ -250,24 +250,44 @@ __global__ void __launch_bounds__(kThreads) k_cfl_final(const double *part, int 
 }
 
 // ---------------------------------------------------------------------------
-// 2D sweep: one tile of T0 x T1 cells, faces of direction DIR.
+// 2D sweep: one tile of T0 x T1 cells, faces of direction DIR, NT threads.
+//
+// Phase 1 reconstructs, along DIR, every cell whose face values the tile's
+// tangential stencils need (normal reconstruction; one cell per thread).
+// Phase 2 gives each face two adjacent lanes, one per side: each lane runs
+// the tangential reconstruction of its side to the G Gauss points, the pair
+// swaps half of the Gauss states (lane ^ 1) so that each lane evaluates
+// strengths and LF fluxes at half of the points, and a second swap sums the
+// quadrature.  Phase 3 forms flux differences and, in the second sweep, the
+// SSP-RK3 stage combination.
 // ---------------------------------------------------------------------------
-template <int DIR, int R, int T0, int T1, int MODE>
-__global__ void __launch_bounds__(kThreads) k_sweep2d(SweepArgs a)
+template <int DIR, int R, int T0, int T1>
+struct SweepShape {
+    static constexpr int UX = (DIR == 0) ? T0 + 2 + 2 * R : T0 + 2 * R;  // staged cells
+    static constexpr int UY = (DIR == 0) ? T1 + 2 * R : T1 + 2 + 2 * R;
+    static constexpr int TX = (DIR == 0) ? T0 + 2 : T0 + 2 * R;          // face traces
+    static constexpr int TY = (DIR == 0) ? T1 + 2 * R : T1 + 2;
+    static constexpr int FX = (DIR == 0) ? T0 + 1 : T0;                  // faces
+    static constexpr int FY = (DIR == 0) ? T1 : T1 + 1;
+};
+
+template <int DIR, int R, int T0, int T1, int NT, int MODE>
+__global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
 {
     constexpr int NV = 4, G = R, OI = R - 1;
-    constexpr int UX = (DIR == 0) ? T0 + 2 + 2 * R : T0 + 2 * R;
-    constexpr int UY = (DIR == 0) ? T1 + 2 * R : T1 + 2 + 2 * R;
-    constexpr int TX = (DIR == 0) ? T0 + 2 : T0 + 2 * R;
-    constexpr int TY = (DIR == 0) ? T1 + 2 * R : T1 + 2;
-    constexpr int FX = (DIR == 0) ? T0 + 1 : T0;
-    constexpr int FY = (DIR == 0) ? T1 : T1 + 1;
-    __shared__ double sU[NV][UY][UX];
+    using S = SweepShape<DIR, R, T0, T1>;
+    constexpr int UX = S::UX, UY = S::UY, TX = S::TX, TY = S::TY, FX = S::FX, FY = S::FY;
+    constexpr int GA = (G + 1) / 2;   // Gauss points evaluated by the lower/left lane of a pair
+    constexpr int NU = NV * UY * UX;
+    constexpr int NF = (MODE == MODE_RECON) ? 0 : NV * FY * FX;
+    static_assert(NF <= NU, "flux tile must fit in the state tile");
+    __shared__ double sUF[NU];        // staged state; reused for the face fluxes
     __shared__ double sSX[UY][UX];
     __shared__ double sSY[UY][UX];
     __shared__ double sTR[NV][TY][TX];
     __shared__ double sTL[NV][TY][TX];
-    __shared__ double sF[MODE == MODE_RECON ? 1 : NV][FY][FX];
+    auto sU = [&](int v, int y, int x) -> double & { return sUF[(v * UY + y) * UX + x]; };
+    auto sF = [&](int v, int y, int x) -> double & { return sUF[(v * FY + y) * FX + x]; };
 
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x * T0, j0 = blockIdx.y * T1;
@@ -278,7 +298,7 @@ __global__ void __launch_bounds__(kThreads) k_sweep2d(SweepArgs a)
     if (MODE != MODE_RECON && a.skip != nullptr && *a.skip != 0.0) {
         // finished run: carry the strengths of the owned flux faces over
         const double *sin = DIR == 0 ? a.sx : a.sy;
-        for (int it = tid; it < FX * FY; it += kThreads) {
+        for (int it = tid; it < FX * FY; it += NT) {
             const int fx = it % FX, fy = it / FX;
             const int x = DIR == 0 ? i0 - 1 + fx : i0 + fx;
             const int y = DIR == 0 ? j0 + fy : j0 - 1 + fy;
@@ -293,20 +313,20 @@ __global__ void __launch_bounds__(kThreads) k_sweep2d(SweepArgs a)
     }
 
     // stage the halo tile
-    for (int it = tid; it < UX * UY; it += kThreads) {
+    for (int it = tid; it < UX * UY; it += NT) {
         const int lx = it % UX, ly = it / UX;
         const int I = ox + lx + a.ng, J = oy + ly + a.ng;
         const bool in = I < a.NX && J < a.NY;
         const long long pos = (long long)J * a.ld + I;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sU[v][ly][lx] = in ? a.U[v * a.plane + pos] : 0.0;
+        for (int v = 0; v < NV; ++v) sU(v, ly, lx) = in ? a.U[v * a.plane + pos] : 0.0;
         sSX[ly][lx] = in ? a.sx[pos] : 0.0;
         sSY[ly][lx] = in ? a.sy[pos] : 0.0;
     }
     __syncthreads();
 
-    // normal reconstruction: face traces of every cell the tile needs
-    for (int it = tid; it < TX * TY; it += kThreads) {
+    // phase 1: normal reconstruction, face traces of every cell the tile needs
+    for (int it = tid; it < TX * TY; it += NT) {
         const int tx = it % TX, ty = it / TX;
         const int lx = (DIR == 0) ? tx + R : tx;
         const int ly = (DIR == 0) ? ty : ty + R;
@@ -314,15 +334,11 @@ __global__ void __launch_bounds__(kThreads) k_sweep2d(SweepArgs a)
         const bool need = (DIR == 0) ? (x <= a.nx && y < a.ny + R) : (x < a.nx + R && y <= a.ny);
         if (!need) continue;
         double s[2 * R];
-        double W[NV][2 * R + 1];
 #pragma unroll
         for (int m = -R; m < R; ++m) s[m + R] = (DIR == 0) ? sSX[ly][lx + m] : sSY[ly + m][lx];
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int m = -R; m <= R; ++m) W[v][m + R] = (DIR == 0) ? sU[v][ly][lx + m] : sU[v][ly + m][lx];
+        auto ld = [&](int v, int m) { return (DIR == 0) ? sU(v, ly, lx + m) : sU(v, ly + m, lx); };
         double out[NV][2];
-        const int lvl = reconstruct_cell<R, NV, 2>(W, s, mc, OI, 0, out);
+        const int lvl = reconstruct_cell<R, NV, 2>(ld, s, mc, OI, 0, out);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             sTR[v][ty][tx] = out[v][0];
@@ -333,80 +349,113 @@ __global__ void __launch_bounds__(kThreads) k_sweep2d(SweepArgs a)
     }
     __syncthreads();
 
-    // tangential reconstruction, strengths and fluxes at the Gauss points
-    for (int it = tid; it < FX * FY; it += kThreads) {
-        const int fx = it % FX, fy = it / FX;
+    // phase 2: two lanes per face (side = lane & 1)
+    constexpr int NITEMS = 2 * FX * FY;
+    for (int base = 0; base < NITEMS; base += NT) {   // uniform trip count: lane pairs swap together
+        const int it = base + tid;
+        const int side = it & 1, f = it >> 1;
+        const int fx = f % FX, fy = f / FX;
         const int x = DIR == 0 ? i0 - 1 + fx : i0 + fx;
         const int y = DIR == 0 ? j0 + fy : j0 - 1 + fy;
-        if (DIR == 0 ? (x > a.nx - 1 || y >= a.ny) : (x >= a.nx || y > a.ny - 1)) continue;
-        double WL[NV][G], WR[NV][G];
-        {
-            double Wt[NV][2 * R + 1], s[2 * R];
+        const bool valid = it < NITEMS && (DIR == 0 ? (x <= a.nx - 1 && y < a.ny) : (x < a.nx && y <= a.ny - 1));
+        double Ws[NV][G];
+        if (valid) {
+            double s[2 * R];
+            // this side's face traces: right-face values of the left (lower)
+            // cell, left-face values of the right (upper) cell
+            const double *tr = side == 0 ? &sTR[0][0][0] : &sTL[0][0][0];
+            if (DIR == 0) {
+                const int tx = fx + side;
+#pragma unroll
+                for (int m = -R; m < R; ++m) s[m + R] = sSY[fy + R + m][tx + R];
+                auto ld = [&](int v, int m) { return tr[(v * TY + fy + R + m) * TX + tx]; };
+                reconstruct_cell<R, NV, G>(ld, s, mc, OI, 2, Ws);
+            } else {
+                const int ty = fy + side;
+#pragma unroll
+                for (int m = -R; m < R; ++m) s[m + R] = sSX[ty + R][fx + R + m];
+                auto ld = [&](int v, int m) { return tr[(v * TY + ty) * TX + fx + R + m]; };
+                reconstruct_cell<R, NV, G>(ld, s, mc, OI, 2, Ws);
+            }
+        } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int m = -R; m <= R; ++m)
-                    Wt[v][m + R] = (DIR == 0) ? sTR[v][fy + R + m][fx] : sTR[v][fy][fx + R + m];
-#pragma unroll
-            for (int m = -R; m < R; ++m) s[m + R] = (DIR == 0) ? sSY[fy + R + m][fx + R] : sSX[fy + R][fx + R + m];
-            reconstruct_cell<R, NV, G>(Wt, s, mc, OI, 2, WL);
-        }
-        {
-            double Wt[NV][2 * R + 1], s[2 * R];
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int m = -R; m <= R; ++m)
-                    Wt[v][m + R] = (DIR == 0) ? sTL[v][fy + R + m][fx + 1] : sTL[v][fy + 1][fx + R + m];
-#pragma unroll
-            for (int m = -R; m < R; ++m)
-                s[m + R] = (DIR == 0) ? sSY[fy + R + m][fx + R + 1] : sSX[fy + R + 1][fx + R + m];
-            reconstruct_cell<R, NV, G>(Wt, s, mc, OI, 2, WR);
+                for (int k = 0; k < G; ++k) Ws[v][k] = 1.0;
         }
         if constexpr (MODE == MODE_RECON) {
-            const long long fid = DIR == 0 ? (long long)y * (a.nx + 1) + (x + 1) : (long long)(y + 1) * a.nx + x;
+            if (valid) {
+                const long long fid =
+                    DIR == 0 ? (long long)y * (a.nx + 1) + (x + 1) : (long long)(y + 1) * a.nx + x;
+                double *dst = side == 0 ? a.wl : a.wr;
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int k = 0; k < G; ++k) dst[(long long)(v * G + k) * a.nfaces + fid] = Ws[v][k];
+            }
+        } else {
+            // lane 0 of the pair evaluates points [0, GA), lane 1 points [GA, G)
+            constexpr int GB = G - GA;
+            double lo[NV][GA], hi[NV][GA];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int k = 0; k < G; ++k) {
-                    a.wl[(long long)(v * G + k) * a.nfaces + fid] = WL[v][k];
-                    a.wr[(long long)(v * G + k) * a.nfaces + fid] = WR[v][k];
+                for (int j = 0; j < GA; ++j) {
+                    lo[v][j] = Ws[v][j];
+                    hi[v][j] = 0.0;
                 }
-        } else {
-            double Cl[NV], Cr[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                Cl[v] = sU[v][fy + R][fx + R];
-                Cr[v] = DIR == 0 ? sU[v][fy + R][fx + R + 1] : sU[v][fy + R + 1][fx + R];
-            }
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int j = 0; j < GB; ++j) hi[v][j] = Ws[v][GA + j];
             double Fs[NV], ssum = 0.0;
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fs[v] = 0.0;
+            const long long pl = (long long)(y + a.ng) * a.ld + x + a.ng;
+            const long long pr = DIR == 0 ? pl + 1 : pl + a.ld;
+            const double *U = a.U;
+            const long long P = a.plane;
+            auto cl = [=](int v) { return U[v * P + pl]; };
+            auto cr = [=](int v) { return U[v * P + pr]; };
 #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                double Wl[NV], Wr[NV], Fk[NV];
+            for (int j = 0; j < GA; ++j) {
+                double Wl[NV], Wr[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    Wl[v] = WL[v][k];
-                    Wr[v] = WR[v][k];
+                    const double own = side == 0 ? lo[v][j] : hi[v][j];
+                    const double other = swap_pair(side == 0 ? hi[v][j] : lo[v][j]);
+                    Wl[v] = side == 0 ? own : other;
+                    Wr[v] = side == 0 ? other : own;
                 }
-                ssum += gauss_point<NV>(Wl, Wr, Cl, Cr, DIR, mc, Fk);
-                const double eta = c_tab.eta[OI][k];
+                const bool has = valid && (side == 0 || j < GB);
+                if (has) {
+                    double Fk[NV];
+                    ssum += gauss_point<NV>(Wl, Wr, cl, cr, DIR, mc, Fk);
+                    const double eta = c_tab.eta[OI][side == 0 ? j : GA + j];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) Fs[v] += eta * Fk[v];
+                    for (int v = 0; v < NV; ++v) Fs[v] = fma(eta, Fk[v], Fs[v]);
+                }
             }
 #pragma unroll
-            for (int v = 0; v < NV; ++v) sF[v][fy][fx] = Fs[v];
-            const bool own = DIR == 0 ? (fx > 0 || i0 == 0) : (fy > 0 || j0 == 0);
-            if (own) a.sig_out[(long long)(y + a.ng) * a.ld + x + a.ng] = ssum / (double)G;
+            for (int v = 0; v < NV; ++v) Fs[v] += swap_pair(Fs[v]);
+            ssum += swap_pair(ssum);
+            if (valid && side == 0) {
+                const bool own = DIR == 0 ? (fx > 0 || i0 == 0) : (fy > 0 || j0 == 0);
+                if (own) a.sig_out[(long long)(y + a.ng) * a.ld + x + a.ng] = ssum / (double)G;
+            }
+            // the flux tile reuses the state tile: phase 2 reads no staged state
+            if (valid && side == 0) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sF(v, fy, fx) = Fs[v];
+            }
         }
     }
     if constexpr (MODE == MODE_RECON) return;
     __syncthreads();
 
-    // flux differences and (second sweep) the stage update
+    // phase 3: flux differences and (second sweep) the stage update
     const double dt = (MODE == MODE_FUSED_Y) ? *a.dt : 0.0;
-    for (int it = tid; it < T0 * T1; it += kThreads) {
+    for (int it = tid; it < T0 * T1; it += NT) {
         const int cx = it % T0, cy = it / T0;
         const int x = i0 + cx, y = j0 + cy;
         if (x >= a.nx || y >= a.ny) continue;
@@ -415,10 +464,10 @@ __global__ void __launch_bounds__(kThreads) k_sweep2d(SweepArgs a)
         for (int v = 0; v < NV; ++v) {
             const long long e = v * a.plane + pos;
             if constexpr (DIR == 0) {
-                const double d = -(sF[v][cy][cx + 1] - sF[v][cy][cx]) * a.inv_dx;
+                const double d = -(sF(v, cy, cx + 1) - sF(v, cy, cx)) * a.inv_dx;
                 a.Res[e] = d;
             } else {
-                const double d = -(sF[v][cy + 1][cx] - sF[v][cy][cx]) * a.inv_dy;
+                const double d = -(sF(v, cy + 1, cx) - sF(v, cy, cx)) * a.inv_dy;
                 const double L = a.Res[e] + d;
                 double o;
                 if (a.stage == 1) o = a.Un[e] + dt * L;
@@ -473,15 +522,11 @@ __global__ void __launch_bounds__(kThreads) k_stage1d(SweepArgs a)
         const int x = ox + lx;
         if (x > a.nx) continue;
         double s[2 * R];
-        double W[NV][2 * R + 1];
 #pragma unroll
         for (int m = -R; m < R; ++m) s[m + R] = sS[lx + m];
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int m = -R; m <= R; ++m) W[v][m + R] = sU[v][lx + m];
+        auto ld = [&](int v, int m) { return sU[v][lx + m]; };
         double out[NV][2];
-        const int lvl = reconstruct_cell<R, NV, 2>(W, s, mc, OI, 0, out);
+        const int lvl = reconstruct_cell<R, NV, 2>(ld, s, mc, OI, 0, out);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             sTR[v][tx] = out[v][0];
@@ -507,13 +552,10 @@ __global__ void __launch_bounds__(kThreads) k_stage1d(SweepArgs a)
                 a.wr[(long long)v * a.nfaces + x + 1] = Wr[v];
             }
         } else {
-            double Cl[NV], Cr[NV], F[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                Cl[v] = sU[v][fx + R];
-                Cr[v] = sU[v][fx + R + 1];
-            }
-            const double sg = gauss_point<NV>(Wl, Wr, Cl, Cr, 0, mc, F);
+            double F[NV];
+            auto cl = [&](int v) { return sU[v][fx + R]; };
+            auto cr = [&](int v) { return sU[v][fx + R + 1]; };
+            const double sg = gauss_point<NV>(Wl, Wr, cl, cr, 0, mc, F);
 #pragma unroll
             for (int v = 0; v < NV; ++v) sF[v][fx] = F[v];
             if (fx > 0 || i0 == 0) a.sig_out[x + a.ng] = sg;
@@ -693,7 +735,11 @@ void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, cons
 }
 
 namespace {
-constexpr int kT0 = 16, kT1 = 16, kT1D = 256;
+constexpr int kT1D = 256;
+constexpr int kNT2D = 512;
+// 2D tiles: (T0 + 1) x T1 x-faces and T0 x (T1 + 1) y-faces = 256 faces,
+// i.e. one face per lane pair of a 512-thread block.
+constexpr int kX_T0 = 15, kX_T1 = 16, kY_T0 = 16, kY_T1 = 15;
 
 template <int R>
 void sweep_r(const Geo &geo, int dir, int mode, const SweepArgs &a, hipStream_t st)
@@ -704,13 +750,14 @@ void sweep_r(const Geo &geo, int dir, int mode, const SweepArgs &a, hipStream_t 
         else k_stage1d<R, kT1D, MODE_FUSED_1D><<<grid, kThreads, 0, st>>>(a);
         return;
     }
-    dim3 grid((geo.nx + kT0 - 1) / kT0, (geo.ny + kT1 - 1) / kT1);
     if (dir == 0) {
-        if (mode == MODE_RECON) k_sweep2d<0, R, kT0, kT1, MODE_RECON><<<grid, kThreads, 0, st>>>(a);
-        else k_sweep2d<0, R, kT0, kT1, MODE_FUSED_X><<<grid, kThreads, 0, st>>>(a);
+        dim3 grid((geo.nx + kX_T0 - 1) / kX_T0, (geo.ny + kX_T1 - 1) / kX_T1);
+        if (mode == MODE_RECON) k_sweep2d<0, R, kX_T0, kX_T1, kNT2D, MODE_RECON><<<grid, kNT2D, 0, st>>>(a);
+        else k_sweep2d<0, R, kX_T0, kX_T1, kNT2D, MODE_FUSED_X><<<grid, kNT2D, 0, st>>>(a);
     } else {
-        if (mode == MODE_RECON) k_sweep2d<1, R, kT0, kT1, MODE_RECON><<<grid, kThreads, 0, st>>>(a);
-        else k_sweep2d<1, R, kT0, kT1, MODE_FUSED_Y><<<grid, kThreads, 0, st>>>(a);
+        dim3 grid((geo.nx + kY_T0 - 1) / kY_T0, (geo.ny + kY_T1 - 1) / kY_T1);
+        if (mode == MODE_RECON) k_sweep2d<1, R, kY_T0, kY_T1, kNT2D, MODE_RECON><<<grid, kNT2D, 0, st>>>(a);
+        else k_sweep2d<1, R, kY_T0, kY_T1, kNT2D, MODE_FUSED_Y><<<grid, kNT2D, 0, st>>>(a);
     }
 }
 }  // namespace
