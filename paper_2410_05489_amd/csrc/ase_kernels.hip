@@ -75,15 +75,37 @@ __device__ __forceinline__ bool src_cell(const BCInfo &b, int I, int J, int &Is,
     return true;
 }
 
+// Ghost frame: full ghost rows (2D) followed by the ghost columns of the
+// interior rows.  frame_size() cells, enumerated by frame_cell().
+__host__ __device__ __forceinline__ long long frame_size(const BCInfo &b)
+{
+    const long long side = (long long)(b.dim == 1 ? 1 : b.ny) * 2 * b.ng;
+    return (b.dim == 1 ? 0 : 2LL * b.ng * b.NX) + side;
+}
+
+__device__ __forceinline__ void frame_cell(const BCInfo &b, long long idx, int &I, int &J)
+{
+    const long long rows = b.dim == 1 ? 0 : 2LL * b.ng * b.NX;
+    if (idx < rows) {
+        const int r = (int)(idx / b.NX);
+        J = r < b.ng ? r : r + b.ny;
+        I = (int)(idx % b.NX);
+    } else {
+        const long long q = idx - rows;
+        const int c = (int)(q % (2 * b.ng));
+        J = b.dim == 1 ? 0 : b.ng + (int)(q / (2 * b.ng));
+        I = c < b.ng ? c : c + b.nx;
+    }
+}
+
 template <int NV>
 __global__ void __launch_bounds__(kThreads) k_bc_cells(BCInfo b, double *U)
 {
-    const long long n = (long long)b.NY * b.NX;
+    const long long n = frame_size(b);
     for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * kThreads) {
-        const int J = (int)(idx / b.NX), I = (int)(idx % b.NX);
-        const bool ghost = (I < b.ng || I >= b.ng + b.nx) || (b.dim == 2 && (J < b.ng || J >= b.ng + b.ny));
-        if (!ghost) continue;
+        int I, J;
+        frame_cell(b, idx, I, J);
         int Is, Js;
         const long long dst = (long long)J * b.ld + I;
         if (src_cell(b, I, J, Is, Js)) {
@@ -116,16 +138,24 @@ __device__ __forceinline__ int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
 // Strengths of the stored faces that are not flux faces.  init = true sets
 // every stored face to its first-order strength.
+// init = 1: every stored face (whole array); init = 0: only the faces of
+// the ghost frame that are not flux faces.
 template <int NV>
 __global__ void __launch_bounds__(kThreads) k_bc_sigma(BCInfo b, MethodConst mc, const double *U, double *sx,
                                                        double *sy, int init)
 {
-    const long long n = (long long)b.NY * b.NX;
+    const long long n = init ? (long long)b.NY * b.NX : frame_size(b);
     const bool xper = b.bc[0] == ASE_BC_PERIODIC;
     const bool yper = b.dim == 2 && b.bc[2] == ASE_BC_PERIODIC;
     for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * kThreads) {
-        const int J = (int)(idx / b.NX), I = (int)(idx % b.NX);
+        int I, J;
+        if (init) {
+            J = (int)(idx / b.NX);
+            I = (int)(idx % b.NX);
+        } else {
+            frame_cell(b, idx, I, J);
+        }
         const long long pos = (long long)J * b.ld + I;
         // x-face between (I,J) and (I+1,J)
         if (I + 1 < b.NX) {
@@ -271,6 +301,22 @@ struct SweepShape {
     static constexpr int FY = (DIR == 0) ? T1 : T1 + 1;
 };
 
+// Tile of this workgroup.  Workgroups are dispatched round-robin over the
+// 8 XCDs (each with its own L2); remapping the linear block index so that
+// every XCD receives one contiguous band of tiles keeps the halos that
+// neighbouring tiles share inside one L2.
+__device__ __forceinline__ void xcd_tile(int &tx, int &ty)
+{
+    constexpr int kXCD = 8;
+    const int gx = gridDim.x, n = gridDim.x * gridDim.y;
+    const int b = blockIdx.y * gx + blockIdx.x;
+    const int per = n / kXCD;
+    int t = b;
+    if (b < per * kXCD) t = (b % kXCD) * per + b / kXCD;
+    tx = t % gx;
+    ty = t / gx;
+}
+
 template <int DIR, int R, int T0, int T1, int NT, int MODE>
 __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
 {
@@ -290,7 +336,9 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
     auto sF = [&](int v, int y, int x) -> double & { return sUF[(v * FY + y) * FX + x]; };
 
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * T0, j0 = blockIdx.y * T1;
+    int btx, bty;
+    xcd_tile(btx, bty);
+    const int i0 = btx * T0, j0 = bty * T1;
     const int ox = (DIR == 0) ? i0 - 1 - R : i0 - R;
     const int oy = (DIR == 0) ? j0 - R : j0 - 1 - R;
     const MethodConst &mc = a.mc;
@@ -691,7 +739,7 @@ void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, 
                     hipStream_t st)
 {
     const BCInfo b = make_bc(g, geo);
-    const int nb = grid_blocks((long long)geo.NY * geo.NX);
+    const int nb = grid_blocks(frame_size(b));
     if (geo.nv == 4) {
         k_bc_cells<4><<<nb, kThreads, 0, st>>>(b, U);
         k_bc_sigma<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
@@ -705,12 +753,13 @@ void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &m
                        double *sy, hipStream_t st)
 {
     const BCInfo b = make_bc(g, geo);
+    const int nf = grid_blocks(frame_size(b));
     const int nb = grid_blocks((long long)geo.NY * geo.NX);
     if (geo.nv == 4) {
-        k_bc_cells<4><<<nb, kThreads, 0, st>>>(b, U);
+        k_bc_cells<4><<<nf, kThreads, 0, st>>>(b, U);
         k_bc_sigma<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
     } else {
-        k_bc_cells<3><<<nb, kThreads, 0, st>>>(b, U);
+        k_bc_cells<3><<<nf, kThreads, 0, st>>>(b, U);
         k_bc_sigma<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
     }
 }
