@@ -16,8 +16,6 @@ namespace ase {
 
 namespace {
 thread_local std::string g_err;
-std::mutex g_tab_mu;
-bool g_tab_ok[64] = {false};
 constexpr size_t kAlign = 256;
 constexpr int kMaxParts = 1024;
 
@@ -35,22 +33,6 @@ int fail(int code, const std::string &msg)
 int hip_fail(hipError_t e, const char *what)
 {
     return fail(ASE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-int ensure_tables()
-{
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev < 0 || dev >= 64) return fail(ASE_ERR_HIP, "device index out of range");
-    std::lock_guard<std::mutex> lk(g_tab_mu);
-    if (g_tab_ok[dev]) return ASE_OK;
-    Tables t;
-    build_tables(&t);
-    e = upload_tables(t);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyToSymbol(tables)");
-    g_tab_ok[dev] = true;
-    return ASE_OK;
 }
 
 int validate(const ase_grid_t *g, const ase_params_t *p, Geo *geo)
@@ -93,7 +75,7 @@ int validate(const ase_grid_t *g, const ase_params_t *p, Geo *geo)
     geo->R = (r - 1) / 2;
     geo->G = g->dim == 1 ? 1 : (r - 1) / 2;
     geo->oi = (r - 3) / 2;
-    return ensure_tables();
+    return ASE_OK;
 }
 
 MethodConst method_const(const ase_params_t *p)

@@ -3,10 +3,10 @@
 // (linear stencils and the WENO-Z-AO(5,3) fallback), Euler primitives, the
 // discontinuity strength and the Lax-Friedrichs flux.
 //
-// Everything is FP64.  Linear reconstructions are applied as precomputed
-// point-evaluation weights (the paper's zero-mean stencil coefficients
-// contracted with the basis at the evaluation point, built on the host by
-// ase_tables.cpp); the DF sums are formed left to right across the stencil.
+// Everything is FP64.  Linear reconstructions are applied as point-evaluation
+// weights (the paper's zero-mean stencil coefficients contracted with the
+// basis at the evaluation point, tabulated at compile time); the DF sums are
+// formed left to right across the stencil.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,6 +30,125 @@ struct Tables {
     double eta[4][4];
 };
 
+// ---------------------------------------------------------------------------
+// Compile-time construction of the tables.  The kernels index them with
+// compile-time constants, so every weight becomes an instruction literal.
+//
+// Stencil coefficients: the zero-mean polynomial coefficients W_xk of the 3-,
+// 5-, 7- and 9-cell stencils printed in Sec. 3.2-3.4 (with W_3 for the
+// misprinted f_3 of the 7-cell W_x1), as integer numerators over a common
+// denominator, taps W_{-h}..W_{h}.  Zero-mean basis on the cell [-1,0]:
+// Z_k(xi) = xi^k - (-1)^k/(k+1), under which those coefficients are the exact
+// cell-average fit.  P(xi) = W_0 + sum_k W_xk Z_k(xi) is linear in the taps;
+// its weights at each evaluation point are tabulated.
+// ---------------------------------------------------------------------------
+namespace tables {
+
+struct Stencil {
+    int h;           // half width
+    int ncoef;       // coefficients W_x1..W_xn
+    double den[8];
+    double num[8][9];  // num[k][m+h]
+};
+
+constexpr Stencil kS3 = {1, 2, {1, 2}, {{0, -1, 1}, {1, -2, 1}}};
+constexpr Stencil kS5 = {2, 4, {12, 8, 6, 24},
+                         {{0, 1, -15, 15, -1}, {-1, 6, -8, 2, 1}, {0, -1, 3, -3, 1}, {1, -4, 6, -4, 1}}};
+constexpr Stencil kS7 = {3, 6, {180, 240, 36, 144, 120, 720},
+                         {{0, -2, 25, -245, 245, -25, 2},
+                          {7, -57, 210, -230, 15, 63, -8},
+                          {0, 1, -11, 28, -28, 11, -1},
+                          {-2, 15, -39, 46, -24, 3, 1},
+                          {0, -1, 5, -10, 10, -5, 1},
+                          {1, -6, 15, -20, 15, -6, 1}}};
+constexpr Stencil kS9 = {4, 8, {5040, 30240, 1440, 3456, 480, 8640, 5040, 40320},
+                         {{0, 9, -119, 889, -7175, 7175, -889, 119, -9},
+                          {-205, 2081, -9835, 28679, -27895, -2065, 11459, -2455, 236},
+                          {0, -7, 89, -587, 1365, -1365, 587, -89, 7},
+                          {13, -128, 556, -1160, 1174, -464, -68, 88, -11},
+                          {0, 1, -11, 41, -75, 75, -41, 11, -1},
+                          {-5, 46, -170, 334, -380, 250, -86, 10, 1},
+                          {0, -1, 7, -21, 35, -35, 21, -7, 1},
+                          {1, -8, 28, -56, 70, -56, 28, -8, 1}}};
+
+// Newton iteration from above: monotone, converges to the root within an ulp.
+constexpr double csqrt(double x)
+{
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 200; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+
+constexpr double zk(int k, double xi)
+{
+    double p = 1.0;
+    for (int i = 0; i < k; ++i) p *= xi;
+    return p - ((k % 2 == 0) ? 1.0 : -1.0) / double(k + 1);
+}
+
+// Gauss-Legendre nodes on [-1/2, 1/2] and weights normalised to 1.
+constexpr void gauss_nodes(int G, double *x, double *w)
+{
+    if (G == 1) {
+        x[0] = 0.0;
+        w[0] = 1.0;
+    } else if (G == 2) {
+        const double a = 1.0 / (2.0 * csqrt(3.0));
+        x[0] = -a;
+        x[1] = a;
+        w[0] = w[1] = 0.5;
+    } else if (G == 3) {
+        const double a = csqrt(0.15);   // sqrt(3/5)/2
+        x[0] = -a;
+        x[1] = 0.0;
+        x[2] = a;
+        w[0] = w[2] = 5.0 / 18.0;
+        w[1] = 4.0 / 9.0;
+    } else {
+        const double t = 2.0 * csqrt(1.2) / 7.0;
+        const double in = 0.5 * csqrt(3.0 / 7.0 - t), out = 0.5 * csqrt(3.0 / 7.0 + t);
+        const double r30 = csqrt(30.0) / 72.0;
+        x[0] = -out;
+        x[1] = -in;
+        x[2] = in;
+        x[3] = out;
+        w[0] = w[3] = 0.25 - r30;
+        w[1] = w[2] = 0.25 + r30;
+    }
+}
+
+constexpr Tables make_tables()
+{
+    Tables t{};
+    const Stencil *st[4] = {&kS3, &kS5, &kS7, &kS9};
+    for (int oi = 0; oi < 4; ++oi) {
+        const int r = 2 * oi + 3;
+        const int G = (r - 1) / 2;
+        double pts[kMaxPts] = {0.0, -1.0, 0.0, 0.0, 0.0, 0.0};
+        double gx[4] = {0, 0, 0, 0}, gw[4] = {0, 0, 0, 0};
+        gauss_nodes(G, gx, gw);
+        for (int k = 0; k < G; ++k) {
+            pts[2 + k] = -0.5 + gx[k];
+            t.eta[oi][k] = gw[k];
+        }
+        for (int q = 0; q < 2 + G; ++q) {
+            for (int k = 1; k <= 4; ++k) t.z[oi][q][k - 1] = zk(k, pts[q]);
+            for (int li = 0; li < 4; ++li) {
+                const Stencil &S = *st[li];
+                t.lin[oi][li][q][4] = 1.0;  // W_0
+                for (int k = 1; k <= S.ncoef; ++k) {
+                    const double zq = zk(k, pts[q]);
+                    for (int m = -S.h; m <= S.h; ++m)
+                        t.lin[oi][li][q][4 + m] += S.num[k - 1][m + S.h] / S.den[k - 1] * zq;
+                }
+            }
+        }
+    }
+    return t;
+}
+
+}  // namespace tables
+
 struct MethodConst {
     double gamma, gm1;          // gamma, gamma - 1
     double thr;                 // sigma_thres
@@ -42,7 +161,7 @@ struct MethodConst {
 
 #if defined(ASE_KERNEL_TU)
 // Device code below is compiled only into the kernel translation unit.
-extern __constant__ Tables c_tab;
+__device__ constexpr Tables kTab = tables::make_tables();
 
 // ---------------------------------------------------------------------------
 // DF factor and level (Sec. 3.1 Eq. discontinuity strength; Algorithm 1 with
@@ -105,7 +224,7 @@ __device__ __forceinline__ void eval_linear(LD ld, int oi, int li, int q0, doubl
         for (int m = -H; m <= H; ++m) w[m + H] = ld(v, m);
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const double *c = c_tab.lin[oi][li][q0 + q];
+            const double *c = kTab.lin[oi][li][q0 + q];
             double acc = c[4 - H] * w[0];
 #pragma unroll
             for (int m = -H + 1; m <= H; ++m) acc = fma(c[4 + m], w[m + H], acc);
@@ -146,7 +265,7 @@ __device__ __forceinline__ void weno_ao53(const double (&W)[5], const double al[
     const double o5 = w5 * inv, om = wm * inv, o0 = w0 * inv, op = wp * inv;
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-        const double *z = c_tab.z[oi][q0 + q];
+        const double *z = kTab.z[oi][q0 + q];
         const double Pm = W0 + al[0] * (am1 * z[0] + am2 * z[1]);
         const double P0 = W0 + al[1] * (a01 * z[0] + a02 * z[1]);
         const double Pp = W0 + al[2] * (ap1 * z[0] + ap2 * z[1]);
@@ -173,7 +292,7 @@ __device__ __forceinline__ int reconstruct_cell(LD ld, const double (&s)[2 * R],
             const double a2 = 0.5 * (Wm - 2.0 * W0 + Wp);
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                const double *z = c_tab.z[oi][q0 + q];
+                const double *z = kTab.z[oi][q0 + q];
                 out[v][q] = W0 + al * (a1 * z[0] + a2 * z[1]);
             }
         }
@@ -326,6 +445,40 @@ __device__ __forceinline__ double gauss_point(double (&Wl)[NV], double (&Wr)[NV]
         }
     }
     lf_flux<NV>(Wl, ql, Wr, qr, dir, F);
+    return sg;
+}
+
+// Strength and LF flux at one Gauss point seen from one side of the face:
+// Wo is this lane's own state, Wt the state across the face, sgn = +1 when
+// the own side is the left (lower) one and -1 otherwise.  Equal to
+// gauss_point with (Wl, Wr) = (Wo, Wt) or (Wt, Wo): the flux average, the
+// signal speed and the strength are symmetric in the two states.
+template <int NV, class CO, class CT>
+__device__ __forceinline__ double gauss_point_sided(double (&Wo)[NV], double (&Wt)[NV], double sgn, CO co, CT ct,
+                                                    int dir, const MethodConst &mc, double (&F)[NV])
+{
+    Prim qo = primitives<NV>(Wo, dir, mc);
+    Prim qt = primitives<NV>(Wt, dir, mc);
+    const double sg = sigma_point(qo, qt);
+    if (mc.flags & 1) {
+        if (!qo.ok) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Wo[v] = co(v);
+            qo = primitives<NV>(Wo, dir, mc);
+        }
+        if (!qt.ok) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Wt[v] = ct(v);
+            qt = primitives<NV>(Wt, dir, mc);
+        }
+    }
+    double Fo[NV], Ft[NV];
+    euler_flux<NV>(Wo, qo, dir, Fo);
+    euler_flux<NV>(Wt, qt, dir, Ft);
+    const double so = fabs(qo.un) + qo.c, st = fabs(qt.un) + qt.c;
+    const double hs = sgn * 0.5 * (so > st ? so : st);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = 0.5 * (Fo[v] + Ft[v]) - hs * (Wt[v] - Wo[v]);
     return sg;
 }
 

@@ -13,15 +13,11 @@
 
 namespace ase {
 
-void build_tables(Tables *t);
-hipError_t upload_tables(const Tables &t);
 
 // Thread-local error message; returns code.
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
-// Tables uploaded once per device.
-int ensure_tables();
 
 struct Geo {
     int dim, nx, ny, ng, ld, NX, NY, nv;

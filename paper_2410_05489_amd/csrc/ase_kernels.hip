@@ -13,12 +13,6 @@
 
 namespace ase {
 
-__constant__ Tables c_tab;
-
-hipError_t upload_tables(const Tables &t)
-{
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_tab), &t, sizeof(Tables), 0, hipMemcpyHostToDevice);
-}
 
 namespace {
 
@@ -330,8 +324,14 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
     __shared__ double sUF[NU];        // staged state; reused for the face fluxes
     __shared__ double sSX[UY][UX];
     __shared__ double sSY[UY][UX];
-    __shared__ double sTR[NV][TY][TX];
-    __shared__ double sTL[NV][TY][TX];
+    // right-face traces, then left-face traces; the second array starts 16
+    // doubles (a half turn of the LDS banks) after a bank-aligned boundary so
+    // that the two lanes of a face pair read different banks
+    constexpr int NT1 = NV * TY * TX;
+    constexpr int TOFF = (NT1 + 31) / 32 * 32 + 16;
+    __shared__ double sT[TOFF + NT1];
+    double(*sTR)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[0]);
+    double(*sTL)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[TOFF]);
     auto sU = [&](int v, int y, int x) -> double & { return sUF[(v * UY + y) * UX + x]; };
     auto sF = [&](int v, int y, int x) -> double & { return sUF[(v * FY + y) * FX + x]; };
 
@@ -465,21 +465,21 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
             const long long P = a.plane;
             auto cl = [=](int v) { return U[v * P + pl]; };
             auto cr = [=](int v) { return U[v * P + pr]; };
+            const double sgn = side == 0 ? 1.0 : -1.0;
 #pragma unroll
             for (int j = 0; j < GA; ++j) {
-                double Wl[NV], Wr[NV];
+                double Wown[NV], Woth[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const double own = side == 0 ? lo[v][j] : hi[v][j];
-                    const double other = swap_pair(side == 0 ? hi[v][j] : lo[v][j]);
-                    Wl[v] = side == 0 ? own : other;
-                    Wr[v] = side == 0 ? other : own;
+                    Wown[v] = side == 0 ? lo[v][j] : hi[v][j];
+                    Woth[v] = swap_pair(side == 0 ? hi[v][j] : lo[v][j]);
                 }
                 const bool has = valid && (side == 0 || j < GB);
                 if (has) {
                     double Fk[NV];
-                    ssum += gauss_point<NV>(Wl, Wr, cl, cr, DIR, mc, Fk);
-                    const double eta = c_tab.eta[OI][side == 0 ? j : GA + j];
+                    ssum += side == 0 ? gauss_point_sided<NV>(Wown, Woth, sgn, cl, cr, DIR, mc, Fk)
+                                      : gauss_point_sided<NV>(Wown, Woth, sgn, cr, cl, DIR, mc, Fk);
+                    const double eta = kTab.eta[OI][side == 0 ? j : GA + j];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) Fs[v] = fma(eta, Fk[v], Fs[v]);
                 }
@@ -683,7 +683,7 @@ __global__ void __launch_bounds__(kThreads) k_flux(FaceGeo f, MethodConst mc, in
             Wr[v] = wr[(long long)(v * f.G + k) * f.nfaces + id];
         }
         lf_flux<NV>(Wl, primitives<NV>(Wl, dir, mc), Wr, primitives<NV>(Wr, dir, mc), dir, Fk);
-        const double eta = (f.dim == 1) ? 1.0 : c_tab.eta[f.oi][k];
+        const double eta = (f.dim == 1) ? 1.0 : kTab.eta[f.oi][k];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fs[v] += eta * Fk[v];
     }
