@@ -192,16 +192,58 @@ size_t ase_workspace_bytes(const ase_grid_t *g, const ase_params_t *p);
 int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, double *t,
              double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Batched 1D instances (one persistent launch) -------------------------
+ * Many independent 1D problems of uneven size stored back to back:
+ * instance k occupies stored cells [offsets[k], offsets[k] + ncells[k] +
+ * 2 ng) of a concatenated state U[v * total + c] (v = rho, rho u, E) and of
+ * a strength array sigma[c] (strength of the face between stored cells c and
+ * c+1 of the same instance; the DF state as in the 1D grid form).  Every
+ * instance has its own dx and its own time t[k] and dt (CFL of its own
+ * cells); all share the method parameters, the boundary kind `bc`
+ * (ASE_BC_PERIODIC or ASE_BC_TRANSMISSIVE) and ng >= (order+1)/2.  The
+ * caller guarantees disjoint, in-range instances (the kernel skips an
+ * instance whose range leaves [0, total)); periodic instances need
+ * ncells >= ng. */
+
+/* Host-side packing of instances into nbins work bins (longest processing
+ * time first on ncells): bin b holds bin_list[bin_start[b] ..
+ * bin_start[b+1]).  HOST arrays: ncells[ninst] in, bin_start[nbins+1] and
+ * bin_list[ninst] out.  Upload both to the device for ase_step_batched. */
+int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_t *bin_start, int32_t *bin_list);
+
+/* Device workspace of ase_step_batched for `total` stored cells. */
+size_t ase_batched_workspace_bytes(int64_t total);
+
+/* First-order DF strengths of every instance (the 1D ase_sigma_init per
+ * instance); fills the ghost cells of U.  Device arrays. */
+int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
+                           const int32_t *ncells, int32_t ng, int64_t total, double *U, double *sigma,
+                           void *stream);
+
+/* nsteps SSP-RK3 steps of every instance in ONE persistent launch: nbins
+ * workgroups of `threads` (256 or 512) lanes, each walking the instances of
+ * its bin through all steps (ghost cells, DF state, per-instance dt, three
+ * stages of the 1D method of ase_step) without returning to the host.
+ * Results equal ase_step on each instance alone.  t: device [ninst], in/out.
+ * dt_hist: optional device [nsteps][ninst].  t_end > 0 stops each instance
+ * at t_end.  bin_start/bin_list: device copies of an ase_batched_plan. */
+int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
+                     const int32_t *ncells, const double *dx, int32_t ng, int64_t total, double *U, double *sigma,
+                     double *t, double *dt_hist, int32_t nsteps, double t_end, const int32_t *bin_start,
+                     const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
+                     void *stream);
+
 /* Per-kernel timing of ase_step, for benchmarks and profiling (not for
  * production runs).  While enabled, ase_step brackets every launch of its
  * reconstruction/flux/update kernels with HIP events on the call's stream
- * (pool of 8192 launches; further launches go unrecorded).
+ * and of ase_step_batched's persistent kernel (pool of 8192 launches;
+ * further launches go unrecorded).
  * ase_profile_enable(1) clears and enables recording, (0) disables it.
  * ase_profile_read waits for the recorded events, then returns the summed
  * duration in milliseconds and the number of launches of one kernel class
  * (ASE_KCLASS_*); it does not clear the record. */
 enum { ASE_KCLASS_SWEEP_X = 0, ASE_KCLASS_SWEEP_Y = 1, ASE_KCLASS_STAGE_1D = 2, ASE_KCLASS_BC = 3,
-       ASE_KCLASS_CFL = 4, ASE_KCLASS_COUNT = 5 };
+       ASE_KCLASS_CFL = 4, ASE_KCLASS_BATCHED = 5, ASE_KCLASS_COUNT = 6 };
 int ase_profile_enable(int on);
 int ase_profile_read(int kernel_class, double *total_ms, int64_t *launches);
 

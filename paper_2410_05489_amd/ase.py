@@ -38,9 +38,10 @@ class AseParams(C.Structure):
 
 EXPORTS = ("ase_last_error", "ase_version", "ase_bc_fill", "ase_sigma_init", "ase_cfl_dt", "ase_reconstruct",
            "ase_df_compute", "ase_flux", "ase_stage_update", "ase_workspace_bytes", "ase_step",
-           "ase_profile_enable", "ase_profile_read")
+           "ase_profile_enable", "ase_profile_read", "ase_batched_plan", "ase_batched_workspace_bytes",
+           "ase_batched_sigma_init", "ase_step_batched")
 
-KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4}
+KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4, "batched": 5}
 
 
 class AseError(RuntimeError):
@@ -69,6 +70,12 @@ def lib():
     L.ase_workspace_bytes.restype = C.c_size_t
     L.ase_workspace_bytes.argtypes = [vp, vp]
     L.ase_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, C.c_int32, C.c_double, vp, C.c_size_t, vp]
+    L.ase_batched_plan.argtypes = [C.c_int32, vp, C.c_int32, vp, vp]
+    L.ase_batched_workspace_bytes.restype = C.c_size_t
+    L.ase_batched_workspace_bytes.argtypes = [C.c_int64]
+    L.ase_batched_sigma_init.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.c_int32, C.c_int64, vp, vp, vp]
+    L.ase_step_batched.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp,
+                                   C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_profile_enable.argtypes = [C.c_int]
     L.ase_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in EXPORTS:
@@ -226,3 +233,60 @@ class Simulation:
 
     def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None):
         step(self.g, self.p, self.U, self.sx, self.sy, self.t, nsteps, t_end, self.ws, dt_hist)
+
+
+def batched_plan(ncells, nbins: int):
+    """Host packing of instances into bins (longest first); returns numpy
+    (bin_start[nbins+1], bin_list[ninst])."""
+    import numpy as np
+    nc = np.ascontiguousarray(ncells, dtype=np.int32)
+    start = np.zeros(nbins + 1, dtype=np.int32)
+    lst = np.zeros(len(nc), dtype=np.int32)
+    _check(lib().ase_batched_plan(len(nc), nc.ctypes.data, nbins, start.ctypes.data, lst.ctypes.data),
+           "ase_batched_plan")
+    return start, lst
+
+
+class BatchedSimulation:
+    """Device state of a batch of 1D instances (see workloads.Batch) and the
+    persistent-launch stepper.  nbins / threads select the launch shape."""
+
+    def __init__(self, batch, device="cuda", nbins: int = 0, threads: int = 256, sigma=None):
+        import numpy as np
+        self.b = batch
+        self.p = batch.params
+        n = batch.ncells
+        off = batch.offsets
+        if np.any(off < 0) or np.any(off[1:] < off[:-1] + n[:-1] + 2 * batch.ng) or \
+                off[-1] + n[-1] + 2 * batch.ng > batch.total:
+            raise AseError("batch instances overlap or leave the array")
+        if batch.bc == 0 and np.any(n < batch.ng):
+            raise AseError("periodic instances need ncells >= ng")
+        self.offsets = torch.as_tensor(off, dtype=torch.int64).to(device)
+        self.ncells = torch.as_tensor(n, dtype=torch.int32).to(device)
+        self.dx = torch.as_tensor(batch.dx, dtype=torch.float64).to(device)
+        self.U = torch.as_tensor(batch.U, dtype=torch.float64).to(device).contiguous()
+        self.sig = torch.zeros(batch.total, dtype=torch.float64, device=device)
+        self.t = torch.zeros(batch.ninst, dtype=torch.float64, device=device)
+        self.nbins = nbins if nbins else min(batch.ninst, 512)
+        self.threads = threads
+        start, lst = batched_plan(n, self.nbins)
+        self.bin_start = torch.as_tensor(start).to(device)
+        self.bin_list = torch.as_tensor(lst).to(device)
+        nbytes = int(lib().ase_batched_workspace_bytes(batch.total))
+        self.ws = Workspace(nbytes, device)
+        P = C.byref(c_params(self.p))
+        if sigma is None:
+            _check(lib().ase_batched_sigma_init(P, batch.bc, batch.ninst, _p(self.offsets), _p(self.ncells), batch.ng,
+                                                batch.total, _p(self.U), _p(self.sig), _stream()),
+                   "ase_batched_sigma_init")
+        else:
+            self.sig.copy_(torch.as_tensor(sigma))
+
+    def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None):
+        b = self.b
+        _check(lib().ase_step_batched(C.byref(c_params(self.p)), b.bc, b.ninst, _p(self.offsets), _p(self.ncells),
+                                      _p(self.dx), b.ng, b.total, _p(self.U), _p(self.sig), _p(self.t),
+                                      _p(dt_hist), int(nsteps), float(t_end), _p(self.bin_start),
+                                      _p(self.bin_list), self.nbins, self.threads, self.ws.ptr, self.ws.nbytes,
+                                      _stream(stream)), "ase_step_batched")

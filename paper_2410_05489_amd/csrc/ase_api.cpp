@@ -2,8 +2,10 @@
 // orchestration of whole SSP-RK3 steps on device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -410,6 +412,130 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
         }
     }
     return check_launch("ase_step");
+}
+
+int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_t *bin_start, int32_t *bin_list)
+{
+    if (ninst < 1 || nbins < 1 || !ncells || !bin_start || !bin_list)
+        return fail(ASE_ERR_ARG, "ase_batched_plan: bad arguments");
+    std::vector<int> order(ninst);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ncells[a] > ncells[b]; });
+    std::vector<long long> load(nbins, 0);
+    std::vector<std::vector<int>> bins(nbins);
+    for (int k : order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bins[b].push_back(k);
+        load[b] += ncells[k] > 0 ? ncells[k] : 0;
+    }
+    int pos = 0;
+    for (int b = 0; b < nbins; ++b) {
+        bin_start[b] = pos;
+        for (int k : bins[b]) bin_list[pos++] = k;
+    }
+    bin_start[nbins] = pos;
+    return ASE_OK;
+}
+
+size_t ase_batched_workspace_bytes(int64_t total)
+{
+    if (total < 1) return 0;
+    return 7 * align_up((size_t)total * sizeof(double));
+}
+
+static int batched_common(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
+                          const int32_t *ncells, int32_t ng, int64_t total, double *U, double *sigma)
+{
+    if (!p) return fail(ASE_ERR_ARG, "null params");
+    const int r = p->order;
+    if (r != 3 && r != 5 && r != 7 && r != 9) return fail(ASE_ERR_ORDER, "order must be 3, 5, 7 or 9");
+    if (ng < (r + 1) / 2) return fail(ASE_ERR_GHOST, "ng must be >= (order+1)/2");
+    if (bc != ASE_BC_PERIODIC && bc != ASE_BC_TRANSMISSIVE) return fail(ASE_ERR_ARG, "bc must be periodic or transmissive");
+    if (ninst < 1 || total < 1) return fail(ASE_ERR_ARG, "ninst and total must be >= 1");
+    if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->sigma_thres > 0.0) || !(p->eps > 0.0) ||
+        !(p->d_hi > 0.0 && p->d_hi < 1.0) || !(p->d_lo >= 0.0 && p->d_lo <= 1.0))
+        return fail(ASE_ERR_ARG, "invalid method parameters");
+    ASE_PTR(offsets, "offsets");
+    ASE_PTR(ncells, "ncells");
+    ASE_PTR(U, "U");
+    ASE_PTR(sigma, "sigma");
+    return ASE_OK;
+}
+
+int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
+                           const int32_t *ncells, int32_t ng, int64_t total, double *U, double *sigma, void *stream)
+{
+    int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
+    if (rc) return rc;
+    BatchLaunch bl;
+    std::memset(&bl, 0, sizeof(bl));
+    bl.offsets = reinterpret_cast<const long long *>(offsets);
+    bl.ncells = ncells;
+    bl.U = U;
+    bl.sig = sigma;
+    bl.total = total;
+    bl.ninst = ninst;
+    bl.ng = ng;
+    bl.bc = bc;
+    bl.init = 1;
+    bl.mc = method_const(p);
+    launch_batched(bl, (hipStream_t)stream);
+    return check_launch("ase_batched_sigma_init");
+}
+
+int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
+                     const int32_t *ncells, const double *dx, int32_t ng, int64_t total, double *U, double *sigma,
+                     double *t, double *dt_hist, int32_t nsteps, double t_end, const int32_t *bin_start,
+                     const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(ASE_ERR_ARG, "nsteps must be >= 0");
+    if (nbins < 1) return fail(ASE_ERR_ARG, "nbins must be >= 1");
+    if (threads != 256 && threads != 512) return fail(ASE_ERR_ARG, "threads must be 256 or 512");
+    ASE_PTR(dx, "dx");
+    ASE_PTR(t, "t");
+    if (dt_hist && misaligned(dt_hist)) return fail(ASE_ERR_ALIGN, "misaligned: dt_hist");
+    if (!bin_start || !bin_list) return fail(ASE_ERR_ARG, "null bin arrays");
+    if (!ws) return fail(ASE_ERR_WORKSPACE, "workspace is required");
+    if (ws_bytes < ase_batched_workspace_bytes(total)) return fail(ASE_ERR_WORKSPACE, "workspace too small");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(ASE_ERR_ALIGN, "workspace must be 256-byte aligned");
+    if (nsteps == 0) return ASE_OK;
+    char *c = static_cast<char *>(ws);
+    const size_t arr = align_up((size_t)total * sizeof(double));
+    BatchLaunch bl;
+    std::memset(&bl, 0, sizeof(bl));
+    bl.offsets = reinterpret_cast<const long long *>(offsets);
+    bl.ncells = ncells;
+    bl.dx = dx;
+    bl.U = U;
+    bl.sig = sigma;
+    bl.t = t;
+    bl.dt_hist = dt_hist;
+    bl.U1 = reinterpret_cast<double *>(c);
+    bl.U2 = reinterpret_cast<double *>(c + 3 * arr);
+    bl.sig2 = reinterpret_cast<double *>(c + 6 * arr);
+    bl.bin_start = bin_start;
+    bl.bin_list = bin_list;
+    bl.total = total;
+    bl.ninst = ninst;
+    bl.nbins = nbins;
+    bl.threads = threads;
+    bl.R = (p->order - 1) / 2;
+    bl.ng = ng;
+    bl.nsteps = nsteps;
+    bl.bc = bc;
+    bl.fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
+    bl.t_end = t_end;
+    bl.cfl = p->cfl;
+    bl.dt_cap = p->dt_cap;
+    bl.mc = method_const(p);
+    {
+        ProfScope ps(ASE_KCLASS_BATCHED, (hipStream_t)stream);
+        launch_batched(bl, (hipStream_t)stream);
+    }
+    return check_launch("ase_step_batched");
 }
 
 int ase_profile_enable(int on)

@@ -78,4 +78,17 @@ void launch_flux(const Geo &geo, const MethodConst &mc, int dir, const double *w
 void launch_stage_update(const ase_grid_t &g, const Geo &geo, int stage, const double *dt, const double *Un,
                          const double *Us, const double *F, const double *Gf, double *Uout, hipStream_t st);
 
+struct BatchLaunch {
+    const long long *offsets;
+    const int *ncells;
+    const double *dx;
+    double *U, *sig, *t, *dt_hist, *U1, *U2, *sig2;
+    const int *bin_start, *bin_list;
+    long long total;
+    int ninst, nbins, threads, R, ng, nsteps, bc, fo, init;
+    double t_end, cfl, dt_cap;
+    MethodConst mc;
+};
+void launch_batched(const BatchLaunch &bl, hipStream_t st);
+
 }  // namespace ase

@@ -528,70 +528,79 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// 1D stage: tile of T cells; reconstruction, strengths, LF flux and update
-// in one pass (MODE_FUSED_1D), or the face states only (MODE_RECON).
+// 1D stage on one tile of T cells: reconstruction, strengths, LF flux and
+// update in one pass (MODE_FUSED_1D), or the face states only (MODE_RECON).
+// The same device routine serves the grid kernel (one tile per workgroup) and
+// the batched persistent kernel (a workgroup walks the tiles of its
+// instances).
 // ---------------------------------------------------------------------------
-template <int R, int T, int MODE>
-__global__ void __launch_bounds__(kThreads) k_stage1d(SweepArgs a)
+struct Tile1D {
+    const double *U;       // stage input (ghosts filled), variable stride `plane`
+    const double *sx;      // strengths read by this stage
+    double *sig_out;       // strengths written at the flux faces
+    const double *Un;      // step-start state
+    double *Uout;          // stage output
+    double *wl, *wr;       // MODE_RECON outputs
+    int8_t *level;
+    long long plane;
+    int nx, ng, NX, nfaces, stage;
+    double inv_dx, dt;
+};
+
+template <int R, int T>
+struct Lds1D {
+    static constexpr int UX = T + 2 + 2 * R;
+    double sU[3][UX];
+    double sS[UX];
+    double sTR[3][T + 2];
+    double sTL[3][T + 2];
+    double sF[3][T + 1];
+};
+
+template <int R, int T, int NT, int MODE>
+__device__ __forceinline__ void stage1d_tile(const Tile1D &a, int i0, const MethodConst &mc, Lds1D<R, T> &L)
 {
     constexpr int NV = 3, OI = R - 1;
-    constexpr int UX = T + 2 + 2 * R;
-    __shared__ double sU[NV][UX];
-    __shared__ double sS[UX];
-    __shared__ double sTR[NV][T + 2];
-    __shared__ double sTL[NV][T + 2];
-    __shared__ double sF[NV][T + 1];
-
+    constexpr int UX = Lds1D<R, T>::UX;
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * T;
     const int ox = i0 - 1 - R;
-    const MethodConst &mc = a.mc;
 
-    if (MODE != MODE_RECON && a.skip != nullptr && *a.skip != 0.0) {
-        for (int fx = tid; fx < T + 1; fx += kThreads) {
-            const int x = i0 - 1 + fx;
-            if (x > a.nx - 1) continue;
-            if (fx > 0 || i0 == 0) a.sig_out[x + a.ng] = a.sx[x + a.ng];
-        }
-        return;
-    }
-
-    for (int lx = tid; lx < UX; lx += kThreads) {
+    for (int lx = tid; lx < UX; lx += NT) {
         const int I = ox + lx + a.ng;
         const bool in = I < a.NX;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sU[v][lx] = in ? a.U[v * a.plane + I] : 0.0;
-        sS[lx] = in ? a.sx[I] : 0.0;
+        for (int v = 0; v < NV; ++v) L.sU[v][lx] = in ? a.U[v * a.plane + I] : 0.0;
+        L.sS[lx] = in ? a.sx[I] : 0.0;
     }
     __syncthreads();
 
-    for (int tx = tid; tx < T + 2; tx += kThreads) {
+    for (int tx = tid; tx < T + 2; tx += NT) {
         const int lx = tx + R;
         const int x = ox + lx;
         if (x > a.nx) continue;
         double s[2 * R];
 #pragma unroll
-        for (int m = -R; m < R; ++m) s[m + R] = sS[lx + m];
-        auto ld = [&](int v, int m) { return sU[v][lx + m]; };
+        for (int m = -R; m < R; ++m) s[m + R] = L.sS[lx + m];
+        auto ld = [&](int v, int m) { return L.sU[v][lx + m]; };
         double out[NV][2];
         const int lvl = reconstruct_cell<R, NV, 2>(ld, s, mc, OI, 0, out);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            sTR[v][tx] = out[v][0];
-            sTL[v][tx] = out[v][1];
+            L.sTR[v][tx] = out[v][0];
+            L.sTL[v][tx] = out[v][1];
         }
         if (MODE == MODE_RECON && a.level != nullptr && x >= 0 && x < a.nx) a.level[x] = (int8_t)lvl;
     }
     __syncthreads();
 
-    for (int fx = tid; fx < T + 1; fx += kThreads) {
+    for (int fx = tid; fx < T + 1; fx += NT) {
         const int x = i0 - 1 + fx;   // face x + 1/2
         if (x > a.nx - 1) continue;
         double Wl[NV], Wr[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            Wl[v] = sTR[v][fx];
-            Wr[v] = sTL[v][fx + 1];
+            Wl[v] = L.sTR[v][fx];
+            Wr[v] = L.sTL[v][fx + 1];
         }
         if constexpr (MODE == MODE_RECON) {
 #pragma unroll
@@ -601,32 +610,206 @@ __global__ void __launch_bounds__(kThreads) k_stage1d(SweepArgs a)
             }
         } else {
             double F[NV];
-            auto cl = [&](int v) { return sU[v][fx + R]; };
-            auto cr = [&](int v) { return sU[v][fx + R + 1]; };
+            auto cl = [&](int v) { return L.sU[v][fx + R]; };
+            auto cr = [&](int v) { return L.sU[v][fx + R + 1]; };
             const double sg = gauss_point<NV>(Wl, Wr, cl, cr, 0, mc, F);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) sF[v][fx] = F[v];
+            for (int v = 0; v < NV; ++v) L.sF[v][fx] = F[v];
             if (fx > 0 || i0 == 0) a.sig_out[x + a.ng] = sg;
         }
     }
     if constexpr (MODE == MODE_RECON) return;
     __syncthreads();
 
-    const double dt = *a.dt;
-    for (int cx = tid; cx < T; cx += kThreads) {
+    const double dt = a.dt;
+    for (int cx = tid; cx < T; cx += NT) {
         const int x = i0 + cx;
         if (x >= a.nx) continue;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const long long e = v * a.plane + x + a.ng;
-            const double L = -(sF[v][cx + 1] - sF[v][cx]) * a.inv_dx;
+            const double Lx = -(L.sF[v][cx + 1] - L.sF[v][cx]) * a.inv_dx;
             double o;
-            if (a.stage == 1) o = a.Un[e] + dt * L;
-            else if (a.stage == 2) o = 0.75 * a.Un[e] + 0.25 * a.U[e] + 0.25 * dt * L;
-            else o = (1.0 / 3.0) * a.Un[e] + (2.0 / 3.0) * a.U[e] + (2.0 / 3.0) * dt * L;
+            if (a.stage == 1) o = a.Un[e] + dt * Lx;
+            else if (a.stage == 2) o = 0.75 * a.Un[e] + 0.25 * a.U[e] + 0.25 * dt * Lx;
+            else o = (1.0 / 3.0) * a.Un[e] + (2.0 / 3.0) * a.U[e] + (2.0 / 3.0) * dt * Lx;
             a.Uout[e] = o;
         }
     }
+}
+
+template <int R, int T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_stage1d(SweepArgs a)
+{
+    __shared__ Lds1D<R, T> L;
+    const int i0 = blockIdx.x * T;
+    if (MODE != MODE_RECON && a.skip != nullptr && *a.skip != 0.0) {
+        for (int fx = threadIdx.x; fx < T + 1; fx += kThreads) {
+            const int x = i0 - 1 + fx;
+            if (x > a.nx - 1) continue;
+            if (fx > 0 || i0 == 0) a.sig_out[x + a.ng] = a.sx[x + a.ng];
+        }
+        return;
+    }
+    Tile1D t;
+    t.U = a.U; t.sx = a.sx; t.sig_out = a.sig_out; t.Un = a.Un; t.Uout = a.Uout;
+    t.wl = a.wl; t.wr = a.wr; t.level = a.level;
+    t.plane = a.plane; t.nx = a.nx; t.ng = a.ng; t.NX = a.NX; t.nfaces = a.nfaces; t.stage = a.stage;
+    t.inv_dx = a.inv_dx;
+    t.dt = (MODE == MODE_RECON) ? 0.0 : *a.dt;
+    stage1d_tile<R, T, kThreads, MODE>(t, i0, a.mc, L);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent 1D kernel: every workgroup walks the instances of its
+// bin (a packing computed on the host) and advances each one through all
+// its steps -- ghost cells, DF state, its own dt, three stages over tiles of
+// T cells -- without leaving the kernel.  Instances are independent, so no
+// workgroup ever waits for another.
+// ---------------------------------------------------------------------------
+struct BatchArgs {
+    const long long *offsets;   // first stored cell of each instance
+    const int *ncells;
+    const double *dx;
+    double *U, *sig, *t, *dt_hist;
+    double *U1, *U2, *sig2;     // workspace, same layout as U / sig
+    const int *bin_start, *bin_list;
+    long long total;
+    int ninst, ng, nsteps, bc, fo;
+    double t_end, cfl, dt_cap;
+    MethodConst mc;
+};
+
+// Ghost cells of one instance and the strengths its stage reads.
+template <int NT>
+__device__ __forceinline__ void batched_fill(const BatchArgs &a, double *U, double *sg, int N, const MethodConst &mc)
+{
+    const int ng = a.ng, NX = N + 2 * ng;
+    const long long P = a.total;
+    for (int k = threadIdx.x; k < 2 * ng; k += NT) {
+        const int I = k < ng ? k : N + k;
+        int Is;
+        if (a.bc == ASE_BC_PERIODIC) Is = k < ng ? I + N : I - N;
+        else Is = k < ng ? ng : ng + N - 1;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) U[v * P + I] = U[v * P + Is];
+    }
+    __syncthreads();
+    for (int I = threadIdx.x; I + 1 < NX; I += NT) {
+        const int f = I - ng;
+        const bool produced = f >= -1 && f <= N - 1;
+        if (a.fo || !produced) {
+            if (!a.fo && a.bc == ASE_BC_PERIODIC) {
+                sg[I] = sg[((f % N) + N) % N + ng];
+            } else {
+                double Wa[3], Wb[3];
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    Wa[v] = U[v * P + I];
+                    Wb[v] = U[v * P + I + 1];
+                }
+                sg[I] = sigma_point(primitives<3>(Wa, 0, mc), primitives<3>(Wb, 0, mc));
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
+{
+    constexpr int T = NT;
+    __shared__ Lds1D<R, T> L;
+    __shared__ double red[NT];
+    __shared__ double s_dt;
+    const MethodConst &mc = a.mc;
+    for (int b = a.bin_start[blockIdx.x]; b < a.bin_start[blockIdx.x + 1]; ++b) {
+        const int k = a.bin_list[b];
+        const long long off = a.offsets[k];
+        const int N = a.ncells[k];
+        if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) continue;   // malformed entry: skipped
+        double *U = a.U + off, *U1 = a.U1 + off, *U2 = a.U2 + off;
+        double *sA = a.sig + off, *sB = a.sig2 + off;
+        const double inv_dx = 1.0 / a.dx[k];
+        double t = a.t[k];
+        int s = 0;
+        for (; s < a.nsteps; ++s) {
+            if (a.t_end > 0.0 && t >= a.t_end) break;
+            batched_fill<NT>(a, U, sA, N, mc);
+            // dt from the signal speeds of this instance
+            double lam = 0.0;
+            for (int i = threadIdx.x; i < N; i += NT) {
+                double W[3];
+#pragma unroll
+                for (int v = 0; v < 3; ++v) W[v] = U[v * a.total + i + a.ng];
+                const Prim q = primitives<3>(W, 0, mc);
+                const double l = (fabs(q.un) + q.c) * inv_dx;
+                lam = (l > lam || l != l) ? l : lam;
+            }
+            red[threadIdx.x] = lam;
+            __syncthreads();
+            for (int w = NT / 2; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) {
+                    const double o = red[threadIdx.x + w];
+                    red[threadIdx.x] = (o > red[threadIdx.x] || o != o) ? o : red[threadIdx.x];
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                double dt = a.cfl / red[0];
+                if (a.dt_cap > 0.0 && dt > a.dt_cap) dt = a.dt_cap;
+                if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
+                s_dt = dt;
+            }
+            __syncthreads();
+            const double dt = s_dt;
+            double *in_st[3] = {U, U1, U2};
+            double *out_st[3] = {U1, U2, U};
+            for (int st = 0; st < 3; ++st) {
+                double *sin = (st == 1) ? sB : sA;
+                double *sout = (st == 1) ? sA : sB;
+                if (st > 0) batched_fill<NT>(a, in_st[st], sin, N, mc);
+                Tile1D tl;
+                tl.U = in_st[st]; tl.sx = sin; tl.sig_out = sout; tl.Un = U; tl.Uout = out_st[st];
+                tl.wl = tl.wr = nullptr; tl.level = nullptr;
+                tl.plane = a.total; tl.nx = N; tl.ng = a.ng; tl.NX = N + 2 * a.ng; tl.nfaces = N + 1;
+                tl.stage = st + 1; tl.inv_dx = inv_dx; tl.dt = dt;
+                for (int i0 = 0; i0 < N; i0 += T) {
+                    stage1d_tile<R, T, NT, MODE_FUSED_1D>(tl, i0, mc, L);
+                    __syncthreads();
+                }
+            }
+            // the new strengths are in sB: swap the roles
+            double *tmp = sA;
+            sA = sB;
+            sB = tmp;
+            t += dt;
+            if (threadIdx.x == 0 && a.dt_hist) a.dt_hist[(long long)s * a.ninst + k] = dt;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            a.t[k] = t;
+            if (a.dt_hist)
+                for (int r = s; r < a.nsteps; ++r) a.dt_hist[(long long)r * a.ninst + k] = 0.0;
+        }
+        if (sA != a.sig + off) {
+            for (int I = threadIdx.x; I < N + 2 * a.ng; I += NT) a.sig[off + I] = sA[I];
+        }
+        __syncthreads();
+    }
+}
+
+// First-order strengths of every instance (one workgroup per instance).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_batched_sigma_init(BatchArgs a)
+{
+    const int k = blockIdx.x;
+    const long long off = a.offsets[k];
+    const int N = a.ncells[k];
+    if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) return;
+    BatchArgs b = a;
+    b.fo = 1;
+    batched_fill<NT>(b, a.U + off, a.sig + off, N, a.mc);
 }
 
 // ---------------------------------------------------------------------------
@@ -859,6 +1042,38 @@ void launch_stage_update(const ase_grid_t &g, const Geo &geo, int stage, const d
         k_stage_update<4><<<nb, kThreads, 0, st>>>(b, stage, dt, Un, Us, F, Gf, 1.0 / g.dx, 1.0 / g.dy, Uout);
     else
         k_stage_update<3><<<nb, kThreads, 0, st>>>(b, stage, dt, Un, Us, F, Gf, 1.0 / g.dx, 1.0 / g.dy, Uout);
+}
+
+void launch_batched(const BatchLaunch &bl, hipStream_t st)
+{
+    BatchArgs a;
+    a.offsets = bl.offsets; a.ncells = bl.ncells; a.dx = bl.dx;
+    a.U = bl.U; a.sig = bl.sig; a.t = bl.t; a.dt_hist = bl.dt_hist;
+    a.U1 = bl.U1; a.U2 = bl.U2; a.sig2 = bl.sig2;
+    a.bin_start = bl.bin_start; a.bin_list = bl.bin_list;
+    a.total = bl.total; a.ninst = bl.ninst; a.ng = bl.ng; a.nsteps = bl.nsteps; a.bc = bl.bc; a.fo = bl.fo;
+    a.t_end = bl.t_end; a.cfl = bl.cfl; a.dt_cap = bl.dt_cap; a.mc = bl.mc;
+    if (bl.init) {
+        k_batched_sigma_init<256><<<bl.ninst, 256, 0, st>>>(a);
+        return;
+    }
+#define ASE_BATCH(RR, NTT) k_batched1d<RR, NTT><<<bl.nbins, NTT, 0, st>>>(a)
+    if (bl.threads == 512) {
+        switch (bl.R) {
+        case 1: ASE_BATCH(1, 512); break;
+        case 2: ASE_BATCH(2, 512); break;
+        case 3: ASE_BATCH(3, 512); break;
+        default: ASE_BATCH(4, 512); break;
+        }
+    } else {
+        switch (bl.R) {
+        case 1: ASE_BATCH(1, 256); break;
+        case 2: ASE_BATCH(2, 256); break;
+        case 3: ASE_BATCH(3, 256); break;
+        default: ASE_BATCH(4, 256); break;
+        }
+    }
+#undef ASE_BATCH
 }
 
 }  // namespace ase

@@ -333,7 +333,8 @@ def batched_riemann(ninst: int = 256, nmin: int = 64, nmax: int = 4096, order: i
         W = frac[None, :] * WL[:, None] + (1 - frac[None, :]) * WR[:, None]
         o = int(offsets[k])
         U[:, o + ng:o + ng + N] = W
-    return Batch(ncells, offsets, dx, ng, U, Params(order=order, gamma=gamma, cfl=cfl), BC_TRANSMISSIVE, nsteps)
+    return Batch(ncells, offsets, dx, ng, U, Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=1),
+                 BC_TRANSMISSIVE, nsteps)
 
 
 def batched_smooth(ninst: int = 16, nmin: int = 64, nmax: int = 512, order: int = 9, seed: int = 1,
