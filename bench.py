@@ -70,6 +70,64 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def bench_batched(args):
+    """Batched 1D form: 256 instances (64..4096 cells), r = 9, in one
+    persistent launch, against per-instance ase_step launches."""
+    import torch
+    from paper_2410_05489_amd import ase, autotune
+    from paper_2410_05489_amd import workloads as WL
+
+    b = WL.batched_riemann(nsteps=args.steps)
+    best = autotune.tune_batched(b, nsteps=10, use_cache=False)
+    sim = ase.BatchedSimulation(b, "cuda", nbins=best["nbins"], threads=best["threads"])
+    sim.run(args.warmup)
+    torch.cuda.synchronize()
+    ase.profile_enable(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    sim.run(args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    kms, kn = ase.profile_read("batched")
+    ase.profile_enable(False)
+    cells = int(b.ncells.sum())
+    value = cells * args.steps / (ms / 1e3) / 1e6
+    # per-instance launches of the same 1D method (ase_step per instance)
+    sims = []
+    for k in range(b.ninst):
+        g = WL.instance_grid(b, k)
+        o = int(b.offsets[k])
+        sims.append(ase.Simulation(g, b.params, b.U[:, o:o + g.NX].reshape(3, 1, g.NX), device="cuda"))
+    pi_steps = max(1, args.steps // 10)
+    for s1 in sims:
+        s1.run(1)
+    torch.cuda.synchronize()
+    start.record()
+    for s1 in sims:
+        s1.run(pi_steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_pi = start.elapsed_time(stop)
+    value_pi = cells * pi_steps / (ms_pi / 1e3) / 1e6
+    flops = alg_flops_per_cell_sweep(b.params.order, 1) * 3 + 3 * 4
+    achieved = flops * cells * args.steps / (kms / 1e3) / 1e12
+    out = {"metric": "Mcell-updates/s, batched 1D order-9 instances, one persistent launch", "value": round(value, 2),
+           "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms / args.steps, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"batched_riemann_{b.ninst}x64..4096_r9_seed0", "ninst": b.ninst, "cells": cells,
+                      "nbins": best["nbins"], "threads": best["threads"]},
+           "per_instance_launches": {"value": round(value_pi, 2), "steps": pi_steps, "ms": round(ms_pi, 3)},
+           "speedup_vs_per_instance": round(value / value_pi, 2),
+           "autotune": best["trials"],
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": "k_batched1d", "avg_launch_ms": round(kms / max(kn, 1), 4)}}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(w, seconds_hint=True):
     """The oracle (single thread, as written) on one step of the same grid."""
     from oracle import oracle as O
@@ -108,6 +166,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU domain decomposition is a design note, not implemented)"}))
         sys.exit(2)
+
+    if args.workload == "batched":
+        return bench_batched(args)
 
     import torch
     from paper_2410_05489_amd import ase

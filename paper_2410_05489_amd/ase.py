@@ -234,6 +234,19 @@ class Simulation:
     def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None):
         step(self.g, self.p, self.U, self.sx, self.sy, self.t, nsteps, t_end, self.ws, dt_hist)
 
+    def capture(self, nsteps: int, t_end: float = 0.0):
+        """A HIP graph of nsteps steps on this state (replay() advances it)."""
+        return _capture(lambda: self.run(nsteps, t_end))
+
+
+def _capture(fn):
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        fn()
+    torch.cuda.synchronize()
+    return graph
+
 
 def batched_plan(ncells, nbins: int):
     """Host packing of instances into bins (longest first); returns numpy
@@ -290,3 +303,7 @@ class BatchedSimulation:
                                       _p(dt_hist), int(nsteps), float(t_end), _p(self.bin_start),
                                       _p(self.bin_list), self.nbins, self.threads, self.ws.ptr, self.ws.nbytes,
                                       _stream(stream)), "ase_step_batched")
+
+    def capture(self, nsteps: int, t_end: float = 0.0):
+        """A HIP graph holding the persistent launch of nsteps steps."""
+        return _capture(lambda: self.run(nsteps, t_end))

@@ -1,0 +1,85 @@
+"""Launch-shape autotuner for the batched persistent kernel.
+
+Times ase_step_batched for a few (bins, threads) shapes on the current GPU
+and keeps the fastest in a JSON cache keyed by (arch, order, instance-count,
+stored-cell total).  Results do not depend on the shape (every instance is
+advanced by the same per-cell arithmetic), only the time does.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+import torch
+
+from . import ase
+
+DEFAULT_CANDIDATES: Sequence[Tuple[int, int]] = ((128, 512), (256, 256), (256, 512), (512, 256), (512, 512),
+                                                  (1024, 256))
+
+
+def cache_path() -> str:
+    return os.environ.get("ASE_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ase_mi355x",
+                                                         "tune.json"))
+
+
+def _arch() -> str:
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:  # noqa: BLE001
+        return "unknown"
+
+
+def batched_key(batch) -> str:
+    return f"{_arch()}/batched/r{batch.params.order}/n{batch.ninst}/c{batch.total}"
+
+
+def _load() -> Dict[str, dict]:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: Dict[str, dict]) -> None:
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_batched(batch, nbins: int, threads: int, nsteps: int, device="cuda") -> float:
+    """Milliseconds for nsteps steps of the whole batch in one launch."""
+    sim = ase.BatchedSimulation(batch, device, nbins=nbins, threads=threads)
+    sim.run(1)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    sim.run(nsteps)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop)
+
+
+def tune_batched(batch, nsteps: int = 10, candidates: Optional[Sequence[Tuple[int, int]]] = None,
+                 use_cache: bool = True) -> dict:
+    """Best {'nbins', 'threads', 'ms'} for this batch shape (cached)."""
+    key = batched_key(batch)
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        return cache[key]
+    trials = []
+    for nbins, threads in (candidates or DEFAULT_CANDIDATES):
+        ms = time_batched(batch, nbins, threads, nsteps)
+        trials.append({"nbins": nbins, "threads": threads, "ms": ms})
+    best = min(trials, key=lambda r: r["ms"])
+    best = dict(best, steps=nsteps, trials=trials)
+    if use_cache:
+        cache[key] = best
+        _store(cache)
+    return best

@@ -162,3 +162,17 @@ def test_batched_full_size():
         assert np.isfinite(a).all() == np.isfinite(c).all(), k
         if np.isfinite(c).all():
             assert _rel(a, c) < 1e-9, k
+
+
+def test_batched_graph_replays_match_eager():
+    b = WL.batched_riemann(ninst=10, nmin=64, nmax=400, order=9, seed=12, nsteps=5)
+    eager = ase.BatchedSimulation(b, DEV, nbins=4)
+    graphed = ase.BatchedSimulation(b, DEV, nbins=4)
+    graph = graphed.capture(5)
+    for rep in range(3):
+        eager.run(5)
+        graph.replay()
+        torch.cuda.synchronize()
+        torch.randn(100, device=DEV).sum().item()
+        assert torch.equal(torch.nan_to_num(eager.U), torch.nan_to_num(graphed.U)), rep
+        assert torch.equal(eager.t, graphed.t), rep

@@ -296,3 +296,25 @@ def test_full_size_one_step(name):
     # with E ~ 1e8), so the bound there is 1e-11; 1e-12 elsewhere.
     tol = 1e-11 if name == "jet1600" else 1e-12
     assert rel_err(g.interior(Ug), g.interior(Uo)) < tol
+
+
+def test_graph_replays_match_eager():
+    """ase_step captured in a HIP graph: every replay, with eager work and
+    synchronisations in between, equals the eager run bit for bit."""
+    w = WL.four_quadrant(70, 9, seed=11, ny=45)
+    g, p = w.grid, w.params
+    eager = ase.Simulation(g, p, w.U, device=DEV)
+    graphed = ase.Simulation(g, p, w.U, device=DEV)
+    graph = graphed.capture(3)
+    for rep in range(4):
+        eager.run(3)
+        graph.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device=DEV).sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        assert torch.equal(eager.U, graphed.U), rep
+        # every stored face (the last column / row has no face)
+        assert torch.equal(eager.sx[:, :g.NX - 1], graphed.sx[:, :g.NX - 1]), rep
+        assert torch.equal(eager.sy[:g.NY - 1, :g.NX], graphed.sy[:g.NY - 1, :g.NX]), rep
+        assert torch.equal(eager.t, graphed.t), rep
+    del junk
