@@ -225,25 +225,85 @@ int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, int32_t ninst, con
  * its bin through all steps (ghost cells, DF state, per-instance dt, three
  * stages of the 1D method of ase_step) without returning to the host.
  * Results equal ase_step on each instance alone.  t: device [ninst], in/out.
- * dt_hist: optional device [nsteps][ninst].  t_end > 0 stops each instance
- * at t_end.  bin_start/bin_list: device copies of an ase_batched_plan. */
+ * dt_hist: optional device [nsteps][ninst].  dt_replay: optional device
+ * [nsteps][ninst] of time steps to take instead of the CFL rule (an entry
+ * <= 0 stops that instance; dt_cap and the clipping at t_end are then not
+ * applied) -- for replaying a recorded run.  t_end > 0 stops each instance at t_end.
+ * bin_start/bin_list: device copies of an ase_batched_plan. */
 int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
                      const int32_t *ncells, const double *dx, int32_t ng, int64_t total, double *U, double *sigma,
-                     double *t, double *dt_hist, int32_t nsteps, double t_end, const int32_t *bin_start,
-                     const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
+                     double *t, double *dt_hist, const double *dt_replay, int32_t nsteps, double t_end,
+                     const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/* ---- Discrete adjoint of the 1D step ---------------------------------------
+ * The paper defines the forward method only.  The adjoint here is the exact
+ * transposed Jacobian of the discrete SSP-RK3 step (Sec. 2.1) with these
+ * decisions frozen at their forward values: the time step, the DF strengths
+ * every stage reads (hence each DF factor of Sec. 3.1 and each stencil level
+ * of Algorithm 1), the side that gives the LF signal speed (Sec. 2.3) and the
+ * positivity replacements.  Differentiated exactly: the reconstructions of
+ * Sec. 3.2-3.4 (including the nonlinear WENO-Z-AO weights), the Euler and LF
+ * fluxes, the stage combinations and the ghost copies of the boundary
+ * conditions.  Boundaries: transmissive or periodic (both sides alike). */
+
+/* Device workspace of ase_adjoint_step on the 1D grid g. */
+size_t ase_adjoint_workspace_bytes(const ase_grid_t *g);
+
+/* lam_n = (dU_{n+1}/dU_n)^T lam_np1 for one step of a 1D grid.  U_n, sigma_n:
+ * the state and DF strengths the step starts from (what ase_step holds before
+ * it; layouts as ase_step, U [3][ld], sigma [ld]); dt: device scalar, the
+ * step's time step (ase_step's dt_hist entry).  Only interior entries of
+ * lam_np1 are read; ghost entries of lam_n are set to 0; lam_n may equal
+ * lam_np1.  U_n and sigma_n are not modified.  The step is recomputed from
+ * (U_n, sigma_n, dt) bit for bit as ase_step takes it.  One workgroup walks
+ * the grid (batches of 1D grids go through ase_adjoint_batched).  Device
+ * pointers; asynchronous on `stream`. */
+int ase_adjoint_step(const ase_grid_t *g, const ase_params_t *p, const double *U_n, const double *sigma_n,
+                     const double *dt, const double *lam_np1, double *lam_n, void *ws, size_t ws_bytes,
                      void *stream);
+
+/* Device workspace of ase_adjoint_batched for `total` stored cells and a
+ * segment of nsteps steps (a tape of 3 nsteps stage inputs). */
+size_t ase_adjoint_batched_workspace_bytes(int64_t total, int32_t nsteps);
+
+/* Adjoint of nsteps batched steps (instance table, bc and bins as in
+ * ase_step_batched; threads 128 or 256).  U_ck, sigma_ck: state and DF
+ * strengths at the segment start (a checkpoint of the forward run);
+ * dt_hist: device [nsteps][ninst], the segment's recorded time steps (0 =
+ * step not taken).  lam [3][total]: in, the adjoint at the segment end; out,
+ * the adjoint at its start (ghost entries 0).  One persistent launch: each
+ * workgroup re-runs the segment forward for its instances, keeping every
+ * stage input in the workspace, then runs the steps back.  Device pointers;
+ * asynchronous on `stream`. */
+int ase_adjoint_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
+                        const int32_t *ncells, const double *dx, int32_t ng, int64_t total, const double *U_ck,
+                        const double *sigma_ck, const double *dt_hist, int32_t nsteps, double *lam,
+                        const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* Objective of the adjoint runs: J_k = dx_k sum_i p_i over the interior cells
+ * of each instance (p from the Euler equation of state, Sec. 2.3), and the
+ * weighted gradient lam = w_k dJ_k/dU = w_k dx_k (gamma-1) (u^2/2, -u, 1)
+ * (ghost entries 0).  weights [ninst] may be NULL (all 1); J [ninst] and
+ * lam [3][total] may each be NULL.  A single 1D grid is the table
+ * {offset 0, nx, dx} with total = ld.  Device pointers; asynchronous. */
+int ase_pressure_objective(const ase_params_t *p, int32_t ninst, const int64_t *offsets, const int32_t *ncells,
+                           const double *dx, int32_t ng, int64_t total, const double *U, const double *weights,
+                           double *J, double *lam, void *stream);
 
 /* Per-kernel timing of ase_step, for benchmarks and profiling (not for
  * production runs).  While enabled, ase_step brackets every launch of its
  * reconstruction/flux/update kernels with HIP events on the call's stream
- * and of ase_step_batched's persistent kernel (pool of 8192 launches;
+ * and of the persistent kernels of ase_step_batched and the adjoint entry
+ * points (pool of 8192 launches;
  * further launches go unrecorded).
  * ase_profile_enable(1) clears and enables recording, (0) disables it.
  * ase_profile_read waits for the recorded events, then returns the summed
  * duration in milliseconds and the number of launches of one kernel class
  * (ASE_KCLASS_*); it does not clear the record. */
 enum { ASE_KCLASS_SWEEP_X = 0, ASE_KCLASS_SWEEP_Y = 1, ASE_KCLASS_STAGE_1D = 2, ASE_KCLASS_BC = 3,
-       ASE_KCLASS_CFL = 4, ASE_KCLASS_BATCHED = 5, ASE_KCLASS_COUNT = 6 };
+       ASE_KCLASS_CFL = 4, ASE_KCLASS_BATCHED = 5, ASE_KCLASS_ADJOINT = 6, ASE_KCLASS_COUNT = 7 };
 int ase_profile_enable(int on);
 int ase_profile_read(int kernel_class, double *total_ms, int64_t *launches);
 

@@ -39,9 +39,10 @@ class AseParams(C.Structure):
 EXPORTS = ("ase_last_error", "ase_version", "ase_bc_fill", "ase_sigma_init", "ase_cfl_dt", "ase_reconstruct",
            "ase_df_compute", "ase_flux", "ase_stage_update", "ase_workspace_bytes", "ase_step",
            "ase_profile_enable", "ase_profile_read", "ase_batched_plan", "ase_batched_workspace_bytes",
-           "ase_batched_sigma_init", "ase_step_batched")
+           "ase_batched_sigma_init", "ase_step_batched", "ase_adjoint_workspace_bytes", "ase_adjoint_step",
+           "ase_adjoint_batched_workspace_bytes", "ase_adjoint_batched", "ase_pressure_objective")
 
-KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4, "batched": 5}
+KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4, "batched": 5, "adjoint": 6}
 
 
 class AseError(RuntimeError):
@@ -75,7 +76,15 @@ def lib():
     L.ase_batched_workspace_bytes.argtypes = [C.c_int64]
     L.ase_batched_sigma_init.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.c_int32, C.c_int64, vp, vp, vp]
     L.ase_step_batched.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp,
-                                   C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+                                   vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+    L.ase_adjoint_workspace_bytes.restype = C.c_size_t
+    L.ase_adjoint_workspace_bytes.argtypes = [vp]
+    L.ase_adjoint_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, vp, C.c_size_t, vp]
+    L.ase_adjoint_batched_workspace_bytes.restype = C.c_size_t
+    L.ase_adjoint_batched_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
+    L.ase_adjoint_batched.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp,
+                                      C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+    L.ase_pressure_objective.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp]
     L.ase_profile_enable.argtypes = [C.c_int]
     L.ase_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in EXPORTS:
@@ -296,14 +305,57 @@ class BatchedSimulation:
         else:
             self.sig.copy_(torch.as_tensor(sigma))
 
-    def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None):
+    def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None, dt_replay=None):
         b = self.b
         _check(lib().ase_step_batched(C.byref(c_params(self.p)), b.bc, b.ninst, _p(self.offsets), _p(self.ncells),
                                       _p(self.dx), b.ng, b.total, _p(self.U), _p(self.sig), _p(self.t),
-                                      _p(dt_hist), int(nsteps), float(t_end), _p(self.bin_start),
+                                      _p(dt_hist), _p(dt_replay), int(nsteps), float(t_end), _p(self.bin_start),
                                       _p(self.bin_list), self.nbins, self.threads, self.ws.ptr, self.ws.nbytes,
                                       _stream(stream)), "ase_step_batched")
 
     def capture(self, nsteps: int, t_end: float = 0.0):
         """A HIP graph holding the persistent launch of nsteps steps."""
         return _capture(lambda: self.run(nsteps, t_end))
+
+
+# ---------------------------------------------------------------------------
+# Discrete adjoint (1D): raw entry points.  The autograd wrappers with
+# checkpointing are in paper_2410_05489_amd.adjoint.
+# ---------------------------------------------------------------------------
+
+def adjoint_workspace_bytes(g: Grid) -> int:
+    n = lib().ase_adjoint_workspace_bytes(C.byref(c_grid(g)))
+    if n == 0:
+        raise AseError("ase_adjoint_workspace_bytes: 1D grid expected")
+    return int(n)
+
+
+def adjoint_step(g, p, U_n, sigma_n, dt, lam_np1, lam_n, ws: Workspace, stream=None):
+    """lam_n = (dU_{n+1}/dU_n)^T lam_np1 for one step of a 1D grid (dt: device
+    scalar tensor; lam_n may be lam_np1)."""
+    G, P = _gp(g, p)
+    _check(lib().ase_adjoint_step(G, P, _p(U_n), _p(sigma_n), _p(dt), _p(lam_np1), _p(lam_n), ws.ptr, ws.nbytes,
+                                  _stream(stream)), "ase_adjoint_step")
+
+
+def adjoint_batched_workspace_bytes(total: int, nsteps: int) -> int:
+    return int(lib().ase_adjoint_batched_workspace_bytes(int(total), int(nsteps)))
+
+
+def adjoint_batched(sim: "BatchedSimulation", U_ck, sig_ck, dt_hist, nsteps: int, lam, ws: Workspace,
+                    threads: int = 256, stream=None):
+    """Adjoint of nsteps steps of a batch from the checkpoint (U_ck, sig_ck);
+    dt_hist [nsteps, ninst] the recorded steps; lam [3, total] in/out."""
+    b = sim.b
+    _check(lib().ase_adjoint_batched(C.byref(c_params(sim.p)), b.bc, b.ninst, _p(sim.offsets), _p(sim.ncells),
+                                     _p(sim.dx), b.ng, b.total, _p(U_ck), _p(sig_ck), _p(dt_hist), int(nsteps),
+                                     _p(lam), _p(sim.bin_start), _p(sim.bin_list), sim.nbins, int(threads), ws.ptr,
+                                     ws.nbytes, _stream(stream)), "ase_adjoint_batched")
+
+
+def pressure_objective(p, offsets, ncells, dx, ng: int, total: int, U, J=None, lam=None, weights=None,
+                       stream=None):
+    """J_k = dx_k sum p over each instance's interior; lam = w_k dJ_k/dU."""
+    _check(lib().ase_pressure_objective(C.byref(c_params(p)), int(ncells.numel()), _p(offsets), _p(ncells), _p(dx),
+                                        int(ng), int(total), _p(U), _p(weights), _p(J), _p(lam),
+                                        _stream(stream)), "ase_pressure_objective")

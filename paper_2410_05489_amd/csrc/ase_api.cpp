@@ -485,9 +485,9 @@ int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, int32_t ninst, con
 
 int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
                      const int32_t *ncells, const double *dx, int32_t ng, int64_t total, double *U, double *sigma,
-                     double *t, double *dt_hist, int32_t nsteps, double t_end, const int32_t *bin_start,
-                     const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
-                     void *stream)
+                     double *t, double *dt_hist, const double *dt_replay, int32_t nsteps, double t_end,
+                     const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
+                     size_t ws_bytes, void *stream)
 {
     int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
     if (rc) return rc;
@@ -497,6 +497,7 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int
     ASE_PTR(dx, "dx");
     ASE_PTR(t, "t");
     if (dt_hist && misaligned(dt_hist)) return fail(ASE_ERR_ALIGN, "misaligned: dt_hist");
+    if (dt_replay && misaligned(dt_replay)) return fail(ASE_ERR_ALIGN, "misaligned: dt_replay");
     if (!bin_start || !bin_list) return fail(ASE_ERR_ARG, "null bin arrays");
     if (!ws) return fail(ASE_ERR_WORKSPACE, "workspace is required");
     if (ws_bytes < ase_batched_workspace_bytes(total)) return fail(ASE_ERR_WORKSPACE, "workspace too small");
@@ -513,6 +514,7 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int
     bl.sig = sigma;
     bl.t = t;
     bl.dt_hist = dt_hist;
+    bl.dt_in = dt_replay;
     bl.U1 = reinterpret_cast<double *>(c);
     bl.U2 = reinterpret_cast<double *>(c + 3 * arr);
     bl.sig2 = reinterpret_cast<double *>(c + 6 * arr);
@@ -536,6 +538,173 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int
         launch_batched(bl, (hipStream_t)stream);
     }
     return check_launch("ase_step_batched");
+}
+
+// ---- adjoint ----------------------------------------------------------------
+
+static size_t adjoint_bytes(long long total, int nsteps)
+{
+    const size_t n = (size_t)total * sizeof(double);
+    return align_up(9 * (size_t)nsteps * n) + align_up(3 * (size_t)nsteps * n) + 2 * align_up(3 * n);
+}
+
+static void carve_adjoint(void *ws, long long total, int nsteps, AdjLaunch *al)
+{
+    const size_t n = (size_t)total * sizeof(double);
+    char *c = static_cast<char *>(ws);
+    al->tapeU = reinterpret_cast<double *>(c);
+    c += align_up(9 * (size_t)nsteps * n);
+    al->tapeS = reinterpret_cast<double *>(c);
+    c += align_up(3 * (size_t)nsteps * n);
+    al->mu1 = reinterpret_cast<double *>(c);
+    c += align_up(3 * n);
+    al->mu2 = reinterpret_cast<double *>(c);
+}
+
+static int check_ws(void *ws, size_t ws_bytes, size_t need)
+{
+    if (!ws) return fail(ASE_ERR_WORKSPACE, "workspace is required");
+    if (ws_bytes < need) return fail(ASE_ERR_WORKSPACE, "workspace too small");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(ASE_ERR_ALIGN, "workspace must be 256-byte aligned");
+    return ASE_OK;
+}
+
+size_t ase_adjoint_workspace_bytes(const ase_grid_t *g)
+{
+    if (!g || g->dim != 1 || g->ld < 1) return 0;
+    return adjoint_bytes(g->ld, 1);
+}
+
+int ase_adjoint_step(const ase_grid_t *g, const ase_params_t *p, const double *U_n, const double *sigma_n,
+                     const double *dt, const double *lam_np1, double *lam_n, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    if (geo.dim != 1) return fail(ASE_ERR_ARG, "ase_adjoint_step: 1D grids only");
+    if (g->bc[0] != g->bc[1] || (g->bc[0] != ASE_BC_TRANSMISSIVE && g->bc[0] != ASE_BC_PERIODIC))
+        return fail(ASE_ERR_ARG, "ase_adjoint_step: boundaries must be both transmissive or both periodic");
+    ASE_PTR(U_n, "U_n");
+    ASE_PTR(sigma_n, "sigma_n");
+    ASE_PTR(dt, "dt");
+    ASE_PTR(lam_np1, "lam_np1");
+    ASE_PTR(lam_n, "lam_n");
+    rc = check_ws(ws, ws_bytes, adjoint_bytes(geo.ld, 1));
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (lam_n != lam_np1) {
+        hipError_t e = hipMemcpyAsync(lam_n, lam_np1, 3 * (size_t)geo.ld * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(lam)");
+    }
+    AdjLaunch al;
+    std::memset(&al, 0, sizeof(al));
+    carve_adjoint(ws, geo.ld, 1, &al);
+    al.n1 = geo.nx;
+    al.dx1 = g->dx;
+    al.ck_U = U_n;
+    al.ck_sig = sigma_n;
+    al.dt_hist = dt;
+    al.lam = lam_n;
+    al.total = geo.ld;
+    al.ninst = 1;
+    al.threads = 256;
+    al.R = geo.R;
+    al.ng = geo.ng;
+    al.nsteps = 1;
+    al.bc = g->bc[0];
+    al.fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
+    al.mc = method_const(p);
+    {
+        ProfScope ps(ASE_KCLASS_ADJOINT, st);
+        launch_adjoint(al, st);
+    }
+    return check_launch("ase_adjoint_step");
+}
+
+size_t ase_adjoint_batched_workspace_bytes(int64_t total, int32_t nsteps)
+{
+    if (total < 1 || nsteps < 1) return 0;
+    return adjoint_bytes(total, nsteps);
+}
+
+int ase_adjoint_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
+                        const int32_t *ncells, const double *dx, int32_t ng, int64_t total, const double *U_ck,
+                        const double *sigma_ck, const double *dt_hist, int32_t nsteps, double *lam,
+                        const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, const_cast<double *>(U_ck),
+                            const_cast<double *>(sigma_ck));
+    if (rc) return rc;
+    if (nsteps < 0) return fail(ASE_ERR_ARG, "nsteps must be >= 0");
+    if (nbins < 1) return fail(ASE_ERR_ARG, "nbins must be >= 1");
+    if (threads != 128 && threads != 256) return fail(ASE_ERR_ARG, "threads must be 128 or 256");
+    ASE_PTR(dx, "dx");
+    ASE_PTR(dt_hist, "dt_hist");
+    ASE_PTR(lam, "lam");
+    if (!bin_start || !bin_list) return fail(ASE_ERR_ARG, "null bin arrays");
+    if (nsteps == 0) return ASE_OK;
+    rc = check_ws(ws, ws_bytes, adjoint_bytes(total, nsteps));
+    if (rc) return rc;
+    AdjLaunch al;
+    std::memset(&al, 0, sizeof(al));
+    carve_adjoint(ws, total, nsteps, &al);
+    al.offsets = reinterpret_cast<const long long *>(offsets);
+    al.ncells = ncells;
+    al.dx = dx;
+    al.ck_U = U_ck;
+    al.ck_sig = sigma_ck;
+    al.dt_hist = dt_hist;
+    al.lam = lam;
+    al.bin_start = bin_start;
+    al.bin_list = bin_list;
+    al.total = total;
+    al.ninst = ninst;
+    al.nbins = nbins;
+    al.threads = threads;
+    al.R = (p->order - 1) / 2;
+    al.ng = ng;
+    al.nsteps = nsteps;
+    al.bc = bc;
+    al.fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
+    al.mc = method_const(p);
+    {
+        ProfScope ps(ASE_KCLASS_ADJOINT, (hipStream_t)stream);
+        launch_adjoint(al, (hipStream_t)stream);
+    }
+    return check_launch("ase_adjoint_batched");
+}
+
+int ase_pressure_objective(const ase_params_t *p, int32_t ninst, const int64_t *offsets, const int32_t *ncells,
+                           const double *dx, int32_t ng, int64_t total, const double *U, const double *weights,
+                           double *J, double *lam, void *stream)
+{
+    if (!p) return fail(ASE_ERR_ARG, "null params");
+    if (!(p->gamma > 1.0)) return fail(ASE_ERR_ARG, "gamma must be > 1");
+    if (ninst < 1 || total < 1 || ng < 0) return fail(ASE_ERR_ARG, "ninst, total must be >= 1 and ng >= 0");
+    ASE_PTR(offsets, "offsets");
+    ASE_PTR(ncells, "ncells");
+    ASE_PTR(dx, "dx");
+    ASE_PTR(U, "U");
+    if (weights && misaligned(weights)) return fail(ASE_ERR_ALIGN, "misaligned: weights");
+    if (J && misaligned(J)) return fail(ASE_ERR_ALIGN, "misaligned: J");
+    if (lam && misaligned(lam)) return fail(ASE_ERR_ALIGN, "misaligned: lam");
+    ObjLaunch ol;
+    std::memset(&ol, 0, sizeof(ol));
+    ol.offsets = reinterpret_cast<const long long *>(offsets);
+    ol.ncells = ncells;
+    ol.dx = dx;
+    ol.U = U;
+    ol.w = weights;
+    ol.J = J;
+    ol.lam = lam;
+    ol.total = total;
+    ol.ninst = ninst;
+    ol.ng = ng;
+    ol.gm1 = p->gamma - 1.0;
+    launch_objective(ol, (hipStream_t)stream);
+    return check_launch("ase_pressure_objective");
 }
 
 int ase_profile_enable(int on)

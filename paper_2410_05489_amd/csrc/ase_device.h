@@ -492,6 +492,210 @@ __device__ __forceinline__ double swap_pair(double x)
     return __hiloint2double(hi2, lo2);
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint building blocks (1D): Jacobians of the reconstruction with the DF
+// factors and the stencil level frozen, and the transposed LF flux with the
+// signal-speed side and positivity replacements frozen.
+// ---------------------------------------------------------------------------
+
+// Forward-mode number with N partial derivatives.
+template <int N>
+struct Dual {
+    double v;
+    double d[N];
+};
+
+template <int N>
+__device__ __forceinline__ Dual<N> dconst(double c)
+{
+    Dual<N> r;
+    r.v = c;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = 0.0;
+    return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator+(const Dual<N> &a, const Dual<N> &b)
+{
+    Dual<N> r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+    return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N> &a, const Dual<N> &b)
+{
+    Dual<N> r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(const Dual<N> &a, const Dual<N> &b)
+{
+    Dual<N> r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(double c, const Dual<N> &a)
+{
+    Dual<N> r;
+    r.v = c * a.v;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = c * a.d[k];
+    return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator/(const Dual<N> &a, const Dual<N> &b)
+{
+    Dual<N> r;
+    r.v = a.v / b.v;
+    const double ib = 1.0 / b.v;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+    return r;
+}
+// |a| with derivative sign(a) (0 at a = 0).
+template <int N>
+__device__ __forceinline__ Dual<N> dabs(const Dual<N> &a)
+{
+    Dual<N> r;
+    r.v = fabs(a.v);
+    const double sg = a.v > 0.0 ? 1.0 : (a.v < 0.0 ? -1.0 : 0.0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = sg * a.d[k];
+    return r;
+}
+
+// Jacobian of the WENO-Z-AO(5,3)+DF face values with respect to W_{-2..2}
+// (DF factors frozen): J[q][m], q = 0 (xi = 0), 1 (xi = -1).
+__device__ __forceinline__ void weno_ao53_jac(const double (&W)[5], const double al[4], const MethodConst &mc, int oi,
+                                              double (&J)[2][5])
+{
+    using D = Dual<5>;
+    D w[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        w[m] = dconst<5>(W[m]);
+        w[m].d[m] = 1.0;
+    }
+    const D &Wm2 = w[0], &Wm1 = w[1], &W0 = w[2], &W1 = w[3], &W2 = w[4];
+    const D am1 = 2.0 * W0 - 3.0 * Wm1 + Wm2, am2 = 0.5 * (Wm2 - 2.0 * Wm1 + W0);
+    const D a01 = W1 - W0, a02 = 0.5 * (Wm1 - 2.0 * W0 + W1);
+    const D ap1 = W1 - W0, ap2 = 0.5 * (W0 - 2.0 * W1 + W2);
+    const D b1 = (1.0 / 12.0) * (-15.0 * W0 + Wm1 + 15.0 * W1 - W2);
+    const D b2 = 0.125 * (-8.0 * W0 + 6.0 * Wm1 - Wm2 + 2.0 * W1 + W2);
+    const D b3 = (1.0 / 6.0) * (3.0 * W0 - Wm1 - 3.0 * W1 + W2);
+    const D b4 = (1.0 / 24.0) * (6.0 * W0 - 4.0 * Wm1 + Wm2 - 4.0 * W1 + W2);
+    const D sm = am1 * am1 - 2.0 * (am1 * am2) + (16.0 / 3.0) * (am2 * am2);
+    const D s0 = a01 * a01 - 2.0 * (a01 * a02) + (16.0 / 3.0) * (a02 * a02);
+    const D sp = ap1 * ap1 - 2.0 * (ap1 * ap2) + (16.0 / 3.0) * (ap2 * ap2);
+    const D s5 = (1.0 / 6.0) * (sm + 4.0 * s0 + sp) + dabs(sm - sp);
+    const D tz = (1.0 / 3.0) * (dabs(s5 - sm) + dabs(s5 - s0) + dabs(s5 - sp));
+    const D tz2 = tz * tz;
+    const D eps = dconst<5>(mc.eps), one = dconst<5>(1.0);
+    const D e5 = s5 + eps, em = sm + eps, e0 = s0 + eps, ep = sp + eps;
+    const D w5 = mc.d5 * (one + tz2 / (e5 * e5));
+    const D wm = mc.d3m * (one + tz2 / (em * em));
+    const D w0 = mc.d30 * (one + tz2 / (e0 * e0));
+    const D wp = mc.d3m * (one + tz2 / (ep * ep));
+    const D ws = w5 + wm + w0 + wp;
+    const D o5 = w5 / ws, om = wm / ws, o0 = w0 / ws, op = wp / ws;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const double *z = kTab.z[oi][q];
+        const D Pm = W0 + al[0] * (z[0] * am1 + z[1] * am2);
+        const D P0 = W0 + al[1] * (z[0] * a01 + z[1] * a02);
+        const D Pp = W0 + al[2] * (z[0] * ap1 + z[1] * ap2);
+        const D P5 = W0 + al[3] * (z[0] * b1 + z[1] * b2 + z[2] * b3 + z[3] * b4);
+        const D inner = mc.inv_d5 * P5 - mc.r3m * Pm - mc.r30 * P0 - mc.r3m * Pp;
+        const D P = o5 * inner + om * Pm + o0 * P0 + op * Pp;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) J[q][m] = P.d[m];
+    }
+}
+
+// Jacobian of one cell's two face values of one variable with respect to its
+// stencil W_{-R..R}: J[q][m + R], q = 0 (xi = 0), 1 (xi = -1).  Same level
+// rule as the forward reconstruction; ldv(m) reads the variable at offset m.
+template <int R, class LDV>
+__device__ __forceinline__ void recon_jacobian_var(LDV ldv, const double (&s)[2 * R], const MethodConst &mc,
+                                                   double (&J)[2][2 * R + 1])
+{
+    constexpr int OI = R - 1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int m = 0; m < 2 * R + 1; ++m) J[q][m] = 0.0;
+    if constexpr (R == 1) {
+        // P = W0 + al ((W1 - W0) Z1 + (W-1 - 2 W0 + W1) Z2 / 2)
+        const double al = df_alpha(s[0] + s[1], mc.thr);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double *z = kTab.z[OI][q];
+            J[q][0] = al * 0.5 * z[1];
+            J[q][1] = 1.0 + al * (-z[0] - z[1]);
+            J[q][2] = al * (z[0] + 0.5 * z[1]);
+        }
+    } else {
+        const int lvl = select_level<R>(s, mc.thr);
+        if (lvl == LVL_WENOAO) {
+            double al[4];
+            al[0] = df_alpha(ssum<R>(s, -2, 0), mc.thr);
+            al[1] = df_alpha(ssum<R>(s, -1, 1), mc.thr);
+            al[2] = df_alpha(ssum<R>(s, 0, 2), mc.thr);
+            al[3] = df_alpha(ssum<R>(s, -2, 2), mc.thr);
+            double W[5], Jw[2][5];
+#pragma unroll
+            for (int m = -2; m <= 2; ++m) W[m + 2] = ldv(m);
+            weno_ao53_jac(W, al, mc, OI, Jw);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int m = -2; m <= 2; ++m) J[q][m + R] = Jw[q][m + 2];
+        } else {
+            // linear levels: the tap weights themselves (compile-time constants)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int m = -R; m <= R; ++m) {
+                    const double w9 = (R >= 4) ? kTab.lin[OI][3][q][4 + m] : 0.0;
+                    const double w7 = (R >= 3 && m >= -3 && m <= 3) ? kTab.lin[OI][2][q][4 + m] : 0.0;
+                    const double w5 = (m >= -2 && m <= 2) ? kTab.lin[OI][1][q][4 + m] : 0.0;
+                    J[q][m + R] = lvl == 9 ? w9 : (lvl == 7 ? w7 : w5);
+                }
+        }
+    }
+}
+
+// Transposed 1D Euler flux Jacobian and signal-speed gradient of a state:
+// gW += (dF/dW)^T gF ; ds/dW written to ds.
+__device__ __forceinline__ void euler1d_vjp(const double (&W)[3], const Prim &q, const MethodConst &mc,
+                                            const double (&gF)[3], double scale, double (&gW)[3], double (&ds)[3])
+{
+    const double rho = W[0], u = q.un, p = q.p, E = W[2];
+    const double gm = mc.gm1;
+    const double pr = gm * 0.5 * u * u, pm = -gm * u, pE = gm;   // dp/d(rho, m, E)
+    const double H = (E + p) / rho;
+    // rows of A = dF/dW
+    const double A[3][3] = {{0.0, 1.0, 0.0},
+                            {-u * u + pr, 2.0 * u + pm, pE},
+                            {u * pr - u * H, H + u * pm, u * (1.0 + pE)}};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gW[c] += scale * (A[0][c] * gF[0] + A[1][c] * gF[1] + A[2][c] * gF[2]);
+    // s = |u| + c, c = sqrt(gamma p / rho)
+    const double su = u > 0.0 ? 1.0 : (u < 0.0 ? -1.0 : 0.0);
+    const double dc = 0.5 * mc.gamma / (q.c * rho);
+    ds[0] = su * (-u / rho) + dc * (pr - p / rho);
+    ds[1] = su * (1.0 / rho) + dc * pm;
+    ds[2] = dc * pE;
+}
+
 #endif  // ASE_KERNEL_TU
 
 }  // namespace ase

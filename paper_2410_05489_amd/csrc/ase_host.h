@@ -83,6 +83,7 @@ struct BatchLaunch {
     const int *ncells;
     const double *dx;
     double *U, *sig, *t, *dt_hist, *U1, *U2, *sig2;
+    const double *dt_in;
     const int *bin_start, *bin_list;
     long long total;
     int ninst, nbins, threads, R, ng, nsteps, bc, fo, init;
@@ -90,5 +91,35 @@ struct BatchLaunch {
     MethodConst mc;
 };
 void launch_batched(const BatchLaunch &bl, hipStream_t st);
+
+struct AdjLaunch {
+    const long long *offsets;   // nullptr: single instance (n1, dx1) at offset 0
+    const int *ncells;
+    const double *dx;
+    int n1;
+    double dx1;
+    const double *ck_U, *ck_sig, *dt_hist;
+    double *lam, *mu1, *mu2, *tapeU, *tapeS;
+    const int *bin_start, *bin_list;   // nullptr: one workgroup per instance
+    long long total;
+    int ninst, nbins, threads, R, ng, nsteps, bc, fo;
+    MethodConst mc;
+};
+void launch_adjoint(const AdjLaunch &al, hipStream_t st);
+
+struct ObjLaunch {
+    const long long *offsets;
+    const int *ncells;
+    const double *dx;
+    int n1;
+    double dx1;
+    const double *U;
+    const double *w;
+    double *J, *lam;
+    long long total;
+    int ninst, ng;
+    double gm1;
+};
+void launch_objective(const ObjLaunch &ol, hipStream_t st);
 
 }  // namespace ase

@@ -672,6 +672,7 @@ struct BatchArgs {
     const int *ncells;
     const double *dx;
     double *U, *sig, *t, *dt_hist;
+    const double *dt_in;        // optional [nsteps][ninst]: replayed time steps instead of the CFL rule
     double *U1, *U2, *sig2;     // workspace, same layout as U / sig
     const int *bin_start, *bin_list;
     long long total;
@@ -736,32 +737,39 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
         for (; s < a.nsteps; ++s) {
             if (a.t_end > 0.0 && t >= a.t_end) break;
             batched_fill<NT>(a, U, sA, N, mc);
-            // dt from the signal speeds of this instance
-            double lam = 0.0;
-            for (int i = threadIdx.x; i < N; i += NT) {
-                double W[3];
+            if (a.dt_in) {
+                const double dtr = a.dt_in[(long long)s * a.ninst + k];
+                if (!(dtr > 0.0)) break;
+                if (threadIdx.x == 0) s_dt = dtr;
+                __syncthreads();
+            } else {
+                // dt from the signal speeds of this instance
+                double lam = 0.0;
+                for (int i = threadIdx.x; i < N; i += NT) {
+                    double W[3];
 #pragma unroll
-                for (int v = 0; v < 3; ++v) W[v] = U[v * a.total + i + a.ng];
-                const Prim q = primitives<3>(W, 0, mc);
-                const double l = (fabs(q.un) + q.c) * inv_dx;
-                lam = (l > lam || l != l) ? l : lam;
-            }
-            red[threadIdx.x] = lam;
-            __syncthreads();
-            for (int w = NT / 2; w > 0; w >>= 1) {
-                if ((int)threadIdx.x < w) {
-                    const double o = red[threadIdx.x + w];
-                    red[threadIdx.x] = (o > red[threadIdx.x] || o != o) ? o : red[threadIdx.x];
+                    for (int v = 0; v < 3; ++v) W[v] = U[v * a.total + i + a.ng];
+                    const Prim q = primitives<3>(W, 0, mc);
+                    const double l = (fabs(q.un) + q.c) * inv_dx;
+                    lam = (l > lam || l != l) ? l : lam;
+                }
+                red[threadIdx.x] = lam;
+                __syncthreads();
+                for (int w = NT / 2; w > 0; w >>= 1) {
+                    if ((int)threadIdx.x < w) {
+                        const double o = red[threadIdx.x + w];
+                        red[threadIdx.x] = (o > red[threadIdx.x] || o != o) ? o : red[threadIdx.x];
+                    }
+                    __syncthreads();
+                }
+                if (threadIdx.x == 0) {
+                    double dt = a.cfl / red[0];
+                    if (a.dt_cap > 0.0 && dt > a.dt_cap) dt = a.dt_cap;
+                    if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
+                    s_dt = dt;
                 }
                 __syncthreads();
             }
-            if (threadIdx.x == 0) {
-                double dt = a.cfl / red[0];
-                if (a.dt_cap > 0.0 && dt > a.dt_cap) dt = a.dt_cap;
-                if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
-                s_dt = dt;
-            }
-            __syncthreads();
             const double dt = s_dt;
             double *in_st[3] = {U, U1, U2};
             double *out_st[3] = {U1, U2, U};
@@ -810,6 +818,432 @@ __global__ void __launch_bounds__(NT) k_batched_sigma_init(BatchArgs a)
     BatchArgs b = a;
     b.fo = 1;
     batched_fill<NT>(b, a.U + off, a.sig + off, N, a.mc);
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of the 1D step.  Frozen decisions: the time step, the
+// strengths every stage read (hence DF factors and stencil levels), the side
+// that gives the LF signal speed and the positivity replacements.  Everything
+// else is differentiated exactly, including the WENO-Z-AO weights and the
+// ghost copies of the boundary conditions.
+//
+// One workgroup owns an instance: it first re-runs the forward steps of the
+// segment from the checkpoint with the recorded time steps, keeping every
+// stage input (state and strengths) in a tape, then walks the steps back:
+//   mu2 = 2/3 lam + J(U2)^T (2/3 dt lam)
+//   mu1 = 1/4 mu2 + J(U1)^T (1/4 dt mu2)
+//   lam = 1/3 lam + 3/4 mu2 + mu1 + J(Un)^T (dt mu1)
+// with J the Jacobian of the residual L.  Each J^T g is a tile pass:
+// traces, transposed LF flux per face, then per variable the transposed
+// reconstruction of each cell scattered as 2R+1 tap contributions and
+// gathered per output cell (no atomics, fixed summation order).
+// ---------------------------------------------------------------------------
+template <int R, int T>
+struct LdsAdj {
+    static constexpr int H = 2 * R + 2;       // state window halo
+    static constexpr int WX = T + 2 * H;      // window cells [i0-H, i0+T+H)
+    static constexpr int NC = T + 2 * R + 2;  // trace cells [i0-R-1, i0+T+R]
+    static constexpr int NF = NC - 1;         // faces between consecutive trace cells
+    double sV[3][WX];
+    double sS[WX];
+    double sG[3][NC];
+    double sGL[3][NF], sGR[3][NF];
+    union {
+        struct {
+            double tr[3][NC], tl[3][NC];
+        } t;
+        double c[2 * R + 1][NC];
+    } u;
+    uint8_t rep[NF];
+};
+
+template <int R, int T>
+union LdsAdjAll {
+    Lds1D<R, T> f;
+    LdsAdj<R, T> b;
+};
+
+struct AdjTile {
+    const double *V, *S;   // stage input (ghosts filled) and the strengths the stage read
+    const double *g;       // adjoint weights (interior)
+    double gscale;         // stage coefficient x dt
+    const double *a0, *a1, *a2;
+    double c0, c1, c2;     // out = c0 a0 + c1 a1 + c2 a2 + J^T (gscale g)
+    double *out;
+    long long plane;
+    int N, ng;
+    double inv_dx;
+};
+
+template <int R, int T, int NT>
+__device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const MethodConst &mc, LdsAdj<R, T> &L)
+{
+    using LA = LdsAdj<R, T>;
+    constexpr int H = LA::H, WX = LA::WX, NC = LA::NC, NF = LA::NF;
+    const int tid = threadIdx.x;
+    const int NXs = a.N + 2 * a.ng;
+    const int xw = i0 - H;       // first window cell
+    const int xc = i0 - R - 1;   // first trace cell
+    const long long P = a.plane;
+
+    for (int lx = tid; lx < WX; lx += NT) {
+        const int I = xw + lx + a.ng;
+        const bool in = I >= 0 && I < NXs;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) L.sV[v][lx] = in ? a.V[v * P + I] : 0.0;
+        L.sS[lx] = in ? a.S[I] : 0.0;
+    }
+    for (int c = tid; c < NC; c += NT) {
+        const int x = xc + c;
+        const bool in = x >= 0 && x < a.N;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) L.sG[v][c] = in ? a.gscale * a.g[v * P + x + a.ng] : 0.0;
+    }
+    __syncthreads();
+
+    // face traces of the cells -1..N that lie in the trace range
+    for (int c = tid; c < NC; c += NT) {
+        const int x = xc + c;
+        if (x < -1 || x > a.N) continue;
+        const int lx = c + (H - R - 1);
+        double s[2 * R];
+#pragma unroll
+        for (int m = -R; m < R; ++m) s[m + R] = L.sS[lx + m];
+        auto ld = [&](int v, int m) { return L.sV[v][lx + m]; };
+        double out[3][2];
+        reconstruct_cell<R, 3, 2>(ld, s, mc, R - 1, 0, out);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            L.u.t.tr[v][c] = out[v][0];
+            L.u.t.tl[v][c] = out[v][1];
+        }
+    }
+    __syncthreads();
+
+    // transposed LF flux of face x + 1/2 between trace cells f and f + 1
+    for (int f = tid; f < NF; f += NT) {
+        const int x = xc + f;
+        double gl[3] = {0.0, 0.0, 0.0}, gr[3] = {0.0, 0.0, 0.0};
+        uint8_t rp = 0;
+        if (x >= -1 && x <= a.N - 1) {
+            double h[3], Wl[3], Wr[3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                h[v] = (L.sG[v][f + 1] - L.sG[v][f]) * a.inv_dx;
+                Wl[v] = L.u.t.tr[v][f];
+                Wr[v] = L.u.t.tl[v][f + 1];
+            }
+            Prim ql = primitives<3>(Wl, 0, mc);
+            Prim qr = primitives<3>(Wr, 0, mc);
+            if (mc.flags & 1) {
+                const int lx = f + (H - R - 1);
+                if (!ql.ok) {
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) Wl[v] = L.sV[v][lx];
+                    ql = primitives<3>(Wl, 0, mc);
+                    rp |= 1;
+                }
+                if (!qr.ok) {
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) Wr[v] = L.sV[v][lx + 1];
+                    qr = primitives<3>(Wr, 0, mc);
+                    rp |= 2;
+                }
+            }
+            const double sl = fabs(ql.un) + ql.c, sr = fabs(qr.un) + qr.c;
+            const bool takel = sl > sr;
+            const double hs = 0.5 * (takel ? sl : sr);
+            double dsl[3], dsr[3];
+            euler1d_vjp(Wl, ql, mc, h, 0.5, gl, dsl);
+            euler1d_vjp(Wr, qr, mc, h, 0.5, gr, dsr);
+            double hd = 0.0;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) hd += h[v] * (Wr[v] - Wl[v]);
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                gl[v] += hs * h[v] - (takel ? 0.5 * hd * dsl[v] : 0.0);
+                gr[v] += -hs * h[v] - (takel ? 0.0 : 0.5 * hd * dsr[v]);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            L.sGL[v][f] = gl[v];
+            L.sGR[v][f] = gr[v];
+        }
+        L.rep[f] = rp;
+    }
+    __syncthreads();
+
+    const bool first = i0 == 0, last = i0 + T >= a.N;
+#pragma unroll 1
+    for (int v = 0; v < 3; ++v) {
+        // tap contributions of each cell: c[m][cell] feeds output cell + m
+        for (int c = tid; c < NC; c += NT) {
+            const int x = xc + c;
+            double cc[2 * R + 1];
+#pragma unroll
+            for (int m = 0; m < 2 * R + 1; ++m) cc[m] = 0.0;
+            if (c >= 1 && c <= NC - 2 && x >= -1 && x <= a.N) {
+                double gR = 0.0, gL = 0.0, d = 0.0;
+                if (x <= a.N - 1) {
+                    if (L.rep[c] & 1) d += L.sGL[v][c];
+                    else gR = L.sGL[v][c];
+                }
+                if (x >= 0) {
+                    if (L.rep[c - 1] & 2) d += L.sGR[v][c - 1];
+                    else gL = L.sGR[v][c - 1];
+                }
+                const int lx = c + (H - R - 1);
+                double s[2 * R];
+#pragma unroll
+                for (int m = -R; m < R; ++m) s[m + R] = L.sS[lx + m];
+                double J[2][2 * R + 1];
+                recon_jacobian_var<R>([&](int m) { return L.sV[v][lx + m]; }, s, mc, J);
+#pragma unroll
+                for (int m = 0; m < 2 * R + 1; ++m) cc[m] = gR * J[0][m] + gL * J[1][m];
+                cc[R] += d;
+            }
+#pragma unroll
+            for (int m = 0; m < 2 * R + 1; ++m) L.u.c[m][c] = cc[m];
+        }
+        __syncthreads();
+        for (int jj = tid; jj < T + 2 * a.ng; jj += NT) {
+            const int j = i0 - a.ng + jj;
+            const bool interior = j >= i0 && j < i0 + T && j < a.N;
+            const bool ghost = (first && j < 0) || (last && j >= a.N && j < a.N + a.ng);
+            if (!interior && !ghost) continue;
+            double G = 0.0;
+#pragma unroll
+            for (int m = -R; m <= R; ++m) {
+                const int c = j - m - xc;
+                if (c >= 1 && c <= NC - 2) G += L.u.c[m + R][c];
+            }
+            const long long e = v * P + j + a.ng;
+            if (interior) {
+                double o = a.c0 * a.a0[e];
+                if (a.a1) o += a.c1 * a.a1[e];
+                if (a.a2) o += a.c2 * a.a2[e];
+                G += o;
+            }
+            a.out[e] = G;
+        }
+        __syncthreads();
+    }
+}
+
+// Add the ghost-cell gradients of `out` onto the interior cells the ghosts
+// copy (transmissive: the boundary cell; periodic: the wrapped cell).
+__device__ __forceinline__ void adj_fold(double *out, long long P, int N, int ng, int bc)
+{
+    const int v = threadIdx.x;
+    if (v < 3) {
+        for (int k = 0; k < ng; ++k) {
+            const int j = k - ng;
+            const int tgt = bc == ASE_BC_PERIODIC ? j + N : 0;
+            if (tgt >= 0 && tgt < N) out[v * P + tgt + ng] += out[v * P + k];
+        }
+        for (int k = 0; k < ng; ++k) {
+            const int tgt = bc == ASE_BC_PERIODIC ? k : N - 1;
+            if (tgt >= 0 && tgt < N) out[v * P + tgt + ng] += out[v * P + N + ng + k];
+        }
+    }
+    __syncthreads();
+}
+
+struct AdjArgs {
+    const long long *offsets;   // nullptr: one instance at offset 0 with n1 cells of width dx1
+    const int *ncells;
+    const double *dx;
+    int n1;
+    double dx1;
+    const double *ck_U, *ck_sig;   // checkpoint at the segment start
+    const double *dt_hist;         // [nsteps][ninst]; 0 = step not taken
+    double *lam;                   // in: adjoint at the segment end; out: at its start
+    double *mu1, *mu2;
+    double *tapeU, *tapeS;         // [3 nsteps][3][total], [3 nsteps][total]
+    const int *bin_start, *bin_list;   // nullptr: instance = workgroup
+    long long total;
+    int ninst, ng, nsteps, bc, fo;
+    MethodConst mc;
+};
+
+template <int R, int NT>
+__device__ __forceinline__ void adj_stage(AdjTile &t, const MethodConst &mc, LdsAdj<R, NT> &L, int bc)
+{
+    for (int i0 = 0; i0 < t.N; i0 += NT) adjoint1d_tile<R, NT, NT>(t, i0, mc, L);
+    adj_fold(t.out, t.plane, t.N, t.ng, bc);
+}
+
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
+{
+    constexpr int T = NT;
+    __shared__ LdsAdjAll<R, T> L;
+    const MethodConst &mc = a.mc;
+    const int tid = threadIdx.x;
+    const int b0 = a.bin_start ? a.bin_start[blockIdx.x] : (int)blockIdx.x;
+    const int b1 = a.bin_start ? a.bin_start[blockIdx.x + 1] : (int)blockIdx.x + 1;
+    for (int b = b0; b < b1; ++b) {
+        const int k = a.bin_start ? a.bin_list[b] : b;
+        long long off;
+        int N;
+        double dx;
+        if (a.offsets) {
+            off = a.offsets[k];
+            N = a.ncells[k];
+            dx = a.dx[k];
+        } else {
+            off = 0;
+            N = a.n1;
+            dx = a.dx1;
+        }
+        if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) continue;   // malformed entry: skipped
+        const int NX = N + 2 * a.ng;
+        const long long P = a.total, SU = 3 * P;
+        const double inv_dx = 1.0 / dx;
+        int nact = 0;
+        while (nact < a.nsteps && a.dt_hist[(long long)nact * a.ninst + k] > 0.0) ++nact;
+
+        // forward over the segment with the recorded steps, keeping the tape
+        for (int I = tid; I < NX; I += NT) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) a.tapeU[v * P + off + I] = a.ck_U[v * P + off + I];
+            a.tapeS[off + I] = a.ck_sig[off + I];
+        }
+        __syncthreads();
+        BatchArgs fb;
+        fb.ng = a.ng;
+        fb.total = a.total;
+        fb.bc = a.bc;
+        fb.fo = a.fo;
+        for (int q = 0; q < nact; ++q) {
+            const double dt = a.dt_hist[(long long)q * a.ninst + k];
+            double *Un = a.tapeU + (3LL * q) * SU + off;
+            for (int st = 0; st < 3; ++st) {
+                double *in = a.tapeU + (3LL * q + st) * SU + off;
+                double *sin = a.tapeS + (3LL * q + st) * P + off;
+                batched_fill<NT>(fb, in, sin, N, mc);
+                if (st == 2 && q == nact - 1) break;
+                Tile1D tl;
+                tl.U = in; tl.sx = sin; tl.Un = Un;
+                tl.Uout = a.tapeU + (3LL * q + st + 1) * SU + off;
+                tl.sig_out = a.tapeS + (3LL * q + st + 1) * P + off;
+                tl.wl = tl.wr = nullptr; tl.level = nullptr;
+                tl.plane = P; tl.nx = N; tl.ng = a.ng; tl.NX = NX; tl.nfaces = N + 1;
+                tl.stage = st + 1; tl.inv_dx = inv_dx; tl.dt = dt;
+                for (int i0 = 0; i0 < N; i0 += T) {
+                    stage1d_tile<R, T, NT, MODE_FUSED_1D>(tl, i0, mc, L.f);
+                    __syncthreads();
+                }
+            }
+        }
+
+        // reverse sweep
+        double *lam = a.lam + off, *mu1 = a.mu1 + off, *mu2 = a.mu2 + off;
+        for (int q = nact - 1; q >= 0; --q) {
+            const double dt = a.dt_hist[(long long)q * a.ninst + k];
+            AdjTile t;
+            t.plane = P; t.N = N; t.ng = a.ng; t.inv_dx = inv_dx;
+            t.a1 = t.a2 = nullptr;
+            t.c1 = t.c2 = 0.0;
+            // stage 3
+            t.V = a.tapeU + (3LL * q + 2) * SU + off;
+            t.S = a.tapeS + (3LL * q + 2) * P + off;
+            t.g = lam; t.gscale = (2.0 / 3.0) * dt;
+            t.a0 = lam; t.c0 = 2.0 / 3.0;
+            t.out = mu2;
+            adj_stage<R, NT>(t, mc, L.b, a.bc);
+            // stage 2
+            t.V = a.tapeU + (3LL * q + 1) * SU + off;
+            t.S = a.tapeS + (3LL * q + 1) * P + off;
+            t.g = mu2; t.gscale = 0.25 * dt;
+            t.a0 = mu2; t.c0 = 0.25;
+            t.out = mu1;
+            adj_stage<R, NT>(t, mc, L.b, a.bc);
+            // stage 1
+            t.V = a.tapeU + (3LL * q) * SU + off;
+            t.S = a.tapeS + (3LL * q) * P + off;
+            t.g = mu1; t.gscale = dt;
+            t.a0 = lam; t.c0 = 1.0 / 3.0;
+            t.a1 = mu2; t.c1 = 0.75;
+            t.a2 = mu1; t.c2 = 1.0;
+            t.out = lam;
+            adj_stage<R, NT>(t, mc, L.b, a.bc);
+        }
+        // ghost slots of the result carry no meaning: clear them
+        for (int kk = tid; kk < 2 * a.ng; kk += NT) {
+            const int I = kk < a.ng ? kk : N + kk;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) lam[v * P + I] = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// J_k = dx_k sum_i p_i over the interior of each instance and its gradient
+// dJ/dU = dx (gamma-1) (u^2/2, -u, 1) (ghost slots 0).  One workgroup per
+// instance, fixed-order tree reduction.
+struct ObjArgs {
+    const long long *offsets;
+    const int *ncells;
+    const double *dx;
+    int n1;
+    double dx1;
+    const double *U;
+    const double *w;   // optional per-instance weights of the gradient
+    double *J, *lam;
+    long long total;
+    int ng;
+    double gm1;
+};
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_pressure_objective(ObjArgs a)
+{
+    __shared__ double red[NT];
+    const int k = blockIdx.x;
+    long long off;
+    int N;
+    double dx;
+    if (a.offsets) {
+        off = a.offsets[k];
+        N = a.ncells[k];
+        dx = a.dx[k];
+    } else {
+        off = 0;
+        N = a.n1;
+        dx = a.dx1;
+    }
+    if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) return;
+    const long long P = a.total;
+    const double wdx = (a.w ? a.w[k] : 1.0) * dx;
+    double acc = 0.0;
+    for (int I = threadIdx.x; I < N + 2 * a.ng; I += NT) {
+        const int i = I - a.ng;
+        const long long e = off + I;
+        if (i < 0 || i >= N) {
+            if (a.lam) {
+#pragma unroll
+                for (int v = 0; v < 3; ++v) a.lam[v * P + e] = 0.0;
+            }
+            continue;
+        }
+        const double rho = a.U[e], m = a.U[P + e], E = a.U[2 * P + e];
+        const double u = m / rho;
+        acc += a.gm1 * (E - 0.5 * m * u);
+        if (a.lam) {
+            a.lam[e] = wdx * a.gm1 * 0.5 * u * u;
+            a.lam[P + e] = -wdx * a.gm1 * u;
+            a.lam[2 * P + e] = wdx * a.gm1;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && a.J) a.J[k] = red[0] * dx;
 }
 
 // ---------------------------------------------------------------------------
@@ -1048,7 +1482,7 @@ void launch_batched(const BatchLaunch &bl, hipStream_t st)
 {
     BatchArgs a;
     a.offsets = bl.offsets; a.ncells = bl.ncells; a.dx = bl.dx;
-    a.U = bl.U; a.sig = bl.sig; a.t = bl.t; a.dt_hist = bl.dt_hist;
+    a.U = bl.U; a.sig = bl.sig; a.t = bl.t; a.dt_hist = bl.dt_hist; a.dt_in = bl.dt_in;
     a.U1 = bl.U1; a.U2 = bl.U2; a.sig2 = bl.sig2;
     a.bin_start = bl.bin_start; a.bin_list = bl.bin_list;
     a.total = bl.total; a.ninst = bl.ninst; a.ng = bl.ng; a.nsteps = bl.nsteps; a.bc = bl.bc; a.fo = bl.fo;
@@ -1074,6 +1508,43 @@ void launch_batched(const BatchLaunch &bl, hipStream_t st)
         }
     }
 #undef ASE_BATCH
+}
+
+void launch_adjoint(const AdjLaunch &al, hipStream_t st)
+{
+    AdjArgs a;
+    a.offsets = al.offsets; a.ncells = al.ncells; a.dx = al.dx; a.n1 = al.n1; a.dx1 = al.dx1;
+    a.ck_U = al.ck_U; a.ck_sig = al.ck_sig; a.dt_hist = al.dt_hist; a.lam = al.lam;
+    a.mu1 = al.mu1; a.mu2 = al.mu2; a.tapeU = al.tapeU; a.tapeS = al.tapeS;
+    a.bin_start = al.bin_start; a.bin_list = al.bin_list;
+    a.total = al.total; a.ninst = al.ninst; a.ng = al.ng; a.nsteps = al.nsteps; a.bc = al.bc; a.fo = al.fo;
+    a.mc = al.mc;
+    const int nblk = al.bin_start ? al.nbins : al.ninst;
+#define ASE_ADJ(RR, NTT) k_adjoint1d<RR, NTT><<<nblk, NTT, 0, st>>>(a)
+    if (al.threads == 128) {
+        switch (al.R) {
+        case 1: ASE_ADJ(1, 128); break;
+        case 2: ASE_ADJ(2, 128); break;
+        case 3: ASE_ADJ(3, 128); break;
+        default: ASE_ADJ(4, 128); break;
+        }
+    } else {
+        switch (al.R) {
+        case 1: ASE_ADJ(1, 256); break;
+        case 2: ASE_ADJ(2, 256); break;
+        case 3: ASE_ADJ(3, 256); break;
+        default: ASE_ADJ(4, 256); break;
+        }
+    }
+#undef ASE_ADJ
+}
+
+void launch_objective(const ObjLaunch &ol, hipStream_t st)
+{
+    ObjArgs a;
+    a.offsets = ol.offsets; a.ncells = ol.ncells; a.dx = ol.dx; a.n1 = ol.n1; a.dx1 = ol.dx1;
+    a.U = ol.U; a.w = ol.w; a.J = ol.J; a.lam = ol.lam; a.total = ol.total; a.ng = ol.ng; a.gm1 = ol.gm1;
+    k_pressure_objective<256><<<ol.ninst, 256, 0, st>>>(a);
 }
 
 }  // namespace ase

@@ -58,3 +58,25 @@ def test_periodic_must_pair():
     G, P = _args(bc=(0, 1, 1, 1))
     assert L.ase_bc_fill(G, P, None, None, None, None) == -1
     assert b"periodic" in L.ase_last_error()
+
+
+def test_adjoint_argument_errors():
+    """The adjoint entry points reject 2D grids, unsupported boundaries and
+    launch shapes before any device work."""
+    L = ase.lib()
+    G, P = _args()                                # 2D grid
+    rc = L.ase_adjoint_step(G, P, None, None, None, None, None, None, 0, None)
+    assert rc == -1 and b"1D" in L.ase_last_error()
+    assert L.ase_adjoint_workspace_bytes(G) == 0
+    w = WL.sod(50, 9)
+    g = w.grid
+    g.bc = (WL.BC_INFLOW_SLOT, WL.BC_TRANSMISSIVE, 1, 1)
+    G1, P1 = C.byref(ase.c_grid(g)), C.byref(ase.c_params(w.params))
+    rc = L.ase_adjoint_step(G1, P1, None, None, None, None, None, None, 0, None)
+    assert rc == -1 and b"transmissive" in L.ase_last_error()
+    g.bc = (WL.BC_TRANSMISSIVE,) * 4
+    assert L.ase_adjoint_workspace_bytes(C.byref(ase.c_grid(g))) > 0
+    rc = L.ase_adjoint_batched(P1, 1, 4, None, None, None, 5, 100, None, None, None, 3, None, None, None, 2, 512,
+                               None, 0, None)
+    assert rc == -1
+    assert L.ase_adjoint_batched_workspace_bytes(1000, 10) >= 1000 * 8 * (12 * 10 + 6)
