@@ -128,6 +128,68 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def measure_adjoint(nsteps=100, every=10, reps=3):
+    """Adjoint/forward wall-time ratio on the batched workload: 256 Riemann
+    instances of 64..4096 cells, order 9, `nsteps` steps; J = sum_k dx_k sum p
+    at the final time; gradient with respect to the initial state through the
+    autograd wrapper (checkpoints every `every` steps).  Forward = the plain
+    persistent launch of nsteps steps; backward = J.sum().backward()
+    (objective gradient + one ase_adjoint_batched launch per segment)."""
+    import numpy as np
+    import torch
+    from paper_2410_05489_amd import adjoint as A
+    from paper_2410_05489_amd import ase, autotune
+    from paper_2410_05489_amd import workloads as WL
+
+    b = WL.batched_riemann(nsteps=nsteps)
+    fwd = autotune.tune_batched(b, nsteps=10, use_cache=False)
+    adj = autotune.tune_adjoint(b, every=every, use_cache=False, fwd_shape=(fwd["nbins"], fwd["threads"]))
+    run = A.BatchedAdjoint(b, "cuda", nbins=fwd["nbins"], threads=fwd["threads"], adj_threads=adj["threads"],
+                           every=every, adj_nbins=adj["nbins"])
+    plain = ase.BatchedSimulation(b, "cuda", nbins=fwd["nbins"], threads=fwd["threads"])
+    U0 = torch.tensor(b.U, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    t_plain, t_fwd, t_bwd = [], [], []
+    for rep in range(reps + 1):
+        plain.U.copy_(U0)
+        plain.t.zero_()
+        torch.cuda.synchronize()
+        ev[0].record()
+        plain.run(nsteps)
+        ev[1].record()
+        x = U0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        ev[2].record()
+        J = run.pressure(run.run(x, nsteps))
+        ev[3].record()
+        if rep == reps:
+            ase.profile_enable(True)
+        ev[4].record()
+        J.sum().backward()
+        ev[5].record()
+        torch.cuda.synchronize()
+        if rep > 0:
+            t_plain.append(ev[0].elapsed_time(ev[1]))
+            t_fwd.append(ev[2].elapsed_time(ev[3]))
+            t_bwd.append(ev[4].elapsed_time(ev[5]))
+    kms, kn = ase.profile_read("adjoint")
+    ase.profile_enable(False)
+    Jh = J.detach().cpu().numpy()
+    gh = x.grad.cpu().numpy()
+    ok = 0
+    for k in range(b.ninst):
+        o, n = int(b.offsets[k]), int(b.ncells[k])
+        ok += int(bool(np.isfinite(Jh[k])) and bool(np.isfinite(gh[:, o:o + n + 2 * b.ng]).all()))
+    med = lambda a: sorted(a)[len(a) // 2]   # noqa: E731
+    tp, tf, tb = med(t_plain), med(t_fwd), med(t_bwd)
+    return {"workload": f"batched_riemann_{b.ninst}x64..4096_r9_seed0", "steps": nsteps, "checkpoint_every": every,
+            "cells": int(b.ncells.sum()), "forward_ms": round(tp, 3), "forward_with_checkpoints_ms": round(tf, 3),
+            "backward_ms": round(tb, 3), "adjoint_fwd_ratio": round(tb / tp, 3),
+            "adjoint_kernel_ms_per_segment": round(kms / max(kn, 1), 3),
+            "forward_shape": [fwd["nbins"], fwd["threads"]], "adjoint_shape": [adj["nbins"], adj["threads"]],
+            "instances_finite": ok, "adjoint_trials": adj["trials"]}
+
+
 def cpu_baseline(w, seconds_hint=True):
     """The oracle (single thread, as written) on one step of the same grid."""
     from oracle import oracle as O
@@ -149,6 +211,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="quad1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -169,6 +232,10 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "adjoint":
+        print(json.dumps({"metric": "adjoint/forward wall-time ratio, batched 1D order 9", **measure_adjoint()}),
+              flush=True)
+        return
 
     import torch
     from paper_2410_05489_amd import ase
@@ -220,6 +287,8 @@ def main():
            "data": "synthetic", "config": {"workload": w.name, "order": p.order, "nx": g.nx, "ny": g.ny,
                                            "gamma": p.gamma, "cfl": p.cfl, "sigma_thres": p.sigma_thres},
            "finite": finite, "roofline": roof}
+    if not args.no_adjoint:
+        out["adjoint"] = measure_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -268,7 +268,7 @@ int ase_adjoint_step(const ase_grid_t *g, const ase_params_t *p, const double *U
 size_t ase_adjoint_batched_workspace_bytes(int64_t total, int32_t nsteps);
 
 /* Adjoint of nsteps batched steps (instance table, bc and bins as in
- * ase_step_batched; threads 128 or 256).  U_ck, sigma_ck: state and DF
+ * ase_step_batched; threads 128, 256 or 512).  U_ck, sigma_ck: state and DF
  * strengths at the segment start (a checkpoint of the forward run);
  * dt_hist: device [nsteps][ninst], the segment's recorded time steps (0 =
  * step not taken).  lam [3][total]: in, the adjoint at the segment end; out,

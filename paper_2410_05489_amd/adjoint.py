@@ -48,7 +48,7 @@ class _BatchedRun(torch.autograd.Function):
             n = min(every, nsteps - s * every)
             if n > 0:
                 ase.adjoint_batched(runner.sim, ckU[s], ckS[s], hist[s * every:s * every + n], n, lam,
-                                    runner.ws_adj, runner.adj_threads)
+                                    runner.ws_adj, runner.adj_threads, runner.adj_plan)
         return lam, None, None
 
 
@@ -78,10 +78,11 @@ class BatchedAdjoint:
     J.sum().backward() gives dJ/dU0 through the adjoint kernels."""
 
     def __init__(self, batch, device="cuda", nbins: int = 0, threads: int = 256, adj_threads: int = 256,
-                 every: int = 10):
+                 every: int = 10, adj_nbins: int = 0):
         self.sim = ase.BatchedSimulation(batch, device, nbins=nbins, threads=threads)
         self.every = int(every)
         self.adj_threads = int(adj_threads)
+        self.adj_plan = ase.device_plan(batch.ncells, adj_nbins, device) if adj_nbins else None
         self.ws_adj = ase.Workspace(ase.adjoint_batched_workspace_bytes(batch.total, self.every), device)
         self.dt_hist = None
 

@@ -342,14 +342,22 @@ def adjoint_batched_workspace_bytes(total: int, nsteps: int) -> int:
     return int(lib().ase_adjoint_batched_workspace_bytes(int(total), int(nsteps)))
 
 
+def device_plan(ncells, nbins: int, device="cuda"):
+    """(nbins, bin_start, bin_list) of batched_plan as device tensors."""
+    start, lst = batched_plan(ncells, nbins)
+    return nbins, torch.as_tensor(start).to(device), torch.as_tensor(lst).to(device)
+
+
 def adjoint_batched(sim: "BatchedSimulation", U_ck, sig_ck, dt_hist, nsteps: int, lam, ws: Workspace,
-                    threads: int = 256, stream=None):
+                    threads: int = 256, plan=None, stream=None):
     """Adjoint of nsteps steps of a batch from the checkpoint (U_ck, sig_ck);
-    dt_hist [nsteps, ninst] the recorded steps; lam [3, total] in/out."""
+    dt_hist [nsteps, ninst] the recorded steps; lam [3, total] in/out.
+    plan: (nbins, bin_start, bin_list) on the device (default: the sim's)."""
     b = sim.b
+    nbins, bs, bl = plan if plan is not None else (sim.nbins, sim.bin_start, sim.bin_list)
     _check(lib().ase_adjoint_batched(C.byref(c_params(sim.p)), b.bc, b.ninst, _p(sim.offsets), _p(sim.ncells),
                                      _p(sim.dx), b.ng, b.total, _p(U_ck), _p(sig_ck), _p(dt_hist), int(nsteps),
-                                     _p(lam), _p(sim.bin_start), _p(sim.bin_list), sim.nbins, int(threads), ws.ptr,
+                                     _p(lam), _p(bs), _p(bl), int(nbins), int(threads), ws.ptr,
                                      ws.nbytes, _stream(stream)), "ase_adjoint_batched")
 
 

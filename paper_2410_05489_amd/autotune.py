@@ -1,9 +1,10 @@
-"""Launch-shape autotuner for the batched persistent kernel.
+"""Launch-shape autotuner for the persistent batched kernels.
 
-Times ase_step_batched for a few (bins, threads) shapes on the current GPU
-and keeps the fastest in a JSON cache keyed by (arch, order, instance-count,
-stored-cell total).  Results do not depend on the shape (every instance is
-advanced by the same per-cell arithmetic), only the time does.
+Times ase_step_batched (and ase_adjoint_batched) for a few (bins, threads)
+shapes on the current GPU and keeps the fastest in a JSON cache keyed by
+(arch, kernel, order, instance-count, stored-cell total).  Results do not
+depend on the shape (every instance is advanced by the same per-cell
+arithmetic), only the time does.
 """
 from __future__ import annotations
 
@@ -79,6 +80,43 @@ def tune_batched(batch, nsteps: int = 10, candidates: Optional[Sequence[Tuple[in
         trials.append({"nbins": nbins, "threads": threads, "ms": ms})
     best = min(trials, key=lambda r: r["ms"])
     best = dict(best, steps=nsteps, trials=trials)
+    if use_cache:
+        cache[key] = best
+        _store(cache)
+    return best
+
+
+ADJOINT_CANDIDATES: Sequence[Tuple[int, int]] = ((256, 256), (256, 512), (512, 256), (512, 512), (1024, 256))
+
+
+def tune_adjoint(batch, every: int = 10, candidates: Optional[Sequence[Tuple[int, int]]] = None,
+                 use_cache: bool = True, fwd_shape: Tuple[int, int] = (256, 256)) -> dict:
+    """Best {'nbins', 'threads', 'ms'} for one adjoint segment of `every`
+    steps of this batch (cached)."""
+    key = f"{_arch()}/adjoint/r{batch.params.order}/n{batch.ninst}/c{batch.total}/s{every}"
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        return cache[key]
+    sim = ase.BatchedSimulation(batch, "cuda", nbins=fwd_shape[0], threads=fwd_shape[1])
+    U0, s0 = sim.U.clone(), sim.sig.clone()
+    hist = torch.zeros((every, batch.ninst), dtype=torch.float64, device="cuda")
+    sim.run(every, dt_hist=hist)
+    ws = ase.Workspace(ase.adjoint_batched_workspace_bytes(batch.total, every))
+    lam = torch.ones((3, batch.total), dtype=torch.float64, device="cuda")
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    trials = []
+    for nbins, threads in (candidates or ADJOINT_CANDIDATES):
+        plan = ase.device_plan(batch.ncells, nbins)
+        ase.adjoint_batched(sim, U0, s0, hist, every, lam, ws, threads, plan)
+        torch.cuda.synchronize()
+        start.record()
+        ase.adjoint_batched(sim, U0, s0, hist, every, lam, ws, threads, plan)
+        stop.record()
+        torch.cuda.synchronize()
+        trials.append({"nbins": nbins, "threads": threads, "ms": start.elapsed_time(stop)})
+    best = min(trials, key=lambda r: r["ms"])
+    best = dict(best, steps=every, trials=trials)
     if use_cache:
         cache[key] = best
         _store(cache)

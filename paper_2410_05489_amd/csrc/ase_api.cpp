@@ -639,7 +639,8 @@ int ase_adjoint_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const 
     if (rc) return rc;
     if (nsteps < 0) return fail(ASE_ERR_ARG, "nsteps must be >= 0");
     if (nbins < 1) return fail(ASE_ERR_ARG, "nbins must be >= 1");
-    if (threads != 128 && threads != 256) return fail(ASE_ERR_ARG, "threads must be 128 or 256");
+    if (threads != 128 && threads != 256 && threads != 512)
+        return fail(ASE_ERR_ARG, "threads must be 128, 256 or 512");
     ASE_PTR(dx, "dx");
     ASE_PTR(dt_hist, "dt_hist");
     ASE_PTR(lam, "lam");

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ase {
 
 // Evaluation-point sets, per nominal order r in {3,5,7,9} (index r/2-1):
@@ -498,149 +500,131 @@ __device__ __forceinline__ double swap_pair(double x)
 // signal-speed side and positivity replacements frozen.
 // ---------------------------------------------------------------------------
 
-// Forward-mode number with N partial derivatives.
-template <int N>
-struct Dual {
-    double v;
-    double d[N];
-};
+// Reverse mode of WENO-Z-AO(5,3)+DF for one variable (DF factors frozen):
+// with Y = g[0] P(xi=0) + g[1] P(xi=-1), returns gW[m+2] = dY/dW_m,
+// m = -2..2.  Every intermediate of weno_ao53 is recomputed, then the
+// adjoints flow back through the nonlinear weights, tau_Z, the smoothness
+// indicators and the sub-stencil coefficients.  |x| has derivative sign(x)
+// (0 at 0).
+__device__ __forceinline__ void weno_ao53_vjp(const double (&W)[5], const double al[4], const MethodConst &mc, int oi,
+                                              const double (&g)[2], double (&gW)[5])
+{
+    const double Wm2 = W[0], Wm1 = W[1], W0 = W[2], W1 = W[3], W2 = W[4];
+    const double am1 = 2.0 * W0 - 3.0 * Wm1 + Wm2, am2 = 0.5 * (Wm2 - 2.0 * Wm1 + W0);
+    const double a01 = W1 - W0, a02 = 0.5 * (Wm1 - 2.0 * W0 + W1);
+    const double ap1 = W1 - W0, ap2 = 0.5 * (W0 - 2.0 * W1 + W2);
+    const double b1 = (-15.0 * W0 + Wm1 + 15.0 * W1 - W2) * (1.0 / 12.0);
+    const double b2 = (-8.0 * W0 + 6.0 * Wm1 - Wm2 + 2.0 * W1 + W2) * 0.125;
+    const double b3 = (3.0 * W0 - Wm1 - 3.0 * W1 + W2) * (1.0 / 6.0);
+    const double b4 = (6.0 * W0 - 4.0 * Wm1 + Wm2 - 4.0 * W1 + W2) * (1.0 / 24.0);
+    const double sm = am1 * am1 - 2.0 * am1 * am2 + (16.0 / 3.0) * am2 * am2;
+    const double s0 = a01 * a01 - 2.0 * a01 * a02 + (16.0 / 3.0) * a02 * a02;
+    const double sp = ap1 * ap1 - 2.0 * ap1 * ap2 + (16.0 / 3.0) * ap2 * ap2;
+    const double sgd = sm > sp ? 1.0 : (sm < sp ? -1.0 : 0.0);
+    const double s5 = (sm + 4.0 * s0 + sp) * (1.0 / 6.0) + fabs(sm - sp);
+    const double sgm = s5 > sm ? 1.0 : (s5 < sm ? -1.0 : 0.0);
+    const double sg0 = s5 > s0 ? 1.0 : (s5 < s0 ? -1.0 : 0.0);
+    const double sgp = s5 > sp ? 1.0 : (s5 < sp ? -1.0 : 0.0);
+    const double tz = (fabs(s5 - sm) + fabs(s5 - s0) + fabs(s5 - sp)) * (1.0 / 3.0);
+    const double tz2 = tz * tz;
+    const double e5 = s5 + mc.eps, em = sm + mc.eps, e0 = s0 + mc.eps, ep = sp + mc.eps;
+    const double i5 = 1.0 / (e5 * e5), im = 1.0 / (em * em), i0 = 1.0 / (e0 * e0), ip = 1.0 / (ep * ep);
+    const double w5 = mc.d5 * (1.0 + tz2 * i5);
+    const double wm = mc.d3m * (1.0 + tz2 * im);
+    const double w0 = mc.d30 * (1.0 + tz2 * i0);
+    const double wp = mc.d3m * (1.0 + tz2 * ip);
+    const double iws = 1.0 / (w5 + wm + w0 + wp);
+    const double o5 = w5 * iws, om = wm * iws, o0 = w0 * iws, op = wp * iws;
 
-template <int N>
-__device__ __forceinline__ Dual<N> dconst(double c)
-{
-    Dual<N> r;
-    r.v = c;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = 0.0;
-    return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator+(const Dual<N> &a, const Dual<N> &b)
-{
-    Dual<N> r;
-    r.v = a.v + b.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
-    return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator-(const Dual<N> &a, const Dual<N> &b)
-{
-    Dual<N> r;
-    r.v = a.v - b.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
-    return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator*(const Dual<N> &a, const Dual<N> &b)
-{
-    Dual<N> r;
-    r.v = a.v * b.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
-    return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator*(double c, const Dual<N> &a)
-{
-    Dual<N> r;
-    r.v = c * a.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = c * a.d[k];
-    return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator/(const Dual<N> &a, const Dual<N> &b)
-{
-    Dual<N> r;
-    r.v = a.v / b.v;
-    const double ib = 1.0 / b.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
-    return r;
-}
-// |a| with derivative sign(a) (0 at a = 0).
-template <int N>
-__device__ __forceinline__ Dual<N> dabs(const Dual<N> &a)
-{
-    Dual<N> r;
-    r.v = fabs(a.v);
-    const double sg = a.v > 0.0 ? 1.0 : (a.v < 0.0 ? -1.0 : 0.0);
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = sg * a.d[k];
-    return r;
-}
-
-// Jacobian of the WENO-Z-AO(5,3)+DF face values with respect to W_{-2..2}
-// (DF factors frozen): J[q][m], q = 0 (xi = 0), 1 (xi = -1).
-__device__ __forceinline__ void weno_ao53_jac(const double (&W)[5], const double al[4], const MethodConst &mc, int oi,
-                                              double (&J)[2][5])
-{
-    using D = Dual<5>;
-    D w[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-        w[m] = dconst<5>(W[m]);
-        w[m].d[m] = 1.0;
-    }
-    const D &Wm2 = w[0], &Wm1 = w[1], &W0 = w[2], &W1 = w[3], &W2 = w[4];
-    const D am1 = 2.0 * W0 - 3.0 * Wm1 + Wm2, am2 = 0.5 * (Wm2 - 2.0 * Wm1 + W0);
-    const D a01 = W1 - W0, a02 = 0.5 * (Wm1 - 2.0 * W0 + W1);
-    const D ap1 = W1 - W0, ap2 = 0.5 * (W0 - 2.0 * W1 + W2);
-    const D b1 = (1.0 / 12.0) * (-15.0 * W0 + Wm1 + 15.0 * W1 - W2);
-    const D b2 = 0.125 * (-8.0 * W0 + 6.0 * Wm1 - Wm2 + 2.0 * W1 + W2);
-    const D b3 = (1.0 / 6.0) * (3.0 * W0 - Wm1 - 3.0 * W1 + W2);
-    const D b4 = (1.0 / 24.0) * (6.0 * W0 - 4.0 * Wm1 + Wm2 - 4.0 * W1 + W2);
-    const D sm = am1 * am1 - 2.0 * (am1 * am2) + (16.0 / 3.0) * (am2 * am2);
-    const D s0 = a01 * a01 - 2.0 * (a01 * a02) + (16.0 / 3.0) * (a02 * a02);
-    const D sp = ap1 * ap1 - 2.0 * (ap1 * ap2) + (16.0 / 3.0) * (ap2 * ap2);
-    const D s5 = (1.0 / 6.0) * (sm + 4.0 * s0 + sp) + dabs(sm - sp);
-    const D tz = (1.0 / 3.0) * (dabs(s5 - sm) + dabs(s5 - s0) + dabs(s5 - sp));
-    const D tz2 = tz * tz;
-    const D eps = dconst<5>(mc.eps), one = dconst<5>(1.0);
-    const D e5 = s5 + eps, em = sm + eps, e0 = s0 + eps, ep = sp + eps;
-    const D w5 = mc.d5 * (one + tz2 / (e5 * e5));
-    const D wm = mc.d3m * (one + tz2 / (em * em));
-    const D w0 = mc.d30 * (one + tz2 / (e0 * e0));
-    const D wp = mc.d3m * (one + tz2 / (ep * ep));
-    const D ws = w5 + wm + w0 + wp;
-    const D o5 = w5 / ws, om = wm / ws, o0 = w0 / ws, op = wp / ws;
+    // adjoints of the weights and of the candidate polynomials
+    double I5 = 0.0, Im = 0.0, I0 = 0.0, Ip = 0.0;
+    double gam1 = 0.0, gam2 = 0.0, ga01 = 0.0, ga02 = 0.0, gap1 = 0.0, gap2 = 0.0;
+    double gb1 = 0.0, gb2 = 0.0, gb3 = 0.0, gb4 = 0.0, gW0 = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const double *z = kTab.z[oi][q];
-        const D Pm = W0 + al[0] * (z[0] * am1 + z[1] * am2);
-        const D P0 = W0 + al[1] * (z[0] * a01 + z[1] * a02);
-        const D Pp = W0 + al[2] * (z[0] * ap1 + z[1] * ap2);
-        const D P5 = W0 + al[3] * (z[0] * b1 + z[1] * b2 + z[2] * b3 + z[3] * b4);
-        const D inner = mc.inv_d5 * P5 - mc.r3m * Pm - mc.r30 * P0 - mc.r3m * Pp;
-        const D P = o5 * inner + om * Pm + o0 * P0 + op * Pp;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) J[q][m] = P.d[m];
+        const double Pm = W0 + al[0] * (am1 * z[0] + am2 * z[1]);
+        const double P0 = W0 + al[1] * (a01 * z[0] + a02 * z[1]);
+        const double Pp = W0 + al[2] * (ap1 * z[0] + ap2 * z[1]);
+        const double P5 = W0 + al[3] * (b1 * z[0] + b2 * z[1] + b3 * z[2] + b4 * z[3]);
+        const double inner = P5 * mc.inv_d5 - mc.r3m * Pm - mc.r30 * P0 - mc.r3m * Pp;
+        I5 += g[q] * inner;
+        Im += g[q] * Pm;
+        I0 += g[q] * P0;
+        Ip += g[q] * Pp;
+        const double gPm = g[q] * (om - o5 * mc.r3m);
+        const double gP0 = g[q] * (o0 - o5 * mc.r30);
+        const double gPp = g[q] * (op - o5 * mc.r3m);
+        const double gP5 = g[q] * o5 * mc.inv_d5;
+        gW0 += gPm + gP0 + gPp + gP5;
+        gam1 += gPm * al[0] * z[0];
+        gam2 += gPm * al[0] * z[1];
+        ga01 += gP0 * al[1] * z[0];
+        ga02 += gP0 * al[1] * z[1];
+        gap1 += gPp * al[2] * z[0];
+        gap2 += gPp * al[2] * z[1];
+        gb1 += gP5 * al[3] * z[0];
+        gb2 += gP5 * al[3] * z[1];
+        gb3 += gP5 * al[3] * z[2];
+        gb4 += gP5 * al[3] * z[3];
     }
+    // o_k = w_k / sum w  ->  dY/dw_k = (I_k - sum_j o_j I_j) / sum w
+    const double Ibar = o5 * I5 + om * Im + o0 * I0 + op * Ip;
+    const double gw5 = (I5 - Ibar) * iws, gwm = (Im - Ibar) * iws, gw0 = (I0 - Ibar) * iws, gwp = (Ip - Ibar) * iws;
+    // w_k = d_k (1 + tz^2 / e_k^2)
+    const double gtz2 = gw5 * mc.d5 * i5 + gwm * mc.d3m * im + gw0 * mc.d30 * i0 + gwp * mc.d3m * ip;
+    double gs5 = -2.0 * gw5 * mc.d5 * tz2 * i5 / e5;
+    double gsm = -2.0 * gwm * mc.d3m * tz2 * im / em;
+    double gs0 = -2.0 * gw0 * mc.d30 * tz2 * i0 / e0;
+    double gsp = -2.0 * gwp * mc.d3m * tz2 * ip / ep;
+    // tau_Z
+    const double gtz = 2.0 * tz * gtz2 * (1.0 / 3.0);
+    gs5 += gtz * (sgm + sg0 + sgp);
+    gsm -= gtz * sgm;
+    gs0 -= gtz * sg0;
+    gsp -= gtz * sgp;
+    // beta_5 = (beta_m + 4 beta_0 + beta_p) / 6 + |beta_m - beta_p|
+    gsm += gs5 * ((1.0 / 6.0) + sgd);
+    gs0 += gs5 * (4.0 / 6.0);
+    gsp += gs5 * ((1.0 / 6.0) - sgd);
+    // beta_k = a1^2 - 2 a1 a2 + 16/3 a2^2
+    gam1 += gsm * (2.0 * am1 - 2.0 * am2);
+    gam2 += gsm * (-2.0 * am1 + (32.0 / 3.0) * am2);
+    ga01 += gs0 * (2.0 * a01 - 2.0 * a02);
+    ga02 += gs0 * (-2.0 * a01 + (32.0 / 3.0) * a02);
+    gap1 += gsp * (2.0 * ap1 - 2.0 * ap2);
+    gap2 += gsp * (-2.0 * ap1 + (32.0 / 3.0) * ap2);
+    // coefficients -> cell averages
+    gW[0] = gam1 + 0.5 * gam2 - gb2 * 0.125 + gb4 * (1.0 / 24.0);
+    gW[1] = -3.0 * gam1 - gam2 + 0.5 * ga02 + gb1 * (1.0 / 12.0) + gb2 * 0.75 - gb3 * (1.0 / 6.0) -
+            gb4 * (4.0 / 24.0);
+    gW[2] = gW0 + 2.0 * gam1 + 0.5 * gam2 - ga01 - ga02 - gap1 + 0.5 * gap2 - gb1 * (15.0 / 12.0) - gb2 +
+            gb3 * 0.5 + gb4 * 0.25;
+    gW[3] = ga01 + 0.5 * ga02 + gap1 - gap2 + gb1 * (15.0 / 12.0) + gb2 * 0.25 - gb3 * 0.5 - gb4 * (4.0 / 24.0);
+    gW[4] = 0.5 * gap2 - gb1 * (1.0 / 12.0) + gb2 * 0.125 + gb3 * (1.0 / 6.0) + gb4 * (1.0 / 24.0);
 }
 
-// Jacobian of one cell's two face values of one variable with respect to its
-// stencil W_{-R..R}: J[q][m + R], q = 0 (xi = 0), 1 (xi = -1).  Same level
-// rule as the forward reconstruction; ldv(m) reads the variable at offset m.
+// Transposed reconstruction of one cell for one variable: with gR, gL the
+// adjoints of the cell's right (xi = 0) and left (xi = -1) face values,
+// cc[m + R] = gR dP(0)/dW_m + gL dP(-1)/dW_m, m = -R..R.  Same level rule
+// as the forward reconstruction; ldv(m) reads the variable at offset m.
 template <int R, class LDV>
-__device__ __forceinline__ void recon_jacobian_var(LDV ldv, const double (&s)[2 * R], const MethodConst &mc,
-                                                   double (&J)[2][2 * R + 1])
+__device__ __forceinline__ void recon_vjp_var(LDV ldv, const double (&s)[2 * R], const MethodConst &mc, double gR,
+                                              double gL, double (&cc)[2 * R + 1])
 {
     constexpr int OI = R - 1;
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int m = 0; m < 2 * R + 1; ++m) J[q][m] = 0.0;
+    for (int m = 0; m < 2 * R + 1; ++m) cc[m] = 0.0;
     if constexpr (R == 1) {
         // P = W0 + al ((W1 - W0) Z1 + (W-1 - 2 W0 + W1) Z2 / 2)
         const double al = df_alpha(s[0] + s[1], mc.thr);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const double *z = kTab.z[OI][q];
-            J[q][0] = al * 0.5 * z[1];
-            J[q][1] = 1.0 + al * (-z[0] - z[1]);
-            J[q][2] = al * (z[0] + 0.5 * z[1]);
+            const double gq = q == 0 ? gR : gL;
+            cc[0] += gq * (al * 0.5 * z[1]);
+            cc[1] += gq * (1.0 + al * (-z[0] - z[1]));
+            cc[2] += gq * (al * (z[0] + 0.5 * z[1]));
         }
     } else {
         const int lvl = select_level<R>(s, mc.thr);
@@ -650,25 +634,30 @@ __device__ __forceinline__ void recon_jacobian_var(LDV ldv, const double (&s)[2 
             al[1] = df_alpha(ssum<R>(s, -1, 1), mc.thr);
             al[2] = df_alpha(ssum<R>(s, 0, 2), mc.thr);
             al[3] = df_alpha(ssum<R>(s, -2, 2), mc.thr);
-            double W[5], Jw[2][5];
+            double W[5], gW[5];
+            const double g2[2] = {gR, gL};
 #pragma unroll
             for (int m = -2; m <= 2; ++m) W[m + 2] = ldv(m);
-            weno_ao53_jac(W, al, mc, OI, Jw);
+            weno_ao53_vjp(W, al, mc, OI, g2, gW);
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int m = -2; m <= 2; ++m) J[q][m + R] = Jw[q][m + 2];
+            for (int m = -2; m <= 2; ++m) cc[m + R] = gW[m + 2];
         } else {
-            // linear levels: the tap weights themselves (compile-time constants)
+            // linear levels: the tap weights themselves, one branch per level
+            // so that they stay compile-time constants
+            auto taps = [&](auto LI) {
+                constexpr int li = decltype(LI)::value, h = li + 1;
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int m = -R; m <= R; ++m) {
-                    const double w9 = (R >= 4) ? kTab.lin[OI][3][q][4 + m] : 0.0;
-                    const double w7 = (R >= 3 && m >= -3 && m <= 3) ? kTab.lin[OI][2][q][4 + m] : 0.0;
-                    const double w5 = (m >= -2 && m <= 2) ? kTab.lin[OI][1][q][4 + m] : 0.0;
-                    J[q][m + R] = lvl == 9 ? w9 : (lvl == 7 ? w7 : w5);
-                }
+                for (int m = -R; m <= R; ++m)
+                    if (m >= -h && m <= h)
+                        cc[m + R] = gR * kTab.lin[OI][li][0][4 + m] + gL * kTab.lin[OI][li][1][4 + m];
+            };
+            if (lvl == 9) {
+                if constexpr (R >= 4) taps(std::integral_constant<int, 3>{});
+            } else if (lvl == 7) {
+                if constexpr (R >= 3) taps(std::integral_constant<int, 2>{});
+            } else {
+                taps(std::integral_constant<int, 1>{});
+            }
         }
     }
 }

@@ -997,10 +997,7 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
                 double s[2 * R];
 #pragma unroll
                 for (int m = -R; m < R; ++m) s[m + R] = L.sS[lx + m];
-                double J[2][2 * R + 1];
-                recon_jacobian_var<R>([&](int m) { return L.sV[v][lx + m]; }, s, mc, J);
-#pragma unroll
-                for (int m = 0; m < 2 * R + 1; ++m) cc[m] = gR * J[0][m] + gL * J[1][m];
+                recon_vjp_var<R>([&](int m) { return L.sV[v][lx + m]; }, s, mc, gR, gL, cc);
                 cc[R] += d;
             }
 #pragma unroll
@@ -1527,6 +1524,13 @@ void launch_adjoint(const AdjLaunch &al, hipStream_t st)
         case 2: ASE_ADJ(2, 128); break;
         case 3: ASE_ADJ(3, 128); break;
         default: ASE_ADJ(4, 128); break;
+        }
+    } else if (al.threads == 512) {
+        switch (al.R) {
+        case 1: ASE_ADJ(1, 512); break;
+        case 2: ASE_ADJ(2, 512); break;
+        case 3: ASE_ADJ(3, 512); break;
+        default: ASE_ADJ(4, 512); break;
         }
     } else {
         switch (al.R) {
