@@ -459,12 +459,15 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
             double Fs[NV], ssum = 0.0;
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fs[v] = 0.0;
+            // cell averages of this lane's side and of the other side (read
+            // only for the positivity replacement)
             const long long pl = (long long)(y + a.ng) * a.ld + x + a.ng;
             const long long pr = DIR == 0 ? pl + 1 : pl + a.ld;
+            const long long po = side == 0 ? pl : pr, pt = side == 0 ? pr : pl;
             const double *U = a.U;
             const long long P = a.plane;
-            auto cl = [=](int v) { return U[v * P + pl]; };
-            auto cr = [=](int v) { return U[v * P + pr]; };
+            auto co = [=](int v) { return U[v * P + po]; };
+            auto ct = [=](int v) { return U[v * P + pt]; };
             const double sgn = side == 0 ? 1.0 : -1.0;
 #pragma unroll
             for (int j = 0; j < GA; ++j) {
@@ -477,8 +480,9 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
                 const bool has = valid && (side == 0 || j < GB);
                 if (has) {
                     double Fk[NV];
-                    ssum += side == 0 ? gauss_point_sided<NV>(Wown, Woth, sgn, cl, cr, DIR, mc, Fk)
-                                      : gauss_point_sided<NV>(Wown, Woth, sgn, cr, cl, DIR, mc, Fk);
+                    // one call for both sides: a select on `side` around the
+                    // call would run the whole point evaluation twice per wave
+                    ssum += gauss_point_sided<NV>(Wown, Woth, sgn, co, ct, DIR, mc, Fk);
                     const double eta = kTab.eta[OI][side == 0 ? j : GA + j];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) Fs[v] = fma(eta, Fk[v], Fs[v]);
