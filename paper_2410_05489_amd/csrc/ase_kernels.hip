@@ -1403,10 +1403,13 @@ void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, cons
 
 namespace {
 constexpr int kT1D = 256;
-constexpr int kNT2D = 512;
+// 2D sweeps: x faces on 15 x 16 tiles with 512 lanes, y faces on 16 x 7
+// tiles with 256 lanes (the y sweep also streams the residual and the
+// step-start state; four smaller workgroups per CU hide that latency better)
+constexpr int kNTX = 512, kNTY = 256;
 // 2D tiles: (T0 + 1) x T1 x-faces and T0 x (T1 + 1) y-faces = 256 faces,
 // i.e. one face per lane pair of a 512-thread block.
-constexpr int kX_T0 = 15, kX_T1 = 16, kY_T0 = 16, kY_T1 = 15;
+constexpr int kX_T0 = 15, kX_T1 = 16, kY_T0 = 16, kY_T1 = 7;
 
 template <int R>
 void sweep_r(const Geo &geo, int dir, int mode, const SweepArgs &a, hipStream_t st)
@@ -1419,12 +1422,12 @@ void sweep_r(const Geo &geo, int dir, int mode, const SweepArgs &a, hipStream_t 
     }
     if (dir == 0) {
         dim3 grid((geo.nx + kX_T0 - 1) / kX_T0, (geo.ny + kX_T1 - 1) / kX_T1);
-        if (mode == MODE_RECON) k_sweep2d<0, R, kX_T0, kX_T1, kNT2D, MODE_RECON><<<grid, kNT2D, 0, st>>>(a);
-        else k_sweep2d<0, R, kX_T0, kX_T1, kNT2D, MODE_FUSED_X><<<grid, kNT2D, 0, st>>>(a);
+        if (mode == MODE_RECON) k_sweep2d<0, R, kX_T0, kX_T1, kNTX, MODE_RECON><<<grid, kNTX, 0, st>>>(a);
+        else k_sweep2d<0, R, kX_T0, kX_T1, kNTX, MODE_FUSED_X><<<grid, kNTX, 0, st>>>(a);
     } else {
         dim3 grid((geo.nx + kY_T0 - 1) / kY_T0, (geo.ny + kY_T1 - 1) / kY_T1);
-        if (mode == MODE_RECON) k_sweep2d<1, R, kY_T0, kY_T1, kNT2D, MODE_RECON><<<grid, kNT2D, 0, st>>>(a);
-        else k_sweep2d<1, R, kY_T0, kY_T1, kNT2D, MODE_FUSED_Y><<<grid, kNT2D, 0, st>>>(a);
+        if (mode == MODE_RECON) k_sweep2d<1, R, kY_T0, kY_T1, kNTY, MODE_RECON><<<grid, kNTY, 0, st>>>(a);
+        else k_sweep2d<1, R, kY_T0, kY_T1, kNTY, MODE_FUSED_Y><<<grid, kNTY, 0, st>>>(a);
     }
 }
 }  // namespace
