@@ -92,37 +92,30 @@ __device__ __forceinline__ void frame_cell(const BCInfo &b, long long idx, int &
     }
 }
 
+// Value of stored cell (I, J) under the boundary conditions: the interior
+// cell it copies, or the inflow state.  Sources are always interior cells,
+// so this never reads a ghost cell and may run while ghosts are written.
 template <int NV>
-__global__ void __launch_bounds__(kThreads) k_bc_cells(BCInfo b, double *U)
+__device__ __forceinline__ void cell_value(const BCInfo &b, const double *U, int I, int J, double (&W)[NV])
 {
-    const long long n = frame_size(b);
-    for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
-         idx += (long long)gridDim.x * kThreads) {
-        int I, J;
-        frame_cell(b, idx, I, J);
-        int Is, Js;
-        const long long dst = (long long)J * b.ld + I;
-        if (src_cell(b, I, J, Is, Js)) {
-            const long long src = (long long)Js * b.ld + Is;
+    int Is, Js;
+    if (src_cell(b, I, J, Is, Js)) {
+        const long long src = (long long)Js * b.ld + Is;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) U[v * b.plane + dst] = U[v * b.plane + src];
-        } else {
+        for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + src];
+    } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) U[v * b.plane + dst] = b.inflow[v];
-        }
+        for (int v = 0; v < NV; ++v) W[v] = b.inflow[v];
     }
 }
 
 template <int NV>
-__device__ __forceinline__ double sigma_first_order(const double *U, long long plane, long long a, long long c,
+__device__ __forceinline__ double sigma_first_order(const BCInfo &b, const double *U, int Ia, int Ja, int Ib, int Jb,
                                                     int dir, const MethodConst &mc)
 {
     double Wa[NV], Wb[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        Wa[v] = U[v * plane + a];
-        Wb[v] = U[v * plane + c];
-    }
+    cell_value<NV>(b, U, Ia, Ja, Wa);
+    cell_value<NV>(b, U, Ib, Jb, Wb);
     const Prim qa = primitives<NV>(Wa, dir, mc);
     const Prim qb = primitives<NV>(Wb, dir, mc);
     return sigma_point(qa, qb);
@@ -130,13 +123,15 @@ __device__ __forceinline__ double sigma_first_order(const double *U, long long p
 
 __device__ __forceinline__ int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
-// Strengths of the stored faces that are not flux faces.  init = true sets
-// every stored face to its first-order strength.
-// init = 1: every stored face (whole array); init = 0: only the faces of
-// the ghost frame that are not flux faces.
+// Ghost cells and the strengths of the stored faces that are not flux faces,
+// in one pass.  init = 0: the ghost frame; each non-flux face takes its
+// periodic image or the first-order strength of its two (boundary-mapped)
+// cells.  init = 1: ghost frame plus first-order strengths of every stored
+// face.  Strengths are computed from the boundary-mapped values directly, so
+// they do not wait for the ghost writes.
 template <int NV>
-__global__ void __launch_bounds__(kThreads) k_bc_sigma(BCInfo b, MethodConst mc, const double *U, double *sx,
-                                                       double *sy, int init)
+__global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, double *U, double *sx, double *sy,
+                                                      int init)
 {
     const long long n = init ? (long long)b.NY * b.NX : frame_size(b);
     const bool xper = b.bc[0] == ASE_BC_PERIODIC;
@@ -151,13 +146,21 @@ __global__ void __launch_bounds__(kThreads) k_bc_sigma(BCInfo b, MethodConst mc,
             frame_cell(b, idx, I, J);
         }
         const long long pos = (long long)J * b.ld + I;
+        const int i = I - b.ng, j = J - b.ng;
+        const bool ghost = i < 0 || i >= b.nx || (b.dim == 2 && (j < 0 || j >= b.ny));
+        if (ghost) {
+            double W[NV];
+            cell_value<NV>(b, U, I, J, W);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v * b.plane + pos] = W[v];
+        }
         // x-face between (I,J) and (I+1,J)
         if (I + 1 < b.NX) {
-            const int f = I - b.ng, j = J - b.ng;
+            const int f = i;
             const bool row_ok = b.dim == 1 || (j >= 0 && j < b.ny);
             const bool produced = row_ok && f >= -1 && f <= b.nx - 1;
             if (init) {
-                sx[pos] = sigma_first_order<NV>(U, b.plane, pos, pos + 1, 0, mc);
+                sx[pos] = sigma_first_order<NV>(b, U, I, J, I + 1, J, 0, mc);
             } else if (!produced) {
                 const int fw = xper ? wrapi(f, b.nx) : f;
                 const int jw = yper ? wrapi(j, b.ny) : j;
@@ -166,22 +169,22 @@ __global__ void __launch_bounds__(kThreads) k_bc_sigma(BCInfo b, MethodConst mc,
                     const int Jw = b.dim == 1 ? 0 : jw + b.ng;
                     sx[pos] = sx[(long long)Jw * b.ld + fw + b.ng];
                 } else {
-                    sx[pos] = sigma_first_order<NV>(U, b.plane, pos, pos + 1, 0, mc);
+                    sx[pos] = sigma_first_order<NV>(b, U, I, J, I + 1, J, 0, mc);
                 }
             }
         }
         if (b.dim == 2 && J + 1 < b.NY) {
-            const int f = J - b.ng, i = I - b.ng;
+            const int f = j;
             const bool produced = i >= 0 && i < b.nx && f >= -1 && f <= b.ny - 1;
             if (init) {
-                sy[pos] = sigma_first_order<NV>(U, b.plane, pos, pos + b.ld, 1, mc);
+                sy[pos] = sigma_first_order<NV>(b, U, I, J, I, J + 1, 1, mc);
             } else if (!produced) {
                 const int fw = yper ? wrapi(f, b.ny) : f;
                 const int iw = xper ? wrapi(i, b.nx) : i;
                 if (iw >= 0 && iw < b.nx && fw >= -1 && fw <= b.ny - 1) {
                     sy[pos] = sy[(long long)(fw + b.ng) * b.ld + iw + b.ng];
                 } else {
-                    sy[pos] = sigma_first_order<NV>(U, b.plane, pos, pos + b.ld, 1, mc);
+                    sy[pos] = sigma_first_order<NV>(b, U, I, J, I, J + 1, 1, mc);
                 }
             }
         }
@@ -1358,28 +1361,17 @@ void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, 
 {
     const BCInfo b = make_bc(g, geo);
     const int nb = grid_blocks(frame_size(b));
-    if (geo.nv == 4) {
-        k_bc_cells<4><<<nb, kThreads, 0, st>>>(b, U);
-        k_bc_sigma<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
-    } else {
-        k_bc_cells<3><<<nb, kThreads, 0, st>>>(b, U);
-        k_bc_sigma<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
-    }
+    if (geo.nv == 4) k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
+    else k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
 }
 
 void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
                        double *sy, hipStream_t st)
 {
     const BCInfo b = make_bc(g, geo);
-    const int nf = grid_blocks(frame_size(b));
     const int nb = grid_blocks((long long)geo.NY * geo.NX);
-    if (geo.nv == 4) {
-        k_bc_cells<4><<<nf, kThreads, 0, st>>>(b, U);
-        k_bc_sigma<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
-    } else {
-        k_bc_cells<3><<<nf, kThreads, 0, st>>>(b, U);
-        k_bc_sigma<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
-    }
+    if (geo.nv == 4) k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
+    else k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
 }
 
 void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,
