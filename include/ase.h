@@ -221,7 +221,7 @@ int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, int32_t ninst, con
                            void *stream);
 
 /* nsteps SSP-RK3 steps of every instance in ONE persistent launch: nbins
- * workgroups of `threads` (256 or 512) lanes, each walking the instances of
+ * workgroups of `threads` (256, 512 or 1024) lanes, each walking the instances of
  * its bin through all steps (ghost cells, DF state, per-instance dt, three
  * stages of the 1D method of ase_step) without returning to the host.
  * Results equal ase_step on each instance alone.  t: device [ninst], in/out.

@@ -16,8 +16,8 @@ import torch
 
 from . import ase
 
-DEFAULT_CANDIDATES: Sequence[Tuple[int, int]] = ((128, 512), (256, 256), (256, 512), (512, 256), (512, 512),
-                                                  (1024, 256))
+DEFAULT_CANDIDATES: Sequence[Tuple[int, int]] = ((128, 512), (256, 256), (256, 512), (512, 512), (128, 1024),
+                                                  (256, 1024))
 
 
 def cache_path() -> str:

@@ -493,7 +493,8 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int
     if (rc) return rc;
     if (nsteps < 0) return fail(ASE_ERR_ARG, "nsteps must be >= 0");
     if (nbins < 1) return fail(ASE_ERR_ARG, "nbins must be >= 1");
-    if (threads != 256 && threads != 512) return fail(ASE_ERR_ARG, "threads must be 256 or 512");
+    if (threads != 256 && threads != 512 && threads != 1024)
+        return fail(ASE_ERR_ARG, "threads must be 256, 512 or 1024");
     ASE_PTR(dx, "dx");
     ASE_PTR(t, "t");
     if (dt_hist && misaligned(dt_hist)) return fail(ASE_ERR_ALIGN, "misaligned: dt_hist");

@@ -604,36 +604,52 @@ __device__ __forceinline__ void weno_ao53_vjp(const double (&W)[5], const double
     gW[4] = 0.5 * gap2 - gb1 * (1.0 / 12.0) + gb2 * 0.125 + gb3 * (1.0 / 6.0) + gb4 * (1.0 / 24.0);
 }
 
+// Frozen decisions of one cell's reconstruction: its level and DF factors
+// (R = 1: al[0] of the 3-cell stencil; WENO-Z-AO: al[0..3] of S^3_{-1},
+// S^3_0, S^3_1 and S^5; linear levels: unused).
+template <int R>
+__device__ __forceinline__ int cell_decisions(const double (&s)[2 * R], const MethodConst &mc, double (&al)[4])
+{
+    al[0] = al[1] = al[2] = al[3] = 1.0;
+    if constexpr (R == 1) {
+        al[0] = df_alpha(s[0] + s[1], mc.thr);
+        return LVL_R3;
+    } else {
+        const int lvl = select_level<R>(s, mc.thr);
+        if (lvl == LVL_WENOAO) {
+            al[0] = df_alpha(ssum<R>(s, -2, 0), mc.thr);
+            al[1] = df_alpha(ssum<R>(s, -1, 1), mc.thr);
+            al[2] = df_alpha(ssum<R>(s, 0, 2), mc.thr);
+            al[3] = df_alpha(ssum<R>(s, -2, 2), mc.thr);
+        }
+        return lvl;
+    }
+}
+
 // Transposed reconstruction of one cell for one variable: with gR, gL the
 // adjoints of the cell's right (xi = 0) and left (xi = -1) face values,
-// cc[m + R] = gR dP(0)/dW_m + gL dP(-1)/dW_m, m = -R..R.  Same level rule
-// as the forward reconstruction; ldv(m) reads the variable at offset m.
+// cc[m + R] = gR dP(0)/dW_m + gL dP(-1)/dW_m, m = -R..R, for the level and
+// DF factors of cell_decisions; ldv(m) reads the variable at offset m.
 template <int R, class LDV>
-__device__ __forceinline__ void recon_vjp_var(LDV ldv, const double (&s)[2 * R], const MethodConst &mc, double gR,
-                                              double gL, double (&cc)[2 * R + 1])
+__device__ __forceinline__ void recon_vjp_var(LDV ldv, int lvl, const double (&al)[4], const MethodConst &mc,
+                                              double gR, double gL, double (&cc)[2 * R + 1])
 {
     constexpr int OI = R - 1;
 #pragma unroll
     for (int m = 0; m < 2 * R + 1; ++m) cc[m] = 0.0;
     if constexpr (R == 1) {
         // P = W0 + al ((W1 - W0) Z1 + (W-1 - 2 W0 + W1) Z2 / 2)
-        const double al = df_alpha(s[0] + s[1], mc.thr);
+        const double a = al[0];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const double *z = kTab.z[OI][q];
             const double gq = q == 0 ? gR : gL;
-            cc[0] += gq * (al * 0.5 * z[1]);
-            cc[1] += gq * (1.0 + al * (-z[0] - z[1]));
-            cc[2] += gq * (al * (z[0] + 0.5 * z[1]));
+            cc[0] += gq * (a * 0.5 * z[1]);
+            cc[1] += gq * (1.0 + a * (-z[0] - z[1]));
+            cc[2] += gq * (a * (z[0] + 0.5 * z[1]));
         }
     } else {
-        const int lvl = select_level<R>(s, mc.thr);
         if (lvl == LVL_WENOAO) {
-            double al[4];
-            al[0] = df_alpha(ssum<R>(s, -2, 0), mc.thr);
-            al[1] = df_alpha(ssum<R>(s, -1, 1), mc.thr);
-            al[2] = df_alpha(ssum<R>(s, 0, 2), mc.thr);
-            al[3] = df_alpha(ssum<R>(s, -2, 2), mc.thr);
             double W[5], gW[5];
             const double g2[2] = {gR, gL};
 #pragma unroll

@@ -547,7 +547,7 @@ struct Tile1D {
     double *sig_out;       // strengths written at the flux faces
     const double *Un;      // step-start state
     double *Uout;          // stage output
-    double *wl, *wr;       // MODE_RECON outputs
+    double *wl, *wr;       // MODE_RECON outputs (may be null)
     int8_t *level;
     long long plane;
     int nx, ng, NX, nfaces, stage;
@@ -610,10 +610,12 @@ __device__ __forceinline__ void stage1d_tile(const Tile1D &a, int i0, const Meth
             Wr[v] = L.sTL[v][fx + 1];
         }
         if constexpr (MODE == MODE_RECON) {
+            if (a.wl != nullptr) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                a.wl[(long long)v * a.nfaces + x + 1] = Wl[v];
-                a.wr[(long long)v * a.nfaces + x + 1] = Wr[v];
+                for (int v = 0; v < NV; ++v) {
+                    a.wl[(long long)v * a.nfaces + x + 1] = Wl[v];
+                    a.wr[(long long)v * a.nfaces + x + 1] = Wr[v];
+                }
             }
         } else {
             double F[NV];
@@ -726,7 +728,10 @@ __device__ __forceinline__ void batched_fill(const BatchArgs &a, double *U, doub
 template <int R, int NT>
 __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
 {
-    constexpr int T = NT;
+    // tile of NT - 2R - 2 cells: every per-cell and per-face loop of a tile
+    // then takes one pass of the workgroup (a longer tile runs a second pass
+    // on one wave while the others wait at the next barrier)
+    constexpr int T = NT - 2 * R - 2;
     __shared__ Lds1D<R, T> L;
     __shared__ double red[NT];
     __shared__ double s_dt;
@@ -855,6 +860,8 @@ struct LdsAdj {
     double sS[WX];
     double sG[3][NC];
     double sGL[3][NF], sGR[3][NF];
+    double sAl[4][NC];       // frozen DF factors of each trace cell
+    int8_t sLev[NC];         // and its stencil level
     union {
         struct {
             double tr[3][NC], tl[3][NC];
@@ -979,6 +986,19 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
         }
         L.rep[f] = rp;
     }
+    // frozen level and DF factors of every contributing cell, once for all
+    // three variables
+    for (int c = tid; c < NC; c += NT) {
+        const int x = xc + c;
+        if (c < 1 || c > NC - 2 || x < -1 || x > a.N) continue;
+        const int lx = c + (H - R - 1);
+        double s[2 * R], al[4];
+#pragma unroll
+        for (int m = -R; m < R; ++m) s[m + R] = L.sS[lx + m];
+        L.sLev[c] = (int8_t)cell_decisions<R>(s, mc, al);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) L.sAl[k][c] = al[k];
+    }
     __syncthreads();
 
     const bool first = i0 == 0, last = i0 + T >= a.N;
@@ -1001,10 +1021,10 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
                     else gL = L.sGR[v][c - 1];
                 }
                 const int lx = c + (H - R - 1);
-                double s[2 * R];
+                double al[4];
 #pragma unroll
-                for (int m = -R; m < R; ++m) s[m + R] = L.sS[lx + m];
-                recon_vjp_var<R>([&](int m) { return L.sV[v][lx + m]; }, s, mc, gR, gL, cc);
+                for (int k = 0; k < 4; ++k) al[k] = L.sAl[k][c];
+                recon_vjp_var<R>([&](int m) { return L.sV[v][lx + m]; }, (int)L.sLev[c], al, mc, gR, gL, cc);
                 cc[R] += d;
             }
 #pragma unroll
@@ -1036,19 +1056,41 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
 }
 
 // Add the ghost-cell gradients of `out` onto the interior cells the ghosts
-// copy (transmissive: the boundary cell; periodic: the wrapped cell).
+// copy (transmissive: the boundary cell; periodic: the wrapped cell).  One
+// thread per variable and side; the ghost values are summed in registers so
+// the target sees a single read-modify-write.
 __device__ __forceinline__ void adj_fold(double *out, long long P, int N, int ng, int bc)
 {
-    const int v = threadIdx.x;
-    if (v < 3) {
-        for (int k = 0; k < ng; ++k) {
-            const int j = k - ng;
-            const int tgt = bc == ASE_BC_PERIODIC ? j + N : 0;
-            if (tgt >= 0 && tgt < N) out[v * P + tgt + ng] += out[v * P + k];
-        }
-        for (int k = 0; k < ng; ++k) {
-            const int tgt = bc == ASE_BC_PERIODIC ? k : N - 1;
-            if (tgt >= 0 && tgt < N) out[v * P + tgt + ng] += out[v * P + N + ng + k];
+    const int v = threadIdx.x >> 1, side = threadIdx.x & 1;
+    if (threadIdx.x < 6) {
+        double *o = out + v * P;
+        if (bc == ASE_BC_PERIODIC && N >= 2 * ng) {
+            // distinct targets: left ghosts -> N-ng..N-1, right ghosts -> 0..ng-1
+            for (int k = 0; k < ng; ++k) {
+                if (side == 0) o[N + k] += o[k];
+                else o[ng + k] += o[N + ng + k];
+            }
+        } else if (bc == ASE_BC_PERIODIC) {
+            if (side == 0) {
+                for (int k = 0; k < ng; ++k) {
+                    const int tgt = k - ng + N;
+                    if (tgt >= 0 && tgt < N) o[tgt + ng] += o[k];
+                }
+                for (int k = 0; k < ng; ++k) {
+                    const int tgt = k;
+                    if (tgt >= 0 && tgt < N) o[tgt + ng] += o[N + ng + k];
+                }
+            }
+        } else if (N > 1) {
+            double acc = 0.0;
+            const int base = side == 0 ? 0 : N + ng;
+            for (int k = 0; k < ng; ++k) acc += o[base + k];
+            o[side == 0 ? ng : ng + N - 1] += acc;
+        } else if (side == 0) {
+            // one cell: both sides fold onto it
+            double acc = 0.0;
+            for (int k = 0; k < ng; ++k) acc += o[k] + o[N + ng + k];
+            o[ng] += acc;
         }
     }
     __syncthreads();
@@ -1071,17 +1113,17 @@ struct AdjArgs {
     MethodConst mc;
 };
 
-template <int R, int NT>
-__device__ __forceinline__ void adj_stage(AdjTile &t, const MethodConst &mc, LdsAdj<R, NT> &L, int bc)
+template <int R, int T, int NT>
+__device__ __forceinline__ void adj_stage(AdjTile &t, const MethodConst &mc, LdsAdj<R, T> &L, int bc)
 {
-    for (int i0 = 0; i0 < t.N; i0 += NT) adjoint1d_tile<R, NT, NT>(t, i0, mc, L);
+    for (int i0 = 0; i0 < t.N; i0 += T) adjoint1d_tile<R, T, NT>(t, i0, mc, L);
     adj_fold(t.out, t.plane, t.N, t.ng, bc);
 }
 
 template <int R, int NT>
 __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
 {
-    constexpr int T = NT;
+    constexpr int T = NT - 2 * R - 2;   // trace cells of a tile = NT (one pass per phase)
     __shared__ LdsAdjAll<R, T> L;
     const MethodConst &mc = a.mc;
     const int tid = threadIdx.x;
@@ -1156,14 +1198,14 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
             t.g = lam; t.gscale = (2.0 / 3.0) * dt;
             t.a0 = lam; t.c0 = 2.0 / 3.0;
             t.out = mu2;
-            adj_stage<R, NT>(t, mc, L.b, a.bc);
+            adj_stage<R, T, NT>(t, mc, L.b, a.bc);
             // stage 2
             t.V = a.tapeU + (3LL * q + 1) * SU + off;
             t.S = a.tapeS + (3LL * q + 1) * P + off;
             t.g = mu2; t.gscale = 0.25 * dt;
             t.a0 = mu2; t.c0 = 0.25;
             t.out = mu1;
-            adj_stage<R, NT>(t, mc, L.b, a.bc);
+            adj_stage<R, T, NT>(t, mc, L.b, a.bc);
             // stage 1
             t.V = a.tapeU + (3LL * q) * SU + off;
             t.S = a.tapeS + (3LL * q) * P + off;
@@ -1172,7 +1214,7 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
             t.a1 = mu2; t.c1 = 0.75;
             t.a2 = mu1; t.c2 = 1.0;
             t.out = lam;
-            adj_stage<R, NT>(t, mc, L.b, a.bc);
+            adj_stage<R, T, NT>(t, mc, L.b, a.bc);
         }
         // ghost slots of the result carry no meaning: clear them
         for (int kk = tid; kk < 2 * a.ng; kk += NT) {
@@ -1407,9 +1449,10 @@ template <int R>
 void sweep_r(const Geo &geo, int dir, int mode, const SweepArgs &a, hipStream_t st)
 {
     if (geo.dim == 1) {
-        dim3 grid((geo.nx + kT1D - 1) / kT1D);
-        if (mode == MODE_RECON) k_stage1d<R, kT1D, MODE_RECON><<<grid, kThreads, 0, st>>>(a);
-        else k_stage1d<R, kT1D, MODE_FUSED_1D><<<grid, kThreads, 0, st>>>(a);
+        constexpr int T1 = kT1D - 2 * R - 2;   // one pass of the workgroup per phase
+        dim3 grid((geo.nx + T1 - 1) / T1);
+        if (mode == MODE_RECON) k_stage1d<R, T1, MODE_RECON><<<grid, kThreads, 0, st>>>(a);
+        else k_stage1d<R, T1, MODE_FUSED_1D><<<grid, kThreads, 0, st>>>(a);
         return;
     }
     if (dir == 0) {
@@ -1488,7 +1531,14 @@ void launch_batched(const BatchLaunch &bl, hipStream_t st)
         return;
     }
 #define ASE_BATCH(RR, NTT) k_batched1d<RR, NTT><<<bl.nbins, NTT, 0, st>>>(a)
-    if (bl.threads == 512) {
+    if (bl.threads == 1024) {
+        switch (bl.R) {
+        case 1: ASE_BATCH(1, 1024); break;
+        case 2: ASE_BATCH(2, 1024); break;
+        case 3: ASE_BATCH(3, 1024); break;
+        default: ASE_BATCH(4, 1024); break;
+        }
+    } else if (bl.threads == 512) {
         switch (bl.R) {
         case 1: ASE_BATCH(1, 512); break;
         case 2: ASE_BATCH(2, 512); break;

@@ -105,7 +105,7 @@ def test_batched_launch_shapes_agree_bitwise():
     boundaries) give identical bits: no cross-workgroup or LDS races."""
     b = WL.batched_riemann(ninst=20, nmin=64, nmax=1500, order=9, seed=6, nsteps=10)
     outs = []
-    for nbins, threads in ((1, 256), (3, 512), (20, 256), (64, 512)):
+    for nbins, threads in ((1, 256), (3, 512), (20, 256), (64, 512), (5, 1024)):
         sim = ase.BatchedSimulation(b, DEV, nbins=nbins, threads=threads)
         sim.run(b.nsteps)
         torch.cuda.synchronize()
