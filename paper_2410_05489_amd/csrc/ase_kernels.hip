@@ -900,20 +900,10 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
     const int xc = i0 - R - 1;   // first trace cell
     const long long P = a.plane;
 
-    for (int lx = tid; lx < WX; lx += NT) {
-        const int I = xw + lx + a.ng;
-        const bool in = I >= 0 && I < NXs;
-#pragma unroll
-        for (int v = 0; v < 3; ++v) L.sV[v][lx] = in ? a.V[v * P + I] : 0.0;
-        L.sS[lx] = in ? a.S[I] : 0.0;
-    }
-    for (int c = tid; c < NC; c += NT) {
-        const int x = xc + c;
-        const bool in = x >= 0 && x < a.N;
-#pragma unroll
-        for (int v = 0; v < 3; ++v) L.sG[v][c] = in ? a.gscale * a.g[v * P + x + a.ng] : 0.0;
-    }
-    __syncthreads();
+    (void)xw;
+    (void)NXs;
+    (void)WX;
+    // the window (state, strengths, weights) is in LDS: adj_stage staged it
 
     // face traces of the cells -1..N that lie in the trace range
     for (int c = tid; c < NC; c += NT) {
@@ -1113,10 +1103,77 @@ struct AdjArgs {
     MethodConst mc;
 };
 
+// Window of one adjoint tile held in registers: state and strengths of cells
+// [i0-H, i0+T+H), weights of the trace cells.  Loaded for the next tile
+// while the current one computes.
+template <int R, int T, int NT>
+struct AdjWin {
+    static constexpr int NW = (LdsAdj<R, T>::WX + NT - 1) / NT;
+    static constexpr int NG = (LdsAdj<R, T>::NC + NT - 1) / NT;
+    double v[NW][4];
+    double g[NG][3];
+};
+
+template <int R, int T, int NT>
+__device__ __forceinline__ void adj_fetch(const AdjTile &a, int i0, AdjWin<R, T, NT> &w)
+{
+    using LA = LdsAdj<R, T>;
+    const int tid = threadIdx.x, NXs = a.N + 2 * a.ng;
+    const long long P = a.plane;
+#pragma unroll
+    for (int q = 0; q < AdjWin<R, T, NT>::NW; ++q) {
+        const int lx = tid + q * NT;
+        const int I = i0 - LA::H + lx + a.ng;
+        const bool in = lx < LA::WX && I >= 0 && I < NXs;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) w.v[q][v] = in ? a.V[v * P + I] : 0.0;
+        w.v[q][3] = in ? a.S[I] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < AdjWin<R, T, NT>::NG; ++q) {
+        const int c = tid + q * NT;
+        const int x = i0 - R - 1 + c;
+        const bool in = c < LA::NC && x >= 0 && x < a.N;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) w.g[q][v] = in ? a.gscale * a.g[v * P + x + a.ng] : 0.0;
+    }
+}
+
+template <int R, int T, int NT>
+__device__ __forceinline__ void adj_stage_window(const AdjWin<R, T, NT> &w, LdsAdj<R, T> &L)
+{
+    using LA = LdsAdj<R, T>;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < AdjWin<R, T, NT>::NW; ++q) {
+        const int lx = tid + q * NT;
+        if (lx < LA::WX) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) L.sV[v][lx] = w.v[q][v];
+            L.sS[lx] = w.v[q][3];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < AdjWin<R, T, NT>::NG; ++q) {
+        const int c = tid + q * NT;
+        if (c < LA::NC) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) L.sG[v][c] = w.g[q][v];
+        }
+    }
+}
+
 template <int R, int T, int NT>
 __device__ __forceinline__ void adj_stage(AdjTile &t, const MethodConst &mc, LdsAdj<R, T> &L, int bc)
 {
-    for (int i0 = 0; i0 < t.N; i0 += T) adjoint1d_tile<R, T, NT>(t, i0, mc, L);
+    AdjWin<R, T, NT> w;
+    adj_fetch<R, T, NT>(t, 0, w);
+    for (int i0 = 0; i0 < t.N; i0 += T) {
+        adj_stage_window<R, T, NT>(w, L);   // the previous tile ended with a barrier
+        __syncthreads();
+        if (i0 + T < t.N) adj_fetch<R, T, NT>(t, i0 + T, w);
+        adjoint1d_tile<R, T, NT>(t, i0, mc, L);
+    }
     adj_fold(t.out, t.plane, t.N, t.ng, bc);
 }
 
