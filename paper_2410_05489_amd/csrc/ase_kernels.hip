@@ -314,8 +314,11 @@ __device__ __forceinline__ void xcd_tile(int &tx, int &ty)
     ty = t / gx;
 }
 
+// Occupancy: with the compact tangential strength plane the x sweep (512
+// lanes) fits three workgroups per CU in LDS and the y sweep (256 lanes)
+// five; the second bound asks the compiler for registers that allow it.
 template <int DIR, int R, int T0, int T1, int NT, int MODE>
-__global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
+__global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
 {
     constexpr int NV = 4, G = R, OI = R - 1;
     using S = SweepShape<DIR, R, T0, T1>;
@@ -325,8 +328,11 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
     constexpr int NF = (MODE == MODE_RECON) ? 0 : NV * FY * FX;
     static_assert(NF <= NU, "flux tile must fit in the state tile");
     __shared__ double sUF[NU];        // staged state; reused for the face fluxes
-    __shared__ double sSX[UY][UX];
-    __shared__ double sSY[UY][UX];
+    // strengths: the normal plane over the whole staged tile, the tangential
+    // plane only where the side cells' columns (rows) read it
+    constexpr int SY = (DIR == 0) ? UY : TY, SX = (DIR == 0) ? TX : UX;
+    __shared__ double sSN[UY][UX];
+    __shared__ double sST[SY][SX];
     // right-face traces, then left-face traces; the second array starts 16
     // doubles (a half turn of the LDS banks) after a bank-aligned boundary so
     // that the two lanes of a face pair read different banks
@@ -371,8 +377,9 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
         const long long pos = (long long)J * a.ld + I;
 #pragma unroll
         for (int v = 0; v < NV; ++v) sU(v, ly, lx) = in ? a.U[v * a.plane + pos] : 0.0;
-        sSX[ly][lx] = in ? a.sx[pos] : 0.0;
-        sSY[ly][lx] = in ? a.sy[pos] : 0.0;
+        sSN[ly][lx] = in ? (DIR == 0 ? a.sx[pos] : a.sy[pos]) : 0.0;
+        const int sty = (DIR == 0) ? ly : ly - R, stx = (DIR == 0) ? lx - R : lx;
+        if (sty >= 0 && sty < SY && stx >= 0 && stx < SX) sST[sty][stx] = in ? (DIR == 0 ? a.sy[pos] : a.sx[pos]) : 0.0;
     }
     __syncthreads();
 
@@ -386,7 +393,7 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
         if (!need) continue;
         double s[2 * R];
 #pragma unroll
-        for (int m = -R; m < R; ++m) s[m + R] = (DIR == 0) ? sSX[ly][lx + m] : sSY[ly + m][lx];
+        for (int m = -R; m < R; ++m) s[m + R] = (DIR == 0) ? sSN[ly][lx + m] : sSN[ly + m][lx];
         auto ld = [&](int v, int m) { return (DIR == 0) ? sU(v, ly, lx + m) : sU(v, ly + m, lx); };
         double out[NV][2];
         const int lvl = reconstruct_cell<R, NV, 2>(ld, s, mc, OI, 0, out);
@@ -418,13 +425,13 @@ __global__ void __launch_bounds__(NT) k_sweep2d(SweepArgs a)
             if (DIR == 0) {
                 const int tx = fx + side;
 #pragma unroll
-                for (int m = -R; m < R; ++m) s[m + R] = sSY[fy + R + m][tx + R];
+                for (int m = -R; m < R; ++m) s[m + R] = sST[fy + R + m][tx];
                 auto ld = [&](int v, int m) { return tr[(v * TY + fy + R + m) * TX + tx]; };
                 reconstruct_cell<R, NV, G>(ld, s, mc, OI, 2, Ws);
             } else {
                 const int ty = fy + side;
 #pragma unroll
-                for (int m = -R; m < R; ++m) s[m + R] = sSX[ty + R][fx + R + m];
+                for (int m = -R; m < R; ++m) s[m + R] = sST[ty][fx + R + m];
                 auto ld = [&](int v, int m) { return tr[(v * TY + ty) * TX + fx + R + m]; };
                 reconstruct_cell<R, NV, G>(ld, s, mc, OI, 2, Ws);
             }
