@@ -214,27 +214,33 @@ int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_
 /* Device workspace of ase_step_batched for `total` stored cells. */
 size_t ase_batched_workspace_bytes(int64_t total);
 
+/* Boundary codes of a batch: `bc` (ASE_BC_PERIODIC or ASE_BC_TRANSMISSIVE)
+ * applies to every instance unless `bc_inst` (device [ninst], may be NULL)
+ * gives one code per instance; there any code other than ASE_BC_PERIODIC
+ * means transmissive.  A periodic instance needs ncells >= ng. */
+
 /* First-order DF strengths of every instance (the 1D ase_sigma_init per
  * instance); fills the ghost cells of U.  Device arrays. */
-int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
-                           const int32_t *ncells, int32_t ng, int64_t total, double *U, double *sigma,
-                           void *stream);
+int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                           const int64_t *offsets, const int32_t *ncells, int32_t ng, int64_t total, double *U,
+                           double *sigma, void *stream);
 
 /* nsteps SSP-RK3 steps of every instance in ONE persistent launch: nbins
  * workgroups of `threads` (256, 512 or 1024) lanes, each walking the instances of
- * its bin through all steps (ghost cells, DF state, per-instance dt, three
- * stages of the 1D method of ase_step) without returning to the host.
+ * its bin through all steps (ghost cells, DF state, per-instance dt and
+ * boundary code, three stages of the 1D method of ase_step) without
+ * returning to the host.
  * Results equal ase_step on each instance alone.  t: device [ninst], in/out.
  * dt_hist: optional device [nsteps][ninst].  dt_replay: optional device
  * [nsteps][ninst] of time steps to take instead of the CFL rule (an entry
  * <= 0 stops that instance; dt_cap and the clipping at t_end are then not
  * applied) -- for replaying a recorded run.  t_end > 0 stops each instance at t_end.
  * bin_start/bin_list: device copies of an ase_batched_plan. */
-int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
-                     const int32_t *ncells, const double *dx, int32_t ng, int64_t total, double *U, double *sigma,
-                     double *t, double *dt_hist, const double *dt_replay, int32_t nsteps, double t_end,
-                     const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
-                     size_t ws_bytes, void *stream);
+int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                     const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
+                     double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay, int32_t nsteps,
+                     double t_end, const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                     void *ws, size_t ws_bytes, void *stream);
 
 /* ---- Discrete adjoint of the 1D step ---------------------------------------
  * The paper defines the forward method only.  The adjoint here is the exact
@@ -276,8 +282,9 @@ size_t ase_adjoint_batched_workspace_bytes(int64_t total, int32_t nsteps);
  * workgroup re-runs the segment forward for its instances, keeping every
  * stage input in the workspace, then runs the steps back.  Device pointers;
  * asynchronous on `stream`. */
-int ase_adjoint_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
-                        const int32_t *ncells, const double *dx, int32_t ng, int64_t total, const double *U_ck,
+int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                        const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
+                        const double *U_ck,
                         const double *sigma_ck, const double *dt_hist, int32_t nsteps, double *lam,
                         const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
                         size_t ws_bytes, void *stream);

@@ -87,12 +87,7 @@ class BatchedAdjoint:
         self.dt_hist = None
 
     def init_sigma(self):
-        b = self.sim.b
-        import ctypes as C
-        ase._check(ase.lib().ase_batched_sigma_init(C.byref(ase.c_params(self.sim.p)), b.bc, b.ninst,
-                                                    ase._p(self.sim.offsets), ase._p(self.sim.ncells), b.ng, b.total,
-                                                    ase._p(self.sim.U), ase._p(self.sim.sig), ase._stream()),
-                   "ase_batched_sigma_init")
+        self.sim.sigma_init()
 
     def run(self, U0: torch.Tensor, nsteps: int) -> torch.Tensor:
         return _BatchedRun.apply(U0, self, int(nsteps))

@@ -74,15 +74,15 @@ def lib():
     L.ase_batched_plan.argtypes = [C.c_int32, vp, C.c_int32, vp, vp]
     L.ase_batched_workspace_bytes.restype = C.c_size_t
     L.ase_batched_workspace_bytes.argtypes = [C.c_int64]
-    L.ase_batched_sigma_init.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.c_int32, C.c_int64, vp, vp, vp]
-    L.ase_step_batched.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp,
+    L.ase_batched_sigma_init.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, C.c_int32, C.c_int64, vp, vp, vp]
+    L.ase_step_batched.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp,
                                    vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_adjoint_workspace_bytes.restype = C.c_size_t
     L.ase_adjoint_workspace_bytes.argtypes = [vp]
     L.ase_adjoint_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, vp, C.c_size_t, vp]
     L.ase_adjoint_batched_workspace_bytes.restype = C.c_size_t
     L.ase_adjoint_batched_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
-    L.ase_adjoint_batched.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp,
+    L.ase_adjoint_batched.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp,
                                       C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_pressure_objective.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp]
     L.ase_profile_enable.argtypes = [C.c_int]
@@ -282,8 +282,13 @@ class BatchedSimulation:
         if np.any(off < 0) or np.any(off[1:] < off[:-1] + n[:-1] + 2 * batch.ng) or \
                 off[-1] + n[-1] + 2 * batch.ng > batch.total:
             raise AseError("batch instances overlap or leave the array")
-        if batch.bc == 0 and np.any(n < batch.ng):
+        bci = getattr(batch, "bc_inst", None)
+        codes = np.full(len(n), batch.bc) if bci is None else np.asarray(bci)
+        if np.any((codes != 0) & (codes != 1)):
+            raise AseError("boundary codes must be periodic (0) or transmissive (1)")
+        if np.any((codes == 0) & (n < batch.ng)):
             raise AseError("periodic instances need ncells >= ng")
+        self.bc_inst = None if bci is None else torch.as_tensor(codes, dtype=torch.int32).to(device)
         self.offsets = torch.as_tensor(off, dtype=torch.int64).to(device)
         self.ncells = torch.as_tensor(n, dtype=torch.int32).to(device)
         self.dx = torch.as_tensor(batch.dx, dtype=torch.float64).to(device)
@@ -299,15 +304,21 @@ class BatchedSimulation:
         self.ws = Workspace(nbytes, device)
         P = C.byref(c_params(self.p))
         if sigma is None:
-            _check(lib().ase_batched_sigma_init(P, batch.bc, batch.ninst, _p(self.offsets), _p(self.ncells), batch.ng,
-                                                batch.total, _p(self.U), _p(self.sig), _stream()),
-                   "ase_batched_sigma_init")
+            self.sigma_init()
         else:
             self.sig.copy_(torch.as_tensor(sigma))
 
+    def sigma_init(self, stream=None):
+        """First-order strengths of every instance (fills ghost cells)."""
+        b = self.b
+        _check(lib().ase_batched_sigma_init(C.byref(c_params(self.p)), b.bc, _p(self.bc_inst), b.ninst,
+                                            _p(self.offsets), _p(self.ncells), b.ng, b.total, _p(self.U),
+                                            _p(self.sig), _stream(stream)), "ase_batched_sigma_init")
+
     def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None, dt_replay=None):
         b = self.b
-        _check(lib().ase_step_batched(C.byref(c_params(self.p)), b.bc, b.ninst, _p(self.offsets), _p(self.ncells),
+        _check(lib().ase_step_batched(C.byref(c_params(self.p)), b.bc, _p(self.bc_inst), b.ninst, _p(self.offsets),
+                                      _p(self.ncells),
                                       _p(self.dx), b.ng, b.total, _p(self.U), _p(self.sig), _p(self.t),
                                       _p(dt_hist), _p(dt_replay), int(nsteps), float(t_end), _p(self.bin_start),
                                       _p(self.bin_list), self.nbins, self.threads, self.ws.ptr, self.ws.nbytes,
@@ -355,7 +366,8 @@ def adjoint_batched(sim: "BatchedSimulation", U_ck, sig_ck, dt_hist, nsteps: int
     plan: (nbins, bin_start, bin_list) on the device (default: the sim's)."""
     b = sim.b
     nbins, bs, bl = plan if plan is not None else (sim.nbins, sim.bin_start, sim.bin_list)
-    _check(lib().ase_adjoint_batched(C.byref(c_params(sim.p)), b.bc, b.ninst, _p(sim.offsets), _p(sim.ncells),
+    _check(lib().ase_adjoint_batched(C.byref(c_params(sim.p)), b.bc, _p(sim.bc_inst), b.ninst, _p(sim.offsets),
+                                     _p(sim.ncells),
                                      _p(sim.dx), b.ng, b.total, _p(U_ck), _p(sig_ck), _p(dt_hist), int(nsteps),
                                      _p(lam), _p(bs), _p(bl), int(nbins), int(threads), ws.ptr,
                                      ws.nbytes, _stream(stream)), "ase_adjoint_batched")

@@ -462,8 +462,9 @@ static int batched_common(const ase_params_t *p, int32_t bc, int32_t ninst, cons
     return ASE_OK;
 }
 
-int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
-                           const int32_t *ncells, int32_t ng, int64_t total, double *U, double *sigma, void *stream)
+int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                           const int64_t *offsets, const int32_t *ncells, int32_t ng, int64_t total, double *U,
+                           double *sigma, void *stream)
 {
     int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
     if (rc) return rc;
@@ -477,17 +478,18 @@ int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, int32_t ninst, con
     bl.ninst = ninst;
     bl.ng = ng;
     bl.bc = bc;
+    bl.bc_inst = bc_inst;
     bl.init = 1;
     bl.mc = method_const(p);
     launch_batched(bl, (hipStream_t)stream);
     return check_launch("ase_batched_sigma_init");
 }
 
-int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
-                     const int32_t *ncells, const double *dx, int32_t ng, int64_t total, double *U, double *sigma,
-                     double *t, double *dt_hist, const double *dt_replay, int32_t nsteps, double t_end,
-                     const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
-                     size_t ws_bytes, void *stream)
+int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                     const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
+                     double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay, int32_t nsteps,
+                     double t_end, const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                     void *ws, size_t ws_bytes, void *stream)
 {
     int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
     if (rc) return rc;
@@ -521,6 +523,7 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int
     bl.sig2 = reinterpret_cast<double *>(c + 6 * arr);
     bl.bin_start = bin_start;
     bl.bin_list = bin_list;
+    bl.bc_inst = bc_inst;
     bl.total = total;
     bl.ninst = ninst;
     bl.nbins = nbins;
@@ -629,8 +632,9 @@ size_t ase_adjoint_batched_workspace_bytes(int64_t total, int32_t nsteps)
     return adjoint_bytes(total, nsteps);
 }
 
-int ase_adjoint_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const int64_t *offsets,
-                        const int32_t *ncells, const double *dx, int32_t ng, int64_t total, const double *U_ck,
+int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                        const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
+                        const double *U_ck,
                         const double *sigma_ck, const double *dt_hist, int32_t nsteps, double *lam,
                         const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
                         size_t ws_bytes, void *stream)
@@ -661,6 +665,7 @@ int ase_adjoint_batched(const ase_params_t *p, int32_t bc, int32_t ninst, const 
     al.lam = lam;
     al.bin_start = bin_start;
     al.bin_list = bin_list;
+    al.bc_inst = bc_inst;
     al.total = total;
     al.ninst = ninst;
     al.nbins = nbins;

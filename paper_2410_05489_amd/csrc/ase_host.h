@@ -85,6 +85,7 @@ struct BatchLaunch {
     double *U, *sig, *t, *dt_hist, *U1, *U2, *sig2;
     const double *dt_in;
     const int *bin_start, *bin_list;
+    const int *bc_inst;
     long long total;
     int ninst, nbins, threads, R, ng, nsteps, bc, fo, init;
     double t_end, cfl, dt_cap;
@@ -101,6 +102,7 @@ struct AdjLaunch {
     const double *ck_U, *ck_sig, *dt_hist;
     double *lam, *mu1, *mu2, *tapeU, *tapeS;
     const int *bin_start, *bin_list;   // nullptr: one workgroup per instance
+    const int *bc_inst;
     long long total;
     int ninst, nbins, threads, R, ng, nsteps, bc, fo;
     MethodConst mc;

@@ -691,22 +691,31 @@ struct BatchArgs {
     const double *dt_in;        // optional [nsteps][ninst]: replayed time steps instead of the CFL rule
     double *U1, *U2, *sig2;     // workspace, same layout as U / sig
     const int *bin_start, *bin_list;
+    const int *bc_inst;         // optional per-instance boundary code (else `bc` for all)
     long long total;
     int ninst, ng, nsteps, bc, fo;
     double t_end, cfl, dt_cap;
     MethodConst mc;
 };
 
+// Boundary code of instance k: periodic, anything else transmissive.
+__device__ __forceinline__ int inst_bc(const int *bc_inst, int bc, int k)
+{
+    const int b = bc_inst ? bc_inst[k] : bc;
+    return b == ASE_BC_PERIODIC ? ASE_BC_PERIODIC : ASE_BC_TRANSMISSIVE;
+}
+
 // Ghost cells of one instance and the strengths its stage reads.
 template <int NT>
-__device__ __forceinline__ void batched_fill(const BatchArgs &a, double *U, double *sg, int N, const MethodConst &mc)
+__device__ __forceinline__ void batched_fill(const BatchArgs &a, int bc, double *U, double *sg, int N,
+                                             const MethodConst &mc)
 {
     const int ng = a.ng, NX = N + 2 * ng;
     const long long P = a.total;
     for (int k = threadIdx.x; k < 2 * ng; k += NT) {
         const int I = k < ng ? k : N + k;
         int Is;
-        if (a.bc == ASE_BC_PERIODIC) Is = k < ng ? I + N : I - N;
+        if (bc == ASE_BC_PERIODIC) Is = k < ng ? I + N : I - N;
         else Is = k < ng ? ng : ng + N - 1;
 #pragma unroll
         for (int v = 0; v < 3; ++v) U[v * P + I] = U[v * P + Is];
@@ -716,7 +725,7 @@ __device__ __forceinline__ void batched_fill(const BatchArgs &a, double *U, doub
         const int f = I - ng;
         const bool produced = f >= -1 && f <= N - 1;
         if (a.fo || !produced) {
-            if (!a.fo && a.bc == ASE_BC_PERIODIC) {
+            if (!a.fo && bc == ASE_BC_PERIODIC) {
                 sg[I] = sg[((f % N) + N) % N + ng];
             } else {
                 double Wa[3], Wb[3];
@@ -748,6 +757,7 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
         const long long off = a.offsets[k];
         const int N = a.ncells[k];
         if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) continue;   // malformed entry: skipped
+        const int bc = inst_bc(a.bc_inst, a.bc, k);
         double *U = a.U + off, *U1 = a.U1 + off, *U2 = a.U2 + off;
         double *sA = a.sig + off, *sB = a.sig2 + off;
         const double inv_dx = 1.0 / a.dx[k];
@@ -755,7 +765,7 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
         int s = 0;
         for (; s < a.nsteps; ++s) {
             if (a.t_end > 0.0 && t >= a.t_end) break;
-            batched_fill<NT>(a, U, sA, N, mc);
+            batched_fill<NT>(a, bc, U, sA, N, mc);
             if (a.dt_in) {
                 const double dtr = a.dt_in[(long long)s * a.ninst + k];
                 if (!(dtr > 0.0)) break;
@@ -795,7 +805,7 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
             for (int st = 0; st < 3; ++st) {
                 double *sin = (st == 1) ? sB : sA;
                 double *sout = (st == 1) ? sA : sB;
-                if (st > 0) batched_fill<NT>(a, in_st[st], sin, N, mc);
+                if (st > 0) batched_fill<NT>(a, bc, in_st[st], sin, N, mc);
                 Tile1D tl;
                 tl.U = in_st[st]; tl.sx = sin; tl.sig_out = sout; tl.Un = U; tl.Uout = out_st[st];
                 tl.wl = tl.wr = nullptr; tl.level = nullptr;
@@ -836,7 +846,7 @@ __global__ void __launch_bounds__(NT) k_batched_sigma_init(BatchArgs a)
     if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) return;
     BatchArgs b = a;
     b.fo = 1;
-    batched_fill<NT>(b, a.U + off, a.sig + off, N, a.mc);
+    batched_fill<NT>(b, inst_bc(a.bc_inst, a.bc, k), a.U + off, a.sig + off, N, a.mc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1105,6 +1115,7 @@ struct AdjArgs {
     double *mu1, *mu2;
     double *tapeU, *tapeS;         // [3 nsteps][3][total], [3 nsteps][total]
     const int *bin_start, *bin_list;   // nullptr: instance = workgroup
+    const int *bc_inst;                // optional per-instance boundary code
     long long total;
     int ninst, ng, nsteps, bc, fo;
     MethodConst mc;
@@ -1208,6 +1219,7 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
             dx = a.dx1;
         }
         if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) continue;   // malformed entry: skipped
+        const int bc = inst_bc(a.bc_inst, a.bc, k);
         const int NX = N + 2 * a.ng;
         const long long P = a.total, SU = 3 * P;
         const double inv_dx = 1.0 / dx;
@@ -1224,7 +1236,7 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
         BatchArgs fb;
         fb.ng = a.ng;
         fb.total = a.total;
-        fb.bc = a.bc;
+        fb.bc = bc;
         fb.fo = a.fo;
         for (int q = 0; q < nact; ++q) {
             const double dt = a.dt_hist[(long long)q * a.ninst + k];
@@ -1232,7 +1244,7 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
             for (int st = 0; st < 3; ++st) {
                 double *in = a.tapeU + (3LL * q + st) * SU + off;
                 double *sin = a.tapeS + (3LL * q + st) * P + off;
-                batched_fill<NT>(fb, in, sin, N, mc);
+                batched_fill<NT>(fb, bc, in, sin, N, mc);
                 if (st == 2 && q == nact - 1) break;
                 Tile1D tl;
                 tl.U = in; tl.sx = sin; tl.Un = Un;
@@ -1262,14 +1274,14 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
             t.g = lam; t.gscale = (2.0 / 3.0) * dt;
             t.a0 = lam; t.c0 = 2.0 / 3.0;
             t.out = mu2;
-            adj_stage<R, T, NT>(t, mc, L.b, a.bc);
+            adj_stage<R, T, NT>(t, mc, L.b, bc);
             // stage 2
             t.V = a.tapeU + (3LL * q + 1) * SU + off;
             t.S = a.tapeS + (3LL * q + 1) * P + off;
             t.g = mu2; t.gscale = 0.25 * dt;
             t.a0 = mu2; t.c0 = 0.25;
             t.out = mu1;
-            adj_stage<R, T, NT>(t, mc, L.b, a.bc);
+            adj_stage<R, T, NT>(t, mc, L.b, bc);
             // stage 1
             t.V = a.tapeU + (3LL * q) * SU + off;
             t.S = a.tapeS + (3LL * q) * P + off;
@@ -1278,7 +1290,7 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
             t.a1 = mu2; t.c1 = 0.75;
             t.a2 = mu1; t.c2 = 1.0;
             t.out = lam;
-            adj_stage<R, T, NT>(t, mc, L.b, a.bc);
+            adj_stage<R, T, NT>(t, mc, L.b, bc);
         }
         // ghost slots of the result carry no meaning: clear them
         for (int kk = tid; kk < 2 * a.ng; kk += NT) {
@@ -1587,7 +1599,7 @@ void launch_batched(const BatchLaunch &bl, hipStream_t st)
     a.offsets = bl.offsets; a.ncells = bl.ncells; a.dx = bl.dx;
     a.U = bl.U; a.sig = bl.sig; a.t = bl.t; a.dt_hist = bl.dt_hist; a.dt_in = bl.dt_in;
     a.U1 = bl.U1; a.U2 = bl.U2; a.sig2 = bl.sig2;
-    a.bin_start = bl.bin_start; a.bin_list = bl.bin_list;
+    a.bin_start = bl.bin_start; a.bin_list = bl.bin_list; a.bc_inst = bl.bc_inst;
     a.total = bl.total; a.ninst = bl.ninst; a.ng = bl.ng; a.nsteps = bl.nsteps; a.bc = bl.bc; a.fo = bl.fo;
     a.t_end = bl.t_end; a.cfl = bl.cfl; a.dt_cap = bl.dt_cap; a.mc = bl.mc;
     if (bl.init) {
@@ -1626,7 +1638,7 @@ void launch_adjoint(const AdjLaunch &al, hipStream_t st)
     a.offsets = al.offsets; a.ncells = al.ncells; a.dx = al.dx; a.n1 = al.n1; a.dx1 = al.dx1;
     a.ck_U = al.ck_U; a.ck_sig = al.ck_sig; a.dt_hist = al.dt_hist; a.lam = al.lam;
     a.mu1 = al.mu1; a.mu2 = al.mu2; a.tapeU = al.tapeU; a.tapeS = al.tapeS;
-    a.bin_start = al.bin_start; a.bin_list = al.bin_list;
+    a.bin_start = al.bin_start; a.bin_list = al.bin_list; a.bc_inst = al.bc_inst;
     a.total = al.total; a.ninst = al.ninst; a.ng = al.ng; a.nsteps = al.nsteps; a.bc = al.bc; a.fo = al.fo;
     a.mc = al.mc;
     const int nblk = al.bin_start ? al.nbins : al.ninst;

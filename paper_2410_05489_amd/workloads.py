@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -288,6 +288,7 @@ class Batch:
     params: Params
     bc: int
     nsteps: int
+    bc_inst: Optional[np.ndarray] = None   # int32 [ninst]: per-instance boundary code (else `bc`)
 
     @property
     def ninst(self) -> int:
@@ -369,5 +370,24 @@ def batched_smooth(ninst: int = 16, nmin: int = 64, nmax: int = 512, order: int 
 def instance_grid(batch: Batch, k: int) -> Grid:
     """The single-instance 1D grid of instance k of a batch."""
     N = int(batch.ncells[k])
-    return Grid(dim=1, nx=N, ny=1, ng=batch.ng, dx=float(batch.dx[k]), dy=float(batch.dx[k]),
-                bc=(batch.bc,) * 4)
+    bc = int(batch.bc_inst[k]) if batch.bc_inst is not None else batch.bc
+    return Grid(dim=1, nx=N, ny=1, ng=batch.ng, dx=float(batch.dx[k]), dy=float(batch.dx[k]), bc=(bc,) * 4)
+
+
+def batched_mixed(ninst: int = 12, nmin: int = 16, nmax: int = 400, order: int = 9, seed: int = 5,
+                  nsteps: int = 20) -> Batch:
+    """Instances with their own boundary conditions: even instances carry the
+    smooth periodic data of batched_smooth, odd ones the transmissive Riemann
+    data of batched_riemann (positivity fallback on)."""
+    sm = batched_smooth(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed, nsteps=nsteps)
+    rm = batched_riemann(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed + 1, nsteps=nsteps)
+    pick = [sm if k % 2 == 0 else rm for k in range(ninst)]
+    ncells, offsets, total = _pack([int(b.ncells[k]) for k, b in enumerate(pick)], sm.ng)
+    U = np.zeros((3, total), dtype=np.float64)
+    for k, b in enumerate(pick):
+        o = int(offsets[k])
+        U[:, o:o + int(ncells[k]) + 2 * sm.ng] = b.instance(k)
+    dx = np.array([float(b.dx[k]) for k, b in enumerate(pick)])
+    bc_inst = np.array([BC_PERIODIC if k % 2 == 0 else BC_TRANSMISSIVE for k in range(ninst)], dtype=np.int32)
+    return Batch(ncells, offsets, dx, sm.ng, U, Params(order=order, gamma=1.4, cfl=0.5, positivity_fallback=1),
+                 BC_TRANSMISSIVE, nsteps, bc_inst)

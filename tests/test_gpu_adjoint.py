@@ -240,3 +240,19 @@ def test_batched_adjoint_full_size():
             continue
         assert abs(Jg[k] - Jo) <= 1e-11 * abs(Jo), k
         assert _rel(g.interior(_inst(b, G, k))[:, 0], go) < 1e-10, k
+
+
+def test_batched_adjoint_mixed_boundaries():
+    """Per-instance boundary codes (periodic and transmissive in one launch):
+    each instance's gradient has the bits of the single-grid path."""
+    b = WL.batched_mixed(ninst=6, nmin=20, nmax=300, order=9, seed=7, nsteps=6)
+    run = A.BatchedAdjoint(b, DEV, nbins=2, every=4)
+    U0 = torch.tensor(b.U, device=DEV, requires_grad=True)
+    run.pressure(run.run(U0, 6)).sum().backward()
+    G = U0.grad.cpu().numpy()
+    for k in range(b.ninst):
+        g = WL.instance_grid(b, k)
+        r1 = A.Adjoint1D(g, b.params, DEV, every=3)
+        u = torch.tensor(_inst(b, b.U, k), device=DEV, requires_grad=True)
+        r1.pressure(r1.run(u, 6)).sum().backward()
+        assert np.array_equal(u.grad.cpu().numpy(), _inst(b, G, k), equal_nan=True), k
