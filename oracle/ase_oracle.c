@@ -37,7 +37,7 @@
 /* Problem statement                                                          */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_INFLOW_SLOT = 2 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_INFLOW_SLOT = 2, ORC_BC_REFLECTIVE = 3 };
 
 typedef struct {
     int32_t dim;        /* 1 or 2 */
@@ -448,13 +448,18 @@ static void bc_fill_cells(const orc_grid *g, double *U)
             int Il = ng - 1 - k, Ir = ng + g->nx + k;
             for (int v = 0; v < nv; ++v) {
                 double *rv = row + v * P;
+                /* a reflective (slip) wall mirrors the cells and reverses the
+                   momentum normal to it (x momentum is variable 1) */
+                double flip = (v == 1) ? -1.0 : 1.0;
                 /* low side */
                 if (g->bc[0] == ORC_BC_PERIODIC) rv[Il] = rv[Il + g->nx];
                 else if (g->bc[0] == ORC_BC_INFLOW_SLOT && in_slot(g, J)) rv[Il] = g->inflow[v];
+                else if (g->bc[0] == ORC_BC_REFLECTIVE) rv[Il] = flip * rv[ng + k];
                 else rv[Il] = rv[ng];
                 /* high side */
                 if (g->bc[1] == ORC_BC_PERIODIC) rv[Ir] = rv[Ir - g->nx];
                 else if (g->bc[1] == ORC_BC_INFLOW_SLOT && in_slot(g, J)) rv[Ir] = g->inflow[v];
+                else if (g->bc[1] == ORC_BC_REFLECTIVE) rv[Ir] = flip * rv[ng + g->nx - 1 - k];
                 else rv[Ir] = rv[ng + g->nx - 1];
             }
         }
@@ -464,10 +469,15 @@ static void bc_fill_cells(const orc_grid *g, double *U)
         int Jl = ng - 1 - k, Jh = ng + g->ny + k;
         for (int v = 0; v < nv; ++v) {
             double *Uv = U + v * P;
+            double flip = (v == 2) ? -1.0 : 1.0;   /* y momentum */
             for (int I = 0; I < NX; ++I) {
                 if (g->bc[2] == ORC_BC_PERIODIC) Uv[(size_t)Jl * g->ld + I] = Uv[(size_t)(Jl + g->ny) * g->ld + I];
+                else if (g->bc[2] == ORC_BC_REFLECTIVE)
+                    Uv[(size_t)Jl * g->ld + I] = flip * Uv[(size_t)(ng + k) * g->ld + I];
                 else Uv[(size_t)Jl * g->ld + I] = Uv[(size_t)ng * g->ld + I];
                 if (g->bc[3] == ORC_BC_PERIODIC) Uv[(size_t)Jh * g->ld + I] = Uv[(size_t)(Jh - g->ny) * g->ld + I];
+                else if (g->bc[3] == ORC_BC_REFLECTIVE)
+                    Uv[(size_t)Jh * g->ld + I] = flip * Uv[(size_t)(ng + g->ny - 1 - k) * g->ld + I];
                 else Uv[(size_t)Jh * g->ld + I] = Uv[(size_t)(ng + g->ny - 1) * g->ld + I];
             }
         }
@@ -821,6 +831,11 @@ static int check_args(const orc_grid *g, const orc_params *p)
     if (g->bc[1] == ORC_BC_PERIODIC && g->bc[0] != ORC_BC_PERIODIC) return -1;
     if (g->dim == 2 && (g->bc[2] == ORC_BC_PERIODIC) != (g->bc[3] == ORC_BC_PERIODIC)) return -1;
     if (g->dim == 2 && (g->bc[2] == ORC_BC_INFLOW_SLOT || g->bc[3] == ORC_BC_INFLOW_SLOT)) return -1;
+    for (int k = 0; k < (g->dim == 2 ? 4 : 2); ++k)
+        if (g->bc[k] < ORC_BC_PERIODIC || g->bc[k] > ORC_BC_REFLECTIVE) return -1;
+    /* a mirror or a wrap reads ng interior cells */
+    if ((g->bc[0] == ORC_BC_REFLECTIVE || g->bc[1] == ORC_BC_REFLECTIVE) && g->nx < g->ng) return -1;
+    if (g->dim == 2 && (g->bc[2] == ORC_BC_REFLECTIVE || g->bc[3] == ORC_BC_REFLECTIVE) && g->ny < g->ng) return -1;
     return 0;
 }
 
