@@ -84,7 +84,7 @@ def _alpha(A, thr):
 class Step1D:
     """One SSP-RK3 step of a 1D grid with frozen decisions.
 
-    ncell, ng, dx, order, bc ('periodic' | 'transmissive'), gamma,
+    ncell, ng, dx, order, bc ('periodic' | 'transmissive' | 'reflective'), gamma,
     sigma_thres, eps, d_hi, d_lo, positivity (bool), df_first_order (bool).
     """
 
@@ -105,6 +105,11 @@ class Step1D:
         N, ng = self.N, self.ng
         if self.bc == "periodic":
             left, right = U[:, N - ng:], U[:, :ng]
+        elif self.bc == "reflective":
+            # slip wall: mirrored cells, momentum reversed
+            sign = torch.tensor([1.0, -1.0, 1.0], dtype=TD)[:, None]
+            left = sign * torch.flip(U[:, :ng], dims=[1])
+            right = sign * torch.flip(U[:, N - ng:], dims=[1])
         else:
             left, right = U[:, :1].expand(3, ng), U[:, N - 1:].expand(3, ng)
         return torch.cat([left, U, right], dim=1)
@@ -128,7 +133,9 @@ class Step1D:
 
     def sigma_fill(self, Ug, sig):
         """Strengths of every stored face: flux faces from `sig`, the others
-        by periodic wrap or from the first-order states (no gradient)."""
+        by periodic wrap or wall mirror (face f -> -f-2 at the left wall,
+        2N-f-2 at the right one) or from the first-order states (no
+        gradient)."""
         N, ng = self.N, self.ng
         NX = N + 2 * ng
         with torch.no_grad():
@@ -142,6 +149,8 @@ class Step1D:
                     continue
                 elif self.bc == "periodic":
                     out[I] = sig[(f % N) + ng]
+                elif self.bc == "reflective":
+                    out[I] = sig[(-f - 2 if f < -1 else 2 * N - f - 2) + ng]
                 else:
                     out[I] = fo[I]
             return out

@@ -527,22 +527,50 @@ static int wrap(int i, int n) { return ((i % n) + n) % n; }
 
 /* Strength on faces the previous stage did not produce.  Flux faces are     */
 /* x-faces i+1/2, i in [-1, nx-1], on interior rows (y-faces likewise).  A     */
-/* face that periodic wrapping maps onto a flux face takes that face's value; */
-/* any other face takes the first-order strength of its two ghost-filled      */
-/* cells.                                                                     */
+/* face that periodic wrapping or reflective mirroring maps onto a flux face  */
+/* takes that face's value (a wall is a symmetry plane of the lagged DF       */
+/* state too); any other face takes the first-order strength of its two       */
+/* ghost-filled cells.                                                        */
+
+/* Cell index mapped by the boundary rule of one axis (periodic wrap or wall   */
+/* mirror); other codes leave it.                                             */
+static int map_cell(int i, int n, int bc_lo, int bc_hi)
+{
+    if (i < 0) {
+        if (bc_lo == ORC_BC_PERIODIC) return wrap(i, n);
+        if (bc_lo == ORC_BC_REFLECTIVE) return -1 - i;
+    } else if (i >= n) {
+        if (bc_hi == ORC_BC_PERIODIC) return wrap(i, n);
+        if (bc_hi == ORC_BC_REFLECTIVE) return 2 * n - 1 - i;
+    }
+    return i;
+}
+
+/* Face index f (face f + 1/2) mapped likewise: a wall at -1/2 maps f to      */
+/* -f-2, a wall at n-1/2 maps f to 2n-f-2.                                    */
+static int map_face(int f, int n, int bc_lo, int bc_hi)
+{
+    if (f < -1) {
+        if (bc_lo == ORC_BC_PERIODIC) return wrap(f, n);
+        if (bc_lo == ORC_BC_REFLECTIVE) return -f - 2;
+    } else if (f > n - 1) {
+        if (bc_hi == ORC_BC_PERIODIC) return wrap(f, n);
+        if (bc_hi == ORC_BC_REFLECTIVE) return 2 * n - f - 2;
+    }
+    return f;
+}
+
 static void bc_fill_sigma(const orc_grid *g, const orc_params *p, const double *U, double *sx, double *sy)
 {
     int ng = g->ng, NX = NXof(g), NY = NYof(g);
-    int xper = g->bc[0] == ORC_BC_PERIODIC;
-    int yper = g->dim == 2 && g->bc[2] == ORC_BC_PERIODIC;
     for (int J = 0; J < NY; ++J) {
         int j = J - ng;
         int jrow_ok = (g->dim == 1) || (j >= 0 && j < g->ny);
         for (int I = 0; I + 1 < NX; ++I) {
             int f = I - ng;                     /* face f + 1/2 */
             if (jrow_ok && f >= -1 && f <= g->nx - 1) continue;   /* produced */
-            int fw = xper ? wrap(f, g->nx) : f;
-            int jw = (g->dim == 2 && yper) ? wrap(j, g->ny) : j;
+            int fw = map_face(f, g->nx, g->bc[0], g->bc[1]);
+            int jw = (g->dim == 2) ? map_cell(j, g->ny, g->bc[2], g->bc[3]) : j;
             int jw_ok = (g->dim == 1) || (jw >= 0 && jw < g->ny);
             if (jw_ok && fw >= -1 && fw <= g->nx - 1) {
                 int Jw = (g->dim == 1) ? 0 : jw + ng;
@@ -553,14 +581,13 @@ static void bc_fill_sigma(const orc_grid *g, const orc_params *p, const double *
         }
     }
     if (g->dim == 1) return;
-    int xper2 = xper;
     for (int J = 0; J + 1 < NY; ++J) {
         int f = J - ng;
         for (int I = 0; I < NX; ++I) {
             int i = I - ng;
             if (i >= 0 && i < g->nx && f >= -1 && f <= g->ny - 1) continue;
-            int fw = yper ? wrap(f, g->ny) : f;
-            int iw = xper2 ? wrap(i, g->nx) : i;
+            int fw = map_face(f, g->ny, g->bc[2], g->bc[3]);
+            int iw = map_cell(i, g->nx, g->bc[0], g->bc[1]);
             if (iw >= 0 && iw < g->nx && fw >= -1 && fw <= g->ny - 1) {
                 sy[(size_t)J * g->ld + I] = sy[(size_t)(fw + ng) * g->ld + iw + ng];
             } else {

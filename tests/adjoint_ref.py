@@ -10,7 +10,7 @@ from paper_2410_05489_amd import workloads as WL
 
 
 def stepper(g, p):
-    bc = "periodic" if g.bc[0] == WL.BC_PERIODIC else "transmissive"
+    bc = {WL.BC_PERIODIC: "periodic", WL.BC_REFLECTIVE: "reflective"}.get(g.bc[0], "transmissive")
     return Step1D(g.nx, g.ng, g.dx, p.order, bc, p.gamma, p.sigma_thres, p.eps, p.d_hi, p.d_lo,
                   bool(p.positivity_fallback), p.df_source == WL.DF_FIRST_ORDER)
 

@@ -15,7 +15,7 @@ from paper_2410_05489_amd import workloads as WL
 
 CASES = [
     ("wave", 9), ("wave", 7), ("wave", 5), ("wave", 3),
-    ("sod", 9), ("sod", 7), ("sod", 5), ("sod", 3), ("rarefaction", 9),
+    ("sod", 9), ("sod", 7), ("sod", 5), ("sod", 3), ("rarefaction", 9), ("wall", 9), ("wall", 5),
 ]
 
 
@@ -24,6 +24,16 @@ def _workload(kind, order, df_fo=False):
         w = WL.density_wave_1d(40, order, seed=1)
     elif kind == "sod":
         w = WL.sod(60, order)
+    elif kind == "wall":
+        # smooth data between two reflective walls
+        w = WL.shu_osher(40, order)
+        g = w.grid
+        g.bc = (WL.BC_REFLECTIVE,) * 4
+        x = (np.arange(g.nx) + 0.5) / g.nx
+        rho = 1.0 + 0.2 * np.cos(np.pi * x)
+        g.interior(w.U)[:, 0] = WL.conservative(rho, 0.3 * np.sin(np.pi * x), 0.0,
+                                                1.0 + 0.1 * np.cos(np.pi * x), 1.4, 1)
+        w.params.positivity_fallback = 0
     elif kind == "rarefaction":
         # strong rarefaction: non-physical face states replaced by averages
         w = WL.riemann_1d(60, (1.115, -4.992, 0.143), (0.884, 4.943, 0.137), order)
@@ -77,12 +87,22 @@ def test_vjp_matches_finite_differences(kind, order):
     largest adjoint component."""
     w = _workload(kind, order)
     g, p = w.grid, w.params
-    U, sx = evolved(w, {"wave": 6, "sod": 1, "rarefaction": 1}[kind])
+    U, sx = evolved(w, {"wave": 6, "sod": 1, "rarefaction": 1, "wall": 4}[kind])
     dt = O.cfl_dt(g, p, U)
     sigs = stage_sigmas(g, p, U, sx, dt)
     lev = _levels(g, p, U, sigs[0])
-    if kind == "wave":
+    if kind in ("wave", "wall"):
         assert np.all(lev == order)               # smooth: top level, DF factor 1
+    elif kind == "wall":
+        # smooth data between two reflective walls
+        w = WL.shu_osher(40, order)
+        g = w.grid
+        g.bc = (WL.BC_REFLECTIVE,) * 4
+        x = (np.arange(g.nx) + 0.5) / g.nx
+        rho = 1.0 + 0.2 * np.cos(np.pi * x)
+        g.interior(w.U)[:, 0] = WL.conservative(rho, 0.3 * np.sin(np.pi * x), 0.0,
+                                                1.0 + 0.1 * np.cos(np.pi * x), 1.4, 1)
+        w.params.positivity_fallback = 0
     elif kind == "rarefaction":
         wl, wr = O.reconstruct(g, p, 0, U.copy(), sigs[0].copy(), np.zeros_like(sigs[0]))
         W = np.concatenate([wl[:, 0], wr[:, 0]], axis=1)

@@ -74,3 +74,18 @@ def test_runs_to_final_time_with_physical_states(make):
     I = g.interior(U)[:, 0]
     pr = (p.gamma - 1) * (I[2] - 0.5 * I[1] ** 2 / I[0])
     assert np.isfinite(I).all() and I[0].min() > 0 and pr.min() > 0
+
+
+def test_box_walls_conserve_in_2d():
+    """Four-quadrant data in a box of reflective walls (lagged DF source: the
+    strengths of the ghost faces are the mirror images of the interior ones),
+    60 steps: mass and energy totals to round-off."""
+    w = WL.four_quadrant(45, 9, seed=7, ny=37)
+    w.grid.bc = (WL.BC_REFLECTIVE,) * 4
+    g, p = w.grid, w.params
+    m0 = g.interior(w.U).sum(axis=(1, 2))
+    U, _, _, _, _ = O.run(g, p, w.U, 60)
+    m1 = g.interior(U).sum(axis=(1, 2))
+    assert np.isfinite(m1).all()
+    for v in (0, 3):
+        assert abs(m1[v] - m0[v]) <= 1e-13 * m0[v], v
