@@ -59,7 +59,11 @@ enum {
     ASE_ERR_WORKSPACE = -6  /* workspace missing or too small            */
 };
 
-enum { ASE_BC_PERIODIC = 0, ASE_BC_TRANSMISSIVE = 1, ASE_BC_INFLOW_SLOT = 2 };
+/* Boundary codes.  TRANSMISSIVE: zero-gradient copy of the boundary cell;
+ * INFLOW_SLOT: Dirichlet inflow state in the ghost cells of the slot rows
+ * (x sides only); REFLECTIVE: slip wall, the ghost cells mirror the interior
+ * cells with the momentum normal to the wall reversed (needs n >= ng). */
+enum { ASE_BC_PERIODIC = 0, ASE_BC_TRANSMISSIVE = 1, ASE_BC_INFLOW_SLOT = 2, ASE_BC_REFLECTIVE = 3 };
 
 /* Flags of ase_params_t. */
 enum {
@@ -214,10 +218,11 @@ int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_
 /* Device workspace of ase_step_batched for `total` stored cells. */
 size_t ase_batched_workspace_bytes(int64_t total);
 
-/* Boundary codes of a batch: `bc` (ASE_BC_PERIODIC or ASE_BC_TRANSMISSIVE)
- * applies to every instance unless `bc_inst` (device [ninst], may be NULL)
- * gives one code per instance; there any code other than ASE_BC_PERIODIC
- * means transmissive.  A periodic instance needs ncells >= ng. */
+/* Boundary codes of a batch: `bc` (ASE_BC_PERIODIC, ASE_BC_TRANSMISSIVE or
+ * ASE_BC_REFLECTIVE, both ends alike) applies to every instance unless
+ * `bc_inst` (device [ninst], may be NULL) gives one code per instance; there
+ * any other code means transmissive.  A periodic or reflective instance
+ * needs ncells >= ng. */
 
 /* First-order DF strengths of every instance (the 1D ase_sigma_init per
  * instance); fills the ghost cells of U.  Device arrays. */

@@ -284,10 +284,10 @@ class BatchedSimulation:
             raise AseError("batch instances overlap or leave the array")
         bci = getattr(batch, "bc_inst", None)
         codes = np.full(len(n), batch.bc) if bci is None else np.asarray(bci)
-        if np.any((codes != 0) & (codes != 1)):
-            raise AseError("boundary codes must be periodic (0) or transmissive (1)")
-        if np.any((codes == 0) & (n < batch.ng)):
-            raise AseError("periodic instances need ncells >= ng")
+        if np.any((codes != 0) & (codes != 1) & (codes != 3)):
+            raise AseError("boundary codes must be periodic (0), transmissive (1) or reflective (3)")
+        if np.any(((codes == 0) | (codes == 3)) & (n < batch.ng)):
+            raise AseError("periodic and reflective instances need ncells >= ng")
         self.bc_inst = None if bci is None else torch.as_tensor(codes, dtype=torch.int32).to(device)
         self.offsets = torch.as_tensor(off, dtype=torch.int64).to(device)
         self.ncells = torch.as_tensor(n, dtype=torch.int32).to(device)

@@ -49,14 +49,18 @@ int validate(const ase_grid_t *g, const ase_params_t *p, Geo *geo)
     if (g->ld < g->nx + 2 * g->ng) return fail(ASE_ERR_ARG, "ld must be >= nx + 2 ng");
     if (!(g->dx > 0.0) || (g->dim == 2 && !(g->dy > 0.0))) return fail(ASE_ERR_ARG, "dx, dy must be > 0");
     for (int k = 0; k < 4; ++k)
-        if (g->bc[k] < 0 || g->bc[k] > 2) return fail(ASE_ERR_ARG, "unknown boundary code");
+        if (g->bc[k] < 0 || g->bc[k] > 3) return fail(ASE_ERR_ARG, "unknown boundary code");
     if ((g->bc[0] == ASE_BC_PERIODIC) != (g->bc[1] == ASE_BC_PERIODIC))
         return fail(ASE_ERR_ARG, "periodic x boundaries must pair");
     if (g->dim == 2 && (g->bc[2] == ASE_BC_PERIODIC) != (g->bc[3] == ASE_BC_PERIODIC))
         return fail(ASE_ERR_ARG, "periodic y boundaries must pair");
     if (g->dim == 2 && (g->bc[2] == ASE_BC_INFLOW_SLOT || g->bc[3] == ASE_BC_INFLOW_SLOT))
         return fail(ASE_ERR_ARG, "inflow slot is an x boundary only");
-    if (g->bc[0] == ASE_BC_PERIODIC && g->nx < g->ng) return fail(ASE_ERR_ARG, "periodic x needs nx >= ng");
+    if ((g->bc[0] == ASE_BC_PERIODIC || g->bc[0] == ASE_BC_REFLECTIVE || g->bc[1] == ASE_BC_REFLECTIVE) &&
+        g->nx < g->ng)
+        return fail(ASE_ERR_ARG, "periodic or reflective x needs nx >= ng");
+    if (g->dim == 2 && (g->bc[2] == ASE_BC_REFLECTIVE || g->bc[3] == ASE_BC_REFLECTIVE) && g->ny < g->ng)
+        return fail(ASE_ERR_ARG, "reflective y needs ny >= ng");
     if (g->dim == 2 && g->bc[2] == ASE_BC_PERIODIC && g->ny < g->ng)
         return fail(ASE_ERR_ARG, "periodic y needs ny >= ng");
     const long long NX = g->nx + 2LL * g->ng, NY = g->dim == 1 ? 1 : g->ny + 2LL * g->ng;
@@ -450,7 +454,8 @@ static int batched_common(const ase_params_t *p, int32_t bc, int32_t ninst, cons
     const int r = p->order;
     if (r != 3 && r != 5 && r != 7 && r != 9) return fail(ASE_ERR_ORDER, "order must be 3, 5, 7 or 9");
     if (ng < (r + 1) / 2) return fail(ASE_ERR_GHOST, "ng must be >= (order+1)/2");
-    if (bc != ASE_BC_PERIODIC && bc != ASE_BC_TRANSMISSIVE) return fail(ASE_ERR_ARG, "bc must be periodic or transmissive");
+    if (bc != ASE_BC_PERIODIC && bc != ASE_BC_TRANSMISSIVE && bc != ASE_BC_REFLECTIVE)
+        return fail(ASE_ERR_ARG, "bc must be periodic, transmissive or reflective");
     if (ninst < 1 || total < 1) return fail(ASE_ERR_ARG, "ninst and total must be >= 1");
     if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->sigma_thres > 0.0) || !(p->eps > 0.0) ||
         !(p->d_hi > 0.0 && p->d_hi < 1.0) || !(p->d_lo >= 0.0 && p->d_lo <= 1.0))
@@ -587,8 +592,10 @@ int ase_adjoint_step(const ase_grid_t *g, const ase_params_t *p, const double *U
     int rc = validate(g, p, &geo);
     if (rc) return rc;
     if (geo.dim != 1) return fail(ASE_ERR_ARG, "ase_adjoint_step: 1D grids only");
-    if (g->bc[0] != g->bc[1] || (g->bc[0] != ASE_BC_TRANSMISSIVE && g->bc[0] != ASE_BC_PERIODIC))
-        return fail(ASE_ERR_ARG, "ase_adjoint_step: boundaries must be both transmissive or both periodic");
+    if (g->bc[0] != g->bc[1] || (g->bc[0] != ASE_BC_TRANSMISSIVE && g->bc[0] != ASE_BC_PERIODIC &&
+                                 g->bc[0] != ASE_BC_REFLECTIVE))
+        return fail(ASE_ERR_ARG,
+                    "ase_adjoint_step: boundaries must be both transmissive, both periodic or both reflective");
     ASE_PTR(U_n, "U_n");
     ASE_PTR(sigma_n, "sigma_n");
     ASE_PTR(dt, "dt");

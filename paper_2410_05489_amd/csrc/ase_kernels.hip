@@ -45,25 +45,37 @@ __device__ __forceinline__ bool in_slot(const BCInfo &b, int J)
 
 // Source of stored cell (I, J) under the boundary conditions: the row is
 // mapped by the y rule, then the column by the x rule within that row (so
-// corners are the y rule applied to x-filled values).  Returns false when
+// corners are the y rule applied to x-filled values).  A reflective (slip)
+// side mirrors the cells and reverses the momentum normal to it: flipx /
+// flipy tell the caller to negate the x / y momentum.  Returns false when
 // the cell takes the inflow state.
-__device__ __forceinline__ bool src_cell(const BCInfo &b, int I, int J, int &Is, int &Js)
+__device__ __forceinline__ bool src_cell(const BCInfo &b, int I, int J, int &Is, int &Js, bool &flipx, bool &flipy)
 {
     Js = J;
+    flipx = flipy = false;
     if (b.dim == 2) {
         const int j = J - b.ng;
-        if (j < 0) Js = (b.bc[2] == ASE_BC_PERIODIC) ? J + b.ny : b.ng;
-        else if (j >= b.ny) Js = (b.bc[3] == ASE_BC_PERIODIC) ? J - b.ny : b.ng + b.ny - 1;
+        if (j < 0) {
+            if (b.bc[2] == ASE_BC_PERIODIC) Js = J + b.ny;
+            else if (b.bc[2] == ASE_BC_REFLECTIVE) { Js = 2 * b.ng - 1 - J; flipy = true; }
+            else Js = b.ng;
+        } else if (j >= b.ny) {
+            if (b.bc[3] == ASE_BC_PERIODIC) Js = J - b.ny;
+            else if (b.bc[3] == ASE_BC_REFLECTIVE) { Js = 2 * (b.ny + b.ng) - 1 - J; flipy = true; }
+            else Js = b.ng + b.ny - 1;
+        }
     }
     Is = I;
     const int i = I - b.ng;
     if (i < 0) {
         if (b.bc[0] == ASE_BC_PERIODIC) Is = I + b.nx;
         else if (b.bc[0] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return false;
+        else if (b.bc[0] == ASE_BC_REFLECTIVE) { Is = 2 * b.ng - 1 - I; flipx = true; }
         else Is = b.ng;
     } else if (i >= b.nx) {
         if (b.bc[1] == ASE_BC_PERIODIC) Is = I - b.nx;
         else if (b.bc[1] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return false;
+        else if (b.bc[1] == ASE_BC_REFLECTIVE) { Is = 2 * (b.nx + b.ng) - 1 - I; flipx = true; }
         else Is = b.ng + b.nx - 1;
     }
     return true;
@@ -99,10 +111,13 @@ template <int NV>
 __device__ __forceinline__ void cell_value(const BCInfo &b, const double *U, int I, int J, double (&W)[NV])
 {
     int Is, Js;
-    if (src_cell(b, I, J, Is, Js)) {
+    bool fx, fy;
+    if (src_cell(b, I, J, Is, Js, fx, fy)) {
         const long long src = (long long)Js * b.ld + Is;
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + src];
+        if (fx) W[1] = -W[1];
+        if (NV == 4 && fy) W[2] = -W[2];
     } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[v] = b.inflow[v];
@@ -123,10 +138,39 @@ __device__ __forceinline__ double sigma_first_order(const BCInfo &b, const doubl
 
 __device__ __forceinline__ int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
+// Cell index mapped by the boundary rule of one axis: periodic wrap or wall
+// mirror; other codes leave it.
+__device__ __forceinline__ int map_cell(int i, int n, int lo, int hi)
+{
+    if (i < 0) {
+        if (lo == ASE_BC_PERIODIC) return wrapi(i, n);
+        if (lo == ASE_BC_REFLECTIVE) return -1 - i;
+    } else if (i >= n) {
+        if (hi == ASE_BC_PERIODIC) return wrapi(i, n);
+        if (hi == ASE_BC_REFLECTIVE) return 2 * n - 1 - i;
+    }
+    return i;
+}
+
+// Face index f (face f + 1/2) mapped likewise: a wall at -1/2 maps f to
+// -f-2, a wall at n-1/2 maps f to 2n-f-2 (a wall is a symmetry plane of the
+// lagged strengths as well as of the cells).
+__device__ __forceinline__ int map_face(int f, int n, int lo, int hi)
+{
+    if (f < -1) {
+        if (lo == ASE_BC_PERIODIC) return wrapi(f, n);
+        if (lo == ASE_BC_REFLECTIVE) return -f - 2;
+    } else if (f > n - 1) {
+        if (hi == ASE_BC_PERIODIC) return wrapi(f, n);
+        if (hi == ASE_BC_REFLECTIVE) return 2 * n - f - 2;
+    }
+    return f;
+}
+
 // Ghost cells and the strengths of the stored faces that are not flux faces,
 // in one pass.  init = 0: the ghost frame; each non-flux face takes its
-// periodic image or the first-order strength of its two (boundary-mapped)
-// cells.  init = 1: ghost frame plus first-order strengths of every stored
+// periodic image or its mirror image at a wall if that is a flux face, else
+// the first-order strength of its two (boundary-mapped) cells.  init = 1: ghost frame plus first-order strengths of every stored
 // face.  Strengths are computed from the boundary-mapped values directly, so
 // they do not wait for the ghost writes.
 template <int NV>
@@ -134,8 +178,6 @@ __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, 
                                                       int init)
 {
     const long long n = init ? (long long)b.NY * b.NX : frame_size(b);
-    const bool xper = b.bc[0] == ASE_BC_PERIODIC;
-    const bool yper = b.dim == 2 && b.bc[2] == ASE_BC_PERIODIC;
     for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * kThreads) {
         int I, J;
@@ -162,8 +204,8 @@ __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, 
             if (init) {
                 sx[pos] = sigma_first_order<NV>(b, U, I, J, I + 1, J, 0, mc);
             } else if (!produced) {
-                const int fw = xper ? wrapi(f, b.nx) : f;
-                const int jw = yper ? wrapi(j, b.ny) : j;
+                const int fw = map_face(f, b.nx, b.bc[0], b.bc[1]);
+                const int jw = b.dim == 2 ? map_cell(j, b.ny, b.bc[2], b.bc[3]) : j;
                 const bool jw_ok = b.dim == 1 || (jw >= 0 && jw < b.ny);
                 if (jw_ok && fw >= -1 && fw <= b.nx - 1) {
                     const int Jw = b.dim == 1 ? 0 : jw + b.ng;
@@ -179,8 +221,8 @@ __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, 
             if (init) {
                 sy[pos] = sigma_first_order<NV>(b, U, I, J, I, J + 1, 1, mc);
             } else if (!produced) {
-                const int fw = yper ? wrapi(f, b.ny) : f;
-                const int iw = xper ? wrapi(i, b.nx) : i;
+                const int fw = map_face(f, b.ny, b.bc[2], b.bc[3]);
+                const int iw = map_cell(i, b.nx, b.bc[0], b.bc[1]);
                 if (iw >= 0 && iw < b.nx && fw >= -1 && fw <= b.ny - 1) {
                     sy[pos] = sy[(long long)(fw + b.ng) * b.ld + iw + b.ng];
                 } else {
@@ -698,11 +740,12 @@ struct BatchArgs {
     MethodConst mc;
 };
 
-// Boundary code of instance k: periodic, anything else transmissive.
+// Boundary code of instance k: periodic, reflective, anything else
+// transmissive.
 __device__ __forceinline__ int inst_bc(const int *bc_inst, int bc, int k)
 {
     const int b = bc_inst ? bc_inst[k] : bc;
-    return b == ASE_BC_PERIODIC ? ASE_BC_PERIODIC : ASE_BC_TRANSMISSIVE;
+    return (b == ASE_BC_PERIODIC || b == ASE_BC_REFLECTIVE) ? b : ASE_BC_TRANSMISSIVE;
 }
 
 // Ghost cells of one instance and the strengths its stage reads.
@@ -716,9 +759,12 @@ __device__ __forceinline__ void batched_fill(const BatchArgs &a, int bc, double 
         const int I = k < ng ? k : N + k;
         int Is;
         if (bc == ASE_BC_PERIODIC) Is = k < ng ? I + N : I - N;
+        else if (bc == ASE_BC_REFLECTIVE) Is = k < ng ? 2 * ng - 1 - I : 2 * (N + ng) - 1 - I;
         else Is = k < ng ? ng : ng + N - 1;
-#pragma unroll
-        for (int v = 0; v < 3; ++v) U[v * P + I] = U[v * P + Is];
+        const double fm = bc == ASE_BC_REFLECTIVE ? -1.0 : 1.0;   // momentum sign at a wall
+        U[I] = U[Is];
+        U[P + I] = fm * U[P + Is];
+        U[2 * P + I] = U[2 * P + Is];
     }
     __syncthreads();
     for (int I = threadIdx.x; I + 1 < NX; I += NT) {
@@ -727,6 +773,8 @@ __device__ __forceinline__ void batched_fill(const BatchArgs &a, int bc, double 
         if (a.fo || !produced) {
             if (!a.fo && bc == ASE_BC_PERIODIC) {
                 sg[I] = sg[((f % N) + N) % N + ng];
+            } else if (!a.fo && bc == ASE_BC_REFLECTIVE) {
+                sg[I] = sg[(f < -1 ? -f - 2 : 2 * N - f - 2) + ng];   // mirror face at a wall
             } else {
                 double Wa[3], Wb[3];
 #pragma unroll
@@ -1087,6 +1135,20 @@ __device__ __forceinline__ void adj_fold(double *out, long long P, int N, int ng
                     const int tgt = k;
                     if (tgt >= 0 && tgt < N) o[tgt + ng] += o[N + ng + k];
                 }
+            }
+        } else if (bc == ASE_BC_REFLECTIVE) {
+            // ghost storage k copies storage 2ng-1-k (left), N+ng+k copies
+            // N+ng-1-k (right); the momentum gradient changes sign
+            const double fm = v == 1 ? -1.0 : 1.0;
+            if (side == 0) {
+                if (N >= 2 * ng) {
+                    for (int k = 0; k < ng; ++k) o[2 * ng - 1 - k] += fm * o[k];
+                } else {
+                    for (int k = 0; k < ng; ++k) o[2 * ng - 1 - k] += fm * o[k];
+                    for (int k = 0; k < ng; ++k) o[N + ng - 1 - k] += fm * o[N + ng + k];
+                }
+            } else if (N >= 2 * ng) {
+                for (int k = 0; k < ng; ++k) o[N + ng - 1 - k] += fm * o[N + ng + k];
             }
         } else if (N > 1) {
             double acc = 0.0;

@@ -425,18 +425,19 @@ def instance_grid(batch: Batch, k: int) -> Grid:
 
 def batched_mixed(ninst: int = 12, nmin: int = 16, nmax: int = 400, order: int = 9, seed: int = 5,
                   nsteps: int = 20) -> Batch:
-    """Instances with their own boundary conditions: even instances carry the
-    smooth periodic data of batched_smooth, odd ones the transmissive Riemann
-    data of batched_riemann (positivity fallback on)."""
+    """Instances with their own boundary conditions: instance k carries the
+    smooth periodic data of batched_smooth (k % 3 == 0), the transmissive
+    Riemann data of batched_riemann (k % 3 == 1) or that Riemann data between
+    two reflective walls (k % 3 == 2); positivity fallback on."""
     sm = batched_smooth(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed, nsteps=nsteps)
     rm = batched_riemann(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed + 1, nsteps=nsteps)
-    pick = [sm if k % 2 == 0 else rm for k in range(ninst)]
+    pick = [sm if k % 3 == 0 else rm for k in range(ninst)]
     ncells, offsets, total = _pack([int(b.ncells[k]) for k, b in enumerate(pick)], sm.ng)
     U = np.zeros((3, total), dtype=np.float64)
     for k, b in enumerate(pick):
         o = int(offsets[k])
         U[:, o:o + int(ncells[k]) + 2 * sm.ng] = b.instance(k)
     dx = np.array([float(b.dx[k]) for k, b in enumerate(pick)])
-    bc_inst = np.array([BC_PERIODIC if k % 2 == 0 else BC_TRANSMISSIVE for k in range(ninst)], dtype=np.int32)
+    bc_inst = np.array([(BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE)[k % 3] for k in range(ninst)], dtype=np.int32)
     return Batch(ncells, offsets, dx, sm.ng, U, Params(order=order, gamma=1.4, cfl=0.5, positivity_fallback=1),
                  BC_TRANSMISSIVE, nsteps, bc_inst)

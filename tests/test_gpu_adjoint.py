@@ -39,10 +39,17 @@ def _case(name):
         w = WL.riemann_1d(300, (1.115, -4.992, 0.143), (0.884, 4.943, 0.137), 9)
         w.params.positivity_fallback = 1
         return w, 1
+    if name == "wall":
+        # Sod data between two reflective walls, lagged DF source
+        w = WL.sod(300, 9)
+        w.grid.bc = (WL.BC_REFLECTIVE,) * 4
+        return w, 40
+    if name == "blast":
+        return WL.blast_wave(300, 9), 5
     raise ValueError(name)
 
 
-CASES = ["wave9", "sod9", "sod7", "sod5", "sod3", "wave5", "wave3", "sodfo", "rarefaction"]
+CASES = ["wave9", "sod9", "sod7", "sod5", "sod3", "wave5", "wave3", "sodfo", "rarefaction", "wall", "blast"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -243,9 +250,9 @@ def test_batched_adjoint_full_size():
 
 
 def test_batched_adjoint_mixed_boundaries():
-    """Per-instance boundary codes (periodic and transmissive in one launch):
+    """Per-instance boundary codes (periodic, transmissive and reflective):
     each instance's gradient has the bits of the single-grid path."""
-    b = WL.batched_mixed(ninst=6, nmin=20, nmax=300, order=9, seed=7, nsteps=6)
+    b = WL.batched_mixed(ninst=9, nmin=20, nmax=300, order=9, seed=7, nsteps=6)
     run = A.BatchedAdjoint(b, DEV, nbins=2, every=4)
     U0 = torch.tensor(b.U, device=DEV, requires_grad=True)
     run.pressure(run.run(U0, 6)).sum().backward()

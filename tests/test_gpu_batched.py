@@ -179,16 +179,16 @@ def test_batched_graph_replays_match_eager():
 
 
 def test_batched_per_instance_boundaries():
-    """Periodic and transmissive instances in one launch: each equals its own
+    """Periodic, transmissive and reflective instances in one launch: each equals its own
     single-grid ase_step run bit for bit, and the oracle within 1e-9."""
-    b = WL.batched_mixed(ninst=8, nmin=16, nmax=300, order=9, seed=5, nsteps=15)
+    b = WL.batched_mixed(ninst=9, nmin=16, nmax=300, order=9, seed=5, nsteps=15)
     sim = ase.BatchedSimulation(b, DEV, nbins=3, threads=512)
     sim.run(b.nsteps)
     torch.cuda.synchronize()
     Ug = sim.U.cpu().numpy()
     for k in range(b.ninst):
         g = WL.instance_grid(b, k)
-        assert g.bc[0] == (WL.BC_PERIODIC if k % 2 == 0 else WL.BC_TRANSMISSIVE)
+        assert g.bc[0] == (WL.BC_PERIODIC, WL.BC_TRANSMISSIVE, WL.BC_REFLECTIVE)[k % 3]
         s1 = ase.Simulation(g, b.params, _instance_state(b, b.U, k), device=DEV)
         s1.run(b.nsteps)
         torch.cuda.synchronize()

@@ -62,6 +62,14 @@ def _case(name, order, ragged=True):
         w = WL.density_wave_1d(70, order, seed=1)
     elif name == "riemann1d":
         w = WL.riemann_1d(301, (1.3, 0.4, 2.0), (0.2, -0.3, 0.1), order, x_split=0.37)
+    elif name == "blast":
+        w = WL.blast_wave(400, order)
+    elif name == "shuosher":
+        w = WL.shu_osher(200, order)
+    elif name == "box":
+        # four-quadrant data between reflective walls on all four sides
+        w = WL.four_quadrant(45 if ragged else 32, order, seed=7, ny=37 if ragged else 0)
+        w.grid.bc = (WL.BC_REFLECTIVE,) * 4
     else:
         raise KeyError(name)
     return w
@@ -78,8 +86,9 @@ def _evolved(w, nsteps):
 
 
 CASES_2D = [("quad", 9), ("quad", 7), ("quad", 5), ("quad", 3), ("quadfo", 9), ("config3", 9), ("wave2d", 9),
-            ("jet", 7)]
-CASES_1D = [("sod", 5), ("wave1d", 9), ("riemann1d", 9), ("riemann1d", 7), ("riemann1d", 3)]
+            ("jet", 7), ("box", 9)]
+CASES_1D = [("sod", 5), ("wave1d", 9), ("riemann1d", 9), ("riemann1d", 7), ("riemann1d", 3), ("blast", 9),
+            ("shuosher", 7)]
 
 
 @pytest.mark.parametrize("name,order", CASES_2D + CASES_1D)
@@ -215,8 +224,9 @@ def _gpu_run(w, U, sx, sy, t, nsteps, t_end=0.0):
 
 
 STEP_CASES = [("quad", 9), ("quad", 7), ("quad", 5), ("quad", 3), ("quadfo", 9), ("config3", 9), ("wave2d", 9),
-              ("jet", 7),
-              ("sod", 5), ("wave1d", 9), ("riemann1d", 9), ("riemann1d", 3)]
+              ("jet", 7), ("box", 9), ("box", 5),
+              ("sod", 5), ("wave1d", 9), ("riemann1d", 9), ("riemann1d", 3), ("blast", 9), ("blast", 5),
+              ("shuosher", 9)]
 
 
 @pytest.mark.parametrize("name,order", STEP_CASES)
@@ -248,7 +258,8 @@ def test_one_step(name, order):
 @pytest.mark.parametrize("name,order,nsteps,t_end", [("sod", 5, 400, 0.2), ("riemann1d", 9, 150, 0.0),
                                                      ("quad", 9, 60, 0.0), ("quadfo", 9, 60, 0.0),
                                                      ("config3", 9, 60, 0.0), ("wave2d", 7, 40, 0.0),
-                                                     ("jet", 7, 60, 0.0)])
+                                                     ("jet", 7, 60, 0.0), ("blast", 9, 300, 0.0),
+                                                     ("shuosher", 9, 400, 1.8), ("box", 9, 60, 0.0)])
 def test_full_run(name, order, nsteps, t_end):
     """Independent runs from the initial data: 1e-9 after the full run."""
     w = _case(name, order)
