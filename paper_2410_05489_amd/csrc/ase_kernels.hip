@@ -375,11 +375,15 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
     constexpr int SY = (DIR == 0) ? UY : TY, SX = (DIR == 0) ? TX : UX;
     __shared__ double sSN[UY][UX];
     __shared__ double sST[SY][SX];
-    // right-face traces, then left-face traces; the second array starts 16
-    // doubles (a half turn of the LDS banks) after a bank-aligned boundary so
-    // that the two lanes of a face pair read different banks
+    // right-face traces, then left-face traces.  The LDS serves a 64-bit
+    // read to 16 lanes per cycle, double d in bank pair d mod 16.  A group of
+    // 16 lanes in phase 2 holds 8 faces, both sides; the offset of the
+    // second array puts the two sides of a face 8 doubles apart modulo 16
+    // (x faces: the upper side reads the next column, +1; y faces: the next
+    // row, +TX), so the 16 reads hit 16 different bank pairs.
     constexpr int NT1 = NV * TY * TX;
-    constexpr int TOFF = (NT1 + 31) / 32 * 32 + 16;
+    constexpr int TSTEP = (DIR == 0) ? 1 : TX;
+    constexpr int TOFF = (NT1 + 15) / 16 * 16 + ((8 - TSTEP) % 16 + 16) % 16;
     __shared__ double sT[TOFF + NT1];
     double(*sTR)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[0]);
     double(*sTL)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[TOFF]);
@@ -425,9 +429,25 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
     }
     __syncthreads();
 
-    // phase 1: normal reconstruction, face traces of every cell the tile needs
+    // phase 1: normal reconstruction, face traces of every cell the tile needs.
+    // x faces (TX = 17 trace columns): each group of 16 lanes takes 16
+    // columns of one row, the last column is walked down its rows; both
+    // orders keep the 16 reads of a group in distinct bank pairs.
     for (int it = tid; it < TX * TY; it += NT) {
-        const int tx = it % TX, ty = it / TX;
+        int tx, ty;
+        if constexpr (DIR == 0 && TX > 16) {
+            constexpr int MAIN = 16 * TY;
+            if (it < MAIN) {
+                tx = it % 16;
+                ty = it / 16;
+            } else {
+                tx = 16 + (it - MAIN) / TY;
+                ty = (it - MAIN) % TY;
+            }
+        } else {
+            tx = it % TX;
+            ty = it / TX;
+        }
         const int lx = (DIR == 0) ? tx + R : tx;
         const int ly = (DIR == 0) ? ty : ty + R;
         const int x = ox + lx, y = oy + ly;
@@ -513,9 +533,10 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
             for (int v = 0; v < NV; ++v) Fs[v] = 0.0;
             // cell averages of this lane's side and of the other side (read
             // only for the positivity replacement)
-            const long long pl = (long long)(y + a.ng) * a.ld + x + a.ng;
-            const long long pr = DIR == 0 ? pl + 1 : pl + a.ld;
-            const long long po = side == 0 ? pl : pr, pt = side == 0 ? pr : pl;
+            // (positions within a plane fit in 32 bits: the host checks it)
+            const int pl = (y + a.ng) * a.ld + x + a.ng;
+            const int pr = DIR == 0 ? pl + 1 : pl + a.ld;
+            const int po = side == 0 ? pl : pr, pt = side == 0 ? pr : pl;
             const double *U = a.U;
             const long long P = a.plane;
             auto co = [=](int v) { return U[v * P + po]; };
@@ -545,7 +566,7 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
             ssum += swap_pair(ssum);
             if (valid && side == 0) {
                 const bool own = DIR == 0 ? (fx > 0 || i0 == 0) : (fy > 0 || j0 == 0);
-                if (own) a.sig_out[(long long)(y + a.ng) * a.ld + x + a.ng] = ssum / (double)G;
+                if (own) a.sig_out[pl] = ssum / (double)G;
             }
             // the flux tile reuses the state tile: phase 2 reads no staged state
             if (valid && side == 0) {
@@ -573,10 +594,11 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
             } else {
                 const double d = -(sF(v, cy + 1, cx) - sF(v, cy, cx)) * a.inv_dy;
                 const double L = a.Res[e] + d;
+                const double Un = a.Un[e];
                 double o;
-                if (a.stage == 1) o = a.Un[e] + dt * L;
-                else if (a.stage == 2) o = 0.75 * a.Un[e] + 0.25 * a.U[e] + 0.25 * dt * L;
-                else o = (1.0 / 3.0) * a.Un[e] + (2.0 / 3.0) * a.U[e] + (2.0 / 3.0) * dt * L;
+                if (a.stage == 1) o = Un + dt * L;
+                else if (a.stage == 2) o = 0.75 * Un + 0.25 * a.U[e] + 0.25 * dt * L;
+                else o = (1.0 / 3.0) * Un + (2.0 / 3.0) * a.U[e] + (2.0 / 3.0) * dt * L;
                 a.Uout[e] = o;
             }
         }
