@@ -122,6 +122,15 @@ static double Zk(int k, double xi)
     return p - mean;
 }
 
+/* dZ_k/dxi = k xi^(k-1): slopes of the reconstruction, which the gas-kinetic */
+/* flux takes at the interface (Sec. 2.2; the derivative in x is this / dx).  */
+static double dZk(int k, double xi)
+{
+    double p = (double)k;
+    for (int m = 1; m < k; ++m) p *= xi;
+    return p;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Stencil coefficients W_xk of the zero-mean polynomial on each stencil.    */
 /* W points at W_0; W[m] is the cell average of the m-th neighbour.           */
@@ -186,6 +195,14 @@ static double poly_eval(double W0, const double *a, int n, double xi)
     return P;
 }
 
+/* dP/dxi = sum_{k=1}^{n} a_k dZ_k/dxi. */
+static double poly_deriv(const double *a, int n, double xi)
+{
+    double D = 0.0;
+    for (int k = 1; k <= n; ++k) D += a[k - 1] * dZk(k, xi);
+    return D;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Discontinuity feedback (Sec. 3.1).                                         */
 /* ------------------------------------------------------------------------ */
@@ -224,8 +241,9 @@ static double beta3(const double a[2])
 
 /* WENO-Z-AO(5,3) with DF (Sec. 3.2).  Wc points at W_0 (needs W_{-2..2});    */
 /* alpha[0..2] are the DF factors of S^{r3}_{-1,0,1}, alpha[3] of S^{r5}.     */
+/* dout (may be NULL) receives dP/dxi of the same combined polynomial.         */
 static void weno_ao53_df(const orc_params *p, const double *Wc, const double alpha[4],
-                         int npts, const double *xi, double *out)
+                         int npts, const double *xi, double *out, double *dout)
 {
     double a3[3][2], a5[4], b3[3];
     for (int k = -1; k <= 1; ++k) {
@@ -269,6 +287,17 @@ static void weno_ao53_df(const orc_params *p, const double *Wc, const double alp
         double P = wb5 * inner;
         for (int k = 0; k < 3; ++k) P += wb3[k] * P3[k];
         out[q] = P;
+        if (dout) {
+            /* the weights do not depend on xi: the same combination of slopes */
+            double D3[3];
+            for (int k = 0; k < 3; ++k) D3[k] = alpha[k] * (a3[k][0] * dZk(1, xi[q]) + a3[k][1] * dZk(2, xi[q]));
+            double D5 = alpha[3] * poly_deriv(a5, 4, xi[q]);
+            double dinner = D5 / d5;
+            for (int k = 0; k < 3; ++k) dinner -= d3[k] / d5 * D3[k];
+            double D = wb5 * dinner;
+            for (int k = 0; k < 3; ++k) D += wb3[k] * D3[k];
+            dout[q] = D;
+        }
     }
 }
 
@@ -283,12 +312,14 @@ enum { ORC_LVL_FIRST = 1, ORC_LVL_WENOAO = 2, ORC_LVL_R3 = 3, ORC_LVL_5 = 5, ORC
 /* stencil L <= r whose DF factor is 1 is used; alpha(S^{r5}) < 1 selects the */
 /* WENO-Z-AO(5,3) with DF.  Reading R12: r = 3 is the centred S^{r3}_0       */
 /* polynomial damped by its own DF factor.                                  */
+/* dout (may be NULL) receives dP/dxi at the same points.                    */
 static int ase_poly(const orc_params *p, int r, const double *Wc, const double *sc,
-                    int npts, const double *xi, double *out)
+                    int npts, const double *xi, double *out, double *dout)
 {
     double thr = p->sigma_thres;
     if (r == 1) {
         for (int q = 0; q < npts; ++q) out[q] = Wc[0];
+        if (dout) for (int q = 0; q < npts; ++q) dout[q] = 0.0;
         return ORC_LVL_FIRST;
     }
     if (r == 3) {
@@ -296,6 +327,8 @@ static int ase_poly(const orc_params *p, int r, const double *Wc, const double *
         coef_r3(0, Wc, a);
         double al = df_alpha(stencil_sum(sc, -1, 1), thr);
         for (int q = 0; q < npts; ++q) out[q] = Wc[0] + al * (a[0] * Zk(1, xi[q]) + a[1] * Zk(2, xi[q]));
+        if (dout)
+            for (int q = 0; q < npts; ++q) dout[q] = al * (a[0] * dZk(1, xi[q]) + a[1] * dZk(2, xi[q]));
         return ORC_LVL_R3;
     }
     /* Start from the 5-cell stencil and extend while the DF factor is 1. */
@@ -323,7 +356,7 @@ static int ase_poly(const orc_params *p, int r, const double *Wc, const double *
         al[1] = df_alpha(stencil_sum(sc, -1, 1), thr);   /* S^{r3}_{0} : cells -1..1 */
         al[2] = df_alpha(stencil_sum(sc, 0, 2), thr);    /* S^{r3}_{1} : cells  0..2 */
         al[3] = alpha5;                                  /* S^{r5}     : cells -2..2 */
-        weno_ao53_df(p, Wc, al, npts, xi, out);
+        weno_ao53_df(p, Wc, al, npts, xi, out, dout);
         return level;
     }
     double a[8];
@@ -332,6 +365,7 @@ static int ase_poly(const orc_params *p, int r, const double *Wc, const double *
     else if (level == 7) { coef_r7(Wc, a); n = 6; }
     else { coef_r9(Wc, a); n = 8; }
     for (int q = 0; q < npts; ++q) out[q] = poly_eval(Wc[0], a, n, xi[q]);
+    if (dout) for (int q = 0; q < npts; ++q) dout[q] = poly_deriv(a, n, xi[q]);
     return level;
 }
 
@@ -677,7 +711,7 @@ static int sweep(const orc_grid *g, const orc_params *p, int dir, const double *
             for (int v = 0; v < nv; ++v) {
                 for (int m = -R; m <= R; ++m) Wline[m + R] = U[v * P + base + m * s_along];
                 for (int m = -R; m < R; ++m) sline[m + R] = snorm[base + m * s_along];
-                int lv = ase_poly(p, r, Wline + R, sline + R, 2, xi_n, out);
+                int lv = ase_poly(p, r, Wline + R, sline + R, 2, xi_n, out, NULL);
                 size_t t = ((size_t)v * nrow + (c + Rt)) * ncell + (a + 1);
                 tR[t] = out[0];
                 tL[t] = out[1];
@@ -707,8 +741,8 @@ static int sweep(const orc_grid *g, const orc_params *p, int dir, const double *
                         sl_line[m + R] = stang[bl + m * s_across];
                         sr_line[m + R] = stang[br + m * s_across];
                     }
-                    ase_poly(p, r, Wl_line + R, sl_line + R, G, xi_g, outl);
-                    ase_poly(p, r, Wr_line + R, sr_line + R, G, xi_g, outr);
+                    ase_poly(p, r, Wl_line + R, sl_line + R, G, xi_g, outl, NULL);
+                    ase_poly(p, r, Wr_line + R, sr_line + R, G, xi_g, outr, NULL);
                 }
                 for (int k = 0; k < G; ++k) { WL[k][v] = outl[k]; WR[k][v] = outr[k]; }
             }
@@ -1077,14 +1111,14 @@ fail:
 int orc_poly(const orc_params *p, const double *W, const double *s, int npts, const double *xi, double *out)
 {
     int R = halfwidth(p->order);
-    return ase_poly(p, p->order, W + R, s + R, npts, xi, out);
+    return ase_poly(p, p->order, W + R, s + R, npts, xi, out, NULL);
 }
 
 /* WENO-Z-AO(5,3) with given DF factors: W[0..4] (W_0 = W[2]).               */
 void orc_weno_ao53(const orc_params *p, const double *W, const double *alpha, int npts, const double *xi,
                    double *out)
 {
-    weno_ao53_df(p, W + 2, alpha, npts, xi, out);
+    weno_ao53_df(p, W + 2, alpha, npts, xi, out, NULL);
 }
 
 /* Stencil coefficients W_xk of stencil kind (3 with sub = -1,0,1; 5; 7; 9)   */
@@ -1118,4 +1152,455 @@ void orc_lf_point(const orc_grid *g, const orc_params *p, const double *Wl, cons
     primitives(g, p, Wl, dir, &ql);
     primitives(g, p, Wr, dir, &qr);
     lf_flux(g, Wl, &ql, Wr, &qr, dir, F);
+}
+
+/* ======================================================================== */
+/* Gas-kinetic flux and two-stage fourth-order time stepping, 1D            */
+/* (Sec. 2.2 and App. A).                                                    */
+/*                                                                          */
+/* Velocity space of the 1D BGK model: particle velocity u and K internal   */
+/* degrees of freedom xi; psi = (1, u, (u^2 + xi^2)/2).  The paper writes   */
+/* the 2D form, K = (4 - 2 gamma)/(gamma - 1); with no v-direction the v    */
+/* degree of freedom joins the internal ones, K = (3 - gamma)/(gamma - 1)   */
+/* (reading: the 1D form of the same model).  A Maxwellian is              */
+/* g = rho (lambda/pi)^((K+1)/2) exp(-lambda((u-U)^2 + xi^2)) with          */
+/* lambda = rho / (2 p).                                                    */
+/*                                                                          */
+/* Moments are taken of polynomials in (u, xi^2), stored as coefficient     */
+/* tables c[n][l] of u^n xi^(2l): <c> = sum c[n][l] <u^n> <xi^(2l)>, the    */
+/* factorisation of App. A.                                                  */
+/* ======================================================================== */
+
+enum { GKS_NU = 8, GKS_NL = 3 };
+typedef struct { double c[GKS_NU][GKS_NL]; } upoly;
+
+typedef struct {
+    double rho, U, lam, K;
+    double um[GKS_NU];   /* <u^n>, whole line        */
+    double up[GKS_NU];   /* <u^n>_{>0}, half line    */
+    double un[GKS_NU];   /* <u^n>_{<0}, half line    */
+    double xm[GKS_NL];   /* <xi^(2l)>                */
+} gks_maxw;
+
+typedef struct { double c1, c2, tau; } orc_gks;
+
+/* Maxwellian of the state W = (rho, rho U, E) and its moments (App. A):     */
+/*   <u^0> = 1, <u^1> = U, <u^(n+2)> = U <u^(n+1)> + (n+1)/(2 lambda) <u^n>; */
+/*   half lines start from erfc(-+sqrt(lambda) U)/2 and                      */
+/*   +-exp(-lambda U^2) / (2 sqrt(pi lambda)), same recursion;              */
+/*   <xi^0> = 1, <xi^2> = K/(2 lambda), <xi^(2l)> = (K + 2(l-1))/(2 lambda)  */
+/*   <xi^(2(l-1))>.                                                          */
+/* Returns -1 when rho <= 0 or p <= 0.                                       */
+static int gks_maxwellian(double gamma, const double *W, gks_maxw *m)
+{
+    double rho = W[0];
+    double U = W[1] / rho;
+    double p = (gamma - 1.0) * (W[2] - 0.5 * rho * U * U);
+    if (!(rho > 0.0) || !(p > 0.0)) return -1;
+    m->rho = rho;
+    m->U = U;
+    m->lam = rho / (2.0 * p);
+    m->K = (3.0 - gamma) / (gamma - 1.0);
+    double lam = m->lam;
+    m->um[0] = 1.0;
+    m->um[1] = U;
+    m->up[0] = 0.5 * erfc(-sqrt(lam) * U);
+    m->un[0] = 0.5 * erfc(sqrt(lam) * U);
+    const double pi = 3.14159265358979323846;
+    double e = exp(-lam * U * U) / (2.0 * sqrt(pi * lam));
+    m->up[1] = U * m->up[0] + e;
+    m->un[1] = U * m->un[0] - e;
+    for (int n = 0; n + 2 < GKS_NU; ++n) {
+        double h = (double)(n + 1) / (2.0 * lam);
+        m->um[n + 2] = U * m->um[n + 1] + h * m->um[n];
+        m->up[n + 2] = U * m->up[n + 1] + h * m->up[n];
+        m->un[n + 2] = U * m->un[n + 1] + h * m->un[n];
+    }
+    m->xm[0] = 1.0;
+    for (int l = 1; l < GKS_NL; ++l) m->xm[l] = (m->K + 2.0 * (l - 1)) / (2.0 * lam) * m->xm[l - 1];
+    return 0;
+}
+
+/* psi_j as a polynomial (j = 0, 1, 2). */
+static upoly gks_psi(int j)
+{
+    upoly q;
+    memset(&q, 0, sizeof q);
+    if (j == 0) q.c[0][0] = 1.0;
+    else if (j == 1) q.c[1][0] = 1.0;
+    else { q.c[2][0] = 0.5; q.c[0][1] = 0.5; }
+    return q;
+}
+
+/* a . psi = a_1 + a_2 u + a_3 (u^2 + xi^2)/2 (the form of every micro slope). */
+static upoly gks_lin(const double a[3])
+{
+    upoly q;
+    memset(&q, 0, sizeof q);
+    for (int j = 0; j < 3; ++j) {
+        upoly s = gks_psi(j);
+        for (int n = 0; n < GKS_NU; ++n)
+            for (int l = 0; l < GKS_NL; ++l) q.c[n][l] += a[j] * s.c[n][l];
+    }
+    return q;
+}
+
+static upoly gks_mul(const upoly *x, const upoly *y)
+{
+    upoly q;
+    memset(&q, 0, sizeof q);
+    for (int n = 0; n < GKS_NU; ++n)
+        for (int l = 0; l < GKS_NL; ++l) {
+            if (x->c[n][l] == 0.0) continue;
+            for (int n2 = 0; n + n2 < GKS_NU; ++n2)
+                for (int l2 = 0; l + l2 < GKS_NL; ++l2) q.c[n + n2][l + l2] += x->c[n][l] * y->c[n2][l2];
+        }
+    return q;
+}
+
+/* u^k as a polynomial. */
+static upoly gks_upow(int k)
+{
+    upoly q;
+    memset(&q, 0, sizeof q);
+    q.c[k][0] = 1.0;
+    return q;
+}
+
+/* <q> with the u-moments um (whole or half line) and the xi-moments xm. */
+static double gks_avg(const upoly *q, const double *um, const double *xm)
+{
+    double s = 0.0;
+    for (int n = 0; n < GKS_NU; ++n)
+        for (int l = 0; l < GKS_NL; ++l) s += q->c[n][l] * um[n] * xm[l];
+    return s;
+}
+
+/* <q psi_j>, j = 0..2. */
+static void gks_avg_psi(const upoly *q, const double *um, const double *xm, double out[3])
+{
+    for (int j = 0; j < 3; ++j) {
+        upoly s = gks_psi(j);
+        upoly t = gks_mul(q, &s);
+        out[j] = gks_avg(&t, um, xm);
+    }
+}
+
+/* Micro slope a from <a . psi psi_j> = b_j (App. A, M a = b with           */
+/* M_ij = <psi_i psi_j>), solved by Gaussian elimination with partial        */
+/* pivoting on the moment matrix built from its definition.                  */
+static void gks_solve(const gks_maxw *m, const double b[3], double a[3])
+{
+    double M[3][4];
+    for (int i = 0; i < 3; ++i) {
+        upoly pi = gks_psi(i);
+        for (int j = 0; j < 3; ++j) {
+            upoly pj = gks_psi(j);
+            upoly t = gks_mul(&pi, &pj);
+            M[i][j] = gks_avg(&t, m->um, m->xm);
+        }
+        M[i][3] = b[i];
+    }
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+        if (piv != c)
+            for (int k = 0; k < 4; ++k) { double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t; }
+        for (int r = c + 1; r < 3; ++r) {
+            double f = M[r][c] / M[c][c];
+            for (int k = c; k < 4; ++k) M[r][k] -= f * M[c][k];
+        }
+    }
+    for (int c = 2; c >= 0; --c) {
+        double s = M[c][3];
+        for (int k = c + 1; k < 3; ++k) s -= M[c][k] * a[k];
+        a[c] = s / M[c][c];
+    }
+}
+
+/* Spatial slope a (b = W_x / rho) and the time slope A from the            */
+/* compatibility condition <A + a u> = 0 moment by moment:                  */
+/* M A = -<(a . psi) u psi>.                                                 */
+static void gks_slopes(const gks_maxw *m, const double *Wx, double a[3], double A[3])
+{
+    double b[3];
+    for (int j = 0; j < 3; ++j) b[j] = Wx[j] / m->rho;
+    gks_solve(m, b, a);
+    upoly la = gks_lin(a), u1 = gks_upow(1);
+    upoly t = gks_mul(&la, &u1);
+    double bt[3];
+    gks_avg_psi(&t, m->um, m->xm, bt);
+    for (int j = 0; j < 3; ++j) bt[j] = -bt[j];
+    gks_solve(m, bt, A);
+}
+
+/* Time integrals over [0, delta] of the coefficients of the distribution    */
+/* at the interface (Eq. GKS flux), collision time tau outside and tau_n in  */
+/* the exponentials, E = exp(-delta/tau_n):                                  */
+/*   q0 = int (1 - e^{-t/tau_n})                                             */
+/*   q1 = int ((t + tau) e^{-t/tau_n} - tau)                                 */
+/*   q2 = int (t - tau + tau e^{-t/tau_n})                                   */
+/*   q3 = int e^{-t/tau_n}                                                   */
+/*   q4 = int (tau + t) e^{-t/tau_n}                                         */
+/*   q5 = int tau e^{-t/tau_n}                                               */
+/* with int e^{-t/tau_n} = tau_n (1 - E) and                                */
+/* int t e^{-t/tau_n} = tau_n^2 (1 - E) - tau_n delta E.                      */
+/* tau_n = 0 is the limit E = 0 (exp(-inf)).                                 */
+static void gks_time_coef(double tau, double taun, double delta, double q[6])
+{
+    double E = exp(-delta / taun);
+    double i0 = taun * (1.0 - E);
+    double i1 = taun * taun * (1.0 - E) - taun * delta * E;
+    q[0] = delta - i0;
+    q[1] = i1 + tau * i0 - tau * delta;
+    q[2] = 0.5 * delta * delta - tau * delta + tau * i0;
+    q[3] = i0;
+    q[4] = tau * i0 + i1;
+    q[5] = tau * i0;
+}
+
+/* Flux transported through the interface over [0, delta] (Eq. total flux)   */
+/* from the two interface states W^l, W^r and their x-slopes:               */
+/*   W^c   = int_{u>0} psi g^l + int_{u<0} psi g^r      (Sec. 3.5)           */
+/*   W^c_x = int_{u>0} psi g^l_x + int_{u<0} psi g^r_x, g_x = (a . psi) g     */
+/*   F = rho_c [q0 <u psi> + q1 <(a^c.psi) u^2 psi> + q2 <(A^c.psi) u psi>]_c */
+/*     + rho_l [q3 <u psi> - q4 <(a^l.psi) u^2 psi> - q5 <(A^l.psi) u psi>]_{l,u>0} */
+/*     + rho_r [same]_{r,u<0}.                                               */
+/* Returns -1 when a state (or W^c) is not physical.                         */
+static int gks_flux_int(double gamma, const double *Wl, const double *Wlx, const double *Wr, const double *Wrx,
+                        double tau, double taun, double delta, double *F)
+{
+    gks_maxw ml, mr, mc;
+    if (gks_maxwellian(gamma, Wl, &ml) || gks_maxwellian(gamma, Wr, &mr)) return -1;
+    double al[3], Al[3], ar[3], Ar[3];
+    gks_slopes(&ml, Wlx, al, Al);
+    gks_slopes(&mr, Wrx, ar, Ar);
+    upoly one = gks_upow(0), u1 = gks_upow(1), u2 = gks_upow(2);
+    upoly pal = gks_lin(al), par = gks_lin(ar);
+    double Wc[3], Wcx[3], t1[3], t2[3];
+    gks_avg_psi(&one, ml.up, ml.xm, t1);
+    gks_avg_psi(&one, mr.un, mr.xm, t2);
+    for (int j = 0; j < 3; ++j) Wc[j] = ml.rho * t1[j] + mr.rho * t2[j];
+    gks_avg_psi(&pal, ml.up, ml.xm, t1);
+    gks_avg_psi(&par, mr.un, mr.xm, t2);
+    for (int j = 0; j < 3; ++j) Wcx[j] = ml.rho * t1[j] + mr.rho * t2[j];
+    if (gks_maxwellian(gamma, Wc, &mc)) return -1;
+    double ac[3], Ac[3];
+    gks_slopes(&mc, Wcx, ac, Ac);
+    double q[6];
+    gks_time_coef(tau, taun, delta, q);
+
+    upoly pac = gks_lin(ac), pAc = gks_lin(Ac), pAl = gks_lin(Al), pAr = gks_lin(Ar);
+    upoly c_a = gks_mul(&pac, &u2), c_A = gks_mul(&pAc, &u1);
+    upoly l_a = gks_mul(&pal, &u2), l_A = gks_mul(&pAl, &u1);
+    upoly r_a = gks_mul(&par, &u2), r_A = gks_mul(&pAr, &u1);
+    double e0[3], e1[3], e2[3], l0[3], l1[3], l2[3], r0[3], r1[3], r2[3];
+    gks_avg_psi(&u1, mc.um, mc.xm, e0);
+    gks_avg_psi(&c_a, mc.um, mc.xm, e1);
+    gks_avg_psi(&c_A, mc.um, mc.xm, e2);
+    gks_avg_psi(&u1, ml.up, ml.xm, l0);
+    gks_avg_psi(&l_a, ml.up, ml.xm, l1);
+    gks_avg_psi(&l_A, ml.up, ml.xm, l2);
+    gks_avg_psi(&u1, mr.un, mr.xm, r0);
+    gks_avg_psi(&r_a, mr.un, mr.xm, r1);
+    gks_avg_psi(&r_A, mr.un, mr.xm, r2);
+    for (int j = 0; j < 3; ++j) {
+        double fc = mc.rho * (q[0] * e0[j] + q[1] * e1[j] + q[2] * e2[j]);
+        double fl = ml.rho * (q[3] * l0[j] - q[4] * l1[j] - q[5] * l2[j]);
+        double fr = mr.rho * (q[3] * r0[j] - q[4] * r1[j] - q[5] * r2[j]);
+        F[j] = fc + fl + fr;
+    }
+    return 0;
+}
+
+/* Numerical collision time of inviscid flow (Sec. 2.2):                     */
+/*   tau_n = C1 dt + C2 |p_l - p_r| / (p_l + p_r) dt.                         */
+/* Reading: the collision time outside the exponentials is the physical one, */
+/* 0 for the Euler equations (gk->tau).                                     */
+static double gks_taun(double gamma, const orc_gks *gk, const double *Wl, const double *Wr, double dt)
+{
+    double pl = (gamma - 1.0) * (Wl[2] - 0.5 * Wl[1] * Wl[1] / Wl[0]);
+    double pr = (gamma - 1.0) * (Wr[2] - 0.5 * Wr[1] * Wr[1] / Wr[0]);
+    return gk->c1 * dt + gk->c2 * fabs(pl - pr) / (pl + pr) * dt;
+}
+
+/* Flux and its time derivative at t_n from the two transported fluxes     */
+/* (Eq. time advance): F = (4 F(dt/2) - F(dt))/dt,                          */
+/* F_t = 4 (F(dt) - 2 F(dt/2)) / dt^2.                                       */
+static int gks_point(double gamma, const orc_gks *gk, double dt, const double *Wl, const double *Wlx,
+                     const double *Wr, const double *Wrx, double *Fn, double *Ft)
+{
+    double taun = gks_taun(gamma, gk, Wl, Wr, dt);
+    double F1[3], F2[3];
+    if (gks_flux_int(gamma, Wl, Wlx, Wr, Wrx, gk->tau, taun, dt, F1)) return -1;
+    if (gks_flux_int(gamma, Wl, Wlx, Wr, Wrx, gk->tau, taun, 0.5 * dt, F2)) return -1;
+    for (int j = 0; j < 3; ++j) {
+        Fn[j] = (4.0 * F2[j] - F1[j]) / dt;
+        Ft[j] = 4.0 * (F1[j] - 2.0 * F2[j]) / (dt * dt);
+    }
+    return 0;
+}
+
+/* L(W) and dL/dt on the interior cells of a 1D grid (Sec. 2.2):            */
+/*   per face i+1/2: the ASE-DF polynomial of cell i at xi = 0 and of cell   */
+/*   i+1 at xi = -1 give W^l, W^r and their slopes (d/dxi / dx); the face    */
+/*   strength is the DF strength of (W^l, W^r) (as on the LF path); with    */
+/*   positivity_fallback a non-physical side becomes its cell average with  */
+/*   zero slope (reading, as R15); then F, F_t (gks_point) and               */
+/*   L = -(F_{i+1/2} - F_{i-1/2})/dx, L_t likewise.                          */
+static int residual_gks1d(const orc_grid *g, const orc_params *p, const orc_gks *gk, const double *U,
+                          const double *sx, double dt, double *L, double *Lt, double *sx_new)
+{
+    int r = p->order, R = halfwidth(r), ng = g->ng, nx = g->nx;
+    size_t P = plane(g);
+    double *F = malloc((size_t)3 * (nx + 1) * sizeof(double));
+    double *FT = malloc((size_t)3 * (nx + 1) * sizeof(double));
+    if (!F || !FT) { free(F); free(FT); return -1; }
+    int rc = 0;
+    for (int a = -1; a < nx; ++a) {
+        int Il = a + ng, Ir = a + 1 + ng;
+        double Wl[3], Wr[3], Wlx[3], Wrx[3], Wlc[3], Wrc[3];
+        for (int v = 0; v < 3; ++v) {
+            double Wline[9], sline[8], out, dout;
+            const double xr = 0.0, xl = -1.0;
+            for (int m = -R; m <= R; ++m) Wline[m + R] = U[v * P + Il + m];
+            for (int m = -R; m < R; ++m) sline[m + R] = sx[Il + m];
+            ase_poly(p, r, Wline + R, sline + R, 1, &xr, &out, &dout);
+            Wl[v] = out;
+            Wlx[v] = dout / g->dx;
+            for (int m = -R; m <= R; ++m) Wline[m + R] = U[v * P + Ir + m];
+            for (int m = -R; m < R; ++m) sline[m + R] = sx[Ir + m];
+            ase_poly(p, r, Wline + R, sline + R, 1, &xl, &out, &dout);
+            Wr[v] = out;
+            Wrx[v] = dout / g->dx;
+            Wlc[v] = U[v * P + Il];
+            Wrc[v] = U[v * P + Ir];
+        }
+        prim_t ql, qr;
+        int okl = primitives(g, p, Wl, 0, &ql);
+        int okr = primitives(g, p, Wr, 0, &qr);
+        if (sx_new) sx_new[Il] = sigma_point(&ql, okl, &qr, okr);
+        if (p->positivity_fallback) {
+            if (okl != 0) for (int v = 0; v < 3; ++v) { Wl[v] = Wlc[v]; Wlx[v] = 0.0; }
+            if (okr != 0) for (int v = 0; v < 3; ++v) { Wr[v] = Wrc[v]; Wrx[v] = 0.0; }
+        }
+        double Fn[3], Ft[3];
+        if (gks_point(p->gamma, gk, dt, Wl, Wlx, Wr, Wrx, Fn, Ft)) {
+            for (int v = 0; v < 3; ++v) Fn[v] = Ft[v] = NAN;
+            rc = 1;
+        }
+        for (int v = 0; v < 3; ++v) {
+            F[(size_t)v * (nx + 1) + (a + 1)] = Fn[v];
+            FT[(size_t)v * (nx + 1) + (a + 1)] = Ft[v];
+        }
+    }
+    for (int i = 0; i < nx; ++i)
+        for (int v = 0; v < 3; ++v) {
+            size_t c = (size_t)v * P + (size_t)(i + ng);
+            L[c] = -(F[(size_t)v * (nx + 1) + (i + 1)] - F[(size_t)v * (nx + 1) + i]) / g->dx;
+            Lt[c] = -(FT[(size_t)v * (nx + 1) + (i + 1)] - FT[(size_t)v * (nx + 1) + i]) / g->dx;
+        }
+    free(F);
+    free(FT);
+    (void)rc;   /* non-physical states propagate as NaN */
+    return 0;
+}
+
+/* nsteps S2O4 steps (Eq. S2O4 temporal) of the 1D GKS solver:               */
+/*   W*      = W^n + dt/2 L(W^n) + dt^2/8 L_t(W^n)                           */
+/*   W^{n+1} = W^n + dt L(W^n) + dt^2/6 (L_t(W^n) + 2 L_t(W*)).              */
+/* The DF state is lagged across the two stages as on the LF path (R9).     */
+/* Returns the number of steps taken, or < 0 on error.                       */
+int orc_step_gks(const orc_grid *g, const orc_params *p, const orc_gks *gk, double *U, double *sx, double *t,
+                 int nsteps, double t_end, double *dt_hist)
+{
+    int e = check_args(g, p);
+    if (e) return e;
+    if (g->dim != 1) return -1;
+    size_t P = plane(g), n = 3 * P;
+    double *Ws = malloc(n * sizeof(double)), *L0 = calloc(n, sizeof(double)), *T0 = calloc(n, sizeof(double));
+    double *L1 = calloc(n, sizeof(double)), *T1 = calloc(n, sizeof(double)), *sxa = malloc(P * sizeof(double));
+    if (!Ws || !L0 || !T0 || !L1 || !T1 || !sxa) {
+        free(Ws); free(L0); free(T0); free(L1); free(T1); free(sxa);
+        return -1;
+    }
+    int taken = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        if (t_end > 0.0 && *t >= t_end) break;
+        stage_bc(g, p, U, sx, NULL);
+        double dt = cfl_dt(g, p, U, *t, t_end);
+        memcpy(Ws, U, n * sizeof(double));
+        memcpy(sxa, sx, P * sizeof(double));
+        residual_gks1d(g, p, gk, U, sx, dt, L0, T0, sxa);
+        for (int v = 0; v < 3; ++v)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t c = (size_t)v * P + (size_t)(i + g->ng);
+                Ws[c] = U[c] + 0.5 * dt * L0[c] + 0.125 * dt * dt * T0[c];
+            }
+        stage_bc(g, p, Ws, sxa, NULL);
+        residual_gks1d(g, p, gk, Ws, sxa, dt, L1, T1, sx);
+        for (int v = 0; v < 3; ++v)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t c = (size_t)v * P + (size_t)(i + g->ng);
+                U[c] = U[c] + dt * L0[c] + dt * dt / 6.0 * (T0[c] + 2.0 * T1[c]);
+            }
+        *t += dt;
+        if (dt_hist) dt_hist[s] = dt;
+        ++taken;
+    }
+    free(Ws); free(L0); free(T0); free(L1); free(T1); free(sxa);
+    return taken;
+}
+
+/* L and L_t of one stage (ghosts and strengths filled inside, as            */
+/* orc_residual); sx_new receives the face strengths (may be NULL).          */
+int orc_residual_gks(const orc_grid *g, const orc_params *p, const orc_gks *gk, double *U, double *sx,
+                     double dt, double *L, double *Lt, double *sx_new)
+{
+    int e = check_args(g, p);
+    if (e) return e;
+    if (g->dim != 1) return -1;
+    stage_bc(g, p, U, sx, NULL);
+    return residual_gks1d(g, p, gk, U, sx, dt, L, Lt, sx_new);
+}
+
+/* Test hooks of the kinetic pieces. */
+int orc_gks_moments(double gamma, const double *W, double *um, double *up, double *un, double *xm)
+{
+    gks_maxw m;
+    if (gks_maxwellian(gamma, W, &m)) return -1;
+    memcpy(um, m.um, sizeof m.um);
+    memcpy(up, m.up, sizeof m.up);
+    memcpy(un, m.un, sizeof m.un);
+    memcpy(xm, m.xm, sizeof m.xm);
+    return GKS_NU;
+}
+
+int orc_gks_slopes(double gamma, const double *W, const double *Wx, double *a, double *A)
+{
+    gks_maxw m;
+    if (gks_maxwellian(gamma, W, &m)) return -1;
+    gks_slopes(&m, Wx, a, A);
+    return 0;
+}
+
+int orc_gks_flux(double gamma, const double *Wl, const double *Wlx, const double *Wr, const double *Wrx,
+                 double tau, double taun, double delta, double *F)
+{
+    return gks_flux_int(gamma, Wl, Wlx, Wr, Wrx, tau, taun, delta, F);
+}
+
+int orc_gks_point(double gamma, const orc_gks *gk, double dt, const double *Wl, const double *Wlx,
+                  const double *Wr, const double *Wrx, double *Fn, double *Ft)
+{
+    return gks_point(gamma, gk, dt, Wl, Wlx, Wr, Wrx, Fn, Ft);
+}
+
+/* ASE-DF polynomial and its xi-derivative at npts points. */
+int orc_poly_d(const orc_params *p, const double *W, const double *s, int npts, const double *xi, double *out,
+               double *dout)
+{
+    int R = halfwidth(p->order);
+    return ase_poly(p, p->order, W + R, s + R, npts, xi, out, dout);
 }

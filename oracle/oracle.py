@@ -69,6 +69,13 @@ def lib():
         L.orc_sigma_point.restype = C.c_double
         L.orc_lf_point.argtypes = [vp, vp, _dp, _dp, C.c_int, _dp]
         L.orc_lf_point.restype = None
+        L.orc_step_gks.argtypes = [vp, vp, vp, _dp, _dp, _dp, C.c_int, C.c_double, _dp]
+        L.orc_residual_gks.argtypes = [vp, vp, vp, _dp, _dp, C.c_double, _dp, _dp, _dp]
+        L.orc_gks_moments.argtypes = [C.c_double, _dp, _dp, _dp, _dp, _dp]
+        L.orc_gks_slopes.argtypes = [C.c_double, _dp, _dp, _dp, _dp]
+        L.orc_gks_flux.argtypes = [C.c_double, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_gks_point.argtypes = [C.c_double, vp, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_poly_d.argtypes = [vp, _dp, _dp, C.c_int, _dp, _dp, _dp]
     return _LIB
 
 
@@ -261,3 +268,81 @@ def lf_point(g, p, Wl, Wr, d):
     G, P = _gp(g, p)
     lib().orc_lf_point(G, P, _ptr(Wl), _ptr(Wr), d, _ptr(F))
     return F
+
+
+# ---- gas-kinetic solver (1D) -------------------------------------------------
+
+class OrcGks(C.Structure):
+    _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("tau", C.c_double)]
+
+
+def c_gks(c1, c2, tau=0.0) -> OrcGks:
+    return OrcGks(float(c1), float(c2), float(tau))
+
+
+def _vec(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def step_gks(g, p, U, sx, t, nsteps, t_end=0.0, c1=0.05, c2=1.0, tau=0.0):
+    """S2O4 GKS steps in place (1D); returns (t, dt history)."""
+    tt = C.c_double(t)
+    hist = np.zeros(max(nsteps, 1))
+    G, P = _gp(g, p)
+    K = c_gks(c1, c2, tau)
+    n = _check(lib().orc_step_gks(G, P, C.byref(K), _ptr(U), _ptr(sx), C.byref(tt), nsteps, t_end,
+                                  _ptr(hist)), "step_gks")
+    return tt.value, hist[:n]
+
+
+def run_gks(g, p, U, nsteps, t_end=0.0, c1=0.05, c2=1.0, tau=0.0):
+    U = U.copy()
+    sx, _ = sigma_init(g, p, U)
+    t, dts = step_gks(g, p, U, sx, 0.0, nsteps, t_end, c1, c2, tau)
+    return U, sx, t, dts
+
+
+def residual_gks(g, p, U, sx, dt, c1=0.05, c2=1.0, tau=0.0):
+    """L, L_t at interior cells and the face strengths of one GKS stage."""
+    L = np.zeros(g.shape())
+    Lt = np.zeros(g.shape())
+    sxn = sx.copy()
+    G, P = _gp(g, p)
+    K = c_gks(c1, c2, tau)
+    _check(lib().orc_residual_gks(G, P, C.byref(K), _ptr(U), _ptr(sx), dt, _ptr(L), _ptr(Lt), _ptr(sxn)),
+           "residual_gks")
+    return L, Lt, sxn
+
+
+def gks_moments(gamma, W):
+    um, up, un, xm = np.zeros(8), np.zeros(8), np.zeros(8), np.zeros(3)
+    _check(lib().orc_gks_moments(gamma, _ptr(_vec(W)), _ptr(um), _ptr(up), _ptr(un), _ptr(xm)), "gks_moments")
+    return um, up, un, xm
+
+
+def gks_slopes(gamma, W, Wx):
+    a, A = np.zeros(3), np.zeros(3)
+    _check(lib().orc_gks_slopes(gamma, _ptr(_vec(W)), _ptr(_vec(Wx)), _ptr(a), _ptr(A)), "gks_slopes")
+    return a, A
+
+
+def gks_flux(gamma, Wl, Wlx, Wr, Wrx, tau, taun, delta):
+    F = np.zeros(3)
+    _check(lib().orc_gks_flux(gamma, _ptr(_vec(Wl)), _ptr(_vec(Wlx)), _ptr(_vec(Wr)), _ptr(_vec(Wrx)),
+                              tau, taun, delta, _ptr(F)), "gks_flux")
+    return F
+
+
+def gks_point(gamma, dt, Wl, Wlx, Wr, Wrx, c1=0.05, c2=1.0, tau=0.0):
+    Fn, Ft = np.zeros(3), np.zeros(3)
+    K = c_gks(c1, c2, tau)
+    _check(lib().orc_gks_point(gamma, C.byref(K), dt, _ptr(_vec(Wl)), _ptr(_vec(Wlx)), _ptr(_vec(Wr)),
+                               _ptr(_vec(Wrx)), _ptr(Fn), _ptr(Ft)), "gks_point")
+    return Fn, Ft
+
+
+def poly_d(p, W, s, xi):
+    W, s, xi = _vec(W), _vec(s), _vec(xi)
+    out, dout = np.zeros(len(xi)), np.zeros(len(xi))
+    lvl = lib().orc_poly_d(C.byref(c_params(p)), _ptr(W), _ptr(s), len(xi), _ptr(xi), _ptr(out), _ptr(dout))
+    return out, dout, lvl
