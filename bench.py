@@ -143,6 +143,88 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def alg_flops_per_cell_gks_stage(order: int) -> float:
+    """Algorithmic FP64 operations per cell of one S2O4 stage of the 1D
+    gas-kinetic path (FMA = 2; divide, square root, exp and erfc = 1 each):
+      reconstruction      : DF sums + 2 faces x 3 vars x (2r-1) for values
+                            and again for slopes
+      strength            : primitives of both sides 2 x 12, strength 14
+      kinetic face flux   : three Maxwellians 21, whole-line moments to
+                            <u^6> 3 x 21, half-line moments 2 x 37, xi
+                            moments 18, micro slopes and time slopes 3 x 70,
+                            kinetic averages W^c, W^c_x 138, nine moment
+                            terms 9 x 30, tau_n 10, two time integrals
+                            2 x 83, F and F_t 22                -> 992
+      update              : L, L_t and the stage combination    -> 30
+    """
+    R = (order - 1) // 2
+    sums = {1: 1, 2: 3, 3: 8, 4: 15}[R]
+    recon = sums + 2 * 2 * 3 * (2 * order - 1)
+    return recon + 2 * 12 + 14 + 992 + 30
+
+
+def bench_gks(args):
+    """1D gas-kinetic solver (S2O4 steps): Shu-Osher-type data on 2^20
+    cells, order 9, one grid resident in HBM."""
+    import torch
+    from paper_2410_05489_amd import ase
+    from paper_2410_05489_amd import workloads as WL
+
+    n = 1 << 20
+    w = WL.shu_osher(n, 9)
+    g, p = w.grid, w.params
+    c1, c2 = 0.05, 1.0
+    sim = ase.GksSimulation(g, p, w.U, c1=c1, c2=c2, device="cuda")
+    sim.run(args.warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    sim.run(args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    finite = bool(torch.isfinite(sim.U).all().item())
+    prof_steps = max(1, min(args.steps, 50))
+    ase.profile_enable(True)
+    sim.run(prof_steps)
+    torch.cuda.synchronize()
+    kern = {k: ase.profile_read(k) for k in ("gks_1d", "bc", "cfl")}
+    ase.profile_enable(False)
+    value = n * args.steps / (ms / 1e3) / 1e6
+    tot, nl = kern["gks_1d"]
+    avg_s = tot / max(nl, 1) / 1e3
+    flops = alg_flops_per_cell_gks_stage(p.order)
+    achieved = flops * n / avg_s / 1e12
+    bytes_cell = (14 + 17) / 2 * 8.0   # stage 1: 14 words per cell, stage 2: 17
+    out = {"metric": "Mcell-updates/s, 1D gas-kinetic S2O4 step, order 9 (FP64)", "value": round(value, 3),
+           "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms / args.steps, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"gks_shu_osher_{n}_r9", "order": 9, "nx": n, "c1": c1, "c2": c2,
+                      "cfl": p.cfl},
+           "finite": finite,
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": "k_gks1d, order 9", "avg_launch_ms": round(avg_s * 1e3, 4), "launches": nl,
+                        "alg_flops_per_launch": flops * n, "alg_bytes_per_launch": bytes_cell * n,
+                        "hbm_frac_alg": round(bytes_cell * n / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                        "kernel_ms_per_step": {k: round(v[0] / prof_steps, 4) for k, v in kern.items() if v[1]}}}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        m = 1 << 18
+        ws = WL.shu_osher(m, 9)
+        U = ws.U.copy()
+        sx, _ = O.sigma_init(ws.grid, ws.params, U)
+        t0 = time.perf_counter()
+        O.step_gks(ws.grid, ws.params, U, sx, 0.0, 1, c1=c1, c2=c2)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m / el / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"1 S2O4 step of the same problem on {m} cells, single-threaded C "
+                                         f"oracle, {el:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def measure_adjoint(nsteps=100, every=10, reps=3):
     """Adjoint/forward wall-time ratio on the batched workload: 256 Riemann
     instances of 64..4096 cells, order 9, `nsteps` steps; J = sum_k dx_k sum p
@@ -247,6 +329,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "gks1d":
+        return bench_gks(args)
     if args.workload == "adjoint":
         print(json.dumps({"metric": "adjoint/forward wall-time ratio, batched 1D order 9", **measure_adjoint()}),
               flush=True)

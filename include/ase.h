@@ -196,6 +196,41 @@ size_t ase_workspace_bytes(const ase_grid_t *g, const ase_params_t *p);
 int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, double *t,
              double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Gas-kinetic solver, 1D (Sec. 2.2, App. A) -----------------------------
+ * The paper's primary flux: the moments of the second-order BGK distribution
+ * at the interface (Eq. GKS flux) integrated over the time step, with the
+ * two-stage fourth-order time stepping (Eq. S2O4 temporal).  The
+ * reconstruction (values and x-slopes of the ASE-DF polynomials at the
+ * faces) and the DF state are those of the Lax-Friedrichs path. */
+typedef struct {
+    double c1, c2;  /* numerical collision time tau_n = c1 dt + c2 |p_l - p_r| / (p_l + p_r) dt */
+    double tau;     /* collision time outside the exponentials: 0 for the Euler equations */
+} ase_gks_t;
+
+/* Flux F and its time derivative F_t at t_n of n independent faces
+ * (Eq. time advance): from the transported fluxes over [0, dt] and
+ * [0, dt/2] of the BGK distribution built on the interface states Wl, Wr
+ * (1D conservative (rho, rho u, E)) and their x-slopes Wlx, Wrx.  All
+ * arrays are device [3][n] (variable-major); p supplies gamma.  A face with
+ * a non-physical state (rho <= 0 or p <= 0, also of the kinetic average)
+ * gets NaN. */
+int ase_gks_flux(const ase_params_t *p, const ase_gks_t *gk, int32_t n, const double *Wl, const double *Wlx,
+                 const double *Wr, const double *Wrx, double dt, double *Fn, double *Ft, void *stream);
+
+/* nsteps S2O4 steps of the 1D gas-kinetic solver (Eq. S2O4 temporal):
+ * W* = W^n + dt/2 L(W^n) + dt^2/8 L_t(W^n),
+ * W^{n+1} = W^n + dt L(W^n) + dt^2/6 (L_t(W^n) + 2 L_t(W*)),
+ * L and L_t the divergences of F and F_t.  Per step: boundary fill, dt
+ * (CFL rule of ase_cfl_dt), two stage launches with a boundary fill
+ * between.  The DF state is lagged across the stages as in ase_step (or
+ * first order with ASE_FLAG_DF_FIRST_ORDER); with
+ * ASE_FLAG_POSITIVITY_FALLBACK a non-physical interface state becomes its
+ * cell average with zero slope.  Arguments as ase_step (1D grids only,
+ * ASE_ERR_ARG otherwise; ws_bytes >= ase_workspace_bytes(g, p)). */
+int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk, double *U, double *sx,
+                 double *t, double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes,
+                 void *stream);
+
 /* ---- Batched 1D instances (one persistent launch) -------------------------
  * Many independent 1D problems of uneven size stored back to back:
  * instance k occupies stored cells [offsets[k], offsets[k] + ncells[k] +
@@ -315,7 +350,8 @@ int ase_pressure_objective(const ase_params_t *p, int32_t ninst, const int64_t *
  * duration in milliseconds and the number of launches of one kernel class
  * (ASE_KCLASS_*); it does not clear the record. */
 enum { ASE_KCLASS_SWEEP_X = 0, ASE_KCLASS_SWEEP_Y = 1, ASE_KCLASS_STAGE_1D = 2, ASE_KCLASS_BC = 3,
-       ASE_KCLASS_CFL = 4, ASE_KCLASS_BATCHED = 5, ASE_KCLASS_ADJOINT = 6, ASE_KCLASS_COUNT = 7 };
+       ASE_KCLASS_CFL = 4, ASE_KCLASS_BATCHED = 5, ASE_KCLASS_ADJOINT = 6, ASE_KCLASS_GKS_1D = 7,
+       ASE_KCLASS_COUNT = 8 };
 int ase_profile_enable(int on);
 int ase_profile_read(int kernel_class, double *total_ms, int64_t *launches);
 

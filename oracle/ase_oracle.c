@@ -1604,3 +1604,517 @@ int orc_poly_d(const orc_params *p, const double *W, const double *s, int npts, 
     int R = halfwidth(p->order);
     return ase_poly(p, p->order, W + R, s + R, npts, xi, out, dout);
 }
+
+/* ======================================================================== */
+/* Gas-kinetic flux and S2O4 stepping, 2D (Sec. 2.1-2.2, App. A).           */
+/*                                                                          */
+/* Local frame of a face: u along the normal, v along the face;             */
+/* psi = (1, u, v, (u^2 + v^2 + xi^2)/2), K = (4 - 2 gamma)/(gamma - 1).     */
+/* Polynomials in (u, v, xi^2) are coefficient tables c[n][m][l] of         */
+/* u^n v^m xi^(2l); <c> = sum c <u^n> <v^m> <xi^(2l)> (App. A), the half    */
+/* lines taken in u only.                                                   */
+/* ======================================================================== */
+
+enum { G2_N = 8, G2_L = 3 };
+typedef struct { double c[G2_N][G2_N][G2_L]; } vpoly;
+
+typedef struct {
+    double rho, U, V, lam, K;
+    double um[G2_N], up[G2_N], un[G2_N];
+    double vm[G2_N];
+    double xm[G2_L];
+    double M[4][4];      /* <psi_i psi_j>, filled by g2_maxwellian */
+} g2_maxw;
+
+static vpoly g2_psi(int j);
+static vpoly g2_mul(const vpoly *x, const vpoly *y);
+static double g2_avg(const vpoly *q, const double *um, const g2_maxw *mw);
+
+/* Maxwellian of the local-frame state W = (rho, rho U, rho V, E). */
+static int g2_maxwellian(double gamma, const double *W, g2_maxw *m)
+{
+    double rho = W[0];
+    double U = W[1] / rho, V = W[2] / rho;
+    double p = (gamma - 1.0) * (W[3] - 0.5 * rho * (U * U + V * V));
+    if (!(rho > 0.0) || !(p > 0.0)) return -1;
+    m->rho = rho;
+    m->U = U;
+    m->V = V;
+    m->lam = rho / (2.0 * p);
+    m->K = (4.0 - 2.0 * gamma) / (gamma - 1.0);
+    double lam = m->lam;
+    const double pi = 3.14159265358979323846;
+    m->um[0] = 1.0;
+    m->um[1] = U;
+    m->vm[0] = 1.0;
+    m->vm[1] = V;
+    m->up[0] = 0.5 * erfc(-sqrt(lam) * U);
+    m->un[0] = 0.5 * erfc(sqrt(lam) * U);
+    double e = exp(-lam * U * U) / (2.0 * sqrt(pi * lam));
+    m->up[1] = U * m->up[0] + e;
+    m->un[1] = U * m->un[0] - e;
+    for (int n = 0; n + 2 < G2_N; ++n) {
+        double h = (double)(n + 1) / (2.0 * lam);
+        m->um[n + 2] = U * m->um[n + 1] + h * m->um[n];
+        m->up[n + 2] = U * m->up[n + 1] + h * m->up[n];
+        m->un[n + 2] = U * m->un[n + 1] + h * m->un[n];
+        m->vm[n + 2] = V * m->vm[n + 1] + h * m->vm[n];
+    }
+    m->xm[0] = 1.0;
+    for (int l = 1; l < G2_L; ++l) m->xm[l] = (m->K + 2.0 * (l - 1)) / (2.0 * lam) * m->xm[l - 1];
+    for (int i = 0; i < 4; ++i) {
+        vpoly pi = g2_psi(i);
+        for (int j = 0; j < 4; ++j) {
+            vpoly pj = g2_psi(j);
+            vpoly t = g2_mul(&pi, &pj);
+            m->M[i][j] = g2_avg(&t, m->um, m);
+        }
+    }
+    return 0;
+}
+
+static vpoly g2_zero(void)
+{
+    vpoly q;
+    memset(&q, 0, sizeof q);
+    return q;
+}
+
+static vpoly g2_psi(int j)
+{
+    vpoly q = g2_zero();
+    if (j == 0) q.c[0][0][0] = 1.0;
+    else if (j == 1) q.c[1][0][0] = 1.0;
+    else if (j == 2) q.c[0][1][0] = 1.0;
+    else { q.c[2][0][0] = 0.5; q.c[0][2][0] = 0.5; q.c[0][0][1] = 0.5; }
+    return q;
+}
+
+static vpoly g2_lin(const double a[4])
+{
+    vpoly q = g2_zero();
+    for (int j = 0; j < 4; ++j) {
+        vpoly s = g2_psi(j);
+        for (int n = 0; n < G2_N; ++n)
+            for (int m = 0; m < G2_N; ++m)
+                for (int l = 0; l < G2_L; ++l) q.c[n][m][l] += a[j] * s.c[n][m][l];
+    }
+    return q;
+}
+
+/* Product of two polynomials (terms beyond the table's degrees must not   */
+/* arise: the callers stay within u^7, v^7, xi^4).                          */
+static vpoly g2_mul(const vpoly *x, const vpoly *y)
+{
+    int yi[G2_N * G2_N * G2_L][3], ny = 0;
+    for (int n = 0; n < G2_N; ++n)
+        for (int m = 0; m < G2_N; ++m)
+            for (int l = 0; l < G2_L; ++l)
+                if (y->c[n][m][l] != 0.0) { yi[ny][0] = n; yi[ny][1] = m; yi[ny][2] = l; ++ny; }
+    vpoly q = g2_zero();
+    for (int n = 0; n < G2_N; ++n)
+        for (int m = 0; m < G2_N; ++m)
+            for (int l = 0; l < G2_L; ++l) {
+                double xv = x->c[n][m][l];
+                if (xv == 0.0) continue;
+                for (int k = 0; k < ny; ++k) {
+                    int n2 = yi[k][0], m2 = yi[k][1], l2 = yi[k][2];
+                    if (n + n2 < G2_N && m + m2 < G2_N && l + l2 < G2_L)
+                        q.c[n + n2][m + m2][l + l2] += xv * y->c[n2][m2][l2];
+                }
+            }
+    return q;
+}
+
+static vpoly g2_add(const vpoly *x, const vpoly *y)
+{
+    vpoly q = *x;
+    for (int n = 0; n < G2_N; ++n)
+        for (int m = 0; m < G2_N; ++m)
+            for (int l = 0; l < G2_L; ++l) q.c[n][m][l] += y->c[n][m][l];
+    return q;
+}
+
+/* u^a v^b */
+static vpoly g2_mono(int a, int b)
+{
+    vpoly q = g2_zero();
+    q.c[a][b][0] = 1.0;
+    return q;
+}
+
+static double g2_avg(const vpoly *q, const double *um, const g2_maxw *mw)
+{
+    double s = 0.0;
+    for (int n = 0; n < G2_N; ++n)
+        for (int m = 0; m < G2_N; ++m)
+            for (int l = 0; l < G2_L; ++l) s += q->c[n][m][l] * um[n] * mw->vm[m] * mw->xm[l];
+    return s;
+}
+
+/* <q psi_j>, j = 0..3: each term c u^n v^m xi^(2l) of q times each term of */
+/* psi_j, averaged (the product written out term by term).                  */
+static void g2_avg_psi(const vpoly *q, const double *um, const g2_maxw *mw, double out[4])
+{
+    /* terms of psi_j: (coefficient, du, dv, dl) */
+    static const double pc[4][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}, {0.5, 0.5, 0.5}};
+    static const int pt[4][3][3] = {{{0, 0, 0}}, {{1, 0, 0}}, {{0, 1, 0}}, {{2, 0, 0}, {0, 2, 0}, {0, 0, 1}}};
+    static const int pn[4] = {1, 1, 1, 3};
+    for (int j = 0; j < 4; ++j) out[j] = 0.0;
+    for (int n = 0; n < G2_N; ++n)
+        for (int m = 0; m < G2_N; ++m)
+            for (int l = 0; l < G2_L; ++l) {
+                double c = q->c[n][m][l];
+                if (c == 0.0) continue;
+                for (int j = 0; j < 4; ++j)
+                    for (int k = 0; k < pn[j]; ++k) {
+                        int n2 = n + pt[j][k][0], m2 = m + pt[j][k][1], l2 = l + pt[j][k][2];
+                        if (n2 >= G2_N || m2 >= G2_N || l2 >= G2_L) continue;   /* never reached */
+                        out[j] += c * pc[j][k] * um[n2] * mw->vm[m2] * mw->xm[l2];
+                    }
+            }
+}
+
+/* M a = b with M_ij = <psi_i psi_j> (App. A), Gaussian elimination. */
+static void g2_solve(const g2_maxw *mw, const double b[4], double a[4])
+{
+    double M[4][5];
+    for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 4; ++j) M[i][j] = mw->M[i][j];
+        M[i][4] = b[i];
+    }
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+        if (piv != c)
+            for (int k = 0; k < 5; ++k) { double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t; }
+        for (int r = c + 1; r < 4; ++r) {
+            double f = M[r][c] / M[c][c];
+            for (int k = c; k < 5; ++k) M[r][k] -= f * M[c][k];
+        }
+    }
+    for (int c = 3; c >= 0; --c) {
+        double s = M[c][4];
+        for (int k = c + 1; k < 4; ++k) s -= M[c][k] * a[k];
+        a[c] = s / M[c][c];
+    }
+}
+
+/* Normal and tangential slopes an, at from W_n, W_t and the time slope A  */
+/* from <A + an u + at v> = 0.                                              */
+static void g2_slopes(const g2_maxw *mw, const double *Wn, const double *Wt, double an[4], double at[4],
+                      double A[4])
+{
+    double b[4];
+    for (int j = 0; j < 4; ++j) b[j] = Wn[j] / mw->rho;
+    g2_solve(mw, b, an);
+    for (int j = 0; j < 4; ++j) b[j] = Wt[j] / mw->rho;
+    g2_solve(mw, b, at);
+    vpoly pn = g2_lin(an), pt = g2_lin(at), u1 = g2_mono(1, 0), v1 = g2_mono(0, 1);
+    vpoly x = g2_mul(&pn, &u1), y = g2_mul(&pt, &v1);
+    vpoly s = g2_add(&x, &y);
+    double bt[4];
+    g2_avg_psi(&s, mw->um, mw, bt);
+    for (int j = 0; j < 4; ++j) bt[j] = -bt[j];
+    g2_solve(mw, bt, A);
+}
+
+/* Transported flux over [0, delta] at one Gauss point in the local frame   */
+/* (Eq. GKS flux with a . u = a_n u + a_t v).                                */
+static int g2_flux_int(double gamma, const double *Wl, const double *Wln, const double *Wlt, const double *Wr,
+                       const double *Wrn, const double *Wrt, double tau, double taun, double delta, double *F)
+{
+    g2_maxw ml, mr, mc;
+    if (g2_maxwellian(gamma, Wl, &ml) || g2_maxwellian(gamma, Wr, &mr)) return -1;
+    double lan[4], lat[4], lA[4], ran[4], rat[4], rA[4];
+    g2_slopes(&ml, Wln, Wlt, lan, lat, lA);
+    g2_slopes(&mr, Wrn, Wrt, ran, rat, rA);
+    vpoly one = g2_mono(0, 0), u1 = g2_mono(1, 0), v1 = g2_mono(0, 1);
+    double Wc[4], Wcn[4], Wct[4], t1[4], t2[4];
+    g2_avg_psi(&one, ml.up, &ml, t1);
+    g2_avg_psi(&one, mr.un, &mr, t2);
+    for (int j = 0; j < 4; ++j) Wc[j] = ml.rho * t1[j] + mr.rho * t2[j];
+    vpoly p1 = g2_lin(lan), p2 = g2_lin(ran);
+    g2_avg_psi(&p1, ml.up, &ml, t1);
+    g2_avg_psi(&p2, mr.un, &mr, t2);
+    for (int j = 0; j < 4; ++j) Wcn[j] = ml.rho * t1[j] + mr.rho * t2[j];
+    p1 = g2_lin(lat);
+    p2 = g2_lin(rat);
+    g2_avg_psi(&p1, ml.up, &ml, t1);
+    g2_avg_psi(&p2, mr.un, &mr, t2);
+    for (int j = 0; j < 4; ++j) Wct[j] = ml.rho * t1[j] + mr.rho * t2[j];
+    if (g2_maxwellian(gamma, Wc, &mc)) return -1;
+    double can[4], cat[4], cA[4];
+    g2_slopes(&mc, Wcn, Wct, can, cat, cA);
+    double q[6];
+    gks_time_coef(tau, taun, delta, q);
+
+    /* (a_n . psi) u + (a_t . psi) v, times u; and (A . psi) u */
+    const double *an[3] = {can, lan, ran}, *at[3] = {cat, lat, rat}, *AA[3] = {cA, lA, rA};
+    const g2_maxw *mm[3] = {&mc, &ml, &mr};
+    const double *um[3] = {mc.um, ml.up, mr.un};
+    double T0[3][4], T1[3][4], T2[3][4];
+    for (int s = 0; s < 3; ++s) {
+        vpoly pn = g2_lin(an[s]), pt = g2_lin(at[s]), pA = g2_lin(AA[s]);
+        vpoly x = g2_mul(&pn, &u1), y = g2_mul(&pt, &v1);
+        vpoly av = g2_add(&x, &y);
+        vpoly avu = g2_mul(&av, &u1), Au = g2_mul(&pA, &u1);
+        g2_avg_psi(&u1, um[s], mm[s], T0[s]);
+        g2_avg_psi(&avu, um[s], mm[s], T1[s]);
+        g2_avg_psi(&Au, um[s], mm[s], T2[s]);
+    }
+    for (int j = 0; j < 4; ++j) {
+        double fc = mc.rho * (q[0] * T0[0][j] + q[1] * T1[0][j] + q[2] * T2[0][j]);
+        double fl = ml.rho * (q[3] * T0[1][j] - q[4] * T1[1][j] - q[5] * T2[1][j]);
+        double fr = mr.rho * (q[3] * T0[2][j] - q[4] * T1[2][j] - q[5] * T2[2][j]);
+        F[j] = fc + fl + fr;
+    }
+    return 0;
+}
+
+/* F and F_t at t_n at one Gauss point (local frame), Eq. time advance.     */
+static int g2_point(double gamma, const orc_gks *gk, double dt, const double *Wl, const double *Wln,
+                    const double *Wlt, const double *Wr, const double *Wrn, const double *Wrt, double *Fn,
+                    double *Ft)
+{
+    double pl = (gamma - 1.0) * (Wl[3] - 0.5 * (Wl[1] * Wl[1] + Wl[2] * Wl[2]) / Wl[0]);
+    double pr = (gamma - 1.0) * (Wr[3] - 0.5 * (Wr[1] * Wr[1] + Wr[2] * Wr[2]) / Wr[0]);
+    double taun = gk->c1 * dt + gk->c2 * fabs(pl - pr) / (pl + pr) * dt;
+    double F1[4], F2[4];
+    if (g2_flux_int(gamma, Wl, Wln, Wlt, Wr, Wrn, Wrt, gk->tau, taun, dt, F1)) return -1;
+    if (g2_flux_int(gamma, Wl, Wln, Wlt, Wr, Wrn, Wrt, gk->tau, taun, 0.5 * dt, F2)) return -1;
+    for (int j = 0; j < 4; ++j) {
+        Fn[j] = (4.0 * F2[j] - F1[j]) / dt;
+        Ft[j] = 4.0 * (F1[j] - 2.0 * F2[j]) / (dt * dt);
+    }
+    return 0;
+}
+
+/* Rotation into the local frame of a face with normal (c, s) (Sec. 2.1):   */
+/* (rho, rho(u c + v s), rho(-u s + v c), E); back with the transpose.       */
+static void rot_in(int c, int s, const double *W, double *Wt)
+{
+    Wt[0] = W[0];
+    Wt[1] = c * W[1] + s * W[2];
+    Wt[2] = -s * W[1] + c * W[2];
+    Wt[3] = W[3];
+}
+
+static void rot_out(int c, int s, const double *Ft, double *F)
+{
+    F[0] = Ft[0];
+    F[1] = c * Ft[1] - s * Ft[2];
+    F[2] = s * Ft[1] + c * Ft[2];
+    F[3] = Ft[3];
+}
+
+/* One direction of the 2D GKS operator: face fluxes F and F_t (compact     */
+/* face numbering) and the face strengths.                                   */
+/*  1. normal reconstruction of the side cells on every row the tangential   */
+/*     stencils reach: values and normal slopes (d/dxi / h_n) at the face;   */
+/*  2. tangential reconstruction (reading R14 for the strengths) of the      */
+/*     values -- at the Gauss points, with the tangential slope d/deta/h_t   */
+/*     -- and of the normal slopes, as line averages with the same           */
+/*     polynomial rule (reading R28);                                        */
+/*  3. per Gauss point: strength, positivity fallback (value to the cell     */
+/*     average, slopes to zero), the flux in the local frame of normal       */
+/*     (cos, sin) = (1, 0) for x-faces, (0, 1) for y-faces, rotated back;    */
+/*     quadrature with the Gauss weights.                                    */
+static int sweep_gks2d(const orc_grid *g, const orc_params *p, const orc_gks *gk, int dir, const double *U,
+                       const double *sx, const double *sy, double dt, double *Fx, double *Ftx, double *sig_out)
+{
+    int r = p->order, R = halfwidth(r), ng = g->ng, nv = 4;
+    int G = ngauss(g, r);
+    size_t P = plane(g);
+    int ld = g->ld;
+    double node[4], eta[4], xi_g[4];
+    gauss_legendre(G, node, eta);
+    for (int k = 0; k < G; ++k) xi_g[k] = -0.5 + node[k];
+    const double hn = dir == 0 ? g->dx : g->dy, ht = dir == 0 ? g->dy : g->dx;
+    const int cs = dir == 0 ? 1 : 0, sn = dir == 0 ? 0 : 1;
+    int n_along = dir == 0 ? g->nx : g->ny;
+    int n_across = dir == 0 ? g->ny : g->nx;
+    size_t nf = (size_t)face_count(g, dir);
+#define CELL2(a, c) ((dir == 0) ? ((size_t)((c) + ng) * ld + (size_t)((a) + ng)) \
+                                : ((size_t)((a) + ng) * ld + (size_t)((c) + ng)))
+    const double *snorm = dir == 0 ? sx : sy;
+    const double *stang = dir == 0 ? sy : sx;
+    ptrdiff_t s_along = dir == 0 ? 1 : ld;
+    ptrdiff_t s_across = dir == 0 ? ld : 1;
+    for (int c = 0; c < n_across; ++c) {
+        for (int a = -1; a < n_along; ++a) {
+            /* per side: line values / normal slopes of rows c-R..c+R */
+            double V[2][4][9], S[2][4][9];
+            for (int side = 0; side < 2; ++side) {
+                int ac = a + side;
+                const double xq = side == 0 ? 0.0 : -1.0;
+                for (int m = -R; m <= R; ++m) {
+                    size_t base = CELL2(ac, c + m);
+                    for (int v = 0; v < nv; ++v) {
+                        double Wline[9], sline[8], out, dout;
+                        for (int k = -R; k <= R; ++k) Wline[k + R] = U[v * P + base + k * s_along];
+                        for (int k = -R; k < R; ++k) sline[k + R] = snorm[base + k * s_along];
+                        ase_poly(p, r, Wline + R, sline + R, 1, &xq, &out, &dout);
+                        V[side][v][m + R] = out;
+                        S[side][v][m + R] = dout / hn;
+                    }
+                }
+            }
+            double Wg[2][4][4], Wgn[2][4][4], Wgt[2][4][4];   /* [side][gauss][var] */
+            for (int side = 0; side < 2; ++side) {
+                size_t bc = CELL2(a + side, c);
+                double st[8];
+                for (int k = -R; k < R; ++k) st[k + R] = stang[bc + k * s_across];
+                for (int v = 0; v < nv; ++v) {
+                    double o[4], d[4], on[4];
+                    ase_poly(p, r, V[side][v] + R, st + R, G, xi_g, o, d);
+                    ase_poly(p, r, S[side][v] + R, st + R, G, xi_g, on, NULL);
+                    for (int k = 0; k < G; ++k) {
+                        Wg[side][k][v] = o[k];
+                        Wgt[side][k][v] = d[k] / ht;
+                        Wgn[side][k][v] = on[k];
+                    }
+                }
+            }
+            double Wcell[2][4];
+            for (int side = 0; side < 2; ++side)
+                for (int v = 0; v < nv; ++v) Wcell[side][v] = U[v * P + CELL2(a + side, c)];
+            double Fs[4] = {0, 0, 0, 0}, Fts[4] = {0, 0, 0, 0}, ssum = 0.0;
+            for (int k = 0; k < G; ++k) {
+                prim_t ql, qr;
+                int okl = primitives(g, p, Wg[0][k], dir, &ql);
+                int okr = primitives(g, p, Wg[1][k], dir, &qr);
+                ssum += sigma_point(&ql, okl, &qr, okr);
+                double *Wl = Wg[0][k], *Wr = Wg[1][k];
+                double *Wln = Wgn[0][k], *Wlt = Wgt[0][k], *Wrn = Wgn[1][k], *Wrt = Wgt[1][k];
+                double z[4] = {0, 0, 0, 0};
+                if (p->positivity_fallback) {
+                    if (okl != 0) { Wl = Wcell[0]; Wln = z; Wlt = z; }
+                    if (okr != 0) { Wr = Wcell[1]; Wrn = z; Wrt = z; }
+                }
+                /* local frame; the tangential direction is (-sin, cos) */
+                double lW[4], lWn[4], lWt[4], rW[4], rWn[4], rWt[4];
+                rot_in(cs, sn, Wl, lW);
+                rot_in(cs, sn, Wln, lWn);
+                rot_in(cs, sn, Wr, rW);
+                rot_in(cs, sn, Wrn, rWn);
+                double mt[4];
+                for (int v = 0; v < 4; ++v) mt[v] = (dir == 0 ? 1.0 : -1.0) * Wlt[v];
+                rot_in(cs, sn, mt, lWt);
+                for (int v = 0; v < 4; ++v) mt[v] = (dir == 0 ? 1.0 : -1.0) * Wrt[v];
+                rot_in(cs, sn, mt, rWt);
+                double fl[4], ftl[4], F[4], Ftk[4];
+                if (g2_point(p->gamma, gk, dt, lW, lWn, lWt, rW, rWn, rWt, fl, ftl)) {
+                    for (int v = 0; v < 4; ++v) fl[v] = ftl[v] = NAN;
+                }
+                rot_out(cs, sn, fl, F);
+                rot_out(cs, sn, ftl, Ftk);
+                for (int v = 0; v < 4; ++v) {
+                    Fs[v] += eta[k] * F[v];
+                    Fts[v] += eta[k] * Ftk[v];
+                }
+            }
+            int fi = dir == 0 ? a : c, fj = dir == 0 ? c : a;
+            size_t fid = face_index(g, dir, fi, fj);
+            for (int v = 0; v < nv; ++v) {
+                Fx[(size_t)v * nf + fid] = Fs[v];
+                Ftx[(size_t)v * nf + fid] = Fts[v];
+            }
+            if (sig_out) sig_out[CELL2(a, c)] = ssum / (double)G;
+        }
+    }
+#undef CELL2
+    return 0;
+}
+
+/* L and L_t of the 2D GKS operator on interior cells. */
+static int residual_gks2d(const orc_grid *g, const orc_params *p, const orc_gks *gk, const double *U,
+                          const double *sx, const double *sy, double dt, double *L, double *Lt, double *sx_new,
+                          double *sy_new)
+{
+    int ng = g->ng;
+    size_t P = plane(g);
+    size_t nfx = (size_t)face_count(g, 0), nfy = (size_t)face_count(g, 1);
+    double *Fx = malloc(4 * nfx * sizeof(double)), *Ftx = malloc(4 * nfx * sizeof(double));
+    double *Fy = malloc(4 * nfy * sizeof(double)), *Fty = malloc(4 * nfy * sizeof(double));
+    if (!Fx || !Ftx || !Fy || !Fty) { free(Fx); free(Ftx); free(Fy); free(Fty); return -1; }
+    sweep_gks2d(g, p, gk, 0, U, sx, sy, dt, Fx, Ftx, sx_new);
+    sweep_gks2d(g, p, gk, 1, U, sx, sy, dt, Fy, Fty, sy_new);
+    for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+            size_t c = (size_t)(j + ng) * g->ld + (size_t)(i + ng);
+            for (int v = 0; v < 4; ++v) {
+                size_t e = v * P + c;
+                size_t fxp = face_index(g, 0, i, j), fxm = face_index(g, 0, i - 1, j);
+                size_t fyp = face_index(g, 1, i, j), fym = face_index(g, 1, i, j - 1);
+                L[e] = -(Fx[v * nfx + fxp] - Fx[v * nfx + fxm]) / g->dx - (Fy[v * nfy + fyp] - Fy[v * nfy + fym]) / g->dy;
+                Lt[e] = -(Ftx[v * nfx + fxp] - Ftx[v * nfx + fxm]) / g->dx
+                        - (Fty[v * nfy + fyp] - Fty[v * nfy + fym]) / g->dy;
+            }
+        }
+    free(Fx); free(Ftx); free(Fy); free(Fty);
+    return 0;
+}
+
+/* nsteps S2O4 steps of the 2D GKS solver (as orc_step_gks). */
+int orc_step_gks2d(const orc_grid *g, const orc_params *p, const orc_gks *gk, double *U, double *sx, double *sy,
+                   double *t, int nsteps, double t_end, double *dt_hist)
+{
+    int e = check_args(g, p);
+    if (e) return e;
+    if (g->dim != 2) return -1;
+    size_t P = plane(g), n = 4 * P;
+    double *Ws = malloc(n * sizeof(double)), *L0 = calloc(n, sizeof(double)), *T0 = calloc(n, sizeof(double));
+    double *L1 = calloc(n, sizeof(double)), *T1 = calloc(n, sizeof(double));
+    double *sxa = malloc(P * sizeof(double)), *sya = malloc(P * sizeof(double));
+    if (!Ws || !L0 || !T0 || !L1 || !T1 || !sxa || !sya) {
+        free(Ws); free(L0); free(T0); free(L1); free(T1); free(sxa); free(sya);
+        return -1;
+    }
+    int taken = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        if (t_end > 0.0 && *t >= t_end) break;
+        stage_bc(g, p, U, sx, sy);
+        double dt = cfl_dt(g, p, U, *t, t_end);
+        memcpy(Ws, U, n * sizeof(double));
+        memcpy(sxa, sx, P * sizeof(double));
+        memcpy(sya, sy, P * sizeof(double));
+        residual_gks2d(g, p, gk, U, sx, sy, dt, L0, T0, sxa, sya);
+        for (int v = 0; v < 4; ++v)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    size_t c = (size_t)v * P + (size_t)(j + g->ng) * g->ld + (size_t)(i + g->ng);
+                    Ws[c] = U[c] + 0.5 * dt * L0[c] + 0.125 * dt * dt * T0[c];
+                }
+        stage_bc(g, p, Ws, sxa, sya);
+        residual_gks2d(g, p, gk, Ws, sxa, sya, dt, L1, T1, sx, sy);
+        for (int v = 0; v < 4; ++v)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    size_t c = (size_t)v * P + (size_t)(j + g->ng) * g->ld + (size_t)(i + g->ng);
+                    U[c] = U[c] + dt * L0[c] + dt * dt / 6.0 * (T0[c] + 2.0 * T1[c]);
+                }
+        *t += dt;
+        if (dt_hist) dt_hist[s] = dt;
+        ++taken;
+    }
+    free(Ws); free(L0); free(T0); free(L1); free(T1); free(sxa); free(sya);
+    return taken;
+}
+
+/* Test hooks of the 2D kinetic pieces (local frame). */
+int orc_gks2_slopes(double gamma, const double *W, const double *Wn, const double *Wt, double *an, double *at,
+                    double *A)
+{
+    g2_maxw m;
+    if (g2_maxwellian(gamma, W, &m)) return -1;
+    g2_slopes(&m, Wn, Wt, an, at, A);
+    return 0;
+}
+
+int orc_gks2_point(double gamma, const orc_gks *gk, double dt, const double *Wl, const double *Wln,
+                   const double *Wlt, const double *Wr, const double *Wrn, const double *Wrt, double *Fn, double *Ft)
+{
+    return g2_point(gamma, gk, dt, Wl, Wln, Wlt, Wr, Wrn, Wrt, Fn, Ft);
+}

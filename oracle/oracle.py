@@ -76,6 +76,9 @@ def lib():
         L.orc_gks_flux.argtypes = [C.c_double, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
         L.orc_gks_point.argtypes = [C.c_double, vp, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_poly_d.argtypes = [vp, _dp, _dp, C.c_int, _dp, _dp, _dp]
+        L.orc_step_gks2d.argtypes = [vp, vp, vp, _dp, _dp, _dp, _dp, C.c_int, C.c_double, _dp]
+        L.orc_gks2_slopes.argtypes = [C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_gks2_point.argtypes = [C.c_double, vp, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     return _LIB
 
 
@@ -346,3 +349,38 @@ def poly_d(p, W, s, xi):
     out, dout = np.zeros(len(xi)), np.zeros(len(xi))
     lvl = lib().orc_poly_d(C.byref(c_params(p)), _ptr(W), _ptr(s), len(xi), _ptr(xi), _ptr(out), _ptr(dout))
     return out, dout, lvl
+
+
+# ---- gas-kinetic solver (2D) -------------------------------------------------
+
+def step_gks2d(g, p, U, sx, sy, t, nsteps, t_end=0.0, c1=0.05, c2=1.0, tau=0.0):
+    """S2O4 GKS steps in place (2D); returns (t, dt history)."""
+    tt = C.c_double(t)
+    hist = np.zeros(max(nsteps, 1))
+    G, P = _gp(g, p)
+    K = c_gks(c1, c2, tau)
+    n = _check(lib().orc_step_gks2d(G, P, C.byref(K), _ptr(U), _ptr(sx), _ptr(sy), C.byref(tt), nsteps, t_end,
+                                    _ptr(hist)), "step_gks2d")
+    return tt.value, hist[:n]
+
+
+def run_gks2d(g, p, U, nsteps, t_end=0.0, c1=0.05, c2=1.0, tau=0.0):
+    U = U.copy()
+    sx, sy = sigma_init(g, p, U)
+    t, dts = step_gks2d(g, p, U, sx, sy, 0.0, nsteps, t_end, c1, c2, tau)
+    return U, sx, sy, t, dts
+
+
+def gks2_slopes(gamma, W, Wn, Wt):
+    an, at, A = np.zeros(4), np.zeros(4), np.zeros(4)
+    _check(lib().orc_gks2_slopes(gamma, _ptr(_vec(W)), _ptr(_vec(Wn)), _ptr(_vec(Wt)), _ptr(an), _ptr(at),
+                                 _ptr(A)), "gks2_slopes")
+    return an, at, A
+
+
+def gks2_point(gamma, dt, Wl, Wln, Wlt, Wr, Wrn, Wrt, c1=0.05, c2=1.0, tau=0.0):
+    Fn, Ft = np.zeros(4), np.zeros(4)
+    K = c_gks(c1, c2, tau)
+    _check(lib().orc_gks2_point(gamma, C.byref(K), dt, _ptr(_vec(Wl)), _ptr(_vec(Wln)), _ptr(_vec(Wlt)),
+                                _ptr(_vec(Wr)), _ptr(_vec(Wrn)), _ptr(_vec(Wrt)), _ptr(Fn), _ptr(Ft)), "gks2_point")
+    return Fn, Ft

@@ -209,7 +209,7 @@ extern "C" {
 
 const char *ase_last_error(void) { return g_err.c_str(); }
 
-int ase_version(void) { return 1; }
+int ase_version(void) { return 2; }
 
 int ase_bc_fill(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, void *stream)
 {
@@ -416,6 +416,131 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
         }
     }
     return check_launch("ase_step");
+}
+
+static GksConst gks_const(const ase_params_t *p, const ase_gks_t *gk)
+{
+    GksConst c;
+    c.K = (3.0 - p->gamma) / (p->gamma - 1.0);
+    c.c1 = gk->c1;
+    c.c2 = gk->c2;
+    c.tau = gk->tau;
+    return c;
+}
+
+static int check_gks(const ase_gks_t *gk)
+{
+    if (!gk) return fail(ASE_ERR_ARG, "null gks parameters");
+    if (!(gk->c1 >= 0.0) || !(gk->c2 >= 0.0) || !(gk->tau >= 0.0))
+        return fail(ASE_ERR_ARG, "gks c1, c2, tau must be >= 0");
+    return ASE_OK;
+}
+
+int ase_gks_flux(const ase_params_t *p, const ase_gks_t *gk, int32_t n, const double *Wl, const double *Wlx,
+                 const double *Wr, const double *Wrx, double dt, double *Fn, double *Ft, void *stream)
+{
+    if (!p) return fail(ASE_ERR_ARG, "null params");
+    int rc = check_gks(gk);
+    if (rc) return rc;
+    if (!(p->gamma > 1.0)) return fail(ASE_ERR_ARG, "gamma must be > 1");
+    if (n < 0) return fail(ASE_ERR_ARG, "n must be >= 0");
+    if (!(dt > 0.0)) return fail(ASE_ERR_ARG, "dt must be > 0");
+    if (n == 0) return ASE_OK;
+    ASE_PTR(Wl, "Wl");
+    ASE_PTR(Wlx, "Wlx");
+    ASE_PTR(Wr, "Wr");
+    ASE_PTR(Wrx, "Wrx");
+    ASE_PTR(Fn, "Fn");
+    ASE_PTR(Ft, "Ft");
+    GksPointArgs a;
+    a.Wl = Wl;
+    a.Wlx = Wlx;
+    a.Wr = Wr;
+    a.Wrx = Wrx;
+    a.Fn = Fn;
+    a.Ft = Ft;
+    a.n = n;
+    a.dt = dt;
+    a.gm1 = p->gamma - 1.0;
+    a.gk = gks_const(p, gk);
+    launch_gks_points(a, (hipStream_t)stream);
+    return check_launch("ase_gks_flux");
+}
+
+int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk, double *U, double *sx,
+                 double *t, double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes, void *stream)
+{
+    Geo geo;
+    int rc = validate(g, p, &geo);
+    if (rc) return rc;
+    if (geo.dim != 1) return fail(ASE_ERR_ARG, "the gas-kinetic path takes 1D grids");
+    rc = check_gks(gk);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(ASE_ERR_ARG, "nsteps must be >= 0");
+    ASE_PTR(U, "U");
+    ASE_PTR(sx, "sx");
+    ASE_PTR(t, "t");
+    if (dt_hist && misaligned(dt_hist)) return fail(ASE_ERR_ALIGN, "misaligned: dt_hist");
+    Workspace w;
+    rc = carve_workspace(geo, ws, ws_bytes, &w);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const MethodConst mc = method_const(p);
+    const bool fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) != 0;
+    auto stage_bc = [&](double *Us, double *sxs) {
+        // (1D: the y-strength argument is unused; the x array stands in as in ase_step)
+        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs, sxs, st);
+        else launch_bc_fill(*g, geo, mc, Us, sxs, sxs, st);
+    };
+    // workspace: W* in U1, L(W^n) in U2, L_t(W^n) in Res, stage-1 strengths in sxa
+    Gks1DArgs a;
+    a.dt = w.scal;
+    a.skip = w.scal + 1;
+    a.plane = geo.plane;
+    a.nx = geo.nx;
+    a.ng = geo.ng;
+    a.NX = geo.NX;
+    a.inv_dx = 1.0 / g->dx;
+    a.mc = mc;
+    a.gk = gks_const(p, gk);
+    a.L0 = w.U2;
+    a.Lt0 = w.Res;
+    for (int s = 0; s < nsteps; ++s) {
+        {
+            ProfScope ps(ASE_KCLASS_BC, st);
+            stage_bc(U, sx);
+        }
+        {
+            ProfScope ps(ASE_KCLASS_CFL, st);
+            launch_cfl(*g, geo, *p, mc, U, t, t, t_end, w.scal, w.scal + 1, dt_hist ? dt_hist + s : nullptr,
+                       w.part, w.nparts, st);
+        }
+        a.stage = 1;
+        a.U = U;
+        a.sx = sx;
+        a.sig_out = w.sxa;
+        a.Un = U;
+        a.Uout = w.U1;
+        {
+            ProfScope ps(ASE_KCLASS_GKS_1D, st);
+            launch_gks1d(geo.R, geo.nx, a, st);
+        }
+        {
+            ProfScope ps(ASE_KCLASS_BC, st);
+            stage_bc(w.U1, w.sxa);
+        }
+        a.stage = 2;
+        a.U = w.U1;
+        a.sx = w.sxa;
+        a.sig_out = sx;
+        a.Un = U;
+        a.Uout = U;
+        {
+            ProfScope ps(ASE_KCLASS_GKS_1D, st);
+            launch_gks1d(geo.R, geo.nx, a, st);
+        }
+    }
+    return check_launch("ase_step_gks");
 }
 
 int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_t *bin_start, int32_t *bin_list)

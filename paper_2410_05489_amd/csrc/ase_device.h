@@ -30,6 +30,11 @@ struct Tables {
     double z[4][kMaxPts][4];
     // Gauss weights eta_k per order (normalised to 1).
     double eta[4][4];
+    // Slopes dP/dxi at the right (f = 0, xi = 0) and left (f = 1, xi = -1)
+    // faces: dlin[li][f][t] weights of the linear levels, dz[f][k-1] =
+    // dZ_k/dxi = k xi^(k-1).  Used by the gas-kinetic flux.
+    double dlin[4][2][kTaps];
+    double dz[2][4];
 };
 
 // ---------------------------------------------------------------------------
@@ -88,6 +93,13 @@ constexpr double zk(int k, double xi)
     return p - ((k % 2 == 0) ? 1.0 : -1.0) / double(k + 1);
 }
 
+constexpr double dzk(int k, double xi)
+{
+    double p = double(k);
+    for (int i = 1; i < k; ++i) p *= xi;
+    return p;
+}
+
 // Gauss-Legendre nodes on [-1/2, 1/2] and weights normalised to 1.
 constexpr void gauss_nodes(int G, double *x, double *w)
 {
@@ -144,6 +156,16 @@ constexpr Tables make_tables()
                         t.lin[oi][li][q][4 + m] += S.num[k - 1][m + S.h] / S.den[k - 1] * zq;
                 }
             }
+        }
+    }
+    for (int f = 0; f < 2; ++f) {
+        const double xf = f == 0 ? 0.0 : -1.0;
+        for (int k = 1; k <= 4; ++k) t.dz[f][k - 1] = dzk(k, xf);
+        for (int li = 0; li < 4; ++li) {
+            const Stencil &S = *st[li];
+            for (int k = 1; k <= S.ncoef; ++k)
+                for (int m = -S.h; m <= S.h; ++m)
+                    t.dlin[li][f][4 + m] += S.num[k - 1][m + S.h] / S.den[k - 1] * dzk(k, xf);
         }
     }
     return t;
@@ -236,25 +258,35 @@ __device__ __forceinline__ void eval_linear(LD ld, int oi, int li, int q0, doubl
 }
 
 // WENO-Z-AO(5,3) with DF factors (Sec. 3.2); one variable, W[0..4] = W_{-2..2}.
-template <int NP>
-__device__ __forceinline__ void weno_ao53(const double (&W)[5], const double al[4], const MethodConst &mc, int oi,
-                                          int q0, double (&out)[NP])
+// The candidate coefficients and the normalised nonlinear weights do not
+// depend on the evaluation point.
+struct WenoAO53 {
+    double am1, am2, a01, a02, ap1, ap2;   // 3-cell sub-stencils (W_x1, W_x2)
+    double b1, b2, b3, b4;                 // 5-cell stencil
+    double o5, om, o0, op;                 // normalised weights
+};
+
+__device__ __forceinline__ WenoAO53 weno_ao53_setup(const double (&W)[5], const MethodConst &mc)
 {
+    WenoAO53 c;
     const double Wm2 = W[0], Wm1 = W[1], W0 = W[2], W1 = W[3], W2 = W[4];
     // sub-stencil coefficients (W_x1, W_x2)
-    const double am1 = 2.0 * W0 - 3.0 * Wm1 + Wm2, am2 = 0.5 * (Wm2 - 2.0 * Wm1 + W0);
-    const double a01 = W1 - W0, a02 = 0.5 * (Wm1 - 2.0 * W0 + W1);
-    const double ap1 = W1 - W0, ap2 = 0.5 * (W0 - 2.0 * W1 + W2);
+    c.am1 = 2.0 * W0 - 3.0 * Wm1 + Wm2;
+    c.am2 = 0.5 * (Wm2 - 2.0 * Wm1 + W0);
+    c.a01 = W1 - W0;
+    c.a02 = 0.5 * (Wm1 - 2.0 * W0 + W1);
+    c.ap1 = W1 - W0;
+    c.ap2 = 0.5 * (W0 - 2.0 * W1 + W2);
     // 5-cell coefficients
-    const double b1 = (-15.0 * W0 + Wm1 + 15.0 * W1 - W2) * (1.0 / 12.0);
-    const double b2 = (-8.0 * W0 + 6.0 * Wm1 - Wm2 + 2.0 * W1 + W2) * 0.125;
-    const double b3 = (3.0 * W0 - Wm1 - 3.0 * W1 + W2) * (1.0 / 6.0);
-    const double b4 = (6.0 * W0 - 4.0 * Wm1 + Wm2 - 4.0 * W1 + W2) * (1.0 / 24.0);
+    c.b1 = (-15.0 * W0 + Wm1 + 15.0 * W1 - W2) * (1.0 / 12.0);
+    c.b2 = (-8.0 * W0 + 6.0 * Wm1 - Wm2 + 2.0 * W1 + W2) * 0.125;
+    c.b3 = (3.0 * W0 - Wm1 - 3.0 * W1 + W2) * (1.0 / 6.0);
+    c.b4 = (6.0 * W0 - 4.0 * Wm1 + Wm2 - 4.0 * W1 + W2) * (1.0 / 24.0);
     // smoothness indicators of the 3-cell polynomials on [-1,0]:
     // int (P')^2 + int (P'')^2 = a1^2 - 2 a1 a2 + 16/3 a2^2
-    const double sm = am1 * am1 - 2.0 * am1 * am2 + (16.0 / 3.0) * am2 * am2;
-    const double s0 = a01 * a01 - 2.0 * a01 * a02 + (16.0 / 3.0) * a02 * a02;
-    const double sp = ap1 * ap1 - 2.0 * ap1 * ap2 + (16.0 / 3.0) * ap2 * ap2;
+    const double sm = c.am1 * c.am1 - 2.0 * c.am1 * c.am2 + (16.0 / 3.0) * c.am2 * c.am2;
+    const double s0 = c.a01 * c.a01 - 2.0 * c.a01 * c.a02 + (16.0 / 3.0) * c.a02 * c.a02;
+    const double sp = c.ap1 * c.ap1 - 2.0 * c.ap1 * c.ap2 + (16.0 / 3.0) * c.ap2 * c.ap2;
     const double s5 = (sm + 4.0 * s0 + sp) * (1.0 / 6.0) + fabs(sm - sp);
     const double tz = (fabs(s5 - sm) + fabs(s5 - s0) + fabs(s5 - sp)) * (1.0 / 3.0);
     const double tz2 = tz * tz;
@@ -264,16 +296,28 @@ __device__ __forceinline__ void weno_ao53(const double (&W)[5], const double al[
     const double w0 = mc.d30 * (1.0 + tz2 / (e0 * e0));
     const double wp = mc.d3m * (1.0 + tz2 / (ep * ep));
     const double inv = 1.0 / (w5 + wm + w0 + wp);
-    const double o5 = w5 * inv, om = wm * inv, o0 = w0 * inv, op = wp * inv;
+    c.o5 = w5 * inv;
+    c.om = wm * inv;
+    c.o0 = w0 * inv;
+    c.op = wp * inv;
+    return c;
+}
+
+template <int NP>
+__device__ __forceinline__ void weno_ao53(const double (&W)[5], const double al[4], const MethodConst &mc, int oi,
+                                          int q0, double (&out)[NP])
+{
+    const WenoAO53 c = weno_ao53_setup(W, mc);
+    const double W0 = W[2];
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         const double *z = kTab.z[oi][q0 + q];
-        const double Pm = W0 + al[0] * (am1 * z[0] + am2 * z[1]);
-        const double P0 = W0 + al[1] * (a01 * z[0] + a02 * z[1]);
-        const double Pp = W0 + al[2] * (ap1 * z[0] + ap2 * z[1]);
-        const double P5 = W0 + al[3] * (b1 * z[0] + b2 * z[1] + b3 * z[2] + b4 * z[3]);
+        const double Pm = W0 + al[0] * (c.am1 * z[0] + c.am2 * z[1]);
+        const double P0 = W0 + al[1] * (c.a01 * z[0] + c.a02 * z[1]);
+        const double Pp = W0 + al[2] * (c.ap1 * z[0] + c.ap2 * z[1]);
+        const double P5 = W0 + al[3] * (c.b1 * z[0] + c.b2 * z[1] + c.b3 * z[2] + c.b4 * z[3]);
         const double inner = P5 * mc.inv_d5 - mc.r3m * Pm - mc.r30 * P0 - mc.r3m * Pp;
-        out[q] = o5 * inner + om * Pm + o0 * P0 + op * Pp;
+        out[q] = c.o5 * inner + c.om * Pm + c.o0 * P0 + c.op * Pp;
     }
 }
 

@@ -124,4 +124,37 @@ struct ObjLaunch {
 };
 void launch_objective(const ObjLaunch &ol, hipStream_t st);
 
+// Gas-kinetic solver (1D).
+struct GksConst {
+    double K;          // internal degrees of freedom, (3 - gamma)/(gamma - 1)
+    double c1, c2;     // numerical collision time tau_n = c1 dt + c2 |dp|/(p_l + p_r) dt
+    double tau;        // collision time outside the exponentials (0: Euler)
+};
+
+struct Gks1DArgs {
+    const double *U;       // stage input (ghosts filled)
+    const double *sx;      // strengths read by this stage
+    double *sig_out;       // strengths written at the flux faces
+    const double *Un;      // step-start state (stage 2)
+    double *Uout;          // stage output
+    double *L0, *Lt0;      // L and L_t of the first stage (written by stage 1, read by stage 2)
+    const double *dt, *skip;
+    long long plane;
+    int nx, ng, NX, stage;
+    double inv_dx;
+    MethodConst mc;
+    GksConst gk;
+};
+void launch_gks1d(int R, int nx, const Gks1DArgs &a, hipStream_t st);
+
+constexpr int kGksPointThreads = 256;
+struct GksPointArgs {
+    const double *Wl, *Wlx, *Wr, *Wrx;   // [3][n]
+    double *Fn, *Ft;                     // [3][n]
+    int n;
+    double dt, gm1;
+    GksConst gk;
+};
+void launch_gks_points(const GksPointArgs &a, hipStream_t st);
+
 }  // namespace ase
