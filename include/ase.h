@@ -217,19 +217,30 @@ typedef struct {
 int ase_gks_flux(const ase_params_t *p, const ase_gks_t *gk, int32_t n, const double *Wl, const double *Wlx,
                  const double *Wr, const double *Wrx, double dt, double *Fn, double *Ft, void *stream);
 
-/* nsteps S2O4 steps of the 1D gas-kinetic solver (Eq. S2O4 temporal):
+/* Bytes of device workspace ase_step_gks needs for grid g (1D: as
+ * ase_workspace_bytes; 2D adds the face-point states and the face fluxes
+ * of both directions).  0 on invalid arguments. */
+size_t ase_gks_workspace_bytes(const ase_grid_t *g, const ase_params_t *p);
+
+/* nsteps S2O4 steps of the gas-kinetic solver (Eq. S2O4 temporal):
  * W* = W^n + dt/2 L(W^n) + dt^2/8 L_t(W^n),
  * W^{n+1} = W^n + dt L(W^n) + dt^2/6 (L_t(W^n) + 2 L_t(W*)),
  * L and L_t the divergences of F and F_t.  Per step: boundary fill, dt
- * (CFL rule of ase_cfl_dt), two stage launches with a boundary fill
- * between.  The DF state is lagged across the stages as in ase_step (or
- * first order with ASE_FLAG_DF_FIRST_ORDER); with
- * ASE_FLAG_POSITIVITY_FALLBACK a non-physical interface state becomes its
- * cell average with zero slope.  Arguments as ase_step (1D grids only,
- * ASE_ERR_ARG otherwise; ws_bytes >= ase_workspace_bytes(g, p)). */
+ * (CFL rule of ase_cfl_dt), two stages with a boundary fill between.  1D:
+ * one fused launch per stage.  2D (Sec. 2.1): per direction a
+ * reconstruction launch (values, normal slopes and tangential slopes of
+ * both sides at every Gauss point: the normal ASE-DF reconstruction, then
+ * the tangential one of the face values and of the normal slopes) and a
+ * flux launch (the BGK flux in the local frame of each Gauss point,
+ * rotated back, Gauss quadrature), then one update launch.  The DF state
+ * is lagged across the stages as in ase_step (or first order with
+ * ASE_FLAG_DF_FIRST_ORDER); with ASE_FLAG_POSITIVITY_FALLBACK a
+ * non-physical interface state becomes its cell average with zero slopes.
+ * Arguments as ase_step (sy: y-face strengths, 2D only, may be NULL in 1D;
+ * ws_bytes >= ase_gks_workspace_bytes(g, p)). */
 int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk, double *U, double *sx,
-                 double *t, double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes,
-                 void *stream);
+                 double *sy, double *t, double *dt_hist, int32_t nsteps, double t_end, void *ws,
+                 size_t ws_bytes, void *stream);
 
 /* ---- Batched 1D instances (one persistent launch) -------------------------
  * Many independent 1D problems of uneven size stored back to back:
@@ -351,7 +362,8 @@ int ase_pressure_objective(const ase_params_t *p, int32_t ninst, const int64_t *
  * (ASE_KCLASS_*); it does not clear the record. */
 enum { ASE_KCLASS_SWEEP_X = 0, ASE_KCLASS_SWEEP_Y = 1, ASE_KCLASS_STAGE_1D = 2, ASE_KCLASS_BC = 3,
        ASE_KCLASS_CFL = 4, ASE_KCLASS_BATCHED = 5, ASE_KCLASS_ADJOINT = 6, ASE_KCLASS_GKS_1D = 7,
-       ASE_KCLASS_COUNT = 8 };
+       ASE_KCLASS_GKS_2D_RECON = 8, ASE_KCLASS_GKS_2D_FLUX = 9, ASE_KCLASS_GKS_2D_UPDATE = 10,
+       ASE_KCLASS_COUNT = 11 };
 int ase_profile_enable(int on);
 int ase_profile_read(int kernel_class, double *total_ms, int64_t *launches);
 

@@ -41,10 +41,10 @@ EXPORTS = ("ase_last_error", "ase_version", "ase_bc_fill", "ase_sigma_init", "as
            "ase_profile_enable", "ase_profile_read", "ase_batched_plan", "ase_batched_workspace_bytes",
            "ase_batched_sigma_init", "ase_step_batched", "ase_adjoint_workspace_bytes", "ase_adjoint_step",
            "ase_adjoint_batched_workspace_bytes", "ase_adjoint_batched", "ase_pressure_objective",
-           "ase_gks_flux", "ase_step_gks")
+           "ase_gks_flux", "ase_gks_workspace_bytes", "ase_step_gks")
 
 KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4, "batched": 5, "adjoint": 6,
-          "gks_1d": 7}
+          "gks_1d": 7, "gks_2d_recon": 8, "gks_2d_flux": 9, "gks_2d_update": 10}
 
 
 class AseGks(C.Structure):
@@ -92,7 +92,9 @@ def lib():
                                       C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_pressure_objective.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp]
     L.ase_gks_flux.argtypes = [vp, vp, C.c_int32, dp, dp, dp, dp, C.c_double, dp, dp, vp]
-    L.ase_step_gks.argtypes = [vp, vp, vp, dp, dp, dp, dp, C.c_int32, C.c_double, vp, C.c_size_t, vp]
+    L.ase_gks_workspace_bytes.restype = C.c_size_t
+    L.ase_gks_workspace_bytes.argtypes = [vp, vp]
+    L.ase_step_gks.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, C.c_int32, C.c_double, vp, C.c_size_t, vp]
     L.ase_profile_enable.argtypes = [C.c_int]
     L.ase_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in EXPORTS:
@@ -267,33 +269,43 @@ def gks_flux(p, gk: AseGks, Wl, Wlx, Wr, Wrx, dt: float, Fn, Ft, stream=None):
                               float(dt), _p(Fn), _p(Ft), _stream(stream)), "ase_gks_flux")
 
 
-def step_gks(g, p, gk: AseGks, U, sx, t, nsteps, t_end, ws: Workspace, dt_hist=None, stream=None):
+def gks_workspace_bytes(g, p) -> int:
     G, P = _gp(g, p)
-    _check(lib().ase_step_gks(G, P, C.byref(gk), _p(U), _p(sx), _p(t), _p(dt_hist), int(nsteps), float(t_end),
-                              ws.ptr, ws.nbytes, _stream(stream)), "ase_step_gks")
+    n = lib().ase_gks_workspace_bytes(G, P)
+    if n == 0:
+        raise AseError(lib().ase_last_error().decode())
+    return n
+
+
+def step_gks(g, p, gk: AseGks, U, sx, sy, t, nsteps, t_end, ws: Workspace, dt_hist=None, stream=None):
+    G, P = _gp(g, p)
+    _check(lib().ase_step_gks(G, P, C.byref(gk), _p(U), _p(sx), _p(sy), _p(t), _p(dt_hist), int(nsteps),
+                              float(t_end), ws.ptr, ws.nbytes, _stream(stream)), "ase_step_gks")
 
 
 class GksSimulation:
-    """Device state (U, sx, t) of a 1D grid advanced by the gas-kinetic
-    solver with S2O4 steps."""
+    """Device state (U, sx, sy, t) of a 1D or 2D grid advanced by the
+    gas-kinetic solver with S2O4 steps."""
 
     def __init__(self, g: Grid, p: Params, U0, c1: float = 0.05, c2: float = 1.0, tau: float = 0.0,
-                 device="cuda", sx=None, t: float = 0.0):
-        if g.dim != 1:
-            raise AseError("the gas-kinetic path takes 1D grids")
+                 device="cuda", sx=None, sy=None, t: float = 0.0):
         self.g, self.p = g, p
         self.gk = c_gks(c1, c2, tau)
         self.U = torch.as_tensor(U0, dtype=torch.float64).to(device).contiguous()
         self.sx = torch.zeros((g.NY, g.ld), dtype=torch.float64, device=device)
+        self.sy = torch.zeros((g.NY, g.ld), dtype=torch.float64, device=device)
         self.t = torch.full((1,), float(t), dtype=torch.float64, device=device)
-        self.ws = Workspace(workspace_bytes(g, p), device)
+        self.ws = Workspace(gks_workspace_bytes(g, p), device)
         if sx is None:
-            sigma_init(g, p, self.U, self.sx, self.sx)
+            sigma_init(g, p, self.U, self.sx, self.sy)
         else:
             self.sx.copy_(torch.as_tensor(sx))
+            if sy is not None:
+                self.sy.copy_(torch.as_tensor(sy))
 
     def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None):
-        step_gks(self.g, self.p, self.gk, self.U, self.sx, self.t, nsteps, t_end, self.ws, dt_hist)
+        step_gks(self.g, self.p, self.gk, self.U, self.sx, self.sy if self.g.dim == 2 else None, self.t, nsteps,
+                 t_end, self.ws, dt_hist)
 
     def capture(self, nsteps: int, t_end: float = 0.0):
         return _capture(lambda: self.run(nsteps, t_end))

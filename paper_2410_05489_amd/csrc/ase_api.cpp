@@ -418,10 +418,11 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
     return check_launch("ase_step");
 }
 
-static GksConst gks_const(const ase_params_t *p, const ase_gks_t *gk)
+static GksConst gks_const(const ase_params_t *p, const ase_gks_t *gk, int dim)
 {
     GksConst c;
-    c.K = (3.0 - p->gamma) / (p->gamma - 1.0);
+    // internal degrees of freedom: 1D (3 - gamma)/(gamma - 1), 2D (4 - 2 gamma)/(gamma - 1)
+    c.K = dim == 1 ? (3.0 - p->gamma) / (p->gamma - 1.0) : (4.0 - 2.0 * p->gamma) / (p->gamma - 1.0);
     c.c1 = gk->c1;
     c.c2 = gk->c2;
     c.tau = gk->tau;
@@ -434,6 +435,42 @@ static int check_gks(const ase_gks_t *gk)
     if (!(gk->c1 >= 0.0) || !(gk->c2 >= 0.0) || !(gk->tau >= 0.0))
         return fail(ASE_ERR_ARG, "gks c1, c2, tau must be >= 0");
     return ASE_OK;
+}
+
+// 2D extras behind the LF workspace: face-point states [2 G 12][nf_max],
+// fluxes Fx, Ftx [4][nfx], Fy, Fty [4][nfy].
+struct GksWs2D {
+    double *rec, *Fx, *Ftx, *Fy, *Fty;
+    long long nfx, nfy;
+};
+
+static size_t gks_extra_bytes(const Geo &geo)
+{
+    if (geo.dim == 1) return 0;
+    const long long nfx = (long long)(geo.nx + 1) * geo.ny, nfy = (long long)geo.nx * (geo.ny + 1);
+    const long long nfm = nfx > nfy ? nfx : nfy;
+    return align_up((size_t)(2 * geo.G * 12) * nfm * sizeof(double)) + 2 * align_up((size_t)4 * nfx * sizeof(double)) +
+           2 * align_up((size_t)4 * nfy * sizeof(double));
+}
+
+static void carve_gks2d(const Geo &geo, void *ws, GksWs2D *w)
+{
+    char *c = static_cast<char *>(ws) + workspace_bytes(geo);
+    w->nfx = (long long)(geo.nx + 1) * geo.ny;
+    w->nfy = (long long)geo.nx * (geo.ny + 1);
+    const long long nfm = w->nfx > w->nfy ? w->nfx : w->nfy;
+    w->rec = reinterpret_cast<double *>(c); c += align_up((size_t)(2 * geo.G * 12) * nfm * sizeof(double));
+    w->Fx = reinterpret_cast<double *>(c); c += align_up((size_t)4 * w->nfx * sizeof(double));
+    w->Ftx = reinterpret_cast<double *>(c); c += align_up((size_t)4 * w->nfx * sizeof(double));
+    w->Fy = reinterpret_cast<double *>(c); c += align_up((size_t)4 * w->nfy * sizeof(double));
+    w->Fty = reinterpret_cast<double *>(c);
+}
+
+size_t ase_gks_workspace_bytes(const ase_grid_t *g, const ase_params_t *p)
+{
+    Geo geo;
+    if (validate(g, p, &geo)) return 0;
+    return workspace_bytes(geo) + gks_extra_bytes(geo);
 }
 
 int ase_gks_flux(const ase_params_t *p, const ase_gks_t *gk, int32_t n, const double *Wl, const double *Wlx,
@@ -462,83 +499,150 @@ int ase_gks_flux(const ase_params_t *p, const ase_gks_t *gk, int32_t n, const do
     a.n = n;
     a.dt = dt;
     a.gm1 = p->gamma - 1.0;
-    a.gk = gks_const(p, gk);
+    a.gk = gks_const(p, gk, 1);
     launch_gks_points(a, (hipStream_t)stream);
     return check_launch("ase_gks_flux");
 }
 
 int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk, double *U, double *sx,
-                 double *t, double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes, void *stream)
+                 double *sy, double *t, double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes,
+                 void *stream)
 {
     Geo geo;
     int rc = validate(g, p, &geo);
     if (rc) return rc;
-    if (geo.dim != 1) return fail(ASE_ERR_ARG, "the gas-kinetic path takes 1D grids");
     rc = check_gks(gk);
     if (rc) return rc;
     if (nsteps < 0) return fail(ASE_ERR_ARG, "nsteps must be >= 0");
     ASE_PTR(U, "U");
     ASE_PTR(sx, "sx");
+    if (geo.dim == 2) ASE_PTR(sy, "sy");
     ASE_PTR(t, "t");
     if (dt_hist && misaligned(dt_hist)) return fail(ASE_ERR_ALIGN, "misaligned: dt_hist");
+    if (ws_bytes < workspace_bytes(geo) + gks_extra_bytes(geo))
+        return fail(ASE_ERR_WORKSPACE, "workspace too small (ase_gks_workspace_bytes)");
     Workspace w;
     rc = carve_workspace(geo, ws, ws_bytes, &w);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const MethodConst mc = method_const(p);
+    const GksConst gc = gks_const(p, gk, geo.dim);
     const bool fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) != 0;
-    auto stage_bc = [&](double *Us, double *sxs) {
-        // (1D: the y-strength argument is unused; the x array stands in as in ase_step)
-        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs, sxs, st);
-        else launch_bc_fill(*g, geo, mc, Us, sxs, sxs, st);
+    double *syv = geo.dim == 2 ? sy : sx;    // 1D: the y-strength argument is unused
+    double *syav = geo.dim == 2 ? w.sya : w.sxa;
+    auto stage_bc = [&](double *Us, double *sxs, double *sys) {
+        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs, sys, st);
+        else launch_bc_fill(*g, geo, mc, Us, sxs, sys, st);
     };
-    // workspace: W* in U1, L(W^n) in U2, L_t(W^n) in Res, stage-1 strengths in sxa
-    Gks1DArgs a;
-    a.dt = w.scal;
-    a.skip = w.scal + 1;
-    a.plane = geo.plane;
-    a.nx = geo.nx;
-    a.ng = geo.ng;
-    a.NX = geo.NX;
-    a.inv_dx = 1.0 / g->dx;
-    a.mc = mc;
-    a.gk = gks_const(p, gk);
-    a.L0 = w.U2;
-    a.Lt0 = w.Res;
+    // workspace: W* in U1, L(W^n) in U2, L_t(W^n) in Res, stage-1 strengths in sxa / sya
+    Gks1DArgs a1;
+    Gks2DArgs a2;
+    Gks2DUpdate up;
+    GksWs2D w2;
+    if (geo.dim == 1) {
+        a1.dt = w.scal;
+        a1.skip = w.scal + 1;
+        a1.plane = geo.plane;
+        a1.nx = geo.nx;
+        a1.ng = geo.ng;
+        a1.NX = geo.NX;
+        a1.inv_dx = 1.0 / g->dx;
+        a1.mc = mc;
+        a1.gk = gc;
+        a1.L0 = w.U2;
+        a1.Lt0 = w.Res;
+    } else {
+        carve_gks2d(geo, ws, &w2);
+        a2.dt = w.scal;
+        a2.skip = w.scal + 1;
+        a2.plane = geo.plane;
+        a2.nx = geo.nx;
+        a2.ny = geo.ny;
+        a2.ng = geo.ng;
+        a2.ld = geo.ld;
+        a2.NX = geo.NX;
+        a2.NY = geo.NY;
+        a2.inv_dx = 1.0 / g->dx;
+        a2.inv_dy = 1.0 / g->dy;
+        a2.mc = mc;
+        a2.gk = gc;
+        a2.rec = w2.rec;
+        up.Fx = w2.Fx;
+        up.Ftx = w2.Ftx;
+        up.Fy = w2.Fy;
+        up.Fty = w2.Fty;
+        up.dt = w.scal;
+        up.skip = w.scal + 1;
+        up.plane = geo.plane;
+        up.nfx = w2.nfx;
+        up.nfy = w2.nfy;
+        up.nx = geo.nx;
+        up.ny = geo.ny;
+        up.ng = geo.ng;
+        up.ld = geo.ld;
+        up.inv_dx = 1.0 / g->dx;
+        up.inv_dy = 1.0 / g->dy;
+        up.L0 = w.U2;
+        up.Lt0 = w.Res;
+    }
+    // one stage: stage 1 from U (strengths sx, sy) into W*, stage 2 from W*
+    // (strengths sxa, sya) into U
+    auto stage = [&](int k) {
+        double *Uin = k == 1 ? U : w.U1;
+        double *sxi = k == 1 ? sx : w.sxa, *syi = k == 1 ? syv : syav;
+        double *sxo = k == 1 ? w.sxa : sx, *syo = k == 1 ? syav : syv;
+        double *Uo = k == 1 ? w.U1 : U;
+        if (geo.dim == 1) {
+            a1.stage = k;
+            a1.U = Uin;
+            a1.sx = sxi;
+            a1.sig_out = sxo;
+            a1.Un = U;
+            a1.Uout = Uo;
+            ProfScope ps(ASE_KCLASS_GKS_1D, st);
+            launch_gks1d(geo.R, geo.nx, a1, st);
+            return;
+        }
+        a2.U = Uin;
+        a2.sx = sxi;
+        a2.sy = syi;
+        for (int dir = 0; dir < 2; ++dir) {
+            a2.sig_out = dir == 0 ? sxo : syo;
+            a2.F = dir == 0 ? w2.Fx : w2.Fy;
+            a2.Ft = dir == 0 ? w2.Ftx : w2.Fty;
+            a2.nfaces = dir == 0 ? w2.nfx : w2.nfy;
+            {
+                ProfScope ps(ASE_KCLASS_GKS_2D_RECON, st);
+                launch_gks2d(geo.R, dir, true, a2, st);
+            }
+            {
+                ProfScope ps(ASE_KCLASS_GKS_2D_FLUX, st);
+                launch_gks2d(geo.R, dir, false, a2, st);
+            }
+        }
+        up.stage = k;
+        up.U = Uin;
+        up.Un = U;
+        up.Uout = Uo;
+        ProfScope ps(ASE_KCLASS_GKS_2D_UPDATE, st);
+        launch_gks2d_update(up, st);
+    };
     for (int s = 0; s < nsteps; ++s) {
         {
             ProfScope ps(ASE_KCLASS_BC, st);
-            stage_bc(U, sx);
+            stage_bc(U, sx, syv);
         }
         {
             ProfScope ps(ASE_KCLASS_CFL, st);
             launch_cfl(*g, geo, *p, mc, U, t, t, t_end, w.scal, w.scal + 1, dt_hist ? dt_hist + s : nullptr,
                        w.part, w.nparts, st);
         }
-        a.stage = 1;
-        a.U = U;
-        a.sx = sx;
-        a.sig_out = w.sxa;
-        a.Un = U;
-        a.Uout = w.U1;
-        {
-            ProfScope ps(ASE_KCLASS_GKS_1D, st);
-            launch_gks1d(geo.R, geo.nx, a, st);
-        }
+        stage(1);
         {
             ProfScope ps(ASE_KCLASS_BC, st);
-            stage_bc(w.U1, w.sxa);
+            stage_bc(w.U1, w.sxa, syav);
         }
-        a.stage = 2;
-        a.U = w.U1;
-        a.sx = w.sxa;
-        a.sig_out = sx;
-        a.Un = U;
-        a.Uout = U;
-        {
-            ProfScope ps(ASE_KCLASS_GKS_1D, st);
-            launch_gks1d(geo.R, geo.nx, a, st);
-        }
+        stage(2);
     }
     return check_launch("ase_step_gks");
 }

@@ -30,11 +30,11 @@ struct Tables {
     double z[4][kMaxPts][4];
     // Gauss weights eta_k per order (normalised to 1).
     double eta[4][4];
-    // Slopes dP/dxi at the right (f = 0, xi = 0) and left (f = 1, xi = -1)
-    // faces: dlin[li][f][t] weights of the linear levels, dz[f][k-1] =
-    // dZ_k/dxi = k xi^(k-1).  Used by the gas-kinetic flux.
-    double dlin[4][2][kTaps];
-    double dz[2][4];
+    // Slopes dP/dxi at the same points: dlin[oi][li][q][t] weights of the
+    // linear levels, dz[oi][q][k-1] = dZ_k/dxi = k xi^(k-1).  Used by the
+    // gas-kinetic flux.
+    double dlin[4][4][kMaxPts][kTaps];
+    double dz[4][kMaxPts][4];
 };
 
 // ---------------------------------------------------------------------------
@@ -158,20 +158,39 @@ constexpr Tables make_tables()
             }
         }
     }
-    for (int f = 0; f < 2; ++f) {
-        const double xf = f == 0 ? 0.0 : -1.0;
-        for (int k = 1; k <= 4; ++k) t.dz[f][k - 1] = dzk(k, xf);
-        for (int li = 0; li < 4; ++li) {
-            const Stencil &S = *st[li];
-            for (int k = 1; k <= S.ncoef; ++k)
-                for (int m = -S.h; m <= S.h; ++m)
-                    t.dlin[li][f][4 + m] += S.num[k - 1][m + S.h] / S.den[k - 1] * dzk(k, xf);
+    for (int oi = 0; oi < 4; ++oi) {
+        const int G = oi + 1;
+        double pts[kMaxPts] = {0.0, -1.0, 0.0, 0.0, 0.0, 0.0};
+        double gx[4] = {0, 0, 0, 0}, gw[4] = {0, 0, 0, 0};
+        gauss_nodes(G, gx, gw);
+        for (int k = 0; k < G; ++k) pts[2 + k] = -0.5 + gx[k];
+        for (int q = 0; q < 2 + G; ++q) {
+            for (int k = 1; k <= 4; ++k) t.dz[oi][q][k - 1] = dzk(k, pts[q]);
+            for (int li = 0; li < 4; ++li) {
+                const Stencil &S = *st[li];
+                for (int k = 1; k <= S.ncoef; ++k)
+                    for (int m = -S.h; m <= S.h; ++m)
+                        t.dlin[oi][li][q][4 + m] += S.num[k - 1][m + S.h] / S.den[k - 1] * dzk(k, pts[q]);
+            }
         }
     }
     return t;
 }
 
 }  // namespace tables
+
+// Extents of a 2D sweep tile of T0 x T1 cells with faces of direction DIR:
+// staged cells (UX x UY), cells whose face traces phase 1 forms (TX x TY),
+// flux faces (FX x FY).
+template <int DIR, int R, int T0, int T1>
+struct SweepShape {
+    static constexpr int UX = (DIR == 0) ? T0 + 2 + 2 * R : T0 + 2 * R;
+    static constexpr int UY = (DIR == 0) ? T1 + 2 * R : T1 + 2 + 2 * R;
+    static constexpr int TX = (DIR == 0) ? T0 + 2 : T0 + 2 * R;
+    static constexpr int TY = (DIR == 0) ? T1 + 2 * R : T1 + 2;
+    static constexpr int FX = (DIR == 0) ? T0 + 1 : T0;
+    static constexpr int FY = (DIR == 0) ? T1 : T1 + 1;
+};
 
 struct MethodConst {
     double gamma, gm1;          // gamma, gamma - 1

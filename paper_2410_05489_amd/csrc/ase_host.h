@@ -147,6 +147,34 @@ struct Gks1DArgs {
 };
 void launch_gks1d(int R, int nx, const Gks1DArgs &a, hipStream_t st);
 
+struct Gks2DArgs {
+    const double *U;       // stage input (ghosts filled)
+    const double *sx, *sy; // strengths read by this stage
+    double *sig_out;       // strengths written at this direction's flux faces
+    double *rec;           // [2 G 12][nfaces] face-point states and slopes
+    double *F, *Ft;        // [4][nfaces] face flux and its time derivative
+    const double *dt, *skip;
+    long long plane, nfaces;
+    int nx, ny, ng, ld, NX, NY;
+    double inv_dx, inv_dy;
+    MethodConst mc;
+    GksConst gk;
+};
+// recon: the face-point reconstruction of direction dir into rec; else the
+// face fluxes from rec
+void launch_gks2d(int R, int dir, bool recon, const Gks2DArgs &a, hipStream_t st);
+
+struct Gks2DUpdate {
+    const double *Fx, *Ftx, *Fy, *Fty;   // [4][nfx], [4][nfy]
+    const double *U, *Un;
+    double *Uout, *L0, *Lt0;
+    const double *dt, *skip;
+    long long plane, nfx, nfy;
+    int nx, ny, ng, ld, stage;
+    double inv_dx, inv_dy;
+};
+void launch_gks2d_update(const Gks2DUpdate &u, hipStream_t st);
+
 constexpr int kGksPointThreads = 256;
 struct GksPointArgs {
     const double *Wl, *Wlx, *Wr, *Wrx;   // [3][n]

@@ -330,15 +330,6 @@ __global__ void __launch_bounds__(kThreads) k_cfl_final(const double *part, int 
 // quadrature.  Phase 3 forms flux differences and, in the second sweep, the
 // SSP-RK3 stage combination.
 // ---------------------------------------------------------------------------
-template <int DIR, int R, int T0, int T1>
-struct SweepShape {
-    static constexpr int UX = (DIR == 0) ? T0 + 2 + 2 * R : T0 + 2 * R;  // staged cells
-    static constexpr int UY = (DIR == 0) ? T1 + 2 * R : T1 + 2 + 2 * R;
-    static constexpr int TX = (DIR == 0) ? T0 + 2 : T0 + 2 * R;          // face traces
-    static constexpr int TY = (DIR == 0) ? T1 + 2 * R : T1 + 2;
-    static constexpr int FX = (DIR == 0) ? T0 + 1 : T0;                  // faces
-    static constexpr int FY = (DIR == 0) ? T1 : T1 + 1;
-};
 
 // Tile of this workgroup.  Workgroups are dispatched round-robin over the
 // 8 XCDs (each with its own L2); remapping the linear block index so that

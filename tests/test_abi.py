@@ -83,17 +83,19 @@ def test_adjoint_argument_errors():
 
 
 def test_gks_argument_errors():
-    """The gas-kinetic entry points reject 2D grids and bad collision
+    """The gas-kinetic entry points reject missing arrays and bad collision
     parameters before any device work."""
     L = ase.lib()
     G, P = _args()                                # 2D grid
     gk = ase.c_gks(0.05, 1.0)
-    rc = L.ase_step_gks(G, P, C.byref(gk), None, None, None, None, 1, 0.0, None, 0, None)
-    assert rc == -1 and b"1D" in L.ase_last_error()
+    assert L.ase_gks_workspace_bytes(G, P) > L.ase_workspace_bytes(G, P)
+    rc = L.ase_step_gks(G, P, C.byref(gk), None, None, None, None, None, 1, 0.0, None, 0, None)
+    assert rc == -1 and b"null" in L.ase_last_error()
     w = WL.sod(50, 5)
     G1, P1 = C.byref(ase.c_grid(w.grid)), C.byref(ase.c_params(w.params))
+    assert L.ase_gks_workspace_bytes(G1, P1) == L.ase_workspace_bytes(G1, P1)
     bad = ase.c_gks(-1.0, 1.0)
-    rc = L.ase_step_gks(G1, P1, C.byref(bad), None, None, None, None, 1, 0.0, None, 0, None)
+    rc = L.ase_step_gks(G1, P1, C.byref(bad), None, None, None, None, None, 1, 0.0, None, 0, None)
     assert rc == -1 and b"c1" in L.ase_last_error()
     rc = L.ase_gks_flux(P1, C.byref(gk), 4, None, None, None, None, 0.0, None, None, None)
     assert rc == -1 and b"dt" in L.ase_last_error()

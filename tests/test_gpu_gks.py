@@ -209,3 +209,99 @@ def test_graph_replay_equals_eager():
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(a.U, b.U) and torch.equal(a.sx, b.sx) and torch.equal(a.t, b.t)
+
+
+# ---------------------------------------------------------------------------
+# 2D
+# ---------------------------------------------------------------------------
+
+def rel_err2(a, b):
+    """Per conserved quantity, the momentum vector sharing one scale."""
+    a = np.asarray(a).reshape(4, -1)
+    b = np.asarray(b).reshape(4, -1)
+    den = np.maximum(np.abs(b).max(axis=1), 1e-300)
+    den[1] = den[2] = max(float(np.sqrt(b[1] ** 2 + b[2] ** 2).max()), 1e-300)
+    return float(np.max(np.abs(a - b).max(axis=1) / den))
+
+
+def _case2d(name, order):
+    if name == "wave2d":
+        return WL.density_wave_2d(24, order, seed=1, amp=1e-3), 0.0, 0.0
+    if name == "quad":
+        return WL.four_quadrant(45, order, seed=3, ny=37), 0.05, 1.0
+    if name == "config3":
+        return WL.four_quadrant(40, order, states=WL.CONFIG3_STATES), 0.05, 1.0
+    if name == "box":
+        w = WL.four_quadrant(33, order, seed=7, ny=29)
+        w.grid.bc = (WL.BC_REFLECTIVE,) * 4
+        return w, 0.05, 1.0
+    raise KeyError(name)
+
+
+def _evolved2d(w, c1, c2, nsteps):
+    U = w.U.copy()
+    sx, sy = O.sigma_init(w.grid, w.params, U)
+    t = 0.0
+    if nsteps:
+        t, _ = O.step_gks2d(w.grid, w.params, U, sx, sy, 0.0, nsteps, c1=c1, c2=c2)
+    return U, sx, sy, t
+
+
+def _gpu2d(w, c1, c2, U, sx, sy, t, nsteps, t_end=0.0):
+    sim = ase.GksSimulation(w.grid, w.params, U, c1=c1, c2=c2, device=DEV, sx=sx, sy=sy, t=t)
+    hist = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=DEV)
+    sim.run(nsteps, t_end, hist)
+    return host(sim.U), host(sim.sx), host(sim.sy), float(host(sim.t)[0]), host(hist)[:nsteps]
+
+
+STEP_CASES_2D = [("wave2d", 5), ("wave2d", 9), ("quad", 9), ("quad", 7), ("quad", 3), ("config3", 5), ("box", 5)]
+
+
+@pytest.mark.parametrize("name,order", STEP_CASES_2D)
+def test_one_step_2d(name, order):
+    w, c1, c2 = _case2d(name, order)
+    g, p = w.grid, w.params
+    U, sx, sy, t = _evolved2d(w, c1, c2, 2)
+    Ug, sxg, syg, tg, hg = _gpu2d(w, c1, c2, U, sx, sy, t, 1)
+    Uo, sxo, syo = U.copy(), sx.copy(), sy.copy()
+    to, ho = O.step_gks2d(g, p, Uo, sxo, syo, t, 1, c1=c1, c2=c2)
+    assert abs(hg[0] - ho[0]) <= 1e-14 * ho[0]
+    assert rel_err2(g.interior(Ug), g.interior(Uo)) < 1e-12
+    ng = g.ng
+    a = np.concatenate([sxg[ng:ng + g.ny, ng - 1:ng + g.nx].ravel(), syg[ng - 1:ng + g.ny, ng:ng + g.nx].ravel()])
+    b = np.concatenate([sxo[ng:ng + g.ny, ng - 1:ng + g.nx].ravel(), syo[ng - 1:ng + g.ny, ng:ng + g.nx].ravel()])
+    fin = np.isfinite(b)
+    assert np.array_equal(fin, np.isfinite(a))
+    assert np.all(np.abs(a[fin] - b[fin]) <= 1e-9 * np.maximum(np.abs(b[fin]), 1.0))
+
+
+@pytest.mark.parametrize("name,order,nsteps", [("wave2d", 5, 20), ("quad", 9, 12)])
+def test_full_run_2d(name, order, nsteps):
+    w, c1, c2 = _case2d(name, order)
+    g, p = w.grid, w.params
+    U0 = w.U.copy()
+    sx, sy = O.sigma_init(g, p, U0)
+    Ug, _, _, tg, hg = _gpu2d(w, c1, c2, U0, sx, sy, 0.0, nsteps)
+    Uo = U0.copy()
+    to, ho = O.step_gks2d(g, p, Uo, sx.copy(), sy.copy(), 0.0, nsteps, c1=c1, c2=c2)
+    assert abs(tg - to) < 1e-14
+    assert rel_err2(g.interior(Ug), g.interior(Uo)) < 1e-9
+
+
+@pytest.mark.parametrize("order,ns,fac", [(5, (20, 40, 80), 0.5), (9, (20, 40), 1.0)])
+def test_sine_wave_2d_design_order(order, ns, fac):
+    """The 2D sine wave of Table 2 (dt = fac dx^(r/4)): the design order
+    through the GPU path."""
+    errs = []
+    for n in ns:
+        w = WL.density_wave_2d(n, order)
+        g, p = w.grid, w.params
+        p.dt_cap = fac * g.dx ** (order / 4.0)
+        p.cfl = 1e3
+        sim = ase.GksSimulation(g, p, w.U, c1=0.0, c2=0.0, device=DEV)
+        sim.run(10 ** 6, 2.0)
+        assert abs(float(host(sim.t)[0]) - 2.0) < 1e-14
+        errs.append(float(np.abs(g.interior(host(sim.U))[0] - g.interior(w.U)[0]).mean()))
+    orders = [np.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    print("sine wave 2D, order", order, "errors", errs, "orders", orders)
+    assert min(orders) > order - 0.6, (errs, orders)

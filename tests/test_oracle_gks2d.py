@@ -1,0 +1,128 @@
+"""Pins of the oracle's 2D gas-kinetic solver (Sec. 2.1-2.2, App. A): the
+micro slopes against App. A's printed 2D closed form, the 2D point flux
+against the (Table-1-pinned) 1D flux for a state without tangential
+structure, a y-invariant 2D run against the 1D solver, x-y transpose
+symmetry, conservation and uniform flow.
+"""
+import numpy as np
+import pytest
+
+from paper_2410_05489_amd import workloads as WL
+from paper_2410_05489_amd.workloads import Grid, Params
+
+GAMMA = 1.4
+
+
+def _prim2(W):
+    rho = W[0]
+    u, v = W[1] / rho, W[2] / rho
+    return rho, u, v, (GAMMA - 1) * (W[3] - 0.5 * rho * (u * u + v * v))
+
+
+STATES2 = [np.array([1.0, 0.3, -0.2, 2.5]), np.array([0.125, -0.2, 0.05, 0.3]), np.array([2.0, 3.0, 1.0, 9.0])]
+
+
+@pytest.mark.parametrize("W", STATES2)
+def test_micro_slopes_match_printed_2d_closed_form(oracle, W):
+    rng = np.random.default_rng(11)
+    Wn, Wt = rng.normal(size=4), rng.normal(size=4)
+    an, at, A = oracle.gks2_slopes(GAMMA, W, Wn, Wt)
+    rho, U, V, p = _prim2(W)
+    lam = rho / (2 * p)
+    K = (4 - 2 * GAMMA) / (GAMMA - 1)
+
+    def closed(b):
+        b1, b2, b3, b4 = b
+        R4 = 2 * b4 - (U * U + V * V + (K + 2) / (2 * lam)) * b1
+        R3 = b3 - V * b1
+        R2 = b2 - U * b1
+        a4 = 4 * lam * lam / (K + 2) * (R4 - 2 * U * R2 - 2 * V * R3)
+        a3 = 2 * lam * R3 - V * a4
+        a2 = 2 * lam * R2 - U * a4
+        a1 = b1 - U * a2 - V * a3 - 0.5 * a4 * (U * U + V * V + (K + 2) / (2 * lam))
+        return np.array([a1, a2, a3, a4])
+    for got, ref in ((an, closed(Wn / rho)), (at, closed(Wt / rho))):
+        assert np.allclose(got, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+
+
+def test_point_flux_reduces_to_1d(oracle):
+    """No tangential velocity or structure: the 2D flux's mass, normal
+    momentum and energy components are the 1D flux (the v degree of freedom
+    is one more internal one), the tangential momentum flux vanishes."""
+    rng = np.random.default_rng(5)
+    for trial in range(6):
+        rl, rr = rng.uniform(0.2, 2.0, 2)
+        ul, ur = rng.uniform(-1, 1, 2)
+        pl, pr = rng.uniform(0.1, 2.0, 2)
+        W1l = np.array([rl, rl * ul, pl / (GAMMA - 1) + 0.5 * rl * ul * ul])
+        W1r = np.array([rr, rr * ur, pr / (GAMMA - 1) + 0.5 * rr * ur * ur])
+        d1l, d1r = rng.normal(size=3), rng.normal(size=3)
+        to2 = lambda w: np.array([w[0], w[1], 0.0, w[2]])
+        for c1, c2, dt in ((0.0, 0.0, 0.01), (0.05, 1.0, 0.003)):
+            F1, T1 = oracle.gks_point(GAMMA, dt, W1l, d1l, W1r, d1r, c1=c1, c2=c2)
+            F2, T2 = oracle.gks2_point(GAMMA, dt, to2(W1l), to2(d1l), np.zeros(4), to2(W1r), to2(d1r), np.zeros(4),
+                                       c1=c1, c2=c2)
+            assert np.allclose(F2[[0, 1, 3]], F1, rtol=1e-12, atol=1e-13)
+            assert abs(F2[2]) < 1e-14
+            assert np.allclose(T2[[0, 1, 3]], T1, rtol=1e-9, atol=1e-9 * (1 + np.abs(F1).max() / dt))
+
+
+def _strip(order, n, ny, W1):
+    """2D grid of n x ny cells, data W1(x) constant in y (periodic y)."""
+    ng = WL.ghosts_for(order)
+    g = Grid(dim=2, nx=n, ny=ny, ng=ng, dx=1.0 / n, dy=1.0 / n, bc=(WL.BC_TRANSMISSIVE, WL.BC_TRANSMISSIVE,
+                                                                     WL.BC_PERIODIC, WL.BC_PERIODIC))
+    U = WL.empty_state(g)
+    W2 = np.stack([W1[0], W1[1], np.zeros_like(W1[0]), W1[2]])
+    g.interior(U)[...] = W2[:, None, :]
+    return g, U
+
+
+@pytest.mark.parametrize("order", [5, 9])
+def test_y_invariant_run_equals_1d(oracle, order):
+    w1 = WL.riemann_1d(48, (1.0, 0.2, 1.0), (0.4, -0.1, 0.3), order, x_split=0.45)
+    g1, p = w1.grid, w1.params
+    p.positivity_fallback = 1
+    W1 = g1.interior(w1.U)[:, 0, :]
+    g2, U2 = _strip(order, 48, g1.ng, W1)
+    g2.dx = g1.dx
+    g2.dy = g1.dx
+    # the 2D CFL rule adds a transverse term: run both with one fixed dt,
+    # the smallest the 2D rule takes
+    _, _, _, _, h2 = oracle.run_gks2d(g2, p, U2, 6, c1=0.05, c2=1.0)
+    p2 = Params(**{**p.__dict__})
+    p2.dt_cap = float(h2.min())
+    p2.cfl = 1e3
+    U1, _, _, _ = oracle.run_gks(g1, p2, w1.U, 6, c1=0.05, c2=1.0)
+    U2o, _, _, _, _ = oracle.run_gks2d(g2, p2, U2, 6, c1=0.05, c2=1.0)
+    a = g2.interior(U2o)
+    b = g1.interior(U1)[:, 0, :]
+    for row in range(g2.ny):
+        assert np.abs(a[[0, 1, 3], row, :] - b).max() < 1e-12 * np.abs(b).max()
+    assert np.abs(a[2]).max() < 1e-12
+
+
+def test_transpose_symmetry(oracle):
+    order, n = 5, 16
+    w = WL.four_quadrant(n, order, seed=2)
+    g, p = w.grid, w.params
+    U0 = w.U.copy()
+    UT = np.ascontiguousarray(np.transpose(U0, (0, 2, 1))[[0, 2, 1, 3]])
+    Ua, _, _, ta, _ = oracle.run_gks2d(g, p, U0, 3, c1=0.05, c2=1.0)
+    Ub, _, _, tb, _ = oracle.run_gks2d(g, p, UT, 3, c1=0.05, c2=1.0)
+    back = np.transpose(Ub, (0, 2, 1))[[0, 2, 1, 3]]
+    assert abs(ta - tb) < 1e-15
+    assert np.abs(g.interior(back) - g.interior(Ua)).max() < 1e-12 * np.abs(g.interior(Ua)).max()
+
+
+def test_conservation_and_uniform_flow(oracle):
+    w = WL.density_wave_2d(12, 5, seed=4, amp=0.05)
+    g, p = w.grid, w.params
+    U, _, _, _, _ = oracle.run_gks2d(g, p, w.U, 4, c1=0.05, c2=1.0)
+    s0 = g.interior(w.U).sum(axis=(1, 2))
+    s1 = g.interior(U).sum(axis=(1, 2))
+    assert np.allclose(s1, s0, rtol=1e-13, atol=0)
+    U0 = w.U.copy()
+    g.interior(U0)[...] = np.array([1.0, 0.5, -0.3, 2.7])[:, None, None]
+    U1, _, _, _, _ = oracle.run_gks2d(g, p, U0, 3, c1=0.05, c2=1.0)
+    assert np.abs(g.interior(U1) - g.interior(U0)).max() < 1e-13
