@@ -225,6 +225,87 @@ def bench_gks(args):
     print(json.dumps(out), flush=True)
 
 
+def alg_flops_per_cell_gks2d_stage(order: int) -> float:
+    """Algorithmic FP64 operations per cell of one S2O4 stage of the 2D
+    gas-kinetic path, per direction (x and y alike; FMA = 2; divide, square
+    root, exp and erfc = 1):
+      normal reconstruction  : DF sums + 2 faces x 4 vars x (2r-1), values
+                               and slopes
+      tangential (two sides) : 2 x (DF sums + G points x 4 vars x (2r-1) x 3:
+                               values, their slopes, the normal slopes)
+      per Gauss point        : 24 moment sums <(c.psi) u^K v^Q psi_j> of
+                               36 products each (5 operations) 4320, nine
+                               micro slopes 225, Maxwellian moments 170,
+                               three Maxwellians 36, time integrals 40,
+                               accumulation 100, strength 38, rotation and
+                               quadrature 20                       -> 4949
+      update                 : 2 x 4 vars x 4 (L, L_t) + stage combination 16
+    """
+    R = (order - 1) // 2
+    G = R
+    sums = {1: 1, 2: 3, 3: 8, 4: 15}[R]
+    normal = sums + 2 * 2 * 4 * (2 * order - 1)
+    tang = 2 * (sums + G * 4 * (2 * order - 1) * 3)
+    return 2 * (normal + tang + G * 4949) + 48
+
+
+def bench_gks2d(args):
+    """2D gas-kinetic solver (S2O4 steps) on the paper's timing problem:
+    the Configuration-3 Riemann problem (Table 4), order 9, with the mesh of
+    its largest entry (400 x 400, 20 steps) and a 1024 x 1024 grid."""
+    import torch
+    from paper_2410_05489_amd import ase
+    from paper_2410_05489_amd import workloads as WL
+
+    c1, c2 = 0.05, 1.0
+    res = {}
+    for n, steps in ((400, 20), (1024, args.steps)):
+        w = WL.four_quadrant(n, 9, states=WL.CONFIG3_STATES)
+        g, p = w.grid, w.params
+        sim = ase.GksSimulation(g, p, w.U, c1=c1, c2=c2, device="cuda")
+        sim.run(args.warmup)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record()
+        sim.run(steps)
+        stop.record()
+        torch.cuda.synchronize()
+        res[n] = (start.elapsed_time(stop), steps, sim, g, p)
+    ms, steps, sim, g, p = res[1024]
+    n = g.nx * g.ny
+    finite = bool(torch.isfinite(sim.U).all().item())
+    prof_steps = max(1, min(steps, 20))
+    ase.profile_enable(True)
+    sim.run(prof_steps)
+    torch.cuda.synchronize()
+    kern = {k: ase.profile_read(k) for k in ("gks_2d_recon", "gks_2d_flux", "gks_2d_update", "bc", "cfl")}
+    ase.profile_enable(False)
+    value = n * steps / (ms / 1e3) / 1e6
+    step_flops = 2 * alg_flops_per_cell_gks2d_stage(9) * n
+    kern_ms = sum(v[0] for v in kern.values()) / prof_steps
+    tot, nl = kern["gks_2d_flux"]
+    ms400 = res[400][0]
+    out = {"metric": "Mcell-updates/s, 2D gas-kinetic S2O4 step, order 9 (FP64)", "value": round(value, 3),
+           "unit": "Mcell-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "ms_per_step": round(ms / steps, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "gks_config3_1024x1024_r9", "order": 9, "nx": g.nx, "ny": g.ny, "c1": c1,
+                      "c2": c2, "cfl": p.cfl},
+           "finite": finite,
+           "table4_config": {"workload": "gks_config3_400x400_r9", "steps": 20, "seconds": round(ms400 / 1e3, 5),
+                             "paper_seconds": 165.221,
+                             "paper_hardware": "one core of an AMD EPYC 7401 (context, not a target)"},
+           "roofline": {"bound": "alu", "achieved": round(step_flops / (kern_ms / 1e3) / 1e12, 3),
+                        "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(step_flops / (kern_ms / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4),
+                        "traffic": None, "kernel": "whole 2D GKS step (recon + flux + update kernels), order 9",
+                        "alg_flops_per_step": step_flops,
+                        "flux_avg_launch_ms": round(tot / max(nl, 1), 4),
+                        "kernel_ms_per_step": {k: round(v[0] / prof_steps, 4) for k, v in kern.items() if v[1]}}}
+    print(json.dumps(out), flush=True)
+
+
 def measure_adjoint(nsteps=100, every=10, reps=3):
     """Adjoint/forward wall-time ratio on the batched workload: 256 Riemann
     instances of 64..4096 cells, order 9, `nsteps` steps; J = sum_k dx_k sum p
@@ -331,6 +412,8 @@ def main():
         return bench_batched(args)
     if args.workload == "gks1d":
         return bench_gks(args)
+    if args.workload == "gks2d":
+        return bench_gks2d(args)
     if args.workload == "adjoint":
         print(json.dumps({"metric": "adjoint/forward wall-time ratio, batched 1D order 9", **measure_adjoint()}),
               flush=True)
