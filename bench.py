@@ -82,6 +82,8 @@ def make_workload(name):
         return WL.four_quadrant(4096, 9, seed=0, nsteps=200)
     if name == "jet":
         return WL.jet(1600, 800, 7, nsteps=500)
+    if name == "dmr":
+        return WL.double_mach(960, 240, 9, nsteps=200)
     raise SystemExit(f"unknown workload {name}")
 
 

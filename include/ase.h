@@ -63,7 +63,8 @@ enum {
  * INFLOW_SLOT: Dirichlet inflow state in the ghost cells of the slot rows
  * (x sides only); REFLECTIVE: slip wall, the ghost cells mirror the interior
  * cells with the momentum normal to the wall reversed (needs n >= ng). */
-enum { ASE_BC_PERIODIC = 0, ASE_BC_TRANSMISSIVE = 1, ASE_BC_INFLOW_SLOT = 2, ASE_BC_REFLECTIVE = 3 };
+enum { ASE_BC_PERIODIC = 0, ASE_BC_TRANSMISSIVE = 1, ASE_BC_INFLOW_SLOT = 2, ASE_BC_REFLECTIVE = 3,
+       ASE_BC_WALL_INFLOW = 4, ASE_BC_MOVING_SHOCK = 5 };
 
 /* Flags of ase_params_t. */
 enum {
@@ -95,6 +96,19 @@ typedef struct {
     double slot_lo, slot_hi;  /* INFLOW_SLOT applies to ghost cells of rows
                            whose centre y lies in (slot_lo, slot_hi); other
                            rows of that side are transmissive.              */
+    /* Boundaries of the double Mach reflection (Sec. 4, Example 4), y sides
+     * only.  WALL_INFLOW (y-lo): ghost cells of columns whose centre x lies
+     * below wall_x0 take the inflow state, the others mirror the wall (as
+     * REFLECTIVE).  MOVING_SHOCK (y-hi): ghost cells of columns whose centre
+     * x lies below shock_x0 + shock_speed t take the inflow state, the
+     * others the outer state; t is the time of the stage being filled
+     * (ase_step, ase_step_gks; the granular ase_bc_fill / ase_sigma_init
+     * use t = 0).  Lagged strengths of their ghost faces are first-order
+     * ones. */
+    double x0;                /* left edge of the domain (column centres)    */
+    double wall_x0;
+    double shock_x0, shock_speed;
+    double outer[4];          /* conservative state beyond the moving shock  */
 } ase_grid_t;
 
 /* Method parameters. */

@@ -37,7 +37,8 @@
 /* Problem statement                                                          */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_INFLOW_SLOT = 2, ORC_BC_REFLECTIVE = 3 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_INFLOW_SLOT = 2, ORC_BC_REFLECTIVE = 3,
+       ORC_BC_WALL_INFLOW = 4, ORC_BC_MOVING_SHOCK = 5 };
 
 typedef struct {
     int32_t dim;        /* 1 or 2 */
@@ -49,6 +50,12 @@ typedef struct {
     double y0;          /* lower edge of the domain in y (slot test) */
     double inflow[4];   /* conservative state of inflow ghost cells */
     double slot_lo, slot_hi;
+    /* double Mach reflection (Sec. 4, Example 4): the y-lo side is inflow
+       below wall_x0 and a slip wall beyond; the y-hi side is inflow below
+       the shock position shock_x0 + shock_speed t and the outer state
+       beyond (column centres, x0 the domain's left edge) */
+    double x0, wall_x0, shock_x0, shock_speed;
+    double outer[4];
 } orc_grid;
 
 /* Source of the interface states the DF strengths are computed from        */
@@ -471,7 +478,7 @@ static int in_slot(const orc_grid *g, int J)
 }
 
 /* Ghost cells: x first on interior rows, then y on every column. */
-static void bc_fill_cells(const orc_grid *g, double *U)
+static void bc_fill_cells(const orc_grid *g, double *U, double t)
 {
     int nv = nvar_of(g), ng = g->ng, NX = NXof(g), NY = NYof(g);
     size_t P = plane(g);
@@ -505,13 +512,19 @@ static void bc_fill_cells(const orc_grid *g, double *U)
             double *Uv = U + v * P;
             double flip = (v == 2) ? -1.0 : 1.0;   /* y momentum */
             for (int I = 0; I < NX; ++I) {
+                /* centre of the column (double Mach reflection sides) */
+                double xc = g->x0 + ((double)(I - ng) + 0.5) * g->dx;
                 if (g->bc[2] == ORC_BC_PERIODIC) Uv[(size_t)Jl * g->ld + I] = Uv[(size_t)(Jl + g->ny) * g->ld + I];
-                else if (g->bc[2] == ORC_BC_REFLECTIVE)
+                else if (g->bc[2] == ORC_BC_REFLECTIVE ||
+                         (g->bc[2] == ORC_BC_WALL_INFLOW && !(xc < g->wall_x0)))
                     Uv[(size_t)Jl * g->ld + I] = flip * Uv[(size_t)(ng + k) * g->ld + I];
+                else if (g->bc[2] == ORC_BC_WALL_INFLOW) Uv[(size_t)Jl * g->ld + I] = g->inflow[v];
                 else Uv[(size_t)Jl * g->ld + I] = Uv[(size_t)ng * g->ld + I];
                 if (g->bc[3] == ORC_BC_PERIODIC) Uv[(size_t)Jh * g->ld + I] = Uv[(size_t)(Jh - g->ny) * g->ld + I];
                 else if (g->bc[3] == ORC_BC_REFLECTIVE)
                     Uv[(size_t)Jh * g->ld + I] = flip * Uv[(size_t)(ng + g->ny - 1 - k) * g->ld + I];
+                else if (g->bc[3] == ORC_BC_MOVING_SHOCK)
+                    Uv[(size_t)Jh * g->ld + I] = (xc < g->shock_x0 + g->shock_speed * t) ? g->inflow[v] : g->outer[v];
                 else Uv[(size_t)Jh * g->ld + I] = Uv[(size_t)(ng + g->ny - 1) * g->ld + I];
             }
         }
@@ -555,7 +568,7 @@ static void sigma_all_first_order(const orc_grid *g, const orc_params *p, const 
 /* Boundary step of a stage: ghost cells, then the strengths the stage's    */
 /* DF factors read -- derived non-flux faces (lagged source) or first-order */
 /* strengths of the stage input on every face (first-order source).        */
-static void stage_bc(const orc_grid *g, const orc_params *p, double *U, double *sx, double *sy);
+static void stage_bc(const orc_grid *g, const orc_params *p, double *U, double *sx, double *sy, double t);
 
 static int wrap(int i, int n) { return ((i % n) + n) % n; }
 
@@ -631,9 +644,11 @@ static void bc_fill_sigma(const orc_grid *g, const orc_params *p, const double *
     }
 }
 
-static void stage_bc(const orc_grid *g, const orc_params *p, double *U, double *sx, double *sy)
+/* Ghost cells at time t (the time of the stage input; only the moving    */
+/* shock side depends on it), then the strengths a stage reads.            */
+static void stage_bc(const orc_grid *g, const orc_params *p, double *U, double *sx, double *sy, double t)
 {
-    bc_fill_cells(g, U);
+    bc_fill_cells(g, U, t);
     if (p->df_source == ORC_DF_FIRST_ORDER) sigma_all_first_order(g, p, U, sx, sy);
     else bc_fill_sigma(g, p, U, sx, sy);
 }
@@ -893,7 +908,13 @@ static int check_args(const orc_grid *g, const orc_params *p)
     if (g->dim == 2 && (g->bc[2] == ORC_BC_PERIODIC) != (g->bc[3] == ORC_BC_PERIODIC)) return -1;
     if (g->dim == 2 && (g->bc[2] == ORC_BC_INFLOW_SLOT || g->bc[3] == ORC_BC_INFLOW_SLOT)) return -1;
     for (int k = 0; k < (g->dim == 2 ? 4 : 2); ++k)
-        if (g->bc[k] < ORC_BC_PERIODIC || g->bc[k] > ORC_BC_REFLECTIVE) return -1;
+        if (g->bc[k] < ORC_BC_PERIODIC || g->bc[k] > ORC_BC_MOVING_SHOCK) return -1;
+    /* the double Mach reflection sides: wall/inflow on y-lo, moving shock on y-hi */
+    for (int k = 0; k < 4; ++k) {
+        if (g->bc[k] == ORC_BC_WALL_INFLOW && !(k == 2 && g->dim == 2)) return -1;
+        if (g->bc[k] == ORC_BC_MOVING_SHOCK && !(k == 3 && g->dim == 2)) return -1;
+    }
+    if (g->dim == 2 && g->bc[2] == ORC_BC_WALL_INFLOW && g->ny < g->ng) return -1;
     /* a mirror or a wrap reads ng interior cells */
     if ((g->bc[0] == ORC_BC_REFLECTIVE || g->bc[1] == ORC_BC_REFLECTIVE) && g->nx < g->ng) return -1;
     if (g->dim == 2 && (g->bc[2] == ORC_BC_REFLECTIVE || g->bc[3] == ORC_BC_REFLECTIVE) && g->ny < g->ng) return -1;
@@ -910,7 +931,16 @@ int orc_bc_fill(const orc_grid *g, const orc_params *p, double *U, double *sx, d
 {
     int e = check_args(g, p);
     if (e) return e;
-    stage_bc(g, p, U, sx, sy);
+    stage_bc(g, p, U, sx, sy, 0.0);
+    return 0;
+}
+
+/* As orc_bc_fill with the ghost cells at time t (the moving-shock side).   */
+int orc_bc_fill_at(const orc_grid *g, const orc_params *p, double t, double *U, double *sx, double *sy)
+{
+    int e = check_args(g, p);
+    if (e) return e;
+    stage_bc(g, p, U, sx, sy, t);
     return 0;
 }
 
@@ -920,7 +950,7 @@ int orc_sigma_init(const orc_grid *g, const orc_params *p, double *U, double *sx
 {
     int e = check_args(g, p);
     if (e) return e;
-    bc_fill_cells(g, U);
+    bc_fill_cells(g, U, 0.0);
     sigma_all_first_order(g, p, U, sx, sy);
     return 0;
 }
@@ -1035,7 +1065,7 @@ int orc_residual(const orc_grid *g, const orc_params *p, double *U, double *sx, 
 {
     int e = check_args(g, p);
     if (e) return e;
-    stage_bc(g, p, U, sx, sy);
+    stage_bc(g, p, U, sx, sy, 0.0);
     size_t n = plane(g);
     double *tx = sx_new ? sx_new : malloc(n * sizeof(double));
     double *ty = (g->dim == 2) ? (sy_new ? sy_new : malloc(n * sizeof(double))) : NULL;
@@ -1075,18 +1105,18 @@ int orc_step(const orc_grid *g, const orc_params *p, double *U, double *sx, doub
         /* filled by the boundary step before they are read.                    */
         memcpy(U1, U, n * sizeof(double));
         memcpy(U2, U, n * sizeof(double));
-        stage_bc(g, p, U, sx, sy);
+        stage_bc(g, p, U, sx, sy, *t);
         double dt = cfl_dt(g, p, U, *t, t_end);
-        /* stage 1 */
+        /* stage 1 (stage inputs at t, t + dt, t + dt/2) */
         memcpy(sxa, sx, P * sizeof(double));
         memcpy(sya, sy ? sy : sx, P * sizeof(double));
         if (residual(g, p, U, sx, sy, L, sxa, g->dim == 2 ? sya : NULL)) goto fail;
         stage_combine(g, 1, dt, U, U, L, U1);
-        stage_bc(g, p, U1, sxa, g->dim == 2 ? sya : NULL);
+        stage_bc(g, p, U1, sxa, g->dim == 2 ? sya : NULL, *t + dt);
         /* stage 2 */
         if (residual(g, p, U1, sxa, sya, L, sx, g->dim == 2 ? sy : NULL)) goto fail;
         stage_combine(g, 2, dt, U, U1, L, U2);
-        stage_bc(g, p, U2, sx, g->dim == 2 ? sy : NULL);
+        stage_bc(g, p, U2, sx, g->dim == 2 ? sy : NULL, *t + 0.5 * dt);
         /* stage 3 */
         if (residual(g, p, U2, sx, sy, L, sxa, g->dim == 2 ? sya : NULL)) goto fail;
         stage_combine(g, 3, dt, U, U2, L, U);
@@ -1528,7 +1558,7 @@ int orc_step_gks(const orc_grid *g, const orc_params *p, const orc_gks *gk, doub
     int taken = 0;
     for (int s = 0; s < nsteps; ++s) {
         if (t_end > 0.0 && *t >= t_end) break;
-        stage_bc(g, p, U, sx, NULL);
+        stage_bc(g, p, U, sx, NULL, *t);
         double dt = cfl_dt(g, p, U, *t, t_end);
         memcpy(Ws, U, n * sizeof(double));
         memcpy(sxa, sx, P * sizeof(double));
@@ -1538,7 +1568,7 @@ int orc_step_gks(const orc_grid *g, const orc_params *p, const orc_gks *gk, doub
                 size_t c = (size_t)v * P + (size_t)(i + g->ng);
                 Ws[c] = U[c] + 0.5 * dt * L0[c] + 0.125 * dt * dt * T0[c];
             }
-        stage_bc(g, p, Ws, sxa, NULL);
+        stage_bc(g, p, Ws, sxa, NULL, *t + 0.5 * dt);
         residual_gks1d(g, p, gk, Ws, sxa, dt, L1, T1, sx);
         for (int v = 0; v < 3; ++v)
             for (int i = 0; i < g->nx; ++i) {
@@ -1561,7 +1591,7 @@ int orc_residual_gks(const orc_grid *g, const orc_params *p, const orc_gks *gk, 
     int e = check_args(g, p);
     if (e) return e;
     if (g->dim != 1) return -1;
-    stage_bc(g, p, U, sx, NULL);
+    stage_bc(g, p, U, sx, NULL, 0.0);
     return residual_gks1d(g, p, gk, U, sx, dt, L, Lt, sx_new);
 }
 
@@ -2075,7 +2105,7 @@ int orc_step_gks2d(const orc_grid *g, const orc_params *p, const orc_gks *gk, do
     int taken = 0;
     for (int s = 0; s < nsteps; ++s) {
         if (t_end > 0.0 && *t >= t_end) break;
-        stage_bc(g, p, U, sx, sy);
+        stage_bc(g, p, U, sx, sy, *t);
         double dt = cfl_dt(g, p, U, *t, t_end);
         memcpy(Ws, U, n * sizeof(double));
         memcpy(sxa, sx, P * sizeof(double));
@@ -2087,7 +2117,7 @@ int orc_step_gks2d(const orc_grid *g, const orc_params *p, const orc_gks *gk, do
                     size_t c = (size_t)v * P + (size_t)(j + g->ng) * g->ld + (size_t)(i + g->ng);
                     Ws[c] = U[c] + 0.5 * dt * L0[c] + 0.125 * dt * dt * T0[c];
                 }
-        stage_bc(g, p, Ws, sxa, sya);
+        stage_bc(g, p, Ws, sxa, sya, *t + 0.5 * dt);
         residual_gks2d(g, p, gk, Ws, sxa, sya, dt, L1, T1, sx, sy);
         for (int v = 0; v < 4; ++v)
             for (int j = 0; j < g->ny; ++j)

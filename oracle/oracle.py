@@ -24,7 +24,8 @@ class OrcGrid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("ng", C.c_int32),
                 ("ld", C.c_int32), ("bc", C.c_int32 * 4), ("dx", C.c_double), ("dy", C.c_double),
                 ("y0", C.c_double), ("inflow", C.c_double * 4), ("slot_lo", C.c_double),
-                ("slot_hi", C.c_double)]
+                ("slot_hi", C.c_double), ("x0", C.c_double), ("wall_x0", C.c_double), ("shock_x0", C.c_double),
+                ("shock_speed", C.c_double), ("outer", C.c_double * 4)]
 
 
 class OrcParams(C.Structure):
@@ -69,6 +70,7 @@ def lib():
         L.orc_sigma_point.restype = C.c_double
         L.orc_lf_point.argtypes = [vp, vp, _dp, _dp, C.c_int, _dp]
         L.orc_lf_point.restype = None
+        L.orc_bc_fill_at.argtypes = [vp, vp, C.c_double, _dp, _dp, _dp]
         L.orc_step_gks.argtypes = [vp, vp, vp, _dp, _dp, _dp, C.c_int, C.c_double, _dp]
         L.orc_residual_gks.argtypes = [vp, vp, vp, _dp, _dp, C.c_double, _dp, _dp, _dp]
         L.orc_gks_moments.argtypes = [C.c_double, _dp, _dp, _dp, _dp, _dp]
@@ -97,6 +99,9 @@ def c_grid(g) -> OrcGrid:
         s.inflow[k] = float(g.inflow[k])
     s.dx, s.dy, s.y0 = g.dx, g.dy, g.y0
     s.slot_lo, s.slot_hi = g.slot_lo, g.slot_hi
+    s.x0, s.wall_x0, s.shock_x0, s.shock_speed = g.x0, g.wall_x0, g.shock_x0, g.shock_speed
+    for k in range(4):
+        s.outer[k] = float(g.outer[k])
     return s
 
 
@@ -141,6 +146,12 @@ def sigma_init(g, p, U):
 def bc_fill(g, p, U, sx, sy):
     G, P = _gp(g, p)
     _check(lib().orc_bc_fill(G, P, _ptr(U), _ptr(sx), _ptr(sy)), "bc_fill")
+
+
+def bc_fill_at(g, p, t, U, sx, sy):
+    """Ghost cells (moving-shock side at time t) and non-flux strengths."""
+    G, P = _gp(g, p)
+    _check(lib().orc_bc_fill_at(G, P, float(t), _ptr(U), _ptr(sx), _ptr(sy)), "bc_fill_at")
 
 
 def reconstruct(g, p, d, U, sx, sy, want_level=False):

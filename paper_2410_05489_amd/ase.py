@@ -27,7 +27,8 @@ class AseGrid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("ng", C.c_int32),
                 ("ld", C.c_int32), ("bc", C.c_int32 * 4), ("dx", C.c_double), ("dy", C.c_double),
                 ("y0", C.c_double), ("inflow", C.c_double * 4), ("slot_lo", C.c_double),
-                ("slot_hi", C.c_double)]
+                ("slot_hi", C.c_double), ("x0", C.c_double), ("wall_x0", C.c_double), ("shock_x0", C.c_double),
+                ("shock_speed", C.c_double), ("outer", C.c_double * 4)]
 
 
 class AseParams(C.Structure):
@@ -111,6 +112,9 @@ def c_grid(g: Grid) -> AseGrid:
         s.bc[k] = int(g.bc[k])
         s.inflow[k] = float(g.inflow[k])
     s.dx, s.dy, s.y0, s.slot_lo, s.slot_hi = g.dx, g.dy, g.y0, g.slot_lo, g.slot_hi
+    s.x0, s.wall_x0, s.shock_x0, s.shock_speed = g.x0, g.wall_x0, g.shock_x0, g.shock_speed
+    for k in range(4):
+        s.outer[k] = float(g.outer[k])
     return s
 
 

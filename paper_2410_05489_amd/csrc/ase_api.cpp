@@ -49,7 +49,15 @@ int validate(const ase_grid_t *g, const ase_params_t *p, Geo *geo)
     if (g->ld < g->nx + 2 * g->ng) return fail(ASE_ERR_ARG, "ld must be >= nx + 2 ng");
     if (!(g->dx > 0.0) || (g->dim == 2 && !(g->dy > 0.0))) return fail(ASE_ERR_ARG, "dx, dy must be > 0");
     for (int k = 0; k < 4; ++k)
-        if (g->bc[k] < 0 || g->bc[k] > 3) return fail(ASE_ERR_ARG, "unknown boundary code");
+        if (g->bc[k] < 0 || g->bc[k] > ASE_BC_MOVING_SHOCK) return fail(ASE_ERR_ARG, "unknown boundary code");
+    for (int k = 0; k < 4; ++k) {
+        if (g->bc[k] == ASE_BC_WALL_INFLOW && !(k == 2 && g->dim == 2))
+            return fail(ASE_ERR_ARG, "WALL_INFLOW is a 2D y-lo boundary only");
+        if (g->bc[k] == ASE_BC_MOVING_SHOCK && !(k == 3 && g->dim == 2))
+            return fail(ASE_ERR_ARG, "MOVING_SHOCK is a 2D y-hi boundary only");
+    }
+    if (g->dim == 2 && g->bc[2] == ASE_BC_WALL_INFLOW && g->ny < g->ng)
+        return fail(ASE_ERR_ARG, "a y wall needs ny >= ng");
     if ((g->bc[0] == ASE_BC_PERIODIC) != (g->bc[1] == ASE_BC_PERIODIC))
         return fail(ASE_ERR_ARG, "periodic x boundaries must pair");
     if (g->dim == 2 && (g->bc[2] == ASE_BC_PERIODIC) != (g->bc[3] == ASE_BC_PERIODIC))
@@ -209,7 +217,7 @@ extern "C" {
 
 const char *ase_last_error(void) { return g_err.c_str(); }
 
-int ase_version(void) { return 2; }
+int ase_version(void) { return 3; }
 
 int ase_bc_fill(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, void *stream)
 {
@@ -356,9 +364,14 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
 
     // Ghost cells and the strengths the stage reads (lagged or first order).
     const bool fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) != 0;
-    auto stage_bc = [&](double *Us, double *sxs_, double *sys_) {
-        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs_, sys_, st);
-        else launch_bc_fill(*g, geo, mc, Us, sxs_, sys_, st);
+    // stage inputs at t_n, t_n + dt, t_n + dt/2; after the dt kernel *t
+    // holds t_n + dt, so the times are *t (first fill: before it), *t and
+    // *t - dt/2
+    auto stage_bc = [&](double *Us, double *sxs_, double *sys_, double ct) {
+        // (dt is read only with a nonzero ct: before the first dt kernel it is unset)
+        const double *dtp = ct != 0.0 ? w.scal : nullptr;
+        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs_, sys_, st, t, dtp, ct);
+        else launch_bc_fill(*g, geo, mc, Us, sxs_, sys_, st, t, dtp, ct);
     };
     double *sxs[2] = {sx, w.sxa};
     double *sys[2] = {geo.dim == 2 ? sy : sx, w.sya};
@@ -367,7 +380,7 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
         double *sxc = sxs[cur], *syc = sys[cur], *sxn = sxs[cur ^ 1], *syn = sys[cur ^ 1];
         {
             ProfScope ps(ASE_KCLASS_BC, st);
-            stage_bc(U, sxc, syc);
+            stage_bc(U, sxc, syc, 0.0);
         }
         {
             ProfScope ps(ASE_KCLASS_CFL, st);
@@ -381,7 +394,7 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
         for (int k = 0; k < 3; ++k) {
             if (k > 0) {
                 ProfScope ps(ASE_KCLASS_BC, st);
-                stage_bc(in_st[k], sx_in[k], sy_in[k]);
+                stage_bc(in_st[k], sx_in[k], sy_in[k], k == 1 ? 0.0 : -0.5);
             }
             a.U = in_st[k];
             a.sx = sx_in[k];
@@ -530,9 +543,12 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
     const bool fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) != 0;
     double *syv = geo.dim == 2 ? sy : sx;    // 1D: the y-strength argument is unused
     double *syav = geo.dim == 2 ? w.sya : w.sxa;
-    auto stage_bc = [&](double *Us, double *sxs, double *sys) {
-        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs, sys, st);
-        else launch_bc_fill(*g, geo, mc, Us, sxs, sys, st);
+    // stage inputs at t_n (before the dt kernel) and t_n + dt/2 = *t - dt/2
+    auto stage_bc = [&](double *Us, double *sxs, double *sys, double ct) {
+        // (dt is read only with a nonzero ct: before the first dt kernel it is unset)
+        const double *dtp = ct != 0.0 ? w.scal : nullptr;
+        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs, sys, st, t, dtp, ct);
+        else launch_bc_fill(*g, geo, mc, Us, sxs, sys, st, t, dtp, ct);
     };
     // workspace: W* in U1, L(W^n) in U2, L_t(W^n) in Res, stage-1 strengths in sxa / sya
     Gks1DArgs a1;
@@ -630,7 +646,7 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
     for (int s = 0; s < nsteps; ++s) {
         {
             ProfScope ps(ASE_KCLASS_BC, st);
-            stage_bc(U, sx, syv);
+            stage_bc(U, sx, syv, 0.0);
         }
         {
             ProfScope ps(ASE_KCLASS_CFL, st);
@@ -640,7 +656,7 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
         stage(1);
         {
             ProfScope ps(ASE_KCLASS_BC, st);
-            stage_bc(w.U1, w.sxa, syav);
+            stage_bc(w.U1, w.sxa, syav, -0.5);
         }
         stage(2);
     }

@@ -40,10 +40,13 @@ size_t workspace_bytes(const Geo &geo);
 int carve_workspace(const Geo &geo, void *ws, size_t bytes, Workspace *w);
 
 // Launchers (asynchronous on `st`).
+// Ghost cells at the stage time *t + ct * *dt (device scalars; t null: time
+// 0, dt null: *t), which only the moving-shock side reads.
 void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx, double *sy,
-                    hipStream_t st);
+                    hipStream_t st, const double *t = nullptr, const double *dt = nullptr, double ct = 0.0);
 void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
-                       double *sy, hipStream_t st);
+                       double *sy, hipStream_t st, const double *t = nullptr, const double *dt = nullptr,
+                       double ct = 0.0);
 void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,
                 const double *t_in, double *t_out, double t_end, double *dt, double *skip, double *dt_hist,
                 double *part, int nparts, hipStream_t st);

@@ -24,6 +24,13 @@ struct BCInfo {
     long long plane;
     double y0, dy, slot_lo, slot_hi;
     double inflow[4];
+    // double Mach reflection sides
+    double x0, dx, wall_x0, shock_x0, shock_speed;
+    double outer[4];
+    // time of the stage being filled: *t + ct * *dt (t, dt device scalars;
+    // null t: time 0)
+    const double *t, *dt;
+    double ct;
 };
 
 BCInfo make_bc(const ase_grid_t &g, const Geo &geo)
@@ -33,7 +40,18 @@ BCInfo make_bc(const ase_grid_t &g, const Geo &geo)
     for (int k = 0; k < 4; ++k) { b.bc[k] = g.bc[k]; b.inflow[k] = g.inflow[k]; }
     b.plane = geo.plane;
     b.y0 = g.y0; b.dy = g.dy; b.slot_lo = g.slot_lo; b.slot_hi = g.slot_hi;
+    b.x0 = g.x0; b.dx = g.dx; b.wall_x0 = g.wall_x0; b.shock_x0 = g.shock_x0; b.shock_speed = g.shock_speed;
+    for (int k = 0; k < 4; ++k) b.outer[k] = g.outer[k];
+    b.t = nullptr;
+    b.dt = nullptr;
+    b.ct = 0.0;
     return b;
+}
+
+__device__ __forceinline__ double bc_time(const BCInfo &b)
+{
+    if (b.t == nullptr) return 0.0;
+    return b.dt == nullptr ? *b.t : *b.t + b.ct * *b.dt;
 }
 
 __device__ __forceinline__ bool in_slot(const BCInfo &b, int J)
@@ -47,21 +65,30 @@ __device__ __forceinline__ bool in_slot(const BCInfo &b, int J)
 // mapped by the y rule, then the column by the x rule within that row (so
 // corners are the y rule applied to x-filled values).  A reflective (slip)
 // side mirrors the cells and reverses the momentum normal to it: flipx /
-// flipy tell the caller to negate the x / y momentum.  Returns false when
-// the cell takes the inflow state.
-__device__ __forceinline__ bool src_cell(const BCInfo &b, int I, int J, int &Is, int &Js, bool &flipx, bool &flipy)
+// flipy tell the caller to negate the x / y momentum.  Returns SRC_CELL, or
+// SRC_INFLOW / SRC_OUTER when the cell takes that fixed state (a fixed
+// y-side state covers the corner columns too).
+enum { SRC_CELL = 0, SRC_INFLOW = 1, SRC_OUTER = 2 };
+
+__device__ __forceinline__ int src_cell(const BCInfo &b, int I, int J, int &Is, int &Js, bool &flipx, bool &flipy)
 {
     Js = J;
     flipx = flipy = false;
     if (b.dim == 2) {
         const int j = J - b.ng;
+        const double xc = b.x0 + ((double)(I - b.ng) + 0.5) * b.dx;
         if (j < 0) {
             if (b.bc[2] == ASE_BC_PERIODIC) Js = J + b.ny;
-            else if (b.bc[2] == ASE_BC_REFLECTIVE) { Js = 2 * b.ng - 1 - J; flipy = true; }
+            else if (b.bc[2] == ASE_BC_REFLECTIVE || (b.bc[2] == ASE_BC_WALL_INFLOW && !(xc < b.wall_x0))) {
+                Js = 2 * b.ng - 1 - J;
+                flipy = true;
+            } else if (b.bc[2] == ASE_BC_WALL_INFLOW) return SRC_INFLOW;
             else Js = b.ng;
         } else if (j >= b.ny) {
             if (b.bc[3] == ASE_BC_PERIODIC) Js = J - b.ny;
             else if (b.bc[3] == ASE_BC_REFLECTIVE) { Js = 2 * (b.ny + b.ng) - 1 - J; flipy = true; }
+            else if (b.bc[3] == ASE_BC_MOVING_SHOCK)
+                return xc < b.shock_x0 + b.shock_speed * bc_time(b) ? SRC_INFLOW : SRC_OUTER;
             else Js = b.ng + b.ny - 1;
         }
     }
@@ -69,16 +96,16 @@ __device__ __forceinline__ bool src_cell(const BCInfo &b, int I, int J, int &Is,
     const int i = I - b.ng;
     if (i < 0) {
         if (b.bc[0] == ASE_BC_PERIODIC) Is = I + b.nx;
-        else if (b.bc[0] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return false;
+        else if (b.bc[0] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return SRC_INFLOW;
         else if (b.bc[0] == ASE_BC_REFLECTIVE) { Is = 2 * b.ng - 1 - I; flipx = true; }
         else Is = b.ng;
     } else if (i >= b.nx) {
         if (b.bc[1] == ASE_BC_PERIODIC) Is = I - b.nx;
-        else if (b.bc[1] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return false;
+        else if (b.bc[1] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return SRC_INFLOW;
         else if (b.bc[1] == ASE_BC_REFLECTIVE) { Is = 2 * (b.nx + b.ng) - 1 - I; flipx = true; }
         else Is = b.ng + b.nx - 1;
     }
-    return true;
+    return SRC_CELL;
 }
 
 // Ghost frame: full ghost rows (2D) followed by the ghost columns of the
@@ -112,15 +139,16 @@ __device__ __forceinline__ void cell_value(const BCInfo &b, const double *U, int
 {
     int Is, Js;
     bool fx, fy;
-    if (src_cell(b, I, J, Is, Js, fx, fy)) {
-        const long long src = (long long)Js * b.ld + Is;
+    const int src = src_cell(b, I, J, Is, Js, fx, fy);
+    if (src == SRC_CELL) {
+        const long long pos = (long long)Js * b.ld + Is;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + src];
+        for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + pos];
         if (fx) W[1] = -W[1];
         if (NV == 4 && fy) W[2] = -W[2];
     } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) W[v] = b.inflow[v];
+        for (int v = 0; v < NV; ++v) W[v] = src == SRC_INFLOW ? b.inflow[v] : b.outer[v];
     }
 }
 
@@ -1550,18 +1578,24 @@ int grid_blocks(long long n)
 // ---------------------------------------------------------------------------
 
 void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx, double *sy,
-                    hipStream_t st)
+                    hipStream_t st, const double *t, const double *dt, double ct)
 {
-    const BCInfo b = make_bc(g, geo);
+    BCInfo b = make_bc(g, geo);
+    b.t = t;
+    b.dt = dt;
+    b.ct = ct;
     const int nb = grid_blocks(frame_size(b));
     if (geo.nv == 4) k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
     else k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
 }
 
 void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
-                       double *sy, hipStream_t st)
+                       double *sy, hipStream_t st, const double *t, const double *dt, double ct)
 {
-    const BCInfo b = make_bc(g, geo);
+    BCInfo b = make_bc(g, geo);
+    b.t = t;
+    b.dt = dt;
+    b.ct = ct;
     const int nb = grid_blocks((long long)geo.NY * geo.NX);
     if (geo.nv == 4) k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
     else k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);

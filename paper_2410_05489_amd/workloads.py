@@ -20,6 +20,8 @@ BC_PERIODIC = 0
 BC_TRANSMISSIVE = 1
 BC_INFLOW_SLOT = 2
 BC_REFLECTIVE = 3   # slip wall: mirrored cells, normal momentum reversed
+BC_WALL_INFLOW = 4  # y-lo: inflow state below wall_x0, slip wall beyond
+BC_MOVING_SHOCK = 5 # y-hi: inflow state behind the moving shock, outer state ahead
 
 # Interface states the DF strengths come from: the previous stage's
 # Gauss-point states (lagged) or the current stage's cell averages.
@@ -41,6 +43,11 @@ class Grid:
     slot_lo: float = 0.0
     slot_hi: float = 0.0
     ld: int = 0
+    x0: float = 0.0
+    wall_x0: float = 0.0
+    shock_x0: float = 0.0
+    shock_speed: float = 0.0
+    outer: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
 
     def __post_init__(self):
         if self.ld == 0:
@@ -252,6 +259,46 @@ def density_wave_2d(n: int, order: int, seed: int = -1, amp: float = 1e-3, cfl: 
     U = empty_state(g)
     _fill_interior(g, U, W)
     return Workload("density_wave_2d", g, Params(order=order, gamma=gamma, cfl=cfl), U, 10 ** 9, 0.0)
+
+
+def double_mach(nx: int = 960, ny: int = 240, order: int = 9, t_end: float = 0.2, cfl: float = 0.5,
+                nsteps: int = 100000) -> Workload:
+    """Double Mach reflection on [0,4] x [0,1]: a Mach 10 shock through
+    (1/6, 0) at 60 degrees to the wall, post-shock (8, 7.145, -4.125,
+    116.8333) above the line y = sqrt(3)(x - 1/6), (1.4, 0, 0, 1) below;
+    gamma 1.4.  Left side inflow of the post-shock state, right side
+    transmissive, bottom post-shock below x = 1/6 and slip wall beyond, top
+    post-shock behind the shock's exact position 1/6 + (1 + 20 t)/sqrt(3).
+    Cell averages from the exact post-shock area of each cell (x integral
+    of the clipped line, 64 midpoints per cell).  First-order DF source and
+    the positivity fallback, as for the other strong-shock problems."""
+    gamma = 1.4
+    post = (8.0, 7.145, -4.125, 116.8333)
+    pre = (1.4, 0.0, 0.0, 1.0)
+    s3 = math.sqrt(3.0)
+    xw = 1.0 / 6.0
+    dx, dy = 4.0 / nx, 1.0 / ny
+
+    def cons(q):
+        r, u, v, p = q
+        return (r, r * u, r * v, p / (gamma - 1.0) + 0.5 * r * (u * u + v * v))
+    g = Grid(dim=2, nx=nx, ny=ny, ng=ghosts_for(order), dx=dx, dy=dy,
+             bc=(BC_INFLOW_SLOT, BC_TRANSMISSIVE, BC_WALL_INFLOW, BC_MOVING_SHOCK), y0=0.0, inflow=cons(post),
+             slot_lo=-1e300, slot_hi=1e300, x0=0.0, wall_x0=xw, shock_x0=xw + 1.0 / s3, shock_speed=20.0 / s3,
+             outer=cons(pre))
+    m = 64
+    xs = (np.arange(nx)[:, None] + (np.arange(m)[None, :] + 0.5) / m) * dx   # [i, sample]
+    line = s3 * (xs - xw)
+    ya = (np.arange(ny) * dy)[:, None, None]
+    # post-shock height of each sub-column inside the cell, as a fraction of dy
+    h = np.clip((ya + dy - np.maximum(ya, line[None, :, :])) / dy, 0.0, 1.0)
+    frac = h.mean(axis=2)                      # [j, i]
+    Wpost, Wpre = np.array(cons(post)), np.array(cons(pre))
+    W = Wpre[:, None, None] + (Wpost - Wpre)[:, None, None] * frac[None]
+    U = empty_state(g)
+    _fill_interior(g, U, W)
+    return Workload("double_mach", g, Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=1,
+                                             df_source=DF_FIRST_ORDER), U, nsteps, t_end)
 
 
 # Configuration 3 of the paper's 2D Riemann tests, quadrant order NE, NW, SW, SE.

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert "ase_step" in names and "ase_reconstruct" in names
     for n in names:
         assert hasattr(L, n), n
-    assert L.ase_version() == 2
+    assert L.ase_version() == 3
 
 
 def _args(order=9, **kw):

@@ -235,6 +235,8 @@ def _case2d(name, order):
         w = WL.four_quadrant(33, order, seed=7, ny=29)
         w.grid.bc = (WL.BC_REFLECTIVE,) * 4
         return w, 0.05, 1.0
+    if name == "dmr":
+        return WL.double_mach(50, 13, order), 0.05, 1.0
     raise KeyError(name)
 
 
@@ -254,7 +256,8 @@ def _gpu2d(w, c1, c2, U, sx, sy, t, nsteps, t_end=0.0):
     return host(sim.U), host(sim.sx), host(sim.sy), float(host(sim.t)[0]), host(hist)[:nsteps]
 
 
-STEP_CASES_2D = [("wave2d", 5), ("wave2d", 9), ("quad", 9), ("quad", 7), ("quad", 3), ("config3", 5), ("box", 5)]
+STEP_CASES_2D = [("wave2d", 5), ("wave2d", 9), ("quad", 9), ("quad", 7), ("quad", 3), ("config3", 5), ("box", 5),
+                 ("dmr", 5)]
 
 
 @pytest.mark.parametrize("name,order", STEP_CASES_2D)

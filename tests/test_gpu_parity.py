@@ -66,6 +66,8 @@ def _case(name, order, ragged=True):
         w = WL.blast_wave(400, order)
     elif name == "shuosher":
         w = WL.shu_osher(200, order)
+    elif name == "dmr":
+        w = WL.double_mach(101 if ragged else 96, 27 if ragged else 24, order)
     elif name == "box":
         # four-quadrant data between reflective walls on all four sides
         w = WL.four_quadrant(45 if ragged else 32, order, seed=7, ny=37 if ragged else 0)
@@ -224,7 +226,7 @@ def _gpu_run(w, U, sx, sy, t, nsteps, t_end=0.0):
 
 
 STEP_CASES = [("quad", 9), ("quad", 7), ("quad", 5), ("quad", 3), ("quadfo", 9), ("config3", 9), ("wave2d", 9),
-              ("jet", 7), ("box", 9), ("box", 5),
+              ("jet", 7), ("box", 9), ("box", 5), ("dmr", 9), ("dmr", 5),
               ("sod", 5), ("wave1d", 9), ("riemann1d", 9), ("riemann1d", 3), ("blast", 9), ("blast", 5),
               ("shuosher", 9)]
 
@@ -259,7 +261,8 @@ def test_one_step(name, order):
                                                      ("quad", 9, 60, 0.0), ("quadfo", 9, 60, 0.0),
                                                      ("config3", 9, 60, 0.0), ("wave2d", 7, 40, 0.0),
                                                      ("jet", 7, 60, 0.0), ("blast", 9, 300, 0.0),
-                                                     ("shuosher", 9, 400, 1.8), ("box", 9, 60, 0.0)])
+                                                     ("shuosher", 9, 400, 1.8), ("box", 9, 60, 0.0),
+                                                     ("dmr", 9, 120, 0.0)])
 def test_full_run(name, order, nsteps, t_end):
     """Independent runs from the initial data: 1e-9 after the full run."""
     w = _case(name, order)
