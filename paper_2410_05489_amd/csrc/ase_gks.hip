@@ -878,9 +878,10 @@ __global__ void __launch_bounds__(kGksPointThreads) k_gks_points(GksPointArgs a)
 }
 
 constexpr int kGksNT = 256;
-// 2D reconstruction tiles (as the LF sweeps): x faces 15 x 16 cells on 512
-// lanes, y faces 16 x 7 cells on 256 lanes
-constexpr int kGX_T0 = 15, kGX_T1 = 16, kGX_NT = 512, kGY_T0 = 16, kGY_T1 = 7, kGY_NT = 256;
+// 2D reconstruction tiles: x faces 15 x 8 cells, y faces 16 x 7 cells, 256
+// lanes each (one (face, side) item per lane in phase 2).  At 147 registers
+// three 4-wave workgroups fit a CU (52 KB of LDS each for x faces).
+constexpr int kGX_T0 = 15, kGX_T1 = 8, kGX_NT = 256, kGY_T0 = 16, kGY_T1 = 7, kGY_NT = 256;
 
 template <int R>
 void gks1d_r(int nx, const Gks1DArgs &a, hipStream_t st)
