@@ -235,12 +235,17 @@ def alg_flops_per_cell_gks2d_stage(order: int) -> float:
                                and slopes
       tangential (two sides) : 2 x (DF sums + G points x 4 vars x (2r-1) x 3:
                                values, their slopes, the normal slopes)
-      per Gauss point        : 24 moment sums <(c.psi) u^K v^Q psi_j> of
-                               36 products each (5 operations) 4320, nine
-                               micro slopes 225, Maxwellian moments 170,
-                               three Maxwellians 36, time integrals 40,
-                               accumulation 100, strength 38, rotation and
-                               quadrature 20                       -> 4949
+      per Gauss point        : 24 moment sums <(c.psi) u^K v^Q psi_j>, 19
+                               general ones of 36 products (137 operations:
+                               c <u^n> <v^m> with the 1/2 of psi_3 and
+                               <xi^(2l)> where they are not 1, plus the sum)
+                               and 5 on c = (1,0,0,0) (16) -> 2683; nine
+                               micro slopes 225 and their right-hand sides
+                               39, Maxwellian moments 206, three
+                               Maxwellians 30, time integrals and tau_n 48,
+                               accumulation into F and the kinetic averages
+                               240, F and F_t 29, strength 38, quadrature
+                               16                                  -> 3554
       update                 : 2 x 4 vars x 4 (L, L_t) + stage combination 16
     """
     R = (order - 1) // 2
@@ -248,7 +253,7 @@ def alg_flops_per_cell_gks2d_stage(order: int) -> float:
     sums = {1: 1, 2: 3, 3: 8, 4: 15}[R]
     normal = sums + 2 * 2 * 4 * (2 * order - 1)
     tang = 2 * (sums + G * 4 * (2 * order - 1) * 3)
-    return 2 * (normal + tang + G * 4949) + 48
+    return 2 * (normal + tang + G * 3554) + 48
 
 
 def bench_gks2d(args):
