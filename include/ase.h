@@ -131,7 +131,8 @@ int ase_version(void);
 
 /* Ghost cells and derived strengths (boundary conditions of Sec. 4).
  * Fills every ghost cell of U (x first on interior rows, then y on every
- * column, so corners take the y rule applied to x-filled values), then the
+ * column, so corners take the y rule applied to x-filled values; a moving
+ * shock side at t = 0), then the
  * strengths a stage reads.  Lagged DF source: every stored strength that is
  * not a flux-face strength -- periodic faces take the wrapped flux-face
  * value, the others the first-order strength of their two cells.
@@ -200,7 +201,9 @@ size_t ase_workspace_bytes(const ase_grid_t *g, const ase_params_t *p);
  * feedback: each stage computes the strengths of its flux faces from its
  * own Gauss-point states, and the next stage's DF factors use them.
  * Per step: boundary fill, dt, then three stages of reconstruction, flux,
- * quadrature and update, all on device.  Steps stop advancing once t >=
+ * quadrature and update, all on device; the ghost cells of the stage
+ * inputs are filled at their times t_n, t_n + dt, t_n + dt/2 (a moving
+ * shock side reads it).  Steps stop advancing once t >=
  * t_end (t_end > 0); remaining launches are no-ops.
  * U, sx, sy: the state (U interior + flux-face strengths), in/out; the DF
  * state must come from ase_sigma_init or a previous ase_step.
