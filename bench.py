@@ -293,6 +293,20 @@ def bench_gks2d(args):
     kern_ms = sum(v[0] for v in kern.values()) / prof_steps
     tot, nl = kern["gks_2d_flux"]
     ms400 = res[400][0]
+    # viscous shock tube (Navier-Stokes through the kinetic flux), the
+    # paper's 500 x 250 mesh, order 9
+    wv = WL.viscous_shock_tube(500, 250, 9)
+    simv = ase.GksSimulation(wv.grid, wv.params, wv.U, c1=1.0, c2=10.0, mu=wv.mu, device="cuda")
+    simv.run(args.warmup)
+    torch.cuda.synchronize()
+    start.record()
+    simv.run(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    msv = start.elapsed_time(stop)
+    vst = {"workload": "viscous_shock_tube_500x250_r9_re200", "steps": steps,
+           "value": round(wv.grid.nx * wv.grid.ny * steps / (msv / 1e3) / 1e6, 3), "unit": "Mcell-updates/s",
+           "ms_per_step": round(msv / steps, 5), "finite": bool(torch.isfinite(simv.U).all().item())}
     out = {"metric": "Mcell-updates/s, 2D gas-kinetic S2O4 step, order 9 (FP64)", "value": round(value, 3),
            "unit": "Mcell-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
            "ms_per_step": round(ms / steps, 5), "higher_is_better": True, "scaling": "weak",
@@ -300,6 +314,7 @@ def bench_gks2d(args):
            "config": {"workload": "gks_config3_1024x1024_r9", "order": 9, "nx": g.nx, "ny": g.ny, "c1": c1,
                       "c2": c2, "cfl": p.cfl},
            "finite": finite,
+           "viscous": vst,
            "table4_config": {"workload": "gks_config3_400x400_r9", "steps": 20, "seconds": round(ms400 / 1e3, 5),
                              "paper_seconds": 165.221,
                              "paper_hardware": "one core of an AMD EPYC 7401 (context, not a target)"},

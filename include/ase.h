@@ -64,7 +64,11 @@ enum {
  * (x sides only); REFLECTIVE: slip wall, the ghost cells mirror the interior
  * cells with the momentum normal to the wall reversed (needs n >= ng). */
 enum { ASE_BC_PERIODIC = 0, ASE_BC_TRANSMISSIVE = 1, ASE_BC_INFLOW_SLOT = 2, ASE_BC_REFLECTIVE = 3,
-       ASE_BC_WALL_INFLOW = 4, ASE_BC_MOVING_SHOCK = 5 };
+       ASE_BC_WALL_INFLOW = 4, ASE_BC_MOVING_SHOCK = 5, ASE_BC_NOSLIP = 6 };
+/* ASE_BC_NOSLIP: no-slip adiabatic wall (Sec. 4, Example 5), any side:
+ * ghost cells mirror the interior with the whole momentum reversed; lagged
+ * strengths mirror as at a slip wall; on the gas-kinetic path the mass and
+ * energy fluxes through it are zero. */
 
 /* Flags of ase_params_t. */
 enum {
@@ -222,6 +226,9 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
 typedef struct {
     double c1, c2;  /* numerical collision time tau_n = c1 dt + c2 |p_l - p_r| / (p_l + p_r) dt */
     double tau;     /* collision time outside the exponentials: 0 for the Euler equations */
+    double mu;      /* > 0: Navier-Stokes (2D only): tau = mu / p with p the pressure of the
+                       equilibrium state at the Gauss point, tau_n = tau + c2 |p_l - p_r| /
+                       (p_l + p_r) dt (c1 unused); Pr = 1, the BGK model's */
 } ase_gks_t;
 
 /* Flux F and its time derivative F_t at t_n of n independent faces

@@ -38,7 +38,12 @@
 /* ------------------------------------------------------------------------ */
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_INFLOW_SLOT = 2, ORC_BC_REFLECTIVE = 3,
-       ORC_BC_WALL_INFLOW = 4, ORC_BC_MOVING_SHOCK = 5 };
+       ORC_BC_WALL_INFLOW = 4, ORC_BC_MOVING_SHOCK = 5, ORC_BC_NOSLIP = 6 };
+
+/* Mirror sides: the slip wall and the no-slip adiabatic wall (Sec. 4,
+   Example 5) both mirror the cells; the slip wall reverses the momentum
+   normal to it, the no-slip wall the whole momentum. */
+static int is_wall(int bc) { return bc == ORC_BC_REFLECTIVE || bc == ORC_BC_NOSLIP; }
 
 typedef struct {
     int32_t dim;        /* 1 or 2 */
@@ -490,17 +495,20 @@ static void bc_fill_cells(const orc_grid *g, double *U, double t)
             for (int v = 0; v < nv; ++v) {
                 double *rv = row + v * P;
                 /* a reflective (slip) wall mirrors the cells and reverses the
-                   momentum normal to it (x momentum is variable 1) */
-                double flip = (v == 1) ? -1.0 : 1.0;
+                   momentum normal to it (x momentum is variable 1); a no-slip
+                   wall reverses both momenta */
+                int mom = v == 1 || (g->dim == 2 && v == 2);
+                double flo = (v == 1 || (g->bc[0] == ORC_BC_NOSLIP && mom)) ? -1.0 : 1.0;
+                double fhi = (v == 1 || (g->bc[1] == ORC_BC_NOSLIP && mom)) ? -1.0 : 1.0;
                 /* low side */
                 if (g->bc[0] == ORC_BC_PERIODIC) rv[Il] = rv[Il + g->nx];
                 else if (g->bc[0] == ORC_BC_INFLOW_SLOT && in_slot(g, J)) rv[Il] = g->inflow[v];
-                else if (g->bc[0] == ORC_BC_REFLECTIVE) rv[Il] = flip * rv[ng + k];
+                else if (is_wall(g->bc[0])) rv[Il] = flo * rv[ng + k];
                 else rv[Il] = rv[ng];
                 /* high side */
                 if (g->bc[1] == ORC_BC_PERIODIC) rv[Ir] = rv[Ir - g->nx];
                 else if (g->bc[1] == ORC_BC_INFLOW_SLOT && in_slot(g, J)) rv[Ir] = g->inflow[v];
-                else if (g->bc[1] == ORC_BC_REFLECTIVE) rv[Ir] = flip * rv[ng + g->nx - 1 - k];
+                else if (is_wall(g->bc[1])) rv[Ir] = fhi * rv[ng + g->nx - 1 - k];
                 else rv[Ir] = rv[ng + g->nx - 1];
             }
         }
@@ -511,18 +519,19 @@ static void bc_fill_cells(const orc_grid *g, double *U, double t)
         for (int v = 0; v < nv; ++v) {
             double *Uv = U + v * P;
             double flip = (v == 2) ? -1.0 : 1.0;   /* y momentum */
+            double flo = (v == 2 || (g->bc[2] == ORC_BC_NOSLIP && v == 1)) ? -1.0 : 1.0;
+            double fhi = (v == 2 || (g->bc[3] == ORC_BC_NOSLIP && v == 1)) ? -1.0 : 1.0;
             for (int I = 0; I < NX; ++I) {
                 /* centre of the column (double Mach reflection sides) */
                 double xc = g->x0 + ((double)(I - ng) + 0.5) * g->dx;
                 if (g->bc[2] == ORC_BC_PERIODIC) Uv[(size_t)Jl * g->ld + I] = Uv[(size_t)(Jl + g->ny) * g->ld + I];
-                else if (g->bc[2] == ORC_BC_REFLECTIVE ||
-                         (g->bc[2] == ORC_BC_WALL_INFLOW && !(xc < g->wall_x0)))
-                    Uv[(size_t)Jl * g->ld + I] = flip * Uv[(size_t)(ng + k) * g->ld + I];
+                else if (is_wall(g->bc[2]) || (g->bc[2] == ORC_BC_WALL_INFLOW && !(xc < g->wall_x0)))
+                    Uv[(size_t)Jl * g->ld + I] = (g->bc[2] == ORC_BC_NOSLIP ? flo : flip) * Uv[(size_t)(ng + k) * g->ld + I];
                 else if (g->bc[2] == ORC_BC_WALL_INFLOW) Uv[(size_t)Jl * g->ld + I] = g->inflow[v];
                 else Uv[(size_t)Jl * g->ld + I] = Uv[(size_t)ng * g->ld + I];
                 if (g->bc[3] == ORC_BC_PERIODIC) Uv[(size_t)Jh * g->ld + I] = Uv[(size_t)(Jh - g->ny) * g->ld + I];
-                else if (g->bc[3] == ORC_BC_REFLECTIVE)
-                    Uv[(size_t)Jh * g->ld + I] = flip * Uv[(size_t)(ng + g->ny - 1 - k) * g->ld + I];
+                else if (is_wall(g->bc[3]))
+                    Uv[(size_t)Jh * g->ld + I] = fhi * Uv[(size_t)(ng + g->ny - 1 - k) * g->ld + I];
                 else if (g->bc[3] == ORC_BC_MOVING_SHOCK)
                     Uv[(size_t)Jh * g->ld + I] = (xc < g->shock_x0 + g->shock_speed * t) ? g->inflow[v] : g->outer[v];
                 else Uv[(size_t)Jh * g->ld + I] = Uv[(size_t)(ng + g->ny - 1) * g->ld + I];
@@ -585,10 +594,10 @@ static int map_cell(int i, int n, int bc_lo, int bc_hi)
 {
     if (i < 0) {
         if (bc_lo == ORC_BC_PERIODIC) return wrap(i, n);
-        if (bc_lo == ORC_BC_REFLECTIVE) return -1 - i;
+        if (is_wall(bc_lo)) return -1 - i;
     } else if (i >= n) {
         if (bc_hi == ORC_BC_PERIODIC) return wrap(i, n);
-        if (bc_hi == ORC_BC_REFLECTIVE) return 2 * n - 1 - i;
+        if (is_wall(bc_hi)) return 2 * n - 1 - i;
     }
     return i;
 }
@@ -599,10 +608,10 @@ static int map_face(int f, int n, int bc_lo, int bc_hi)
 {
     if (f < -1) {
         if (bc_lo == ORC_BC_PERIODIC) return wrap(f, n);
-        if (bc_lo == ORC_BC_REFLECTIVE) return -f - 2;
+        if (is_wall(bc_lo)) return -f - 2;
     } else if (f > n - 1) {
         if (bc_hi == ORC_BC_PERIODIC) return wrap(f, n);
-        if (bc_hi == ORC_BC_REFLECTIVE) return 2 * n - f - 2;
+        if (is_wall(bc_hi)) return 2 * n - f - 2;
     }
     return f;
 }
@@ -908,7 +917,7 @@ static int check_args(const orc_grid *g, const orc_params *p)
     if (g->dim == 2 && (g->bc[2] == ORC_BC_PERIODIC) != (g->bc[3] == ORC_BC_PERIODIC)) return -1;
     if (g->dim == 2 && (g->bc[2] == ORC_BC_INFLOW_SLOT || g->bc[3] == ORC_BC_INFLOW_SLOT)) return -1;
     for (int k = 0; k < (g->dim == 2 ? 4 : 2); ++k)
-        if (g->bc[k] < ORC_BC_PERIODIC || g->bc[k] > ORC_BC_MOVING_SHOCK) return -1;
+        if (g->bc[k] < ORC_BC_PERIODIC || g->bc[k] > ORC_BC_NOSLIP) return -1;
     /* the double Mach reflection sides: wall/inflow on y-lo, moving shock on y-hi */
     for (int k = 0; k < 4; ++k) {
         if (g->bc[k] == ORC_BC_WALL_INFLOW && !(k == 2 && g->dim == 2)) return -1;
@@ -916,8 +925,8 @@ static int check_args(const orc_grid *g, const orc_params *p)
     }
     if (g->dim == 2 && g->bc[2] == ORC_BC_WALL_INFLOW && g->ny < g->ng) return -1;
     /* a mirror or a wrap reads ng interior cells */
-    if ((g->bc[0] == ORC_BC_REFLECTIVE || g->bc[1] == ORC_BC_REFLECTIVE) && g->nx < g->ng) return -1;
-    if (g->dim == 2 && (g->bc[2] == ORC_BC_REFLECTIVE || g->bc[3] == ORC_BC_REFLECTIVE) && g->ny < g->ng) return -1;
+    if ((is_wall(g->bc[0]) || is_wall(g->bc[1])) && g->nx < g->ng) return -1;
+    if (g->dim == 2 && (is_wall(g->bc[2]) || is_wall(g->bc[3])) && g->ny < g->ng) return -1;
     return 0;
 }
 
@@ -1212,7 +1221,9 @@ typedef struct {
     double xm[GKS_NL];   /* <xi^(2l)>                */
 } gks_maxw;
 
-typedef struct { double c1, c2, tau; } orc_gks;
+/* c1, c2: numerical collision time; tau: collision time outside the
+   exponentials (inviscid); mu > 0: viscous flow, tau = mu/p (Sec. 2.2) */
+typedef struct { double c1, c2, tau, mu; } orc_gks;
 
 /* Maxwellian of the state W = (rho, rho U, E) and its moments (App. A):     */
 /*   <u^0> = 1, <u^1> = U, <u^(n+2)> = U <u^(n+1)> + (n+1)/(2 lambda) <u^n>; */
@@ -1547,7 +1558,7 @@ int orc_step_gks(const orc_grid *g, const orc_params *p, const orc_gks *gk, doub
 {
     int e = check_args(g, p);
     if (e) return e;
-    if (g->dim != 1) return -1;
+    if (g->dim != 1 || gk->mu > 0.0) return -1;   /* viscous flow: 2D only */
     size_t P = plane(g), n = 3 * P;
     double *Ws = malloc(n * sizeof(double)), *L0 = calloc(n, sizeof(double)), *T0 = calloc(n, sizeof(double));
     double *L1 = calloc(n, sizeof(double)), *T1 = calloc(n, sizeof(double)), *sxa = malloc(P * sizeof(double));
@@ -1904,16 +1915,43 @@ static int g2_flux_int(double gamma, const double *Wl, const double *Wln, const 
 }
 
 /* F and F_t at t_n at one Gauss point (local frame), Eq. time advance.     */
+/* Collision times (Sec. 2.2).  Inviscid: tau as given, tau_n = C1 dt +    */
+/* C2 |p_l - p_r|/(p_l + p_r) dt.  Viscous (mu > 0): tau = mu/p with p the  */
+/* pressure of the equilibrium state W^c at the interface (reading), and    */
+/* tau_n = tau + C2 |p_l - p_r|/(p_l + p_r) dt.                              */
+static int g2_times(double gamma, const orc_gks *gk, double dt, const double *Wl, const double *Wr, double *tau,
+                    double *taun)
+{
+    double pl = (gamma - 1.0) * (Wl[3] - 0.5 * (Wl[1] * Wl[1] + Wl[2] * Wl[2]) / Wl[0]);
+    double pr = (gamma - 1.0) * (Wr[3] - 0.5 * (Wr[1] * Wr[1] + Wr[2] * Wr[2]) / Wr[0]);
+    double jump = gk->c2 * fabs(pl - pr) / (pl + pr) * dt;
+    if (!(gk->mu > 0.0)) {
+        *tau = gk->tau;
+        *taun = gk->c1 * dt + jump;
+        return 0;
+    }
+    g2_maxw ml, mr, mc;
+    if (g2_maxwellian(gamma, Wl, &ml) || g2_maxwellian(gamma, Wr, &mr)) return -1;
+    vpoly one = g2_mono(0, 0);
+    double t1[4], t2[4], Wc[4];
+    g2_avg_psi(&one, ml.up, &ml, t1);
+    g2_avg_psi(&one, mr.un, &mr, t2);
+    for (int j = 0; j < 4; ++j) Wc[j] = ml.rho * t1[j] + mr.rho * t2[j];
+    if (g2_maxwellian(gamma, Wc, &mc)) return -1;
+    *tau = gk->mu / (mc.rho / (2.0 * mc.lam));
+    *taun = *tau + jump;
+    return 0;
+}
+
 static int g2_point(double gamma, const orc_gks *gk, double dt, const double *Wl, const double *Wln,
                     const double *Wlt, const double *Wr, const double *Wrn, const double *Wrt, double *Fn,
                     double *Ft)
 {
-    double pl = (gamma - 1.0) * (Wl[3] - 0.5 * (Wl[1] * Wl[1] + Wl[2] * Wl[2]) / Wl[0]);
-    double pr = (gamma - 1.0) * (Wr[3] - 0.5 * (Wr[1] * Wr[1] + Wr[2] * Wr[2]) / Wr[0]);
-    double taun = gk->c1 * dt + gk->c2 * fabs(pl - pr) / (pl + pr) * dt;
+    double tau, taun;
+    if (g2_times(gamma, gk, dt, Wl, Wr, &tau, &taun)) return -1;
     double F1[4], F2[4];
-    if (g2_flux_int(gamma, Wl, Wln, Wlt, Wr, Wrn, Wrt, gk->tau, taun, dt, F1)) return -1;
-    if (g2_flux_int(gamma, Wl, Wln, Wlt, Wr, Wrn, Wrt, gk->tau, taun, 0.5 * dt, F2)) return -1;
+    if (g2_flux_int(gamma, Wl, Wln, Wlt, Wr, Wrn, Wrt, tau, taun, dt, F1)) return -1;
+    if (g2_flux_int(gamma, Wl, Wln, Wlt, Wr, Wrn, Wrt, tau, taun, 0.5 * dt, F2)) return -1;
     for (int j = 0; j < 4; ++j) {
         Fn[j] = (4.0 * F2[j] - F1[j]) / dt;
         Ft[j] = 4.0 * (F1[j] - 2.0 * F2[j]) / (dt * dt);
@@ -2047,6 +2085,17 @@ static int sweep_gks2d(const orc_grid *g, const orc_params *p, const orc_gks *gk
             }
             int fi = dir == 0 ? a : c, fj = dir == 0 ? c : a;
             size_t fid = face_index(g, dir, fi, fj);
+            /* no-slip adiabatic wall (reading): nothing crosses it, the mass
+               and energy fluxes are zero; the momentum flux (pressure and
+               viscous stress) is the kinetic one.  The mirrored ghost
+               cells reverse the tangential velocity too, which the
+               tangential-slope terms of the distribution do not see as a
+               symmetry, so the kinetic mass flux would not vanish. */
+            int lo = dir == 0 ? g->bc[0] : g->bc[2], hi = dir == 0 ? g->bc[1] : g->bc[3];
+            if ((a == -1 && lo == ORC_BC_NOSLIP) || (a == n_along - 1 && hi == ORC_BC_NOSLIP)) {
+                Fs[0] = Fs[3] = 0.0;
+                Fts[0] = Fts[3] = 0.0;
+            }
             for (int v = 0; v < nv; ++v) {
                 Fx[(size_t)v * nf + fid] = Fs[v];
                 Ftx[(size_t)v * nf + fid] = Fts[v];

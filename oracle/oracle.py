@@ -287,11 +287,11 @@ def lf_point(g, p, Wl, Wr, d):
 # ---- gas-kinetic solver (1D) -------------------------------------------------
 
 class OrcGks(C.Structure):
-    _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("tau", C.c_double)]
+    _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("tau", C.c_double), ("mu", C.c_double)]
 
 
-def c_gks(c1, c2, tau=0.0) -> OrcGks:
-    return OrcGks(float(c1), float(c2), float(tau))
+def c_gks(c1, c2, tau=0.0, mu=0.0) -> OrcGks:
+    return OrcGks(float(c1), float(c2), float(tau), float(mu))
 
 
 def _vec(x):
@@ -364,21 +364,21 @@ def poly_d(p, W, s, xi):
 
 # ---- gas-kinetic solver (2D) -------------------------------------------------
 
-def step_gks2d(g, p, U, sx, sy, t, nsteps, t_end=0.0, c1=0.05, c2=1.0, tau=0.0):
-    """S2O4 GKS steps in place (2D); returns (t, dt history)."""
+def step_gks2d(g, p, U, sx, sy, t, nsteps, t_end=0.0, c1=0.05, c2=1.0, tau=0.0, mu=0.0):
+    """S2O4 GKS steps in place (2D; mu > 0: viscous); returns (t, dt history)."""
     tt = C.c_double(t)
     hist = np.zeros(max(nsteps, 1))
     G, P = _gp(g, p)
-    K = c_gks(c1, c2, tau)
+    K = c_gks(c1, c2, tau, mu)
     n = _check(lib().orc_step_gks2d(G, P, C.byref(K), _ptr(U), _ptr(sx), _ptr(sy), C.byref(tt), nsteps, t_end,
                                     _ptr(hist)), "step_gks2d")
     return tt.value, hist[:n]
 
 
-def run_gks2d(g, p, U, nsteps, t_end=0.0, c1=0.05, c2=1.0, tau=0.0):
+def run_gks2d(g, p, U, nsteps, t_end=0.0, c1=0.05, c2=1.0, tau=0.0, mu=0.0):
     U = U.copy()
     sx, sy = sigma_init(g, p, U)
-    t, dts = step_gks2d(g, p, U, sx, sy, 0.0, nsteps, t_end, c1, c2, tau)
+    t, dts = step_gks2d(g, p, U, sx, sy, 0.0, nsteps, t_end, c1, c2, tau, mu)
     return U, sx, sy, t, dts
 
 
@@ -389,9 +389,9 @@ def gks2_slopes(gamma, W, Wn, Wt):
     return an, at, A
 
 
-def gks2_point(gamma, dt, Wl, Wln, Wlt, Wr, Wrn, Wrt, c1=0.05, c2=1.0, tau=0.0):
+def gks2_point(gamma, dt, Wl, Wln, Wlt, Wr, Wrn, Wrt, c1=0.05, c2=1.0, tau=0.0, mu=0.0):
     Fn, Ft = np.zeros(4), np.zeros(4)
-    K = c_gks(c1, c2, tau)
+    K = c_gks(c1, c2, tau, mu)
     _check(lib().orc_gks2_point(gamma, C.byref(K), dt, _ptr(_vec(Wl)), _ptr(_vec(Wln)), _ptr(_vec(Wlt)),
                                 _ptr(_vec(Wr)), _ptr(_vec(Wrn)), _ptr(_vec(Wrt)), _ptr(Fn), _ptr(Ft)), "gks2_point")
     return Fn, Ft

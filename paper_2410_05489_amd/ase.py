@@ -49,7 +49,7 @@ KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4, "batched
 
 
 class AseGks(C.Structure):
-    _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("tau", C.c_double)]
+    _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("tau", C.c_double), ("mu", C.c_double)]
 
 
 class AseError(RuntimeError):
@@ -262,8 +262,8 @@ class Simulation:
         return _capture(lambda: self.run(nsteps, t_end))
 
 
-def c_gks(c1: float = 0.05, c2: float = 1.0, tau: float = 0.0) -> AseGks:
-    return AseGks(float(c1), float(c2), float(tau))
+def c_gks(c1: float = 0.05, c2: float = 1.0, tau: float = 0.0, mu: float = 0.0) -> AseGks:
+    return AseGks(float(c1), float(c2), float(tau), float(mu))
 
 
 def gks_flux(p, gk: AseGks, Wl, Wlx, Wr, Wrx, dt: float, Fn, Ft, stream=None):
@@ -292,9 +292,9 @@ class GksSimulation:
     gas-kinetic solver with S2O4 steps."""
 
     def __init__(self, g: Grid, p: Params, U0, c1: float = 0.05, c2: float = 1.0, tau: float = 0.0,
-                 device="cuda", sx=None, sy=None, t: float = 0.0):
+                 device="cuda", sx=None, sy=None, t: float = 0.0, mu: float = 0.0):
         self.g, self.p = g, p
-        self.gk = c_gks(c1, c2, tau)
+        self.gk = c_gks(c1, c2, tau, mu)
         self.U = torch.as_tensor(U0, dtype=torch.float64).to(device).contiguous()
         self.sx = torch.zeros((g.NY, g.ld), dtype=torch.float64, device=device)
         self.sy = torch.zeros((g.NY, g.ld), dtype=torch.float64, device=device)

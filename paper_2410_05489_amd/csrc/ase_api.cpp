@@ -49,7 +49,7 @@ int validate(const ase_grid_t *g, const ase_params_t *p, Geo *geo)
     if (g->ld < g->nx + 2 * g->ng) return fail(ASE_ERR_ARG, "ld must be >= nx + 2 ng");
     if (!(g->dx > 0.0) || (g->dim == 2 && !(g->dy > 0.0))) return fail(ASE_ERR_ARG, "dx, dy must be > 0");
     for (int k = 0; k < 4; ++k)
-        if (g->bc[k] < 0 || g->bc[k] > ASE_BC_MOVING_SHOCK) return fail(ASE_ERR_ARG, "unknown boundary code");
+        if (g->bc[k] < 0 || g->bc[k] > ASE_BC_NOSLIP) return fail(ASE_ERR_ARG, "unknown boundary code");
     for (int k = 0; k < 4; ++k) {
         if (g->bc[k] == ASE_BC_WALL_INFLOW && !(k == 2 && g->dim == 2))
             return fail(ASE_ERR_ARG, "WALL_INFLOW is a 2D y-lo boundary only");
@@ -64,10 +64,12 @@ int validate(const ase_grid_t *g, const ase_params_t *p, Geo *geo)
         return fail(ASE_ERR_ARG, "periodic y boundaries must pair");
     if (g->dim == 2 && (g->bc[2] == ASE_BC_INFLOW_SLOT || g->bc[3] == ASE_BC_INFLOW_SLOT))
         return fail(ASE_ERR_ARG, "inflow slot is an x boundary only");
-    if ((g->bc[0] == ASE_BC_PERIODIC || g->bc[0] == ASE_BC_REFLECTIVE || g->bc[1] == ASE_BC_REFLECTIVE) &&
+    if ((g->bc[0] == ASE_BC_PERIODIC || g->bc[0] == ASE_BC_REFLECTIVE || g->bc[1] == ASE_BC_REFLECTIVE ||
+         g->bc[0] == ASE_BC_NOSLIP || g->bc[1] == ASE_BC_NOSLIP) &&
         g->nx < g->ng)
         return fail(ASE_ERR_ARG, "periodic or reflective x needs nx >= ng");
-    if (g->dim == 2 && (g->bc[2] == ASE_BC_REFLECTIVE || g->bc[3] == ASE_BC_REFLECTIVE) && g->ny < g->ng)
+    if (g->dim == 2 && (g->bc[2] == ASE_BC_REFLECTIVE || g->bc[3] == ASE_BC_REFLECTIVE ||
+                        g->bc[2] == ASE_BC_NOSLIP || g->bc[3] == ASE_BC_NOSLIP) && g->ny < g->ng)
         return fail(ASE_ERR_ARG, "reflective y needs ny >= ng");
     if (g->dim == 2 && g->bc[2] == ASE_BC_PERIODIC && g->ny < g->ng)
         return fail(ASE_ERR_ARG, "periodic y needs ny >= ng");
@@ -439,14 +441,15 @@ static GksConst gks_const(const ase_params_t *p, const ase_gks_t *gk, int dim)
     c.c1 = gk->c1;
     c.c2 = gk->c2;
     c.tau = gk->tau;
+    c.mu = gk->mu;
     return c;
 }
 
 static int check_gks(const ase_gks_t *gk)
 {
     if (!gk) return fail(ASE_ERR_ARG, "null gks parameters");
-    if (!(gk->c1 >= 0.0) || !(gk->c2 >= 0.0) || !(gk->tau >= 0.0))
-        return fail(ASE_ERR_ARG, "gks c1, c2, tau must be >= 0");
+    if (!(gk->c1 >= 0.0) || !(gk->c2 >= 0.0) || !(gk->tau >= 0.0) || !(gk->mu >= 0.0))
+        return fail(ASE_ERR_ARG, "gks c1, c2, tau, mu must be >= 0");
     return ASE_OK;
 }
 
@@ -492,6 +495,7 @@ int ase_gks_flux(const ase_params_t *p, const ase_gks_t *gk, int32_t n, const do
     if (!p) return fail(ASE_ERR_ARG, "null params");
     int rc = check_gks(gk);
     if (rc) return rc;
+    if (gk->mu > 0.0) return fail(ASE_ERR_ARG, "viscous flow (mu > 0) needs a 2D grid");
     if (!(p->gamma > 1.0)) return fail(ASE_ERR_ARG, "gamma must be > 1");
     if (n < 0) return fail(ASE_ERR_ARG, "n must be >= 0");
     if (!(dt > 0.0)) return fail(ASE_ERR_ARG, "dt must be > 0");
@@ -526,6 +530,7 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
     if (rc) return rc;
     rc = check_gks(gk);
     if (rc) return rc;
+    if (geo.dim == 1 && gk->mu > 0.0) return fail(ASE_ERR_ARG, "viscous flow (mu > 0) needs a 2D grid");
     if (nsteps < 0) return fail(ASE_ERR_ARG, "nsteps must be >= 0");
     ASE_PTR(U, "U");
     ASE_PTR(sx, "sx");
@@ -580,6 +585,7 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
         a2.NY = geo.NY;
         a2.inv_dx = 1.0 / g->dx;
         a2.inv_dy = 1.0 / g->dy;
+        for (int k = 0; k < 4; ++k) a2.bc[k] = g->bc[k];
         a2.mc = mc;
         a2.gk = gc;
         a2.rec = w2.rec;

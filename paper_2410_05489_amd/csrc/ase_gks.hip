@@ -448,9 +448,31 @@ __device__ __forceinline__ bool gks2_point(const double (&Wl)[4], const double (
     const double K = gk.K;
     const Maxw2 ml = maxwellian2(Wl, gm1), mr = maxwellian2(Wr, gm1);
     const double pl = 0.5 * ml.rho / ml.lam, pr = 0.5 * mr.rho / mr.lam;
-    const double taun = gk.c1 * dt + gk.c2 * fabs(pl - pr) / (pl + pr) * dt;
+    const double jump = gk.c2 * fabs(pl - pr) / (pl + pr) * dt;
+    double tau = gk.tau, taun = gk.c1 * dt + jump;
+    if (gk.mu > 0.0) {
+        // viscous: tau = mu / p of the equilibrium state W^c (the kinetic
+        // average of the two half Maxwellians), tau_n = tau + the jump term
+        const double one[4] = {1.0, 0.0, 0.0, 0.0};
+        double Mh[kNM], Mv[kNV2], t[4], Wc0[4];
+        moments_half_line(ml.U, ml.lam, 1.0, Mh);
+        moments_line<kNV2>(ml.V, ml.lam, Mv);
+        const double Xl2 = K * 0.5 / ml.lam;
+        lin_moment2<0, 0>(one, Mh, Mv, Xl2, 0.0, t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Wc0[j] = ml.rho * t[j];
+        moments_half_line(mr.U, mr.lam, -1.0, Mh);
+        moments_line<kNV2>(mr.V, mr.lam, Mv);
+        const double Xr2 = K * 0.5 / mr.lam;
+        lin_moment2<0, 0>(one, Mh, Mv, Xr2, 0.0, t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Wc0[j] = fma(mr.rho, t[j], Wc0[j]);
+        const Maxw2 m0 = maxwellian2(Wc0, gm1);
+        tau = gk.mu / (0.5 * m0.rho / m0.lam);
+        taun = tau + jump;
+    }
     double q[2][6];
-    time_coefs(dt, gk.tau, taun, q);
+    time_coefs(dt, tau, taun, q);
     double F[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
     double Wc[4] = {0, 0, 0, 0}, Wcn[4] = {0, 0, 0, 0}, Wct[4] = {0, 0, 0, 0};
     side_terms2(ml, 1.0, Wln, Wlt, K, q, F, Wc, Wcn, Wct);
@@ -700,6 +722,15 @@ __global__ void __launch_bounds__(kGksPointThreads) k_gks2d_flux(Gks2DArgs a)
             Fs[v] = fma(eta, Fg[v], Fs[v]);
             Fts[v] = fma(eta, Ftg[v], Fts[v]);
         }
+    }
+    // no-slip adiabatic wall: no mass or energy crosses it (the mirrored
+    // ghost cells reverse the tangential velocity too, which the
+    // tangential-slope terms do not see as a symmetry)
+    const int lo = DIR == 0 ? a.bc[0] : a.bc[2], hi = DIR == 0 ? a.bc[1] : a.bc[3];
+    const int k1 = DIR == 0 ? i : j, n1 = DIR == 0 ? a.nx : a.ny;
+    if ((k1 == -1 && lo == ASE_BC_NOSLIP) || (k1 == n1 - 1 && hi == ASE_BC_NOSLIP)) {
+        Fs[0] = Fs[3] = 0.0;
+        Fts[0] = Fts[3] = 0.0;
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {

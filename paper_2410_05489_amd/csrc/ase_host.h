@@ -132,6 +132,7 @@ struct GksConst {
     double K;          // internal degrees of freedom, (3 - gamma)/(gamma - 1)
     double c1, c2;     // numerical collision time tau_n = c1 dt + c2 |dp|/(p_l + p_r) dt
     double tau;        // collision time outside the exponentials (0: Euler)
+    double mu;         // > 0: viscous, tau = mu / p of the equilibrium state
 };
 
 struct Gks1DArgs {
@@ -159,6 +160,7 @@ struct Gks2DArgs {
     const double *dt, *skip;
     long long plane, nfaces;
     int nx, ny, ng, ld, NX, NY;
+    int bc[4];             // boundary codes (no-slip wall faces carry no mass or energy)
     double inv_dx, inv_dy;
     MethodConst mc;
     GksConst gk;

@@ -79,31 +79,44 @@ __device__ __forceinline__ int src_cell(const BCInfo &b, int I, int J, int &Is, 
         const double xc = b.x0 + ((double)(I - b.ng) + 0.5) * b.dx;
         if (j < 0) {
             if (b.bc[2] == ASE_BC_PERIODIC) Js = J + b.ny;
-            else if (b.bc[2] == ASE_BC_REFLECTIVE || (b.bc[2] == ASE_BC_WALL_INFLOW && !(xc < b.wall_x0))) {
+            else if (b.bc[2] == ASE_BC_REFLECTIVE || b.bc[2] == ASE_BC_NOSLIP ||
+                     (b.bc[2] == ASE_BC_WALL_INFLOW && !(xc < b.wall_x0))) {
                 Js = 2 * b.ng - 1 - J;
                 flipy = true;
+                flipx = b.bc[2] == ASE_BC_NOSLIP;
             } else if (b.bc[2] == ASE_BC_WALL_INFLOW) return SRC_INFLOW;
             else Js = b.ng;
         } else if (j >= b.ny) {
             if (b.bc[3] == ASE_BC_PERIODIC) Js = J - b.ny;
-            else if (b.bc[3] == ASE_BC_REFLECTIVE) { Js = 2 * (b.ny + b.ng) - 1 - J; flipy = true; }
-            else if (b.bc[3] == ASE_BC_MOVING_SHOCK)
+            else if (b.bc[3] == ASE_BC_REFLECTIVE || b.bc[3] == ASE_BC_NOSLIP) {
+                Js = 2 * (b.ny + b.ng) - 1 - J;
+                flipy = true;
+                flipx = b.bc[3] == ASE_BC_NOSLIP;
+            } else if (b.bc[3] == ASE_BC_MOVING_SHOCK)
                 return xc < b.shock_x0 + b.shock_speed * bc_time(b) ? SRC_INFLOW : SRC_OUTER;
             else Js = b.ng + b.ny - 1;
         }
     }
+    // the x rule toggles the flips of the y rule (a no-slip corner reverses
+    // the momentum twice)
     Is = I;
     const int i = I - b.ng;
     if (i < 0) {
         if (b.bc[0] == ASE_BC_PERIODIC) Is = I + b.nx;
         else if (b.bc[0] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return SRC_INFLOW;
-        else if (b.bc[0] == ASE_BC_REFLECTIVE) { Is = 2 * b.ng - 1 - I; flipx = true; }
-        else Is = b.ng;
+        else if (b.bc[0] == ASE_BC_REFLECTIVE || b.bc[0] == ASE_BC_NOSLIP) {
+            Is = 2 * b.ng - 1 - I;
+            flipx = !flipx;
+            if (b.bc[0] == ASE_BC_NOSLIP) flipy = !flipy;
+        } else Is = b.ng;
     } else if (i >= b.nx) {
         if (b.bc[1] == ASE_BC_PERIODIC) Is = I - b.nx;
         else if (b.bc[1] == ASE_BC_INFLOW_SLOT && in_slot(b, Js)) return SRC_INFLOW;
-        else if (b.bc[1] == ASE_BC_REFLECTIVE) { Is = 2 * (b.nx + b.ng) - 1 - I; flipx = true; }
-        else Is = b.ng + b.nx - 1;
+        else if (b.bc[1] == ASE_BC_REFLECTIVE || b.bc[1] == ASE_BC_NOSLIP) {
+            Is = 2 * (b.nx + b.ng) - 1 - I;
+            flipx = !flipx;
+            if (b.bc[1] == ASE_BC_NOSLIP) flipy = !flipy;
+        } else Is = b.ng + b.nx - 1;
     }
     return SRC_CELL;
 }
@@ -166,16 +179,18 @@ __device__ __forceinline__ double sigma_first_order(const BCInfo &b, const doubl
 
 __device__ __forceinline__ int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
+__device__ __forceinline__ bool is_wall(int bc) { return bc == ASE_BC_REFLECTIVE || bc == ASE_BC_NOSLIP; }
+
 // Cell index mapped by the boundary rule of one axis: periodic wrap or wall
 // mirror; other codes leave it.
 __device__ __forceinline__ int map_cell(int i, int n, int lo, int hi)
 {
     if (i < 0) {
         if (lo == ASE_BC_PERIODIC) return wrapi(i, n);
-        if (lo == ASE_BC_REFLECTIVE) return -1 - i;
+        if (is_wall(lo)) return -1 - i;
     } else if (i >= n) {
         if (hi == ASE_BC_PERIODIC) return wrapi(i, n);
-        if (hi == ASE_BC_REFLECTIVE) return 2 * n - 1 - i;
+        if (is_wall(hi)) return 2 * n - 1 - i;
     }
     return i;
 }
@@ -187,10 +202,10 @@ __device__ __forceinline__ int map_face(int f, int n, int lo, int hi)
 {
     if (f < -1) {
         if (lo == ASE_BC_PERIODIC) return wrapi(f, n);
-        if (lo == ASE_BC_REFLECTIVE) return -f - 2;
+        if (is_wall(lo)) return -f - 2;
     } else if (f > n - 1) {
         if (hi == ASE_BC_PERIODIC) return wrapi(f, n);
-        if (hi == ASE_BC_REFLECTIVE) return 2 * n - f - 2;
+        if (is_wall(hi)) return 2 * n - f - 2;
     }
     return f;
 }

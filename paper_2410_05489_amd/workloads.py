@@ -22,6 +22,7 @@ BC_INFLOW_SLOT = 2
 BC_REFLECTIVE = 3   # slip wall: mirrored cells, normal momentum reversed
 BC_WALL_INFLOW = 4  # y-lo: inflow state below wall_x0, slip wall beyond
 BC_MOVING_SHOCK = 5 # y-hi: inflow state behind the moving shock, outer state ahead
+BC_NOSLIP = 6       # no-slip adiabatic wall: mirrored cells, whole momentum reversed
 
 # Interface states the DF strengths come from: the previous stage's
 # Gauss-point states (lagged) or the current stage's cell averages.
@@ -299,6 +300,31 @@ def double_mach(nx: int = 960, ny: int = 240, order: int = 9, t_end: float = 0.2
     _fill_interior(g, U, W)
     return Workload("double_mach", g, Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=1,
                                              df_source=DF_FIRST_ORDER), U, nsteps, t_end)
+
+
+def viscous_shock_tube(nx: int = 500, ny: int = 250, order: int = 5, re: float = 200.0, t_end: float = 1.0,
+                       cfl: float = 0.5, nsteps: int = 100000) -> Workload:
+    """Viscous shock tube on [0,1] x [0,0.5]: (120, 0, 0, 120/gamma) for
+    x < 0.5, (1.2, 0, 0, 1.2/gamma) beyond, gamma 1.4, Pr = 1 (the BGK
+    model's), mu = 1/Re; no-slip adiabatic walls left, right and below, a
+    symmetry plane on top.  First-order DF source, positivity fallback.
+    The workload carries mu (`w.mu`) for the gas-kinetic solver."""
+    gamma = 1.4
+    dx, dy = 1.0 / nx, 0.5 / ny
+    g = Grid(dim=2, nx=nx, ny=ny, ng=ghosts_for(order), dx=dx, dy=dy,
+             bc=(BC_NOSLIP, BC_NOSLIP, BC_NOSLIP, BC_REFLECTIVE))
+    # the split x = 0.5 falls on a face for even nx; otherwise area fractions
+    xl = np.arange(nx) * dx
+    frac = np.clip((0.5 - xl) / dx, 0.0, 1.0)
+    rho = 1.2 + (120.0 - 1.2) * frac
+    p = rho / gamma
+    W = np.stack([rho, 0 * rho, 0 * rho, p / (gamma - 1.0)])[:, None, :].repeat(ny, axis=1)
+    U = empty_state(g)
+    _fill_interior(g, U, W)
+    w = Workload("viscous_shock_tube", g, Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=1,
+                                                 df_source=DF_FIRST_ORDER), U, nsteps, t_end)
+    w.mu = 1.0 / re
+    return w
 
 
 # Configuration 3 of the paper's 2D Riemann tests, quadrant order NE, NW, SW, SE.

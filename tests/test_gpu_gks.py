@@ -225,49 +225,65 @@ def rel_err2(a, b):
 
 
 def _case2d(name, order):
+    """(workload, c1, c2, mu)"""
     if name == "wave2d":
-        return WL.density_wave_2d(24, order, seed=1, amp=1e-3), 0.0, 0.0
+        return WL.density_wave_2d(24, order, seed=1, amp=1e-3), 0.0, 0.0, 0.0
     if name == "quad":
-        return WL.four_quadrant(33, order, seed=3, ny=29), 0.05, 1.0
+        return WL.four_quadrant(33, order, seed=3, ny=29), 0.05, 1.0, 0.0
     if name == "config3":
-        return WL.four_quadrant(40, order, states=WL.CONFIG3_STATES), 0.05, 1.0
+        return WL.four_quadrant(40, order, states=WL.CONFIG3_STATES), 0.05, 1.0, 0.0
     if name == "box":
         w = WL.four_quadrant(33, order, seed=7, ny=29)
         w.grid.bc = (WL.BC_REFLECTIVE,) * 4
-        return w, 0.05, 1.0
+        return w, 0.05, 1.0, 0.0
     if name == "dmr":
-        return WL.double_mach(50, 13, order), 0.05, 1.0
+        return WL.double_mach(50, 13, order), 0.05, 1.0, 0.0
+    if name == "shear":          # viscous: a shear wave in a uniform gas
+        w = WL.density_wave_2d(20, order, seed=3, amp=1e-3)
+        g = w.grid
+        I = g.interior(w.U)
+        I[2] = I[0] * 0.01 * np.sin(2 * np.pi * (np.arange(g.nx) + 0.5) / g.nx)[None, :]
+        I[1] = 0.0
+        I[3] = 1.0 / 0.4 + 0.5 * I[2] ** 2 / I[0]
+        return w, 0.0, 0.0, 0.01
+    if name == "vst":            # viscous shock tube, no-slip walls
+        w = WL.viscous_shock_tube(50, 25, order)
+        return w, 1.0, 10.0, w.mu
+    if name == "noslip":
+        w = WL.four_quadrant(33, order, seed=5, ny=29)
+        w.grid.bc = (WL.BC_NOSLIP,) * 4
+        return w, 1.0, 10.0, 0.01
     raise KeyError(name)
 
 
-def _evolved2d(w, c1, c2, nsteps):
+def _evolved2d(w, c1, c2, mu, nsteps):
     U = w.U.copy()
     sx, sy = O.sigma_init(w.grid, w.params, U)
     t = 0.0
     if nsteps:
-        t, _ = O.step_gks2d(w.grid, w.params, U, sx, sy, 0.0, nsteps, c1=c1, c2=c2)
+        t, _ = O.step_gks2d(w.grid, w.params, U, sx, sy, 0.0, nsteps, c1=c1, c2=c2, mu=mu)
     return U, sx, sy, t
 
 
-def _gpu2d(w, c1, c2, U, sx, sy, t, nsteps, t_end=0.0):
-    sim = ase.GksSimulation(w.grid, w.params, U, c1=c1, c2=c2, device=DEV, sx=sx, sy=sy, t=t)
+def _gpu2d(w, c1, c2, mu, U, sx, sy, t, nsteps, t_end=0.0):
+    sim = ase.GksSimulation(w.grid, w.params, U, c1=c1, c2=c2, mu=mu, device=DEV, sx=sx, sy=sy, t=t)
     hist = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=DEV)
     sim.run(nsteps, t_end, hist)
     return host(sim.U), host(sim.sx), host(sim.sy), float(host(sim.t)[0]), host(hist)[:nsteps]
 
 
 STEP_CASES_2D = [("wave2d", 5), ("wave2d", 9), ("quad", 9), ("quad", 7), ("quad", 3), ("config3", 5), ("box", 5),
-                 ("dmr", 5)]
+                 ("dmr", 5), ("shear", 5), ("shear", 9), ("vst", 5), ("vst", 9), ("noslip", 5)]
 
 
 @pytest.mark.parametrize("name,order", STEP_CASES_2D)
 def test_one_step_2d(name, order):
-    w, c1, c2 = _case2d(name, order)
+    w, c1, c2, mu = _case2d(name, order)
     g, p = w.grid, w.params
-    U, sx, sy, t = _evolved2d(w, c1, c2, 2)
-    Ug, sxg, syg, tg, hg = _gpu2d(w, c1, c2, U, sx, sy, t, 1)
+    U, sx, sy, t = _evolved2d(w, c1, c2, mu, 2)
+    Ug, sxg, syg, tg, hg = _gpu2d(w, c1, c2, mu, U, sx, sy, t, 1)
     Uo, sxo, syo = U.copy(), sx.copy(), sy.copy()
-    to, ho = O.step_gks2d(g, p, Uo, sxo, syo, t, 1, c1=c1, c2=c2)
+    to, ho = O.step_gks2d(g, p, Uo, sxo, syo, t, 1, c1=c1, c2=c2, mu=mu)
     assert abs(hg[0] - ho[0]) <= 1e-14 * ho[0]
     assert rel_err2(g.interior(Ug), g.interior(Uo)) < 1e-12
     ng = g.ng
@@ -278,17 +294,26 @@ def test_one_step_2d(name, order):
     assert np.all(np.abs(a[fin] - b[fin]) <= 1e-9 * np.maximum(np.abs(b[fin]), 1.0))
 
 
-@pytest.mark.parametrize("name,order,nsteps", [("wave2d", 5, 10), ("quad", 9, 6)])
+@pytest.mark.parametrize("name,order,nsteps", [("wave2d", 5, 10), ("quad", 9, 6), ("shear", 5, 10), ("vst", 5, 8)])
 def test_full_run_2d(name, order, nsteps):
-    w, c1, c2 = _case2d(name, order)
+    w, c1, c2, mu = _case2d(name, order)
     g, p = w.grid, w.params
     U0 = w.U.copy()
     sx, sy = O.sigma_init(g, p, U0)
-    Ug, _, _, tg, hg = _gpu2d(w, c1, c2, U0, sx, sy, 0.0, nsteps)
+    Ug, _, _, tg, hg = _gpu2d(w, c1, c2, mu, U0, sx, sy, 0.0, nsteps)
     Uo = U0.copy()
-    to, ho = O.step_gks2d(g, p, Uo, sx.copy(), sy.copy(), 0.0, nsteps, c1=c1, c2=c2)
+    to, ho = O.step_gks2d(g, p, Uo, sx.copy(), sy.copy(), 0.0, nsteps, c1=c1, c2=c2, mu=mu)
     assert abs(tg - to) < 1e-14
     assert rel_err2(g.interior(Ug), g.interior(Uo)) < 1e-9
+
+
+def test_no_slip_box_conserves_mass_and_energy_on_gpu():
+    w, c1, c2, mu = _case2d("noslip", 5)
+    g = w.grid
+    Ug, _, _, _, _ = _gpu2d(w, c1, c2, mu, w.U, None, None, 0.0, 5)
+    s0 = g.interior(w.U).sum(axis=(1, 2))
+    s1 = g.interior(Ug).sum(axis=(1, 2))
+    assert abs(s1[0] - s0[0]) < 1e-12 * s0[0] and abs(s1[3] - s0[3]) < 1e-12 * s0[3]
 
 
 @pytest.mark.parametrize("order,ns,fac", [(5, (20, 40, 80), 0.5), (9, (20, 40), 1.0)])

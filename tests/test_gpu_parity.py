@@ -66,6 +66,10 @@ def _case(name, order, ragged=True):
         w = WL.blast_wave(400, order)
     elif name == "shuosher":
         w = WL.shu_osher(200, order)
+    elif name == "noslip":
+        # four-quadrant data between no-slip adiabatic walls
+        w = WL.four_quadrant(45 if ragged else 32, order, seed=8, ny=37 if ragged else 0)
+        w.grid.bc = (WL.BC_NOSLIP,) * 4
     elif name == "dmr":
         w = WL.double_mach(101 if ragged else 96, 27 if ragged else 24, order)
     elif name == "box":
@@ -226,7 +230,7 @@ def _gpu_run(w, U, sx, sy, t, nsteps, t_end=0.0):
 
 
 STEP_CASES = [("quad", 9), ("quad", 7), ("quad", 5), ("quad", 3), ("quadfo", 9), ("config3", 9), ("wave2d", 9),
-              ("jet", 7), ("box", 9), ("box", 5), ("dmr", 9), ("dmr", 5),
+              ("jet", 7), ("box", 9), ("box", 5), ("dmr", 9), ("dmr", 5), ("noslip", 7),
               ("sod", 5), ("wave1d", 9), ("riemann1d", 9), ("riemann1d", 3), ("blast", 9), ("blast", 5),
               ("shuosher", 9)]
 

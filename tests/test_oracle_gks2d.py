@@ -126,3 +126,65 @@ def test_conservation_and_uniform_flow(oracle):
     g.interior(U0)[...] = np.array([1.0, 0.5, -0.3, 2.7])[:, None, None]
     U1, _, _, _, _ = oracle.run_gks2d(g, p, U0, 3, c1=0.05, c2=1.0)
     assert np.abs(g.interior(U1) - g.interior(U0)).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# viscous flow (Sec. 2.2: tau = mu/p) and the no-slip adiabatic wall
+# ---------------------------------------------------------------------------
+
+def _shear_wave(n, order, V=0.01):
+    import math
+    ng = WL.ghosts_for(order)
+    g = Grid(dim=2, nx=n, ny=ng, ng=ng, dx=1.0 / n, dy=1.0 / n, bc=(WL.BC_PERIODIC,) * 4)
+    xl = np.arange(n) / n
+    vbar = V * (np.cos(2 * math.pi * xl) - np.cos(2 * math.pi * (xl + 1.0 / n))) / (2 * math.pi / n)
+    U = WL.empty_state(g)
+    g.interior(U)[...] = np.stack([np.ones(n), np.zeros(n), vbar, 1.0 / (GAMMA - 1) + 0.5 * vbar ** 2])[:, None, :]
+    return g, U, vbar
+
+
+def test_shear_wave_decays_at_the_navier_stokes_rate(oracle):
+    """v = V sin(2 pi x) in a uniform gas decays as exp(-(mu/rho) k^2 t):
+    the collision time mu/p gives the BGK model's viscosity mu."""
+    import math
+    n, order, mu, T = 32, 5, 0.01, 0.2
+    g, U, vbar = _shear_wave(n, order)
+    p = Params(order=order, gamma=GAMMA, cfl=0.4)
+    Uo, _, _, t, _ = oracle.run_gks2d(g, p, U, 1000, T, c1=0.0, c2=0.0, mu=mu)
+    assert abs(t - T) < 1e-14
+    xc = (np.arange(n) + 0.5) / n
+    proj = lambda f: np.mean(f * np.sin(2 * math.pi * xc))
+    v = g.interior(Uo)[2, 0] / g.interior(Uo)[0, 0]
+    ratio = proj(v) / proj(vbar)
+    assert abs(ratio / math.exp(-mu * (2 * math.pi) ** 2 * T) - 1) < 5e-4
+    # inviscid: the wave is carried unchanged (to the scheme's accuracy)
+    Ui, _, _, _, _ = oracle.run_gks2d(g, p, U, 1000, T, c1=0.0, c2=0.0, mu=0.0)
+    vi = g.interior(Ui)[2, 0] / g.interior(Ui)[0, 0]
+    assert abs(proj(vi) / proj(vbar) - 1) < 1e-5
+
+
+def test_no_slip_box_conserves_mass_and_energy(oracle):
+    w = WL.four_quadrant(16, 5, seed=4)
+    g, p = w.grid, w.params
+    g.bc = (WL.BC_NOSLIP,) * 4
+    U, _, _, _, _ = oracle.run_gks2d(g, p, w.U, 5, c1=1.0, c2=10.0, mu=0.01)
+    s0 = g.interior(w.U).sum(axis=(1, 2))
+    s1 = g.interior(U).sum(axis=(1, 2))
+    assert abs(s1[0] - s0[0]) < 1e-13 * s0[0] and abs(s1[3] - s0[3]) < 1e-13 * s0[3]
+    # the ghost cells mirror the wall with both momenta reversed
+    Ub = w.U.copy()
+    sx, sy = oracle.sigma_init(g, p, Ub)
+    ng = g.ng
+    for k in range(ng):
+        row_in = Ub[:, ng + k, ng:ng + g.nx]
+        row_gh = Ub[:, ng - 1 - k, ng:ng + g.nx]
+        assert np.array_equal(row_gh[[0, 3]], row_in[[0, 3]])
+        assert np.array_equal(row_gh[[1, 2]], -row_in[[1, 2]])
+
+
+def test_viscous_shock_tube_runs(oracle):
+    w = WL.viscous_shock_tube(50, 25, 5)
+    g, p = w.grid, w.params
+    U, _, _, t, _ = oracle.run_gks2d(g, p, w.U, 20, c1=1.0, c2=10.0, mu=w.mu)
+    rho, u, v, pr = _prim2(g.interior(U))
+    assert np.isfinite(rho).all() and rho.min() > 0 and pr.min() > 0
