@@ -427,7 +427,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "launches": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this program runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU domain decomposition is a design note, not implemented)"}))
         sys.exit(2)
 
