@@ -531,7 +531,22 @@ __global__ void __launch_bounds__(NT) k_gks2d_recon(Gks2DArgs a)
     __shared__ double sU[NV][UY][UX];
     __shared__ double sSN[UY][UX];
     __shared__ double sST[SY][SX];
-    __shared__ double sTR[NV][TY][TX], sTL[NV][TY][TX], sDR[NV][TY][TX], sDL[NV][TY][TX];
+    // face traces and their normal slopes, right- and left-face values of
+    // each cell: four segments of one array, placed so that the two lanes of
+    // a face pair (8 faces per 16 lanes) read addresses 8 doubles apart
+    // modulo 16 (the LDS serves a 64-bit read to 16 lanes per cycle, double
+    // d in bank pair d mod 16); the upper side reads the next column (x
+    // faces, +1) or the next row (y faces, +TX)
+    constexpr int NT1 = NV * TY * TX;
+    constexpr int SEG = (NT1 + 15) / 16 * 16;
+    constexpr int TSTEP = (DIR == 0) ? 1 : TX;
+    constexpr int PAIR = SEG + ((8 - TSTEP) % 16 + 16) % 16;
+    constexpr int OTL = PAIR, ODR = (OTL + NT1 + 15) / 16 * 16, ODL = ODR + PAIR;
+    __shared__ double sT[ODL + NT1];
+    double(*sTR)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[0]);
+    double(*sTL)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[OTL]);
+    double(*sDR)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[ODR]);
+    double(*sDL)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[ODL]);
     if (a.skip != nullptr && *a.skip != 0.0) return;
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x * T0, j0 = blockIdx.y * T1;
@@ -554,7 +569,22 @@ __global__ void __launch_bounds__(NT) k_gks2d_recon(Gks2DArgs a)
     __syncthreads();
 
     for (int it = tid; it < TX * TY; it += NT) {
-        const int tx = it % TX, ty = it / TX;
+        // x faces (TX = 17): groups of 16 lanes take 16 columns of one row,
+        // the last column is walked down its rows (distinct bank pairs)
+        int tx, ty;
+        if constexpr (DIR == 0 && TX > 16) {
+            constexpr int MAIN = 16 * TY;
+            if (it < MAIN) {
+                tx = it % 16;
+                ty = it / 16;
+            } else {
+                tx = 16 + (it - MAIN) / TY;
+                ty = (it - MAIN) % TY;
+            }
+        } else {
+            tx = it % TX;
+            ty = it / TX;
+        }
         const int lx = (DIR == 0) ? tx + R : tx;
         const int ly = (DIR == 0) ? ty : ty + R;
         const int x = ox + lx, y = oy + ly;
@@ -909,10 +939,10 @@ __global__ void __launch_bounds__(kGksPointThreads) k_gks_points(GksPointArgs a)
 }
 
 constexpr int kGksNT = 256;
-// 2D reconstruction tiles: x faces 15 x 8 cells, y faces 16 x 7 cells, 256
-// lanes each (one (face, side) item per lane in phase 2).  At 147 registers
-// three 4-wave workgroups fit a CU (52 KB of LDS each for x faces).
-constexpr int kGX_T0 = 15, kGX_T1 = 8, kGX_NT = 256, kGY_T0 = 16, kGY_T1 = 7, kGY_NT = 256;
+// 2D reconstruction tiles: x faces 15 x 7 cells, y faces 16 x 7 cells, 256
+// lanes each (phase 1 in one pass of 255 / 216 cells, phase 2 one (face,
+// side) item per lane).  At 147 registers three 4-wave workgroups fit a CU.
+constexpr int kGX_T0 = 15, kGX_T1 = 7, kGX_NT = 256, kGY_T0 = 16, kGY_T1 = 7, kGY_NT = 256;
 
 template <int R>
 void gks1d_r(int nx, const Gks1DArgs &a, hipStream_t st)
