@@ -390,11 +390,11 @@ __device__ __forceinline__ void xcd_tile(int &tx, int &ty)
     ty = t / gx;
 }
 
-// Occupancy: with the compact tangential strength plane the x sweep (512
-// lanes) fits three workgroups per CU in LDS and the y sweep (256 lanes)
-// five; the second bound asks the compiler for registers that allow it.
+// Occupancy: the bound of six 256-lane waves per SIMD (80 registers) gives
+// the x sweep (512 lanes, 52 KB of LDS) three workgroups per CU and the y
+// sweep (256 lanes, 19 KB with its traces over the staged state) six.
 template <int DIR, int R, int T0, int T1, int NT, int MODE>
-__global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
+__global__ void __launch_bounds__(NT, 6) k_sweep2d(SweepArgs a)
 {
     constexpr int NV = 4, G = R, OI = R - 1;
     using S = SweepShape<DIR, R, T0, T1>;
@@ -403,7 +403,11 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
     constexpr int NU = NV * UY * UX;
     constexpr int NF = (MODE == MODE_RECON) ? 0 : NV * FY * FX;
     static_assert(NF <= NU, "flux tile must fit in the state tile");
-    __shared__ double sUF[NU];        // staged state; reused for the face fluxes
+    // y faces: the face traces overwrite the staged state once phase 1 has
+    // read it, so a workgroup needs 19 instead of 32 KB of LDS and six fit on
+    // a CU (the register bound of 80 then decides).  x faces keep separate
+    // arrays: their 512-lane workgroups are register-bound at three per CU.
+    constexpr bool SHARE = (DIR == 1);
     // strengths: the normal plane over the whole staged tile, the tangential
     // plane only where the side cells' columns (rows) read it
     constexpr int SY = (DIR == 0) ? UY : TY, SX = (DIR == 0) ? TX : UX;
@@ -418,7 +422,11 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
     constexpr int NT1 = NV * TY * TX;
     constexpr int TSTEP = (DIR == 0) ? 1 : TX;
     constexpr int TOFF = (NT1 + 15) / 16 * 16 + ((8 - TSTEP) % 16 + 16) % 16;
-    __shared__ double sT[TOFF + NT1];
+    constexpr int NTT = TOFF + NT1;
+    // staged state; the face traces (SHARE); the face fluxes
+    __shared__ double sUF[SHARE ? (NU > NTT ? NU : NTT) : NU];
+    __shared__ double sTown[SHARE ? 1 : NTT];
+    double *sT = SHARE ? sUF : sTown;
     double(*sTR)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[0]);
     double(*sTL)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[TOFF]);
     auto sU = [&](int v, int y, int x) -> double & { return sUF[(v * UY + y) * UX + x]; };
@@ -463,6 +471,34 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
     }
     __syncthreads();
 
+    if constexpr (SHARE) {
+        // phase 1 in one pass, the traces held in registers until every lane
+        // has read its stencil from the staged state they replace
+        static_assert(DIR == 1 && TX * TY <= NT, "one phase-1 pass");
+        const int tx = tid % TX, ty = tid / TX;
+        const int lx = tx, ly = ty + R;
+        const int x = ox + lx, y = oy + ly;
+        const bool need = tid < TX * TY && x < a.nx + R && y <= a.ny;
+        double out[NV][2];
+        int lvl = 0;
+        if (need) {
+            double s[2 * R];
+#pragma unroll
+            for (int m = -R; m < R; ++m) s[m + R] = sSN[ly + m][lx];
+            auto ld = [&](int v, int m) { return sU(v, ly + m, lx); };
+            lvl = reconstruct_cell<R, NV, 2>(ld, s, mc, OI, 0, out);
+        }
+        __syncthreads();
+        if (need) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                sTR[v][ty][tx] = out[v][0];
+                sTL[v][ty][tx] = out[v][1];
+            }
+            if (MODE == MODE_RECON && a.level != nullptr && x >= 0 && x < a.nx && y >= 0 && y < a.ny)
+                a.level[(long long)y * a.nx + x] = (int8_t)lvl;
+        }
+    } else {
     // phase 1: normal reconstruction, face traces of every cell the tile needs.
     // x faces (TX = 17 trace columns): each group of 16 lanes takes 16
     // columns of one row, the last column is walked down its rows; both
@@ -501,10 +537,15 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
         if (MODE == MODE_RECON && a.level != nullptr && x >= 0 && x < a.nx && y >= 0 && y < a.ny)
             a.level[(long long)y * a.nx + x] = (int8_t)lvl;
     }
+    }
     __syncthreads();
 
     // phase 2: two lanes per face (side = lane & 1)
     constexpr int NITEMS = 2 * FX * FY;
+    static_assert(!SHARE || NITEMS <= NT, "one phase-2 pass");
+    double Fkeep[NV];        // SHARE: this face's flux, stored after the traces are read
+    bool keep = false;
+    int kfx = 0, kfy = 0;
     for (int base = 0; base < NITEMS; base += NT) {   // uniform trip count: lane pairs swap together
         const int it = base + tid;
         const int side = it & 1, f = it >> 1;
@@ -602,14 +643,30 @@ __global__ void __launch_bounds__(NT, DIR == 0 ? 6 : 5) k_sweep2d(SweepArgs a)
                 const bool own = DIR == 0 ? (fx > 0 || i0 == 0) : (fy > 0 || j0 == 0);
                 if (own) a.sig_out[pl] = ssum / (double)G;
             }
-            // the flux tile reuses the state tile: phase 2 reads no staged state
+            // the flux tile reuses the state tile (x faces: phase 2 reads no
+            // staged state; y faces: stored once every lane has read its traces)
             if (valid && side == 0) {
+                if constexpr (SHARE) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sF(v, fy, fx) = Fs[v];
+                    for (int v = 0; v < NV; ++v) Fkeep[v] = Fs[v];
+                    keep = true;
+                    kfx = fx;
+                    kfy = fy;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) sF(v, fy, fx) = Fs[v];
+                }
             }
         }
     }
     if constexpr (MODE == MODE_RECON) return;
+    if constexpr (SHARE) {
+        __syncthreads();   // the traces are read; the flux tile overwrites them
+        if (keep) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sF(v, kfy, kfx) = Fkeep[v];
+        }
+    }
     __syncthreads();
 
     // phase 3: flux differences and (second sweep) the stage update
@@ -1639,10 +1696,10 @@ namespace {
 constexpr int kT1D = 256;
 // 2D sweeps: x faces on 15 x 16 tiles with 512 lanes, y faces on 16 x 7
 // tiles with 256 lanes (the y sweep also streams the residual and the
-// step-start state; four smaller workgroups per CU hide that latency better)
+// step-start state; more, smaller workgroups per CU hide that latency better).
+// (T0 + 1) x T1 = 256 x-faces and T0 x (T1 + 1) = 128 y-faces: one face per
+// lane pair of the block.
 constexpr int kNTX = 512, kNTY = 256;
-// 2D tiles: (T0 + 1) x T1 x-faces and T0 x (T1 + 1) y-faces = 256 faces,
-// i.e. one face per lane pair of a 512-thread block.
 constexpr int kX_T0 = 15, kX_T1 = 16, kY_T0 = 16, kY_T1 = 7;
 
 template <int R>
