@@ -547,6 +547,22 @@ __device__ __forceinline__ double gauss_point_sided(double (&Wo)[NV], double (&W
     return sg;
 }
 
+// Tile of this workgroup.  Workgroups are dispatched round-robin over the
+// 8 XCDs (each with its own L2); remapping the linear block index so that
+// every XCD receives one contiguous band of tiles keeps the halos that
+// neighbouring tiles share inside one L2.
+__device__ __forceinline__ void xcd_tile(int &tx, int &ty)
+{
+    constexpr int kXCD = 8;
+    const int gx = gridDim.x, n = gridDim.x * gridDim.y;
+    const int b = blockIdx.y * gx + blockIdx.x;
+    const int per = n / kXCD;
+    int t = b;
+    if (b < per * kXCD) t = (b % kXCD) * per + b / kXCD;
+    tx = t % gx;
+    ty = t / gx;
+}
+
 // Exchange a double with the neighbouring lane (lane ^ 1) of a pair.  Both
 // lanes of the pair must be active.
 __device__ __forceinline__ double swap_pair(double x)

@@ -549,7 +549,9 @@ __global__ void __launch_bounds__(NT) k_gks2d_recon(Gks2DArgs a)
     double(*sDL)[TY][TX] = reinterpret_cast<double(*)[TY][TX]>(&sT[ODL]);
     if (a.skip != nullptr && *a.skip != 0.0) return;
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * T0, j0 = blockIdx.y * T1;
+    int btx, bty;
+    xcd_tile(btx, bty);
+    const int i0 = btx * T0, j0 = bty * T1;
     const int ox = (DIR == 0) ? i0 - 1 - R : i0 - R;
     const int oy = (DIR == 0) ? j0 - R : j0 - 1 - R;
     const MethodConst &mc = a.mc;

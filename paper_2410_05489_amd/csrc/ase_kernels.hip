@@ -374,22 +374,6 @@ __global__ void __launch_bounds__(kThreads) k_cfl_final(const double *part, int 
 // SSP-RK3 stage combination.
 // ---------------------------------------------------------------------------
 
-// Tile of this workgroup.  Workgroups are dispatched round-robin over the
-// 8 XCDs (each with its own L2); remapping the linear block index so that
-// every XCD receives one contiguous band of tiles keeps the halos that
-// neighbouring tiles share inside one L2.
-__device__ __forceinline__ void xcd_tile(int &tx, int &ty)
-{
-    constexpr int kXCD = 8;
-    const int gx = gridDim.x, n = gridDim.x * gridDim.y;
-    const int b = blockIdx.y * gx + blockIdx.x;
-    const int per = n / kXCD;
-    int t = b;
-    if (b < per * kXCD) t = (b % kXCD) * per + b / kXCD;
-    tx = t % gx;
-    ty = t / gx;
-}
-
 // Occupancy: the bound of six 256-lane waves per SIMD (80 registers) gives
 // the x sweep (512 lanes, 52 KB of LDS) three workgroups per CU and the y
 // sweep (256 lanes, 19 KB with its traces over the staged state) six.
