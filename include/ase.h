@@ -56,7 +56,9 @@ enum {
     ASE_ERR_GHOST = -3,     /* ng < (order+1)/2                          */
     ASE_ERR_ALIGN = -4,     /* device pointer not 8-byte aligned         */
     ASE_ERR_HIP = -5,       /* a HIP runtime call failed                 */
-    ASE_ERR_WORKSPACE = -6  /* workspace missing or too small            */
+    ASE_ERR_WORKSPACE = -6, /* workspace missing or too small            */
+    ASE_ERR_NONPHYSICAL = -7 /* ASE_FLAG_FAIL_NONPHYSICAL: the final state
+                                holds a cell with rho <= 0, p <= 0 or NaN */
 };
 
 /* Boundary codes.  TRANSMISSIVE: zero-gradient copy of the boundary cell;
@@ -82,7 +84,14 @@ enum {
      * order"): the first-order states of the current stage input, i.e. the
      * two cell averages beside each face; ase_bc_fill then recomputes every
      * stored strength from the ghost-filled state. */
-    ASE_FLAG_DF_FIRST_ORDER = 2
+    ASE_FLAG_DF_FIRST_ORDER = 2,
+    /* ase_step, ase_step_gks: after the last step count the interior cells
+     * whose average has rho <= 0, p <= 0 or a NaN component and return
+     * ASE_ERR_NONPHYSICAL if there is one (U, the strengths and t are
+     * written all the same).  The count is read back to the host, so the
+     * call synchronises its stream; it cannot be captured in a graph
+     * (ASE_ERR_ARG while the stream is capturing). */
+    ASE_FLAG_FAIL_NONPHYSICAL = 4
 };
 
 /* Grid and boundary description (the problem statement of Sec. 2.1 and

@@ -21,6 +21,8 @@ _LIB = None
 
 FLAG_POSITIVITY_FALLBACK = 1
 FLAG_DF_FIRST_ORDER = 2
+FLAG_FAIL_NONPHYSICAL = 4
+ERR_NONPHYSICAL = -7
 
 
 class AseGrid(C.Structure):
@@ -53,7 +55,11 @@ class AseGks(C.Structure):
 
 
 class AseError(RuntimeError):
-    pass
+    """A failed library call; `code` is its ASE_ERR_* status."""
+
+    def __init__(self, msg: str, code: int = 0):
+        super().__init__(msg)
+        self.code = code
 
 
 def lib():
@@ -122,7 +128,8 @@ def c_params(p: Params) -> AseParams:
     s = AseParams()
     s.order = int(p.order)
     s.flags = (FLAG_POSITIVITY_FALLBACK if p.positivity_fallback else 0) | \
-        (FLAG_DF_FIRST_ORDER if p.df_source == 1 else 0)
+        (FLAG_DF_FIRST_ORDER if p.df_source == 1 else 0) | \
+        (FLAG_FAIL_NONPHYSICAL if p.fail_nonphysical else 0)
     s.gamma, s.cfl, s.sigma_thres, s.eps = p.gamma, p.cfl, p.sigma_thres, p.eps
     s.d_hi, s.d_lo, s.dt_cap = p.d_hi, p.d_lo, p.dt_cap
     return s
@@ -147,7 +154,7 @@ def _p(t: Optional[torch.Tensor]):
 def _check(rc: int, what: str):
     if rc != 0:
         msg = lib().ase_last_error().decode()
-        raise AseError(f"{what} failed ({rc}): {msg}")
+        raise AseError(f"{what} failed ({rc}): {msg}", rc)
 
 
 def _gp(g, p):

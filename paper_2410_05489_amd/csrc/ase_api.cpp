@@ -341,6 +341,39 @@ int ase_stage_update(const ase_grid_t *g, const ase_params_t *p, int stage, cons
     return check_launch("ase_stage_update");
 }
 
+// ASE_FLAG_FAIL_NONPHYSICAL: refuse graph capture before any launch ...
+static int nonphysical_capturable(const ase_params_t *p, hipStream_t st)
+{
+    if (!(p->flags & ASE_FLAG_FAIL_NONPHYSICAL)) return ASE_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(ASE_ERR_ARG, "ASE_FLAG_FAIL_NONPHYSICAL synchronises the stream and cannot be captured");
+    return ASE_OK;
+}
+
+// ... and after the last step count the non-physical interior cells.
+static int nonphysical_check(const ase_grid_t *g, const Geo &geo, const ase_params_t *p, const double *U,
+                             const Workspace &w, hipStream_t st, const char *who)
+{
+    if (!(p->flags & ASE_FLAG_FAIL_NONPHYSICAL)) return ASE_OK;
+    launch_nonphysical(*g, geo, method_const(p), U, w.part, w.nparts, st);
+    int rc = check_launch(who);
+    if (rc) return rc;
+    std::vector<double> part((size_t)w.nparts);
+    hipError_t e = hipMemcpyAsync(part.data(), w.part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(non-physical count)");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    double n = 0.0;
+    for (double c : part) n += c;
+    if (n > 0.0)
+        return fail(ASE_ERR_NONPHYSICAL, std::string(who) + ": " + std::to_string((long long)n) +
+                                             " interior cells with rho <= 0, p <= 0 or NaN");
+    return ASE_OK;
+}
+
 int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, double *t,
              double *dt_hist, int32_t nsteps, double t_end, void *ws, size_t ws_bytes, void *stream)
 {
@@ -357,6 +390,8 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
     rc = carve_workspace(geo, ws, ws_bytes, &w);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
+    rc = nonphysical_capturable(p, st);
+    if (rc) return rc;
     const MethodConst mc = method_const(p);
     SweepArgs a = base_args(g, geo, mc);
     a.dt = w.scal;
@@ -430,7 +465,9 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
             if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(sy)");
         }
     }
-    return check_launch("ase_step");
+    rc = check_launch("ase_step");
+    if (rc) return rc;
+    return nonphysical_check(g, geo, p, U, w, st, "ase_step");
 }
 
 static GksConst gks_const(const ase_params_t *p, const ase_gks_t *gk, int dim)
@@ -543,6 +580,8 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
     rc = carve_workspace(geo, ws, ws_bytes, &w);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
+    rc = nonphysical_capturable(p, st);
+    if (rc) return rc;
     const MethodConst mc = method_const(p);
     const GksConst gc = gks_const(p, gk, geo.dim);
     const bool fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) != 0;
@@ -666,7 +705,9 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
         }
         stage(2);
     }
-    return check_launch("ase_step_gks");
+    rc = check_launch("ase_step_gks");
+    if (rc) return rc;
+    return nonphysical_check(g, geo, p, U, w, st, "ase_step_gks");
 }
 
 int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_t *bin_start, int32_t *bin_list)

@@ -47,6 +47,9 @@ void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, 
 void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
                        double *sy, hipStream_t st, const double *t = nullptr, const double *dt = nullptr,
                        double ct = 0.0);
+// per-block counts of non-physical interior cells into part[0..nparts)
+void launch_nonphysical(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, const double *U, double *part,
+                        int nparts, hipStream_t st);
 void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,
                 const double *t_in, double *t_out, double t_end, double *dt, double *skip, double *dt_hist,
                 double *part, int nparts, hipStream_t st);

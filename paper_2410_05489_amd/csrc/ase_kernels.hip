@@ -311,6 +311,40 @@ __global__ void __launch_bounds__(kThreads) k_cfl_partial(BCInfo b, MethodConst 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Number of interior cells with rho <= 0, p <= 0 or a NaN among them, per
+// block (an exact integer in a double); the host adds the blocks up.
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_nonphysical_partial(BCInfo b, MethodConst mc, const double *U,
+                                                                  double *part)
+{
+    __shared__ double red[kThreads];
+    const int ny = b.dim == 1 ? 1 : b.ny;
+    const long long n = (long long)ny * b.nx;
+    double cnt = 0.0;
+    for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * kThreads) {
+        const int j = (int)(idx / b.nx), i = (int)(idx % b.nx);
+        const long long pos = (long long)(b.dim == 1 ? 0 : j + b.ng) * b.ld + i + b.ng;
+        double W[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + pos];
+        double ke = W[1] * W[1];
+        if constexpr (NV == 4) ke += W[2] * W[2];
+        const double p = mc.gm1 * (W[NV - 1] - 0.5 * ke / W[0]);
+        bool bad = !(W[0] > 0.0) || !(p > 0.0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) bad = bad || W[v] != W[v];
+        cnt += bad ? 1.0 : 0.0;
+    }
+    red[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 struct InflowSpeed {
     int on, dim;
     double W[4];
@@ -1655,6 +1689,14 @@ void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &m
     const int nb = grid_blocks((long long)geo.NY * geo.NX);
     if (geo.nv == 4) k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
     else k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
+}
+
+void launch_nonphysical(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, const double *U, double *part,
+                        int nparts, hipStream_t st)
+{
+    const BCInfo b = make_bc(g, geo);
+    if (geo.nv == 4) k_nonphysical_partial<4><<<nparts, kThreads, 0, st>>>(b, mc, U, part);
+    else k_nonphysical_partial<3><<<nparts, kThreads, 0, st>>>(b, mc, U, part);
 }
 
 void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,

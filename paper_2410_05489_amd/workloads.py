@@ -94,6 +94,7 @@ class Params:
     dt_cap: float = 0.0
     positivity_fallback: int = 0
     df_source: int = 0          # DF_LAGGED or DF_FIRST_ORDER
+    fail_nonphysical: int = 0   # ase_step / ase_step_gks report a non-physical final state
 
 
 @dataclasses.dataclass

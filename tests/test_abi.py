@@ -100,3 +100,19 @@ def test_gks_argument_errors():
     rc = L.ase_gks_flux(P1, C.byref(gk), 4, None, None, None, None, 0.0, None, None, None)
     assert rc == -1 and b"dt" in L.ase_last_error()
     assert L.ase_gks_flux(P1, C.byref(gk), 0, None, None, None, None, 0.1, None, None, None) == 0
+
+
+def test_python_constants_match_header():
+    """Flag and status values the binding uses are the header's."""
+    text = open(os.path.join(ROOT, "include", "ase.h")).read()
+
+    def val(name):
+        return int(re.search(rf"\b{name}\s*=\s*(-?\d+)", text).group(1))
+
+    assert val("ASE_FLAG_POSITIVITY_FALLBACK") == ase.FLAG_POSITIVITY_FALLBACK
+    assert val("ASE_FLAG_DF_FIRST_ORDER") == ase.FLAG_DF_FIRST_ORDER
+    assert val("ASE_FLAG_FAIL_NONPHYSICAL") == ase.FLAG_FAIL_NONPHYSICAL
+    assert val("ASE_ERR_NONPHYSICAL") == ase.ERR_NONPHYSICAL
+    p = WL.sod(20, 5).params
+    p.fail_nonphysical = 1
+    assert ase.c_params(p).flags & ase.FLAG_FAIL_NONPHYSICAL

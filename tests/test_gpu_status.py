@@ -1,0 +1,121 @@
+"""ASE_FLAG_FAIL_NONPHYSICAL on the GPU: ase_step and ase_step_gks report a
+final state that holds cells with rho <= 0, p <= 0 or a NaN; the count they
+report is checked against the same predicate evaluated here in numpy, and a
+flagged run of a physical state equals the unflagged one bit for bit."""
+import copy
+import re
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_05489_amd import ase
+from paper_2410_05489_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _nonphysical(g, U, gamma):
+    """Cells of the interior whose average is not a physical state."""
+    I = g.interior(U)
+    rho, E = I[0], I[-1]
+    ke = I[1] ** 2 + (I[2] ** 2 if I.shape[0] == 4 else 0.0)
+    with np.errstate(all="ignore"):
+        p = (gamma - 1.0) * (E - 0.5 * ke / rho)
+        bad = ~(rho > 0) | ~(p > 0) | np.isnan(I).any(axis=0)
+    return int(bad.sum())
+
+
+def _spoil(w):
+    """Three bad cells: negative pressure, zero density, a NaN momentum."""
+    g = w.grid
+    U = w.U.copy()
+    n = g.ng
+    if g.dim == 2:
+        U[3, n + 7, n + 11] = 0.1 * U[3, n + 7, n + 11] - 10.0
+        U[0, n + 2, n + 30] = 0.0
+        U[1, n + 20, n + 3] = np.nan
+    else:
+        U[2, 0, n + 7] = -1.0
+        U[0, 0, n + 20] = 0.0
+        U[1, 0, n + 33] = np.nan
+    return U
+
+
+def _flagged(p):
+    q = copy.copy(p)
+    q.fail_nonphysical = 1
+    return q
+
+
+@pytest.mark.parametrize("name", ["quad2d", "sod1d"])
+def test_step_reports_nonphysical_state(name):
+    w = WL.four_quadrant(40, 9, seed=3) if name == "quad2d" else WL.sod(60, 5)
+    g, p = w.grid, w.params
+    U = _spoil(w)
+    expect = _nonphysical(g, U, p.gamma)
+    assert expect == 3
+    # unflagged: no status, state untouched by a zero-step call
+    sim = ase.Simulation(g, p, U, device=DEV)
+    sim.run(0)
+    torch.cuda.synchronize()
+    # flagged: ASE_ERR_NONPHYSICAL with the count
+    sim = ase.Simulation(g, _flagged(p), U, device=DEV)
+    with pytest.raises(ase.AseError) as e:
+        sim.run(0)
+    assert e.value.code == ase.ERR_NONPHYSICAL
+    assert int(re.search(r"(\d+) interior cells", str(e.value)).group(1)) == expect
+
+
+@pytest.mark.parametrize("name", ["quad2d", "sod1d"])
+def test_gks_step_reports_nonphysical_state(name):
+    w = WL.four_quadrant(40, 5, seed=3) if name == "quad2d" else WL.sod(60, 5)
+    g, p = w.grid, w.params
+    U = _spoil(w)
+    sim = ase.GksSimulation(g, _flagged(p), U, c1=0.05, c2=1.0, device=DEV)
+    with pytest.raises(ase.AseError) as e:
+        sim.run(0)
+    assert e.value.code == ase.ERR_NONPHYSICAL
+    assert int(re.search(r"(\d+) interior cells", str(e.value)).group(1)) == _nonphysical(g, U, p.gamma)
+
+
+def test_flag_leaves_physical_runs_unchanged():
+    w = WL.four_quadrant(48, 9, seed=5, ny=40)
+    g, p = w.grid, w.params
+    a = ase.Simulation(g, p, w.U, device=DEV)
+    b = ase.Simulation(g, _flagged(p), w.U, device=DEV)
+    a.run(4)
+    b.run(4)
+    torch.cuda.synchronize()
+    assert torch.equal(a.U, b.U) and torch.equal(a.sx, b.sx) and torch.equal(a.sy, b.sy)
+    assert torch.equal(a.t, b.t)
+    ga = ase.GksSimulation(g, p, w.U, c1=0.05, c2=1.0, device=DEV)
+    gb = ase.GksSimulation(g, _flagged(p), w.U, c1=0.05, c2=1.0, device=DEV)
+    ga.run(3)
+    gb.run(3)
+    torch.cuda.synchronize()
+    assert torch.equal(ga.U, gb.U)
+
+
+def test_flag_refuses_graph_capture():
+    """The flag needs a read-back, so a capturing stream is refused before
+    any work is recorded; the capture then ends empty."""
+    w = WL.four_quadrant(32, 9, seed=2)
+    g, p = w.grid, w.params
+    sim = ase.Simulation(g, _flagged(p), w.U, device=DEV)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    code = None
+    with torch.cuda.graph(graph):
+        try:
+            sim.run(2)
+        except ase.AseError as e:
+            code = e.code
+    torch.cuda.synchronize()
+    assert code == -1
+    # the same simulation still runs outside the capture
+    sim.run(2)
+    torch.cuda.synchronize()
+    assert np.isfinite(sim.U.cpu().numpy()).all()
