@@ -632,8 +632,19 @@ __global__ void __launch_bounds__(NT, 6) k_sweep2d(SweepArgs a)
             const int po = side == 0 ? pl : pr, pt = side == 0 ? pr : pl;
             const double *U = a.U;
             const long long P = a.plane;
-            auto co = [=](int v) { return U[v * P + po]; };
-            auto ct = [=](int v) { return U[v * P + pt]; };
+            // the replacement is rare: an empty asm on the position keeps
+            // its address arithmetic from being hoisted into registers that
+            // stay live across the Gauss points (4 spilled registers)
+            auto co = [=](int v) {
+                int q = po;
+                asm volatile("" : "+v"(q));
+                return U[v * P + q];
+            };
+            auto ct = [=](int v) {
+                int q = pt;
+                asm volatile("" : "+v"(q));
+                return U[v * P + q];
+            };
             const double sgn = side == 0 ? 1.0 : -1.0;
 #pragma unroll
             for (int j = 0; j < GA; ++j) {
