@@ -99,6 +99,7 @@ def test_flag_leaves_physical_runs_unchanged():
     assert torch.equal(ga.U, gb.U)
 
 
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
 def test_flag_refuses_graph_capture():
     """The flag needs a read-back, so a capturing stream is refused before
     any work is recorded; the capture then ends empty."""
