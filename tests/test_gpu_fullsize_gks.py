@@ -1,0 +1,138 @@
+"""Gas-kinetic path at the sizes and launch shapes the bench times (2D
+Configuration 3 at 1024^2, 1D Shu-Osher at 2^20 cells, order 9), checked
+against the oracle on sampled cells: the GPU advances the whole grid one
+S2O4 step, and the oracle advances a window of the same input around each
+sample.  Influence travels at most 2 (R + 1) + 2 cells per step (two stages,
+each reading reconstruction stencils of R + 1 cells and lagged strengths of
+its faces), so a window reaching H cells beyond its centre gives the centre
+exactly where H exceeds that; windows are clipped at the domain edges, whose
+boundary rule the window then shares.  Both sides take the same time step
+(a cap below the CFL one, computed here from the input)."""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2410_05489_amd import ase
+from paper_2410_05489_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+C1, C2 = 0.05, 1.0
+
+
+def _cfl_dt(g, p, U):
+    """CFL time step of the input state (the rule of the dt kernel)."""
+    I = g.interior(U)
+    rho = I[0]
+    u = I[1] / rho
+    if g.dim == 2:
+        v = I[2] / rho
+        pr = (p.gamma - 1.0) * (I[3] - 0.5 * rho * (u * u + v * v))
+        c = np.sqrt(p.gamma * pr / rho)
+        lam = (np.abs(u) + c) / g.dx + (np.abs(v) + c) / g.dy
+    else:
+        pr = (p.gamma - 1.0) * (I[2] - 0.5 * rho * u * u)
+        c = np.sqrt(p.gamma * pr / rho)
+        lam = (np.abs(u) + c) / g.dx
+    return p.cfl / float(lam.max())
+
+
+def _capped(w):
+    p = copy.copy(w.params)
+    p.dt_cap = 0.5 * _cfl_dt(w.grid, p, w.U)
+    return p
+
+
+def _window(w, lo, hi):
+    """Sub-grid of cells [lo, hi) per axis (x, y), same spacing and boundary
+    codes, interior copied from the workload's input."""
+    g = w.grid
+    if g.dim == 2:
+        sg = WL.Grid(dim=2, nx=hi[0] - lo[0], ny=hi[1] - lo[1], ng=g.ng, dx=g.dx, dy=g.dy, bc=g.bc)
+        U = WL.empty_state(sg)
+        sg.interior(U)[...] = g.interior(w.U)[:, lo[1]:hi[1], lo[0]:hi[0]]
+    else:
+        sg = WL.Grid(dim=1, nx=hi[0] - lo[0], ny=1, ng=g.ng, dx=g.dx, dy=g.dy, bc=g.bc)
+        U = WL.empty_state(sg)
+        sg.interior(U)[...] = g.interior(w.U)[:, :, lo[0]:hi[0]]
+    return sg, U
+
+
+def _scale(g, U):
+    """Max-norm of each conserved variable over the interior (momentum
+    components share the scale of the momentum vector)."""
+    I = g.interior(U).reshape(g.nvar, -1)
+    s = np.abs(I).max(axis=1)
+    if g.nvar == 4:
+        s[1] = s[2] = float(np.sqrt(I[1] ** 2 + I[2] ** 2).max())
+    return np.maximum(s, 1e-300)
+
+
+def test_gks2d_config3_1024_sampled():
+    R = 4
+    H = 2 * (R + 1) + 2 + 4
+    w = WL.four_quadrant(1024, 9, states=WL.CONFIG3_STATES)
+    g = w.grid
+    p = _capped(w)
+    sim = ase.GksSimulation(g, p, w.U, c1=C1, c2=C2, device=DEV)
+    sim.run(1)
+    Ug = sim.U.cpu().numpy()
+    dU = g.interior(Ug) - g.interior(w.U)
+    assert np.isfinite(dU).all()
+    scale = _scale(g, w.U)
+    # the quadrant lines cross at x = y = 0.7 (cells 716 | 717); corners,
+    # edges and the crossing, the four lines, uniform interior
+    centres = [(716, 716), (717, 717), (717, 300), (300, 716), (905, 717), (716, 1023), (0, 0), (1023, 717),
+               (512, 100)]
+    worst = worst_inc = 0.0
+    inc_scale = np.abs(dU).reshape(4, -1).max(axis=1)
+    for ci, cj in centres:
+        lo = (max(0, ci - H), max(0, cj - H))
+        hi = (min(g.nx, ci + H + 1), min(g.ny, cj + H + 1))
+        sg, U = _window(w, lo, hi)
+        sx, sy = O.sigma_init(sg, p, U)
+        U0 = U.copy()
+        O.step_gks2d(sg, p, U, sx, sy, 0.0, 1, c1=C1, c2=C2)
+        o = sg.interior(U)[:, cj - lo[1], ci - lo[0]]
+        do = o - sg.interior(U0)[:, cj - lo[1], ci - lo[0]]
+        gv = g.interior(Ug)[:, cj, ci]
+        worst = max(worst, float(np.max(np.abs(gv - o) / scale)))
+        dg = dU[:, cj, ci]
+        worst_inc = max(worst_inc, float(np.max(np.abs(dg - do) / np.maximum(inc_scale, 1e-300))))
+    assert worst < 1e-12, worst
+    assert worst_inc < 1e-9, worst_inc
+
+
+def test_gks1d_shu_osher_2p20_sampled():
+    R = 4
+    H = 2 * (R + 1) + 2 + 8
+    n = 1 << 20
+    w = WL.shu_osher(n, 9)
+    g = w.grid
+    p = _capped(w)
+    sim = ase.GksSimulation(g, p, w.U, c1=C1, c2=C2, device=DEV)
+    sim.run(1)
+    Ug = sim.U.cpu().numpy()
+    dU = g.interior(Ug) - g.interior(w.U)
+    assert np.isfinite(dU).all()
+    scale = _scale(g, w.U)
+    inc_scale = np.abs(dU).reshape(3, -1).max(axis=1)
+    shock = n // 10   # x = 1 on [0, 10]
+    centres = [0, 5, shock - 1, shock, shock + 1, shock + 3, n // 3, n // 2 + 17, n - 6, n - 1]
+    worst = worst_inc = 0.0
+    for c in centres:
+        lo, hi = max(0, c - H), min(n, c + H + 1)
+        sg, U = _window(w, (lo,), (hi,))
+        sx, _ = O.sigma_init(sg, p, U)
+        U0 = U.copy()
+        O.step_gks(sg, p, U, sx, 0.0, 1, c1=C1, c2=C2)
+        o = sg.interior(U)[:, 0, c - lo]
+        do = o - sg.interior(U0)[:, 0, c - lo]
+        gv = g.interior(Ug)[:, 0, c]
+        worst = max(worst, float(np.max(np.abs(gv - o) / scale)))
+        worst_inc = max(worst_inc, float(np.max(np.abs(dU[:, 0, c] - do) / np.maximum(inc_scale, 1e-300))))
+    assert worst < 1e-12, worst
+    assert worst_inc < 1e-9, worst_inc
