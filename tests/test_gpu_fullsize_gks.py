@@ -1,5 +1,6 @@
 """Gas-kinetic path at the sizes and launch shapes the bench times (2D
-Configuration 3 at 1024^2, 1D Shu-Osher at 2^20 cells, order 9), checked
+Configuration 3 at 1024^2, the viscous shock tube at 500 x 250, 1D
+Shu-Osher at 2^20 cells, order 9), checked
 against the oracle on sampled cells: the GPU advances the whole grid one
 S2O4 step, and the oracle advances a window of the same input around each
 sample.  Influence travels at most 2 (R + 1) + 2 cells per step (two stages,
@@ -71,37 +72,55 @@ def _scale(g, U):
     return np.maximum(s, 1e-300)
 
 
-def test_gks2d_config3_1024_sampled():
-    R = 4
-    H = 2 * (R + 1) + 2 + 4
-    w = WL.four_quadrant(1024, 9, states=WL.CONFIG3_STATES)
+def _check2d(w, c1, c2, mu, centres, H):
+    """One GPU step of the whole grid against oracle windows around centres
+    (cell (i, j) pairs); returns the worst state and increment errors."""
     g = w.grid
     p = _capped(w)
-    sim = ase.GksSimulation(g, p, w.U, c1=C1, c2=C2, device=DEV)
+    sim = ase.GksSimulation(g, p, w.U, c1=c1, c2=c2, mu=mu, device=DEV)
     sim.run(1)
     Ug = sim.U.cpu().numpy()
     dU = g.interior(Ug) - g.interior(w.U)
     assert np.isfinite(dU).all()
-    scale = _scale(g, w.U)
-    # the quadrant lines cross at x = y = 0.7 (cells 716 | 717); corners,
-    # edges and the crossing, the four lines, uniform interior
-    centres = [(716, 716), (717, 717), (717, 300), (300, 716), (905, 717), (716, 1023), (0, 0), (1023, 717),
-               (512, 100)]
+    scale = _scale(g, Ug)   # of the advanced state (the input may hold a zero momentum)
+    # increments below 1e-12 of the state are rounding noise for this check
+    inc_scale = np.maximum(np.abs(dU).reshape(4, -1).max(axis=1), 1e-12 * scale)
     worst = worst_inc = 0.0
-    inc_scale = np.abs(dU).reshape(4, -1).max(axis=1)
     for ci, cj in centres:
         lo = (max(0, ci - H), max(0, cj - H))
         hi = (min(g.nx, ci + H + 1), min(g.ny, cj + H + 1))
         sg, U = _window(w, lo, hi)
         sx, sy = O.sigma_init(sg, p, U)
         U0 = U.copy()
-        O.step_gks2d(sg, p, U, sx, sy, 0.0, 1, c1=C1, c2=C2)
+        O.step_gks2d(sg, p, U, sx, sy, 0.0, 1, c1=c1, c2=c2, mu=mu)
         o = sg.interior(U)[:, cj - lo[1], ci - lo[0]]
         do = o - sg.interior(U0)[:, cj - lo[1], ci - lo[0]]
-        gv = g.interior(Ug)[:, cj, ci]
-        worst = max(worst, float(np.max(np.abs(gv - o) / scale)))
-        dg = dU[:, cj, ci]
-        worst_inc = max(worst_inc, float(np.max(np.abs(dg - do) / np.maximum(inc_scale, 1e-300))))
+        worst = max(worst, float(np.max(np.abs(g.interior(Ug)[:, cj, ci] - o) / scale)))
+        worst_inc = max(worst_inc, float(np.max(np.abs(dU[:, cj, ci] - do) / inc_scale)))
+    return worst, worst_inc
+
+
+def test_gks2d_config3_1024_sampled():
+    """Configuration 3 at 1024^2: the quadrant lines cross at x = y = 0.7
+    (cells 716 | 717); samples on the crossing, the four lines, the corners
+    and edges and the uniform interior."""
+    w = WL.four_quadrant(1024, 9, states=WL.CONFIG3_STATES)
+    centres = [(716, 716), (717, 717), (717, 300), (300, 716), (905, 717), (716, 1023), (0, 0), (1023, 717),
+               (512, 100)]
+    worst, worst_inc = _check2d(w, C1, C2, 0.0, centres, H=2 * 5 + 2 + 4)
+    assert worst < 1e-12, worst
+    assert worst_inc < 1e-9, worst_inc
+
+
+def test_gks2d_viscous_shock_tube_500x250_sampled():
+    """Viscous shock tube at 500 x 250, r = 9, Re 200 (no-slip walls left,
+    right and below, symmetry on top): samples on the diaphragm at x = 0.5
+    (cells 249 | 250) from the bottom wall to the symmetry plane, and the
+    corners."""
+    w = WL.viscous_shock_tube(500, 250, 9)
+    centres = [(249, 0), (250, 0), (249, 1), (250, 125), (249, 249), (250, 248), (0, 0), (499, 0), (499, 249),
+               (100, 60)]
+    worst, worst_inc = _check2d(w, 1.0, 10.0, w.mu, centres, H=2 * 5 + 2 + 4)
     assert worst < 1e-12, worst
     assert worst_inc < 1e-9, worst_inc
 
@@ -118,8 +137,8 @@ def test_gks1d_shu_osher_2p20_sampled():
     Ug = sim.U.cpu().numpy()
     dU = g.interior(Ug) - g.interior(w.U)
     assert np.isfinite(dU).all()
-    scale = _scale(g, w.U)
-    inc_scale = np.abs(dU).reshape(3, -1).max(axis=1)
+    scale = _scale(g, Ug)   # of the advanced state (the input may hold a zero momentum)
+    inc_scale = np.maximum(np.abs(dU).reshape(3, -1).max(axis=1), 1e-12 * scale)
     shock = n // 10   # x = 1 on [0, 10]
     centres = [0, 5, shock - 1, shock, shock + 1, shock + 3, n // 3, n // 2 + 17, n - 6, n - 1]
     worst = worst_inc = 0.0
@@ -133,6 +152,6 @@ def test_gks1d_shu_osher_2p20_sampled():
         do = o - sg.interior(U0)[:, 0, c - lo]
         gv = g.interior(Ug)[:, 0, c]
         worst = max(worst, float(np.max(np.abs(gv - o) / scale)))
-        worst_inc = max(worst_inc, float(np.max(np.abs(dU[:, 0, c] - do) / np.maximum(inc_scale, 1e-300))))
+        worst_inc = max(worst_inc, float(np.max(np.abs(dU[:, 0, c] - do) / inc_scale)))
     assert worst < 1e-12, worst
     assert worst_inc < 1e-9, worst_inc
