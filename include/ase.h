@@ -14,7 +14,9 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
  *    asynchronous on that stream; results are ready once the caller
  *    synchronises the stream.  Scalars such as dt and t live in device
- *    memory so whole steps can run without a host round trip.
+ *    memory so whole steps can run without a host round trip.  (Only
+ *    ASE_FLAG_FAIL_NONPHYSICAL makes ase_step / ase_step_gks synchronise,
+ *    to read back the count they report.)
  *  - Return value: ASE_OK (0) or a negative ASE_ERR_* code; the message of
  *    the last failure on the calling host thread is ase_last_error().
  *    Argument errors are detected before anything is launched.
