@@ -42,7 +42,8 @@ def _args(order=9, **kw):
 
 
 @pytest.mark.parametrize("kw,code", [({"order": 4}, -2), ({"order": 11}, -2), ({"ng": 4}, -3),
-                                     ({"ld": 20}, -1), ({"dim": 3}, -1)])
+                                     ({"ld": 20}, -1), ({"dim": 3}, -1), ({"nx": 0}, -1), ({"ny": 0}, -1),
+                                     ({"nx": -5}, -1)])
 def test_argument_errors(kw, code):
     L = ase.lib()
     order = kw.pop("order", 9)
@@ -116,3 +117,20 @@ def test_python_constants_match_header():
     p = WL.sod(20, 5).params
     p.fail_nonphysical = 1
     assert ase.c_params(p).flags & ase.FLAG_FAIL_NONPHYSICAL
+
+
+def test_empty_batches_are_rejected():
+    """A batch of no instances, an empty plan or a batch of no cells is an
+    argument error (host checks, nothing launched)."""
+    L = ase.lib()
+    nc = (C.c_int32 * 2)(5, 7)
+    start = (C.c_int32 * 3)()
+    lst = (C.c_int32 * 2)()
+    assert L.ase_batched_plan(0, nc, 2, start, lst) == -1
+    assert L.ase_batched_plan(2, nc, 0, start, lst) == -1
+    assert L.ase_batched_plan(2, nc, 2, start, lst) == 0
+    assert sorted(lst) == [0, 1] and start[2] == 2
+    P = C.byref(ase.c_params(WL.sod(20, 9).params))
+    rc = L.ase_step_batched(P, 1, None, 0, None, None, None, 5, 0, None, None, None, None, None, 1, 0.0, None,
+                            None, 1, 256, None, 0, None)
+    assert rc == -1 and len(L.ase_last_error()) > 0
