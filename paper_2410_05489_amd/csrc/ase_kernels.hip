@@ -211,15 +211,22 @@ __device__ __forceinline__ int map_face(int f, int n, int lo, int hi)
 }
 
 // Ghost cells and the strengths of the stored faces that are not flux faces,
-// in one pass.  init = 0: the ghost frame; each non-flux face takes its
+// in one launch.  init = 0: the ghost frame; each non-flux face takes its
 // periodic image or its mirror image at a wall if that is a flux face, else
-// the first-order strength of its two (boundary-mapped) cells.  init = 1: ghost frame plus first-order strengths of every stored
-// face.  Strengths are computed from the boundary-mapped values directly, so
-// they do not wait for the ghost writes.
+// the first-order strength of its two (boundary-mapped) cells.  init = 1:
+// ghost frame plus first-order strengths of every stored face.  The three
+// jobs of a cell -- its ghost value, the strength of its x-face, that of its
+// y-face -- are independent (strengths read boundary-mapped interior values,
+// never the ghosts being written, and non-flux faces only the flux faces).
+// For the frame they run in separate workgroups (blockIdx.y): the frame is
+// too small to fill the chip, and three short chains per cell finish sooner
+// than one.  The whole-grid pass (one workgroup row) keeps them together,
+// sharing the cell loads.
 template <int NV>
 __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, double *U, double *sx, double *sy,
                                                       int init)
 {
+    const int job = gridDim.y == 1 ? -1 : (int)blockIdx.y;   // -1: every job
     const long long n = init ? (long long)b.NY * b.NX : frame_size(b);
     for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * kThreads) {
@@ -233,14 +240,14 @@ __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, 
         const long long pos = (long long)J * b.ld + I;
         const int i = I - b.ng, j = J - b.ng;
         const bool ghost = i < 0 || i >= b.nx || (b.dim == 2 && (j < 0 || j >= b.ny));
-        if (ghost) {
+        if ((job < 0 || job == 0) && ghost) {
             double W[NV];
             cell_value<NV>(b, U, I, J, W);
 #pragma unroll
             for (int v = 0; v < NV; ++v) U[v * b.plane + pos] = W[v];
         }
         // x-face between (I,J) and (I+1,J)
-        if (I + 1 < b.NX) {
+        if ((job < 0 || job == 1) && I + 1 < b.NX) {
             const int f = i;
             const bool row_ok = b.dim == 1 || (j >= 0 && j < b.ny);
             const bool produced = row_ok && f >= -1 && f <= b.nx - 1;
@@ -258,7 +265,7 @@ __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, 
                 }
             }
         }
-        if (b.dim == 2 && J + 1 < b.NY) {
+        if ((job < 0 || job == 2) && b.dim == 2 && J + 1 < b.NY) {
             const int f = j;
             const bool produced = i >= 0 && i < b.nx && f >= -1 && f <= b.ny - 1;
             if (init) {
@@ -1685,9 +1692,9 @@ void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, 
     b.t = t;
     b.dt = dt;
     b.ct = ct;
-    const int nb = grid_blocks(frame_size(b));
-    if (geo.nv == 4) k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
-    else k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
+    const dim3 grid(grid_blocks(frame_size(b)), geo.dim == 2 ? 3 : 2);
+    if (geo.nv == 4) k_bc_fill<4><<<grid, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
+    else k_bc_fill<3><<<grid, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
 }
 
 void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
