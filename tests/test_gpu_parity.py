@@ -339,3 +339,25 @@ def test_graph_replays_match_eager():
         assert torch.equal(eager.sy[:g.NY - 1, :g.NX], graphed.sy[:g.NY - 1, :g.NX]), rep
         assert torch.equal(eager.t, graphed.t), rep
     del junk
+
+
+@pytest.mark.parametrize("t_end", [0.0, 0.004])
+def test_steps_in_one_call_equal_single_step_calls(t_end):
+    """n steps in one ase_step call (ping-pong strength planes, the device
+    dt and skip flag carried from step to step) equal n calls of one step
+    each: dt history and state bit for bit, also across t_end."""
+    w = WL.four_quadrant(70, 9, seed=11, ny=45)
+    g, p = w.grid, w.params
+    n = 8
+    a = ase.Simulation(g, p, w.U, device=DEV)
+    b = ase.Simulation(g, p, w.U, device=DEV)
+    ha = torch.zeros(n, dtype=torch.float64, device=DEV)
+    hb = torch.zeros(n, dtype=torch.float64, device=DEV)
+    a.run(n, t_end, dt_hist=ha)
+    for s in range(n):
+        b.run(1, t_end, dt_hist=hb[s:s + 1])
+    torch.cuda.synchronize()
+    assert torch.equal(ha, hb)
+    assert torch.equal(a.U, b.U) and torch.equal(a.t, b.t)
+    if t_end > 0.0:
+        assert float(a.t.cpu()[0]) == t_end and float(ha[-1].cpu()) == 0.0
