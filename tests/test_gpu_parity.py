@@ -159,13 +159,34 @@ def _recon_pair(w, d, nsteps=2):
     return (U, sx, sy), (wlo, wro, levo), (host(wlg), host(wrg), host(levg))
 
 
+def _flip_report(w, d, sx, sy, levg, levo, limit=5):
+    """Level flips between the two sides, each with how close its nested
+    strength sums A_5, A_7, A_9 come to the threshold, min |A - thr| / thr
+    (a flip at a relative distance near the rounding level is a tie; one far
+    from it is a mistake)."""
+    g, p = w.grid, w.params
+    levg = np.asarray(levg).reshape(g.ny, g.nx)
+    levo = np.asarray(levo).reshape(g.ny, g.nx)
+    s = np.asarray(sx if d == 0 else sy).reshape(g.NY, g.ld)
+    R = (p.order - 1) // 2
+    out = []
+    for j, i in np.argwhere(levg != levo)[:limit]:
+        J = 0 if g.dim == 1 else j + g.ng
+        I = i + g.ng
+        faces = [s[J, I + m] if d == 0 else s[J + m, I] for m in range(-R, R)]
+        sums = [sum(faces[R - h:R + h]) for h in (2, 3, 4) if h <= R]
+        rel = min((abs(a - p.sigma_thres) / p.sigma_thres for a in sums), default=float("nan"))
+        out.append(f"cell ({i},{j}): gpu {levg[j, i]} oracle {levo[j, i]}, min|A-thr|/thr {rel:.2e}")
+    return "; ".join(out)
+
+
 @pytest.mark.parametrize("name,order", CASES_2D + CASES_1D)
 def test_reconstruct(name, order):
     w = _case(name, order)
     dirs = (0, 1) if w.grid.dim == 2 else (0,)
     for d in dirs:
-        (U, _, _), (wlo, wro, levo), (wlg, wrg, levg) = _recon_pair(w, d)
-        assert np.array_equal(levg, levo), d
+        (U, sx, sy), (wlo, wro, levo), (wlg, wrg, levg) = _recon_pair(w, d)
+        assert np.array_equal(levg, levo), (d, _flip_report(w, d, sx, sy, levg, levo))
         nv = w.grid.nvar
         scale = np.abs(w.grid.interior(U)).reshape(nv, -1).max(axis=1)[:, None, None]
         assert np.max(np.abs(wlg - wlo) / scale) < 1e-12, d
