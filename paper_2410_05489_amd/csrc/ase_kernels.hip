@@ -210,50 +210,42 @@ __device__ __forceinline__ int map_face(int f, int n, int lo, int hi)
     return f;
 }
 
-// Ghost cells and the strengths of the stored faces that are not flux faces,
-// in one launch.  init = 0: the ghost frame; each non-flux face takes its
-// periodic image or its mirror image at a wall if that is a flux face, else
-// the first-order strength of its two (boundary-mapped) cells.  init = 1:
-// ghost frame plus first-order strengths of every stored face.  The three
-// jobs of a cell -- its ghost value, the strength of its x-face, that of its
-// y-face -- are independent (strengths read boundary-mapped interior values,
-// never the ghosts being written, and non-flux faces only the flux faces).
-// For the frame they run in separate workgroups (blockIdx.y): the frame is
-// too small to fill the chip, and three short chains per cell finish sooner
-// than one.  The whole-grid pass (one workgroup row) keeps them together,
-// sharing the cell loads.
+// The ghost frame: ghost cells and the strengths of the stored faces that
+// are not flux faces; each non-flux face takes its periodic image or its
+// mirror image at a wall if that is a flux face, else the first-order
+// strength of its two (boundary-mapped) cells.  The three jobs of a frame
+// cell -- its ghost value, the strength of its x-face, that of its y-face --
+// are independent (strengths read boundary-mapped interior values, never
+// the ghosts being written, and non-flux faces only the flux faces) and run
+// in separate workgroups (blockIdx.y): the frame is too small to fill the
+// chip, and three short chains per cell finish sooner than one.
+// ghosts_only: job 0 alone, one workgroup row (the first-order DF source:
+// k_sigma_fo then derives every strength from the filled state).
 template <int NV>
 __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, double *U, double *sx, double *sy,
-                                                      int init)
+                                                      int ghosts_only)
 {
-    const int job = gridDim.y == 1 ? -1 : (int)blockIdx.y;   // -1: every job
-    const long long n = init ? (long long)b.NY * b.NX : frame_size(b);
+    const int job = ghosts_only ? 0 : (int)blockIdx.y;
+    const long long n = frame_size(b);
     for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * kThreads) {
         int I, J;
-        if (init) {
-            J = (int)(idx / b.NX);
-            I = (int)(idx % b.NX);
-        } else {
-            frame_cell(b, idx, I, J);
-        }
+        frame_cell(b, idx, I, J);
         const long long pos = (long long)J * b.ld + I;
         const int i = I - b.ng, j = J - b.ng;
         const bool ghost = i < 0 || i >= b.nx || (b.dim == 2 && (j < 0 || j >= b.ny));
-        if ((job < 0 || job == 0) && ghost) {
+        if (job == 0 && ghost) {
             double W[NV];
             cell_value<NV>(b, U, I, J, W);
 #pragma unroll
             for (int v = 0; v < NV; ++v) U[v * b.plane + pos] = W[v];
         }
         // x-face between (I,J) and (I+1,J)
-        if ((job < 0 || job == 1) && I + 1 < b.NX) {
+        if (job == 1 && I + 1 < b.NX) {
             const int f = i;
             const bool row_ok = b.dim == 1 || (j >= 0 && j < b.ny);
             const bool produced = row_ok && f >= -1 && f <= b.nx - 1;
-            if (init) {
-                sx[pos] = sigma_first_order<NV>(b, U, I, J, I + 1, J, 0, mc);
-            } else if (!produced) {
+            if (!produced) {
                 const int fw = map_face(f, b.nx, b.bc[0], b.bc[1]);
                 const int jw = b.dim == 2 ? map_cell(j, b.ny, b.bc[2], b.bc[3]) : j;
                 const bool jw_ok = b.dim == 1 || (jw >= 0 && jw < b.ny);
@@ -265,12 +257,10 @@ __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, 
                 }
             }
         }
-        if ((job < 0 || job == 2) && b.dim == 2 && J + 1 < b.NY) {
+        if (job == 2 && b.dim == 2 && J + 1 < b.NY) {
             const int f = j;
             const bool produced = i >= 0 && i < b.nx && f >= -1 && f <= b.ny - 1;
-            if (init) {
-                sy[pos] = sigma_first_order<NV>(b, U, I, J, I, J + 1, 1, mc);
-            } else if (!produced) {
+            if (!produced) {
                 const int fw = map_face(f, b.ny, b.bc[2], b.bc[3]);
                 const int iw = map_cell(i, b.nx, b.bc[0], b.bc[1]);
                 if (iw >= 0 && iw < b.nx && fw >= -1 && fw <= b.ny - 1) {
@@ -281,6 +271,55 @@ __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, 
             }
         }
     }
+}
+
+// First-order strength of every stored face from the ghost-filled state
+// (what sigma_first_order gives from the boundary-mapped values, which the
+// ghost cells now hold): the primitive variables of each cell once, for a
+// tile of 32 x 8 stored cells plus the next column and row, in LDS; then
+// each cell's x-face and y-face with the next cell, argument order and
+// normal/tangential roles as in sigma_first_order.
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_sigma_fo(BCInfo b, MethodConst mc, const double *U, double *sx,
+                                                       double *sy)
+{
+    constexpr int TXs = 32, TYs = kThreads / TXs;
+    __shared__ double sp[TYs + 1][TXs + 1], su[TYs + 1][TXs + 1], sv[TYs + 1][TXs + 1], sic[TYs + 1][TXs + 1];
+    __shared__ bool sok[TYs + 1][TXs + 1];
+    const int NYs = b.dim == 1 ? 1 : b.NY;
+    const int I0 = blockIdx.x * TXs, J0 = blockIdx.y * TYs;
+    for (int it = threadIdx.x; it < (TYs + 1) * (TXs + 1); it += kThreads) {
+        const int lx = it % (TXs + 1), ly = it / (TXs + 1);
+        const int I = I0 + lx, J = J0 + ly;
+        if (I >= b.NX || J >= NYs) continue;
+        const long long pos = (long long)J * b.ld + I;
+        double W[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + pos];
+        const Prim q = primitives<NV>(W, 0, mc);
+        sp[ly][lx] = q.p;
+        su[ly][lx] = q.un;
+        sv[ly][lx] = q.ut;
+        sic[ly][lx] = q.ic;
+        sok[ly][lx] = q.ok;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % TXs, ly = threadIdx.x / TXs;
+    const int I = I0 + lx, J = J0 + ly;
+    if (I >= b.NX || J >= NYs) return;
+    const long long pos = (long long)J * b.ld + I;
+    auto prim = [&](int y, int x, bool xface) {
+        Prim q;
+        q.p = sp[y][x];
+        q.un = xface ? su[y][x] : sv[y][x];
+        q.ut = xface ? sv[y][x] : su[y][x];
+        q.ic = sic[y][x];
+        q.c = 0.0;
+        q.ok = sok[y][x];
+        return q;
+    };
+    if (I + 1 < b.NX) sx[pos] = sigma_point(prim(ly, lx, true), prim(ly, lx + 1, true));
+    if (b.dim == 2 && J + 1 < b.NY) sy[pos] = sigma_point(prim(ly, lx, false), prim(ly + 1, lx, false));
 }
 
 // ---------------------------------------------------------------------------
@@ -1704,9 +1743,16 @@ void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &m
     b.t = t;
     b.dt = dt;
     b.ct = ct;
-    const int nb = grid_blocks((long long)geo.NY * geo.NX);
-    if (geo.nv == 4) k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
-    else k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
+    // ghost frame, then every strength from the filled state
+    const int nb = grid_blocks(frame_size(b));
+    const dim3 tiles((geo.NX + 31) / 32, (geo.NY + kThreads / 32 - 1) / (kThreads / 32));
+    if (geo.nv == 4) {
+        k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
+        k_sigma_fo<4><<<tiles, kThreads, 0, st>>>(b, mc, U, sx, sy);
+    } else {
+        k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
+        k_sigma_fo<3><<<tiles, kThreads, 0, st>>>(b, mc, U, sx, sy);
+    }
 }
 
 void launch_nonphysical(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, const double *U, double *part,
