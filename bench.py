@@ -27,7 +27,7 @@ METRIC = "Mcell-updates/s, 9th-order 2D ASE step (FP64) + % HBM roofline; adjoin
 # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy (summary in
 # profiles/k_sweep2d_quad1024_r9.md).  Valid only for the kernel sources with
 # this fingerprint; once they change the bench reports traffic as null.
-MEASURED_TRAFFIC = {"fingerprint": "841af17a03c396ce", "sweep_x": 96694903, "sweep_y": 153972489}
+MEASURED_TRAFFIC = {"fingerprint": "e165722cfa1b0476", "sweep_x": 96689715, "sweep_y": 153959067}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
