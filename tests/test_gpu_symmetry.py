@@ -60,3 +60,25 @@ def test_mirror(axis):
     back = np.ascontiguousarray(np.flip(b, axis=axis))
     back[mom] = -back[mom]
     assert _close(back, a, g) < 1e-12
+
+
+def _run_gks(w, U, n, mu=0.0):
+    sim = ase.GksSimulation(w.grid, w.params, U, c1=0.05, c2=1.0, mu=mu, device=DEV)
+    sim.run(n)
+    torch.cuda.synchronize()
+    return sim.U.cpu().numpy(), float(sim.t.cpu()[0])
+
+
+@pytest.mark.parametrize("order,mu", [(9, 0.0), (5, 0.0), (5, 2e-3)])
+def test_gks_transpose(order, mu):
+    """The gas-kinetic x and y flux kernels (local frames rotated by 90
+    degrees) against each other, inviscid and viscous."""
+    w = WL.four_quadrant(48, order, states=WL.CONFIG3_STATES, split=(0.57, 0.44))
+    g = w.grid
+    assert g.ld == g.NX == g.NY
+    UT = np.ascontiguousarray(w.U.transpose(0, 2, 1)[[0, 2, 1, 3]])
+    a, ta = _run_gks(w, w.U, 2, mu)
+    b, tb = _run_gks(w, UT, 2, mu)
+    assert abs(ta - tb) <= 1e-14 * ta
+    back = np.ascontiguousarray(b.transpose(0, 2, 1)[[0, 2, 1, 3]])
+    assert _close(back, a, g) < 1e-12
