@@ -328,6 +328,29 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
                      double t_end, const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Allocation-free batched stepping --------------------------------------
+ * For callers that cannot allocate device memory or hand in a workspace:
+ * code under HIP graph capture, tight serving loops, hosts that forbid
+ * hipMalloc.  ase_step_batched_noalloc is ase_step_batched with the same
+ * arguments (minus ws, ws_bytes), the same kernels and the same results;
+ * its workspace is a fixed device array of ASE_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends (located
+ * on the first call on each device).  The call allocates and frees nothing.
+ * A batch whose workspace, ase_batched_workspace_bytes(total), exceeds
+ * ASE_NOALLOC_SCRATCH_BYTES (total > 1198368 stored cells) is refused with
+ * ASE_ERR_WORKSPACE before anything is launched.  All calls on one GPU share
+ * the array, which keeps the last call's contents (no call depends on
+ * them: every scratch word is written before it is read): calls that can
+ * overlap on the same GPU (other streams, other host threads) race, and
+ * the caller must serialise them. */
+#define ASE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+int ase_step_batched_noalloc(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                             const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng,
+                             int64_t total, double *U, double *sigma, double *t, double *dt_hist,
+                             const double *dt_replay, int32_t nsteps, double t_end, const int32_t *bin_start,
+                             const int32_t *bin_list, int32_t nbins, int32_t threads, void *stream);
+
 /* ---- Discrete adjoint of the 1D step ---------------------------------------
  * The paper defines the forward method only.  The adjoint here is the exact
  * transposed Jacobian of the discrete SSP-RK3 step (Sec. 2.1) with these

@@ -44,7 +44,7 @@ EXPORTS = ("ase_last_error", "ase_version", "ase_bc_fill", "ase_sigma_init", "as
            "ase_profile_enable", "ase_profile_read", "ase_batched_plan", "ase_batched_workspace_bytes",
            "ase_batched_sigma_init", "ase_step_batched", "ase_adjoint_workspace_bytes", "ase_adjoint_step",
            "ase_adjoint_batched_workspace_bytes", "ase_adjoint_batched", "ase_pressure_objective",
-           "ase_gks_flux", "ase_gks_workspace_bytes", "ase_step_gks")
+           "ase_gks_flux", "ase_gks_workspace_bytes", "ase_step_gks", "ase_step_batched_noalloc")
 
 KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4, "batched": 5, "adjoint": 6,
           "gks_1d": 7, "gks_2d_recon": 8, "gks_2d_flux": 9, "gks_2d_update": 10}
@@ -90,6 +90,8 @@ def lib():
     L.ase_batched_sigma_init.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, C.c_int32, C.c_int64, vp, vp, vp]
     L.ase_step_batched.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp,
                                    vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+    L.ase_step_batched_noalloc.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp,
+                                           vp, vp, vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp]
     L.ase_adjoint_workspace_bytes.restype = C.c_size_t
     L.ase_adjoint_workspace_bytes.argtypes = [vp]
     L.ase_adjoint_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, vp, C.c_size_t, vp]
@@ -389,8 +391,18 @@ class BatchedSimulation:
                                             _p(self.offsets), _p(self.ncells), b.ng, b.total, _p(self.U),
                                             _p(self.sig), _stream(stream)), "ase_batched_sigma_init")
 
-    def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None, dt_replay=None):
+    def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None, dt_replay=None, noalloc=False):
+        """nsteps steps of every instance in one persistent launch; noalloc
+        takes the allocation-free entry point (the library's fixed scratch
+        instead of this object's workspace)."""
         b = self.b
+        if noalloc:
+            _check(lib().ase_step_batched_noalloc(
+                C.byref(c_params(self.p)), b.bc, _p(self.bc_inst), b.ninst, _p(self.offsets), _p(self.ncells),
+                _p(self.dx), b.ng, b.total, _p(self.U), _p(self.sig), _p(self.t), _p(dt_hist), _p(dt_replay),
+                int(nsteps), float(t_end), _p(self.bin_start), _p(self.bin_list), self.nbins, self.threads,
+                _stream(stream)), "ase_step_batched_noalloc")
+            return
         _check(lib().ase_step_batched(C.byref(c_params(self.p)), b.bc, _p(self.bc_inst), b.ninst, _p(self.offsets),
                                       _p(self.ncells),
                                       _p(self.dx), b.ng, b.total, _p(self.U), _p(self.sig), _p(self.t),

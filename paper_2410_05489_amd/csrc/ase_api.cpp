@@ -841,6 +841,27 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
     return check_launch("ase_step_batched");
 }
 
+int ase_step_batched_noalloc(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                             const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng,
+                             int64_t total, double *U, double *sigma, double *t, double *dt_hist,
+                             const double *dt_replay, int32_t nsteps, double t_end, const int32_t *bin_start,
+                             const int32_t *bin_list, int32_t nbins, int32_t threads, void *stream)
+{
+    int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
+    if (rc) return rc;
+    const size_t need = ase_batched_workspace_bytes(total);
+    if (need > ASE_NOALLOC_SCRATCH_BYTES)
+        return fail(ASE_ERR_WORKSPACE, "batch too large for the fixed scratch: ase_batched_workspace_bytes(total) = " +
+                                           std::to_string(need) + " > ASE_NOALLOC_SCRATCH_BYTES = " +
+                                           std::to_string((size_t)ASE_NOALLOC_SCRATCH_BYTES));
+    void *scr = nullptr;
+    rc = noalloc_scratch(&scr);
+    if (rc) return rc;
+    return ase_step_batched(p, bc, bc_inst, ninst, offsets, ncells, dx, ng, total, U, sigma, t, dt_hist, dt_replay,
+                            nsteps, t_end, bin_start, bin_list, nbins, threads, scr, ASE_NOALLOC_SCRATCH_BYTES,
+                            stream);
+}
+
 // ---- adjoint ----------------------------------------------------------------
 
 static size_t adjoint_bytes(long long total, int nsteps)

@@ -98,6 +98,8 @@ struct BatchLaunch {
     MethodConst mc;
 };
 void launch_batched(const BatchLaunch &bl, hipStream_t st);
+// Address of this device's fixed scratch array (ASE_NOALLOC_SCRATCH_BYTES).
+int noalloc_scratch(void **ptr);
 
 struct AdjLaunch {
     const long long *offsets;   // nullptr: single instance (n1, dx1) at offset 0

@@ -8,6 +8,9 @@
 // LDS, and evaluate Gauss points, strengths and fluxes from there.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <mutex>
+
 #include "ase_device.h"
 #include "ase_host.h"
 
@@ -1066,7 +1069,9 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
                 for (int r = s; r < a.nsteps; ++r) a.dt_hist[(long long)r * a.ninst + k] = 0.0;
         }
         if (sA != a.sig + off) {
-            for (int I = threadIdx.x; I < N + 2 * a.ng; I += NT) a.sig[off + I] = sA[I];
+            // the N + 2 ng - 1 stored faces; the last stored cell has no face
+            // on its right, so its entry is neither written nor copied
+            for (int I = threadIdx.x; I + 1 < N + 2 * a.ng; I += NT) a.sig[off + I] = sA[I];
         }
         __syncthreads();
     }
@@ -1945,6 +1950,40 @@ void launch_objective(const ObjLaunch &ol, hipStream_t st)
     a.offsets = ol.offsets; a.ncells = ol.ncells; a.dx = ol.dx; a.n1 = ol.n1; a.dx1 = ol.dx1;
     a.U = ol.U; a.w = ol.w; a.J = ol.J; a.lam = ol.lam; a.total = ol.total; a.ng = ol.ng; a.gm1 = ol.gm1;
     k_pressure_objective<256><<<ol.ninst, 256, 0, st>>>(a);
+}
+
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free batched entry point: the two
+// stage states and the second strength array of k_batched1d live in this
+// module-scope array instead of a caller workspace.  Every GPU the library
+// runs on holds its own copy until the process ends.  Host code takes the
+// address hipGetSymbolAddress returns on the current device (kept per
+// device after the first call) and never the array's name, which on the
+// host is only a stand-in for the symbol.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[ASE_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+
+int noalloc_scratch(void **ptr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(ASE_ERR_ARG, "device index beyond the scratch table");
+    static std::mutex mu;
+    static void *addr[kMaxScratchDevices];
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if ((reinterpret_cast<uintptr_t>(p) & 255u) != 0) return fail(ASE_ERR_ALIGN, "scratch not 256-byte aligned");
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return ASE_OK;
 }
 
 }  // namespace ase
