@@ -40,7 +40,7 @@ def kernel_fingerprint() -> str:
     return h.hexdigest()[:16]
 
 
-def alg_flops_per_cell_sweep(order: int, dim: int) -> float:
+def alg_flops_per_cell_sweep(order: int, dim: int, lagged: bool = False) -> float:
     """Algorithmic FP64 operations per interior cell for one direction of one
     stage on the top linear branch (every operation of the method counted once;
     an FMA counts 2, a divide or square root 1).
@@ -48,10 +48,13 @@ def alg_flops_per_cell_sweep(order: int, dim: int) -> float:
     2D, r = 2R+1, G = R Gauss points:
       normal reconstruction   : DF sums (r-2 + ... adds) + 2 points x 4 vars x (2r-1)
       tangential (two sides)  : 2 x (DF sums + G points x 4 vars x (2r-1))
-      per Gauss point         : primitives 2 x 12, strength 14, LF flux 33,
-                                quadrature 8, strength sum 1   -> 80
-      face strength mean      : 1
+      per Gauss point         : primitives 2 x 12, LF flux 33, quadrature 8 -> 65;
+                                lagged DF source: + strength 14 and its sum 1
+      face strength mean      : 1 (lagged DF source)
       flux difference         : 4 vars x 2
+    With the first-order DF source the strengths are the cell-average ones,
+    formed outside the sweeps (per cell one set of primitives and the
+    strengths of its two faces).
     """
     R = (order - 1) // 2
     sums = {1: 1, 2: 3, 3: 8, 4: 15}[R]
@@ -62,16 +65,38 @@ def alg_flops_per_cell_sweep(order: int, dim: int) -> float:
     G = R
     normal = sums + 2 * 4 * (2 * order - 1)
     tang = 2 * (sums + G * 4 * (2 * order - 1))
-    return normal + tang + G * 80 + 1 + 8
+    return normal + tang + G * (80 if lagged else 65) + (1 if lagged else 0) + 8
 
 
-def alg_bytes_per_cell(kernel: str) -> float:
+def alg_bytes_per_cell(kernel: str, lagged: bool = False) -> float:
     """Algorithmic HBM bytes per interior cell of one launch (FP64 words):
     x sweep reads the stage state (4) and both strength planes (2), writes the
-    new x strengths (1) and the x residual (4); y sweep reads the stage state
-    (4), both strength planes (2), the x residual (4) and the step-start state
-    (4, stages 2-3), writes the stage output (4) and the new y strengths (1)."""
-    return {"sweep_x": 11 * 8.0, "sweep_y": (19 * 8.0 * 2 + 15 * 8.0) / 3.0}[kernel]
+    x residual (4); y sweep reads the stage state (4), both strength planes
+    (2), the x residual (4) and the step-start state (4, stages 2-3), writes
+    the stage output (4).  Lagged DF source: each sweep also writes its new
+    strengths (1)."""
+    w = 1 if lagged else 0
+    return {"sweep_x": (10 + w) * 8.0, "sweep_y": ((18 + w) * 8.0 * 2 + (14 + w) * 8.0) / 3.0}[kernel]
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads the oracle may use: OMP_NUM_THREADS when set, else the CPUs
+    this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
 
 
 def make_workload(name):
@@ -341,7 +366,16 @@ def measure_adjoint(nsteps=100, every=10, reps=3):
     from paper_2410_05489_amd import ase, autotune
     from paper_2410_05489_amd import workloads as WL
 
-    b = WL.batched_riemann(nsteps=nsteps)
+    b_all = WL.batched_riemann(nsteps=nsteps)
+    # instances the method loses (status != 0 after nsteps) are left out of
+    # the timing: NaN arithmetic is no work of the method
+    probe = ase.BatchedSimulation(b_all, "cuda", nbins=min(b_all.ninst, 256))
+    st = torch.zeros(b_all.ninst, dtype=torch.int32, device="cuda")
+    probe.run(nsteps, status=st)
+    torch.cuda.synchronize()
+    keep = np.flatnonzero(st.cpu().numpy() == 0)
+    del probe
+    b = WL.batch_subset(b_all, keep)
     fwd = autotune.tune_batched(b, nsteps=10, use_cache=False)
     adj = autotune.tune_adjoint(b, every=every, use_cache=False, fwd_shape=(fwd["nbins"], fwd["threads"]))
     run = A.BatchedAdjoint(b, "cuda", nbins=fwd["nbins"], threads=fwd["threads"], adj_threads=adj["threads"],
@@ -382,7 +416,9 @@ def measure_adjoint(nsteps=100, every=10, reps=3):
         ok += int(bool(np.isfinite(Jh[k])) and bool(np.isfinite(gh[:, o:o + n + 2 * b.ng]).all()))
     med = lambda a: sorted(a)[len(a) // 2]   # noqa: E731
     tp, tf, tb = med(t_plain), med(t_fwd), med(t_bwd)
-    return {"workload": f"batched_riemann_{b.ninst}x64..4096_r9_seed0", "steps": nsteps, "checkpoint_every": every,
+    return {"workload": f"batched_riemann_{b_all.ninst}x64..4096_r9_seed0", "instances_timed": b.ninst,
+            "instances_lost": [int(k) for k in np.flatnonzero(st.cpu().numpy() != 0)],
+            "steps": nsteps, "checkpoint_every": every,
             "cells": int(b.ncells.sum()), "forward_ms": round(tp, 3), "forward_with_checkpoints_ms": round(tf, 3),
             "backward_ms": round(tb, 3), "adjoint_fwd_ratio": round(tb / tp, 3),
             "adjoint_kernel_ms_per_segment": round(kms / max(kn, 1), 3),
@@ -390,19 +426,28 @@ def measure_adjoint(nsteps=100, every=10, reps=3):
             "instances_finite": ok, "adjoint_trials": adj["trials"]}
 
 
-def cpu_baseline(w, seconds_hint=True):
-    """The oracle (single thread, as written) on three steps of the same grid."""
+def cpu_baseline(w):
+    """The oracle as it stands (OpenMP over grid lines) on the host's
+    threads: three steps of the same grid from its initial state; and one
+    step on a single thread."""
     from oracle import oracle as O
-    U = w.U.copy()
-    sx, sy = O.sigma_init(w.grid, w.params, U)
-    k = 3
-    t0 = time.perf_counter()
-    O.step(w.grid, w.params, U, sx, sy, 0.0, k)
-    el = time.perf_counter() - t0
     n = w.grid.ncells()
-    return {"value": n * k / el / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} steps of {w.name} ({n} cells) from its initial state, single-threaded C oracle, "
-                      f"{el:.1f} s"}
+    nt = host_threads()
+    rates = {}
+    for threads, k in ((nt, 3), (1, 1)):
+        used = O.set_threads(threads)
+        U = w.U.copy()
+        sx, sy = O.sigma_init(w.grid, w.params, U)
+        t0 = time.perf_counter()
+        O.step(w.grid, w.params, U, sx, sy, 0.0, k)
+        el = time.perf_counter() - t0
+        rates[threads] = (n * k / el / 1e6, used, k, el)
+    v, used, k, el = rates[nt]
+    v1, _, k1, el1 = rates[1]
+    return {"value": v, "unit": "Mcell-updates/s", "cores": used, "kind": "oracle",
+            "sample": f"{k} steps of {w.name} ({n} cells) from its initial state, C oracle on {used} threads, "
+                      f"{el:.1f} s; 1 step on 1 thread, {el1:.1f} s",
+            "single_thread": v1, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -480,11 +525,17 @@ def main():
     dom = max(("sweep_x", "sweep_y"), key=lambda k: kern[k][0])
     tot, nl = kern[dom]
     avg_s = tot / max(nl, 1) / 1e3
-    flops = alg_flops_per_cell_sweep(p.order, g.dim) + (4 + 56.0 / 3.0 if dom == "sweep_y" else 0.0)
+    lagged = p.df_source == 0
+    flops = alg_flops_per_cell_sweep(p.order, g.dim, lagged) + (4 + 56.0 / 3.0 if dom == "sweep_y" else 0.0)
     achieved_tf = flops * ncell / avg_s / 1e12
-    bytes_launch = alg_bytes_per_cell(dom) * ncell
+    bytes_launch = alg_bytes_per_cell(dom, lagged) * ncell
+    # minimal HBM traffic of a step: read U^n (3 stages), U^(s-1) (stages 2,
+    # 3), write U^(s) (3 stages) = 8 nvar words per cell-update; the lagged
+    # DF source adds a read and a write of each face strength per stage
+    step_bytes = 8 * 4 * 8 + (12 * 8 if lagged else 0)
     traffic = None
-    if args.workload == "quad1024" and kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]:
+    if args.workload in MEASURED_TRAFFIC.get("workloads", ("quad1024",)) and \
+            kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]:
         traffic = MEASURED_TRAFFIC[dom]
     roof = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved_tf / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
@@ -492,15 +543,17 @@ def main():
             "avg_launch_ms": round(avg_s * 1e3, 4), "launches": nl,
             "alg_flops_per_launch": flops * ncell, "alg_bytes_per_launch": bytes_launch,
             "hbm_frac_alg": round(bytes_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4),
-            "step_alg_bytes_per_cell": 352,
-            "step_hbm_frac_alg": round(value * 1e6 * 352 / 1e9 / HBM_PEAK_GBS, 4),
+            "step_alg_bytes_per_cell": step_bytes,
+            "step_hbm_frac_alg": round(value * 1e6 * step_bytes / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_ms_per_step": {k: round(v[0] / prof_steps, 4) for k, v in kern.items() if v[1]},
             "profiled_steps": prof_steps}
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Mcell-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic", "config": {"workload": w.name, "order": p.order, "nx": g.nx, "ny": g.ny,
-                                           "gamma": p.gamma, "cfl": p.cfl, "sigma_thres": p.sigma_thres},
+                                           "gamma": p.gamma, "cfl": p.cfl, "sigma_thres": p.sigma_thres,
+                                           "df_source": "lagged" if lagged else "first_order",
+                                           "positivity_fallback": bool(p.positivity_fallback)},
            "finite": finite, "roofline": roof}
     if not args.no_adjoint:
         out["adjoint"] = measure_adjoint()

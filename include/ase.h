@@ -314,19 +314,28 @@ int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, const int32_t *bc_
 /* nsteps SSP-RK3 steps of every instance in ONE persistent launch: nbins
  * workgroups of `threads` (256, 512 or 1024) lanes, each walking the instances of
  * its bin through all steps (ghost cells, DF state, per-instance dt and
- * boundary code, three stages of the 1D method of ase_step) without
- * returning to the host.
+ * boundary code, three stages of the 1D method of ase_step, Sec. 2.1-3.4)
+ * without returning to the host.
  * Results equal ase_step on each instance alone.  t: device [ninst], in/out.
  * dt_hist: optional device [nsteps][ninst].  dt_replay: optional device
  * [nsteps][ninst] of time steps to take instead of the CFL rule (an entry
  * <= 0 stops that instance; dt_cap and the clipping at t_end are then not
  * applied) -- for replaying a recorded run.  t_end > 0 stops each instance at t_end.
+ * status: optional device int32 [ninst], out.  When given, an instance whose
+ * CFL time step is not a positive number at the start of step s (some cell
+ * has rho <= 0, p <= 0 or a NaN: the method has lost the state) stops there
+ * and gets status s+1; the others get 0.  A stopped instance keeps the
+ * state and time it had (dt_hist 0 from step s on).  Without status such an
+ * instance runs on with NaN values, as ase_step does.
+ * With ASE_FLAG_DF_FIRST_ORDER the strengths handed back in sigma are the
+ * first-order ones of each final state (ase_step likewise).
  * bin_start/bin_list: device copies of an ase_batched_plan. */
 int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
                      const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
-                     double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay, int32_t nsteps,
-                     double t_end, const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
-                     void *ws, size_t ws_bytes, void *stream);
+                     double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay,
+                     int32_t *status, int32_t nsteps, double t_end, const int32_t *bin_start,
+                     const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
+                     void *stream);
 
 /* ---- Allocation-free batched stepping --------------------------------------
  * For callers that cannot allocate device memory or hand in a workspace:
@@ -348,8 +357,9 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
 int ase_step_batched_noalloc(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
                              const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng,
                              int64_t total, double *U, double *sigma, double *t, double *dt_hist,
-                             const double *dt_replay, int32_t nsteps, double t_end, const int32_t *bin_start,
-                             const int32_t *bin_list, int32_t nbins, int32_t threads, void *stream);
+                             const double *dt_replay, int32_t *status, int32_t nsteps, double t_end,
+                             const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                             void *stream);
 
 /* ---- Discrete adjoint of the 1D step ---------------------------------------
  * The paper defines the forward method only.  The adjoint here is the exact

@@ -17,7 +17,14 @@
  * paper is garbled or silent, the reading taken is stated at the spot
  * (readings R1..R16 are listed in the design notes of the repository).
  *
- * Build: gcc -O2 -fno-fast-math -ffp-contract=off -shared -fPIC -lm
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC -lm
+ *
+ * Threads: the loops over grid lines (rows or columns) of the sweeps, the
+ * residual, the first-order strengths and the stage combination run under
+ * OpenMP.  Every iteration writes its own cells and faces and no parallel
+ * loop reduces, so results are bitwise the same for any thread count
+ * (orc_set_threads); the time-step maximum stays a serial loop.  Grids of
+ * at most 4096 cells run every loop serially.
  *
  * Array layout (shared with callers, not with any GPU source):
  *   U[v*NY*ld + J*ld + I], I in [0,NX), J in [0,NY), NX = nx+2ng,
@@ -32,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Problem statement                                                          */
@@ -565,11 +575,13 @@ static double sigma_first_order(const orc_grid *g, const orc_params *p, const do
 static void sigma_all_first_order(const orc_grid *g, const orc_params *p, const double *U, double *sx, double *sy)
 {
     int NX = NXof(g), NY = NYof(g);
+#pragma omp parallel for schedule(static) if ((long)NY * NX > 4096)
     for (int J = 0; J < NY; ++J)
         for (int I = 0; I + 1 < NX; ++I)
             sx[(size_t)J * g->ld + I] = sigma_first_order(g, p, U, I, J, I + 1, J, 0);
     if (g->dim == 2)
-        for (int J = 0; J + 1 < NY; ++J)
+#pragma omp parallel for schedule(static) if ((long)NY * NX > 4096)
+        for (int J = 0; J < NY - 1; ++J)
             for (int I = 0; I < NX; ++I)
                 sy[(size_t)J * g->ld + I] = sigma_first_order(g, p, U, I, J, I, J + 1, 1);
 }
@@ -728,6 +740,7 @@ static int sweep(const orc_grid *g, const orc_params *p, int dir, const double *
     ptrdiff_t s_across = dir == 0 ? ld : 1;
 
     /* 1. normal reconstruction */
+#pragma omp parallel for schedule(static) if ((long)n_across * n_along > 4096)
     for (int c = -Rt; c < n_across + Rt; ++c) {
         for (int a = -1; a <= n_along; ++a) {
             size_t base = CELL(a, c);
@@ -746,6 +759,7 @@ static int sweep(const orc_grid *g, const orc_params *p, int dir, const double *
     }
 
     /* 2.-3. tangential reconstruction and fluxes */
+#pragma omp parallel for schedule(static) if ((long)n_across * n_along > 4096)
     for (int c = 0; c < n_across; ++c) {
         for (int a = -1; a < n_along; ++a) {          /* face a + 1/2 */
             double WL[4][4], WR[4][4];                  /* [gauss][var] */
@@ -817,6 +831,7 @@ static int residual(const orc_grid *g, const orc_params *p, const double *U, con
         if (sweep(g, p, 1, U, sx, sy, NULL, NULL, Fy, sy_new, NULL)) { free(Fx); free(Fy); return -1; }
     }
     int nyl = g->dim == 1 ? 1 : g->ny;
+#pragma omp parallel for schedule(static) if ((long)nyl * g->nx > 4096)
     for (int j = 0; j < nyl; ++j) {
         for (int i = 0; i < g->nx; ++i) {
             size_t c = (size_t)(g->dim == 1 ? 0 : j + ng) * g->ld + (size_t)(i + ng);
@@ -893,6 +908,7 @@ static void stage_combine(const orc_grid *g, int stage, double dt, const double 
     int nv = nvar_of(g), ng = g->ng;
     size_t P = plane(g);
     int nyl = g->dim == 1 ? 1 : g->ny;
+#pragma omp parallel for collapse(2) schedule(static) if ((long)nyl * g->nx > 4096)
     for (int v = 0; v < nv; ++v)
         for (int j = 0; j < nyl; ++j)
             for (int i = 0; i < g->nx; ++i) {
@@ -1135,6 +1151,9 @@ int orc_step(const orc_grid *g, const orc_params *p, double *U, double *sx, doub
         if (dt_hist) dt_hist[s] = dt;
         ++taken;
     }
+    /* First-order source: the strengths handed back are those the next     */
+    /* stage would read, the first-order strengths of the final state.       */
+    if (p->df_source == ORC_DF_FIRST_ORDER && nsteps > 0) stage_bc(g, p, U, sx, sy, *t);
     free(U1); free(U2); free(L); free(sxa); free(sya);
     return taken;
 fail:
@@ -1175,6 +1194,19 @@ double orc_beta3(const double *a) { return beta3(a); }
 double orc_zk(int k, double xi) { return Zk(k, xi); }
 double orc_alpha(double A, double thres) { return df_alpha(A, thres); }
 void orc_gauss(int G, double *node, double *eta) { gauss_legendre(G, node, eta); }
+
+/* Threads of the parallel loops (n >= 1); returns the count now in effect
+   (1 when built without OpenMP). */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* Discontinuity strength and LF flux of one Gauss point (dir 0 / 1). */
 double orc_sigma_point(const orc_grid *g, const orc_params *p, const double *Wl, const double *Wr, int dir)

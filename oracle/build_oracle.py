@@ -9,7 +9,7 @@ def build() -> str:
     src = os.path.join(HERE, "ase_oracle.c")
     out = os.path.join(HERE, "liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11", "-Wall", "-shared", "-fPIC",
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11", "-Wall", "-fopenmp", "-shared", "-fPIC",
            "-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)

@@ -66,6 +66,8 @@ def lib():
         L.orc_alpha.restype = C.c_double
         L.orc_gauss.argtypes = [C.c_int, _dp, _dp]
         L.orc_gauss.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
         L.orc_sigma_point.argtypes = [vp, vp, _dp, _dp, C.c_int]
         L.orc_sigma_point.restype = C.c_double
         L.orc_lf_point.argtypes = [vp, vp, _dp, _dp, C.c_int, _dp]
@@ -259,6 +261,11 @@ def zk(k, xi):
 
 def alpha(A, thres):
     return lib().orc_alpha(A, thres)
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops; returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def gauss(G):

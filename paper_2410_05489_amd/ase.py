@@ -89,9 +89,9 @@ def lib():
     L.ase_batched_workspace_bytes.argtypes = [C.c_int64]
     L.ase_batched_sigma_init.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, C.c_int32, C.c_int64, vp, vp, vp]
     L.ase_step_batched.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp,
-                                   vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+                                   vp, vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_step_batched_noalloc.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp,
-                                           vp, vp, vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp]
+                                           vp, vp, vp, vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp]
     L.ase_adjoint_workspace_bytes.restype = C.c_size_t
     L.ase_adjoint_workspace_bytes.argtypes = [vp]
     L.ase_adjoint_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, vp, C.c_size_t, vp]
@@ -391,22 +391,25 @@ class BatchedSimulation:
                                             _p(self.offsets), _p(self.ncells), b.ng, b.total, _p(self.U),
                                             _p(self.sig), _stream(stream)), "ase_batched_sigma_init")
 
-    def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None, dt_replay=None, noalloc=False):
+    def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None, dt_replay=None, noalloc=False,
+            status=None):
         """nsteps steps of every instance in one persistent launch; noalloc
         takes the allocation-free entry point (the library's fixed scratch
-        instead of this object's workspace)."""
+        instead of this object's workspace); status (int32 [ninst] on the
+        device) stops and flags instances whose state turns non-physical."""
         b = self.b
         if noalloc:
             _check(lib().ase_step_batched_noalloc(
                 C.byref(c_params(self.p)), b.bc, _p(self.bc_inst), b.ninst, _p(self.offsets), _p(self.ncells),
                 _p(self.dx), b.ng, b.total, _p(self.U), _p(self.sig), _p(self.t), _p(dt_hist), _p(dt_replay),
-                int(nsteps), float(t_end), _p(self.bin_start), _p(self.bin_list), self.nbins, self.threads,
-                _stream(stream)), "ase_step_batched_noalloc")
+                _p(status), int(nsteps), float(t_end), _p(self.bin_start), _p(self.bin_list), self.nbins,
+                self.threads, _stream(stream)), "ase_step_batched_noalloc")
             return
         _check(lib().ase_step_batched(C.byref(c_params(self.p)), b.bc, _p(self.bc_inst), b.ninst, _p(self.offsets),
                                       _p(self.ncells),
                                       _p(self.dx), b.ng, b.total, _p(self.U), _p(self.sig), _p(self.t),
-                                      _p(dt_hist), _p(dt_replay), int(nsteps), float(t_end), _p(self.bin_start),
+                                      _p(dt_hist), _p(dt_replay), _p(status), int(nsteps), float(t_end),
+                                      _p(self.bin_start),
                                       _p(self.bin_list), self.nbins, self.threads, self.ws.ptr, self.ws.nbytes,
                                       _stream(stream)), "ase_step_batched")
 

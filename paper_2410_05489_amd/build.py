@@ -1,4 +1,5 @@
 """Build libase.so (HIP, gfx950) in-tree with hipcc."""
+import hashlib
 import os
 import shutil
 import subprocess
@@ -20,7 +21,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _source_digest() -> str:
+    """Digest of every source and header the library is built from."""
+    h = hashlib.sha256()
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC))
+    files.append(os.path.join(HERE, "..", "include", "ase.h"))
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
+    # The translation units share structure layouts (ase_host.h): objects
+    # compiled from different versions of the sources would disagree on them
+    # and hand the kernels wrong pointers.  A build during which any source
+    # changed is refused.
+    digest = _source_digest()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
@@ -34,6 +52,9 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     tmp = LIB + ".tmp"
     subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], check=True)
+    if _source_digest() != digest:
+        os.remove(tmp)
+        raise RuntimeError("sources changed during the build: libase.so not replaced; build again")
     os.replace(tmp, LIB)
     return LIB
 

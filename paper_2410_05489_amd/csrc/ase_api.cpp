@@ -219,7 +219,7 @@ extern "C" {
 
 const char *ase_last_error(void) { return g_err.c_str(); }
 
-int ase_version(void) { return 3; }
+int ase_version(void) { return 4; }
 
 int ase_bc_fill(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, double *sy, void *stream)
 {
@@ -457,7 +457,14 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
         }
         cur ^= 1;
     }
-    if (cur == 1) {
+    if (fo) {
+        // first-order source: hand back the strengths of the final state
+        // (the sweeps write none in this mode)
+        if (nsteps > 0) {
+            ProfScope ps(ASE_KCLASS_BC, st);
+            stage_bc(U, sx, geo.dim == 2 ? sy : sx, 0.0);
+        }
+    } else if (cur == 1) {
         hipError_t e = hipMemcpyAsync(sx, w.sxa, (size_t)geo.plane * sizeof(double), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(sx)");
         if (geo.dim == 2) {
@@ -784,9 +791,10 @@ int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, const int32_t *bc_
 
 int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
                      const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
-                     double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay, int32_t nsteps,
-                     double t_end, const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
-                     void *ws, size_t ws_bytes, void *stream)
+                     double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay,
+                     int32_t *status, int32_t nsteps, double t_end, const int32_t *bin_start,
+                     const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
+                     void *stream)
 {
     int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
     if (rc) return rc;
@@ -798,6 +806,7 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
     ASE_PTR(t, "t");
     if (dt_hist && misaligned(dt_hist)) return fail(ASE_ERR_ALIGN, "misaligned: dt_hist");
     if (dt_replay && misaligned(dt_replay)) return fail(ASE_ERR_ALIGN, "misaligned: dt_replay");
+    if (status && (reinterpret_cast<uintptr_t>(status) & 3u) != 0) return fail(ASE_ERR_ALIGN, "misaligned: status");
     if (!bin_start || !bin_list) return fail(ASE_ERR_ARG, "null bin arrays");
     if (!ws) return fail(ASE_ERR_WORKSPACE, "workspace is required");
     if (ws_bytes < ase_batched_workspace_bytes(total)) return fail(ASE_ERR_WORKSPACE, "workspace too small");
@@ -815,6 +824,7 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
     bl.t = t;
     bl.dt_hist = dt_hist;
     bl.dt_in = dt_replay;
+    bl.status = status;
     bl.U1 = reinterpret_cast<double *>(c);
     bl.U2 = reinterpret_cast<double *>(c + 3 * arr);
     bl.sig2 = reinterpret_cast<double *>(c + 6 * arr);
@@ -844,8 +854,9 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
 int ase_step_batched_noalloc(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
                              const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng,
                              int64_t total, double *U, double *sigma, double *t, double *dt_hist,
-                             const double *dt_replay, int32_t nsteps, double t_end, const int32_t *bin_start,
-                             const int32_t *bin_list, int32_t nbins, int32_t threads, void *stream)
+                             const double *dt_replay, int32_t *status, int32_t nsteps, double t_end,
+                             const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                             void *stream)
 {
     int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
     if (rc) return rc;
@@ -858,8 +869,8 @@ int ase_step_batched_noalloc(const ase_params_t *p, int32_t bc, const int32_t *b
     rc = noalloc_scratch(&scr);
     if (rc) return rc;
     return ase_step_batched(p, bc, bc_inst, ninst, offsets, ncells, dx, ng, total, U, sigma, t, dt_hist, dt_replay,
-                            nsteps, t_end, bin_start, bin_list, nbins, threads, scr, ASE_NOALLOC_SCRATCH_BYTES,
-                            stream);
+                            status, nsteps, t_end, bin_start, bin_list, nbins, threads, scr,
+                            ASE_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 // ---- adjoint ----------------------------------------------------------------

@@ -518,13 +518,16 @@ __device__ __forceinline__ double gauss_point(double (&Wl)[NV], double (&Wr)[NV]
 // the own side is the left (lower) one and -1 otherwise.  Equal to
 // gauss_point with (Wl, Wr) = (Wo, Wt) or (Wt, Wo): the flux average, the
 // signal speed and the strength are symmetric in the two states.
+// With want_sigma false (first-order DF source: the strengths come from the
+// cell averages) the Gauss-point strength is not evaluated and 0 returned.
 template <int NV, class CO, class CT>
 __device__ __forceinline__ double gauss_point_sided(double (&Wo)[NV], double (&Wt)[NV], double sgn, CO co, CT ct,
-                                                    int dir, const MethodConst &mc, double (&F)[NV])
+                                                    int dir, const MethodConst &mc, double (&F)[NV],
+                                                    bool want_sigma = true)
 {
     Prim qo = primitives<NV>(Wo, dir, mc);
     Prim qt = primitives<NV>(Wt, dir, mc);
-    const double sg = sigma_point(qo, qt);
+    const double sg = want_sigma ? sigma_point(qo, qt) : 0.0;
     if (mc.flags & 1) {
         if (!qo.ok) {
 #pragma unroll

@@ -90,6 +90,7 @@ struct BatchLaunch {
     const double *dx;
     double *U, *sig, *t, *dt_hist, *U1, *U2, *sig2;
     const double *dt_in;
+    int *status;
     const int *bin_start, *bin_list;
     const int *bc_inst;
     long long total;

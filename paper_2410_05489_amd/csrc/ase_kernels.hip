@@ -507,7 +507,11 @@ __global__ void __launch_bounds__(NT, 6) k_sweep2d(SweepArgs a)
     const int oy = (DIR == 0) ? j0 - R : j0 - 1 - R;
     const MethodConst &mc = a.mc;
 
+    // first-order DF source: the stage's strengths come from its cell
+    // averages (boundary step), so the sweep evaluates and writes none
+    const bool want_sigma = (a.mc.flags & ASE_FLAG_DF_FIRST_ORDER) == 0;
     if (MODE != MODE_RECON && a.skip != nullptr && *a.skip != 0.0) {
+        if (!want_sigma) return;
         // finished run: carry the strengths of the owned flux faces over
         const double *sin = DIR == 0 ? a.sx : a.sy;
         for (int it = tid; it < FX * FY; it += NT) {
@@ -708,7 +712,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep2d(SweepArgs a)
                     double Fk[NV];
                     // one call for both sides: a select on `side` around the
                     // call would run the whole point evaluation twice per wave
-                    ssum += gauss_point_sided<NV>(Wown, Woth, sgn, co, ct, DIR, mc, Fk);
+                    ssum += gauss_point_sided<NV>(Wown, Woth, sgn, co, ct, DIR, mc, Fk, want_sigma);
                     const double eta = kTab.eta[OI][side == 0 ? j : GA + j];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) Fs[v] = fma(eta, Fk[v], Fs[v]);
@@ -717,7 +721,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep2d(SweepArgs a)
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fs[v] += swap_pair(Fs[v]);
             ssum += swap_pair(ssum);
-            if (valid && side == 0) {
+            if (want_sigma && valid && side == 0) {
                 const bool own = DIR == 0 ? (fx > 0 || i0 == 0) : (fy > 0 || j0 == 0);
                 if (own) a.sig_out[pl] = ssum / (double)G;
             }
@@ -922,6 +926,7 @@ struct BatchArgs {
     const double *dx;
     double *U, *sig, *t, *dt_hist;
     const double *dt_in;        // optional [nsteps][ninst]: replayed time steps instead of the CFL rule
+    int *status;                // optional [ninst]: 0, or s+1 if the instance stopped at step s
     double *U1, *U2, *sig2;     // workspace, same layout as U / sig
     const int *bin_start, *bin_list;
     const int *bc_inst;         // optional per-instance boundary code (else `bc` for all)
@@ -1001,6 +1006,7 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
         double *sA = a.sig + off, *sB = a.sig2 + off;
         const double inv_dx = 1.0 / a.dx[k];
         double t = a.t[k];
+        if (a.status != nullptr && threadIdx.x == 0) a.status[k] = 0;
         int s = 0;
         for (; s < a.nsteps; ++s) {
             if (a.t_end > 0.0 && t >= a.t_end) break;
@@ -1039,6 +1045,12 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
                 __syncthreads();
             }
             const double dt = s_dt;
+            if (a.status != nullptr && !a.dt_in && !(dt > 0.0)) {
+                // a signal speed of the state is NaN (rho <= 0 or p <= 0
+                // somewhere): the instance stops here and says so
+                if (threadIdx.x == 0) a.status[k] = s + 1;
+                break;
+            }
             double *in_st[3] = {U, U1, U2};
             double *out_st[3] = {U1, U2, U};
             for (int st = 0; st < 3; ++st) {
@@ -1063,6 +1075,8 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
             if (threadIdx.x == 0 && a.dt_hist) a.dt_hist[(long long)s * a.ninst + k] = dt;
             __syncthreads();
         }
+        // first-order source: hand back the strengths of the final state
+        if (a.fo && a.nsteps > 0) batched_fill<NT>(a, bc, U, sA, N, mc);
         if (threadIdx.x == 0) {
             a.t[k] = t;
             if (a.dt_hist)
@@ -1873,7 +1887,7 @@ void launch_batched(const BatchLaunch &bl, hipStream_t st)
 {
     BatchArgs a;
     a.offsets = bl.offsets; a.ncells = bl.ncells; a.dx = bl.dx;
-    a.U = bl.U; a.sig = bl.sig; a.t = bl.t; a.dt_hist = bl.dt_hist; a.dt_in = bl.dt_in;
+    a.U = bl.U; a.sig = bl.sig; a.t = bl.t; a.dt_hist = bl.dt_hist; a.dt_in = bl.dt_in; a.status = bl.status;
     a.U1 = bl.U1; a.U2 = bl.U2; a.sig2 = bl.sig2;
     a.bin_start = bl.bin_start; a.bin_list = bl.bin_list; a.bc_inst = bl.bc_inst;
     a.total = bl.total; a.ninst = bl.ninst; a.ng = bl.ng; a.nsteps = bl.nsteps; a.bc = bl.bc; a.fo = bl.fo;

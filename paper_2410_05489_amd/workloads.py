@@ -93,7 +93,7 @@ class Params:
     d_lo: float = 0.85
     dt_cap: float = 0.0
     positivity_fallback: int = 0
-    df_source: int = 0          # DF_LAGGED or DF_FIRST_ORDER
+    df_source: int = 1          # DF_FIRST_ORDER (the reading adopted) or DF_LAGGED
     fail_nonphysical: int = 0   # ase_step / ase_step_gks report a non-physical final state
 
 
@@ -161,7 +161,7 @@ def sod(n: int = 200, order: int = 5) -> Workload:
 def blast_wave(n: int = 400, order: int = 9, t_end: float = 0.038) -> Workload:
     """Woodward-Colella blast wave on [0,1]: (1,0,1000) | (1,0,0.01) | (1,0,100)
     split at 0.1 and 0.9, reflective walls at both ends, gamma 1.4, CFL 0.5
-    (exact cell averages; positivity fallback and first-order DF source on)."""
+    (exact cell averages)."""
     dx = 1.0 / n
     g = Grid(dim=1, nx=n, ny=1, ng=ghosts_for(order), dx=dx, dy=dx, bc=(BC_REFLECTIVE,) * 4)
     xl = np.arange(n) * dx
@@ -174,11 +174,7 @@ def blast_wave(n: int = 400, order: int = 9, t_end: float = 0.038) -> Workload:
     W = np.stack([np.ones(n), np.zeros(n), E])
     U = empty_state(g)
     _fill_interior(g, U, W)
-    # the lagged DF source lets the first stages reconstruct across the 1e5
-    # pressure jump with linear stencils (non-physical states in step 1 at
-    # r >= 5); the first-order source runs the problem at every order
-    return Workload("blast_wave", g, Params(order=order, gamma=gamma, cfl=0.5, positivity_fallback=1,
-                                            df_source=DF_FIRST_ORDER), U, 100000, t_end)
+    return Workload("blast_wave", g, Params(order=order, gamma=gamma, cfl=0.5), U, 100000, t_end)
 
 
 def shu_osher(n: int = 200, order: int = 9, t_end: float = 1.8) -> Workload:
@@ -202,8 +198,7 @@ def shu_osher(n: int = 200, order: int = 9, t_end: float = 1.8) -> Workload:
     E = fl * WL_[2] + (1.0 - fl) * (1.0 / (gamma - 1.0))
     U = empty_state(g)
     _fill_interior(g, U, np.stack([rho, mom, E]))
-    return Workload("shu_osher", g, Params(order=order, gamma=gamma, cfl=0.5, positivity_fallback=1), U,
-                    100000, t_end)
+    return Workload("shu_osher", g, Params(order=order, gamma=gamma, cfl=0.5), U, 100000, t_end)
 
 
 def density_wave_1d(n: int, order: int, seed: int = -1, amp: float = 1e-3, cfl: float = 0.5,
@@ -299,8 +294,7 @@ def double_mach(nx: int = 960, ny: int = 240, order: int = 9, t_end: float = 0.2
     W = Wpre[:, None, None] + (Wpost - Wpre)[:, None, None] * frac[None]
     U = empty_state(g)
     _fill_interior(g, U, W)
-    return Workload("double_mach", g, Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=1,
-                                             df_source=DF_FIRST_ORDER), U, nsteps, t_end)
+    return Workload("double_mach", g, Params(order=order, gamma=gamma, cfl=cfl), U, nsteps, t_end)
 
 
 def viscous_shock_tube(nx: int = 500, ny: int = 250, order: int = 5, re: float = 200.0, t_end: float = 1.0,
@@ -374,7 +368,7 @@ def four_quadrant(n: int = 1024, order: int = 9, seed: int = 0, nsteps: int = 20
     U = empty_state(g)
     _fill_interior(g, U, W)
     return Workload(f"four_quadrant_{n}x{nyy}_r{order}_seed{seed}", g,
-                    Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=1), U, nsteps, 0.0)
+                    Params(order=order, gamma=gamma, cfl=cfl), U, nsteps, 0.0)
 
 
 def jet(nx: int = 1600, ny: int = 800, order: int = 7, u_jet: float = 7400.0, nsteps: int = 500,
@@ -457,8 +451,7 @@ def batched_riemann(ninst: int = 256, nmin: int = 64, nmax: int = 4096, order: i
         W = frac[None, :] * WL[:, None] + (1 - frac[None, :]) * WR[:, None]
         o = int(offsets[k])
         U[:, o + ng:o + ng + N] = W
-    return Batch(ncells, offsets, dx, ng, U, Params(order=order, gamma=gamma, cfl=cfl, positivity_fallback=1),
-                 BC_TRANSMISSIVE, nsteps)
+    return Batch(ncells, offsets, dx, ng, U, Params(order=order, gamma=gamma, cfl=cfl), BC_TRANSMISSIVE, nsteps)
 
 
 def batched_smooth(ninst: int = 16, nmin: int = 64, nmax: int = 512, order: int = 9, seed: int = 1,
@@ -490,6 +483,19 @@ def batched_smooth(ninst: int = 16, nmin: int = 64, nmax: int = 512, order: int 
     return Batch(ncells, offsets, dx, ng, U, Params(order=order, gamma=gamma, cfl=cfl), BC_PERIODIC, nsteps)
 
 
+def batch_subset(batch: Batch, keep) -> Batch:
+    """The instances `keep` (indices, in order) of a batch, packed anew."""
+    keep = [int(k) for k in keep]
+    ncells, offsets, total = _pack([int(batch.ncells[k]) for k in keep], batch.ng)
+    U = np.zeros((3, total), dtype=np.float64)
+    for j, k in enumerate(keep):
+        o = int(offsets[j])
+        U[:, o:o + int(ncells[j]) + 2 * batch.ng] = batch.instance(k)
+    bci = None if batch.bc_inst is None else np.asarray(batch.bc_inst)[keep].astype(np.int32)
+    return Batch(ncells, offsets, np.asarray(batch.dx)[keep].copy(), batch.ng, U, dataclasses.replace(batch.params),
+                 batch.bc, batch.nsteps, bci)
+
+
 def instance_grid(batch: Batch, k: int) -> Grid:
     """The single-instance 1D grid of instance k of a batch."""
     N = int(batch.ncells[k])
@@ -502,7 +508,7 @@ def batched_mixed(ninst: int = 12, nmin: int = 16, nmax: int = 400, order: int =
     """Instances with their own boundary conditions: instance k carries the
     smooth periodic data of batched_smooth (k % 3 == 0), the transmissive
     Riemann data of batched_riemann (k % 3 == 1) or that Riemann data between
-    two reflective walls (k % 3 == 2); positivity fallback on."""
+    two reflective walls (k % 3 == 2)."""
     sm = batched_smooth(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed, nsteps=nsteps)
     rm = batched_riemann(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed + 1, nsteps=nsteps)
     pick = [sm if k % 3 == 0 else rm for k in range(ninst)]
@@ -513,5 +519,5 @@ def batched_mixed(ninst: int = 12, nmin: int = 16, nmax: int = 400, order: int =
         U[:, o:o + int(ncells[k]) + 2 * sm.ng] = b.instance(k)
     dx = np.array([float(b.dx[k]) for k, b in enumerate(pick)])
     bc_inst = np.array([(BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE)[k % 3] for k in range(ninst)], dtype=np.int32)
-    return Batch(ncells, offsets, dx, sm.ng, U, Params(order=order, gamma=1.4, cfl=0.5, positivity_fallback=1),
-                 BC_TRANSMISSIVE, nsteps, bc_inst)
+    return Batch(ncells, offsets, dx, sm.ng, U, Params(order=order, gamma=1.4, cfl=0.5), BC_TRANSMISSIVE, nsteps,
+                 bc_inst)

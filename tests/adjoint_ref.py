@@ -1,6 +1,8 @@
 """Helpers shared by the adjoint tests: the torch adjoint oracle set up for a
 1D grid, and one SSP-RK3 step of the C oracle with the three stage strengths
 replayed (the frozen-decision map whose transposed Jacobian the adjoint is)."""
+import dataclasses
+
 import numpy as np
 import torch
 
@@ -16,15 +18,29 @@ def stepper(g, p):
 
 
 def _residual(g, p, U, s):
-    L, sn, _ = O.residual(g, p, U.copy(), s.copy(), np.zeros_like(s))
+    """The C oracle's L(U) with the strengths s replayed: the boundary step
+    runs with the lagged rule, which keeps the flux-face strengths as given
+    (and for periodic, transmissive and reflective ends derives the other
+    faces as the first-order rule does from first-order flux faces)."""
+    q = dataclasses.replace(p, df_source=WL.DF_LAGGED)
+    L, sn, _ = O.residual(g, q, U.copy(), s.copy(), np.zeros_like(s))
     return L, sn
 
 
 def stage_sigmas(g, p, U, sx, dt):
     """Strength arrays read by the three stages of the C oracle's step from
-    (U, sx) with time step dt."""
+    (U, sx) with time step dt: the previous stage's Gauss-point strengths
+    (lagged source) or the first-order strengths of each stage input."""
+    if p.df_source == WL.DF_FIRST_ORDER:
+        s0 = O.sigma_init(g, p, U.copy())[0]
+        L1, _ = _residual(g, p, U, s0)
+        U1 = U + dt * L1
+        s1 = O.sigma_init(g, p, U1.copy())[0]
+        L2, _ = _residual(g, p, U1, s1)
+        U2 = 0.75 * U + 0.25 * U1 + 0.25 * dt * L2
+        s2 = O.sigma_init(g, p, U2.copy())[0]
+        return [s0, s1, s2]
     L1, s1 = _residual(g, p, U, sx)
-    U1 = U.copy()
     U1 = U + dt * L1
     L2, s2 = _residual(g, p, U1, s1)
     return [sx.copy(), s1, s2]

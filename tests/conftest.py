@@ -1,6 +1,11 @@
 import os
 import sys
 
+# parallel test workers: one oracle thread each (the oracle's OpenMP loops
+# would otherwise oversubscribe the host)
+if os.environ.get("PYTEST_XDIST_WORKER"):
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))

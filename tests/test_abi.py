@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert "ase_step" in names and "ase_reconstruct" in names
     for n in names:
         assert hasattr(L, n), n
-    assert L.ase_version() == 3
+    assert L.ase_version() == 4
 
 
 def _args(order=9, **kw):
@@ -131,6 +131,6 @@ def test_empty_batches_are_rejected():
     assert L.ase_batched_plan(2, nc, 2, start, lst) == 0
     assert sorted(lst) == [0, 1] and start[2] == 2
     P = C.byref(ase.c_params(WL.sod(20, 9).params))
-    rc = L.ase_step_batched(P, 1, None, 0, None, None, None, 5, 0, None, None, None, None, None, 1, 0.0, None,
-                            None, 1, 256, None, 0, None)
+    rc = L.ase_step_batched(P, 1, None, 0, None, None, None, 5, 0, None, None, None, None, None, None, 1, 0.0,
+                            None, None, 1, 256, None, 0, None)
     assert rc == -1 and len(L.ase_last_error()) > 0

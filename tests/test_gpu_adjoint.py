@@ -28,19 +28,29 @@ def _case(name):
     if name.startswith("wave"):
         n, order = {"wave9": (600, 9), "wave5": (300, 5), "wave3": (300, 3)}[name]
         return WL.density_wave_1d(n, order, seed=2), 4
-    if name == "sodfo":
+    if name == "sodlag":
+        # the lagged DF source: strengths from the previous stage's face states
         w = WL.sod(300, 9)
-        w.params.df_source = WL.DF_FIRST_ORDER
+        w.params.df_source = WL.DF_LAGGED
         return w, 2
     if name.startswith("sod"):
         n, order = {"sod9": (600, 9), "sod7": (300, 7), "sod5": (300, 5), "sod3": (300, 3)}[name]
         return WL.sod(n, order), 1
     if name == "rarefaction":
+        # lagged source: its first stage reconstructs across the jump, whose
+        # non-physical face states the positivity replacement takes over
         w = WL.riemann_1d(300, (1.115, -4.992, 0.143), (0.884, 4.943, 0.137), 9)
         w.params.positivity_fallback = 1
+        w.params.df_source = WL.DF_LAGGED
         return w, 1
     if name == "wall":
-        # Sod data between two reflective walls, lagged DF source
+        # Sod data between two reflective walls, lagged DF source (mirrored
+        # ghost-face strengths)
+        w = WL.sod(300, 9)
+        w.grid.bc = (WL.BC_REFLECTIVE,) * 4
+        w.params.df_source = WL.DF_LAGGED
+        return w, 40
+    if name == "wallfo":
         w = WL.sod(300, 9)
         w.grid.bc = (WL.BC_REFLECTIVE,) * 4
         return w, 40
@@ -49,7 +59,8 @@ def _case(name):
     raise ValueError(name)
 
 
-CASES = ["wave9", "sod9", "sod7", "sod5", "sod3", "wave5", "wave3", "sodfo", "rarefaction", "wall", "blast"]
+CASES = ["wave9", "sod9", "sod7", "sod5", "sod3", "wave5", "wave3", "sodlag", "rarefaction", "wall", "wallfo",
+         "blast"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -180,17 +191,32 @@ def test_batched_adjoint_launch_shapes_agree_bitwise():
 
 
 def test_batched_adjoint_fd_smooth():
-    """Smooth periodic instances (every DF factor 1): 32 components per
-    instance, central differences of J_k through the GPU forward with the
-    recorded time steps replayed, within 1e-6 of the largest gradient entry."""
-    b = WL.batched_smooth(ninst=16, nmin=64, nmax=512, order=9, seed=1, nsteps=20)
+    """Smooth periodic instances, 100 steps with checkpoints every 10 (the
+    batched adjoint configuration): 32 components per instance, central
+    differences (h = 1e-6 relative) of J_k through the GPU forward with the
+    recorded time steps replayed, each component within 1e-6 of
+    max(|fd|, |grad|) plus the rounding floor of the difference quotient,
+    4 eps |J_k| / h.  Every stage of every step is checked smooth on the
+    oracle (all stencil strength sums below the threshold, so every DF
+    factor is 1 and the frozen-decision gradient is the full one)."""
+    from adjoint_ref import stage_sigmas
+    b = WL.batched_smooth(ninst=16, nmin=64, nmax=512, order=9, seed=1, nsteps=100)
+    R = (b.params.order - 1) // 2
+    for k in range(b.ninst):
+        g = WL.instance_grid(b, k)
+        U = _inst(b, b.U, k).copy()
+        sx, _ = O.sigma_init(g, b.params, U)
+        for _ in range(b.nsteps):
+            dt = O.cfl_dt(g, b.params, U)
+            for sg in stage_sigmas(g, b.params, U, sx, dt):
+                assert 2 * R * float(sg.max()) < b.params.sigma_thres, k
+            O.step(g, b.params, U, sx, None, 0.0, 1)
     run = A.BatchedAdjoint(b, DEV, nbins=16, every=10)
     U0 = torch.tensor(b.U, device=DEV, requires_grad=True)
     J = run.pressure(run.run(U0, b.nsteps))
-    R = (b.params.order - 1) // 2
-    assert float(run.sim.sig.max()) * 2 * R < b.params.sigma_thres   # all sums below the threshold
     J.sum().backward()
     G = U0.grad.cpu().numpy()
+    Jk = J.detach().cpu().numpy()
     hist = run.dt_hist.clone()
     fwd = ase.BatchedSimulation(b, DEV, nbins=16)
     rng = np.random.default_rng(4)
@@ -208,6 +234,8 @@ def test_batched_adjoint_fd_smooth():
         ase.pressure_objective(fwd.p, fwd.offsets, fwd.ncells, fwd.dx, b.ng, b.total, fwd.U, J=Jv)
         return Jv.cpu().numpy()
 
+    eps = np.finfo(np.float64).eps
+    worst = 0.0
     for c in range(32):
         Up, Um = b.U.copy(), b.U.copy()
         hs = np.zeros(b.ninst)
@@ -221,7 +249,12 @@ def test_batched_adjoint_fd_smooth():
         for k in range(b.ninst):
             v, i = comps[k][c]
             gk = _inst(b, G, k)[:, 0, b.ng:b.ng + int(b.ncells[k])]
-            assert abs(fd[k] - gk[v, i]) <= 1e-6 * np.abs(gk).max(), (k, v, i, fd[k], gk[v, i])
+            floor = 4 * eps * abs(Jk[k]) / hs[k]
+            err = abs(fd[k] - gk[v, i])
+            bound = 1e-6 * max(abs(fd[k]), abs(gk[v, i])) + floor
+            worst = max(worst, err / bound)
+            assert err <= bound, (k, v, i, fd[k], gk[v, i], floor)
+    print(f"adjoint fd: worst error / bound {worst:.3f}", flush=True)
 
 
 def test_batched_adjoint_full_size():

@@ -199,3 +199,47 @@ def test_batched_per_instance_boundaries():
         assert np.isfinite(a).all() == np.isfinite(c).all(), k
         if np.isfinite(c).all():
             assert _rel(a[:, 0], c) < 1e-9, k
+
+
+def _nonphysical(W):
+    """Some cell of a 1D conservative state [3, n] with rho <= 0, p <= 0 or
+    a NaN (gamma 1.4)."""
+    rho, m, E = W
+    p = 0.4 * (E - 0.5 * m * m / rho)
+    return bool(np.any(~np.isfinite(W)) or np.any(rho <= 0) or np.any(p <= 0))
+
+
+def test_batched_status_flags_and_stops_lost_instances():
+    """The 256-instance batch (order 9, 100 steps) with a status array: the
+    instances whose state the method loses are flagged with the step at
+    which they stopped, holding a non-physical state there, as the oracle's
+    state after the same number of steps does; every other instance has
+    status 0 and the bits of the run without a status array."""
+    b = WL.batched_riemann()
+    st = torch.full((b.ninst,), -1, dtype=torch.int32, device=DEV)
+    a = ase.BatchedSimulation(b, DEV, nbins=256, threads=256)
+    hist = torch.zeros((b.nsteps, b.ninst), dtype=torch.float64, device=DEV)
+    a.run(b.nsteps, 0.0, hist, status=st)
+    r = ase.BatchedSimulation(b, DEV, nbins=256, threads=256)
+    r.run(b.nsteps)
+    torch.cuda.synchronize()
+    status = st.cpu().numpy()
+    Ua, Ur, ha = a.U.cpu().numpy(), r.U.cpu().numpy(), hist.cpu().numpy()
+    assert np.all(status >= 0)
+    lost = np.flatnonzero(status)
+    print(f"status: {len(lost)} of {b.ninst} instances stopped: {lost.tolist()}", flush=True)
+    assert 0 < len(lost) < b.ninst // 10
+    for k in range(b.ninst):
+        g = WL.instance_grid(b, k)
+        wa = g.interior(_instance_state(b, Ua, k))[:, 0]
+        wr = g.interior(_instance_state(b, Ur, k))[:, 0]
+        if status[k] == 0:
+            assert np.array_equal(wa, wr), k
+            assert not _nonphysical(wa), k
+            continue
+        s = int(status[k]) - 1
+        assert _nonphysical(wa), k
+        assert np.all(ha[s:, k] == 0.0) and np.all(ha[:s, k] > 0.0), k
+        # the oracle loses it at the same point
+        g, Uo, _, _ = _oracle_run(b, k, s)
+        assert _nonphysical(g.interior(Uo)[:, 0]), k

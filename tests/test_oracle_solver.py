@@ -260,10 +260,12 @@ def test_ghost_cells(oracle):
 
 
 def test_sigma_state_rules(oracle):
-    """Strengths of non-flux faces: periodic wrap, or first order from the
-    adjacent ghost-filled cells."""
+    """Lagged DF source: strengths of non-flux faces are the periodic wrap,
+    or first order from the adjacent ghost-filled cells; the first-order
+    source recomputes every face from the stage input."""
     w = WL.four_quadrant(16, 9, seed=4)
     g, p = w.grid, w.params
+    p.df_source = WL.DF_LAGGED
     U = w.U.copy()
     sx, sy = oracle.sigma_init(g, p, U)
     # one step makes the flux-face strengths differ from first order
@@ -280,6 +282,7 @@ def test_sigma_state_rules(oracle):
     # periodic: every face equals its wrapped flux face
     w = WL.density_wave_2d(12, 9, seed=5, amp=0.1)
     g, p = w.grid, w.params
+    p.df_source = WL.DF_LAGGED
     U = w.U.copy()
     sx, sy = oracle.sigma_init(g, p, U)
     oracle.step(g, p, U, sx, sy, 0.0, 1)
@@ -290,6 +293,17 @@ def test_sigma_state_rules(oracle):
             jw = (J - ng) % g.ny + ng
             iw = (I - ng) % g.nx + ng
             assert sx[J, I] == sx[jw, iw]
+    # first-order source: the boundary step makes every stored strength the
+    # first-order one of the (ghost-filled) stage input
+    w = WL.four_quadrant(16, 9, seed=4)
+    g, p = w.grid, w.params
+    assert p.df_source == WL.DF_FIRST_ORDER
+    U = w.U.copy()
+    sx, sy = oracle.sigma_init(g, p, U)
+    oracle.step(g, p, U, sx, sy, 0.0, 1)
+    oracle.bc_fill(g, p, U, sx, sy)
+    fo_x, fo_y = oracle.sigma_init(g, p, U.copy())
+    assert np.array_equal(sx[:, :-1], fo_x[:, :-1]) and np.array_equal(sy[:-1], fo_y[:-1])
 
 
 def test_levels_smooth_and_shocked(oracle):
@@ -306,3 +320,31 @@ def test_levels_smooth_and_shocked(oracle):
     sx, sy = oracle.sigma_init(g, p, U)
     _, _, lev = oracle.reconstruct(g, p, 0, U, sx, sy, want_level=True)
     assert set(np.unique(lev)) >= {2, 9}
+
+
+def test_oracle_threads_do_not_change_results(oracle):
+    """The oracle's parallel loops write disjoint cells and faces: one
+    thread and several give the same bits (2D and 1D, both DF sources)."""
+    # (grids above 4096 cells: smaller ones run every loop serially)
+    cases = [WL.four_quadrant(83, 9, seed=2, ny=61), WL.blast_wave(5003, 7)]
+    lag = WL.four_quadrant(71, 7, seed=6)
+    lag.params.df_source = WL.DF_LAGGED
+    lag.params.positivity_fallback = 1
+    cases.append(lag)
+    before = oracle.set_threads(0)
+    try:
+        for w in cases:
+            g, p = w.grid, w.params
+            out = []
+            for nt in (1, 3):
+                assert oracle.set_threads(nt) == nt
+                U = w.U.copy()
+                sx, sy = oracle.sigma_init(g, p, U)
+                oracle.step(g, p, U, sx, sy if g.dim == 2 else None, 0.0, 3)
+                out.append((U, sx, sy))
+            assert np.isfinite(out[0][0]).all()
+            for a, b in zip(out[0], out[1]):
+                if a is not None:
+                    assert np.array_equal(a.view(np.int64), b.view(np.int64))
+    finally:
+        oracle.set_threads(before)

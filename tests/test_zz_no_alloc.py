@@ -64,7 +64,8 @@ def test_noalloc_refuses_batches_beyond_the_scratch():
     assert int(ase.lib().ase_batched_workspace_bytes(too_big - 1)) <= SCRATCH_BYTES
     rc = ase.lib().ase_step_batched_noalloc(
         C.byref(ase.c_params(b.params)), b.bc, None, b.ninst, sim.offsets.data_ptr(), sim.ncells.data_ptr(),
-        sim.dx.data_ptr(), b.ng, too_big, sim.U.data_ptr(), sim.sig.data_ptr(), sim.t.data_ptr(), None, None, 2, 0.0,
+        sim.dx.data_ptr(), b.ng, too_big, sim.U.data_ptr(), sim.sig.data_ptr(), sim.t.data_ptr(), None, None, None,
+        2, 0.0,
         sim.bin_start.data_ptr(), sim.bin_list.data_ptr(), sim.nbins, sim.threads,
         torch.cuda.current_stream().cuda_stream)
     assert rc == ERR_WORKSPACE
