@@ -450,6 +450,11 @@ def cpu_baseline(w):
             "single_thread": v1, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -510,6 +515,7 @@ def main():
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
     finite = bool(torch.isfinite(sim.U).all().item())
+    progress(f"{args.workload}: {args.steps} steps in {ms:.1f} ms")
     # per-kernel durations from a separate run with event timing around every
     # launch (the events themselves slow the step, so the timed run above has
     # none)
@@ -556,8 +562,10 @@ def main():
                                            "positivity_fallback": bool(p.positivity_fallback)},
            "finite": finite, "roofline": roof}
     if not args.no_adjoint:
+        progress("adjoint/forward ratio on the batched workload")
         out["adjoint"] = measure_adjoint()
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

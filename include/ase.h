@@ -80,12 +80,14 @@ enum {
      * average of its own cell for the flux (its strength is +inf anyway). */
     ASE_FLAG_POSITIVITY_FALLBACK = 1,
     /* Source of the interface states the DF strengths (Sec. 3.1) are
-     * computed from.  Clear (default, "lagged"): the Gauss-point states of
-     * the previous stage's reconstruction, so the strengths are part of the
-     * state and ase_bc_fill derives the non-flux faces.  Set ("first
-     * order"): the first-order states of the current stage input, i.e. the
-     * two cell averages beside each face; ase_bc_fill then recomputes every
-     * stored strength from the ghost-filled state. */
+     * computed from.  Set ("first order", the reading this library's
+     * workloads use): the first-order states of the current stage input,
+     * i.e. the two cell averages beside each face; ase_bc_fill then
+     * recomputes every stored strength from the ghost-filled state, and
+     * the 2D sweeps evaluate no Gauss-point strengths.  Clear ("lagged"):
+     * the Gauss-point states of the previous stage's reconstruction, so the
+     * strengths are part of the state and ase_bc_fill derives the non-flux
+     * faces. */
     ASE_FLAG_DF_FIRST_ORDER = 2,
     /* ase_step, ase_step_gks: after the last step count the interior cells
      * whose average has rho <= 0, p <= 0 or a NaN component and return
@@ -212,9 +214,13 @@ int ase_stage_update(const ase_grid_t *g, const ase_params_t *p, int stage, cons
 /* Bytes of device workspace that ase_step / ase_cfl_dt need for grid g. */
 size_t ase_workspace_bytes(const ase_grid_t *g, const ase_params_t *p);
 
-/* nsteps SSP-RK3 steps of the whole method with lagged discontinuity
- * feedback: each stage computes the strengths of its flux faces from its
- * own Gauss-point states, and the next stage's DF factors use them.
+/* nsteps SSP-RK3 steps (Eq. SSP-RK3) of the whole method: the ASE-DF
+ * reconstruction of Sec. 3 with Gauss points on the faces (Sec. 2.1), the
+ * Lax-Friedrichs flux of Sec. 2.3 and the conservative update of the
+ * semi-discrete form (Sec. 2.1).  The DF strengths a stage reads come from
+ * its own cell averages (ASE_FLAG_DF_FIRST_ORDER; the strengths handed back
+ * are those of the final state) or, lagged, from the previous stage's
+ * Gauss-point states (each stage writes the strengths of its flux faces).
  * Per step: boundary fill, dt, then three stages of reconstruction, flux,
  * quadrature and update, all on device; the ghost cells of the stage
  * inputs are filled at their times t_n, t_n + dt, t_n + dt/2 (a moving
@@ -284,8 +290,8 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
  * a strength array sigma[c] (strength of the face between stored cells c and
  * c+1 of the same instance; the DF state as in the 1D grid form).  Every
  * instance has its own dx and its own time t[k] and dt (CFL of its own
- * cells); all share the method parameters, the boundary kind `bc`
- * (ASE_BC_PERIODIC or ASE_BC_TRANSMISSIVE) and ng >= (order+1)/2.  The
+ * cells); all share the method parameters and ng >= (order+1)/2; the
+ * boundary kind is `bc` or, per instance, bc_inst (below).  The
  * caller guarantees disjoint, in-range instances (the kernel skips an
  * instance whose range leaves [0, total)); periodic instances need
  * ncells >= ng. */
@@ -370,7 +376,8 @@ int ase_step_batched_noalloc(const ase_params_t *p, int32_t bc, const int32_t *b
  * positivity replacements.  Differentiated exactly: the reconstructions of
  * Sec. 3.2-3.4 (including the nonlinear WENO-Z-AO weights), the Euler and LF
  * fluxes, the stage combinations and the ghost copies of the boundary
- * conditions.  Boundaries: transmissive or periodic (both sides alike). */
+ * conditions.  Boundaries: transmissive, periodic or reflective (both sides
+ * alike; per instance in the batched form).  1D grids only. */
 
 /* Device workspace of ase_adjoint_step on the 1D grid g. */
 size_t ase_adjoint_workspace_bytes(const ase_grid_t *g);
