@@ -25,9 +25,11 @@ METRIC = "Mcell-updates/s, 9th-order 2D ASE step (FP64) + % HBM roofline; adjoin
 
 # HBM bytes per launch of the two sweep kernels on the default workload, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy (summary in
-# profiles/k_sweep2d_quad1024_r9.md).  Valid only for the kernel sources with
+# profiles/k_sweep2d_quad1024_r9.md, 1024^2 and 4096^2).  Valid only for the kernel sources with
 # this fingerprint; once they change the bench reports traffic as null.
-MEASURED_TRAFFIC = {"fingerprint": "e165722cfa1b0476", "sweep_x": 96689715, "sweep_y": 153959067}
+MEASURED_TRAFFIC = {"fingerprint": "1b45387da80409a0", "workloads": ("quad1024", "quad4096"),
+                    "quad1024": {"sweep_x": 87917985, "sweep_y": 145330802},
+                    "quad4096": {"sweep_x": 1752534685, "sweep_y": 2785175578}}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
@@ -540,9 +542,8 @@ def main():
     # DF source adds a read and a write of each face strength per stage
     step_bytes = 8 * 4 * 8 + (12 * 8 if lagged else 0)
     traffic = None
-    if args.workload in MEASURED_TRAFFIC.get("workloads", ("quad1024",)) and \
-            kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]:
-        traffic = MEASURED_TRAFFIC[dom]
+    if args.workload in MEASURED_TRAFFIC["workloads"] and kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]:
+        traffic = MEASURED_TRAFFIC[args.workload][dom]
     roof = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved_tf / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
             "kernel": f"k_sweep2d ({dom}), order {p.order}",
