@@ -399,21 +399,28 @@ int ase_adjoint_step(const ase_grid_t *g, const ase_params_t *p, const double *U
  * segment of nsteps steps (a tape of 3 nsteps stage inputs). */
 size_t ase_adjoint_batched_workspace_bytes(int64_t total, int32_t nsteps);
 
+/* Phases of ase_adjoint_batched. */
+enum { ASE_ADJ_TAPE = 1, ASE_ADJ_REVERSE = 2 };
+
 /* Adjoint of nsteps batched steps (instance table, bc and bins as in
  * ase_step_batched; threads 128, 256 or 512).  U_ck, sigma_ck: state and DF
  * strengths at the segment start (a checkpoint of the forward run);
  * dt_hist: device [nsteps][ninst], the segment's recorded time steps (0 =
  * step not taken).  lam [3][total]: in, the adjoint at the segment end; out,
- * the adjoint at its start (ghost entries 0).  One persistent launch: each
- * workgroup re-runs the segment forward for its instances, keeping every
- * stage input in the workspace, then runs the steps back.  Device pointers;
- * asynchronous on `stream`. */
+ * the adjoint at its start (ghost entries 0).  One persistent launch per
+ * phase: with ASE_ADJ_TAPE each workgroup re-runs the segment forward for
+ * its instances and keeps every stage input in the workspace (lam is not
+ * touched); with ASE_ADJ_REVERSE it runs the steps back over the tape a
+ * tape phase left in the same workspace for the same segment and
+ * arguments; both bits do both in one launch.  A tape phase of one segment
+ * (its own workspace) may run concurrently with the reverse phase of
+ * another on a second stream.  Device pointers; asynchronous on `stream`. */
 int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
                         const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
                         const double *U_ck,
                         const double *sigma_ck, const double *dt_hist, int32_t nsteps, double *lam,
-                        const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
-                        size_t ws_bytes, void *stream);
+                        const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                        int32_t phase, void *ws, size_t ws_bytes, void *stream);
 
 /* Objective of the adjoint runs: J_k = dx_k sum_i p_i over the interior cells
  * of each instance (p from the Euler equation of state, Sec. 2.3), and the

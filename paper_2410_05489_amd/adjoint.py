@@ -44,11 +44,40 @@ class _BatchedRun(torch.autograd.Function):
         ckU, ckS, hist = ctx.saved_tensors
         every = runner.every
         lam = gU.contiguous().clone()
-        for s in reversed(range(ckU.shape[0])):
+        segs = [s for s in reversed(range(ckU.shape[0])) if min(every, nsteps - s * every) > 0]
+
+        def call(s, ws, phase, stream=None):
             n = min(every, nsteps - s * every)
-            if n > 0:
-                ase.adjoint_batched(runner.sim, ckU[s], ckS[s], hist[s * every:s * every + n], n, lam,
-                                    runner.ws_adj, runner.adj_threads, runner.adj_plan)
+            ase.adjoint_batched(runner.sim, ckU[s], ckS[s], hist[s * every:s * every + n], n, lam, ws,
+                                runner.adj_threads, runner.adj_plan, stream=stream, phase=phase)
+
+        if not runner.overlap or len(segs) < 2:
+            for s in segs:
+                call(s, runner.ws_adj, ase.ADJ_TAPE | ase.ADJ_REVERSE)
+            return lam, None, None
+        # The recomputation of a segment needs only its checkpoint, not the
+        # adjoint: it runs on a side stream into the other workspace while
+        # the main stream runs the previous segment back.
+        main = torch.cuda.current_stream()
+        side = runner.side_stream()
+        ws = (runner.ws_adj, runner.ws_adj_other())
+        side.wait_stream(main)
+        call(segs[0], ws[0], ase.ADJ_TAPE)
+        tape_done, rev_done = {}, {}
+        for i, s in enumerate(segs):
+            if i + 1 < len(segs):
+                with torch.cuda.stream(side):
+                    if i >= 1:
+                        side.wait_event(rev_done[i - 1])   # its workspace held segment i-1's tape
+                    call(segs[i + 1], ws[(i + 1) % 2], ase.ADJ_TAPE, stream=side)
+                    tape_done[i + 1] = torch.cuda.Event()
+                    tape_done[i + 1].record(side)
+            if i >= 1:
+                main.wait_event(tape_done[i])
+            call(s, ws[i % 2], ase.ADJ_REVERSE, stream=main)
+            rev_done[i] = torch.cuda.Event()
+            rev_done[i].record(main)
+        main.wait_stream(side)
         return lam, None, None
 
 
@@ -78,13 +107,29 @@ class BatchedAdjoint:
     J.sum().backward() gives dJ/dU0 through the adjoint kernels."""
 
     def __init__(self, batch, device="cuda", nbins: int = 0, threads: int = 256, adj_threads: int = 256,
-                 every: int = 10, adj_nbins: int = 0):
+                 every: int = 10, adj_nbins: int = 0, overlap: bool = True):
         self.sim = ase.BatchedSimulation(batch, device, nbins=nbins, threads=threads)
         self.every = int(every)
         self.adj_threads = int(adj_threads)
         self.adj_plan = ase.device_plan(batch.ncells, adj_nbins, device) if adj_nbins else None
         self.ws_adj = ase.Workspace(ase.adjoint_batched_workspace_bytes(batch.total, self.every), device)
+        self.device = device
+        self.overlap = overlap          # recompute segment s-1 while running segment s back
+        self._ws2 = None
+        self._side = None
         self.dt_hist = None
+
+    def ws_adj_other(self):
+        """The second tape workspace of the overlapped backward."""
+        if self._ws2 is None:
+            self._ws2 = ase.Workspace(self.ws_adj.nbytes, self.device)
+        return self._ws2
+
+    def side_stream(self):
+        """The stream the recomputations run on (default priority)."""
+        if self._side is None:
+            self._side = torch.cuda.Stream(device=self.device)
+        return self._side
 
     def init_sigma(self):
         self.sim.sigma_init()

@@ -98,7 +98,7 @@ def lib():
     L.ase_adjoint_batched_workspace_bytes.restype = C.c_size_t
     L.ase_adjoint_batched_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
     L.ase_adjoint_batched.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp,
-                                      C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+                                      C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_pressure_objective.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp]
     L.ase_gks_flux.argtypes = [vp, vp, C.c_int32, dp, dp, dp, dp, C.c_double, dp, dp, vp]
     L.ase_gks_workspace_bytes.restype = C.c_size_t
@@ -448,17 +448,22 @@ def device_plan(ncells, nbins: int, device="cuda"):
     return nbins, torch.as_tensor(start).to(device), torch.as_tensor(lst).to(device)
 
 
+ADJ_TAPE, ADJ_REVERSE = 1, 2
+
+
 def adjoint_batched(sim: "BatchedSimulation", U_ck, sig_ck, dt_hist, nsteps: int, lam, ws: Workspace,
-                    threads: int = 256, plan=None, stream=None):
+                    threads: int = 256, plan=None, stream=None, phase: int = ADJ_TAPE | ADJ_REVERSE):
     """Adjoint of nsteps steps of a batch from the checkpoint (U_ck, sig_ck);
     dt_hist [nsteps, ninst] the recorded steps; lam [3, total] in/out.
-    plan: (nbins, bin_start, bin_list) on the device (default: the sim's)."""
+    plan: (nbins, bin_start, bin_list) on the device (default: the sim's).
+    phase: ADJ_TAPE (recompute the segment into ws), ADJ_REVERSE (run it
+    back from the tape in ws) or both."""
     b = sim.b
     nbins, bs, bl = plan if plan is not None else (sim.nbins, sim.bin_start, sim.bin_list)
     _check(lib().ase_adjoint_batched(C.byref(c_params(sim.p)), b.bc, _p(sim.bc_inst), b.ninst, _p(sim.offsets),
                                      _p(sim.ncells),
                                      _p(sim.dx), b.ng, b.total, _p(U_ck), _p(sig_ck), _p(dt_hist), int(nsteps),
-                                     _p(lam), _p(bs), _p(bl), int(nbins), int(threads), ws.ptr,
+                                     _p(lam), _p(bs), _p(bl), int(nbins), int(threads), int(phase), ws.ptr,
                                      ws.nbytes, _stream(stream)), "ase_adjoint_batched")
 
 

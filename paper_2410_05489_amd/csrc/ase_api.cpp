@@ -949,6 +949,7 @@ int ase_adjoint_step(const ase_grid_t *g, const ase_params_t *p, const double *U
     al.nsteps = 1;
     al.bc = g->bc[0];
     al.fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
+    al.phase = ASE_ADJ_TAPE | ASE_ADJ_REVERSE;
     al.mc = method_const(p);
     {
         ProfScope ps(ASE_KCLASS_ADJOINT, st);
@@ -967,8 +968,8 @@ int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_ins
                         const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
                         const double *U_ck,
                         const double *sigma_ck, const double *dt_hist, int32_t nsteps, double *lam,
-                        const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws,
-                        size_t ws_bytes, void *stream)
+                        const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                        int32_t phase, void *ws, size_t ws_bytes, void *stream)
 {
     int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, const_cast<double *>(U_ck),
                             const_cast<double *>(sigma_ck));
@@ -977,6 +978,8 @@ int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_ins
     if (nbins < 1) return fail(ASE_ERR_ARG, "nbins must be >= 1");
     if (threads != 128 && threads != 256 && threads != 512)
         return fail(ASE_ERR_ARG, "threads must be 128, 256 or 512");
+    if (phase < ASE_ADJ_TAPE || phase > (ASE_ADJ_TAPE | ASE_ADJ_REVERSE))
+        return fail(ASE_ERR_ARG, "phase must be ASE_ADJ_TAPE, ASE_ADJ_REVERSE or both");
     ASE_PTR(dx, "dx");
     ASE_PTR(dt_hist, "dt_hist");
     ASE_PTR(lam, "lam");
@@ -1006,6 +1009,7 @@ int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_ins
     al.nsteps = nsteps;
     al.bc = bc;
     al.fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
+    al.phase = phase;
     al.mc = method_const(p);
     {
         ProfScope ps(ASE_KCLASS_ADJOINT, (hipStream_t)stream);

@@ -114,6 +114,7 @@ struct AdjLaunch {
     const int *bc_inst;
     long long total;
     int ninst, nbins, threads, R, ng, nsteps, bc, fo;
+    int phase;   // ASE_ADJ_TAPE, ASE_ADJ_REVERSE or both
     MethodConst mc;
 };
 void launch_adjoint(const AdjLaunch &al, hipStream_t st);

@@ -1387,6 +1387,7 @@ struct AdjArgs {
     const int *bc_inst;                // optional per-instance boundary code
     long long total;
     int ninst, ng, nsteps, bc, fo;
+    int phase;                         // bit 1: record the tape; bit 2: reverse sweep
     MethodConst mc;
 };
 
@@ -1496,6 +1497,7 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
         while (nact < a.nsteps && a.dt_hist[(long long)nact * a.ninst + k] > 0.0) ++nact;
 
         // forward over the segment with the recorded steps, keeping the tape
+        if (a.phase & ASE_ADJ_TAPE) {
         for (int I = tid; I < NX; I += NT) {
 #pragma unroll
             for (int v = 0; v < 3; ++v) a.tapeU[v * P + off + I] = a.ck_U[v * P + off + I];
@@ -1528,6 +1530,8 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
                 }
             }
         }
+        }
+        if (!(a.phase & ASE_ADJ_REVERSE)) continue;
 
         // reverse sweep
         double *lam = a.lam + off, *mu1 = a.mu1 + off, *mu2 = a.mu2 + off;
@@ -1930,6 +1934,7 @@ void launch_adjoint(const AdjLaunch &al, hipStream_t st)
     a.mu1 = al.mu1; a.mu2 = al.mu2; a.tapeU = al.tapeU; a.tapeS = al.tapeS;
     a.bin_start = al.bin_start; a.bin_list = al.bin_list; a.bc_inst = al.bc_inst;
     a.total = al.total; a.ninst = al.ninst; a.ng = al.ng; a.nsteps = al.nsteps; a.bc = al.bc; a.fo = al.fo;
+    a.phase = al.phase;
     a.mc = al.mc;
     const int nblk = al.bin_start ? al.nbins : al.ninst;
 #define ASE_ADJ(RR, NTT) k_adjoint1d<RR, NTT><<<nblk, NTT, 0, st>>>(a)

@@ -119,7 +119,9 @@ int main()
                                     dummy, nullptr, nullptr, nullptr, 1, 0.0, &n1, &n1, 1, 256,
                                     nullptr) == ASE_ERR_WORKSPACE);
     EXPECT(ase_adjoint_batched(&p, 7, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy, dummy, 1, dummy, &n1, &n1,
-                               1, 256, dummy, 1 << 20, nullptr) == ASE_ERR_ARG);
+                               1, 256, ASE_ADJ_TAPE | ASE_ADJ_REVERSE, dummy, 1 << 20, nullptr) == ASE_ERR_ARG);
+    EXPECT(ase_adjoint_batched(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy, dummy, 1,
+                               dummy, &n1, &n1, 1, 256, 0, dummy, 1 << 20, nullptr) == ASE_ERR_ARG);
     EXPECT(ase_pressure_objective(nullptr, 1, &off, &n1, dummy, 5, 20, dummy, nullptr, nullptr, nullptr,
                                   nullptr) != ASE_OK);
     EXPECT(ase_profile_read(99, nullptr, nullptr) != ASE_OK);

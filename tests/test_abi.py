@@ -78,7 +78,7 @@ def test_adjoint_argument_errors():
     g.bc = (WL.BC_TRANSMISSIVE,) * 4
     assert L.ase_adjoint_workspace_bytes(C.byref(ase.c_grid(g))) > 0
     rc = L.ase_adjoint_batched(P1, 1, None, 4, None, None, None, 5, 100, None, None, None, 3, None, None, None, 2,
-                               1024, None, 0, None)
+                               1024, 3, None, 0, None)
     assert rc == -1
     assert L.ase_adjoint_batched_workspace_bytes(1000, 10) >= 1000 * 8 * (12 * 10 + 6)
 

@@ -296,3 +296,39 @@ def test_batched_adjoint_mixed_boundaries():
         u = torch.tensor(_inst(b, b.U, k), device=DEV, requires_grad=True)
         r1.pressure(r1.run(u, 6)).sum().backward()
         assert np.array_equal(u.grad.cpu().numpy(), _inst(b, G, k), equal_nan=True), k
+
+
+def test_batched_adjoint_phases_and_overlap_bitwise():
+    """The backward with the recomputation of each segment on a side stream
+    (tape phase into a second workspace while the main stream runs the
+    previous segment back) gives the bits of the one-launch-per-segment
+    backward; so does a tape launch followed by a reverse launch."""
+    b = WL.batched_riemann(ninst=14, nmin=40, nmax=2000, order=9, seed=21, nsteps=11)
+    grads = []
+    for overlap in (False, True):
+        run = A.BatchedAdjoint(b, DEV, nbins=5, every=3, overlap=overlap)
+        U0 = torch.tensor(b.U, device=DEV, requires_grad=True)
+        run.pressure(run.run(U0, b.nsteps)).sum().backward()
+        torch.cuda.synchronize()
+        grads.append(U0.grad.cpu().numpy())
+    assert np.array_equal(grads[0], grads[1], equal_nan=True)
+    # one segment, split into its two phases
+    run = A.BatchedAdjoint(b, DEV, nbins=5, every=4)
+    U0 = torch.tensor(b.U, device=DEV)
+    run.run(U0, 4)
+    hist = run.dt_hist[:4].clone()
+    sig0 = torch.zeros(b.total, dtype=torch.float64, device=DEV)
+    run.sim.U.copy_(U0)
+    run.init_sigma()
+    sig0.copy_(run.sim.sig)
+    rng = np.random.default_rng(3)
+    lam0 = torch.tensor(rng.standard_normal((3, b.total)), device=DEV)
+    outs = []
+    for phases in ((ase.ADJ_TAPE | ase.ADJ_REVERSE,), (ase.ADJ_TAPE, ase.ADJ_REVERSE)):
+        lam = lam0.clone()
+        ws = ase.Workspace(ase.adjoint_batched_workspace_bytes(b.total, 4), DEV)
+        for ph in phases:
+            ase.adjoint_batched(run.sim, U0, sig0, hist, 4, lam, ws, 256, phase=ph)
+        torch.cuda.synchronize()
+        outs.append(lam.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1], equal_nan=True)
