@@ -120,11 +120,18 @@ static int nparts_for(const Geo &geo)
     return (int)(b < 1 ? 1 : b);
 }
 
+// signal-speed partials: those of k_cfl_partial or one per first-order fill tile
+static size_t parts_capacity(const Geo &geo)
+{
+    const int n = sigma_init_parts(geo);
+    return (size_t)(n > kMaxParts ? n : kMaxParts);
+}
+
 size_t workspace_bytes(const Geo &geo)
 {
     const size_t state = align_up((size_t)geo.nv * (size_t)geo.plane * sizeof(double));
     const size_t plane = align_up((size_t)geo.plane * sizeof(double));
-    return 3 * state + 2 * plane + align_up(4 * sizeof(double)) + align_up(kMaxParts * sizeof(double));
+    return 3 * state + 2 * plane + align_up(4 * sizeof(double)) + align_up(parts_capacity(geo) * sizeof(double));
 }
 
 int carve_workspace(const Geo &geo, void *ws, size_t bytes, Workspace *w)
@@ -404,11 +411,20 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
     // stage inputs at t_n, t_n + dt, t_n + dt/2; after the dt kernel *t
     // holds t_n + dt, so the times are *t (first fill: before it), *t and
     // *t - dt/2
-    auto stage_bc = [&](double *Us, double *sxs_, double *sys_, double ct) {
+    // With the first-order source the fill of a step's first stage input also
+    // leaves the signal-speed maxima of the time step in w.part.
+    auto stage_bc = [&](double *Us, double *sxs_, double *sys_, double ct, double *part = nullptr) {
         // (dt is read only with a nonzero ct: before the first dt kernel it is unset)
         const double *dtp = ct != 0.0 ? w.scal : nullptr;
-        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs_, sys_, st, t, dtp, ct);
+        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs_, sys_, st, t, dtp, ct, part);
         else launch_bc_fill(*g, geo, mc, Us, sxs_, sys_, st, t, dtp, ct);
+    };
+    auto step_dt = [&](int s) {
+        double *dth = dt_hist ? dt_hist + s : nullptr;
+        if (fo)
+            launch_cfl_final(*g, geo, *p, mc, t, t, t_end, w.scal, w.scal + 1, dth, w.part, sigma_init_parts(geo), st);
+        else
+            launch_cfl(*g, geo, *p, mc, U, t, t, t_end, w.scal, w.scal + 1, dth, w.part, w.nparts, st);
     };
     double *sxs[2] = {sx, w.sxa};
     double *sys[2] = {geo.dim == 2 ? sy : sx, w.sya};
@@ -417,12 +433,11 @@ int ase_step(const ase_grid_t *g, const ase_params_t *p, double *U, double *sx, 
         double *sxc = sxs[cur], *syc = sys[cur], *sxn = sxs[cur ^ 1], *syn = sys[cur ^ 1];
         {
             ProfScope ps(ASE_KCLASS_BC, st);
-            stage_bc(U, sxc, syc, 0.0);
+            stage_bc(U, sxc, syc, 0.0, w.part);
         }
         {
             ProfScope ps(ASE_KCLASS_CFL, st);
-            launch_cfl(*g, geo, *p, mc, U, t, t, t_end, w.scal, w.scal + 1, dt_hist ? dt_hist + s : nullptr,
-                       w.part, w.nparts, st);
+            step_dt(s);
         }
         double *in_st[3] = {U, w.U1, w.U2};
         double *out_st[3] = {w.U1, w.U2, U};
@@ -595,10 +610,10 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
     double *syv = geo.dim == 2 ? sy : sx;    // 1D: the y-strength argument is unused
     double *syav = geo.dim == 2 ? w.sya : w.sxa;
     // stage inputs at t_n (before the dt kernel) and t_n + dt/2 = *t - dt/2
-    auto stage_bc = [&](double *Us, double *sxs, double *sys, double ct) {
+    auto stage_bc = [&](double *Us, double *sxs, double *sys, double ct, double *part = nullptr) {
         // (dt is read only with a nonzero ct: before the first dt kernel it is unset)
         const double *dtp = ct != 0.0 ? w.scal : nullptr;
-        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs, sys, st, t, dtp, ct);
+        if (fo) launch_sigma_init(*g, geo, mc, Us, sxs, sys, st, t, dtp, ct, part);
         else launch_bc_fill(*g, geo, mc, Us, sxs, sys, st, t, dtp, ct);
     };
     // workspace: W* in U1, L(W^n) in U2, L_t(W^n) in Res, stage-1 strengths in sxa / sya
@@ -698,12 +713,16 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
     for (int s = 0; s < nsteps; ++s) {
         {
             ProfScope ps(ASE_KCLASS_BC, st);
-            stage_bc(U, sx, syv, 0.0);
+            stage_bc(U, sx, syv, 0.0, w.part);
         }
         {
             ProfScope ps(ASE_KCLASS_CFL, st);
-            launch_cfl(*g, geo, *p, mc, U, t, t, t_end, w.scal, w.scal + 1, dt_hist ? dt_hist + s : nullptr,
-                       w.part, w.nparts, st);
+            double *dth = dt_hist ? dt_hist + s : nullptr;
+            if (fo)
+                launch_cfl_final(*g, geo, *p, mc, t, t, t_end, w.scal, w.scal + 1, dth, w.part,
+                                 sigma_init_parts(geo), st);
+            else
+                launch_cfl(*g, geo, *p, mc, U, t, t, t_end, w.scal, w.scal + 1, dth, w.part, w.nparts, st);
         }
         stage(1);
         {

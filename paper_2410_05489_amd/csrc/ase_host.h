@@ -44,15 +44,29 @@ int carve_workspace(const Geo &geo, void *ws, size_t bytes, Workspace *w);
 // 0, dt null: *t), which only the moving-shock side reads.
 void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx, double *sy,
                     hipStream_t st, const double *t = nullptr, const double *dt = nullptr, double ct = 0.0);
+// First-order DF source: ghost cells and every stored strength from the filled
+// state in one launch; with `part`, also the signal-speed maxima of the
+// time step, sigma_init_parts(geo) of them (for launch_cfl_final).
 void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
                        double *sy, hipStream_t st, const double *t = nullptr, const double *dt = nullptr,
-                       double ct = 0.0);
+                       double ct = 0.0, double *part = nullptr);
+// its tiles: 256 cells of the row in 1D, 32 x 8 stored cells in 2D
+constexpr int kFoTX1 = 256, kFoTX2 = 32, kFoTY2 = 8;
+inline int sigma_init_parts(const Geo &geo)
+{
+    if (geo.dim == 1) return (geo.NX + kFoTX1 - 1) / kFoTX1;
+    return ((geo.NX + kFoTX2 - 1) / kFoTX2) * ((geo.NY + kFoTY2 - 1) / kFoTY2);
+}
 // per-block counts of non-physical interior cells into part[0..nparts)
 void launch_nonphysical(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, const double *U, double *part,
                         int nparts, hipStream_t st);
 void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,
                 const double *t_in, double *t_out, double t_end, double *dt, double *skip, double *dt_hist,
                 double *part, int nparts, hipStream_t st);
+// the time step from nparts signal-speed maxima already in part
+void launch_cfl_final(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc,
+                      const double *t_in, double *t_out, double t_end, double *dt, double *skip, double *dt_hist,
+                      const double *part, int nparts, hipStream_t st);
 
 enum SweepMode { MODE_RECON = 0, MODE_FUSED_X = 1, MODE_FUSED_Y = 2, MODE_FUSED_1D = 3 };
 

@@ -221,14 +221,12 @@ __device__ __forceinline__ int map_face(int f, int n, int lo, int hi)
 // are independent (strengths read boundary-mapped interior values, never
 // the ghosts being written, and non-flux faces only the flux faces) and run
 // in separate workgroups (blockIdx.y): the frame is too small to fill the
-// chip, and three short chains per cell finish sooner than one.
-// ghosts_only: job 0 alone, one workgroup row (the first-order DF source:
-// k_sigma_fo then derives every strength from the filled state).
+// chip, and three short chains per cell finish sooner than one.  (With the
+// first-order DF source k_fill_fo does the ghosts and every strength.)
 template <int NV>
-__global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, double *U, double *sx, double *sy,
-                                                      int ghosts_only)
+__global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, double *U, double *sx, double *sy)
 {
-    const int job = ghosts_only ? 0 : (int)blockIdx.y;
+    const int job = (int)blockIdx.y;
     const long long n = frame_size(b);
     for (long long idx = (long long)blockIdx.x * kThreads + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * kThreads) {
@@ -276,38 +274,78 @@ __global__ void __launch_bounds__(kThreads) k_bc_fill(BCInfo b, MethodConst mc, 
     }
 }
 
-// First-order strength of every stored face from the ghost-filled state
-// (what sigma_first_order gives from the boundary-mapped values, which the
-// ghost cells now hold): the primitive variables of each cell once, for a
-// tile of 32 x 8 stored cells plus the next column and row, in LDS; then
-// each cell's x-face and y-face with the next cell, argument order and
-// normal/tangential roles as in sigma_first_order.
-template <int NV>
-__global__ void __launch_bounds__(kThreads) k_sigma_fo(BCInfo b, MethodConst mc, const double *U, double *sx,
-                                                       double *sy)
+// ---------------------------------------------------------------------------
+// Time step: per-block maxima of the signal-speed sum, then one block that
+// reduces them, clips against t_end and advances t.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double max_nan(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// First-order DF source of a stage input in one pass: the ghost cells, every
+// stored strength from the two cell averages beside its face, and, when
+// `part` is given, the largest signal-speed sum of the tile's interior cells
+// for the time step (the per-cell value of k_cfl_partial).  Tiles of TX x TY
+// stored cells plus the next column and row; the primitive variables of each
+// cell are formed once, in LDS, and each cell's x-face and y-face take the
+// argument order and normal/tangential roles of sigma_first_order.  A ghost
+// cell gets the value of the interior cell it copies (cell_value never reads
+// a ghost, so tiles may write ghosts while others read), which is what
+// k_bc_fill writes there; the strengths are those of the filled state.
+template <int NV, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_fill_fo(BCInfo b, MethodConst mc, double *U, double *sx, double *sy,
+                                                     double inv_dx, double inv_dy, double *part)
 {
-    constexpr int TXs = 32, TYs = kThreads / TXs;
-    __shared__ double sp[TYs + 1][TXs + 1], su[TYs + 1][TXs + 1], sv[TYs + 1][TXs + 1], sic[TYs + 1][TXs + 1];
-    __shared__ bool sok[TYs + 1][TXs + 1];
+    constexpr int NT = TX * TY;
+    __shared__ double sp[TY + 1][TX + 1], su[TY + 1][TX + 1], sv[TY + 1][TX + 1], sic[TY + 1][TX + 1];
+    __shared__ bool sok[TY + 1][TX + 1];
+    __shared__ double red[NT / 64];
     const int NYs = b.dim == 1 ? 1 : b.NY;
-    const int I0 = blockIdx.x * TXs, J0 = blockIdx.y * TYs;
-    for (int it = threadIdx.x; it < (TYs + 1) * (TXs + 1); it += kThreads) {
-        const int lx = it % (TXs + 1), ly = it / (TXs + 1);
+    const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TY;
+    double lam = 0.0;
+    for (int it = threadIdx.x; it < (TY + 1) * (TX + 1); it += NT) {
+        const int lx = it % (TX + 1), ly = it / (TX + 1);
         const int I = I0 + lx, J = J0 + ly;
         if (I >= b.NX || J >= NYs) continue;
         const long long pos = (long long)J * b.ld + I;
+        const int i = I - b.ng, j = J - b.ng;
+        const bool ghost = i < 0 || i >= b.nx || (b.dim == 2 && (j < 0 || j >= b.ny));
+        const bool own = lx < TX && ly < TY;
         double W[NV];
+        if (ghost) {
+            cell_value<NV>(b, U, I, J, W);
+            if (own) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + pos];
+                for (int v = 0; v < NV; ++v) U[v * b.plane + pos] = W[v];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + pos];
+        }
         const Prim q = primitives<NV>(W, 0, mc);
         sp[ly][lx] = q.p;
         su[ly][lx] = q.un;
         sv[ly][lx] = q.ut;
         sic[ly][lx] = q.ic;
         sok[ly][lx] = q.ok;
+        if (part != nullptr && own && !ghost) {
+            double l = (fabs(q.un) + q.c) * inv_dx;
+            if constexpr (NV == 4) l = l + (fabs(q.ut) + q.c) * inv_dy;
+            lam = max_nan(lam, l);
+        }
+    }
+    if (part != nullptr) {
+        // the maximum is exact and NaN-sticky in any order
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) lam = max_nan(lam, __shfl_xor(lam, o));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
     }
     __syncthreads();
-    const int lx = threadIdx.x % TXs, ly = threadIdx.x / TXs;
+    if (part != nullptr && threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) m = max_nan(m, red[w]);
+        part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = m;
+    }
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const int I = I0 + lx, J = J0 + ly;
     if (I >= b.NX || J >= NYs) return;
     const long long pos = (long long)J * b.ld + I;
@@ -324,12 +362,6 @@ __global__ void __launch_bounds__(kThreads) k_sigma_fo(BCInfo b, MethodConst mc,
     if (I + 1 < b.NX) sx[pos] = sigma_point(prim(ly, lx, true), prim(ly, lx + 1, true));
     if (b.dim == 2 && J + 1 < b.NY) sy[pos] = sigma_point(prim(ly, lx, false), prim(ly + 1, lx, false));
 }
-
-// ---------------------------------------------------------------------------
-// Time step: per-block maxima of the signal-speed sum, then one block that
-// reduces them, clips against t_end and advances t.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double max_nan(double a, double b) { return (b > a || b != b) ? b : a; }
 
 template <int NV>
 __global__ void __launch_bounds__(kThreads) k_cfl_partial(BCInfo b, MethodConst mc, const double *U, double inv_dx,
@@ -1755,26 +1787,24 @@ void launch_bc_fill(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, 
     b.dt = dt;
     b.ct = ct;
     const dim3 grid(grid_blocks(frame_size(b)), geo.dim == 2 ? 3 : 2);
-    if (geo.nv == 4) k_bc_fill<4><<<grid, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
-    else k_bc_fill<3><<<grid, kThreads, 0, st>>>(b, mc, U, sx, sy, 0);
+    if (geo.nv == 4) k_bc_fill<4><<<grid, kThreads, 0, st>>>(b, mc, U, sx, sy);
+    else k_bc_fill<3><<<grid, kThreads, 0, st>>>(b, mc, U, sx, sy);
 }
 
 void launch_sigma_init(const ase_grid_t &g, const Geo &geo, const MethodConst &mc, double *U, double *sx,
-                       double *sy, hipStream_t st, const double *t, const double *dt, double ct)
+                       double *sy, hipStream_t st, const double *t, const double *dt, double ct, double *part)
 {
     BCInfo b = make_bc(g, geo);
     b.t = t;
     b.dt = dt;
     b.ct = ct;
-    // ghost frame, then every strength from the filled state
-    const int nb = grid_blocks(frame_size(b));
-    const dim3 tiles((geo.NX + 31) / 32, (geo.NY + kThreads / 32 - 1) / (kThreads / 32));
-    if (geo.nv == 4) {
-        k_bc_fill<4><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
-        k_sigma_fo<4><<<tiles, kThreads, 0, st>>>(b, mc, U, sx, sy);
+    const double idx = 1.0 / g.dx, idy = geo.dim == 2 ? 1.0 / g.dy : 0.0;
+    if (geo.dim == 1) {
+        const dim3 tiles((geo.NX + kFoTX1 - 1) / kFoTX1);
+        k_fill_fo<3, kFoTX1, 1><<<tiles, kFoTX1, 0, st>>>(b, mc, U, sx, sy, idx, idy, part);
     } else {
-        k_bc_fill<3><<<nb, kThreads, 0, st>>>(b, mc, U, sx, sy, 1);
-        k_sigma_fo<3><<<tiles, kThreads, 0, st>>>(b, mc, U, sx, sy);
+        const dim3 tiles((geo.NX + kFoTX2 - 1) / kFoTX2, (geo.NY + kFoTY2 - 1) / kFoTY2);
+        k_fill_fo<4, kFoTX2, kFoTY2><<<tiles, kFoTX2 * kFoTY2, 0, st>>>(b, mc, U, sx, sy, idx, idy, part);
     }
 }
 
@@ -1786,6 +1816,20 @@ void launch_nonphysical(const ase_grid_t &g, const Geo &geo, const MethodConst &
     else k_nonphysical_partial<3><<<nparts, kThreads, 0, st>>>(b, mc, U, part);
 }
 
+void launch_cfl_final(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc,
+                      const double *t_in, double *t_out, double t_end, double *dt, double *skip, double *dt_hist,
+                      const double *part, int nparts, hipStream_t st)
+{
+    InflowSpeed inf;
+    inf.on = (g.bc[0] == ASE_BC_INFLOW_SLOT || g.bc[1] == ASE_BC_INFLOW_SLOT) ? 1 : 0;
+    inf.dim = geo.dim;
+    for (int k = 0; k < 4; ++k) inf.W[k] = g.inflow[k];
+    inf.inv_dx = 1.0 / g.dx;
+    inf.inv_dy = geo.dim == 2 ? 1.0 / g.dy : 0.0;
+    k_cfl_final<<<1, kThreads, 0, st>>>(part, nparts, p.cfl, p.dt_cap, t_in, t_out, t_end, dt, skip, dt_hist, inf,
+                                        mc);
+}
+
 void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,
                 const double *t_in, double *t_out, double t_end, double *dt, double *skip, double *dt_hist,
                 double *part, int nparts, hipStream_t st)
@@ -1795,14 +1839,7 @@ void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, cons
         k_cfl_partial<4><<<nparts, kThreads, 0, st>>>(b, mc, U, 1.0 / g.dx, 1.0 / g.dy, part);
     else
         k_cfl_partial<3><<<nparts, kThreads, 0, st>>>(b, mc, U, 1.0 / g.dx, 1.0 / g.dy, part);
-    InflowSpeed inf;
-    inf.on = (g.bc[0] == ASE_BC_INFLOW_SLOT || g.bc[1] == ASE_BC_INFLOW_SLOT) ? 1 : 0;
-    inf.dim = geo.dim;
-    for (int k = 0; k < 4; ++k) inf.W[k] = g.inflow[k];
-    inf.inv_dx = 1.0 / g.dx;
-    inf.inv_dy = geo.dim == 2 ? 1.0 / g.dy : 0.0;
-    k_cfl_final<<<1, kThreads, 0, st>>>(part, nparts, p.cfl, p.dt_cap, t_in, t_out, t_end, dt, skip, dt_hist, inf,
-                                        mc);
+    launch_cfl_final(g, geo, p, mc, t_in, t_out, t_end, dt, skip, dt_hist, part, nparts, st);
 }
 
 namespace {

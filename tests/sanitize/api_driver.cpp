@@ -15,11 +15,13 @@ namespace ase {
 void launch_bc_fill(const ase_grid_t &, const Geo &, const MethodConst &, double *, double *, double *, hipStream_t,
                     const double *, const double *, double) {}
 void launch_sigma_init(const ase_grid_t &, const Geo &, const MethodConst &, double *, double *, double *,
-                       hipStream_t, const double *, const double *, double) {}
+                       hipStream_t, const double *, const double *, double, double *) {}
 void launch_nonphysical(const ase_grid_t &, const Geo &, const MethodConst &, const double *, double *, int,
                         hipStream_t) {}
 void launch_cfl(const ase_grid_t &, const Geo &, const ase_params_t &, const MethodConst &, const double *,
                 const double *, double *, double, double *, double *, double *, double *, int, hipStream_t) {}
+void launch_cfl_final(const ase_grid_t &, const Geo &, const ase_params_t &, const MethodConst &, const double *,
+                      double *, double, double *, double *, double *, const double *, int, hipStream_t) {}
 void launch_sweep(const Geo &, int, int, const SweepArgs &, hipStream_t) {}
 void launch_df(const Geo &, const MethodConst &, int, const double *, const double *, double *, hipStream_t) {}
 void launch_flux(const Geo &, const MethodConst &, int, const double *, const double *, double *, hipStream_t) {}
