@@ -490,13 +490,15 @@ __device__ __forceinline__ void lf_flux(const double (&Wl)[NV], const Prim &ql, 
 // Strength and LF flux at one Gauss point, with the optional positivity
 // replacement of a non-physical side by its cell average (fetched lazily:
 // cl(v) / cr(v) return variable v of the left / right cell average).
+// With want_sigma false (first-order DF source) the strength is not
+// evaluated and 0 returned.
 template <int NV, class CL, class CR>
 __device__ __forceinline__ double gauss_point(double (&Wl)[NV], double (&Wr)[NV], CL cl, CR cr, int dir,
-                                              const MethodConst &mc, double (&F)[NV])
+                                              const MethodConst &mc, double (&F)[NV], bool want_sigma = true)
 {
     Prim ql = primitives<NV>(Wl, dir, mc);
     Prim qr = primitives<NV>(Wr, dir, mc);
-    const double sg = sigma_point(ql, qr);
+    const double sg = want_sigma ? sigma_point(ql, qr) : 0.0;
     if (mc.flags & 1) {
         if (!ql.ok) {
 #pragma unroll

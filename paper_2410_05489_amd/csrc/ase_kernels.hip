@@ -847,6 +847,18 @@ __device__ __forceinline__ void stage1d_tile(const Tile1D &a, int i0, const Meth
     constexpr int UX = Lds1D<R, T>::UX;
     const int tid = threadIdx.x;
     const int ox = i0 - 1 - R;
+    const bool want_sigma = (mc.flags & ASE_FLAG_DF_FIRST_ORDER) == 0;
+
+    // the step-start state of this lane's cell, for the stage combination
+    // (loaded now, used after the flux phase)
+    static_assert(T <= NT, "one cell of the tile per lane");
+    double un[NV] = {};
+    if constexpr (MODE != MODE_RECON) {
+        if (tid < T && i0 + tid < a.nx && a.stage > 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) un[v] = a.Un[v * a.plane + i0 + tid + a.ng];
+        }
+    }
 
     for (int lx = tid; lx < UX; lx += NT) {
         const int I = ox + lx + a.ng;
@@ -897,27 +909,28 @@ __device__ __forceinline__ void stage1d_tile(const Tile1D &a, int i0, const Meth
             double F[NV];
             auto cl = [&](int v) { return L.sU[v][fx + R]; };
             auto cr = [&](int v) { return L.sU[v][fx + R + 1]; };
-            const double sg = gauss_point<NV>(Wl, Wr, cl, cr, 0, mc, F);
+            const double sg = gauss_point<NV>(Wl, Wr, cl, cr, 0, mc, F, want_sigma);
 #pragma unroll
             for (int v = 0; v < NV; ++v) L.sF[v][fx] = F[v];
-            if (fx > 0 || i0 == 0) a.sig_out[x + a.ng] = sg;
+            if (want_sigma && (fx > 0 || i0 == 0)) a.sig_out[x + a.ng] = sg;
         }
     }
     if constexpr (MODE == MODE_RECON) return;
     __syncthreads();
 
     const double dt = a.dt;
-    for (int cx = tid; cx < T; cx += NT) {
-        const int x = i0 + cx;
-        if (x >= a.nx) continue;
+    {
+        const int cx = tid, x = i0 + cx;
+        if (cx >= T || x >= a.nx) return;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const long long e = v * a.plane + x + a.ng;
             const double Lx = -(L.sF[v][cx + 1] - L.sF[v][cx]) * a.inv_dx;
+            const double us = L.sU[v][cx + R + 1];   // the stage input (= U^n in stage 1)
             double o;
-            if (a.stage == 1) o = a.Un[e] + dt * Lx;
-            else if (a.stage == 2) o = 0.75 * a.Un[e] + 0.25 * a.U[e] + 0.25 * dt * Lx;
-            else o = (1.0 / 3.0) * a.Un[e] + (2.0 / 3.0) * a.U[e] + (2.0 / 3.0) * dt * Lx;
+            if (a.stage == 1) o = us + dt * Lx;
+            else if (a.stage == 2) o = 0.75 * un[v] + 0.25 * us + 0.25 * dt * Lx;
+            else o = (1.0 / 3.0) * un[v] + (2.0 / 3.0) * us + (2.0 / 3.0) * dt * Lx;
             a.Uout[e] = o;
         }
     }
@@ -995,13 +1008,42 @@ __device__ __forceinline__ void batched_fill(const BatchArgs &a, int bc, double 
         U[2 * P + I] = U[2 * P + Is];
     }
     __syncthreads();
+    if (a.fo) {
+        // every face from the cell averages beside it; each lane forms the
+        // primitive variables of its cell once and takes its right
+        // neighbour's from the next lane (the last lane of a wave forms them
+        // itself).  Uniform trip count: all lanes take part in the swaps.
+        for (int I0 = 0; I0 + 1 < NX; I0 += NT) {
+            const int I = I0 + threadIdx.x;
+            double Wa[3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) Wa[v] = I < NX ? U[v * P + I] : 1.0;
+            const Prim qa = primitives<3>(Wa, 0, mc);
+            Prim qb;
+            qb.p = __shfl_down(qa.p, 1);
+            qb.un = __shfl_down(qa.un, 1);
+            qb.ut = __shfl_down(qa.ut, 1);
+            qb.ic = __shfl_down(qa.ic, 1);
+            qb.c = 0.0;
+            qb.ok = __shfl_down((int)qa.ok, 1) != 0;
+            if ((threadIdx.x & 63) == 63 && I + 1 < NX) {
+                double Wb[3];
+#pragma unroll
+                for (int v = 0; v < 3; ++v) Wb[v] = U[v * P + I + 1];
+                qb = primitives<3>(Wb, 0, mc);
+            }
+            if (I + 1 < NX) sg[I] = sigma_point(qa, qb);
+        }
+        __syncthreads();
+        return;
+    }
     for (int I = threadIdx.x; I + 1 < NX; I += NT) {
         const int f = I - ng;
         const bool produced = f >= -1 && f <= N - 1;
-        if (a.fo || !produced) {
-            if (!a.fo && bc == ASE_BC_PERIODIC) {
+        if (!produced) {
+            if (bc == ASE_BC_PERIODIC) {
                 sg[I] = sg[((f % N) + N) % N + ng];
-            } else if (!a.fo && bc == ASE_BC_REFLECTIVE) {
+            } else if (bc == ASE_BC_REFLECTIVE) {
                 sg[I] = sg[(f < -1 ? -f - 2 : 2 * N - f - 2) + ng];   // mirror face at a wall
             } else {
                 double Wa[3], Wb[3];
@@ -1025,7 +1067,7 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
     // on one wave while the others wait at the next barrier)
     constexpr int T = NT - 2 * R - 2;
     __shared__ Lds1D<R, T> L;
-    __shared__ double red[NT];
+    __shared__ double red[NT / 64];
     __shared__ double s_dt;
     const MethodConst &mc = a.mc;
     for (int b = a.bin_start[blockIdx.x]; b < a.bin_start[blockIdx.x + 1]; ++b) {
@@ -1057,19 +1099,18 @@ __global__ void __launch_bounds__(NT) k_batched1d(BatchArgs a)
                     for (int v = 0; v < 3; ++v) W[v] = U[v * a.total + i + a.ng];
                     const Prim q = primitives<3>(W, 0, mc);
                     const double l = (fabs(q.un) + q.c) * inv_dx;
-                    lam = (l > lam || l != l) ? l : lam;
+                    lam = max_nan(lam, l);
                 }
-                red[threadIdx.x] = lam;
+                // the maximum is exact and NaN-sticky in any order: lanes of a
+                // wave first, then the waves
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) lam = max_nan(lam, __shfl_xor(lam, o));
+                if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
                 __syncthreads();
-                for (int w = NT / 2; w > 0; w >>= 1) {
-                    if ((int)threadIdx.x < w) {
-                        const double o = red[threadIdx.x + w];
-                        red[threadIdx.x] = (o > red[threadIdx.x] || o != o) ? o : red[threadIdx.x];
-                    }
-                    __syncthreads();
-                }
                 if (threadIdx.x == 0) {
-                    double dt = a.cfl / red[0];
+                    double m = red[0];
+                    for (int w = 1; w < NT / 64; ++w) m = max_nan(m, red[w]);
+                    double dt = a.cfl / m;
                     if (a.dt_cap > 0.0 && dt > a.dt_cap) dt = a.dt_cap;
                     if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
                     s_dt = dt;
@@ -1298,6 +1339,19 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
     const bool first = i0 == 0, last = i0 + T >= a.N;
 #pragma unroll 1
     for (int v = 0; v < 3; ++v) {
+        // this lane's first gather cell: its stage-combination terms, loaded
+        // now and used after the tap phase
+        double pa0 = 0.0, pa1 = 0.0, pa2 = 0.0;
+        {
+            const int j = i0 - a.ng + tid;
+            const bool interior = tid < T + 2 * a.ng && j >= i0 && j < i0 + T && j < a.N;
+            if (interior) {
+                const long long e = v * P + j + a.ng;
+                pa0 = a.a0[e];
+                if (a.a1) pa1 = a.a1[e];
+                if (a.a2) pa2 = a.a2[e];
+            }
+        }
         // tap contributions of each cell: c[m][cell] feeds output cell + m
         for (int c = tid; c < NC; c += NT) {
             const int x = xc + c;
@@ -1338,9 +1392,10 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
             }
             const long long e = v * P + j + a.ng;
             if (interior) {
-                double o = a.c0 * a.a0[e];
-                if (a.a1) o += a.c1 * a.a1[e];
-                if (a.a2) o += a.c2 * a.a2[e];
+                const bool pre = jj == tid;
+                double o = a.c0 * (pre ? pa0 : a.a0[e]);
+                if (a.a1) o += a.c1 * (pre ? pa1 : a.a1[e]);
+                if (a.a2) o += a.c2 * (pre ? pa2 : a.a2[e]);
                 G += o;
             }
             a.out[e] = G;
