@@ -295,38 +295,53 @@ __global__ void __launch_bounds__(TX * TY) k_fill_fo(BCInfo b, MethodConst mc, d
                                                      double inv_dx, double inv_dy, double *part)
 {
     constexpr int NT = TX * TY;
+    constexpr int NI = ((TY + 1) * (TX + 1) + NT - 1) / NT;   // items per lane
     __shared__ double sp[TY + 1][TX + 1], su[TY + 1][TX + 1], sv[TY + 1][TX + 1], sic[TY + 1][TX + 1];
     __shared__ bool sok[TY + 1][TX + 1];
     __shared__ double red[NT / 64];
     const int NYs = b.dim == 1 ? 1 : b.NY;
     const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TY;
     double lam = 0.0;
-    for (int it = threadIdx.x; it < (TY + 1) * (TX + 1); it += NT) {
+    // all loads of a lane first, then the primitive variables
+    double W[NI][NV];
+    bool valid[NI], ghost[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int it = threadIdx.x + k * NT;
         const int lx = it % (TX + 1), ly = it / (TX + 1);
         const int I = I0 + lx, J = J0 + ly;
-        if (I >= b.NX || J >= NYs) continue;
-        const long long pos = (long long)J * b.ld + I;
+        valid[k] = it < (TY + 1) * (TX + 1) && I < b.NX && J < NYs;
         const int i = I - b.ng, j = J - b.ng;
-        const bool ghost = i < 0 || i >= b.nx || (b.dim == 2 && (j < 0 || j >= b.ny));
-        const bool own = lx < TX && ly < TY;
-        double W[NV];
-        if (ghost) {
-            cell_value<NV>(b, U, I, J, W);
-            if (own) {
+        ghost[k] = i < 0 || i >= b.nx || (b.dim == 2 && (j < 0 || j >= b.ny));
+        if (!valid[k]) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) U[v * b.plane + pos] = W[v];
-            }
+            for (int v = 0; v < NV; ++v) W[k][v] = 0.0;
+        } else if (ghost[k]) {
+            cell_value<NV>(b, U, I, J, W[k]);
         } else {
+            const long long pos = (long long)J * b.ld + I;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) W[v] = U[v * b.plane + pos];
+            for (int v = 0; v < NV; ++v) W[k][v] = U[v * b.plane + pos];
         }
-        const Prim q = primitives<NV>(W, 0, mc);
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        if (!valid[k]) continue;
+        const int it = threadIdx.x + k * NT;
+        const int lx = it % (TX + 1), ly = it / (TX + 1);
+        const bool own = lx < TX && ly < TY;
+        if (ghost[k] && own) {
+            const long long pos = (long long)(J0 + ly) * b.ld + I0 + lx;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v * b.plane + pos] = W[k][v];
+        }
+        const Prim q = primitives<NV>(W[k], 0, mc);
         sp[ly][lx] = q.p;
         su[ly][lx] = q.un;
         sv[ly][lx] = q.ut;
         sic[ly][lx] = q.ic;
         sok[ly][lx] = q.ok;
-        if (part != nullptr && own && !ghost) {
+        if (part != nullptr && own && !ghost[k]) {
             double l = (fabs(q.un) + q.c) * inv_dx;
             if constexpr (NV == 4) l = l + (fabs(q.ut) + q.c) * inv_dy;
             lam = max_nan(lam, l);
@@ -453,7 +468,18 @@ __global__ void __launch_bounds__(kThreads) k_cfl_final(const double *part, int 
         }
         lam = max_nan(lam, l);
     }
-    for (int k = threadIdx.x; k < nparts; k += kThreads) lam = max_nan(lam, part[k]);
+    // eight loads in flight per lane (the partials are >= 0, so a padding 0
+    // leaves the maximum as it is)
+    for (int k0 = threadIdx.x; k0 < nparts; k0 += 8 * kThreads) {
+        double pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * kThreads;
+            pv[u] = k < nparts ? part[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) lam = max_nan(lam, pv[u]);
+    }
     red[threadIdx.x] = lam;
     __syncthreads();
     for (int s = kThreads / 2; s > 0; s >>= 1) {
