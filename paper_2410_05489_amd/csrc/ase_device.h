@@ -300,34 +300,52 @@ __device__ __forceinline__ void eval_linear(LD ld, int oi, int li, int q0, doubl
 // of the weights (table sym): the tap sums and differences are formed once
 // and each mirror pair of points costs one dot product of H + 1 and one of
 // H terms (r = 9: 30 operations per variable instead of 36).
+template <int H>
+__device__ __forceinline__ double sym_even(const double *c, double w0, const double (&sm)[H])
+{
+    double E = c[0] * w0;
+#pragma unroll
+    for (int m = 1; m <= H; ++m) E = fma(c[m], sm[m - 1], E);
+    return E;
+}
+
+template <int H>
+__device__ __forceinline__ double sym_odd(const double *c, const double (&dm)[H])
+{
+    double O = c[5] * dm[0];
+#pragma unroll
+    for (int m = 2; m <= H; ++m) O = fma(c[4 + m], dm[m - 1], O);
+    return O;
+}
+
 template <int NV, int NP, int H, class LD>
 __device__ __forceinline__ void eval_linear_gauss(LD ld, int oi, int li, double (&out)[NV][NP])
 {
-    static_assert(NP >= 3 && NP <= 4, "two mirror pairs, or a pair and the centre");
+    static_assert(NP <= 4, "at most two mirror pairs");
+    if constexpr (NP >= 3) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double w0 = ld(v, 0);
-        double sm[H], dm[H];
+        for (int v = 0; v < NV; ++v) {
+            const double w0 = ld(v, 0);
+            double sm[H], dm[H];
 #pragma unroll
-        for (int m = 1; m <= H; ++m) {
-            const double wp = ld(v, m), wm = ld(v, -m);
-            sm[m - 1] = wp + wm;
-            dm[m - 1] = wp - wm;
-        }
-#pragma unroll
-        for (int p = 0; p < (NP + 1) / 2; ++p) {
-            const double *c = kTab.sym[oi][li][p];
-            double E = c[0] * w0;
-#pragma unroll
-            for (int m = 1; m <= H; ++m) E = fma(c[m], sm[m - 1], E);
-            if (2 * p + 1 == NP) {
-                out[v][p] = E;   // the centre point: no odd part
+            for (int m = 1; m <= H; ++m) {
+                const double wp = ld(v, m), wm = ld(v, -m);
+                sm[m - 1] = wp + wm;
+                dm[m - 1] = wp - wm;
+            }
+            const double *c0 = kTab.sym[oi][li][0], *c1 = kTab.sym[oi][li][1];
+            const double E0 = sym_even<H>(c0, w0, sm), O0 = sym_odd<H>(c0, dm);
+            const double E1 = sym_even<H>(c1, w0, sm);
+            if constexpr (NP == 4) {
+                const double O1 = sym_odd<H>(c1, dm);
+                out[v][0] = E0 + O0;
+                out[v][1] = E1 + O1;
+                out[v][2] = E1 - O1;
+                out[v][3] = E0 - O0;
             } else {
-                double O = c[5] * dm[0];
-#pragma unroll
-                for (int m = 2; m <= H; ++m) O = fma(c[4 + m], dm[m - 1], O);
-                out[v][p] = E + O;
-                out[v][NP - 1 - p] = E - O;
+                out[v][0] = E0 + O0;
+                out[v][1] = E1;   // the centre point: no odd part
+                out[v][2] = E0 - O0;
             }
         }
     }
@@ -420,24 +438,22 @@ __device__ __forceinline__ int reconstruct_cell(LD ld, const double (&s)[2 * R],
         }
         return lvl;
     } else {
-        // the linear level of H taps each side: at three or four Gauss points
-        // (q0 = 2) in the mirror-pair form
-        auto linear = [&](auto Hc, int li) {
-            constexpr int H = decltype(Hc)::value;
-            if constexpr (NP >= 3) {
-                if (q0 == 2) {
-                    eval_linear_gauss<NV, NP, H>(ld, oi, li, out);
-                    return;
-                }
-            }
-            eval_linear<NV, NP, H>(ld, oi, li, q0, out);
-        };
+        // the linear levels: at three or four Gauss points (q0 = 2) in the
+        // mirror-pair form
+        constexpr bool kPairs = NP >= 3;
         if (lvl == 9) {
-            if constexpr (R >= 4) linear(std::integral_constant<int, 4>{}, 3);
+            if constexpr (R >= 4) {
+                if (kPairs && q0 == 2) eval_linear_gauss<NV, NP, 4>(ld, oi, 3, out);
+                else eval_linear<NV, NP, 4>(ld, oi, 3, q0, out);
+            }
         } else if (lvl == 7) {
-            if constexpr (R >= 3) linear(std::integral_constant<int, 3>{}, 2);
+            if constexpr (R >= 3) {
+                if (kPairs && q0 == 2) eval_linear_gauss<NV, NP, 3>(ld, oi, 2, out);
+                else eval_linear<NV, NP, 3>(ld, oi, 2, q0, out);
+            }
         } else if (lvl == 5) {
-            linear(std::integral_constant<int, 2>{}, 1);
+            if (kPairs && q0 == 2) eval_linear_gauss<NV, NP, 2>(ld, oi, 1, out);
+            else eval_linear<NV, NP, 2>(ld, oi, 1, q0, out);
         } else {
             double al[4];
             al[0] = df_alpha(ssum<R>(s, -2, 0), mc.thr);
