@@ -1242,11 +1242,11 @@ struct LdsAdj {
     uint8_t rep[NF];
 };
 
-template <int R, int T>
-union LdsAdjAll {
-    Lds1D<R, T> f;
-    LdsAdj<R, T> b;
-};
+// LDS of one phase: the forward tiles for the tape, the transposed tiles
+// for the reverse sweep (each phase is its own kernel and allocates only its
+// own, so the tape runs at the forward kernel's occupancy)
+template <int R, int T, int PH>
+using LdsAdjPhase = std::conditional_t<PH == ASE_ADJ_TAPE, Lds1D<R, T>, LdsAdj<R, T>>;
 
 struct AdjTile {
     const double *V, *S;   // stage input (ghosts filled) and the strengths the stage read
@@ -1578,11 +1578,14 @@ __device__ __forceinline__ void adj_stage(AdjTile &t, const MethodConst &mc, Lds
     adj_fold(t.out, t.plane, t.N, t.ng, bc);
 }
 
-template <int R, int NT>
-__global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
+// The tape phase is the forward kernel's work: bounded to 128 registers
+// (four waves per SIMD) like k_batched1d.
+template <int R, int NT, int PH>
+__global__ void __launch_bounds__(NT, PH == ASE_ADJ_TAPE ? 4 : 1) k_adjoint1d(AdjArgs a)
 {
+    static_assert(PH == ASE_ADJ_TAPE || PH == ASE_ADJ_REVERSE, "one phase per kernel");
     constexpr int T = NT - 2 * R - 2;   // trace cells of a tile = NT (one pass per phase)
-    __shared__ LdsAdjAll<R, T> L;
+    __shared__ LdsAdjPhase<R, T, PH> L;
     const MethodConst &mc = a.mc;
     const int tid = threadIdx.x;
     const int b0 = a.bin_start ? a.bin_start[blockIdx.x] : (int)blockIdx.x;
@@ -1610,81 +1613,81 @@ __global__ void __launch_bounds__(NT) k_adjoint1d(AdjArgs a)
         while (nact < a.nsteps && a.dt_hist[(long long)nact * a.ninst + k] > 0.0) ++nact;
 
         // forward over the segment with the recorded steps, keeping the tape
-        if (a.phase & ASE_ADJ_TAPE) {
-        for (int I = tid; I < NX; I += NT) {
+        if constexpr (PH == ASE_ADJ_TAPE) {
+            for (int I = tid; I < NX; I += NT) {
 #pragma unroll
-            for (int v = 0; v < 3; ++v) a.tapeU[v * P + off + I] = a.ck_U[v * P + off + I];
-            a.tapeS[off + I] = a.ck_sig[off + I];
-        }
-        __syncthreads();
-        BatchArgs fb;
-        fb.ng = a.ng;
-        fb.total = a.total;
-        fb.bc = bc;
-        fb.fo = a.fo;
-        for (int q = 0; q < nact; ++q) {
-            const double dt = a.dt_hist[(long long)q * a.ninst + k];
-            double *Un = a.tapeU + (3LL * q) * SU + off;
-            for (int st = 0; st < 3; ++st) {
-                double *in = a.tapeU + (3LL * q + st) * SU + off;
-                double *sin = a.tapeS + (3LL * q + st) * P + off;
-                batched_fill<NT>(fb, bc, in, sin, N, mc);
-                if (st == 2 && q == nact - 1) break;
-                Tile1D tl;
-                tl.U = in; tl.sx = sin; tl.Un = Un;
-                tl.Uout = a.tapeU + (3LL * q + st + 1) * SU + off;
-                tl.sig_out = a.tapeS + (3LL * q + st + 1) * P + off;
-                tl.wl = tl.wr = nullptr; tl.level = nullptr;
-                tl.plane = P; tl.nx = N; tl.ng = a.ng; tl.NX = NX; tl.nfaces = N + 1;
-                tl.stage = st + 1; tl.inv_dx = inv_dx; tl.dt = dt;
-                for (int i0 = 0; i0 < N; i0 += T) {
-                    stage1d_tile<R, T, NT, MODE_FUSED_1D>(tl, i0, mc, L.f);
-                    __syncthreads();
+                for (int v = 0; v < 3; ++v) a.tapeU[v * P + off + I] = a.ck_U[v * P + off + I];
+                a.tapeS[off + I] = a.ck_sig[off + I];
+            }
+            __syncthreads();
+            BatchArgs fb;
+            fb.ng = a.ng;
+            fb.total = a.total;
+            fb.bc = bc;
+            fb.fo = a.fo;
+            for (int q = 0; q < nact; ++q) {
+                const double dt = a.dt_hist[(long long)q * a.ninst + k];
+                double *Un = a.tapeU + (3LL * q) * SU + off;
+                for (int st = 0; st < 3; ++st) {
+                    double *in = a.tapeU + (3LL * q + st) * SU + off;
+                    double *sin = a.tapeS + (3LL * q + st) * P + off;
+                    batched_fill<NT>(fb, bc, in, sin, N, mc);
+                    if (st == 2 && q == nact - 1) break;
+                    Tile1D tl;
+                    tl.U = in; tl.sx = sin; tl.Un = Un;
+                    tl.Uout = a.tapeU + (3LL * q + st + 1) * SU + off;
+                    tl.sig_out = a.tapeS + (3LL * q + st + 1) * P + off;
+                    tl.wl = tl.wr = nullptr; tl.level = nullptr;
+                    tl.plane = P; tl.nx = N; tl.ng = a.ng; tl.NX = NX; tl.nfaces = N + 1;
+                    tl.stage = st + 1; tl.inv_dx = inv_dx; tl.dt = dt;
+                    for (int i0 = 0; i0 < N; i0 += T) {
+                        stage1d_tile<R, T, NT, MODE_FUSED_1D>(tl, i0, mc, L);
+                        __syncthreads();
+                    }
                 }
             }
         }
+        if constexpr (PH == ASE_ADJ_REVERSE) {
+            // reverse sweep
+            double *lam = a.lam + off, *mu1 = a.mu1 + off, *mu2 = a.mu2 + off;
+            for (int q = nact - 1; q >= 0; --q) {
+                const double dt = a.dt_hist[(long long)q * a.ninst + k];
+                AdjTile t;
+                t.plane = P; t.N = N; t.ng = a.ng; t.inv_dx = inv_dx;
+                t.a1 = t.a2 = nullptr;
+                t.c1 = t.c2 = 0.0;
+                // stage 3
+                t.V = a.tapeU + (3LL * q + 2) * SU + off;
+                t.S = a.tapeS + (3LL * q + 2) * P + off;
+                t.g = lam; t.gscale = (2.0 / 3.0) * dt;
+                t.a0 = lam; t.c0 = 2.0 / 3.0;
+                t.out = mu2;
+                adj_stage<R, T, NT>(t, mc, L, bc);
+                // stage 2
+                t.V = a.tapeU + (3LL * q + 1) * SU + off;
+                t.S = a.tapeS + (3LL * q + 1) * P + off;
+                t.g = mu2; t.gscale = 0.25 * dt;
+                t.a0 = mu2; t.c0 = 0.25;
+                t.out = mu1;
+                adj_stage<R, T, NT>(t, mc, L, bc);
+                // stage 1
+                t.V = a.tapeU + (3LL * q) * SU + off;
+                t.S = a.tapeS + (3LL * q) * P + off;
+                t.g = mu1; t.gscale = dt;
+                t.a0 = lam; t.c0 = 1.0 / 3.0;
+                t.a1 = mu2; t.c1 = 0.75;
+                t.a2 = mu1; t.c2 = 1.0;
+                t.out = lam;
+                adj_stage<R, T, NT>(t, mc, L, bc);
+            }
+            // ghost slots of the result carry no meaning: clear them
+            for (int kk = tid; kk < 2 * a.ng; kk += NT) {
+                const int I = kk < a.ng ? kk : N + kk;
+    #pragma unroll
+                for (int v = 0; v < 3; ++v) lam[v * P + I] = 0.0;
+            }
+            __syncthreads();
         }
-        if (!(a.phase & ASE_ADJ_REVERSE)) continue;
-
-        // reverse sweep
-        double *lam = a.lam + off, *mu1 = a.mu1 + off, *mu2 = a.mu2 + off;
-        for (int q = nact - 1; q >= 0; --q) {
-            const double dt = a.dt_hist[(long long)q * a.ninst + k];
-            AdjTile t;
-            t.plane = P; t.N = N; t.ng = a.ng; t.inv_dx = inv_dx;
-            t.a1 = t.a2 = nullptr;
-            t.c1 = t.c2 = 0.0;
-            // stage 3
-            t.V = a.tapeU + (3LL * q + 2) * SU + off;
-            t.S = a.tapeS + (3LL * q + 2) * P + off;
-            t.g = lam; t.gscale = (2.0 / 3.0) * dt;
-            t.a0 = lam; t.c0 = 2.0 / 3.0;
-            t.out = mu2;
-            adj_stage<R, T, NT>(t, mc, L.b, bc);
-            // stage 2
-            t.V = a.tapeU + (3LL * q + 1) * SU + off;
-            t.S = a.tapeS + (3LL * q + 1) * P + off;
-            t.g = mu2; t.gscale = 0.25 * dt;
-            t.a0 = mu2; t.c0 = 0.25;
-            t.out = mu1;
-            adj_stage<R, T, NT>(t, mc, L.b, bc);
-            // stage 1
-            t.V = a.tapeU + (3LL * q) * SU + off;
-            t.S = a.tapeS + (3LL * q) * P + off;
-            t.g = mu1; t.gscale = dt;
-            t.a0 = lam; t.c0 = 1.0 / 3.0;
-            t.a1 = mu2; t.c1 = 0.75;
-            t.a2 = mu1; t.c2 = 1.0;
-            t.out = lam;
-            adj_stage<R, T, NT>(t, mc, L.b, bc);
-        }
-        // ghost slots of the result carry no meaning: clear them
-        for (int kk = tid; kk < 2 * a.ng; kk += NT) {
-            const int I = kk < a.ng ? kk : N + kk;
-#pragma unroll
-            for (int v = 0; v < 3; ++v) lam[v * P + I] = 0.0;
-        }
-        __syncthreads();
     }
 }
 
@@ -2055,7 +2058,15 @@ void launch_adjoint(const AdjLaunch &al, hipStream_t st)
     a.phase = al.phase;
     a.mc = al.mc;
     const int nblk = al.bin_start ? al.nbins : al.ninst;
-#define ASE_ADJ(RR, NTT) k_adjoint1d<RR, NTT><<<nblk, NTT, 0, st>>>(a)
+    // the tape of every instance, then the reverse sweep of every instance
+    // (instances are independent: the same results as one phase after the
+    // other per instance)
+#define ASE_ADJ(RR, NTT)                                                                         \
+    do {                                                                                         \
+        if (al.phase & ASE_ADJ_TAPE) k_adjoint1d<RR, NTT, ASE_ADJ_TAPE><<<nblk, NTT, 0, st>>>(a); \
+        if (al.phase & ASE_ADJ_REVERSE)                                                          \
+            k_adjoint1d<RR, NTT, ASE_ADJ_REVERSE><<<nblk, NTT, 0, st>>>(a);                      \
+    } while (0)
     if (al.threads == 128) {
         switch (al.R) {
         case 1: ASE_ADJ(1, 128); break;
