@@ -27,9 +27,9 @@ METRIC = "Mcell-updates/s, 9th-order 2D ASE step (FP64) + % HBM roofline; adjoin
 # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy (summary in
 # profiles/k_sweep2d_quad1024_r9.md, 1024^2 and 4096^2).  Valid only for the kernel sources with
 # this fingerprint; once they change the bench reports traffic as null.
-MEASURED_TRAFFIC = {"fingerprint": "1b45387da80409a0", "workloads": ("quad1024", "quad4096"),
-                    "quad1024": {"sweep_x": 87917985, "sweep_y": 145330802},
-                    "quad4096": {"sweep_x": 1752534685, "sweep_y": 2785175578}}
+MEASURED_TRAFFIC = {"fingerprint": "ed3f7674a45ab11d", "workloads": ("quad1024", "quad4096"),
+                    "quad1024": {"sweep_x": 88271665, "sweep_y": 145297094},
+                    "quad4096": {"sweep_x": 1752572188, "sweep_y": 2782968192}}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
@@ -56,7 +56,10 @@ def alg_flops_per_cell_sweep(order: int, dim: int, lagged: bool = False) -> floa
       flux difference         : 4 vars x 2
     With the first-order DF source the strengths are the cell-average ones,
     formed outside the sweeps (per cell one set of primitives and the
-    strengths of its two faces).
+    strengths of its two faces).  The count is the method's direct form: the
+    kernels evaluate the linear levels at three or four Gauss points in mirror
+    pairs (r = 9: 44 instead of 68 operations per variable and side), so they
+    execute fewer operations than counted here for the tangential part.
     """
     R = (order - 1) // 2
     sums = {1: 1, 2: 3, 3: 8, 4: 15}[R]
