@@ -300,7 +300,11 @@ __global__ void __launch_bounds__(TX * TY) k_fill_fo(BCInfo b, MethodConst mc, d
     __shared__ bool sok[TY + 1][TX + 1];
     __shared__ double red[NT / 64];
     const int NYs = b.dim == 1 ? 1 : b.NY;
-    const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TY;
+    // tiles in contiguous bands per XCD: the extra column and row a tile
+    // reads are then mostly in its own L2
+    int btx, bty;
+    xcd_tile(btx, bty);
+    const int I0 = btx * TX, J0 = bty * TY;
     double lam = 0.0;
     // all loads of a lane first, then the primitive variables
     double W[NI][NV];
