@@ -25,9 +25,9 @@ METRIC = "Mcell-updates/s, 9th-order 2D ASE step (FP64) + % HBM roofline; adjoin
 
 # HBM bytes per launch of the two sweep kernels on the default workload, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy (summary in
-# profiles/k_sweep2d_quad1024_r9.md, 1024^2 and 4096^2).  Valid only for the kernel sources with
-# this fingerprint; once they change the bench reports traffic as null.
-MEASURED_TRAFFIC = {"fingerprint": "ed3f7674a45ab11d", "workloads": ("quad1024", "quad4096"),
+# profiles/k_sweep2d_quad1024_r9.md, 1024^2 and 4096^2).  Valid only for the sweep kernel sources
+# with this fingerprint (kernel_fingerprint); once they change the bench reports traffic as null.
+MEASURED_TRAFFIC = {"fingerprint": "926046370baada12", "workloads": ("quad1024", "quad4096"),
                     "quad1024": {"sweep_x": 88271665, "sweep_y": 145297094},
                     "quad4096": {"sweep_x": 1752572188, "sweep_y": 2782968192}}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
@@ -35,10 +35,23 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
 
 def kernel_fingerprint() -> str:
+    """Hash of what the two sweep kernels compile from: the device helpers,
+    the sweep arguments, the text of the sweep kernel itself and the
+    compiler flags (the other kernels of the library do not enter)."""
+    from paper_2410_05489_amd import build as B
+    csrc = os.path.join(ROOT, "paper_2410_05489_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("ase_kernels.hip", "ase_device.h"):
-        with open(os.path.join(ROOT, "paper_2410_05489_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "ase_device.h"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "ase_host.h")) as fh:
+        host = fh.read()
+    i = host.index("enum SweepMode")
+    h.update(host[i:host.index("};", host.index("struct SweepArgs")) + 2].encode())
+    with open(os.path.join(csrc, "ase_kernels.hip")) as fh:
+        k = fh.read()
+    i = k.index("// 2D sweep: one tile of T0 x T1 cells")
+    h.update(k[i:k.index("\n}\n", k.index("k_sweep2d(SweepArgs a)")) + 3].encode())
+    h.update(" ".join(B.HIP_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
