@@ -578,6 +578,10 @@ def main():
                                            "df_source": "lagged" if lagged else "first_order",
                                            "positivity_fallback": bool(p.positivity_fallback)},
            "finite": finite, "roofline": roof}
+    if args.workload == "jet":
+        # the method as read does not carry this case through its 500 steps
+        out["config"]["full_run"] = ("fails: a cell-average pressure turns negative at step 182 of 500 "
+                                     "(oracle and GPU alike); timed over the first steps only")
     if not args.no_adjoint:
         progress("adjoint/forward ratio on the batched workload")
         out["adjoint"] = measure_adjoint()
