@@ -340,13 +340,15 @@ def test_ragged_and_tiny_grids():
         assert rel_err(g.interior(Ug), g.interior(Uo)) < 1e-12, (nx, ny)
 
 
-@pytest.mark.parametrize("name", ["quad1024", "jet1600", "dmr960"])
+@pytest.mark.parametrize("name", ["quad1024", "quad4096", "jet1600", "dmr960"])
 def test_full_size_one_step(name):
-    """Bench sizes (1024^2 r=9 four-quadrant; 1600x800 r=7 jet; 960x240 r=9
-    double Mach reflection), one step through ase_step from an identical
-    state, every cell compared."""
+    """Bench sizes (1024^2 and 4096^2 r=9 four-quadrant; 1600x800 r=7 jet;
+    960x240 r=9 double Mach reflection), one step through ase_step from an
+    identical state, every cell compared."""
     if name == "quad1024":
         w = WL.four_quadrant(1024, 9, seed=0)
+    elif name == "quad4096":
+        w = WL.four_quadrant(4096, 9, seed=0)
     elif name == "dmr960":
         w = WL.double_mach(960, 240, 9)
     else:
