@@ -451,12 +451,16 @@ struct InflowSpeed {
     double inv_dx, inv_dy;
 };
 
-__global__ void __launch_bounds__(kThreads) k_cfl_final(const double *part, int nparts, double cfl, double dt_cap,
-                                                        const double *t_in, double *t_out, double t_end,
-                                                        double *dt_out, double *skip_out, double *dt_hist,
-                                                        InflowSpeed inf, MethodConst mc)
+// One workgroup of kFinalThreads lanes (a lane's loads in flight cover the
+// partials of a 1024^2 grid's fill tiles in one round).
+constexpr int kFinalThreads = 1024;
+
+__global__ void __launch_bounds__(kFinalThreads) k_cfl_final(const double *part, int nparts, double cfl,
+                                                             double dt_cap, const double *t_in, double *t_out,
+                                                             double t_end, double *dt_out, double *skip_out,
+                                                             double *dt_hist, InflowSpeed inf, MethodConst mc)
 {
-    __shared__ double red[kThreads];
+    __shared__ double red[kFinalThreads / 64];
     double lam = 0.0;
     if (threadIdx.x == 0 && inf.on) {
         // inflow ghost states enter the domain: their signal speed counts too
@@ -474,28 +478,30 @@ __global__ void __launch_bounds__(kThreads) k_cfl_final(const double *part, int 
     }
     // eight loads in flight per lane (the partials are >= 0, so a padding 0
     // leaves the maximum as it is)
-    for (int k0 = threadIdx.x; k0 < nparts; k0 += 8 * kThreads) {
+    for (int k0 = threadIdx.x; k0 < nparts; k0 += 8 * kFinalThreads) {
         double pv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u * kThreads;
+            const int k = k0 + u * kFinalThreads;
             pv[u] = k < nparts ? part[k] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) lam = max_nan(lam, pv[u]);
     }
-    red[threadIdx.x] = lam;
+    // the maximum is exact and NaN-sticky in any order: lanes, then waves
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lam = max_nan(lam, __shfl_xor(lam, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
     __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] = max_nan(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int w = 1; w < kFinalThreads / 64; ++w) m = max_nan(m, red[w]);
         const double t = *t_in;
         const bool skip = t_end > 0.0 && t >= t_end;
         double dt = 0.0;
         if (!skip) {
-            dt = cfl / red[0];
+            dt = cfl / m;
             if (dt_cap > 0.0 && dt > dt_cap) dt = dt_cap;
             if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
         }
@@ -1914,8 +1920,8 @@ void launch_cfl_final(const ase_grid_t &g, const Geo &geo, const ase_params_t &p
     for (int k = 0; k < 4; ++k) inf.W[k] = g.inflow[k];
     inf.inv_dx = 1.0 / g.dx;
     inf.inv_dy = geo.dim == 2 ? 1.0 / g.dy : 0.0;
-    k_cfl_final<<<1, kThreads, 0, st>>>(part, nparts, p.cfl, p.dt_cap, t_in, t_out, t_end, dt, skip, dt_hist, inf,
-                                        mc);
+    k_cfl_final<<<1, kFinalThreads, 0, st>>>(part, nparts, p.cfl, p.dt_cap, t_in, t_out, t_end, dt, skip, dt_hist,
+                                             inf, mc);
 }
 
 void launch_cfl(const ase_grid_t &g, const Geo &geo, const ase_params_t &p, const MethodConst &mc, const double *U,
