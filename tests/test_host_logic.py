@@ -72,3 +72,30 @@ def test_batched_plan_rejects_bad_arguments():
     assert L.ase_batched_plan(3, None, 3, start, lst) == -1
     assert L.ase_batched_plan(3, nc, 3, None, lst) == -1
     assert L.ase_batched_plan(-1, nc, 3, start, lst) == -1
+
+
+def test_traffic_fingerprint_follows_only_the_sweep_sources(tmp_path, monkeypatch):
+    """bench.py reports the measured sweep traffic only while the sources the
+    sweep kernel compiles from are unchanged: edits elsewhere in the kernel
+    file leave the fingerprint alone, edits to the sweep or to the device
+    helpers change it."""
+    import os
+    import shutil
+
+    import bench
+
+    src = os.path.join(bench.ROOT, "paper_2410_05489_amd", "csrc")
+    csrc = tmp_path / "paper_2410_05489_amd" / "csrc"
+    shutil.copytree(src, csrc)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    f0 = bench.kernel_fingerprint()
+    k = csrc / "ase_kernels.hip"
+    text = k.read_text()
+    k.write_text(text.replace("k_fill_fo(BCInfo b,", "k_fill_fo(BCInfo  b,", 1))
+    assert bench.kernel_fingerprint() == f0
+    k.write_text(text.replace("k_sweep2d(SweepArgs a)\n{", "k_sweep2d(SweepArgs a)\n{ ", 1))
+    assert bench.kernel_fingerprint() != f0
+    k.write_text(text)
+    d = csrc / "ase_device.h"
+    d.write_text(d.read_text() + "\n")
+    assert bench.kernel_fingerprint() != f0
