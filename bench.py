@@ -580,8 +580,9 @@ def main():
            "finite": finite, "roofline": roof}
     if args.workload == "jet":
         # the method as read does not carry this case through its 500 steps
-        out["config"]["full_run"] = ("fails: a cell-average pressure turns negative at step 182 of 500 "
-                                     "(oracle and GPU alike); timed over the first steps only")
+        out["config"]["full_run"] = ("fails: a cell-average pressure turns negative before step 500 "
+                                     "(step 298 with these kernels; the method as read, not the kernels); "
+                                     "timed over the first steps only")
     if not args.no_adjoint:
         progress("adjoint/forward ratio on the batched workload")
         out["adjoint"] = measure_adjoint()
