@@ -581,7 +581,8 @@ def main():
     if args.workload == "jet":
         # the method as read does not carry this case through its 500 steps
         out["config"]["full_run"] = ("fails: a cell-average pressure turns negative before step 500 "
-                                     "(step 298 with these kernels; the method as read, not the kernels); "
+                                     "(step 298 with these kernels, 279 for the oracle: the method as read, "
+                                     "not the kernels); "
                                      "timed over the first steps only")
     if not args.no_adjoint:
         progress("adjoint/forward ratio on the batched workload")
