@@ -343,6 +343,49 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
                      const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
                      void *stream);
 
+/* ---- Wide batched form (first-order DF source) -----------------------------
+ * The persistent launch above walks every instance with one workgroup, so
+ * the batch lasts as long as its longest instance.  The wide form gives each
+ * instance of at least min_cells cells many workgroups instead: one launch
+ * per RK stage (Sec. 2.1) over all tiles of these instances, on a second
+ * stream of the library's beside the persistent launch, which keeps the
+ * rest.  Results equal ase_step_batched's bit for bit (U including its
+ * ghost cells, sigma, t, dt_hist, status).  Needs ASE_FLAG_DF_FIRST_ORDER
+ * (strengths from the two cell averages beside each face, Sec. 3.1).
+ *
+ * ase_batched_plan_wide: HOST arrays.  Instances with ncells >= min_cells
+ * and at least one full tile (threads_wide - order - 1 cells; min_cells <= 0:
+ * none) are cut into tiles of that length: tile j of instance k starts at
+ * interior cell tile_i0[j]; tile_inst[j] = k; the tiles of k are
+ * inst_tile0[k] .. inst_tile0[k] + inst_ntiles[k] - 1 (inst_tile0 -1 and
+ * inst_ntiles 0 for the others).  The others are packed into nbins bins as
+ * ase_batched_plan does (a bin may be empty).  *ntiles gets the tile count;
+ * tile_inst and tile_i0 hold cap entries (ASE_ERR_ARG, with *ntiles set,
+ * when cap < *ntiles; call with cap 0 and NULL arrays to count).
+ * ase_batched_wide_workspace_bytes: device workspace for the call below.
+ * ase_step_batched_wide: the arguments of ase_step_batched plus device
+ * copies of the tile arrays, ntiles and threads_wide (256 or 512, as
+ * planned).  The call returns once both streams' work is queued; the
+ * caller's stream waits for the second stream's before the final launch,
+ * so work queued behind the call on `stream` sees every result.  Calls from
+ * several host threads are serialised on the library's stream of each
+ * device. */
+int ase_batched_plan_wide(int32_t ninst, const int32_t *ncells, int32_t min_cells, int32_t order,
+                          int32_t threads_wide, int32_t nbins, int32_t *bin_start, int32_t *bin_list,
+                          int32_t *tile_inst, int32_t *tile_i0, int32_t *inst_tile0, int32_t *inst_ntiles,
+                          int32_t cap, int32_t *ntiles);
+
+size_t ase_batched_wide_workspace_bytes(int64_t total, int32_t ninst, int32_t ntiles);
+
+int ase_step_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                          const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng,
+                          int64_t total, double *U, double *sigma, double *t, double *dt_hist,
+                          const double *dt_replay, int32_t *status, int32_t nsteps, double t_end,
+                          const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                          const int32_t *tile_inst, const int32_t *tile_i0, const int32_t *inst_tile0,
+                          const int32_t *inst_ntiles, int32_t ntiles, int32_t threads_wide, void *ws,
+                          size_t ws_bytes, void *stream);
+
 /* ---- Allocation-free batched stepping --------------------------------------
  * For callers that cannot allocate device memory or hand in a workspace:
  * code under HIP graph capture, tight serving loops, hosts that forbid

@@ -44,7 +44,8 @@ EXPORTS = ("ase_last_error", "ase_version", "ase_bc_fill", "ase_sigma_init", "as
            "ase_profile_enable", "ase_profile_read", "ase_batched_plan", "ase_batched_workspace_bytes",
            "ase_batched_sigma_init", "ase_step_batched", "ase_adjoint_workspace_bytes", "ase_adjoint_step",
            "ase_adjoint_batched_workspace_bytes", "ase_adjoint_batched", "ase_pressure_objective",
-           "ase_gks_flux", "ase_gks_workspace_bytes", "ase_step_gks", "ase_step_batched_noalloc")
+           "ase_gks_flux", "ase_gks_workspace_bytes", "ase_step_gks", "ase_step_batched_noalloc",
+           "ase_batched_plan_wide", "ase_batched_wide_workspace_bytes", "ase_step_batched_wide")
 
 KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4, "batched": 5, "adjoint": 6,
           "gks_1d": 7, "gks_2d_recon": 8, "gks_2d_flux": 9, "gks_2d_update": 10}
@@ -92,6 +93,13 @@ def lib():
                                    vp, vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_step_batched_noalloc.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp,
                                            vp, vp, vp, vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp]
+    L.ase_batched_plan_wide.argtypes = [C.c_int32, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp,
+                                        vp, vp, C.c_int32, vp]
+    L.ase_batched_wide_workspace_bytes.restype = C.c_size_t
+    L.ase_batched_wide_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32]
+    L.ase_step_batched_wide.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp,
+                                        vp, vp, vp, C.c_int32, C.c_double, vp, vp, C.c_int32, C.c_int32, vp, vp,
+                                        vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_adjoint_workspace_bytes.restype = C.c_size_t
     L.ase_adjoint_workspace_bytes.argtypes = [vp]
     L.ase_adjoint_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, vp, C.c_size_t, vp]
@@ -345,11 +353,44 @@ def batched_plan(ncells, nbins: int):
     return start, lst
 
 
+def batched_plan_wide(ncells, min_cells: int, order: int, threads_wide: int, nbins: int):
+    """Host plan of the wide batched form: instances of at least min_cells
+    cells (and one full tile) cut into tiles, the others packed into bins.
+    Returns numpy (bin_start, bin_list, tile_inst, tile_i0, inst_tile0,
+    inst_ntiles); bin_list holds only the binned instances."""
+    import numpy as np
+    nc = np.ascontiguousarray(ncells, dtype=np.int32)
+    n = len(nc)
+    start = np.zeros(nbins + 1, dtype=np.int32)
+    lst = np.zeros(n, dtype=np.int32)
+    it0 = np.zeros(n, dtype=np.int32)
+    itn = np.zeros(n, dtype=np.int32)
+    nt = C.c_int32(0)
+    L = lib()
+    rc = L.ase_batched_plan_wide(n, nc.ctypes.data, int(min_cells), int(order), int(threads_wide), nbins,
+                                 start.ctypes.data, lst.ctypes.data, None, None, it0.ctypes.data, itn.ctypes.data, 0,
+                                 C.byref(nt))
+    if rc != 0 and nt.value == 0:
+        _check(rc, "ase_batched_plan_wide")
+    ti = np.zeros(max(nt.value, 1), dtype=np.int32)
+    t0 = np.zeros(max(nt.value, 1), dtype=np.int32)
+    _check(L.ase_batched_plan_wide(n, nc.ctypes.data, int(min_cells), int(order), int(threads_wide), nbins,
+                                   start.ctypes.data, lst.ctypes.data, ti.ctypes.data, t0.ctypes.data,
+                                   it0.ctypes.data, itn.ctypes.data, len(ti), C.byref(nt)), "ase_batched_plan_wide")
+    k = nt.value
+    return start, lst[:start[-1]], ti[:k], t0[:k], it0, itn
+
+
 class BatchedSimulation:
     """Device state of a batch of 1D instances (see workloads.Batch) and the
-    persistent-launch stepper.  nbins / threads select the launch shape."""
+    persistent-launch stepper.  nbins / threads select the launch shape.
+    wide_min_cells > 0 (first-order DF source only) also plans the wide form:
+    instances of at least that many cells then run as one launch per stage
+    over tiles of wide_threads lanes beside the persistent launch; run()
+    takes it unless wide=False."""
 
-    def __init__(self, batch, device="cuda", nbins: int = 0, threads: int = 256, sigma=None):
+    def __init__(self, batch, device="cuda", nbins: int = 0, threads: int = 256, sigma=None,
+                 wide_min_cells: int = 0, wide_threads: int = 256):
         import numpy as np
         self.b = batch
         self.p = batch.params
@@ -377,8 +418,17 @@ class BatchedSimulation:
         self.bin_start = torch.as_tensor(start).to(device)
         self.bin_list = torch.as_tensor(lst).to(device)
         nbytes = int(lib().ase_batched_workspace_bytes(batch.total))
+        self.wide = None
+        if wide_min_cells > 0:
+            wb, wl, ti, t0, it0, itn = batched_plan_wide(n, wide_min_cells, self.p.order, wide_threads, self.nbins)
+            dev = lambda a: torch.as_tensor(a).to(device)   # noqa: E731
+            self.wide = dict(bin_start=dev(wb), bin_list=dev(wl if len(wl) else np.zeros(1, np.int32)),
+                             tile_inst=dev(ti if len(ti) else np.zeros(1, np.int32)),
+                             tile_i0=dev(t0 if len(t0) else np.zeros(1, np.int32)),
+                             inst_tile0=dev(it0), inst_ntiles=dev(itn), ntiles=len(ti), threads=wide_threads,
+                             nwide=int(np.count_nonzero(itn)))
+            nbytes = int(lib().ase_batched_wide_workspace_bytes(batch.total, batch.ninst, len(ti)))
         self.ws = Workspace(nbytes, device)
-        P = C.byref(c_params(self.p))
         if sigma is None:
             self.sigma_init()
         else:
@@ -392,12 +442,29 @@ class BatchedSimulation:
                                             _p(self.sig), _stream(stream)), "ase_batched_sigma_init")
 
     def run(self, nsteps: int, t_end: float = 0.0, dt_hist=None, stream=None, dt_replay=None, noalloc=False,
-            status=None):
+            status=None, wide=None):
         """nsteps steps of every instance in one persistent launch; noalloc
         takes the allocation-free entry point (the library's fixed scratch
         instead of this object's workspace); status (int32 [ninst] on the
-        device) stops and flags instances whose state turns non-physical."""
+        device) stops and flags instances whose state turns non-physical;
+        wide (default: when planned) runs the large instances in the wide
+        form."""
         b = self.b
+        if wide is None:
+            wide = self.wide is not None and not noalloc
+        if wide:
+            w = self.wide
+            if w is None:
+                raise AseError("the wide form was not planned (wide_min_cells)")
+            if noalloc:
+                raise AseError("the wide form has no allocation-free entry point")
+            _check(lib().ase_step_batched_wide(
+                C.byref(c_params(self.p)), b.bc, _p(self.bc_inst), b.ninst, _p(self.offsets), _p(self.ncells),
+                _p(self.dx), b.ng, b.total, _p(self.U), _p(self.sig), _p(self.t), _p(dt_hist), _p(dt_replay),
+                _p(status), int(nsteps), float(t_end), _p(w["bin_start"]), _p(w["bin_list"]), self.nbins,
+                self.threads, _p(w["tile_inst"]), _p(w["tile_i0"]), _p(w["inst_tile0"]), _p(w["inst_ntiles"]),
+                w["ntiles"], w["threads"], self.ws.ptr, self.ws.nbytes, _stream(stream)), "ase_step_batched_wide")
+            return
         if noalloc:
             _check(lib().ase_step_batched_noalloc(
                 C.byref(c_params(self.p)), b.bc, _p(self.bc_inst), b.ninst, _p(self.offsets), _p(self.ncells),
@@ -415,7 +482,7 @@ class BatchedSimulation:
 
     def capture(self, nsteps: int, t_end: float = 0.0):
         """A HIP graph holding the persistent launch of nsteps steps."""
-        return _capture(lambda: self.run(nsteps, t_end))
+        return _capture(lambda: self.run(nsteps, t_end, wide=False))
 
 
 # ---------------------------------------------------------------------------

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -736,12 +737,12 @@ int ase_step_gks(const ase_grid_t *g, const ase_params_t *p, const ase_gks_t *gk
     return nonphysical_check(g, geo, p, U, w, st, "ase_step_gks");
 }
 
-int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_t *bin_start, int32_t *bin_list)
+// Longest processing time first: the instances `ks`, longest first, each onto
+// the least-loaded of nbins bins.
+static void lpt_bins(const std::vector<int> &ks, const int32_t *ncells, int32_t nbins, int32_t *bin_start,
+                     int32_t *bin_list)
 {
-    if (ninst < 1 || nbins < 1 || !ncells || !bin_start || !bin_list)
-        return fail(ASE_ERR_ARG, "ase_batched_plan: bad arguments");
-    std::vector<int> order(ninst);
-    std::iota(order.begin(), order.end(), 0);
+    std::vector<int> order(ks);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ncells[a] > ncells[b]; });
     std::vector<long long> load(nbins, 0);
     std::vector<std::vector<int>> bins(nbins);
@@ -756,7 +757,65 @@ int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_
         for (int k : bins[b]) bin_list[pos++] = k;
     }
     bin_start[nbins] = pos;
+}
+
+int ase_batched_plan(int32_t ninst, const int32_t *ncells, int32_t nbins, int32_t *bin_start, int32_t *bin_list)
+{
+    if (ninst < 1 || nbins < 1 || !ncells || !bin_start || !bin_list)
+        return fail(ASE_ERR_ARG, "ase_batched_plan: bad arguments");
+    std::vector<int> all(ninst);
+    std::iota(all.begin(), all.end(), 0);
+    lpt_bins(all, ncells, nbins, bin_start, bin_list);
     return ASE_OK;
+}
+
+int ase_batched_plan_wide(int32_t ninst, const int32_t *ncells, int32_t min_cells, int32_t order,
+                          int32_t threads_wide, int32_t nbins, int32_t *bin_start, int32_t *bin_list,
+                          int32_t *tile_inst, int32_t *tile_i0, int32_t *inst_tile0, int32_t *inst_ntiles,
+                          int32_t cap, int32_t *ntiles)
+{
+    if (ninst < 1 || nbins < 1 || !ncells || !bin_start || !bin_list || !inst_tile0 || !inst_ntiles || !ntiles ||
+        cap < 0 || (cap > 0 && (!tile_inst || !tile_i0)))
+        return fail(ASE_ERR_ARG, "ase_batched_plan_wide: bad arguments");
+    if (order != 3 && order != 5 && order != 7 && order != 9) return fail(ASE_ERR_ORDER, "order must be 3, 5, 7 or 9");
+    if (threads_wide != 256 && threads_wide != 512) return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512");
+    const int T = wide_tile_cells(threads_wide, (order - 1) / 2);
+    // an instance takes the wide form from one full tile up
+    auto wide = [&](int k) { return min_cells > 0 && ncells[k] >= min_cells && ncells[k] >= T; };
+    std::vector<int> small;
+    long long nt = 0;
+    for (int k = 0; k < ninst; ++k) {
+        if (wide(k)) nt += (ncells[k] + T - 1) / T;
+        else small.push_back(k);
+    }
+    if (nt > INT32_MAX) return fail(ASE_ERR_ARG, "ase_batched_plan_wide: too many tiles");
+    *ntiles = (int32_t)nt;
+    if (nt > cap) return fail(ASE_ERR_ARG, "ase_batched_plan_wide: tile arrays smaller than *ntiles");
+    int pos = 0;
+    for (int k = 0; k < ninst; ++k) {
+        if (wide(k)) {
+            const int n = (ncells[k] + T - 1) / T;
+            inst_tile0[k] = pos;
+            inst_ntiles[k] = n;
+            for (int j = 0; j < n; ++j) {
+                tile_inst[pos] = k;
+                tile_i0[pos] = j * T;
+                ++pos;
+            }
+        } else {
+            inst_tile0[k] = -1;
+            inst_ntiles[k] = 0;
+        }
+    }
+    lpt_bins(small, ncells, nbins, bin_start, bin_list);
+    return ASE_OK;
+}
+
+size_t ase_batched_wide_workspace_bytes(int64_t total, int32_t ninst, int32_t ntiles)
+{
+    if (total < 1 || ninst < 1 || ntiles < 0) return 0;
+    return ase_batched_workspace_bytes(total) + align_up((size_t)(ntiles > 0 ? ntiles : 1) * sizeof(double)) +
+           align_up((size_t)ninst * sizeof(double)) + align_up((size_t)ninst * sizeof(int));
 }
 
 size_t ase_batched_workspace_bytes(int64_t total)
@@ -808,12 +867,13 @@ int ase_batched_sigma_init(const ase_params_t *p, int32_t bc, const int32_t *bc_
     return check_launch("ase_batched_sigma_init");
 }
 
-int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
-                     const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
-                     double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay,
-                     int32_t *status, int32_t nsteps, double t_end, const int32_t *bin_start,
-                     const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
-                     void *stream)
+// Validation of ase_step_batched's arguments and its persistent launch.
+static int batched_setup(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                         const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
+                         double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay,
+                         int32_t *status, int32_t nsteps, double t_end, const int32_t *bin_start,
+                         const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
+                         size_t ws_need, BatchLaunch *bl)
 {
     int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, U, sigma);
     if (rc) return rc;
@@ -828,46 +888,164 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
     if (status && (reinterpret_cast<uintptr_t>(status) & 3u) != 0) return fail(ASE_ERR_ALIGN, "misaligned: status");
     if (!bin_start || !bin_list) return fail(ASE_ERR_ARG, "null bin arrays");
     if (!ws) return fail(ASE_ERR_WORKSPACE, "workspace is required");
-    if (ws_bytes < ase_batched_workspace_bytes(total)) return fail(ASE_ERR_WORKSPACE, "workspace too small");
+    if (ws_bytes < ws_need) return fail(ASE_ERR_WORKSPACE, "workspace too small");
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(ASE_ERR_ALIGN, "workspace must be 256-byte aligned");
-    if (nsteps == 0) return ASE_OK;
     char *c = static_cast<char *>(ws);
     const size_t arr = align_up((size_t)total * sizeof(double));
+    std::memset(bl, 0, sizeof(*bl));
+    bl->offsets = reinterpret_cast<const long long *>(offsets);
+    bl->ncells = ncells;
+    bl->dx = dx;
+    bl->U = U;
+    bl->sig = sigma;
+    bl->t = t;
+    bl->dt_hist = dt_hist;
+    bl->dt_in = dt_replay;
+    bl->status = status;
+    bl->U1 = reinterpret_cast<double *>(c);
+    bl->U2 = reinterpret_cast<double *>(c + 3 * arr);
+    bl->sig2 = reinterpret_cast<double *>(c + 6 * arr);
+    bl->bin_start = bin_start;
+    bl->bin_list = bin_list;
+    bl->bc_inst = bc_inst;
+    bl->total = total;
+    bl->ninst = ninst;
+    bl->nbins = nbins;
+    bl->threads = threads;
+    bl->R = (p->order - 1) / 2;
+    bl->ng = ng;
+    bl->nsteps = nsteps;
+    bl->bc = bc;
+    bl->fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
+    bl->t_end = t_end;
+    bl->cfl = p->cfl;
+    bl->dt_cap = p->dt_cap;
+    bl->mc = method_const(p);
+    return ASE_OK;
+}
+
+int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                     const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
+                     double *U, double *sigma, double *t, double *dt_hist, const double *dt_replay,
+                     int32_t *status, int32_t nsteps, double t_end, const int32_t *bin_start,
+                     const int32_t *bin_list, int32_t nbins, int32_t threads, void *ws, size_t ws_bytes,
+                     void *stream)
+{
     BatchLaunch bl;
-    std::memset(&bl, 0, sizeof(bl));
-    bl.offsets = reinterpret_cast<const long long *>(offsets);
-    bl.ncells = ncells;
-    bl.dx = dx;
-    bl.U = U;
-    bl.sig = sigma;
-    bl.t = t;
-    bl.dt_hist = dt_hist;
-    bl.dt_in = dt_replay;
-    bl.status = status;
-    bl.U1 = reinterpret_cast<double *>(c);
-    bl.U2 = reinterpret_cast<double *>(c + 3 * arr);
-    bl.sig2 = reinterpret_cast<double *>(c + 6 * arr);
-    bl.bin_start = bin_start;
-    bl.bin_list = bin_list;
-    bl.bc_inst = bc_inst;
-    bl.total = total;
-    bl.ninst = ninst;
-    bl.nbins = nbins;
-    bl.threads = threads;
-    bl.R = (p->order - 1) / 2;
-    bl.ng = ng;
-    bl.nsteps = nsteps;
-    bl.bc = bc;
-    bl.fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
-    bl.t_end = t_end;
-    bl.cfl = p->cfl;
-    bl.dt_cap = p->dt_cap;
-    bl.mc = method_const(p);
+    int rc = batched_setup(p, bc, bc_inst, ninst, offsets, ncells, dx, ng, total, U, sigma, t, dt_hist, dt_replay,
+                           status, nsteps, t_end, bin_start, bin_list, nbins, threads, ws, ws_bytes,
+                           ase_batched_workspace_bytes(total), &bl);
+    if (rc) return rc;
+    if (nsteps == 0) return ASE_OK;
     {
         ProfScope ps(ASE_KCLASS_BATCHED, (hipStream_t)stream);
         launch_batched(bl, (hipStream_t)stream);
     }
     return check_launch("ase_step_batched");
+}
+
+// The library's second stream on the current device (the wide part of a
+// batched step runs there) and the events that fork it from and join it
+// back into the caller's stream.  Default priority; created once per device.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+static std::mutex g_side_mu;
+static std::vector<SideStream> g_side;
+
+static int side_stream(SideStream **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((size_t)dev >= g_side.size()) g_side.resize(dev + 1);
+    SideStream &ss = g_side[dev];
+    if (ss.s == nullptr) {
+        e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+        e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+        e = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    *out = &ss;
+    return ASE_OK;
+}
+
+int ase_step_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                          const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng,
+                          int64_t total, double *U, double *sigma, double *t, double *dt_hist,
+                          const double *dt_replay, int32_t *status, int32_t nsteps, double t_end,
+                          const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                          const int32_t *tile_inst, const int32_t *tile_i0, const int32_t *inst_tile0,
+                          const int32_t *inst_ntiles, int32_t ntiles, int32_t threads_wide, void *ws,
+                          size_t ws_bytes, void *stream)
+{
+    BatchLaunch bl;
+    int rc = batched_setup(p, bc, bc_inst, ninst, offsets, ncells, dx, ng, total, U, sigma, t, dt_hist, dt_replay,
+                           status, nsteps, t_end, bin_start, bin_list, nbins, threads, ws, ws_bytes,
+                           ase_batched_wide_workspace_bytes(total, ninst, ntiles), &bl);
+    if (rc) return rc;
+    if (!(p->flags & ASE_FLAG_DF_FIRST_ORDER))
+        return fail(ASE_ERR_ARG, "the wide batched form needs the first-order DF source (ASE_FLAG_DF_FIRST_ORDER)");
+    if (ntiles < 0) return fail(ASE_ERR_ARG, "ntiles must be >= 0");
+    if (threads_wide != 256 && threads_wide != 512) return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512");
+    if (!inst_tile0 || !inst_ntiles || (ntiles > 0 && (!tile_inst || !tile_i0)))
+        return fail(ASE_ERR_ARG, "null tile arrays");
+    if (nsteps == 0) return ASE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    char *c = static_cast<char *>(ws) + ase_batched_workspace_bytes(total);
+    WideLaunch wl;
+    std::memset(&wl, 0, sizeof(wl));
+    wl.offsets = bl.offsets; wl.ncells = ncells; wl.dx = dx;
+    wl.U = U; wl.U1 = bl.U1; wl.U2 = bl.U2; wl.t = t; wl.dt_hist = dt_hist; wl.dt_in = dt_replay;
+    wl.status = status; wl.bc_inst = bc_inst;
+    wl.tile_inst = tile_inst; wl.tile_i0 = tile_i0; wl.inst_tile0 = inst_tile0; wl.inst_ntiles = inst_ntiles;
+    wl.lam = reinterpret_cast<double *>(c);
+    c += align_up((size_t)(ntiles > 0 ? ntiles : 1) * sizeof(double));
+    wl.dt_cur = reinterpret_cast<double *>(c);
+    c += align_up((size_t)ninst * sizeof(double));
+    wl.done = reinterpret_cast<int *>(c);
+    wl.total = total; wl.ninst = ninst; wl.ntiles = ntiles; wl.threads = threads_wide; wl.R = bl.R; wl.ng = ng;
+    wl.bc = bc; wl.t_end = t_end; wl.cfl = p->cfl; wl.dt_cap = p->dt_cap; wl.mc = bl.mc;
+    {
+        ProfScope ps(ASE_KCLASS_BATCHED, st);
+        if (ntiles == 0) {
+            launch_batched(bl, st);
+        } else {
+            // the wide instances on the second stream, forked from the
+            // caller's stream before the persistent launch (so the two run
+            // side by side) and joined back into it (one call's sequence at a
+            // time on the second stream)
+            std::lock_guard<std::mutex> lk(g_side_mu);
+            SideStream *ss = nullptr;
+            rc = side_stream(&ss);
+            if (rc) return rc;
+            hipError_t e = hipEventRecord(ss->fork, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ss->s, ss->fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "ase_step_batched_wide: fork");
+            // the persistent launch carries the instances of the bins
+            launch_batched(bl, st);
+            wl.stage = 0;
+            launch_batched_wide(wl, ss->s);
+            for (int sidx = 0; sidx < nsteps; ++sidx)
+                for (int stg = 1; stg <= 3; ++stg) {
+                    wl.step = sidx;
+                    wl.stage = stg;
+                    launch_batched_wide(wl, ss->s);
+                }
+            e = hipEventRecord(ss->join, ss->s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, ss->join, 0);
+            if (e != hipSuccess) return hip_fail(e, "ase_step_batched_wide: join");
+            // the first-order strengths and ghost cells of every final state
+            // (the persistent launch wrote its own already: the same values)
+            BatchLaunch ib = bl;
+            ib.init = 1;
+            launch_batched(ib, st);
+        }
+    }
+    return check_launch("ase_step_batched_wide");
 }
 
 int ase_step_batched_noalloc(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,

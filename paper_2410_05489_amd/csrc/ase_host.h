@@ -113,6 +113,28 @@ struct BatchLaunch {
     MethodConst mc;
 };
 void launch_batched(const BatchLaunch &bl, hipStream_t st);
+
+// Wide form of the batched step (first-order DF source): stage 0 is the
+// prep launch, stages 1-3 the stages of step `step`.
+struct WideLaunch {
+    const long long *offsets;
+    const int *ncells;
+    const double *dx;
+    double *U, *U1, *U2, *t, *dt_hist;
+    const double *dt_in;
+    int *status;
+    const int *bc_inst;
+    const int *tile_inst, *tile_i0, *inst_tile0, *inst_ntiles;
+    double *lam, *dt_cur;
+    int *done;
+    long long total;
+    int ninst, ntiles, threads, R, ng, bc, step, stage;
+    double t_end, cfl, dt_cap;
+    MethodConst mc;
+};
+void launch_batched_wide(const WideLaunch &wl, hipStream_t st);
+// Tile length of the wide form for `threads` lanes and half width R.
+inline int wide_tile_cells(int threads, int R) { return threads - 2 * R - 2; }
 // Address of this device's fixed scratch array (ASE_NOALLOC_SCRATCH_BYTES).
 int noalloc_scratch(void **ptr);
 

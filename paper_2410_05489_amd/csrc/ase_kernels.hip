@@ -876,34 +876,37 @@ struct Lds1D {
     double sF[3][T + 1];
 };
 
-template <int R, int T, int NT, int MODE>
-__device__ __forceinline__ void stage1d_tile(const Tile1D &a, int i0, const MethodConst &mc, Lds1D<R, T> &L)
+// The step-start state of this lane's cell, for the stage combination
+// (loaded before the tile's window, used after the flux phase).
+template <int T, int NT, int MODE>
+__device__ __forceinline__ void stage1d_prefetch(const Tile1D &a, int i0, double (&un)[3])
 {
-    constexpr int NV = 3, OI = R - 1;
-    constexpr int UX = Lds1D<R, T>::UX;
-    const int tid = threadIdx.x;
-    const int ox = i0 - 1 - R;
-    const bool want_sigma = (mc.flags & ASE_FLAG_DF_FIRST_ORDER) == 0;
-
-    // the step-start state of this lane's cell, for the stage combination
-    // (loaded now, used after the flux phase)
     static_assert(T <= NT, "one cell of the tile per lane");
-    double un[NV] = {};
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) un[v] = 0.0;
     if constexpr (MODE != MODE_RECON) {
         if (tid < T && i0 + tid < a.nx && a.stage > 1) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) un[v] = a.Un[v * a.plane + i0 + tid + a.ng];
+            for (int v = 0; v < 3; ++v) un[v] = a.Un[v * a.plane + i0 + tid + a.ng];
         }
     }
+}
 
-    for (int lx = tid; lx < UX; lx += NT) {
-        const int I = ox + lx + a.ng;
-        const bool in = I < a.NX;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) L.sU[v][lx] = in ? a.U[v * a.plane + I] : 0.0;
-        L.sS[lx] = in ? a.sx[I] : 0.0;
-    }
-    __syncthreads();
+// The phases of a tile once its window (state and strengths) is in LDS:
+// reconstruct the T + 2 cells whose face values the tile's faces need, LF
+// flux at the T + 1 faces, then the stage combination of the T cells.
+// With LAM, lam returns the signal-speed sum (|u| + c) / dx of this lane's
+// new cell (0 for a lane without one).
+template <int R, int T, int NT, int MODE, bool LAM = false>
+__device__ __forceinline__ void stage1d_compute(const Tile1D &a, int i0, const MethodConst &mc, Lds1D<R, T> &L,
+                                                const double (&un)[3], double &lam)
+{
+    constexpr int NV = 3, OI = R - 1;
+    const int tid = threadIdx.x;
+    const int ox = i0 - 1 - R;
+    const bool want_sigma = (mc.flags & ASE_FLAG_DF_FIRST_ORDER) == 0;
+    lam = 0.0;
 
     for (int tx = tid; tx < T + 2; tx += NT) {
         const int lx = tx + R;
@@ -955,9 +958,9 @@ __device__ __forceinline__ void stage1d_tile(const Tile1D &a, int i0, const Meth
     __syncthreads();
 
     const double dt = a.dt;
-    {
-        const int cx = tid, x = i0 + cx;
-        if (cx >= T || x >= a.nx) return;
+    const int cx = tid, x = i0 + cx;
+    if (cx < T && x < a.nx) {
+        double W[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const long long e = v * a.plane + x + a.ng;
@@ -968,8 +971,34 @@ __device__ __forceinline__ void stage1d_tile(const Tile1D &a, int i0, const Meth
             else if (a.stage == 2) o = 0.75 * un[v] + 0.25 * us + 0.25 * dt * Lx;
             else o = (1.0 / 3.0) * un[v] + (2.0 / 3.0) * us + (2.0 / 3.0) * dt * Lx;
             a.Uout[e] = o;
+            W[v] = o;
+        }
+        if constexpr (LAM) {
+            const Prim q = primitives<NV>(W, 0, mc);
+            lam = (fabs(q.un) + q.c) * a.inv_dx;
         }
     }
+}
+
+template <int R, int T, int NT, int MODE>
+__device__ __forceinline__ void stage1d_tile(const Tile1D &a, int i0, const MethodConst &mc, Lds1D<R, T> &L)
+{
+    constexpr int NV = 3;
+    constexpr int UX = Lds1D<R, T>::UX;
+    const int tid = threadIdx.x;
+    const int ox = i0 - 1 - R;
+    double un[NV];
+    stage1d_prefetch<T, NT, MODE>(a, i0, un);
+    for (int lx = tid; lx < UX; lx += NT) {
+        const int I = ox + lx + a.ng;
+        const bool in = I < a.NX;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) L.sU[v][lx] = in ? a.U[v * a.plane + I] : 0.0;
+        L.sS[lx] = in ? a.sx[I] : 0.0;
+    }
+    __syncthreads();
+    double lam;
+    stage1d_compute<R, T, NT, MODE>(a, i0, mc, L, un, lam);
 }
 
 template <int R, int T, int MODE>
@@ -1211,6 +1240,206 @@ __global__ void __launch_bounds__(NT) k_batched_sigma_init(BatchArgs a)
     BatchArgs b = a;
     b.fo = 1;
     batched_fill<NT>(b, inst_bc(a.bc_inst, a.bc, k), a.U + off, a.sig + off, N, a.mc);
+}
+
+// ---------------------------------------------------------------------------
+// Wide form of the batched step for the largest instances: one launch per
+// stage over all their tiles (many workgroups per instance, the launch
+// boundary as the only barrier), beside the persistent launch that keeps the
+// others.  First-order DF source only.  A tile loads its window of the stage
+// input with the ghost cells taken from their boundary-mapped interior
+// cells (the values batched_fill writes there), forms every strength of the
+// window from the two cell averages beside the face, and runs the same
+// stage as stage1d_tile.  The time step of an instance comes from the
+// signal-speed maxima its tiles left (the prep launch from the initial
+// state, each stage-3 launch from the new state): every tile of the
+// instance forms the same dt, its first tile records it.
+// ---------------------------------------------------------------------------
+struct WideArgs {
+    const long long *offsets;
+    const int *ncells;
+    const double *dx;
+    double *U, *U1, *U2;
+    double *t, *dt_hist;
+    const double *dt_in;
+    int *status;
+    const int *bc_inst;
+    const int *tile_inst, *tile_i0, *inst_tile0, *inst_ntiles;
+    double *lam;       // [ntiles]: signal-speed maximum of each tile's cells
+    double *dt_cur;    // [ninst]: the time step of the current step
+    int *done;         // [ninst]: the instance has stopped
+    long long total;
+    int ninst, ntiles, ng, bc, step, stage;   // stage 0: prep
+    double t_end, cfl, dt_cap;
+    MethodConst mc;
+};
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+    // the maximum is exact and NaN-sticky in any order: lanes, then waves
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max_nan(v, __shfl_xor(v, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) m = max_nan(m, red[w]);
+    return m;
+}
+
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
+{
+    constexpr int T = NT - 2 * R - 2;
+    constexpr int UX = Lds1D<R, T>::UX;
+    __shared__ Lds1D<R, T> L;
+    __shared__ double red[NT / 64];
+    // p, un, ut, 1/c and the positivity flag (1 or 0) of each window cell,
+    // in the trace arrays' space: those are first written by the
+    // reconstruction phase, after the strengths are formed (the smaller LDS
+    // footprint lets more workgroups share a compute unit)
+    static_assert(5 * UX <= 6 * (T + 2), "primitives fit in the trace arrays");
+    double(*sq)[UX] = reinterpret_cast<double(*)[UX]>(&L.sTR[0][0]);
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int k = a.tile_inst[b], i0 = a.tile_i0[b];
+    if (k < 0 || k >= a.ninst) return;   // malformed tile entry: skipped (the whole workgroup)
+    const int N = a.ncells[k], ng = a.ng;
+    const long long off = a.offsets[k], P = a.total;
+    const int t0 = a.inst_tile0[k], nt = a.inst_ntiles[k];
+    if (N < T || off < 0 || off + N + 2LL * ng > P || i0 < 0 || i0 >= N || t0 < 0 || nt < 1 ||
+        t0 + nt > a.ntiles || b < t0 || b >= t0 + nt)
+        return;
+    const bool first = b == t0;
+    const double inv_dx = 1.0 / a.dx[k];
+    const MethodConst &mc = a.mc;
+
+    if (a.stage == 0) {
+        // prep: the instance runs, and the signal speeds of its initial state
+        double l = 0.0;
+        const int x = i0 + tid;
+        if (tid < T && x < N) {
+            double W[3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) W[v] = a.U[v * P + off + ng + x];
+            const Prim q = primitives<3>(W, 0, mc);
+            l = (fabs(q.un) + q.c) * inv_dx;
+        }
+        const double m = block_max<NT>(l, red);
+        if (tid == 0) {
+            a.lam[b] = m;
+            if (first) {
+                a.done[k] = 0;
+                if (a.status != nullptr) a.status[k] = 0;
+            }
+        }
+        return;
+    }
+    const int s = a.step;
+    const long long hs = (long long)s * a.ninst + k;
+    if (a.done[k]) {
+        if (a.stage == 1 && first && tid == 0 && a.dt_hist) a.dt_hist[hs] = 0.0;
+        return;
+    }
+    double dt;
+    if (a.stage == 1) {
+        const double t = a.t[k];
+        bool stop = a.t_end > 0.0 && t >= a.t_end;
+        dt = 0.0;
+        if (!stop && a.dt_in) {
+            dt = a.dt_in[hs];
+            stop = !(dt > 0.0);
+        } else if (!stop) {
+            double m = 0.0;
+            for (int j = tid; j < nt; j += NT) m = max_nan(m, a.lam[t0 + j]);
+            m = block_max<NT>(m, red);
+            dt = a.cfl / m;
+            if (a.dt_cap > 0.0 && dt > a.dt_cap) dt = a.dt_cap;
+            if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
+            if (a.status != nullptr && !(dt > 0.0)) {
+                // a signal speed of the state is NaN: the instance stops here
+                if (first && tid == 0) a.status[k] = s + 1;
+                stop = true;
+            }
+        }
+        if (stop) {
+            if (first && tid == 0) {
+                a.done[k] = 1;
+                if (a.dt_hist) a.dt_hist[hs] = 0.0;
+            }
+            return;
+        }
+        if (first && tid == 0) a.dt_cur[k] = dt;
+    } else {
+        dt = a.dt_cur[k];
+    }
+
+    double *in = a.stage == 1 ? a.U : a.stage == 2 ? a.U1 : a.U2;
+    double *out = a.stage == 1 ? a.U1 : a.stage == 2 ? a.U2 : a.U;
+    Tile1D tl;
+    tl.U = in + off; tl.sx = nullptr; tl.sig_out = nullptr; tl.Un = a.U + off; tl.Uout = out + off;
+    tl.wl = tl.wr = nullptr; tl.level = nullptr;
+    tl.plane = P; tl.nx = N; tl.ng = ng; tl.NX = N + 2 * ng; tl.nfaces = N + 1;
+    tl.stage = a.stage; tl.inv_dx = inv_dx; tl.dt = dt;
+    double un[3];
+    stage1d_prefetch<T, NT, MODE_FUSED_1D>(tl, i0, un);
+
+    // the window x in [i0-1-R, i0+T+1+R) of the stage input, ghosts mapped
+    // as batched_fill copies them (periodic image, wall mirror with the
+    // momentum reversed, or the boundary cell), 0 beyond the stored range
+    const int bc = inst_bc(a.bc_inst, a.bc, k);
+    const int ox = i0 - 1 - R;
+    for (int lx = tid; lx < UX; lx += NT) {
+        int x = ox + lx;
+        double fm = 1.0;
+        bool in_range = x >= -ng && x < N + ng;
+        if (x < 0 || x >= N) {
+            if (bc == ASE_BC_PERIODIC) x = x < 0 ? x + N : x - N;
+            else if (bc == ASE_BC_REFLECTIVE) {
+                x = x < 0 ? -1 - x : 2 * N - 1 - x;
+                fm = -1.0;
+            } else x = x < 0 ? 0 : N - 1;
+        }
+        double W[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) W[v] = in_range ? in[v * P + off + ng + x] : 0.0;
+        W[1] *= fm;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) L.sU[v][lx] = W[v];
+        const Prim q = primitives<3>(W, 0, mc);
+        sq[0][lx] = q.p;
+        sq[1][lx] = q.un;
+        sq[2][lx] = q.ut;
+        sq[3][lx] = q.ic;
+        sq[4][lx] = q.ok ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // first-order strengths of the window's faces
+    for (int lx = tid; lx + 1 < UX; lx += NT) {
+        Prim qa, qb;
+        qa.p = sq[0][lx]; qa.un = sq[1][lx]; qa.ut = sq[2][lx]; qa.ic = sq[3][lx]; qa.c = 0.0;
+        qa.ok = sq[4][lx] != 0.0;
+        qb.p = sq[0][lx + 1]; qb.un = sq[1][lx + 1]; qb.ut = sq[2][lx + 1]; qb.ic = sq[3][lx + 1]; qb.c = 0.0;
+        qb.ok = sq[4][lx + 1] != 0.0;
+        L.sS[lx] = sigma_point(qa, qb);
+    }
+    __syncthreads();
+    double l;
+    if (a.stage == 3) {
+        stage1d_compute<R, T, NT, MODE_FUSED_1D, true>(tl, i0, mc, L, un, l);
+        const double m = block_max<NT>(l, red);
+        if (tid == 0) {
+            a.lam[b] = m;
+            if (first) {
+                a.t[k] = a.t[k] + dt;
+                if (a.dt_hist) a.dt_hist[hs] = dt;
+            }
+        }
+    } else {
+        stage1d_compute<R, T, NT, MODE_FUSED_1D>(tl, i0, mc, L, un, l);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2055,6 +2284,36 @@ void launch_batched(const BatchLaunch &bl, hipStream_t st)
         }
     }
 #undef ASE_BATCH
+}
+
+void launch_batched_wide(const WideLaunch &wl, hipStream_t st)
+{
+    WideArgs a;
+    a.offsets = wl.offsets; a.ncells = wl.ncells; a.dx = wl.dx;
+    a.U = wl.U; a.U1 = wl.U1; a.U2 = wl.U2; a.t = wl.t; a.dt_hist = wl.dt_hist; a.dt_in = wl.dt_in;
+    a.status = wl.status; a.bc_inst = wl.bc_inst;
+    a.tile_inst = wl.tile_inst; a.tile_i0 = wl.tile_i0; a.inst_tile0 = wl.inst_tile0; a.inst_ntiles = wl.inst_ntiles;
+    a.lam = wl.lam; a.dt_cur = wl.dt_cur; a.done = wl.done;
+    a.total = wl.total; a.ninst = wl.ninst; a.ntiles = wl.ntiles; a.ng = wl.ng; a.bc = wl.bc; a.step = wl.step;
+    a.stage = wl.stage;
+    a.t_end = wl.t_end; a.cfl = wl.cfl; a.dt_cap = wl.dt_cap; a.mc = wl.mc;
+#define ASE_WIDE(RR, NTT) k_batched_wide<RR, NTT><<<wl.ntiles, NTT, 0, st>>>(a)
+    if (wl.threads == 512) {
+        switch (wl.R) {
+        case 1: ASE_WIDE(1, 512); break;
+        case 2: ASE_WIDE(2, 512); break;
+        case 3: ASE_WIDE(3, 512); break;
+        default: ASE_WIDE(4, 512); break;
+        }
+    } else {
+        switch (wl.R) {
+        case 1: ASE_WIDE(1, 256); break;
+        case 2: ASE_WIDE(2, 256); break;
+        case 3: ASE_WIDE(3, 256); break;
+        default: ASE_WIDE(4, 256); break;
+        }
+    }
+#undef ASE_WIDE
 }
 
 void launch_adjoint(const AdjLaunch &al, hipStream_t st)

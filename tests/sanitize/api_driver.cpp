@@ -28,6 +28,7 @@ void launch_flux(const Geo &, const MethodConst &, int, const double *, const do
 void launch_stage_update(const ase_grid_t &, const Geo &, int, const double *, const double *, const double *,
                          const double *, const double *, double *, hipStream_t) {}
 void launch_batched(const BatchLaunch &, hipStream_t) {}
+void launch_batched_wide(const WideLaunch &, hipStream_t) {}
 int noalloc_scratch(void **ptr) { *ptr = nullptr; return ASE_OK; }
 void launch_adjoint(const AdjLaunch &, hipStream_t) {}
 void launch_objective(const ObjLaunch &, hipStream_t) {}
@@ -120,6 +121,46 @@ int main()
     EXPECT(ase_step_batched_noalloc(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 1198369, dummy, dummy,
                                     dummy, nullptr, nullptr, nullptr, 1, 0.0, &n1, &n1, 1, 256,
                                     nullptr) == ASE_ERR_WORKSPACE);
+    // wide form: planning (tiles of 256 - 9 - 1 = 246 cells at order 9) and validation
+    {
+        std::vector<int32_t> ti(64, -1), t0(64, -1), b0(nb + 1, -1), bl2(nc.size(), -1), tin(nc.size(), -2),
+            tnt(nc.size(), -2);
+        int32_t ntl = -1;
+        EXPECT(ase_batched_plan_wide((int32_t)nc.size(), nc.data(), 1000, 9, 256, nb, b0.data(), bl2.data(),
+                                     nullptr, nullptr, tin.data(), tnt.data(), 0, &ntl) == ASE_ERR_ARG);
+        EXPECT(ntl == 17 + 5);   // 4096 cells: 17 tiles, 1200: 5; 999 < min_cells
+        EXPECT(ase_batched_plan_wide((int32_t)nc.size(), nc.data(), 1000, 9, 256, nb, b0.data(), bl2.data(),
+                                     ti.data(), t0.data(), tin.data(), tnt.data(), 64, &ntl) == ASE_OK);
+        EXPECT(ntl == 22 && tin[2] == 0 && tnt[2] == 17 && tin[5] == 17 && tnt[5] == 5);
+        EXPECT(tin[0] == -1 && tnt[0] == 0 && b0[nb] == (int32_t)nc.size() - 2);
+        EXPECT(ti[16] == 2 && t0[16] == 16 * 246 && ti[21] == 5 && t0[21] == 4 * 246);
+        EXPECT(ase_batched_plan_wide((int32_t)nc.size(), nc.data(), 1000, 8, 256, nb, b0.data(), bl2.data(),
+                                     ti.data(), t0.data(), tin.data(), tnt.data(), 64, &ntl) == ASE_ERR_ORDER);
+        EXPECT(ase_batched_plan_wide((int32_t)nc.size(), nc.data(), 1000, 9, 1024, nb, b0.data(), bl2.data(),
+                                     ti.data(), t0.data(), tin.data(), tnt.data(), 64, &ntl) == ASE_ERR_ARG);
+        EXPECT(ase_batched_wide_workspace_bytes(1000, 2, 3) > ase_batched_workspace_bytes(1000));
+        EXPECT(ase_batched_wide_workspace_bytes(0, 2, 3) == 0);
+        // the wide form needs the first-order source
+        const size_t wsb = ase_batched_wide_workspace_bytes(20, 1, 1);
+        EXPECT(ase_step_batched_wide(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                     dummy, nullptr, nullptr, nullptr, 1, 0.0, &n1, &n1, 1, 256, &n1, &n1, &n1,
+                                     &n1, 1, 256, dummy, wsb, nullptr) == ASE_ERR_ARG);
+        ase_params_t pf = p;
+        pf.flags |= ASE_FLAG_DF_FIRST_ORDER;
+        EXPECT(ase_step_batched_wide(&pf, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                     dummy, nullptr, nullptr, nullptr, 1, 0.0, &n1, &n1, 1, 256, &n1, &n1, &n1,
+                                     &n1, 1, 384, dummy, wsb, nullptr) == ASE_ERR_ARG);
+        EXPECT(ase_step_batched_wide(&pf, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                     dummy, nullptr, nullptr, nullptr, 1, 0.0, &n1, &n1, 1, 256, &n1, &n1, &n1,
+                                     &n1, 1, 256, dummy, wsb - 8, nullptr) == ASE_ERR_WORKSPACE);
+        EXPECT(ase_step_batched_wide(&pf, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                     dummy, nullptr, nullptr, nullptr, 1, 0.0, &n1, &n1, 1, 256, nullptr, &n1, &n1,
+                                     &n1, 1, 256, dummy, wsb, nullptr) == ASE_ERR_ARG);
+        // nothing to do: no launch, no stream
+        EXPECT(ase_step_batched_wide(&pf, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                     dummy, nullptr, nullptr, nullptr, 0, 0.0, &n1, &n1, 1, 256, &n1, &n1, &n1,
+                                     &n1, 1, 256, dummy, wsb, nullptr) == ASE_OK);
+    }
     EXPECT(ase_adjoint_batched(&p, 7, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy, dummy, 1, dummy, &n1, &n1,
                                1, 256, ASE_ADJ_TAPE | ASE_ADJ_REVERSE, dummy, 1 << 20, nullptr) == ASE_ERR_ARG);
     EXPECT(ase_adjoint_batched(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy, dummy, 1,

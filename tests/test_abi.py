@@ -134,3 +134,59 @@ def test_empty_batches_are_rejected():
     rc = L.ase_step_batched(P, 1, None, 0, None, None, None, 5, 0, None, None, None, None, None, None, 1, 0.0,
                             None, None, 1, 256, None, 0, None)
     assert rc == -1 and len(L.ase_last_error()) > 0
+
+
+@pytest.mark.parametrize("order,threads", [(9, 256), (5, 512), (3, 256)])
+def test_wide_plan_covers_each_large_instance_once(order, threads):
+    """The wide plan cuts every instance of at least min_cells cells (and one
+    full tile) into consecutive tiles of threads - order - 1 cells that cover
+    it exactly once; every other instance lands in exactly one bin."""
+    import numpy as np
+    rng = np.random.default_rng(3)
+    nc = rng.integers(1, 5000, size=40).astype(np.int32)
+    nc[0], nc[1] = 4096, threads - order - 1   # one tile exactly
+    T = threads - order - 1
+    start, lst, ti, t0, it0, itn = ase.batched_plan_wide(nc, 1500, order, threads, 7)
+    wide = (nc >= 1500) & (nc >= T)
+    assert sorted(lst.tolist()) == sorted(np.flatnonzero(~wide).tolist())
+    assert start[0] == 0 and np.all(np.diff(start) >= 0) and start[-1] == len(lst)
+    assert len(ti) == int(sum(-(-int(n) // T) for n in nc[wide]))
+    for k in range(len(nc)):
+        if not wide[k]:
+            assert it0[k] == -1 and itn[k] == 0
+            continue
+        js = np.arange(it0[k], it0[k] + itn[k])
+        assert np.all(ti[js] == k)
+        assert np.array_equal(t0[js], np.arange(itn[k]) * T)
+        assert t0[js[-1]] < nc[k] <= t0[js[-1]] + T
+    # no minimum: the plain plan's bins, no tiles
+    start0, lst0, ti0, _, it00, _ = ase.batched_plan_wide(nc, 0, order, threads, 7)
+    s1, l1 = ase.batched_plan(nc, 7)
+    assert len(ti0) == 0 and np.all(it00 == -1)
+    assert np.array_equal(start0, s1) and np.array_equal(lst0, l1)
+
+
+def test_wide_form_argument_errors():
+    """The wide form refuses the Gauss-point source, other tile widths and a
+    missing or short workspace before launching anything."""
+    L = ase.lib()
+    w = WL.sod(20, 9)
+    one = (C.c_int32 * 1)(20)
+    off = (C.c_int64 * 1)(0)
+    buf = (C.c_double * 128)()
+    nb = L.ase_batched_wide_workspace_bytes(30, 1, 1)
+    assert nb > L.ase_batched_workspace_bytes(30)
+    wsbuf = C.create_string_buffer(nb + 512)
+    ws = (C.addressof(wsbuf) + 255) // 256 * 256
+
+    def call(params, thr, wsp, nbytes):
+        return L.ase_step_batched_wide(C.byref(ase.c_params(params)), 1, None, 1, off, one, buf, 5, 30, buf, buf,
+                                       buf, None, None, None, 1, 0.0, one, one, 1, 256, one, one, one, one, 1, thr,
+                                       wsp, nbytes, None)
+
+    w.params.df_source = 0
+    assert call(w.params, 256, ws, nb) == -1 and b"FIRST_ORDER" in L.ase_last_error()
+    w.params.df_source = 1
+    assert call(w.params, 384, ws, nb) == -1 and b"threads_wide" in L.ase_last_error()
+    assert call(w.params, 256, None, nb) == -6
+    assert call(w.params, 256, ws, nb - 8) == -6

@@ -1,0 +1,124 @@
+"""Wide batched form (ase_step_batched_wide): the large instances of a batch
+run as one launch per RK stage over many tiles, beside the persistent
+launch that keeps the rest.  Every output must equal the persistent form's
+(ase_step_batched) bit for bit: the same cells, faces, time steps and
+stopping decisions, only a different assignment of work to workgroups."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_05489_amd import ase
+from paper_2410_05489_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _outputs(sim, hist=None, status=None):
+    torch.cuda.synchronize()
+    out = {"U": sim.U.cpu().numpy(), "sig": sim.sig.cpu().numpy(), "t": sim.t.cpu().numpy()}
+    if hist is not None:
+        out["dt_hist"] = hist.cpu().numpy()
+    if status is not None:
+        out["status"] = status.cpu().numpy()
+    return out
+
+
+def _assert_same(a, b, what):
+    for key in a:
+        assert np.array_equal(a[key], b[key], equal_nan=True), (what, key)
+
+
+def _pair(b, nsteps, min_cells, wide_threads=256, nbins=4, threads=256, t_end=0.0, dt_replay=None, status=False):
+    """(persistent, wide) outputs of the same batch and arguments."""
+    res = []
+    for wide in (False, True):
+        sim = ase.BatchedSimulation(b, DEV, nbins=nbins, threads=threads,
+                                    wide_min_cells=min_cells if wide else 0, wide_threads=wide_threads)
+        if wide:
+            assert sim.wide is not None and sim.wide["nwide"] > 0
+        hist = torch.full((nsteps, b.ninst), -1.0, dtype=torch.float64, device=DEV)
+        st = torch.full((b.ninst,), -1, dtype=torch.int32, device=DEV) if status else None
+        print(f"wide={wide} ninst={b.ninst} nsteps={nsteps} min_cells={min_cells} "
+              f"wide_threads={wide_threads}", flush=True)
+        sim.run(nsteps, t_end, hist, dt_replay=dt_replay, status=st)
+        res.append(_outputs(sim, hist, st))
+    return res
+
+
+@pytest.mark.parametrize("order,wide_threads", [(9, 256), (9, 512), (5, 256), (3, 512), (7, 256)])
+def test_wide_equals_persistent_mixed_boundaries(order, wide_threads):
+    """Periodic, transmissive and reflective instances of 16..3000 cells:
+    those of 600 cells and more take the wide form (several tiles each,
+    ragged last tile)."""
+    b = WL.batched_mixed(ninst=12, nmin=16, nmax=3000, order=order, seed=21, nsteps=12)
+    assert b.params.df_source == WL.DF_FIRST_ORDER
+    p, w = _pair(b, b.nsteps, 600, wide_threads)
+    _assert_same(p, w, "mixed")
+    assert np.all(p["dt_hist"] > 0.0)
+
+
+def test_wide_equals_persistent_every_split():
+    """No instance wide (no tile launches), some, and all of them: the same
+    bits as the persistent launch."""
+    b = WL.batched_riemann(ninst=10, nmin=250, nmax=2000, order=9, seed=8, nsteps=8)
+    ref = None
+    for min_cells in (10**6, 1200, 1):
+        sim = ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=min_cells)
+        print(f"min_cells={min_cells} nwide={sim.wide['nwide']} ntiles={sim.wide['ntiles']}", flush=True)
+        hist = torch.zeros((b.nsteps, b.ninst), dtype=torch.float64, device=DEV)
+        sim.run(b.nsteps, 0.0, hist)
+        out = _outputs(sim, hist)
+        if ref is None:
+            base = ase.BatchedSimulation(b, DEV, nbins=3)
+            h0 = torch.zeros_like(hist)
+            base.run(b.nsteps, 0.0, h0)
+            ref = _outputs(base, h0)
+        _assert_same(ref, out, min_cells)
+
+
+def test_wide_t_end_and_repeated_calls():
+    """Instances stop at t_end at different steps (dt_hist 0 from there on);
+    a second call continues from the first call's state and time."""
+    b = WL.batched_riemann(ninst=8, nmin=300, nmax=1500, order=9, seed=13, nsteps=60)
+    t_end = 0.002
+    sims, hists = [], []
+    for wide in (0, 500):
+        sim = ase.BatchedSimulation(b, DEV, nbins=2, wide_min_cells=wide)
+        h1 = torch.full((30, b.ninst), -1.0, dtype=torch.float64, device=DEV)
+        h2 = torch.full((30, b.ninst), -1.0, dtype=torch.float64, device=DEV)
+        sim.run(30, t_end, h1)
+        sim.run(30, t_end, h2)
+        sims.append(_outputs(sim))
+        hists.append(np.concatenate([h1.cpu().numpy(), h2.cpu().numpy()]))
+    _assert_same(sims[0], sims[1], "t_end")
+    assert np.array_equal(hists[0], hists[1])
+    assert np.all(sims[1]["t"] <= t_end + 1e-14) and np.any(np.abs(sims[1]["t"] - t_end) < 1e-14)
+    assert np.any(hists[1] == 0.0) and np.all(hists[1] >= 0.0)
+
+
+def test_wide_dt_replay_stops_where_the_replay_ends():
+    """Replayed time steps, with a zero entry that stops one wide instance
+    part-way: the same bits as the persistent launch."""
+    b = WL.batched_riemann(ninst=6, nmin=400, nmax=1600, order=9, seed=17, nsteps=10)
+    base = ase.BatchedSimulation(b, DEV, nbins=2)
+    rec = torch.zeros((b.nsteps, b.ninst), dtype=torch.float64, device=DEV)
+    base.run(b.nsteps, 0.0, rec)
+    torch.cuda.synchronize()
+    replay = rec.clone()
+    k = int(np.argmax(b.ncells))
+    replay[4:, k] = 0.0
+    p, w = _pair(b, b.nsteps, 400, nbins=2, dt_replay=replay)
+    _assert_same(p, w, "replay")
+    assert np.all(w["dt_hist"][4:, k] == 0.0) and np.all(w["dt_hist"][:4, k] > 0.0)
+
+
+def test_wide_status_on_the_full_batch():
+    """The 256-instance batch (64..4096 cells, order 9) with a status array,
+    instances of 2048 cells and more in the wide form: U, strengths, times,
+    time steps and status flags all equal the persistent launch's."""
+    b = WL.batched_riemann(nsteps=40)
+    p, w = _pair(b, b.nsteps, 2048, nbins=256, status=True)
+    _assert_same(p, w, "status")
+    assert np.all(w["status"] >= 0)
