@@ -131,29 +131,45 @@ def make_workload(name):
 
 
 def bench_batched(args):
-    """Batched 1D form: 256 instances (64..4096 cells), r = 9, in one
-    persistent launch, against per-instance ase_step launches."""
+    """Batched 1D form: 256 instances (64..4096 cells), r = 9: the persistent
+    launch, with the large instances in the wide form when that is faster
+    (autotuned), against per-instance ase_step launches."""
     import torch
     from paper_2410_05489_amd import ase, autotune
     from paper_2410_05489_amd import workloads as WL
 
     b = WL.batched_riemann(nsteps=args.steps)
-    best = autotune.tune_batched(b, nsteps=10, use_cache=False)
-    sim = ase.BatchedSimulation(b, "cuda", nbins=best["nbins"], threads=best["threads"])
-    sim.run(args.warmup)
-    torch.cuda.synchronize()
-    ase.profile_enable(True)
+    if args.batched_shape:
+        # a fixed launch shape (profiling runs): no autotuner trials
+        nb, th, mc, wt = (int(x) for x in args.batched_shape.split(":"))
+        best = {"nbins": nb, "threads": th, "min_cells": mc, "wide_threads": wt, "ms": None,
+                "trials": [{"nbins": 256, "threads": 1024, "min_cells": 0, "wide_threads": 0, "ms": None}]}
+    else:
+        best = autotune.tune_batched(b, nsteps=10, use_cache=False)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    sim.run(args.steps)
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    kms, kn = ase.profile_read("batched")
-    ase.profile_enable(False)
+
+    def timed(sim, prof):
+        sim.run(args.warmup)
+        torch.cuda.synchronize()
+        ase.profile_enable(prof)
+        start.record()
+        sim.run(args.steps)
+        stop.record()
+        torch.cuda.synchronize()
+        k = ase.profile_read("batched")
+        ase.profile_enable(False)
+        return start.elapsed_time(stop), k
+
+    sim = ase.BatchedSimulation(b, "cuda", nbins=best["nbins"], threads=best["threads"],
+                                wide_min_cells=best["min_cells"], wide_threads=best["wide_threads"] or 256)
+    ms, (kms, kn) = timed(sim, True)
     cells = int(b.ncells.sum())
     value = cells * args.steps / (ms / 1e3) / 1e6
+    # the fastest persistent launch alone, for comparison
+    pbest = min((t for t in best["trials"] if t["min_cells"] == 0), key=lambda t: t["ms"] or 0.0)
+    ms_p, _ = timed(ase.BatchedSimulation(b, "cuda", nbins=pbest["nbins"], threads=pbest["threads"]), False)
+    value_p = cells * args.steps / (ms_p / 1e3) / 1e6
     # per-instance launches of the same 1D method (ase_step per instance)
     sims = []
     for k in range(b.ninst):
@@ -173,18 +189,26 @@ def bench_batched(args):
     value_pi = cells * pi_steps / (ms_pi / 1e3) / 1e6
     flops = alg_flops_per_cell_sweep(b.params.order, 1) * 3 + 3 * 4
     achieved = flops * cells * args.steps / (kms / 1e3) / 1e12
-    out = {"metric": "Mcell-updates/s, batched 1D order-9 instances, one persistent launch", "value": round(value, 2),
+    wide = best["min_cells"] > 0
+    out = {"metric": "Mcell-updates/s, batched 1D order-9 instances", "value": round(value, 2),
            "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms / args.steps, 5), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"batched_riemann_{b.ninst}x64..4096_r9_seed0", "ninst": b.ninst, "cells": cells,
-                      "nbins": best["nbins"], "threads": best["threads"]},
+                      "form": "persistent + wide" if wide else "persistent",
+                      "nbins": best["nbins"], "threads": best["threads"], "wide_min_cells": best["min_cells"],
+                      "wide_threads": best["wide_threads"],
+                      "wide_instances": sim.wide["nwide"] if wide else 0,
+                      "wide_tiles": sim.wide["ntiles"] if wide else 0},
+           "persistent_only": {"value": round(value_p, 2), "ms": round(ms_p, 3), "nbins": pbest["nbins"],
+                               "threads": pbest["threads"]},
            "per_instance_launches": {"value": round(value_pi, 2), "steps": pi_steps, "ms": round(ms_pi, 3)},
            "speedup_vs_per_instance": round(value / value_pi, 2),
            "autotune": best["trials"],
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
-                        "kernel": "k_batched1d", "avg_launch_ms": round(kms / max(kn, 1), 4)}}
+                        "kernel": "k_batched1d + k_batched_wide" if wide else "k_batched1d",
+                        "avg_call_ms": round(kms / max(kn, 1), 4)}}
     print(json.dumps(out), flush=True)
 
 
@@ -394,7 +418,9 @@ def measure_adjoint(nsteps=100, every=10, reps=3):
     keep = np.flatnonzero(st.cpu().numpy() == 0)
     del probe
     b = WL.batch_subset(b_all, keep)
-    fwd = autotune.tune_batched(b, nsteps=10, use_cache=False)
+    # the adjoint's own forward (tape re-runs and checkpoints) is the
+    # persistent launch: the ratio is taken against that form
+    fwd = autotune.tune_batched(b, nsteps=10, use_cache=False, wide=False)
     adj = autotune.tune_adjoint(b, every=every, use_cache=False, fwd_shape=(fwd["nbins"], fwd["threads"]))
     run = A.BatchedAdjoint(b, "cuda", nbins=fwd["nbins"], threads=fwd["threads"], adj_threads=adj["threads"],
                            every=every, adj_nbins=adj["nbins"])
@@ -434,11 +460,29 @@ def measure_adjoint(nsteps=100, every=10, reps=3):
         ok += int(bool(np.isfinite(Jh[k])) and bool(np.isfinite(gh[:, o:o + n + 2 * b.ng]).all()))
     med = lambda a: sorted(a)[len(a) // 2]   # noqa: E731
     tp, tf, tb = med(t_plain), med(t_fwd), med(t_bwd)
+    # the fastest forward of the same batch (the wide form where it wins)
+    wbest = autotune.tune_batched(b, nsteps=10, use_cache=False)
+    fast = ase.BatchedSimulation(b, "cuda", nbins=wbest["nbins"], threads=wbest["threads"],
+                                 wide_min_cells=wbest["min_cells"], wide_threads=wbest["wide_threads"] or 256)
+    t_fast = []
+    for rep in range(reps + 1):
+        fast.U.copy_(U0)
+        fast.t.zero_()
+        torch.cuda.synchronize()
+        ev[0].record()
+        fast.run(nsteps)
+        ev[1].record()
+        torch.cuda.synchronize()
+        if rep > 0:
+            t_fast.append(ev[0].elapsed_time(ev[1]))
+    tw = med(t_fast)
     return {"workload": f"batched_riemann_{b_all.ninst}x64..4096_r9_seed0", "instances_timed": b.ninst,
             "instances_lost": [int(k) for k in np.flatnonzero(st.cpu().numpy() != 0)],
             "steps": nsteps, "checkpoint_every": every,
             "cells": int(b.ncells.sum()), "forward_ms": round(tp, 3), "forward_with_checkpoints_ms": round(tf, 3),
             "backward_ms": round(tb, 3), "adjoint_fwd_ratio": round(tb / tp, 3),
+            "fastest_forward_ms": round(tw, 3), "fastest_forward_form": "persistent + wide" if wbest["min_cells"]
+            else "persistent", "adjoint_fastest_fwd_ratio": round(tb / tw, 3),
             "adjoint_kernel_ms_per_segment": round(kms / max(kn, 1), 3),
             "forward_shape": [fwd["nbins"], fwd["threads"]], "adjoint_shape": [adj["nbins"], adj["threads"]],
             "instances_finite": ok, "adjoint_trials": adj["trials"]}
@@ -481,6 +525,9 @@ def main():
     ap.add_argument("--workload", default="quad1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio measurement")
+    ap.add_argument("--batched-shape", default="", metavar="BINS:THREADS:MIN_CELLS:WIDE_THREADS",
+                    help="--workload batched: this launch shape instead of the autotuner's (MIN_CELLS 0: "
+                         "the persistent launch alone; the persistent comparison then uses 256 bins of 1024 lanes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()

@@ -48,8 +48,19 @@ class _BatchedRun(torch.autograd.Function):
 
         def call(s, ws, phase, stream=None):
             n = min(every, nsteps - s * every)
-            ase.adjoint_batched(runner.sim, ckU[s], ckS[s], hist[s * every:s * every + n], n, lam, ws,
-                                runner.adj_threads, runner.adj_plan, stream=stream, phase=phase)
+            h = hist[s * every:s * every + n]
+            if runner.wide_plan is None:
+                ase.adjoint_batched(runner.sim, ckU[s], ckS[s], h, n, lam, ws, runner.adj_threads, runner.adj_plan,
+                                    stream=stream, phase=phase)
+                return
+            # the tape of every instance in the persistent launch, the
+            # reverse sweep with the large instances in the wide form
+            if phase & ase.ADJ_TAPE:
+                ase.adjoint_batched(runner.sim, ckU[s], ckS[s], h, n, lam, ws, runner.adj_threads,
+                                    runner.adj_plan, stream=stream, phase=ase.ADJ_TAPE)
+            if phase & ase.ADJ_REVERSE:
+                ase.adjoint_batched_wide(runner.sim, ckU[s], ckS[s], h, n, lam, ws, runner.adj_threads,
+                                         runner.wide_plan, stream=stream)
 
         if not runner.overlap or len(segs) < 2:
             for s in segs:
@@ -107,11 +118,20 @@ class BatchedAdjoint:
     J.sum().backward() gives dJ/dU0 through the adjoint kernels."""
 
     def __init__(self, batch, device="cuda", nbins: int = 0, threads: int = 256, adj_threads: int = 256,
-                 every: int = 10, adj_nbins: int = 0, overlap: bool = True):
-        self.sim = ase.BatchedSimulation(batch, device, nbins=nbins, threads=threads)
+                 every: int = 10, adj_nbins: int = 0, overlap: bool = True, wide_min_cells: int = 0,
+                 wide_threads: int = 256, adj_wide_min_cells: int = 0, adj_wide_threads: int = 256):
+        """wide_min_cells / wide_threads: the forward's wide form (as
+        BatchedSimulation); adj_wide_min_cells / adj_wide_threads: the reverse
+        sweep's (ase_adjoint_batched_wide; 0: the persistent launch only)."""
+        self.sim = ase.BatchedSimulation(batch, device, nbins=nbins, threads=threads, wide_min_cells=wide_min_cells,
+                                         wide_threads=wide_threads)
         self.every = int(every)
         self.adj_threads = int(adj_threads)
         self.adj_plan = ase.device_plan(batch.ncells, adj_nbins, device) if adj_nbins else None
+        self.wide_plan = None
+        if adj_wide_min_cells > 0:
+            self.wide_plan = ase.wide_plan_device(batch.ncells, adj_wide_min_cells, batch.params.order,
+                                                  adj_wide_threads, adj_nbins or self.sim.nbins, device)
         self.ws_adj = ase.Workspace(ase.adjoint_batched_workspace_bytes(batch.total, self.every), device)
         self.device = device
         self.overlap = overlap          # recompute segment s-1 while running segment s back

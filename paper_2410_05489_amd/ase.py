@@ -45,7 +45,8 @@ EXPORTS = ("ase_last_error", "ase_version", "ase_bc_fill", "ase_sigma_init", "as
            "ase_batched_sigma_init", "ase_step_batched", "ase_adjoint_workspace_bytes", "ase_adjoint_step",
            "ase_adjoint_batched_workspace_bytes", "ase_adjoint_batched", "ase_pressure_objective",
            "ase_gks_flux", "ase_gks_workspace_bytes", "ase_step_gks", "ase_step_batched_noalloc",
-           "ase_batched_plan_wide", "ase_batched_wide_workspace_bytes", "ase_step_batched_wide")
+           "ase_batched_plan_wide", "ase_batched_wide_workspace_bytes", "ase_step_batched_wide",
+           "ase_adjoint_batched_wide")
 
 KCLASS = {"sweep_x": 0, "sweep_y": 1, "stage_1d": 2, "bc": 3, "cfl": 4, "batched": 5, "adjoint": 6,
           "gks_1d": 7, "gks_2d_recon": 8, "gks_2d_flux": 9, "gks_2d_update": 10}
@@ -107,6 +108,9 @@ def lib():
     L.ase_adjoint_batched_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
     L.ase_adjoint_batched.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp,
                                       C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+    L.ase_adjoint_batched_wide.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp,
+                                           vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32,
+                                           C.c_int32, vp, C.c_size_t, vp]
     L.ase_pressure_objective.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp]
     L.ase_gks_flux.argtypes = [vp, vp, C.c_int32, dp, dp, dp, dp, C.c_double, dp, dp, vp]
     L.ase_gks_workspace_bytes.restype = C.c_size_t
@@ -420,14 +424,8 @@ class BatchedSimulation:
         nbytes = int(lib().ase_batched_workspace_bytes(batch.total))
         self.wide = None
         if wide_min_cells > 0:
-            wb, wl, ti, t0, it0, itn = batched_plan_wide(n, wide_min_cells, self.p.order, wide_threads, self.nbins)
-            dev = lambda a: torch.as_tensor(a).to(device)   # noqa: E731
-            self.wide = dict(bin_start=dev(wb), bin_list=dev(wl if len(wl) else np.zeros(1, np.int32)),
-                             tile_inst=dev(ti if len(ti) else np.zeros(1, np.int32)),
-                             tile_i0=dev(t0 if len(t0) else np.zeros(1, np.int32)),
-                             inst_tile0=dev(it0), inst_ntiles=dev(itn), ntiles=len(ti), threads=wide_threads,
-                             nwide=int(np.count_nonzero(itn)))
-            nbytes = int(lib().ase_batched_wide_workspace_bytes(batch.total, batch.ninst, len(ti)))
+            self.wide = wide_plan_device(n, wide_min_cells, self.p.order, wide_threads, self.nbins, device)
+            nbytes = int(lib().ase_batched_wide_workspace_bytes(batch.total, batch.ninst, self.wide["ntiles"]))
         self.ws = Workspace(nbytes, device)
         if sigma is None:
             self.sigma_init()
@@ -532,6 +530,33 @@ def adjoint_batched(sim: "BatchedSimulation", U_ck, sig_ck, dt_hist, nsteps: int
                                      _p(sim.dx), b.ng, b.total, _p(U_ck), _p(sig_ck), _p(dt_hist), int(nsteps),
                                      _p(lam), _p(bs), _p(bl), int(nbins), int(threads), int(phase), ws.ptr,
                                      ws.nbytes, _stream(stream)), "ase_adjoint_batched")
+
+
+def wide_plan_device(ncells, min_cells: int, order: int, threads_wide: int, nbins: int, device="cuda") -> dict:
+    """batched_plan_wide on the device: bin_start, bin_list, tile_inst,
+    tile_i0, inst_tile0, inst_ntiles (tensors), ntiles, threads, nbins, nwide."""
+    import numpy as np
+    wb, wl, ti, t0, it0, itn = batched_plan_wide(ncells, min_cells, order, threads_wide, nbins)
+    one = np.zeros(1, np.int32)
+    dev = lambda a: torch.as_tensor(a if len(a) else one).to(device)   # noqa: E731
+    return dict(bin_start=dev(wb), bin_list=dev(wl), tile_inst=dev(ti), tile_i0=dev(t0), inst_tile0=dev(it0),
+                inst_ntiles=dev(itn), ntiles=len(ti), threads=threads_wide, nbins=nbins,
+                nwide=int(np.count_nonzero(itn)))
+
+
+def adjoint_batched_wide(sim: "BatchedSimulation", U_ck, sig_ck, dt_hist, nsteps: int, lam, ws: Workspace,
+                         threads: int, wplan: dict, stream=None):
+    """Reverse phase of adjoint_batched with the tiled instances of wplan
+    (wide_plan_device) in the wide form; the tape in ws comes from an
+    ADJ_TAPE call of adjoint_batched with a plan of every instance."""
+    b = sim.b
+    w = wplan
+    _check(lib().ase_adjoint_batched_wide(
+        C.byref(c_params(sim.p)), b.bc, _p(sim.bc_inst), b.ninst, _p(sim.offsets), _p(sim.ncells), _p(sim.dx),
+        b.ng, b.total, _p(U_ck), _p(sig_ck), _p(dt_hist), int(nsteps), _p(lam), _p(w["bin_start"]),
+        _p(w["bin_list"]), int(w["nbins"]), int(threads), _p(w["tile_inst"]), _p(w["tile_i0"]),
+        _p(w["inst_ntiles"]), int(w["ntiles"]), int(w["threads"]), ws.ptr, ws.nbytes, _stream(stream)),
+        "ase_adjoint_batched_wide")
 
 
 def pressure_objective(p, offsets, ncells, dx, ng: int, total: int, U, J=None, lam=None, weights=None,

@@ -1,10 +1,12 @@
-"""Launch-shape autotuner for the persistent batched kernels.
+"""Launch-shape autotuner for the batched kernels.
 
 Times ase_step_batched (and ase_adjoint_batched) for a few (bins, threads)
-shapes on the current GPU and keeps the fastest in a JSON cache keyed by
-(arch, kernel, order, instance-count, stored-cell total).  Results do not
-depend on the shape (every instance is advanced by the same per-cell
-arithmetic), only the time does.
+shapes on the current GPU, and with the first-order DF source the wide form
+(ase_step_batched_wide) for a few (bins, threads, min_cells, wide threads)
+splits, and keeps the fastest in a JSON cache keyed by (arch, kernel, order,
+instance-count, stored-cell total).  Results do not depend on the shape
+(every instance is advanced by the same per-cell arithmetic), only the time
+does.
 """
 from __future__ import annotations
 
@@ -20,6 +22,12 @@ DEFAULT_CANDIDATES: Sequence[Tuple[int, int]] = ((128, 512), (256, 256), (256, 5
                                                   (256, 1024))
 
 
+# (bins, threads, min_cells, wide_threads) of the wide form
+WIDE_CANDIDATES: Sequence[Tuple[int, int, int, int]] = ((128, 256, 768, 256), (64, 256, 768, 256),
+                                                        (128, 512, 1024, 256), (256, 512, 1024, 256),
+                                                        (128, 512, 1536, 256), (128, 512, 1024, 512))
+
+
 def cache_path() -> str:
     return os.environ.get("ASE_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ase_mi355x",
                                                          "tune.json"))
@@ -33,7 +41,7 @@ def _arch() -> str:
 
 
 def batched_key(batch) -> str:
-    return f"{_arch()}/batched/r{batch.params.order}/n{batch.ninst}/c{batch.total}"
+    return f"{_arch()}/batched2/r{batch.params.order}/n{batch.ninst}/c{batch.total}/s{batch.params.df_source}"
 
 
 def _load() -> Dict[str, dict]:
@@ -53,9 +61,12 @@ def _store(d: Dict[str, dict]) -> None:
     os.replace(tmp, path)
 
 
-def time_batched(batch, nbins: int, threads: int, nsteps: int, device="cuda") -> float:
-    """Milliseconds for nsteps steps of the whole batch in one launch."""
-    sim = ase.BatchedSimulation(batch, device, nbins=nbins, threads=threads)
+def time_batched(batch, nbins: int, threads: int, nsteps: int, device="cuda", min_cells: int = 0,
+                 wide_threads: int = 256) -> float:
+    """Milliseconds for nsteps steps of the whole batch in one call
+    (min_cells > 0: the wide form)."""
+    sim = ase.BatchedSimulation(batch, device, nbins=nbins, threads=threads, wide_min_cells=min_cells,
+                                wide_threads=wide_threads)
     sim.run(1)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -68,16 +79,26 @@ def time_batched(batch, nbins: int, threads: int, nsteps: int, device="cuda") ->
 
 
 def tune_batched(batch, nsteps: int = 10, candidates: Optional[Sequence[Tuple[int, int]]] = None,
-                 use_cache: bool = True) -> dict:
-    """Best {'nbins', 'threads', 'ms'} for this batch shape (cached)."""
+                 use_cache: bool = True, wide: Optional[bool] = None,
+                 wide_candidates: Optional[Sequence[Tuple[int, int, int, int]]] = None) -> dict:
+    """Best {'nbins', 'threads', 'min_cells', 'wide_threads', 'ms'} for this
+    batch shape (cached); min_cells 0 is the persistent launch alone.  wide
+    (default: with the first-order DF source) adds the wide-form splits."""
     key = batched_key(batch)
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
         return cache[key]
+    if wide is None:
+        wide = batch.params.df_source == 1
     trials = []
     for nbins, threads in (candidates or DEFAULT_CANDIDATES):
         ms = time_batched(batch, nbins, threads, nsteps)
-        trials.append({"nbins": nbins, "threads": threads, "ms": ms})
+        trials.append({"nbins": nbins, "threads": threads, "min_cells": 0, "wide_threads": 0, "ms": ms})
+    if wide:
+        for nbins, threads, mc, wt in (wide_candidates or WIDE_CANDIDATES):
+            nb = min(nbins, batch.ninst)
+            ms = time_batched(batch, nb, threads, nsteps, min_cells=mc, wide_threads=wt)
+            trials.append({"nbins": nb, "threads": threads, "min_cells": mc, "wide_threads": wt, "ms": ms})
     best = min(trials, key=lambda r: r["ms"])
     best = dict(best, steps=nsteps, trials=trials)
     if use_cache:

@@ -1161,12 +1161,12 @@ size_t ase_adjoint_batched_workspace_bytes(int64_t total, int32_t nsteps)
     return adjoint_bytes(total, nsteps);
 }
 
-int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
-                        const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
-                        const double *U_ck,
-                        const double *sigma_ck, const double *dt_hist, int32_t nsteps, double *lam,
-                        const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
-                        int32_t phase, void *ws, size_t ws_bytes, void *stream)
+// Validation of ase_adjoint_batched's arguments and its launch description.
+static int adjoint_setup(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                         const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
+                         const double *U_ck, const double *sigma_ck, const double *dt_hist, int32_t nsteps,
+                         double *lam, const int32_t *bin_start, const int32_t *bin_list, int32_t nbins,
+                         int32_t threads, int32_t phase, void *ws, size_t ws_bytes, AdjLaunch *al)
 {
     int rc = batched_common(p, bc, ninst, offsets, ncells, ng, total, const_cast<double *>(U_ck),
                             const_cast<double *>(sigma_ck));
@@ -1184,35 +1184,96 @@ int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_ins
     if (nsteps == 0) return ASE_OK;
     rc = check_ws(ws, ws_bytes, adjoint_bytes(total, nsteps));
     if (rc) return rc;
+    std::memset(al, 0, sizeof(*al));
+    carve_adjoint(ws, total, nsteps, al);
+    al->offsets = reinterpret_cast<const long long *>(offsets);
+    al->ncells = ncells;
+    al->dx = dx;
+    al->ck_U = U_ck;
+    al->ck_sig = sigma_ck;
+    al->dt_hist = dt_hist;
+    al->lam = lam;
+    al->bin_start = bin_start;
+    al->bin_list = bin_list;
+    al->bc_inst = bc_inst;
+    al->total = total;
+    al->ninst = ninst;
+    al->nbins = nbins;
+    al->threads = threads;
+    al->R = (p->order - 1) / 2;
+    al->ng = ng;
+    al->nsteps = nsteps;
+    al->bc = bc;
+    al->fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
+    al->phase = phase;
+    al->mc = method_const(p);
+    return ASE_OK;
+}
+
+int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                        const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng, int64_t total,
+                        const double *U_ck,
+                        const double *sigma_ck, const double *dt_hist, int32_t nsteps, double *lam,
+                        const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
+                        int32_t phase, void *ws, size_t ws_bytes, void *stream)
+{
     AdjLaunch al;
-    std::memset(&al, 0, sizeof(al));
-    carve_adjoint(ws, total, nsteps, &al);
-    al.offsets = reinterpret_cast<const long long *>(offsets);
-    al.ncells = ncells;
-    al.dx = dx;
-    al.ck_U = U_ck;
-    al.ck_sig = sigma_ck;
-    al.dt_hist = dt_hist;
-    al.lam = lam;
-    al.bin_start = bin_start;
-    al.bin_list = bin_list;
-    al.bc_inst = bc_inst;
-    al.total = total;
-    al.ninst = ninst;
-    al.nbins = nbins;
-    al.threads = threads;
-    al.R = (p->order - 1) / 2;
-    al.ng = ng;
-    al.nsteps = nsteps;
-    al.bc = bc;
-    al.fo = (p->flags & ASE_FLAG_DF_FIRST_ORDER) ? 1 : 0;
-    al.phase = phase;
-    al.mc = method_const(p);
+    int rc = adjoint_setup(p, bc, bc_inst, ninst, offsets, ncells, dx, ng, total, U_ck, sigma_ck, dt_hist, nsteps,
+                           lam, bin_start, bin_list, nbins, threads, phase, ws, ws_bytes, &al);
+    if (rc || nsteps == 0) return rc;
     {
         ProfScope ps(ASE_KCLASS_ADJOINT, (hipStream_t)stream);
         launch_adjoint(al, (hipStream_t)stream);
     }
     return check_launch("ase_adjoint_batched");
+}
+
+int ase_adjoint_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
+                             const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng,
+                             int64_t total, const double *U_ck, const double *sigma_ck, const double *dt_hist,
+                             int32_t nsteps, double *lam, const int32_t *bin_start, const int32_t *bin_list,
+                             int32_t nbins, int32_t threads, const int32_t *tile_inst, const int32_t *tile_i0,
+                             const int32_t *inst_ntiles, int32_t ntiles, int32_t threads_wide, void *ws,
+                             size_t ws_bytes, void *stream)
+{
+    AdjLaunch al;
+    int rc = adjoint_setup(p, bc, bc_inst, ninst, offsets, ncells, dx, ng, total, U_ck, sigma_ck, dt_hist, nsteps,
+                           lam, bin_start, bin_list, nbins, threads, ASE_ADJ_REVERSE, ws, ws_bytes, &al);
+    if (rc) return rc;
+    if (ntiles < 0) return fail(ASE_ERR_ARG, "ntiles must be >= 0");
+    if (threads_wide != 256 && threads_wide != 512) return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512");
+    if (!inst_ntiles || (ntiles > 0 && (!tile_inst || !tile_i0))) return fail(ASE_ERR_ARG, "null tile arrays");
+    if (nsteps == 0) return ASE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    AdjWideLaunch wl;
+    std::memset(&wl, 0, sizeof(wl));
+    wl.offsets = al.offsets; wl.ncells = ncells; wl.dx = dx; wl.dt_hist = dt_hist;
+    wl.lam = lam; wl.mu1 = al.mu1; wl.mu2 = al.mu2; wl.tapeU = al.tapeU; wl.tapeS = al.tapeS;
+    wl.bc_inst = bc_inst; wl.tile_inst = tile_inst; wl.tile_i0 = tile_i0; wl.inst_ntiles = inst_ntiles;
+    wl.total = total; wl.ninst = ninst; wl.ntiles = ntiles; wl.threads = threads_wide; wl.R = al.R; wl.ng = ng;
+    wl.nsteps = nsteps; wl.bc = bc; wl.mc = al.mc;
+    {
+        ProfScope ps(ASE_KCLASS_ADJOINT, st);
+        if (ntiles == 0) {
+            launch_adjoint(al, st);
+        } else {
+            // the wide instances on the library's second stream, forked before
+            // the persistent launch and joined back after the last fold
+            std::lock_guard<std::mutex> lk(g_side_mu);
+            SideStream *ss = nullptr;
+            rc = side_stream(&ss);
+            if (rc) return rc;
+            hipError_t e = hipEventRecord(ss->fork, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ss->s, ss->fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "ase_adjoint_batched_wide: fork");
+            launch_adjoint(al, st);
+            launch_adjoint_wide(wl, ss->s);
+            e = hipEventRecord(ss->join, ss->s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, ss->join, 0);
+            if (e != hipSuccess) return hip_fail(e, "ase_adjoint_batched_wide: join");
+        }
+    }
+    return check_launch("ase_adjoint_batched_wide");
 }
 
 int ase_pressure_objective(const ase_params_t *p, int32_t ninst, const int64_t *offsets, const int32_t *ncells,

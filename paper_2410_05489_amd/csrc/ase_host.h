@@ -155,6 +155,20 @@ struct AdjLaunch {
 };
 void launch_adjoint(const AdjLaunch &al, hipStream_t st);
 
+// Reverse sweep of the wide instances (tiles of threads - 2R - 2 cells) over
+// the tape the persistent tape phase left in the workspace.
+struct AdjWideLaunch {
+    const long long *offsets;
+    const int *ncells;
+    const double *dx, *dt_hist;
+    double *lam, *mu1, *mu2, *tapeU, *tapeS;
+    const int *bc_inst, *tile_inst, *tile_i0, *inst_ntiles;
+    long long total;
+    int ninst, ntiles, threads, R, ng, nsteps, bc;
+    MethodConst mc;
+};
+void launch_adjoint_wide(const AdjWideLaunch &wl, hipStream_t st);
+
 struct ObjLaunch {
     const long long *offsets;
     const int *ncells;

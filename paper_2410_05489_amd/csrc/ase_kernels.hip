@@ -1296,12 +1296,6 @@ __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
     constexpr int UX = Lds1D<R, T>::UX;
     __shared__ Lds1D<R, T> L;
     __shared__ double red[NT / 64];
-    // p, un, ut, 1/c and the positivity flag (1 or 0) of each window cell,
-    // in the trace arrays' space: those are first written by the
-    // reconstruction phase, after the strengths are formed (the smaller LDS
-    // footprint lets more workgroups share a compute unit)
-    static_assert(5 * UX <= 6 * (T + 2), "primitives fit in the trace arrays");
-    double(*sq)[UX] = reinterpret_cast<double(*)[UX]>(&L.sTR[0][0]);
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
     const int k = a.tile_inst[b], i0 = a.tile_i0[b];
@@ -1386,15 +1380,17 @@ __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
     double un[3];
     stage1d_prefetch<T, NT, MODE_FUSED_1D>(tl, i0, un);
 
-    // the window x in [i0-1-R, i0+T+1+R) of the stage input, ghosts mapped
-    // as batched_fill copies them (periodic image, wall mirror with the
-    // momentum reversed, or the boundary cell), 0 beyond the stored range
+    // the window x in [i0-1-R, i0+T+1+R) of the stage input (one cell per
+    // lane: the window is NT cells long), ghosts mapped as batched_fill
+    // copies them (periodic image, wall mirror with the momentum reversed,
+    // or the boundary cell), 0 beyond the stored range
+    static_assert(UX == NT, "one window cell per lane");
     const int bc = inst_bc(a.bc_inst, a.bc, k);
     const int ox = i0 - 1 - R;
-    for (int lx = tid; lx < UX; lx += NT) {
+    auto window_cell = [&](int lx, double(&W)[3]) {
         int x = ox + lx;
         double fm = 1.0;
-        bool in_range = x >= -ng && x < N + ng;
+        const bool in_range = x >= -ng && x < N + ng;
         if (x < 0 || x >= N) {
             if (bc == ASE_BC_PERIODIC) x = x < 0 ? x + N : x - N;
             else if (bc == ASE_BC_REFLECTIVE) {
@@ -1402,29 +1398,31 @@ __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
                 fm = -1.0;
             } else x = x < 0 ? 0 : N - 1;
         }
-        double W[3];
 #pragma unroll
         for (int v = 0; v < 3; ++v) W[v] = in_range ? in[v * P + off + ng + x] : 0.0;
         W[1] *= fm;
+    };
+    double W[3];
+    window_cell(tid, W);
 #pragma unroll
-        for (int v = 0; v < 3; ++v) L.sU[v][lx] = W[v];
-        const Prim q = primitives<3>(W, 0, mc);
-        sq[0][lx] = q.p;
-        sq[1][lx] = q.un;
-        sq[2][lx] = q.ut;
-        sq[3][lx] = q.ic;
-        sq[4][lx] = q.ok ? 1.0 : 0.0;
+    for (int v = 0; v < 3; ++v) L.sU[v][tid] = W[v];
+    // first-order strength of the face on this cell's right: the neighbour's
+    // primitive variables from the next lane (the last lane of a wave forms
+    // them itself), as in batched_fill
+    const Prim qa = primitives<3>(W, 0, mc);
+    Prim qb;
+    qb.p = __shfl_down(qa.p, 1);
+    qb.un = __shfl_down(qa.un, 1);
+    qb.ut = __shfl_down(qa.ut, 1);
+    qb.ic = __shfl_down(qa.ic, 1);
+    qb.c = 0.0;
+    qb.ok = __shfl_down((int)qa.ok, 1) != 0;
+    if ((tid & 63) == 63 && tid + 1 < UX) {
+        double Wb[3];
+        window_cell(tid + 1, Wb);
+        qb = primitives<3>(Wb, 0, mc);
     }
-    __syncthreads();
-    // first-order strengths of the window's faces
-    for (int lx = tid; lx + 1 < UX; lx += NT) {
-        Prim qa, qb;
-        qa.p = sq[0][lx]; qa.un = sq[1][lx]; qa.ut = sq[2][lx]; qa.ic = sq[3][lx]; qa.c = 0.0;
-        qa.ok = sq[4][lx] != 0.0;
-        qb.p = sq[0][lx + 1]; qb.un = sq[1][lx + 1]; qb.ut = sq[2][lx + 1]; qb.ic = sq[3][lx + 1]; qb.c = 0.0;
-        qb.ok = sq[4][lx + 1] != 0.0;
-        L.sS[lx] = sigma_point(qa, qb);
-    }
+    if (tid + 1 < UX) L.sS[tid] = sigma_point(qa, qb);
     __syncthreads();
     double l;
     if (a.stage == 3) {
@@ -1467,13 +1465,15 @@ struct LdsAdj {
     static constexpr int NC = T + 2 * R + 2;  // trace cells [i0-R-1, i0+T+R]
     static constexpr int NF = NC - 1;         // faces between consecutive trace cells
     double sV[3][WX];
-    double sS[WX];
     double sG[3][NC];
     double sGL[3][NF], sGR[3][NF];
     double sAl[4][NC];       // frozen DF factors of each trace cell
     int8_t sLev[NC];         // and its stencil level
     union {
+        // window strengths and face traces (trace, flux and decision
+        // phases), then the tap contributions (tap and gather phases)
         struct {
+            double sS[WX];
             double tr[3][NC], tl[3][NC];
         } t;
         double c[2 * R + 1][NC];
@@ -1522,7 +1522,7 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
         const int lx = c + (H - R - 1);
         double s[2 * R];
 #pragma unroll
-        for (int m = -R; m < R; ++m) s[m + R] = L.sS[lx + m];
+        for (int m = -R; m < R; ++m) s[m + R] = L.u.t.sS[lx + m];
         auto ld = [&](int v, int m) { return L.sV[v][lx + m]; };
         double out[3][2];
         reconstruct_cell<R, 3, 2>(ld, s, mc, R - 1, 0, out);
@@ -1594,7 +1594,7 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
         const int lx = c + (H - R - 1);
         double s[2 * R], al[4];
 #pragma unroll
-        for (int m = -R; m < R; ++m) s[m + R] = L.sS[lx + m];
+        for (int m = -R; m < R; ++m) s[m + R] = L.u.t.sS[lx + m];
         L.sLev[c] = (int8_t)cell_decisions<R>(s, mc, al);
 #pragma unroll
         for (int k = 0; k < 4; ++k) L.sAl[k][c] = al[k];
@@ -1790,7 +1790,7 @@ __device__ __forceinline__ void adj_stage_window(const AdjWin<R, T, NT> &w, LdsA
         if (lx < LA::WX) {
 #pragma unroll
             for (int v = 0; v < 3; ++v) L.sV[v][lx] = w.v[q][v];
-            L.sS[lx] = w.v[q][3];
+            L.u.t.sS[lx] = w.v[q][3];
         }
     }
 #pragma unroll
@@ -1928,6 +1928,139 @@ __global__ void __launch_bounds__(NT, PH == ASE_ADJ_TAPE ? 4 : 1) k_adjoint1d(Ad
             __syncthreads();
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Wide form of the reverse sweep for the largest instances: one launch per
+// (step, transposed stage) over all their tiles, then a launch that folds
+// each instance's ghost gradients onto the cells they copy (adj_fold), as
+// adj_stage does after its tile loop.  The tape comes from the tape phase of
+// the persistent kernel (every instance).  Within one transposed stage no
+// tile reads what another writes (each reads the previous stage's folded
+// output and its own cells' combination terms), so the launches give the
+// persistent reverse sweep's results bit for bit.
+// ---------------------------------------------------------------------------
+struct AdjWideArgs {
+    const long long *offsets;
+    const int *ncells;
+    const double *dx;
+    const double *dt_hist;
+    double *lam, *mu1, *mu2;
+    const double *tapeU, *tapeS;
+    const int *bc_inst;
+    const int *tile_inst, *tile_i0, *inst_ntiles;
+    long long total;
+    int ninst, ntiles, ng, nsteps, bc;
+    int q, stage;   // step, transposed stage 3, 2 or 1; stage 0: clear the ghost slots of lam
+    MethodConst mc;
+};
+
+// Steps the segment took for instance k (the persistent kernel's count).
+__device__ __forceinline__ int adj_nact(const AdjWideArgs &a, int k)
+{
+    int n = 0;
+    while (n < a.nsteps && a.dt_hist[(long long)n * a.ninst + k] > 0.0) ++n;
+    return n;
+}
+
+// The transposed stage `stage` of step q as adj_stage sets it up.
+__device__ __forceinline__ AdjTile adj_wide_tile(const AdjWideArgs &a, int k, int q, int stage)
+{
+    const long long off = a.offsets[k], P = a.total, SU = 3 * P;
+    const double dt = a.dt_hist[(long long)q * a.ninst + k];
+    double *lam = a.lam + off, *mu1 = a.mu1 + off, *mu2 = a.mu2 + off;
+    AdjTile t;
+    t.plane = P; t.N = a.ncells[k]; t.ng = a.ng; t.inv_dx = 1.0 / a.dx[k];
+    t.a1 = t.a2 = nullptr;
+    t.c1 = t.c2 = 0.0;
+    t.V = a.tapeU + (3LL * q + stage - 1) * SU + off;
+    t.S = a.tapeS + (3LL * q + stage - 1) * P + off;
+    if (stage == 3) {
+        t.g = lam; t.gscale = (2.0 / 3.0) * dt;
+        t.a0 = lam; t.c0 = 2.0 / 3.0;
+        t.out = mu2;
+    } else if (stage == 2) {
+        t.g = mu2; t.gscale = 0.25 * dt;
+        t.a0 = mu2; t.c0 = 0.25;
+        t.out = mu1;
+    } else {
+        t.g = mu1; t.gscale = dt;
+        t.a0 = lam; t.c0 = 1.0 / 3.0;
+        t.a1 = mu2; t.c1 = 0.75;
+        t.a2 = mu1; t.c2 = 1.0;
+        t.out = lam;
+    }
+    return t;
+}
+
+template <int R, int NT>
+__global__ void __launch_bounds__(NT, 1) k_adjoint_wide(AdjWideArgs a)
+{
+    constexpr int T = NT - 2 * R - 2;
+    __shared__ LdsAdj<R, T> L;
+    const int b = blockIdx.x;
+    const int k = a.tile_inst[b], i0 = a.tile_i0[b];
+    if (k < 0 || k >= a.ninst) return;   // malformed tile entry: skipped (the whole workgroup)
+    const int N = a.ncells[k];
+    const long long off = a.offsets[k];
+    if (N < T || off < 0 || off + N + 2LL * a.ng > a.total || i0 < 0 || i0 >= N) return;
+    const bool active = a.q < adj_nact(a, k);
+    // a transmissive instance's boundary tile holds both its ghost cells and
+    // the cell they copy: it folds them itself (and at the end of the sweep
+    // clears the ghost slots of lam); the fold launch takes the others
+    const int bc = inst_bc(a.bc_inst, a.bc, k);
+    const bool local = bc != ASE_BC_PERIODIC && bc != ASE_BC_REFLECTIVE;
+    const bool clear = local && a.q == 0 && a.stage == 1;
+    if (!active && !clear) return;
+    const AdjTile t = adj_wide_tile(a, k, a.q, a.stage);
+    if (active) {
+        AdjWin<R, T, NT> w;
+        adj_fetch<R, T, NT>(t, i0, w);
+        adj_stage_window<R, T, NT>(w, L);
+        __syncthreads();
+        adjoint1d_tile<R, T, NT>(t, i0, a.mc, L);   // ends with a barrier
+    }
+    if (local) {
+        const int v = threadIdx.x >> 1, side = threadIdx.x & 1;
+        const bool mine = side == 0 ? i0 == 0 : i0 + T >= N;
+        if (threadIdx.x < 6 && mine) {
+            // adj_fold's transmissive sum, in its order
+            double *o = t.out + v * a.total;
+            const int base = side == 0 ? 0 : N + a.ng;
+            if (active) {
+                double acc = 0.0;
+                for (int kk = 0; kk < a.ng; ++kk) acc += o[base + kk];
+                o[side == 0 ? a.ng : a.ng + N - 1] += acc;
+            }
+            if (clear)
+                for (int kk = 0; kk < a.ng; ++kk) o[base + kk] = 0.0;
+        }
+    }
+}
+
+// One workgroup of 64 lanes per instance; instances without tiles and
+// transmissive ones return.
+__global__ void __launch_bounds__(64) k_adjoint_wide_fold(AdjWideArgs a)
+{
+    const int k = blockIdx.x;
+    if (a.inst_ntiles[k] < 1) return;
+    const int N = a.ncells[k];
+    const long long off = a.offsets[k], P = a.total;
+    if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) return;
+    const int bc = inst_bc(a.bc_inst, a.bc, k);
+    if (bc != ASE_BC_PERIODIC && bc != ASE_BC_REFLECTIVE) return;   // folded by its boundary tiles
+    if (a.stage == 0) {
+        double *lam = a.lam + off;
+        for (int kk = threadIdx.x; kk < 2 * a.ng; kk += 64) {
+            const int I = kk < a.ng ? kk : N + kk;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) lam[v * P + I] = 0.0;
+        }
+        return;
+    }
+    if (a.q >= adj_nact(a, k)) return;
+    double *out = (a.stage == 3 ? a.mu2 : a.stage == 2 ? a.mu1 : a.lam) + off;
+    adj_fold(out, P, N, a.ng, bc);
 }
 
 // J_k = dx_k sum_i p_i over the interior of each instance and its gradient
@@ -2314,6 +2447,44 @@ void launch_batched_wide(const WideLaunch &wl, hipStream_t st)
         }
     }
 #undef ASE_WIDE
+}
+
+void launch_adjoint_wide(const AdjWideLaunch &wl, hipStream_t st)
+{
+    AdjWideArgs a;
+    a.offsets = wl.offsets; a.ncells = wl.ncells; a.dx = wl.dx; a.dt_hist = wl.dt_hist;
+    a.lam = wl.lam; a.mu1 = wl.mu1; a.mu2 = wl.mu2; a.tapeU = wl.tapeU; a.tapeS = wl.tapeS;
+    a.bc_inst = wl.bc_inst; a.tile_inst = wl.tile_inst; a.tile_i0 = wl.tile_i0; a.inst_ntiles = wl.inst_ntiles;
+    a.total = wl.total; a.ninst = wl.ninst; a.ntiles = wl.ntiles; a.ng = wl.ng; a.nsteps = wl.nsteps;
+    a.bc = wl.bc; a.mc = wl.mc;
+    // the fold launches have work only for periodic and reflective instances
+    const bool folds = wl.bc_inst != nullptr || wl.bc == ASE_BC_PERIODIC || wl.bc == ASE_BC_REFLECTIVE;
+    // steps back, each as its three transposed stages and their folds
+    for (int q = wl.nsteps - 1; q >= 0; --q) {
+        for (int stage = 3; stage >= 1; --stage) {
+            a.q = q;
+            a.stage = stage;
+            if (wl.threads == 512) {
+                switch (wl.R) {
+                case 1: k_adjoint_wide<1, 512><<<wl.ntiles, 512, 0, st>>>(a); break;
+                case 2: k_adjoint_wide<2, 512><<<wl.ntiles, 512, 0, st>>>(a); break;
+                case 3: k_adjoint_wide<3, 512><<<wl.ntiles, 512, 0, st>>>(a); break;
+                default: k_adjoint_wide<4, 512><<<wl.ntiles, 512, 0, st>>>(a); break;
+                }
+            } else {
+                switch (wl.R) {
+                case 1: k_adjoint_wide<1, 256><<<wl.ntiles, 256, 0, st>>>(a); break;
+                case 2: k_adjoint_wide<2, 256><<<wl.ntiles, 256, 0, st>>>(a); break;
+                case 3: k_adjoint_wide<3, 256><<<wl.ntiles, 256, 0, st>>>(a); break;
+                default: k_adjoint_wide<4, 256><<<wl.ntiles, 256, 0, st>>>(a); break;
+                }
+            }
+            if (folds) k_adjoint_wide_fold<<<wl.ninst, 64, 0, st>>>(a);
+        }
+    }
+    a.q = 0;
+    a.stage = 0;
+    if (folds) k_adjoint_wide_fold<<<wl.ninst, 64, 0, st>>>(a);
 }
 
 void launch_adjoint(const AdjLaunch &al, hipStream_t st)

@@ -31,6 +31,7 @@ void launch_batched(const BatchLaunch &, hipStream_t) {}
 void launch_batched_wide(const WideLaunch &, hipStream_t) {}
 int noalloc_scratch(void **ptr) { *ptr = nullptr; return ASE_OK; }
 void launch_adjoint(const AdjLaunch &, hipStream_t) {}
+void launch_adjoint_wide(const AdjWideLaunch &, hipStream_t) {}
 void launch_objective(const ObjLaunch &, hipStream_t) {}
 void launch_gks1d(int, int, const Gks1DArgs &, hipStream_t) {}
 void launch_gks2d(int, int, bool, const Gks2DArgs &, hipStream_t) {}
@@ -165,6 +166,15 @@ int main()
                                1, 256, ASE_ADJ_TAPE | ASE_ADJ_REVERSE, dummy, 1 << 20, nullptr) == ASE_ERR_ARG);
     EXPECT(ase_adjoint_batched(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy, dummy, 1,
                                dummy, &n1, &n1, 1, 256, 0, dummy, 1 << 20, nullptr) == ASE_ERR_ARG);
+    EXPECT(ase_adjoint_batched_wide(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                    dummy, 1, dummy, &n1, &n1, 1, 256, &n1, &n1, &n1, 1, 384, dummy, 1 << 30,
+                                    nullptr) == ASE_ERR_ARG);
+    EXPECT(ase_adjoint_batched_wide(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                    dummy, 1, dummy, &n1, &n1, 1, 256, nullptr, &n1, &n1, 1, 256, dummy, 1 << 30,
+                                    nullptr) == ASE_ERR_ARG);
+    EXPECT(ase_adjoint_batched_wide(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                    dummy, 1, dummy, &n1, &n1, 1, 256, &n1, &n1, &n1, 1, 256, dummy, 64,
+                                    nullptr) == ASE_ERR_WORKSPACE);
     EXPECT(ase_pressure_objective(nullptr, 1, &off, &n1, dummy, 5, 20, dummy, nullptr, nullptr, nullptr,
                                   nullptr) != ASE_OK);
     EXPECT(ase_profile_read(99, nullptr, nullptr) != ASE_OK);

@@ -1,0 +1,97 @@
+"""Wide form of the batched reverse sweep (ase_adjoint_batched_wide): the
+large instances run back as one launch per step and transposed stage over
+their tiles, the others in the persistent launch.  The adjoint must equal the
+persistent reverse sweep's (ase_adjoint_batched) bit for bit, and so must
+the gradients of the autograd wrapper built on it."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_05489_amd import adjoint as A
+from paper_2410_05489_amd import ase
+from paper_2410_05489_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _segment(b, nsteps, stop=None):
+    """Checkpoint (U0, sigma0) and the recorded time steps of nsteps steps of
+    batch b; stop = (k, q): instance k takes only q steps of the segment."""
+    sim = ase.BatchedSimulation(b, DEV, nbins=3)
+    U0 = sim.U.clone()
+    sig0 = sim.sig.clone()
+    hist = torch.zeros((nsteps, b.ninst), dtype=torch.float64, device=DEV)
+    sim.run(nsteps, dt_hist=hist)
+    torch.cuda.synchronize()
+    if stop is not None:
+        k, q = stop
+        hist[q:, k] = 0.0
+    return sim, U0, sig0, hist
+
+
+def _reverse_pair(b, nsteps, min_cells, adj_threads, wide_threads, stop=None, seed=3):
+    sim, U0, sig0, hist = _segment(b, nsteps, stop)
+    lam0 = torch.tensor(np.random.default_rng(seed).standard_normal((3, b.total)), device=DEV)
+    nbins = 4
+    full = ase.device_plan(b.ncells, nbins, DEV)
+    wplan = ase.wide_plan_device(b.ncells, min_cells, b.params.order, wide_threads, nbins, DEV)
+    assert wplan["nwide"] > 0 and wplan["nwide"] < b.ninst
+    ws = ase.Workspace(ase.adjoint_batched_workspace_bytes(b.total, nsteps), DEV)
+    print(f"ninst={b.ninst} order={b.params.order} nsteps={nsteps} min_cells={min_cells} "
+          f"adj_threads={adj_threads} wide_threads={wide_threads} nwide={wplan['nwide']} "
+          f"ntiles={wplan['ntiles']} stop={stop}", flush=True)
+    a = lam0.clone()
+    ase.adjoint_batched(sim, U0, sig0, hist, nsteps, a, ws, adj_threads, full)
+    w = lam0.clone()
+    ase.adjoint_batched(sim, U0, sig0, hist, nsteps, w, ws, adj_threads, full, phase=ase.ADJ_TAPE)
+    ase.adjoint_batched_wide(sim, U0, sig0, hist, nsteps, w, ws, adj_threads, wplan)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), w.cpu().numpy()
+
+
+@pytest.mark.parametrize("order,adj_threads,wide_threads", [(9, 512, 256), (9, 256, 512), (5, 256, 256),
+                                                            (3, 128, 256), (7, 512, 512)])
+def test_wide_reverse_equals_persistent_mixed_boundaries(order, adj_threads, wide_threads):
+    """Periodic, transmissive and reflective instances of 20..2500 cells;
+    those of 700 and more run back in the wide form; one of them stops two
+    steps into the segment."""
+    b = WL.batched_mixed(ninst=12, nmin=20, nmax=2500, order=order, seed=31, nsteps=4)
+    big = int(np.argmax(b.ncells))
+    a, w = _reverse_pair(b, 4, 700, adj_threads, wide_threads, stop=(big, 2))
+    print(f"non-finite adjoint entries: {int((~np.isfinite(a)).sum())}", flush=True)
+    assert np.array_equal(a, w, equal_nan=True)
+
+
+def test_wide_autograd_gradient_equals_persistent():
+    """The autograd wrapper with the wide forward and the wide reverse sweep
+    (overlapped tape recomputation, checkpoints every 3 steps) gives the
+    persistent wrapper's forward state and gradient bit for bit."""
+    b = WL.batched_riemann(ninst=14, nmin=40, nmax=3000, order=9, seed=21, nsteps=11)
+    outs = []
+    for wide in (0, 800):
+        run = A.BatchedAdjoint(b, DEV, nbins=5, every=3, adj_threads=512, wide_min_cells=wide,
+                               adj_wide_min_cells=wide)
+        U0 = torch.tensor(b.U, device=DEV, requires_grad=True)
+        UN = run.run(U0, b.nsteps)
+        run.pressure(UN).sum().backward()
+        torch.cuda.synchronize()
+        outs.append((UN.detach().cpu().numpy(), U0.grad.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0], equal_nan=True)
+    assert np.array_equal(outs[0][1], outs[1][1], equal_nan=True)
+
+
+def test_wide_autograd_full_batch():
+    """The 256-instance batch (64..4096 cells, order 9), 20 steps with
+    checkpoints every 10, instances of 768 cells and more in both wide forms:
+    the gradient of the persistent wrapper bit for bit."""
+    b = WL.batched_riemann(nsteps=20)
+    grads = []
+    for wide in (0, 768):
+        run = A.BatchedAdjoint(b, DEV, nbins=256, every=10, adj_threads=512, adj_nbins=256,
+                               wide_min_cells=wide, adj_wide_min_cells=wide)
+        U0 = torch.tensor(b.U, device=DEV, requires_grad=True)
+        run.pressure(run.run(U0, b.nsteps)).sum().backward()
+        torch.cuda.synchronize()
+        grads.append(U0.grad.cpu().numpy())
+    assert np.array_equal(grads[0], grads[1], equal_nan=True)

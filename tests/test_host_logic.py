@@ -42,14 +42,18 @@ def test_autotuner_picks_the_fastest_shape_and_caches_it(tmp_path, monkeypatch):
              (256, 1024): 1.9}
     calls = []
 
-    def fake_time(batch, nbins, threads, nsteps, device="cuda"):
-        calls.append((nbins, threads))
-        return times[(nbins, threads)]
+    def fake_time(batch, nbins, threads, nsteps, device="cuda", min_cells=0, wide_threads=256):
+        calls.append((nbins, threads, min_cells))
+        # the wide splits (bins capped at the instance count) are all slower here
+        return times[(nbins, threads)] if min_cells == 0 else 5.0 + min_cells / 1e4
 
     monkeypatch.setattr(autotune, "time_batched", fake_time)
     best = autotune.tune_batched(b, nsteps=4)
-    assert (best["nbins"], best["threads"]) == (256, 512) and best["ms"] == 1.75
-    assert sorted(calls) == sorted(times)
+    assert (best["nbins"], best["threads"], best["min_cells"]) == (256, 512, 0) and best["ms"] == 1.75
+    assert sorted(c[:2] for c in calls if c[2] == 0) == sorted(times)
+    # first-order DF source: the wide splits were timed as well, bins capped
+    wide = [c for c in calls if c[2] > 0]
+    assert len(wide) == len(autotune.WIDE_CANDIDATES) and all(c[0] <= b.ninst for c in wide)
     stored = json.load(open(tmp_path / "tune.json"))
     assert stored[autotune.batched_key(b)]["threads"] == 512
 
@@ -59,6 +63,16 @@ def test_autotuner_picks_the_fastest_shape_and_caches_it(tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "time_batched", no_timing)
     again = autotune.tune_batched(b, nsteps=4)
     assert (again["nbins"], again["threads"]) == (256, 512)
+    # a wide split that wins is what the tuner hands back
+    monkeypatch.setattr(autotune, "time_batched",
+                        lambda batch, nbins, threads, nsteps, device="cuda", min_cells=0, wide_threads=256:
+                        1.0 if (min_cells, wide_threads) == (1024, 512) else 2.0)
+    w = autotune.tune_batched(b, nsteps=4, use_cache=False)
+    assert (w["min_cells"], w["wide_threads"], w["ms"]) == (1024, 512, 1.0)
+    # the Gauss-point DF source has no wide form
+    b.params.df_source = 0
+    g = autotune.tune_batched(b, nsteps=4, use_cache=False)
+    assert all(t["min_cells"] == 0 for t in g["trials"])
     # a different batch shape is a different key
     b2 = WL.batched_riemann(ninst=13, nmin=16, nmax=200, nsteps=3)
     assert autotune.batched_key(b2) != autotune.batched_key(b)
