@@ -400,8 +400,10 @@ def measure_adjoint(nsteps=100, every=10, reps=3):
     instances of 64..4096 cells, order 9, `nsteps` steps; J = sum_k dx_k sum p
     at the final time; gradient with respect to the initial state through the
     autograd wrapper (checkpoints every `every` steps).  Forward = the plain
-    persistent launch of nsteps steps; backward = J.sum().backward()
-    (objective gradient + one ase_adjoint_batched launch per segment)."""
+    batched run of nsteps steps; backward = J.sum().backward() (objective
+    gradient + the tape and reverse launches of each segment).  Two pairs:
+    the fastest forward and backward (each autotuned, the wide forms
+    included), which gives the ratio, and the persistent launches alone."""
     import numpy as np
     import torch
     from paper_2410_05489_amd import adjoint as A
@@ -418,73 +420,71 @@ def measure_adjoint(nsteps=100, every=10, reps=3):
     keep = np.flatnonzero(st.cpu().numpy() == 0)
     del probe
     b = WL.batch_subset(b_all, keep)
-    # the adjoint's own forward (tape re-runs and checkpoints) is the
-    # persistent launch: the ratio is taken against that form
-    fwd = autotune.tune_batched(b, nsteps=10, use_cache=False, wide=False)
-    adj = autotune.tune_adjoint(b, every=every, use_cache=False, fwd_shape=(fwd["nbins"], fwd["threads"]))
-    run = A.BatchedAdjoint(b, "cuda", nbins=fwd["nbins"], threads=fwd["threads"], adj_threads=adj["threads"],
-                           every=every, adj_nbins=adj["nbins"])
-    plain = ase.BatchedSimulation(b, "cuda", nbins=fwd["nbins"], threads=fwd["threads"])
+    fwd = autotune.tune_batched(b, nsteps=10, use_cache=False)
+    fwd_p = min((t for t in fwd["trials"] if t["min_cells"] == 0), key=lambda t: t["ms"])
+    adj = autotune.tune_adjoint(b, every=every, use_cache=False, fwd_shape=(fwd_p["nbins"], fwd_p["threads"]))
+    adj_p = min((t for t in adj["trials"] if t["min_cells"] == 0), key=lambda t: t["ms"])
     U0 = torch.tensor(b.U, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    t_plain, t_fwd, t_bwd = [], [], []
-    for rep in range(reps + 1):
-        plain.U.copy_(U0)
-        plain.t.zero_()
-        torch.cuda.synchronize()
-        ev[0].record()
-        plain.run(nsteps)
-        ev[1].record()
-        x = U0.clone().requires_grad_(True)
-        torch.cuda.synchronize()
-        ev[2].record()
-        J = run.pressure(run.run(x, nsteps))
-        ev[3].record()
-        if rep == reps:
-            ase.profile_enable(True)
-        ev[4].record()
-        J.sum().backward()
-        ev[5].record()
-        torch.cuda.synchronize()
-        if rep > 0:
-            t_plain.append(ev[0].elapsed_time(ev[1]))
-            t_fwd.append(ev[2].elapsed_time(ev[3]))
-            t_bwd.append(ev[4].elapsed_time(ev[5]))
+    med = lambda a: sorted(a)[len(a) // 2]   # noqa: E731
+
+    def timed(f, a, profile):
+        """Median (plain forward, forward with checkpoints, backward) ms of
+        forward shape f and adjoint shape a; the gradient and objective of
+        the last repetition."""
+        run = A.BatchedAdjoint(b, "cuda", nbins=f["nbins"], threads=f["threads"], adj_threads=a["threads"],
+                               every=every, adj_nbins=a["nbins"], wide_min_cells=f["min_cells"],
+                               wide_threads=f["wide_threads"] or 256, adj_wide_min_cells=a["min_cells"],
+                               adj_wide_threads=a["wide_threads"] or 256)
+        plain = ase.BatchedSimulation(b, "cuda", nbins=f["nbins"], threads=f["threads"],
+                                      wide_min_cells=f["min_cells"], wide_threads=f["wide_threads"] or 256)
+        t_plain, t_fwd, t_bwd = [], [], []
+        for rep in range(reps + 1):
+            plain.U.copy_(U0)
+            plain.t.zero_()
+            torch.cuda.synchronize()
+            ev[0].record()
+            plain.run(nsteps)
+            ev[1].record()
+            x = U0.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            ev[2].record()
+            J = run.pressure(run.run(x, nsteps))
+            ev[3].record()
+            if profile and rep == reps:
+                ase.profile_enable(True)
+            ev[4].record()
+            J.sum().backward()
+            ev[5].record()
+            torch.cuda.synchronize()
+            if rep > 0:
+                t_plain.append(ev[0].elapsed_time(ev[1]))
+                t_fwd.append(ev[2].elapsed_time(ev[3]))
+                t_bwd.append(ev[4].elapsed_time(ev[5]))
+        return med(t_plain), med(t_fwd), med(t_bwd), J.detach().cpu().numpy(), x.grad.cpu().numpy()
+
+    tp, tf, tb, Jh, gh = timed(fwd, adj, True)
     kms, kn = ase.profile_read("adjoint")
     ase.profile_enable(False)
-    Jh = J.detach().cpu().numpy()
-    gh = x.grad.cpu().numpy()
+    pp, pf, pb, _, _ = timed(fwd_p, adj_p, False)
     ok = 0
     for k in range(b.ninst):
         o, n = int(b.offsets[k]), int(b.ncells[k])
         ok += int(bool(np.isfinite(Jh[k])) and bool(np.isfinite(gh[:, o:o + n + 2 * b.ng]).all()))
-    med = lambda a: sorted(a)[len(a) // 2]   # noqa: E731
-    tp, tf, tb = med(t_plain), med(t_fwd), med(t_bwd)
-    # the fastest forward of the same batch (the wide form where it wins)
-    wbest = autotune.tune_batched(b, nsteps=10, use_cache=False)
-    fast = ase.BatchedSimulation(b, "cuda", nbins=wbest["nbins"], threads=wbest["threads"],
-                                 wide_min_cells=wbest["min_cells"], wide_threads=wbest["wide_threads"] or 256)
-    t_fast = []
-    for rep in range(reps + 1):
-        fast.U.copy_(U0)
-        fast.t.zero_()
-        torch.cuda.synchronize()
-        ev[0].record()
-        fast.run(nsteps)
-        ev[1].record()
-        torch.cuda.synchronize()
-        if rep > 0:
-            t_fast.append(ev[0].elapsed_time(ev[1]))
-    tw = med(t_fast)
+    form = lambda t: "persistent + wide" if t["min_cells"] else "persistent"   # noqa: E731
     return {"workload": f"batched_riemann_{b_all.ninst}x64..4096_r9_seed0", "instances_timed": b.ninst,
             "instances_lost": [int(k) for k in np.flatnonzero(st.cpu().numpy() != 0)],
             "steps": nsteps, "checkpoint_every": every,
             "cells": int(b.ncells.sum()), "forward_ms": round(tp, 3), "forward_with_checkpoints_ms": round(tf, 3),
             "backward_ms": round(tb, 3), "adjoint_fwd_ratio": round(tb / tp, 3),
-            "fastest_forward_ms": round(tw, 3), "fastest_forward_form": "persistent + wide" if wbest["min_cells"]
-            else "persistent", "adjoint_fastest_fwd_ratio": round(tb / tw, 3),
-            "adjoint_kernel_ms_per_segment": round(kms / max(kn, 1), 3),
-            "forward_shape": [fwd["nbins"], fwd["threads"]], "adjoint_shape": [adj["nbins"], adj["threads"]],
+            "forward_form": form(fwd), "adjoint_form": form(adj),
+            "forward_shape": [fwd["nbins"], fwd["threads"], fwd["min_cells"], fwd["wide_threads"]],
+            "adjoint_shape": [adj["nbins"], adj["threads"], adj["min_cells"], adj["wide_threads"]],
+            "adjoint_ms_per_segment_call": round(kms / max(kn, 1), 3),
+            "persistent_only": {"forward_ms": round(pp, 3), "forward_with_checkpoints_ms": round(pf, 3),
+                                "backward_ms": round(pb, 3), "adjoint_fwd_ratio": round(pb / pp, 3),
+                                "forward_shape": [fwd_p["nbins"], fwd_p["threads"]],
+                                "adjoint_shape": [adj_p["nbins"], adj_p["threads"]]},
             "instances_finite": ok, "adjoint_trials": adj["trials"]}
 
 

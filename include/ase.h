@@ -367,9 +367,10 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
  * copies of the tile arrays, ntiles and threads_wide (256 or 512, as
  * planned).  The call returns once both streams' work is queued; the
  * caller's stream waits for the second stream's before the final launch,
- * so work queued behind the call on `stream` sees every result.  Calls from
- * several host threads are serialised on the library's stream of each
- * device. */
+ * so work queued behind the call on `stream` sees every result.  The
+ * library keeps one second stream (and two events) per device and caller
+ * stream, created on first use and held until the process ends; calls on
+ * different caller streams run concurrently. */
 int ase_batched_plan_wide(int32_t ninst, const int32_t *ncells, int32_t min_cells, int32_t order,
                           int32_t threads_wide, int32_t nbins, int32_t *bin_start, int32_t *bin_list,
                           int32_t *tile_inst, int32_t *tile_i0, int32_t *inst_tile0, int32_t *inst_ntiles,
@@ -465,27 +466,27 @@ int ase_adjoint_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_ins
                         const int32_t *bin_start, const int32_t *bin_list, int32_t nbins, int32_t threads,
                         int32_t phase, void *ws, size_t ws_bytes, void *stream);
 
-/* Reverse phase of ase_adjoint_batched with the instances of a wide plan
- * (ase_batched_plan_wide) split: the binned instances run back in the
- * persistent launch, each tiled instance as one launch per step and
- * transposed stage over its tiles (plus a launch that adds its ghost
- * gradients onto the cells the ghosts copy), on the library's second stream
- * beside the persistent launch.  The tape must come from an
- * ASE_ADJ_TAPE call of ase_adjoint_batched with a plan of EVERY instance,
- * into the same workspace, for the same segment.  Arguments as
- * ase_adjoint_batched (bins: the wide plan's, which hold only the untiled
- * instances; no phase argument) plus device copies of tile_inst, tile_i0 and
- * inst_ntiles, ntiles and threads_wide (256 or 512; it sets the tile length
- * threads_wide - order - 1 the plan was made for).  lam equals
- * ase_adjoint_batched's bit for bit.  Work queued behind the call on
- * `stream` sees every result. */
+/* ase_adjoint_batched with the instances of a wide plan
+ * (ase_batched_plan_wide) split (first-order DF source): the binned
+ * instances run in the persistent launch, each tiled instance as one launch
+ * per step and forward stage over its tiles (tape phase) and one per step
+ * and transposed stage (reverse phase; plus, for periodic and reflective
+ * instances, a launch that adds the ghost gradients onto the cells the
+ * ghosts copy), on the library's second stream for `stream` (as in
+ * ase_step_batched_wide) beside the persistent launch.  Arguments as ase_adjoint_batched (bins: the wide plan's, which
+ * hold only the untiled instances) plus device copies of tile_inst, tile_i0
+ * and inst_ntiles, ntiles and threads_wide (256 or 512; it sets the tile
+ * length threads_wide - order - 1 the plan was made for).  A reverse phase
+ * needs the tape of a tape phase of this call with the same plan and
+ * segment in the same workspace.  lam equals ase_adjoint_batched's bit for
+ * bit.  Work queued behind the call on `stream` sees every result. */
 int ase_adjoint_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, int32_t ninst,
                              const int64_t *offsets, const int32_t *ncells, const double *dx, int32_t ng,
                              int64_t total, const double *U_ck, const double *sigma_ck, const double *dt_hist,
                              int32_t nsteps, double *lam, const int32_t *bin_start, const int32_t *bin_list,
                              int32_t nbins, int32_t threads, const int32_t *tile_inst, const int32_t *tile_i0,
-                             const int32_t *inst_ntiles, int32_t ntiles, int32_t threads_wide, void *ws,
-                             size_t ws_bytes, void *stream);
+                             const int32_t *inst_ntiles, int32_t ntiles, int32_t threads_wide, int32_t phase,
+                             void *ws, size_t ws_bytes, void *stream);
 
 /* Objective of the adjoint runs: J_k = dx_k sum_i p_i over the interior cells
  * of each instance (p from the Euler equation of state, Sec. 2.3), and the

@@ -53,14 +53,8 @@ class _BatchedRun(torch.autograd.Function):
                 ase.adjoint_batched(runner.sim, ckU[s], ckS[s], h, n, lam, ws, runner.adj_threads, runner.adj_plan,
                                     stream=stream, phase=phase)
                 return
-            # the tape of every instance in the persistent launch, the
-            # reverse sweep with the large instances in the wide form
-            if phase & ase.ADJ_TAPE:
-                ase.adjoint_batched(runner.sim, ckU[s], ckS[s], h, n, lam, ws, runner.adj_threads,
-                                    runner.adj_plan, stream=stream, phase=ase.ADJ_TAPE)
-            if phase & ase.ADJ_REVERSE:
-                ase.adjoint_batched_wide(runner.sim, ckU[s], ckS[s], h, n, lam, ws, runner.adj_threads,
-                                         runner.wide_plan, stream=stream)
+            ase.adjoint_batched_wide(runner.sim, ckU[s], ckS[s], h, n, lam, ws, runner.adj_threads,
+                                     runner.wide_plan, stream=stream, phase=phase)
 
         if not runner.overlap or len(segs) < 2:
             for s in segs:

@@ -110,7 +110,7 @@ def lib():
                                       C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_adjoint_batched_wide.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp,
                                            vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32,
-                                           C.c_int32, vp, C.c_size_t, vp]
+                                           C.c_int32, C.c_int32, vp, C.c_size_t, vp]
     L.ase_pressure_objective.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp]
     L.ase_gks_flux.argtypes = [vp, vp, C.c_int32, dp, dp, dp, dp, C.c_double, dp, dp, vp]
     L.ase_gks_workspace_bytes.restype = C.c_size_t
@@ -545,18 +545,18 @@ def wide_plan_device(ncells, min_cells: int, order: int, threads_wide: int, nbin
 
 
 def adjoint_batched_wide(sim: "BatchedSimulation", U_ck, sig_ck, dt_hist, nsteps: int, lam, ws: Workspace,
-                         threads: int, wplan: dict, stream=None):
-    """Reverse phase of adjoint_batched with the tiled instances of wplan
-    (wide_plan_device) in the wide form; the tape in ws comes from an
-    ADJ_TAPE call of adjoint_batched with a plan of every instance."""
+                         threads: int, wplan: dict, stream=None, phase: int = ADJ_TAPE | ADJ_REVERSE):
+    """adjoint_batched with the tiled instances of wplan (wide_plan_device)
+    in the wide form; a reverse phase reads the tape a tape phase of the
+    same plan left in ws."""
     b = sim.b
     w = wplan
     _check(lib().ase_adjoint_batched_wide(
         C.byref(c_params(sim.p)), b.bc, _p(sim.bc_inst), b.ninst, _p(sim.offsets), _p(sim.ncells), _p(sim.dx),
         b.ng, b.total, _p(U_ck), _p(sig_ck), _p(dt_hist), int(nsteps), _p(lam), _p(w["bin_start"]),
         _p(w["bin_list"]), int(w["nbins"]), int(threads), _p(w["tile_inst"]), _p(w["tile_i0"]),
-        _p(w["inst_ntiles"]), int(w["ntiles"]), int(w["threads"]), ws.ptr, ws.nbytes, _stream(stream)),
-        "ase_adjoint_batched_wide")
+        _p(w["inst_ntiles"]), int(w["ntiles"]), int(w["threads"]), int(phase), ws.ptr, ws.nbytes,
+        _stream(stream)), "ase_adjoint_batched_wide")
 
 
 def pressure_objective(p, offsets, ncells, dx, ng: int, total: int, U, J=None, lam=None, weights=None,

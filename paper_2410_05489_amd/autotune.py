@@ -108,13 +108,22 @@ def tune_batched(batch, nsteps: int = 10, candidates: Optional[Sequence[Tuple[in
 
 
 ADJOINT_CANDIDATES: Sequence[Tuple[int, int]] = ((256, 256), (256, 512), (512, 256), (512, 512), (1024, 256))
+# (min_cells, wide_threads) of the wide reverse sweep, beside the best
+# persistent shape
+ADJOINT_WIDE_CANDIDATES: Sequence[Tuple[int, int]] = ((400, 256), (768, 256), (1536, 256))
 
 
 def tune_adjoint(batch, every: int = 10, candidates: Optional[Sequence[Tuple[int, int]]] = None,
-                 use_cache: bool = True, fwd_shape: Tuple[int, int] = (256, 256)) -> dict:
-    """Best {'nbins', 'threads', 'ms'} for one adjoint segment of `every`
-    steps of this batch (cached)."""
-    key = f"{_arch()}/adjoint/r{batch.params.order}/n{batch.ninst}/c{batch.total}/s{every}"
+                 use_cache: bool = True, fwd_shape: Tuple[int, int] = (256, 256),
+                 wide_candidates: Optional[Sequence[Tuple[int, int]]] = None) -> dict:
+    """Best {'nbins', 'threads', 'min_cells', 'wide_threads', 'ms'} for one
+    adjoint segment of `every` steps of this batch (cached): the persistent
+    shapes, then (first-order DF source) the wide reverse sweep beside the
+    best of them; min_cells 0 is the persistent sweep alone.  The time is
+    that of the reverse phase while the next tape phase runs on a second
+    stream, as in the autograd backward, whose length the reverse phases
+    set ('tape_ms': the tape phase alone)."""
+    key = f"{_arch()}/adjoint2/r{batch.params.order}/n{batch.ninst}/c{batch.total}/s{every}"
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
         return cache[key]
@@ -126,16 +135,40 @@ def tune_adjoint(batch, every: int = 10, candidates: Optional[Sequence[Tuple[int
     lam = torch.ones((3, batch.total), dtype=torch.float64, device="cuda")
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
+    mid = torch.cuda.Event(enable_timing=True)
+    ws2 = ase.Workspace(ws.nbytes)
+    side = torch.cuda.Stream()
+
+    def timed(call):
+        """(tape ms, reverse ms beside a tape into the other workspace) of
+        the second of two rounds; call(ws, phase, stream)."""
+        for rep in range(2):
+            start.record()
+            call(ws, ase.ADJ_TAPE, None)
+            mid.record()
+            side.wait_event(mid)
+            with torch.cuda.stream(side):
+                call(ws2, ase.ADJ_TAPE, side)
+            call(ws, ase.ADJ_REVERSE, None)
+            stop.record()
+            torch.cuda.synchronize()
+        return start.elapsed_time(mid), mid.elapsed_time(stop)
+
     trials = []
     for nbins, threads in (candidates or ADJOINT_CANDIDATES):
         plan = ase.device_plan(batch.ncells, nbins)
-        ase.adjoint_batched(sim, U0, s0, hist, every, lam, ws, threads, plan)
-        torch.cuda.synchronize()
-        start.record()
-        ase.adjoint_batched(sim, U0, s0, hist, every, lam, ws, threads, plan)
-        stop.record()
-        torch.cuda.synchronize()
-        trials.append({"nbins": nbins, "threads": threads, "ms": start.elapsed_time(stop)})
+        tt, tr = timed(lambda w, ph, stm: ase.adjoint_batched(sim, U0, s0, hist, every, lam, w, threads, plan,
+                                                              stream=stm, phase=ph))
+        trials.append({"nbins": nbins, "threads": threads, "min_cells": 0, "wide_threads": 0, "ms": tr,
+                       "tape_ms": tt})
+    if batch.params.df_source == 1:
+        pb = min(trials, key=lambda r: r["ms"])
+        for mc, wt in (wide_candidates or ADJOINT_WIDE_CANDIDATES):
+            wplan = ase.wide_plan_device(batch.ncells, mc, batch.params.order, wt, pb["nbins"])
+            tt, tr = timed(lambda w, ph, stm: ase.adjoint_batched_wide(sim, U0, s0, hist, every, lam, w,
+                                                                       pb["threads"], wplan, stream=stm, phase=ph))
+            trials.append({"nbins": pb["nbins"], "threads": pb["threads"], "min_cells": mc, "wide_threads": wt,
+                           "ms": tr, "tape_ms": tt})
     best = min(trials, key=lambda r: r["ms"])
     best = dict(best, steps=every, trials=trials)
     if use_cache:

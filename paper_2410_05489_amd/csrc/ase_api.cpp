@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <mutex>
 #include <string>
@@ -944,23 +945,24 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
     return check_launch("ase_step_batched");
 }
 
-// The library's second stream on the current device (the wide part of a
-// batched step runs there) and the events that fork it from and join it
-// back into the caller's stream.  Default priority; created once per device.
+// The library's second stream for a caller's stream on the current device
+// (the wide part of a batched call runs there) and the events that fork it
+// from and join it back into the caller's stream.  One per (device, caller
+// stream), so calls on different streams stay concurrent; default priority;
+// created on first use and kept until the process ends.
 struct SideStream {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
 static std::mutex g_side_mu;
-static std::vector<SideStream> g_side;
+static std::map<std::pair<int, hipStream_t>, SideStream> g_side;
 
-static int side_stream(SideStream **out)
+static int side_stream(hipStream_t caller, SideStream **out)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if ((size_t)dev >= g_side.size()) g_side.resize(dev + 1);
-    SideStream &ss = g_side[dev];
+    SideStream &ss = g_side[std::make_pair(dev, caller)];
     if (ss.s == nullptr) {
         e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
@@ -1016,11 +1018,10 @@ int ase_step_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_i
         } else {
             // the wide instances on the second stream, forked from the
             // caller's stream before the persistent launch (so the two run
-            // side by side) and joined back into it (one call's sequence at a
-            // time on the second stream)
+            // side by side) and joined back into it
             std::lock_guard<std::mutex> lk(g_side_mu);
             SideStream *ss = nullptr;
-            rc = side_stream(&ss);
+            rc = side_stream(st, &ss);
             if (rc) return rc;
             hipError_t e = hipEventRecord(ss->fork, st);
             if (e == hipSuccess) e = hipStreamWaitEvent(ss->s, ss->fork, 0);
@@ -1233,13 +1234,15 @@ int ase_adjoint_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *b
                              int64_t total, const double *U_ck, const double *sigma_ck, const double *dt_hist,
                              int32_t nsteps, double *lam, const int32_t *bin_start, const int32_t *bin_list,
                              int32_t nbins, int32_t threads, const int32_t *tile_inst, const int32_t *tile_i0,
-                             const int32_t *inst_ntiles, int32_t ntiles, int32_t threads_wide, void *ws,
-                             size_t ws_bytes, void *stream)
+                             const int32_t *inst_ntiles, int32_t ntiles, int32_t threads_wide, int32_t phase,
+                             void *ws, size_t ws_bytes, void *stream)
 {
     AdjLaunch al;
     int rc = adjoint_setup(p, bc, bc_inst, ninst, offsets, ncells, dx, ng, total, U_ck, sigma_ck, dt_hist, nsteps,
-                           lam, bin_start, bin_list, nbins, threads, ASE_ADJ_REVERSE, ws, ws_bytes, &al);
+                           lam, bin_start, bin_list, nbins, threads, phase, ws, ws_bytes, &al);
     if (rc) return rc;
+    if (!(p->flags & ASE_FLAG_DF_FIRST_ORDER))
+        return fail(ASE_ERR_ARG, "the wide batched form needs the first-order DF source (ASE_FLAG_DF_FIRST_ORDER)");
     if (ntiles < 0) return fail(ASE_ERR_ARG, "ntiles must be >= 0");
     if (threads_wide != 256 && threads_wide != 512) return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512");
     if (!inst_ntiles || (ntiles > 0 && (!tile_inst || !tile_i0))) return fail(ASE_ERR_ARG, "null tile arrays");
@@ -1247,7 +1250,7 @@ int ase_adjoint_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *b
     hipStream_t st = (hipStream_t)stream;
     AdjWideLaunch wl;
     std::memset(&wl, 0, sizeof(wl));
-    wl.offsets = al.offsets; wl.ncells = ncells; wl.dx = dx; wl.dt_hist = dt_hist;
+    wl.offsets = al.offsets; wl.ncells = ncells; wl.dx = dx; wl.dt_hist = dt_hist; wl.ck_U = U_ck;
     wl.lam = lam; wl.mu1 = al.mu1; wl.mu2 = al.mu2; wl.tapeU = al.tapeU; wl.tapeS = al.tapeS;
     wl.bc_inst = bc_inst; wl.tile_inst = tile_inst; wl.tile_i0 = tile_i0; wl.inst_ntiles = inst_ntiles;
     wl.total = total; wl.ninst = ninst; wl.ntiles = ntiles; wl.threads = threads_wide; wl.R = al.R; wl.ng = ng;
@@ -1261,13 +1264,14 @@ int ase_adjoint_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *b
             // the persistent launch and joined back after the last fold
             std::lock_guard<std::mutex> lk(g_side_mu);
             SideStream *ss = nullptr;
-            rc = side_stream(&ss);
+            rc = side_stream(st, &ss);
             if (rc) return rc;
             hipError_t e = hipEventRecord(ss->fork, st);
             if (e == hipSuccess) e = hipStreamWaitEvent(ss->s, ss->fork, 0);
             if (e != hipSuccess) return hip_fail(e, "ase_adjoint_batched_wide: fork");
             launch_adjoint(al, st);
-            launch_adjoint_wide(wl, ss->s);
+            if (phase & ASE_ADJ_TAPE) launch_tape_wide(wl, ss->s);
+            if (phase & ASE_ADJ_REVERSE) launch_adjoint_wide(wl, ss->s);
             e = hipEventRecord(ss->join, ss->s);
             if (e == hipSuccess) e = hipStreamWaitEvent(st, ss->join, 0);
             if (e != hipSuccess) return hip_fail(e, "ase_adjoint_batched_wide: join");

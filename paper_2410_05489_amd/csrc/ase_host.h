@@ -160,7 +160,7 @@ void launch_adjoint(const AdjLaunch &al, hipStream_t st);
 struct AdjWideLaunch {
     const long long *offsets;
     const int *ncells;
-    const double *dx, *dt_hist;
+    const double *dx, *dt_hist, *ck_U;
     double *lam, *mu1, *mu2, *tapeU, *tapeS;
     const int *bc_inst, *tile_inst, *tile_i0, *inst_ntiles;
     long long total;
@@ -168,6 +168,8 @@ struct AdjWideLaunch {
     MethodConst mc;
 };
 void launch_adjoint_wide(const AdjWideLaunch &wl, hipStream_t st);
+// Tape phase of the wide instances (forward stages into the tape slots).
+void launch_tape_wide(const AdjWideLaunch &wl, hipStream_t st);
 
 struct ObjLaunch {
     const long long *offsets;

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <mutex>
 
 #include "ase_device.h"
@@ -1289,6 +1290,60 @@ __device__ __forceinline__ double block_max(double v, double *red)
     return m;
 }
 
+// Stage input u (instance base, ghost slots not read) at cell x in
+// [-ng, N + ng): ghosts mapped as batched_fill copies them (periodic image,
+// wall mirror with the momentum reversed, or the boundary cell); 0 beyond.
+__device__ __forceinline__ void mapped_cell(const double *u, long long P, int N, int ng, int bc, int x,
+                                            double (&W)[3])
+{
+    double fm = 1.0;
+    const bool in_range = x >= -ng && x < N + ng;
+    if (x < 0 || x >= N) {
+        if (bc == ASE_BC_PERIODIC) x = x < 0 ? x + N : x - N;
+        else if (bc == ASE_BC_REFLECTIVE) {
+            x = x < 0 ? -1 - x : 2 * N - 1 - x;
+            fm = -1.0;
+        } else x = x < 0 ? 0 : N - 1;
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) W[v] = in_range ? u[v * P + ng + x] : 0.0;
+    W[1] *= fm;
+}
+
+// The window x in [i0-1-R, i0+T+1+R) of the stage input u into L.sU (one
+// cell per lane: the window is NT cells long) and the first-order strength
+// of the face on each window cell's right into L.sS: the neighbour's
+// primitive variables from the next lane (the last lane of a wave forms them
+// itself), as in batched_fill.  Ends with a barrier.
+template <int R, int NT>
+__device__ __forceinline__ void wide_window(const double *u, long long P, int N, int ng, int bc, int i0,
+                                            const MethodConst &mc, Lds1D<R, NT - 2 * R - 2> &L)
+{
+    constexpr int UX = Lds1D<R, NT - 2 * R - 2>::UX;
+    static_assert(UX == NT, "one window cell per lane");
+    const int tid = threadIdx.x;
+    const int ox = i0 - 1 - R;
+    double W[3];
+    mapped_cell(u, P, N, ng, bc, ox + tid, W);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) L.sU[v][tid] = W[v];
+    const Prim qa = primitives<3>(W, 0, mc);
+    Prim qb;
+    qb.p = __shfl_down(qa.p, 1);
+    qb.un = __shfl_down(qa.un, 1);
+    qb.ut = __shfl_down(qa.ut, 1);
+    qb.ic = __shfl_down(qa.ic, 1);
+    qb.c = 0.0;
+    qb.ok = __shfl_down((int)qa.ok, 1) != 0;
+    if ((tid & 63) == 63 && tid + 1 < UX) {
+        double Wb[3];
+        mapped_cell(u, P, N, ng, bc, ox + tid + 1, Wb);
+        qb = primitives<3>(Wb, 0, mc);
+    }
+    if (tid + 1 < UX) L.sS[tid] = sigma_point(qa, qb);
+    __syncthreads();
+}
+
 template <int R, int NT>
 __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
 {
@@ -1380,50 +1435,7 @@ __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
     double un[3];
     stage1d_prefetch<T, NT, MODE_FUSED_1D>(tl, i0, un);
 
-    // the window x in [i0-1-R, i0+T+1+R) of the stage input (one cell per
-    // lane: the window is NT cells long), ghosts mapped as batched_fill
-    // copies them (periodic image, wall mirror with the momentum reversed,
-    // or the boundary cell), 0 beyond the stored range
-    static_assert(UX == NT, "one window cell per lane");
-    const int bc = inst_bc(a.bc_inst, a.bc, k);
-    const int ox = i0 - 1 - R;
-    auto window_cell = [&](int lx, double(&W)[3]) {
-        int x = ox + lx;
-        double fm = 1.0;
-        const bool in_range = x >= -ng && x < N + ng;
-        if (x < 0 || x >= N) {
-            if (bc == ASE_BC_PERIODIC) x = x < 0 ? x + N : x - N;
-            else if (bc == ASE_BC_REFLECTIVE) {
-                x = x < 0 ? -1 - x : 2 * N - 1 - x;
-                fm = -1.0;
-            } else x = x < 0 ? 0 : N - 1;
-        }
-#pragma unroll
-        for (int v = 0; v < 3; ++v) W[v] = in_range ? in[v * P + off + ng + x] : 0.0;
-        W[1] *= fm;
-    };
-    double W[3];
-    window_cell(tid, W);
-#pragma unroll
-    for (int v = 0; v < 3; ++v) L.sU[v][tid] = W[v];
-    // first-order strength of the face on this cell's right: the neighbour's
-    // primitive variables from the next lane (the last lane of a wave forms
-    // them itself), as in batched_fill
-    const Prim qa = primitives<3>(W, 0, mc);
-    Prim qb;
-    qb.p = __shfl_down(qa.p, 1);
-    qb.un = __shfl_down(qa.un, 1);
-    qb.ut = __shfl_down(qa.ut, 1);
-    qb.ic = __shfl_down(qa.ic, 1);
-    qb.c = 0.0;
-    qb.ok = __shfl_down((int)qa.ok, 1) != 0;
-    if ((tid & 63) == 63 && tid + 1 < UX) {
-        double Wb[3];
-        window_cell(tid + 1, Wb);
-        qb = primitives<3>(Wb, 0, mc);
-    }
-    if (tid + 1 < UX) L.sS[tid] = sigma_point(qa, qb);
-    __syncthreads();
+    wide_window<R, NT>(in + off, P, N, ng, inst_bc(a.bc_inst, a.bc, k), i0, mc, L);
     double l;
     if (a.stage == 3) {
         stage1d_compute<R, T, NT, MODE_FUSED_1D, true>(tl, i0, mc, L, un, l);
@@ -1945,13 +1957,15 @@ struct AdjWideArgs {
     const int *ncells;
     const double *dx;
     const double *dt_hist;
+    const double *ck_U;   // checkpoint at the segment start (tape phase)
     double *lam, *mu1, *mu2;
-    const double *tapeU, *tapeS;
+    double *tapeU, *tapeS;
     const int *bc_inst;
     const int *tile_inst, *tile_i0, *inst_ntiles;
     long long total;
     int ninst, ntiles, ng, nsteps, bc;
     int q, stage;   // step, transposed stage 3, 2 or 1; stage 0: clear the ghost slots of lam
+                    // (tape kernel: forward stage 0, 1 or 2 of step q)
     MethodConst mc;
 };
 
@@ -2036,6 +2050,96 @@ __global__ void __launch_bounds__(NT, 1) k_adjoint_wide(AdjWideArgs a)
                 for (int kk = 0; kk < a.ng; ++kk) o[base + kk] = 0.0;
         }
     }
+}
+
+// Tape of the wide instances: forward stage `stage` (0, 1, 2) of step q of
+// every tile, as the tape phase of k_adjoint1d runs it, with the recorded
+// time step.  The stage input is tape slot 3q + stage (the checkpoint for
+// the first); the launch writes that slot's ghost cells and every face
+// strength the way batched_fill leaves them, the checkpoint's interior into
+// slot 0, and the stage output into the interior of the next slot (the last
+// stage of the last step taken has no output: the reverse sweep never reads
+// it).
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_tape_wide(AdjWideArgs a)
+{
+    constexpr int T = NT - 2 * R - 2;
+    constexpr int UX = Lds1D<R, T>::UX;
+    __shared__ Lds1D<R, T> L;
+    const int tid = threadIdx.x, b = blockIdx.x;
+    const int k = a.tile_inst[b], i0 = a.tile_i0[b];
+    if (k < 0 || k >= a.ninst) return;   // malformed tile entry: skipped (the whole workgroup)
+    const int N = a.ncells[k], ng = a.ng;
+    const long long off = a.offsets[k], P = a.total, SU = 3 * P;
+    if (N < T || off < 0 || off + N + 2LL * ng > P || i0 < 0 || i0 >= N) return;
+    const int q = a.q, st = a.stage;
+    const int nact = adj_nact(a, k);
+    if (q >= nact) return;
+    const int bc = inst_bc(a.bc_inst, a.bc, k);
+    const bool from_ck = q == 0 && st == 0;
+    double *slot = a.tapeU + (3LL * q + st) * SU + off;
+    double *sslot = a.tapeS + (3LL * q + st) * P + off;
+    const double *in = from_ck ? a.ck_U + off : slot;
+    const bool last_stage = st == 2 && q == nact - 1;
+
+    Tile1D tl;
+    tl.U = const_cast<double *>(in); tl.sx = nullptr; tl.sig_out = nullptr;
+    tl.Un = a.tapeU + (3LL * q) * SU + off;
+    tl.Uout = a.tapeU + (3LL * q + st + 1) * SU + off;
+    tl.wl = tl.wr = nullptr; tl.level = nullptr;
+    tl.plane = P; tl.nx = N; tl.ng = ng; tl.NX = N + 2 * ng; tl.nfaces = N + 1;
+    tl.stage = st + 1; tl.inv_dx = 1.0 / a.dx[k]; tl.dt = a.dt_hist[(long long)q * a.ninst + k];
+    double un[3];
+    stage1d_prefetch<T, NT, MODE_FUSED_1D>(tl, i0, un);
+    wide_window<R, NT>(in, P, N, ng, bc, i0, a.mc, L);
+
+    // the input slot as batched_fill leaves it: ghost cells (boundary
+    // tiles), the checkpoint's interior (slot 0), and the strength of every
+    // face x + 1/2, x in [-ng, N + ng - 1): own faces x in [i0, i0 + T),
+    // ghost faces by the boundary tiles
+    const int ox = i0 - 1 - R;
+    const bool first = i0 == 0, last = i0 + T >= N;
+    auto face = [&](int x) {
+        const int lx = x - ox;
+        if (lx >= 0 && lx + 1 < UX) return L.sS[lx];
+        double Wa[3], Wb[3];
+        mapped_cell(in, P, N, ng, bc, x, Wa);
+        mapped_cell(in, P, N, ng, bc, x + 1, Wb);
+        return sigma_point(primitives<3>(Wa, 0, a.mc), primitives<3>(Wb, 0, a.mc));
+    };
+    {
+        const int x = i0 + tid;
+        if (tid < T && x < N) {
+            sslot[x + ng] = face(x);
+            if (from_ck) {
+#pragma unroll
+                for (int v = 0; v < 3; ++v) slot[v * P + x + ng] = L.sU[v][x - ox];
+            }
+        }
+    }
+    if (first || last) {
+        for (int kk = tid; kk < ng; kk += NT) {
+            if (first) {
+                const int x = -ng + kk;
+                double W[3];
+                mapped_cell(in, P, N, ng, bc, x, W);
+#pragma unroll
+                for (int v = 0; v < 3; ++v) slot[v * P + x + ng] = W[v];
+                sslot[x + ng] = face(x);
+            }
+            if (last) {
+                const int x = N + kk;
+                double W[3];
+                mapped_cell(in, P, N, ng, bc, x, W);
+#pragma unroll
+                for (int v = 0; v < 3; ++v) slot[v * P + x + ng] = W[v];
+                if (x + 1 < N + ng) sslot[x + ng] = face(x);
+            }
+        }
+    }
+    if (last_stage) return;
+    double l;
+    stage1d_compute<R, T, NT, MODE_FUSED_1D>(tl, i0, a.mc, L, un, l);
 }
 
 // One workgroup of 64 lanes per instance; instances without tiles and
@@ -2449,9 +2553,42 @@ void launch_batched_wide(const WideLaunch &wl, hipStream_t st)
 #undef ASE_WIDE
 }
 
+void launch_tape_wide(const AdjWideLaunch &wl, hipStream_t st)
+{
+    AdjWideArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.offsets = wl.offsets; a.ncells = wl.ncells; a.dx = wl.dx; a.dt_hist = wl.dt_hist; a.ck_U = wl.ck_U;
+    a.tapeU = wl.tapeU; a.tapeS = wl.tapeS;
+    a.bc_inst = wl.bc_inst; a.tile_inst = wl.tile_inst; a.tile_i0 = wl.tile_i0; a.inst_ntiles = wl.inst_ntiles;
+    a.total = wl.total; a.ninst = wl.ninst; a.ntiles = wl.ntiles; a.ng = wl.ng; a.nsteps = wl.nsteps;
+    a.bc = wl.bc; a.mc = wl.mc;
+    for (int q = 0; q < wl.nsteps; ++q) {
+        for (int stage = 0; stage < 3; ++stage) {
+            a.q = q;
+            a.stage = stage;
+            if (wl.threads == 512) {
+                switch (wl.R) {
+                case 1: k_tape_wide<1, 512><<<wl.ntiles, 512, 0, st>>>(a); break;
+                case 2: k_tape_wide<2, 512><<<wl.ntiles, 512, 0, st>>>(a); break;
+                case 3: k_tape_wide<3, 512><<<wl.ntiles, 512, 0, st>>>(a); break;
+                default: k_tape_wide<4, 512><<<wl.ntiles, 512, 0, st>>>(a); break;
+                }
+            } else {
+                switch (wl.R) {
+                case 1: k_tape_wide<1, 256><<<wl.ntiles, 256, 0, st>>>(a); break;
+                case 2: k_tape_wide<2, 256><<<wl.ntiles, 256, 0, st>>>(a); break;
+                case 3: k_tape_wide<3, 256><<<wl.ntiles, 256, 0, st>>>(a); break;
+                default: k_tape_wide<4, 256><<<wl.ntiles, 256, 0, st>>>(a); break;
+                }
+            }
+        }
+    }
+}
+
 void launch_adjoint_wide(const AdjWideLaunch &wl, hipStream_t st)
 {
     AdjWideArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.offsets = wl.offsets; a.ncells = wl.ncells; a.dx = wl.dx; a.dt_hist = wl.dt_hist;
     a.lam = wl.lam; a.mu1 = wl.mu1; a.mu2 = wl.mu2; a.tapeU = wl.tapeU; a.tapeS = wl.tapeS;
     a.bc_inst = wl.bc_inst; a.tile_inst = wl.tile_inst; a.tile_i0 = wl.tile_i0; a.inst_ntiles = wl.inst_ntiles;

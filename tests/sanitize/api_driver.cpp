@@ -32,6 +32,7 @@ void launch_batched_wide(const WideLaunch &, hipStream_t) {}
 int noalloc_scratch(void **ptr) { *ptr = nullptr; return ASE_OK; }
 void launch_adjoint(const AdjLaunch &, hipStream_t) {}
 void launch_adjoint_wide(const AdjWideLaunch &, hipStream_t) {}
+void launch_tape_wide(const AdjWideLaunch &, hipStream_t) {}
 void launch_objective(const ObjLaunch &, hipStream_t) {}
 void launch_gks1d(int, int, const Gks1DArgs &, hipStream_t) {}
 void launch_gks2d(int, int, bool, const Gks2DArgs &, hipStream_t) {}
@@ -166,14 +167,23 @@ int main()
                                1, 256, ASE_ADJ_TAPE | ASE_ADJ_REVERSE, dummy, 1 << 20, nullptr) == ASE_ERR_ARG);
     EXPECT(ase_adjoint_batched(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy, dummy, 1,
                                dummy, &n1, &n1, 1, 256, 0, dummy, 1 << 20, nullptr) == ASE_ERR_ARG);
+    ase_params_t pfo = p;
+    pfo.flags |= ASE_FLAG_DF_FIRST_ORDER;
+    // the wide adjoint: first-order source only, 256 or 512 lanes, tile arrays, a phase
     EXPECT(ase_adjoint_batched_wide(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
-                                    dummy, 1, dummy, &n1, &n1, 1, 256, &n1, &n1, &n1, 1, 384, dummy, 1 << 30,
+                                    dummy, 1, dummy, &n1, &n1, 1, 256, &n1, &n1, &n1, 1, 256, 2, dummy, 1 << 30,
+                                    nullptr) == ASE_ERR_ARG);
+    EXPECT(ase_adjoint_batched_wide(&pfo, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                    dummy, 1, dummy, &n1, &n1, 1, 256, &n1, &n1, &n1, 1, 384, 2, dummy, 1 << 30,
+                                    nullptr) == ASE_ERR_ARG);
+    EXPECT(ase_adjoint_batched_wide(&pfo, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                    dummy, 1, dummy, &n1, &n1, 1, 256, nullptr, &n1, &n1, 1, 256, 2, dummy, 1 << 30,
+                                    nullptr) == ASE_ERR_ARG);
+    EXPECT(ase_adjoint_batched_wide(&pfo, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
+                                    dummy, 1, dummy, &n1, &n1, 1, 256, &n1, &n1, &n1, 1, 256, 4, dummy, 1 << 30,
                                     nullptr) == ASE_ERR_ARG);
     EXPECT(ase_adjoint_batched_wide(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
-                                    dummy, 1, dummy, &n1, &n1, 1, 256, nullptr, &n1, &n1, 1, 256, dummy, 1 << 30,
-                                    nullptr) == ASE_ERR_ARG);
-    EXPECT(ase_adjoint_batched_wide(&p, ASE_BC_TRANSMISSIVE, nullptr, 1, &off, &n1, dummy, 5, 20, dummy, dummy,
-                                    dummy, 1, dummy, &n1, &n1, 1, 256, &n1, &n1, &n1, 1, 256, dummy, 64,
+                                    dummy, 1, dummy, &n1, &n1, 1, 256, &n1, &n1, &n1, 1, 256, 2, dummy, 64,
                                     nullptr) == ASE_ERR_WORKSPACE);
     EXPECT(ase_pressure_objective(nullptr, 1, &off, &n1, dummy, 5, 20, dummy, nullptr, nullptr, nullptr,
                                   nullptr) != ASE_OK);

@@ -43,10 +43,16 @@ def _reverse_pair(b, nsteps, min_cells, adj_threads, wide_threads, stop=None, se
           f"ntiles={wplan['ntiles']} stop={stop}", flush=True)
     a = lam0.clone()
     ase.adjoint_batched(sim, U0, sig0, hist, nsteps, a, ws, adj_threads, full)
+    # both phases in one call, and as two calls (the wide tape phase into a
+    # workspace that held the persistent tape)
     w = lam0.clone()
-    ase.adjoint_batched(sim, U0, sig0, hist, nsteps, w, ws, adj_threads, full, phase=ase.ADJ_TAPE)
     ase.adjoint_batched_wide(sim, U0, sig0, hist, nsteps, w, ws, adj_threads, wplan)
+    w2 = lam0.clone()
+    ws2 = ase.Workspace(ws.nbytes, DEV)
+    ase.adjoint_batched_wide(sim, U0, sig0, hist, nsteps, w2, ws2, adj_threads, wplan, phase=ase.ADJ_TAPE)
+    ase.adjoint_batched_wide(sim, U0, sig0, hist, nsteps, w2, ws2, adj_threads, wplan, phase=ase.ADJ_REVERSE)
     torch.cuda.synchronize()
+    assert np.array_equal(w.cpu().numpy(), w2.cpu().numpy(), equal_nan=True)
     return a.cpu().numpy(), w.cpu().numpy()
 
 
