@@ -429,11 +429,15 @@ def _pack(ncells: Sequence[int], ng: int) -> Tuple[np.ndarray, np.ndarray, int]:
 
 
 def batched_riemann(ninst: int = 256, nmin: int = 64, nmax: int = 4096, order: int = 9, seed: int = 0,
-                    nsteps: int = 100, cfl: float = 0.5) -> Batch:
+                    nsteps: int = 100, cfl: float = 0.5, sizes: Optional[Sequence[int]] = None) -> Batch:
     """Independent 1D Riemann problems on [0,1] split at 0.5, transmissive:
-    rho in [0.1,2], |u| <= 2, p in [0.05,2] per side; N uniform in [nmin, nmax]."""
+    rho in [0.1,2], |u| <= 2, p in [0.05,2] per side; N uniform in [nmin, nmax]
+    (or the given sizes, one instance each)."""
     rng = np.random.default_rng(seed)
     n = rng.integers(nmin, nmax + 1, size=ninst)
+    if sizes is not None:
+        n = np.asarray(sizes, dtype=np.int64)
+        ninst = len(n)
     ng = ghosts_for(order)
     ncells, offsets, total = _pack(n, ng)
     gamma = 1.4
@@ -455,12 +459,15 @@ def batched_riemann(ninst: int = 256, nmin: int = 64, nmax: int = 4096, order: i
 
 
 def batched_smooth(ninst: int = 16, nmin: int = 64, nmax: int = 512, order: int = 9, seed: int = 1,
-                   nsteps: int = 20, cfl: float = 0.5) -> Batch:
+                   nsteps: int = 20, cfl: float = 0.5, sizes: Optional[Sequence[int]] = None) -> Batch:
     """Smooth periodic 1D instances: rho = 1 + 0.2 sin(2 pi x + phi),
     u = 0.5 + 0.1 cos(2 pi x), p = 1 + 0.1 sin(2 pi x + psi) (point values at
     five Gauss-Legendre nodes per cell averaged, i.e. 9th-order cell averages)."""
     rng = np.random.default_rng(seed)
     n = rng.integers(nmin, nmax + 1, size=ninst)
+    if sizes is not None:
+        n = np.asarray(sizes, dtype=np.int64)
+        ninst = len(n)
     ng = ghosts_for(order)
     ncells, offsets, total = _pack(n, ng)
     gamma = 1.4
@@ -504,13 +511,17 @@ def instance_grid(batch: Batch, k: int) -> Grid:
 
 
 def batched_mixed(ninst: int = 12, nmin: int = 16, nmax: int = 400, order: int = 9, seed: int = 5,
-                  nsteps: int = 20) -> Batch:
+                  nsteps: int = 20, sizes: Optional[Sequence[int]] = None) -> Batch:
     """Instances with their own boundary conditions: instance k carries the
     smooth periodic data of batched_smooth (k % 3 == 0), the transmissive
     Riemann data of batched_riemann (k % 3 == 1) or that Riemann data between
-    two reflective walls (k % 3 == 2)."""
-    sm = batched_smooth(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed, nsteps=nsteps)
-    rm = batched_riemann(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed + 1, nsteps=nsteps)
+    two reflective walls (k % 3 == 2); sizes: the cell counts, one instance
+    each (else drawn from [nmin, nmax])."""
+    if sizes is not None:
+        ninst = len(sizes)
+    sm = batched_smooth(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed, nsteps=nsteps, sizes=sizes)
+    rm = batched_riemann(ninst=ninst, nmin=nmin, nmax=nmax, order=order, seed=seed + 1, nsteps=nsteps,
+                         sizes=sizes)
     pick = [sm if k % 3 == 0 else rm for k in range(ninst)]
     ncells, offsets, total = _pack([int(b.ncells[k]) for k, b in enumerate(pick)], sm.ng)
     U = np.zeros((3, total), dtype=np.float64)

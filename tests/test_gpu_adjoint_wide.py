@@ -101,3 +101,16 @@ def test_wide_autograd_full_batch():
         torch.cuda.synchronize()
         grads.append(U0.grad.cpu().numpy())
     assert np.array_equal(grads[0], grads[1], equal_nan=True)
+
+
+@pytest.mark.parametrize("order,wide_threads", [(9, 256), (5, 512)])
+def test_wide_adjoint_tile_edges(order, wide_threads):
+    """Cell counts at the tile edges under each boundary kind (a reflective
+    instance whose last tile holds one cell folds its right ghosts onto
+    cells of the tile before), beside small persistent instances."""
+    T = wide_threads - order - 1
+    sizes = [T, T + 1, 2 * T - 1, 2 * T, 2 * T + 1]
+    sizes = [n for n in sizes for _ in range(3)] + [20, 100, 150]
+    b = WL.batched_mixed(order=order, seed=43, nsteps=3, sizes=sizes)
+    a, w = _reverse_pair(b, 3, T, 256, wide_threads)
+    assert np.array_equal(a, w, equal_nan=True)

@@ -122,3 +122,16 @@ def test_wide_status_on_the_full_batch():
     p, w = _pair(b, b.nsteps, 2048, nbins=256, status=True)
     _assert_same(p, w, "status")
     assert np.all(w["status"] >= 0)
+
+
+@pytest.mark.parametrize("order,wide_threads", [(9, 256), (5, 512)])
+def test_wide_tile_edges(order, wide_threads):
+    """Cell counts at the tile edges (one full tile, one cell more, one short
+    of two tiles, two, two and one cell) under each boundary kind, beside
+    small persistent instances: the persistent launch's bits."""
+    T = wide_threads - order - 1
+    sizes = [T, T + 1, 2 * T - 1, 2 * T, 2 * T + 1]
+    sizes = [n for n in sizes for _ in range(3)] + [20, 100, 150]
+    b = WL.batched_mixed(order=order, seed=41, nsteps=6, sizes=sizes)
+    p, w = _pair(b, b.nsteps, T, wide_threads, nbins=2)
+    _assert_same(p, w, "edges")
