@@ -115,13 +115,18 @@ def test_wide_dt_replay_stops_where_the_replay_ends():
 
 
 def test_wide_status_on_the_full_batch():
-    """The 256-instance batch (64..4096 cells, order 9) with a status array,
-    instances of 2048 cells and more in the wide form: U, strengths, times,
-    time steps and status flags all equal the persistent launch's."""
-    b = WL.batched_riemann(nsteps=40)
+    """The 256-instance batch (64..4096 cells, order 9, 100 steps) with a
+    status array, instances of 2048 cells and more in the wide form: U,
+    strengths, times, time steps and status flags all equal the persistent
+    launch's, including those of the wide instances the method loses."""
+    b = WL.batched_riemann(nsteps=100)
     p, w = _pair(b, b.nsteps, 2048, nbins=256, status=True)
     _assert_same(p, w, "status")
-    assert np.all(w["status"] >= 0)
+    st = w["status"]
+    assert np.all(st >= 0)
+    lost_wide = [k for k in np.flatnonzero(st) if b.ncells[k] >= 2048]
+    print(f"lost: {np.flatnonzero(st).tolist()}, wide among them: {lost_wide}", flush=True)
+    assert len(lost_wide) > 0
 
 
 @pytest.mark.parametrize("order,wide_threads", [(9, 256), (5, 512)])
