@@ -363,8 +363,9 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
  * tile_inst and tile_i0 hold cap entries (ASE_ERR_ARG, with *ntiles set,
  * when cap < *ntiles; call with cap 0 and NULL arrays to count).
  * ase_batched_wide_workspace_bytes: device workspace for the call below.
- * ase_step_batched_wide: the arguments of ase_step_batched plus device
- * copies of the tile arrays, ntiles and threads_wide (256 or 512, as
+ * ase_step_batched_wide: the arguments of ase_step_batched (bin_start and
+ * bin_list: the wide plan's, which hold only the untiled instances) plus
+ * device copies of the tile arrays, ntiles and threads_wide (256 or 512, as
  * planned).  The call returns once both streams' work is queued; the
  * caller's stream waits for the second stream's before the final launch,
  * so work queued behind the call on `stream` sees every result.  The

@@ -1039,10 +1039,12 @@ int ase_step_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_i
             e = hipEventRecord(ss->join, ss->s);
             if (e == hipSuccess) e = hipStreamWaitEvent(st, ss->join, 0);
             if (e != hipSuccess) return hip_fail(e, "ase_step_batched_wide: join");
-            // the first-order strengths and ghost cells of every final state
-            // (the persistent launch wrote its own already: the same values)
+            // the first-order strengths and ghost cells of the final states
+            // of the tiled instances (the persistent launch wrote those of
+            // its own)
             BatchLaunch ib = bl;
             ib.init = 1;
+            ib.only = inst_ntiles;
             launch_batched(ib, st);
         }
     }

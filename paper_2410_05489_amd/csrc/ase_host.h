@@ -107,6 +107,7 @@ struct BatchLaunch {
     int *status;
     const int *bin_start, *bin_list;
     const int *bc_inst;
+    const int *only;   // init: optional [ninst], only the instances with only[k] > 0
     long long total;
     int ninst, nbins, threads, R, ng, nsteps, bc, fo, init;
     double t_end, cfl, dt_cap;

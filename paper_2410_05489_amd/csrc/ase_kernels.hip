@@ -1041,6 +1041,7 @@ struct BatchArgs {
     double *U1, *U2, *sig2;     // workspace, same layout as U / sig
     const int *bin_start, *bin_list;
     const int *bc_inst;         // optional per-instance boundary code (else `bc` for all)
+    const int *only;            // k_batched_sigma_init: optional [ninst], instances with only[k] > 0
     long long total;
     int ninst, ng, nsteps, bc, fo;
     double t_end, cfl, dt_cap;
@@ -1235,6 +1236,7 @@ template <int NT>
 __global__ void __launch_bounds__(NT) k_batched_sigma_init(BatchArgs a)
 {
     const int k = blockIdx.x;
+    if (a.only != nullptr && a.only[k] < 1) return;
     const long long off = a.offsets[k];
     const int N = a.ncells[k];
     if (N < 1 || off < 0 || off + N + 2LL * a.ng > a.total) return;
@@ -2490,7 +2492,7 @@ void launch_batched(const BatchLaunch &bl, hipStream_t st)
     a.offsets = bl.offsets; a.ncells = bl.ncells; a.dx = bl.dx;
     a.U = bl.U; a.sig = bl.sig; a.t = bl.t; a.dt_hist = bl.dt_hist; a.dt_in = bl.dt_in; a.status = bl.status;
     a.U1 = bl.U1; a.U2 = bl.U2; a.sig2 = bl.sig2;
-    a.bin_start = bl.bin_start; a.bin_list = bl.bin_list; a.bc_inst = bl.bc_inst;
+    a.bin_start = bl.bin_start; a.bin_list = bl.bin_list; a.bc_inst = bl.bc_inst; a.only = bl.only;
     a.total = bl.total; a.ninst = bl.ninst; a.ng = bl.ng; a.nsteps = bl.nsteps; a.bc = bl.bc; a.fo = bl.fo;
     a.t_end = bl.t_end; a.cfl = bl.cfl; a.dt_cap = bl.dt_cap; a.mc = bl.mc;
     if (bl.init) {
