@@ -140,3 +140,47 @@ def test_wide_tile_edges(order, wide_threads):
     b = WL.batched_mixed(order=order, seed=41, nsteps=6, sizes=sizes)
     p, w = _pair(b, b.nsteps, T, wide_threads, nbins=2)
     _assert_same(p, w, "edges")
+
+
+def test_wide_full_size_against_the_oracle():
+    """The 256-instance batch, 100 steps, instances of 768 cells and more in
+    the wide form: the six largest instances the method keeps against the
+    oracle run of each alone (1e-9 relative after the full run), and one
+    step of every instance (1e-12; an instance whose first step already
+    leaves the physical states must do so on both sides)."""
+    from oracle import oracle as O
+
+    def oracle_run(b, k, nsteps):
+        g = WL.instance_grid(b, k)
+        o, n = int(b.offsets[k]), int(b.ncells[k])
+        U = np.ascontiguousarray(b.U[:, o:o + n + 2 * b.ng]).reshape(3, 1, n + 2 * b.ng).copy()
+        sx, _ = O.sigma_init(g, b.params, U)
+        O.step(g, b.params, U, sx, None, 0.0, nsteps, 0.0)
+        return g, U
+
+    def rel(a, c):
+        den = np.maximum(np.abs(c).max(axis=-1), 1e-300)
+        return float(np.max(np.abs(a - c).max(axis=-1) / den))
+
+    for nsteps, tol, picks in ((1, 1e-12, None), (100, 1e-9, 6)):
+        b = WL.batched_riemann(nsteps=nsteps)
+        sim = ase.BatchedSimulation(b, DEV, nbins=64, wide_min_cells=768)
+        st = torch.zeros(b.ninst, dtype=torch.int32, device=DEV)
+        print(f"wide full size: {nsteps} steps, {sim.wide['nwide']} wide instances", flush=True)
+        sim.run(nsteps, status=st)
+        torch.cuda.synchronize()
+        Ug, status = sim.U.cpu().numpy(), st.cpu().numpy()
+        ks = range(b.ninst) if picks is None else \
+            [int(k) for k in np.argsort(b.ncells)[::-1] if status[k] == 0][:picks]
+        for k in ks:
+            if status[k] != 0:
+                continue
+            g, Uo = oracle_run(b, k, nsteps)
+            o, n = int(b.offsets[k]), int(b.ncells[k])
+            a = Ug[:, o + b.ng:o + b.ng + n]
+            c = g.interior(Uo)[:, 0]
+            assert np.isfinite(a).all() == np.isfinite(c).all(), k
+            if np.isfinite(c).all():
+                assert rel(a, c) < tol, (k, nsteps)
+            else:
+                print(f"instance {k} ({n} cells) leaves the physical states in step 1 on both sides", flush=True)
