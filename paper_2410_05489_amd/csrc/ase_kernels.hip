@@ -1479,15 +1479,14 @@ struct LdsAdj {
     static constexpr int NC = T + 2 * R + 2;  // trace cells [i0-R-1, i0+T+R]
     static constexpr int NF = NC - 1;         // faces between consecutive trace cells
     double sV[3][WX];
-    double sG[3][NC];
     double sGL[3][NF], sGR[3][NF];
-    double sAl[4][NC];       // frozen DF factors of each trace cell
-    int8_t sLev[NC];         // and its stencil level
     union {
-        // window strengths and face traces (trace, flux and decision
-        // phases), then the tap contributions (tap and gather phases)
+        // window strengths, adjoint weights and face traces (trace, flux and
+        // decision phases), then the tap contributions (tap and gather
+        // phases)
         struct {
             double sS[WX];
+            double sG[3][NC];
             double tr[3][NC], tl[3][NC];
         } t;
         double c[2 * R + 1][NC];
@@ -1557,7 +1556,7 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
             double h[3], Wl[3], Wr[3];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
-                h[v] = (L.sG[v][f + 1] - L.sG[v][f]) * a.inv_dx;
+                h[v] = (L.u.t.sG[v][f + 1] - L.u.t.sG[v][f]) * a.inv_dx;
                 Wl[v] = L.u.t.tr[v][f];
                 Wr[v] = L.u.t.tl[v][f + 1];
             }
@@ -1600,18 +1599,20 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
         }
         L.rep[f] = rp;
     }
-    // frozen level and DF factors of every contributing cell, once for all
-    // three variables
-    for (int c = tid; c < NC; c += NT) {
-        const int x = xc + c;
-        if (c < 1 || c > NC - 2 || x < -1 || x > a.N) continue;
-        const int lx = c + (H - R - 1);
-        double s[2 * R], al[4];
+    // frozen level and DF factors of this lane's trace cell (one per lane:
+    // NC = NT), once for all three variables, kept in registers
+    static_assert(NC == NT, "one trace cell per lane");
+    int lev = 0;
+    double dal[4] = {0.0, 0.0, 0.0, 0.0};
+    {
+        const int c = tid, x = xc + c;
+        if (c >= 1 && c <= NC - 2 && x >= -1 && x <= a.N) {
+            const int lx = c + (H - R - 1);
+            double s[2 * R];
 #pragma unroll
-        for (int m = -R; m < R; ++m) s[m + R] = L.u.t.sS[lx + m];
-        L.sLev[c] = (int8_t)cell_decisions<R>(s, mc, al);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) L.sAl[k][c] = al[k];
+            for (int m = -R; m < R; ++m) s[m + R] = L.u.t.sS[lx + m];
+            lev = cell_decisions<R>(s, mc, dal);
+        }
     }
     __syncthreads();
 
@@ -1648,10 +1649,7 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
                     else gL = L.sGR[v][c - 1];
                 }
                 const int lx = c + (H - R - 1);
-                double al[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) al[k] = L.sAl[k][c];
-                recon_vjp_var<R>([&](int m) { return L.sV[v][lx + m]; }, (int)L.sLev[c], al, mc, gR, gL, cc);
+                recon_vjp_var<R>([&](int m) { return L.sV[v][lx + m]; }, lev, dal, mc, gR, gL, cc);
                 cc[R] += d;
             }
 #pragma unroll
@@ -1812,7 +1810,7 @@ __device__ __forceinline__ void adj_stage_window(const AdjWin<R, T, NT> &w, LdsA
         const int c = tid + q * NT;
         if (c < LA::NC) {
 #pragma unroll
-            for (int v = 0; v < 3; ++v) L.sG[v][c] = w.g[q][v];
+            for (int v = 0; v < 3; ++v) L.u.t.sG[v][c] = w.g[q][v];
         }
     }
 }
@@ -2010,7 +2008,7 @@ __device__ __forceinline__ AdjTile adj_wide_tile(const AdjWideArgs &a, int k, in
 }
 
 template <int R, int NT>
-__global__ void __launch_bounds__(NT, 1) k_adjoint_wide(AdjWideArgs a)
+__global__ void __launch_bounds__(NT, 4) k_adjoint_wide(AdjWideArgs a)
 {
     constexpr int T = NT - 2 * R - 2;
     __shared__ LdsAdj<R, T> L;
