@@ -184,3 +184,26 @@ def test_wide_full_size_against_the_oracle():
                 assert rel(a, c) < tol, (k, nsteps)
             else:
                 print(f"instance {k} ({n} cells) leaves the physical states in step 1 on both sides", flush=True)
+
+
+def test_wide_calls_on_two_streams_at_once():
+    """Two batches stepped in the wide form on two streams at the same time
+    (each caller stream gets its own second stream from the library): each
+    ends with the bits of its run alone on the default stream."""
+    b1 = WL.batched_mixed(ninst=10, nmin=20, nmax=2500, order=9, seed=51, nsteps=20)
+    b2 = WL.batched_riemann(ninst=12, nmin=300, nmax=3000, order=9, seed=52, nsteps=20)
+    alone = []
+    for b in (b1, b2):
+        sim = ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=600)
+        sim.run(b.nsteps)
+        alone.append(_outputs(sim))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    sims = [ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=600) for b in (b1, b2)]
+    torch.cuda.synchronize()
+    for _ in range(4):   # interleaved calls of 5 steps each
+        for sim, st in zip(sims, (s1, s2)):
+            with torch.cuda.stream(st):
+                sim.run(5, stream=st)
+    torch.cuda.synchronize()
+    for sim, ref in zip(sims, alone):
+        _assert_same(ref, _outputs(sim), "two streams")
