@@ -233,7 +233,13 @@ __device__ constexpr Tables kTab = tables::make_tables();
 constexpr int LVL_WENOAO = 2;
 constexpr int LVL_R3 = 3;
 
-__device__ __forceinline__ double df_alpha(double A, double thr) { return A < thr ? 1.0 : thr / A; }
+__device__ __forceinline__ double rcp_nr(double x);
+// thr / A by a refined reciprocal; an infinite strength (a non-physical
+// state beside a face) gives 0 as the quotient does
+__device__ __forceinline__ double df_alpha(double A, double thr)
+{
+    return A < thr ? 1.0 : (__builtin_isinf(A) ? 0.0 : thr * rcp_nr(A));
+}
 
 // Sum of face strengths s[lo..hi-1] in left-to-right order.
 template <int R>
@@ -385,11 +391,13 @@ __device__ __forceinline__ WenoAO53 weno_ao53_setup(const double (&W)[5], const 
     const double tz = (fabs(s5 - sm) + fabs(s5 - s0) + fabs(s5 - sp)) * (1.0 / 3.0);
     const double tz2 = tz * tz;
     const double e5 = s5 + mc.eps, em = sm + mc.eps, e0 = s0 + mc.eps, ep = sp + mc.eps;
-    const double w5 = mc.d5 * (1.0 + tz2 / (e5 * e5));
-    const double wm = mc.d3m * (1.0 + tz2 / (em * em));
-    const double w0 = mc.d30 * (1.0 + tz2 / (e0 * e0));
-    const double wp = mc.d3m * (1.0 + tz2 / (ep * ep));
-    const double inv = 1.0 / (w5 + wm + w0 + wp);
+    // reciprocals as the hardware estimate refined (rcp_nr, within an ulp or
+    // two): the weights are continuous in them and decide nothing discrete
+    const double w5 = mc.d5 * (1.0 + tz2 * rcp_nr(e5 * e5));
+    const double wm = mc.d3m * (1.0 + tz2 * rcp_nr(em * em));
+    const double w0 = mc.d30 * (1.0 + tz2 * rcp_nr(e0 * e0));
+    const double wp = mc.d3m * (1.0 + tz2 * rcp_nr(ep * ep));
+    const double inv = rcp_nr(w5 + wm + w0 + wp);
     c.o5 = w5 * inv;
     c.om = wm * inv;
     c.o0 = w0 * inv;
