@@ -27,9 +27,9 @@ METRIC = "Mcell-updates/s, 9th-order 2D ASE step (FP64) + % HBM roofline; adjoin
 # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy (summary in
 # profiles/k_sweep2d_quad1024_r9.md, 1024^2 and 4096^2).  Valid only for the sweep kernel sources
 # with this fingerprint (kernel_fingerprint); once they change the bench reports traffic as null.
-MEASURED_TRAFFIC = {"fingerprint": "926046370baada12", "workloads": ("quad1024", "quad4096"),
-                    "quad1024": {"sweep_x": 88271665, "sweep_y": 145297094},
-                    "quad4096": {"sweep_x": 1752572188, "sweep_y": 2782968192}}
+MEASURED_TRAFFIC = {"fingerprint": "5e5b813e0774b09c", "workloads": ("quad1024", "quad4096"),
+                    "quad1024": {"sweep_x": 88022912, "sweep_y": 156486528},
+                    "quad4096": {"sweep_x": 1751501024, "sweep_y": 2908951552}}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 

@@ -749,7 +749,15 @@ __global__ void __launch_bounds__(NT, 6) k_sweep2d(SweepArgs a)
             // cell averages of this lane's side and of the other side (read
             // only for the positivity replacement)
             // (positions within a plane fit in 32 bits: the host checks it)
-            const int pl = (y + a.ng) * a.ld + x + a.ng;
+            // The face position is formed again from the lane index (behind
+            // an empty asm, so that x and y need not stay live across the
+            // reconstruction: they were spilled there).
+            int tid2 = tid;
+            asm volatile("" : "+v"(tid2));
+            const int f2 = (base + tid2) >> 1;
+            const int x2 = DIR == 0 ? i0 - 1 + f2 % FX : i0 + f2 % FX;
+            const int y2 = DIR == 0 ? j0 + f2 / FX : j0 - 1 + f2 / FX;
+            const int pl = (y2 + a.ng) * a.ld + x2 + a.ng;
             const int pr = DIR == 0 ? pl + 1 : pl + a.ld;
             const int po = side == 0 ? pl : pr, pt = side == 0 ? pr : pl;
             const double *U = a.U;
