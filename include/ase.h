@@ -353,9 +353,16 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
  * ghost cells, sigma, t, dt_hist, status).  Needs ASE_FLAG_DF_FIRST_ORDER
  * (strengths from the two cell averages beside each face, Sec. 3.1).
  *
+ * threads_wide is 256 or 512 lanes per tile, optionally or'ed with
+ * ASE_WIDE_STEP: then one launch per step instead of per stage, each tile
+ * running the three stages of the step in on-chip memory over a window that
+ * reaches three stages' stencils beyond its cells; tiles are then
+ * threads_wide - 3 (order + 1) cells long instead of threads_wide - order - 1.
+ * Plan and step call take the same value.
+ *
  * ase_batched_plan_wide: HOST arrays.  Instances with ncells >= min_cells
- * and at least one full tile (threads_wide - order - 1 cells; min_cells <= 0:
- * none) are cut into tiles of that length: tile j of instance k starts at
+ * and at least one full tile (min_cells <= 0: none) are cut into tiles of
+ * that length: tile j of instance k starts at
  * interior cell tile_i0[j]; tile_inst[j] = k; the tiles of k are
  * inst_tile0[k] .. inst_tile0[k] + inst_ntiles[k] - 1 (inst_tile0 -1 and
  * inst_ntiles 0 for the others).  The others are packed into nbins bins as
@@ -365,13 +372,14 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
  * ase_batched_wide_workspace_bytes: device workspace for the call below.
  * ase_step_batched_wide: the arguments of ase_step_batched (bin_start and
  * bin_list: the wide plan's, which hold only the untiled instances) plus
- * device copies of the tile arrays, ntiles and threads_wide (256 or 512, as
- * planned).  The call returns once both streams' work is queued; the
+ * device copies of the tile arrays, ntiles and threads_wide (as planned).  The call returns once both streams' work is queued; the
  * caller's stream waits for the second stream's before the final launch,
  * so work queued behind the call on `stream` sees every result.  The
  * library keeps one second stream (and two events) per device and caller
  * stream, created on first use and held until the process ends; calls on
  * different caller streams run concurrently. */
+#define ASE_WIDE_STEP 0x10000
+
 int ase_batched_plan_wide(int32_t ninst, const int32_t *ncells, int32_t min_cells, int32_t order,
                           int32_t threads_wide, int32_t nbins, int32_t *bin_start, int32_t *bin_list,
                           int32_t *tile_inst, int32_t *tile_i0, int32_t *inst_tile0, int32_t *inst_ntiles,

@@ -390,8 +390,9 @@ class BatchedSimulation:
     persistent-launch stepper.  nbins / threads select the launch shape.
     wide_min_cells > 0 (first-order DF source only) also plans the wide form:
     instances of at least that many cells then run as one launch per stage
-    over tiles of wide_threads lanes beside the persistent launch; run()
-    takes it unless wide=False."""
+    (per step with WIDE_STEP or'ed into wide_threads) over tiles of
+    wide_threads lanes beside the persistent launch; run() takes it unless
+    wide=False."""
 
     def __init__(self, batch, device="cuda", nbins: int = 0, threads: int = 256, sigma=None,
                  wide_min_cells: int = 0, wide_threads: int = 256):
@@ -514,6 +515,8 @@ def device_plan(ncells, nbins: int, device="cuda"):
 
 
 ADJ_TAPE, ADJ_REVERSE = 1, 2
+# or'ed into wide_threads: the wide form advances one whole step per launch
+WIDE_STEP = 0x10000
 
 
 def adjoint_batched(sim: "BatchedSimulation", U_ck, sig_ck, dt_hist, nsteps: int, lam, ws: Workspace,

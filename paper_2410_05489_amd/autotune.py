@@ -23,9 +23,13 @@ DEFAULT_CANDIDATES: Sequence[Tuple[int, int]] = ((128, 512), (256, 256), (256, 5
 
 
 # (bins, threads, min_cells, wide_threads) of the wide form
+# (wide_threads with ase.WIDE_STEP: one launch per step)
 WIDE_CANDIDATES: Sequence[Tuple[int, int, int, int]] = ((128, 256, 768, 256), (64, 256, 768, 256),
                                                         (128, 512, 1024, 256), (256, 512, 1024, 256),
-                                                        (128, 512, 1536, 256), (128, 512, 1024, 512))
+                                                        (128, 512, 1536, 256), (128, 512, 1024, 512),
+                                                        (64, 256, 768, 256 | ase.WIDE_STEP),
+                                                        (64, 256, 896, 256 | ase.WIDE_STEP),
+                                                        (128, 512, 1024, 256 | ase.WIDE_STEP))
 
 
 def cache_path() -> str:

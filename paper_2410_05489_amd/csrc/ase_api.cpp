@@ -779,8 +779,11 @@ int ase_batched_plan_wide(int32_t ninst, const int32_t *ncells, int32_t min_cell
         cap < 0 || (cap > 0 && (!tile_inst || !tile_i0)))
         return fail(ASE_ERR_ARG, "ase_batched_plan_wide: bad arguments");
     if (order != 3 && order != 5 && order != 7 && order != 9) return fail(ASE_ERR_ORDER, "order must be 3, 5, 7 or 9");
-    if (threads_wide != 256 && threads_wide != 512) return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512");
-    const int T = wide_tile_cells(threads_wide, (order - 1) / 2);
+    const int nt_lanes = threads_wide & ~ASE_WIDE_STEP;
+    if ((nt_lanes != 256 && nt_lanes != 512) || (threads_wide & ~(ASE_WIDE_STEP | 0x3ff)))
+        return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512, optionally with ASE_WIDE_STEP");
+    const int T = (threads_wide & ASE_WIDE_STEP) ? wide_step_tile_cells(nt_lanes, (order - 1) / 2)
+                                                 : wide_tile_cells(nt_lanes, (order - 1) / 2);
     // an instance takes the wide form from one full tile up
     auto wide = [&](int k) { return min_cells > 0 && ncells[k] >= min_cells && ncells[k] >= T; };
     std::vector<int> small;
@@ -815,7 +818,7 @@ int ase_batched_plan_wide(int32_t ninst, const int32_t *ncells, int32_t min_cell
 size_t ase_batched_wide_workspace_bytes(int64_t total, int32_t ninst, int32_t ntiles)
 {
     if (total < 1 || ninst < 1 || ntiles < 0) return 0;
-    return ase_batched_workspace_bytes(total) + align_up((size_t)(ntiles > 0 ? ntiles : 1) * sizeof(double)) +
+    return ase_batched_workspace_bytes(total) + align_up((size_t)(ntiles > 0 ? ntiles : 1) * 2 * sizeof(double)) +
            align_up((size_t)ninst * sizeof(double)) + align_up((size_t)ninst * sizeof(int));
 }
 
@@ -992,7 +995,9 @@ int ase_step_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_i
     if (!(p->flags & ASE_FLAG_DF_FIRST_ORDER))
         return fail(ASE_ERR_ARG, "the wide batched form needs the first-order DF source (ASE_FLAG_DF_FIRST_ORDER)");
     if (ntiles < 0) return fail(ASE_ERR_ARG, "ntiles must be >= 0");
-    if (threads_wide != 256 && threads_wide != 512) return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512");
+    const int nt_lanes = threads_wide & ~ASE_WIDE_STEP;
+    if ((nt_lanes != 256 && nt_lanes != 512) || (threads_wide & ~(ASE_WIDE_STEP | 0x3ff)))
+        return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512, optionally with ASE_WIDE_STEP");
     if (!inst_tile0 || !inst_ntiles || (ntiles > 0 && (!tile_inst || !tile_i0)))
         return fail(ASE_ERR_ARG, "null tile arrays");
     if (nsteps == 0) return ASE_OK;
@@ -1005,11 +1010,13 @@ int ase_step_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_i
     wl.status = status; wl.bc_inst = bc_inst;
     wl.tile_inst = tile_inst; wl.tile_i0 = tile_i0; wl.inst_tile0 = inst_tile0; wl.inst_ntiles = inst_ntiles;
     wl.lam = reinterpret_cast<double *>(c);
-    c += align_up((size_t)(ntiles > 0 ? ntiles : 1) * sizeof(double));
+    c += align_up((size_t)(ntiles > 0 ? ntiles : 1) * 2 * sizeof(double));
     wl.dt_cur = reinterpret_cast<double *>(c);
     c += align_up((size_t)ninst * sizeof(double));
     wl.done = reinterpret_cast<int *>(c);
-    wl.total = total; wl.ninst = ninst; wl.ntiles = ntiles; wl.threads = threads_wide; wl.R = bl.R; wl.ng = ng;
+    wl.total = total; wl.ninst = ninst; wl.ntiles = ntiles; wl.threads = nt_lanes; wl.R = bl.R; wl.ng = ng;
+    wl.per_step = (threads_wide & ASE_WIDE_STEP) ? 1 : 0;
+    wl.nsteps = nsteps;
     wl.bc = bc; wl.t_end = t_end; wl.cfl = p->cfl; wl.dt_cap = p->dt_cap; wl.mc = bl.mc;
     {
         ProfScope ps(ASE_KCLASS_BATCHED, st);
@@ -1031,7 +1038,7 @@ int ase_step_batched_wide(const ase_params_t *p, int32_t bc, const int32_t *bc_i
             wl.stage = 0;
             launch_batched_wide(wl, ss->s);
             for (int sidx = 0; sidx < nsteps; ++sidx)
-                for (int stg = 1; stg <= 3; ++stg) {
+                for (int stg = 1; stg <= (wl.per_step ? 1 : 3); ++stg) {
                     wl.step = sidx;
                     wl.stage = stg;
                     launch_batched_wide(wl, ss->s);

@@ -129,13 +129,17 @@ struct WideLaunch {
     double *lam, *dt_cur;
     int *done;
     long long total;
-    int ninst, ntiles, threads, R, ng, bc, step, stage;
+    int ninst, ntiles, threads, R, ng, bc, step, stage, nsteps;
+    int per_step;   // one launch per step (k_batched_wide_step) instead of per stage
     double t_end, cfl, dt_cap;
     MethodConst mc;
 };
 void launch_batched_wide(const WideLaunch &wl, hipStream_t st);
-// Tile length of the wide form for `threads` lanes and half width R.
+// Tile length of the wide form for `threads` lanes and half width R (one
+// launch per stage: the window reaches R + 1 cells beyond the tile on each
+// side; one launch per step: three times that).
 inline int wide_tile_cells(int threads, int R) { return threads - 2 * R - 2; }
+inline int wide_step_tile_cells(int threads, int R) { return threads - 6 * R - 6; }
 // Address of this device's fixed scratch array (ASE_NOALLOC_SCRATCH_BYTES).
 int noalloc_scratch(void **ptr);
 

@@ -902,12 +902,26 @@ __device__ __forceinline__ void stage1d_prefetch(const Tile1D &a, int i0, double
     }
 }
 
+// SSP-RK3 stage combination (Sec. 2.1) of one value from the step-start
+// value un, the stage input us and the residual Lx, with its multiply-adds
+// written out: every kernel that updates a 1D cell rounds it alike,
+// whatever the compiler would contract in its context.
+__device__ __forceinline__ double rk3_combine(int stage, double un, double us, double dt, double Lx)
+{
+    if (stage == 1) return fma(dt, Lx, us);
+    if (stage == 2) return fma(0.25 * dt, Lx, fma(0.75, un, 0.25 * us));
+    return fma((2.0 / 3.0) * dt, Lx, fma(1.0 / 3.0, un, (2.0 / 3.0) * us));
+}
+
 // The phases of a tile once its window (state and strengths) is in LDS:
 // reconstruct the T + 2 cells whose face values the tile's faces need, LF
 // flux at the T + 1 faces, then the stage combination of the T cells.
 // With LAM, lam returns the signal-speed sum (|u| + c) / dx of this lane's
-// new cell (0 for a lane without one).
-template <int R, int T, int NT, int MODE, bool LAM = false>
+// new cell (0 for a lane without one).  With LDS_OUT the new values of all
+// T cells replace the stage input in L.sU (each lane its own cell, after the
+// flux phase) and nothing is written to memory: the caller keeps a whole
+// step in LDS and makes sure a.nx lets every cell through.
+template <int R, int T, int NT, int MODE, bool LAM = false, bool LDS_OUT = false>
 __device__ __forceinline__ void stage1d_compute(const Tile1D &a, int i0, const MethodConst &mc, Lds1D<R, T> &L,
                                                 const double (&un)[3], double &lam)
 {
@@ -968,17 +982,24 @@ __device__ __forceinline__ void stage1d_compute(const Tile1D &a, int i0, const M
 
     const double dt = a.dt;
     const int cx = tid, x = i0 + cx;
+    if constexpr (LDS_OUT) {
+        if (cx < T) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double Lx = -(L.sF[v][cx + 1] - L.sF[v][cx]) * a.inv_dx;
+                L.sU[v][cx + R + 1] = rk3_combine(a.stage, un[v], L.sU[v][cx + R + 1], dt, Lx);
+            }
+        }
+        return;
+    }
     if (cx < T && x < a.nx) {
         double W[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const long long e = v * a.plane + x + a.ng;
             const double Lx = -(L.sF[v][cx + 1] - L.sF[v][cx]) * a.inv_dx;
-            const double us = L.sU[v][cx + R + 1];   // the stage input (= U^n in stage 1)
-            double o;
-            if (a.stage == 1) o = us + dt * Lx;
-            else if (a.stage == 2) o = 0.75 * un[v] + 0.25 * us + 0.25 * dt * Lx;
-            else o = (1.0 / 3.0) * un[v] + (2.0 / 3.0) * us + (2.0 / 3.0) * dt * Lx;
+            // the stage input is U^n in stage 1
+            const double o = rk3_combine(a.stage, un[v], L.sU[v][cx + R + 1], dt, Lx);
             a.Uout[e] = o;
             W[v] = o;
         }
@@ -1281,6 +1302,7 @@ struct WideArgs {
     int *done;         // [ninst]: the instance has stopped
     long long total;
     int ninst, ntiles, ng, bc, step, stage;   // stage 0: prep
+    int nsteps;                               // steps of the call (one-launch-per-step form)
     double t_end, cfl, dt_cap;
     MethodConst mc;
 };
@@ -1358,7 +1380,6 @@ template <int R, int NT>
 __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
 {
     constexpr int T = NT - 2 * R - 2;
-    constexpr int UX = Lds1D<R, T>::UX;
     __shared__ Lds1D<R, T> L;
     __shared__ double red[NT / 64];
     const int tid = threadIdx.x;
@@ -1459,6 +1480,252 @@ __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
         }
     } else {
         stage1d_compute<R, T, NT, MODE_FUSED_1D>(tl, i0, mc, L, un, l);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wide form with one launch per step.  A tile's window reaches 3 (R + 1)
+// cells beyond the cells it owns on each side, the reach of three stages, so
+// the tile runs all three RK stages in LDS and writes only its own cells of
+// the new state.  Ghost cells of walls and open ends are taken again from
+// their mapped cells of the window before each stage (a window that holds a
+// ghost also holds its mapped cells, far enough inside to be exact at that
+// stage); on a periodic instance the window simply wraps round, and a tile
+// computes the wrapped cells itself from the same values the tile owning
+// them uses.  Cells of the window whose inputs reach beyond it are computed
+// from garbage and never used.  The state and the instance times alternate
+// between two buffers from step to step (neighbouring tiles read the halo of
+// the step's input while others write the output), arranged so that the
+// call's last step writes U and t; the per-tile signal-speed maxima
+// alternate likewise.  Every output equals the per-stage form's and the
+// persistent launch's bit for bit: each cell value is formed by the same
+// operations on the same operands.
+// ---------------------------------------------------------------------------
+
+// Stage input u (instance base) at window cell x of a step's window: the
+// periodic image of any x, or as mapped_cell for walls and open ends.
+__device__ __forceinline__ void step_cell(const double *u, long long P, int N, int ng, int bc, int x,
+                                          double (&W)[3])
+{
+    if (bc == ASE_BC_PERIODIC) {
+        int xm = x % N;
+        if (xm < 0) xm += N;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) W[v] = u[v * P + ng + xm];
+    } else {
+        mapped_cell(u, P, N, ng, bc, x, W);
+    }
+}
+
+// Window position p (cell x) of the stage values in LDS; a ghost cell of a
+// wall or open end (x in [-ng, 0) or [N, N + ng)) reads its mapped cell of
+// the window instead.  Returns whether p is such a ghost.
+template <int R, int T>
+__device__ __forceinline__ bool step_lds_cell(const Lds1D<R, T> &L, int p, int x, int N, int ng, int bc,
+                                              double (&W)[3])
+{
+    constexpr int UX = Lds1D<R, T>::UX;
+    int q = p;
+    double fm = 1.0;
+    const bool ghost = bc != ASE_BC_PERIODIC && ((x >= -ng && x < 0) || (x >= N && x < N + ng));
+    if (ghost) {
+        int y;
+        if (bc == ASE_BC_REFLECTIVE) {
+            y = x < 0 ? -1 - x : 2 * N - 1 - x;
+            fm = -1.0;
+        } else {
+            y = x < 0 ? 0 : N - 1;
+        }
+        q = p + (y - x);
+        q = q < 0 ? 0 : (q > UX - 1 ? UX - 1 : q);
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) W[v] = L.sU[v][q];
+    W[1] *= fm;
+    return ghost;
+}
+
+// First-order strength of the face on the right of window position tid from
+// W (this lane's cell) and the next lane's cell (next: the last lane of a
+// wave forms that one itself), as wide_window does.
+template <int R, int T>
+__device__ __forceinline__ void step_sigma(Lds1D<R, T> &L, const double (&W)[3], const double (&Wn)[3],
+                                           const MethodConst &mc)
+{
+    constexpr int UX = Lds1D<R, T>::UX;
+    const int tid = threadIdx.x;
+    const Prim qa = primitives<3>(W, 0, mc);
+    Prim qb;
+    qb.p = __shfl_down(qa.p, 1);
+    qb.un = __shfl_down(qa.un, 1);
+    qb.ut = __shfl_down(qa.ut, 1);
+    qb.ic = __shfl_down(qa.ic, 1);
+    qb.c = 0.0;
+    qb.ok = __shfl_down((int)qa.ok, 1) != 0;
+    if ((tid & 63) == 63 && tid + 1 < UX) qb = primitives<3>(Wn, 0, mc);
+    if (tid + 1 < UX) L.sS[tid] = sigma_point(qa, qb);
+}
+
+// Bounded to five waves per SIMD (88 registers, no spills; unbounded it takes
+// 117 and runs four, 5 % slower; six spill).
+template <int R, int NT>
+__global__ void __launch_bounds__(NT, 5) k_batched_wide_step(WideArgs a)
+{
+    constexpr int T = NT - 2 * R - 2;   // cells one stage updates: window positions R + 1 .. NT - R - 2
+    constexpr int H = 3 * (R + 1);      // halo of the step's window
+    constexpr int TS = NT - 2 * H;      // cells a tile owns
+    static_assert(TS > H, "tile shorter than its halo");
+    __shared__ Lds1D<R, T> L;
+    __shared__ double red[NT / 64];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int k = a.tile_inst[b], i0 = a.tile_i0[b];
+    if (k < 0 || k >= a.ninst) return;   // malformed tile entry: skipped (the whole workgroup)
+    const int N = a.ncells[k], ng = a.ng;
+    const long long off = a.offsets[k], P = a.total;
+    const int t0 = a.inst_tile0[k], nt = a.inst_ntiles[k];
+    if (N < TS || off < 0 || off + N + 2LL * ng > P || i0 < 0 || i0 >= N || t0 < 0 || nt < 1 ||
+        t0 + nt > a.ntiles || b < t0 || b >= t0 + nt || a.nsteps < 1)
+        return;
+    const bool first = b == t0;
+    const double inv_dx = 1.0 / a.dx[k];
+    const MethodConst &mc = a.mc;
+    const int bc = inst_bc(a.bc_inst, a.bc, k);
+    // buffer A (U, t) takes the output of the call's last step
+    double *tA = a.t, *tB = a.dt_cur;
+    const int x = i0 + tid;              // this lane's owned cell, tid < TS
+    const bool owns = tid < TS && x < N;
+
+    if (a.stage == 0) {
+        // prep: the instance runs, the signal speeds of its initial state,
+        // and with an odd step count the state and time into buffer B
+        const bool to_b = (a.nsteps & 1) != 0;
+        double l = 0.0;
+        if (owns) {
+            double W[3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) W[v] = a.U[v * P + off + ng + x];
+            if (to_b) {
+#pragma unroll
+                for (int v = 0; v < 3; ++v) a.U1[v * P + off + ng + x] = W[v];
+            }
+            const Prim q = primitives<3>(W, 0, mc);
+            l = (fabs(q.un) + q.c) * inv_dx;
+        }
+        const double m = block_max<NT>(l, red);
+        if (tid == 0) {
+            a.lam[b] = m;
+            if (first) {
+                a.done[k] = 0;
+                if (a.status != nullptr) a.status[k] = 0;
+                if (to_b) tB[k] = tA[k];
+            }
+        }
+        return;
+    }
+    const int s = a.step;
+    const bool dst_a = ((a.nsteps - 1 - s) & 1) == 0;
+    const double *X = (dst_a ? a.U1 : a.U) + off;
+    double *Y = (dst_a ? a.U : a.U1) + off;
+    const double t = dst_a ? tB[k] : tA[k];
+    double *tdst = dst_a ? tA : tB;
+    const double *lam_in = a.lam + (s & 1) * (long long)a.ntiles;
+    double *lam_out = a.lam + ((s + 1) & 1) * (long long)a.ntiles;
+    const long long hs = (long long)s * a.ninst + k;
+
+    bool stop = a.done[k] != 0;
+    double dt = 0.0;
+    if (!stop) {
+        stop = a.t_end > 0.0 && t >= a.t_end;
+        if (!stop && a.dt_in) {
+            dt = a.dt_in[hs];
+            stop = !(dt > 0.0);
+        } else if (!stop) {
+            double m = 0.0;
+            for (int j = tid; j < nt; j += NT) m = max_nan(m, lam_in[t0 + j]);
+            m = block_max<NT>(m, red);
+            dt = a.cfl / m;
+            if (a.dt_cap > 0.0 && dt > a.dt_cap) dt = a.dt_cap;
+            if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
+            if (a.status != nullptr && !(dt > 0.0)) {
+                // a signal speed of the state is NaN: the instance stops here
+                if (first && tid == 0) a.status[k] = s + 1;
+                stop = true;
+            }
+        }
+    }
+    if (stop) {
+        // the state and time carry over to the other buffer unchanged
+        if (owns) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) Y[v * P + ng + x] = X[v * P + ng + x];
+        }
+        if (first && tid == 0) {
+            a.done[k] = 1;
+            tdst[k] = t;
+            if (a.dt_hist) a.dt_hist[hs] = 0.0;
+        }
+        return;
+    }
+
+    // the step's window of the input state, and the strengths of its faces
+    const int ox = i0 - H;   // window position p holds cell ox + p
+    {
+        double W[3], Wn[3];
+        step_cell(X, P, N, ng, bc, ox + tid, W);
+        if ((tid & 63) == 63 && tid + 1 < NT) step_cell(X, P, N, ng, bc, ox + tid + 1, Wn);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) L.sU[v][tid] = W[v];
+        step_sigma<R, T>(L, W, Wn, mc);
+    }
+    __syncthreads();
+    double un[3];   // U^n of the cell this lane updates (window position tid + R + 1)
+#pragma unroll
+    for (int v = 0; v < 3; ++v) un[v] = tid < T ? L.sU[v][tid + R + 1] : 0.0;
+
+    Tile1D tl;
+    tl.U = nullptr; tl.sx = nullptr; tl.sig_out = nullptr; tl.Un = nullptr; tl.Uout = nullptr;
+    tl.wl = tl.wr = nullptr; tl.level = nullptr;
+    tl.plane = P; tl.nx = 1 << 30; tl.ng = ng; tl.NX = 1 << 30; tl.nfaces = 1 << 30;
+    tl.inv_dx = inv_dx; tl.dt = dt;
+#pragma unroll 1
+    for (int stg = 1; stg <= 3; ++stg) {
+        if (stg > 1) {
+            // ghost cells of the new stage values again, then the strengths
+            double W[3], Wn[3];
+            const bool g = step_lds_cell<R, T>(L, tid, ox + tid, N, ng, bc, W);
+            if ((tid & 63) == 63 && tid + 1 < NT) step_lds_cell<R, T>(L, tid + 1, ox + tid + 1, N, ng, bc, Wn);
+            if (g) {
+#pragma unroll
+                for (int v = 0; v < 3; ++v) L.sU[v][tid] = W[v];
+            }
+            step_sigma<R, T>(L, W, Wn, mc);
+            __syncthreads();
+        }
+        tl.stage = stg;
+        double l;
+        stage1d_compute<R, T, NT, MODE_FUSED_1D, false, true>(tl, ox + R + 1, mc, L, un, l);
+        __syncthreads();
+    }
+
+    double l = 0.0;
+    if (owns) {
+        double W[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            W[v] = L.sU[v][H + tid];
+            Y[v * P + ng + x] = W[v];
+        }
+        const Prim q = primitives<3>(W, 0, mc);
+        l = (fabs(q.un) + q.c) * inv_dx;
+    }
+    const double m = block_max<NT>(l, red);
+    if (tid == 0) {
+        lam_out[b] = m;
+        if (first) {
+            tdst[k] = t + dt;
+            if (a.dt_hist) a.dt_hist[hs] = dt;
+        }
     }
 }
 
@@ -2540,9 +2807,13 @@ void launch_batched_wide(const WideLaunch &wl, hipStream_t st)
     a.tile_inst = wl.tile_inst; a.tile_i0 = wl.tile_i0; a.inst_tile0 = wl.inst_tile0; a.inst_ntiles = wl.inst_ntiles;
     a.lam = wl.lam; a.dt_cur = wl.dt_cur; a.done = wl.done;
     a.total = wl.total; a.ninst = wl.ninst; a.ntiles = wl.ntiles; a.ng = wl.ng; a.bc = wl.bc; a.step = wl.step;
-    a.stage = wl.stage;
+    a.stage = wl.stage; a.nsteps = wl.nsteps;
     a.t_end = wl.t_end; a.cfl = wl.cfl; a.dt_cap = wl.dt_cap; a.mc = wl.mc;
-#define ASE_WIDE(RR, NTT) k_batched_wide<RR, NTT><<<wl.ntiles, NTT, 0, st>>>(a)
+#define ASE_WIDE(RR, NTT)                                                     \
+    do {                                                                      \
+        if (wl.per_step) k_batched_wide_step<RR, NTT><<<wl.ntiles, NTT, 0, st>>>(a); \
+        else k_batched_wide<RR, NTT><<<wl.ntiles, NTT, 0, st>>>(a);           \
+    } while (0)
     if (wl.threads == 512) {
         switch (wl.R) {
         case 1: ASE_WIDE(1, 512); break;

@@ -136,16 +136,19 @@ def test_empty_batches_are_rejected():
     assert rc == -1 and len(L.ase_last_error()) > 0
 
 
-@pytest.mark.parametrize("order,threads", [(9, 256), (5, 512), (3, 256)])
+@pytest.mark.parametrize("order,threads", [(9, 256), (5, 512), (3, 256), (9, 256 | ase.WIDE_STEP),
+                                          (7, 512 | ase.WIDE_STEP)])
 def test_wide_plan_covers_each_large_instance_once(order, threads):
     """The wide plan cuts every instance of at least min_cells cells (and one
-    full tile) into consecutive tiles of threads - order - 1 cells that cover
-    it exactly once; every other instance lands in exactly one bin."""
+    full tile) into consecutive tiles of threads - order - 1 cells (one
+    launch per step: threads - 3 (order + 1)) that cover it exactly once;
+    every other instance lands in exactly one bin."""
     import numpy as np
     rng = np.random.default_rng(3)
     nc = rng.integers(1, 5000, size=40).astype(np.int32)
-    nc[0], nc[1] = 4096, threads - order - 1   # one tile exactly
-    T = threads - order - 1
+    lanes = threads & ~ase.WIDE_STEP
+    T = lanes - (3 if threads & ase.WIDE_STEP else 1) * (order + 1)
+    nc[0], nc[1] = 4096, T   # one tile exactly
     start, lst, ti, t0, it0, itn = ase.batched_plan_wide(nc, 1500, order, threads, 7)
     wide = (nc >= 1500) & (nc >= T)
     assert sorted(lst.tolist()) == sorted(np.flatnonzero(~wide).tolist())
@@ -188,5 +191,7 @@ def test_wide_form_argument_errors():
     assert call(w.params, 256, ws, nb) == -1 and b"FIRST_ORDER" in L.ase_last_error()
     w.params.df_source = 1
     assert call(w.params, 384, ws, nb) == -1 and b"threads_wide" in L.ase_last_error()
+    assert call(w.params, 1024 | ase.WIDE_STEP, ws, nb) == -1 and b"threads_wide" in L.ase_last_error()
+    assert call(w.params, 256 | (ase.WIDE_STEP << 1), ws, nb) == -1 and b"threads_wide" in L.ase_last_error()
     assert call(w.params, 256, None, nb) == -6
     assert call(w.params, 256, ws, nb - 8) == -6

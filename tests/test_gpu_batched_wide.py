@@ -13,6 +13,13 @@ from paper_2410_05489_amd import workloads as WL
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
+WS = ase.WIDE_STEP   # or'ed into wide_threads: one launch per step
+
+
+def _tile(wide_threads, order):
+    """Tile length of the wide form for these lanes (and form) and order."""
+    halo = 3 if wide_threads & WS else 1
+    return (wide_threads & ~WS) - halo * (order + 1)
 
 
 def _outputs(sim, hist=None, status=None):
@@ -47,7 +54,9 @@ def _pair(b, nsteps, min_cells, wide_threads=256, nbins=4, threads=256, t_end=0.
     return res
 
 
-@pytest.mark.parametrize("order,wide_threads", [(9, 256), (9, 512), (5, 256), (3, 512), (7, 256)])
+@pytest.mark.parametrize("order,wide_threads", [(9, 256), (9, 512), (5, 256), (3, 512), (7, 256),
+                                                (9, 256 | WS), (9, 512 | WS), (5, 256 | WS), (3, 512 | WS),
+                                                (7, 256 | WS)])
 def test_wide_equals_persistent_mixed_boundaries(order, wide_threads):
     """Periodic, transmissive and reflective instances of 16..3000 cells:
     those of 600 cells and more take the wide form (several tiles each,
@@ -59,13 +68,14 @@ def test_wide_equals_persistent_mixed_boundaries(order, wide_threads):
     assert np.all(p["dt_hist"] > 0.0)
 
 
-def test_wide_equals_persistent_every_split():
+@pytest.mark.parametrize("wide_threads", [256, 256 | WS])
+def test_wide_equals_persistent_every_split(wide_threads):
     """No instance wide (no tile launches), some, and all of them: the same
     bits as the persistent launch."""
     b = WL.batched_riemann(ninst=10, nmin=250, nmax=2000, order=9, seed=8, nsteps=8)
     ref = None
     for min_cells in (10**6, 1200, 1):
-        sim = ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=min_cells)
+        sim = ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=min_cells, wide_threads=wide_threads)
         print(f"min_cells={min_cells} nwide={sim.wide['nwide']} ntiles={sim.wide['ntiles']}", flush=True)
         hist = torch.zeros((b.nsteps, b.ninst), dtype=torch.float64, device=DEV)
         sim.run(b.nsteps, 0.0, hist)
@@ -78,27 +88,32 @@ def test_wide_equals_persistent_every_split():
         _assert_same(ref, out, min_cells)
 
 
-def test_wide_t_end_and_repeated_calls():
+@pytest.mark.parametrize("wide_threads,calls", [(256, (30, 30)), (256 | WS, (30, 30)), (256 | WS, (7, 4, 1, 48)),
+                                                 (512 | WS, (1, 1, 13, 45))])
+def test_wide_t_end_and_repeated_calls(wide_threads, calls):
     """Instances stop at t_end at different steps (dt_hist 0 from there on);
-    a second call continues from the first call's state and time."""
-    b = WL.batched_riemann(ninst=8, nmin=300, nmax=1500, order=9, seed=13, nsteps=60)
+    each call continues from the previous call's state and time (odd and
+    even step counts: the one-launch-per-step form alternates two buffers)."""
+    b = WL.batched_riemann(ninst=8, nmin=300, nmax=1500, order=9, seed=13, nsteps=sum(calls))
     t_end = 0.002
     sims, hists = [], []
     for wide in (0, 500):
-        sim = ase.BatchedSimulation(b, DEV, nbins=2, wide_min_cells=wide)
-        h1 = torch.full((30, b.ninst), -1.0, dtype=torch.float64, device=DEV)
-        h2 = torch.full((30, b.ninst), -1.0, dtype=torch.float64, device=DEV)
-        sim.run(30, t_end, h1)
-        sim.run(30, t_end, h2)
+        sim = ase.BatchedSimulation(b, DEV, nbins=2, wide_min_cells=wide, wide_threads=wide_threads)
+        hs = []
+        for n in calls:
+            h = torch.full((n, b.ninst), -1.0, dtype=torch.float64, device=DEV)
+            sim.run(n, t_end, h)
+            hs.append(h)
         sims.append(_outputs(sim))
-        hists.append(np.concatenate([h1.cpu().numpy(), h2.cpu().numpy()]))
+        hists.append(np.concatenate([h.cpu().numpy() for h in hs]))
     _assert_same(sims[0], sims[1], "t_end")
     assert np.array_equal(hists[0], hists[1])
     assert np.all(sims[1]["t"] <= t_end + 1e-14) and np.any(np.abs(sims[1]["t"] - t_end) < 1e-14)
     assert np.any(hists[1] == 0.0) and np.all(hists[1] >= 0.0)
 
 
-def test_wide_dt_replay_stops_where_the_replay_ends():
+@pytest.mark.parametrize("wide_threads", [256, 256 | WS])
+def test_wide_dt_replay_stops_where_the_replay_ends(wide_threads):
     """Replayed time steps, with a zero entry that stops one wide instance
     part-way: the same bits as the persistent launch."""
     b = WL.batched_riemann(ninst=6, nmin=400, nmax=1600, order=9, seed=17, nsteps=10)
@@ -109,18 +124,19 @@ def test_wide_dt_replay_stops_where_the_replay_ends():
     replay = rec.clone()
     k = int(np.argmax(b.ncells))
     replay[4:, k] = 0.0
-    p, w = _pair(b, b.nsteps, 400, nbins=2, dt_replay=replay)
+    p, w = _pair(b, b.nsteps, 400, wide_threads, nbins=2, dt_replay=replay)
     _assert_same(p, w, "replay")
     assert np.all(w["dt_hist"][4:, k] == 0.0) and np.all(w["dt_hist"][:4, k] > 0.0)
 
 
-def test_wide_status_on_the_full_batch():
+@pytest.mark.parametrize("wide_threads", [256, 256 | WS])
+def test_wide_status_on_the_full_batch(wide_threads):
     """The 256-instance batch (64..4096 cells, order 9, 100 steps) with a
     status array, instances of 2048 cells and more in the wide form: U,
     strengths, times, time steps and status flags all equal the persistent
     launch's, including those of the wide instances the method loses."""
     b = WL.batched_riemann(nsteps=100)
-    p, w = _pair(b, b.nsteps, 2048, nbins=256, status=True)
+    p, w = _pair(b, b.nsteps, 2048, wide_threads, nbins=256, status=True)
     _assert_same(p, w, "status")
     st = w["status"]
     assert np.all(st >= 0)
@@ -129,12 +145,12 @@ def test_wide_status_on_the_full_batch():
     assert len(lost_wide) > 0
 
 
-@pytest.mark.parametrize("order,wide_threads", [(9, 256), (5, 512)])
+@pytest.mark.parametrize("order,wide_threads", [(9, 256), (5, 512), (9, 256 | WS), (5, 512 | WS), (3, 256 | WS)])
 def test_wide_tile_edges(order, wide_threads):
     """Cell counts at the tile edges (one full tile, one cell more, one short
     of two tiles, two, two and one cell) under each boundary kind, beside
     small persistent instances: the persistent launch's bits."""
-    T = wide_threads - order - 1
+    T = _tile(wide_threads, order)
     sizes = [T, T + 1, 2 * T - 1, 2 * T, 2 * T + 1]
     sizes = [n for n in sizes for _ in range(3)] + [20, 100, 150]
     b = WL.batched_mixed(order=order, seed=41, nsteps=6, sizes=sizes)
@@ -186,7 +202,8 @@ def test_wide_full_size_against_the_oracle():
                 print(f"instance {k} ({n} cells) leaves the physical states in step 1 on both sides", flush=True)
 
 
-def test_wide_calls_on_two_streams_at_once():
+@pytest.mark.parametrize("wide_threads", [256, 256 | WS])
+def test_wide_calls_on_two_streams_at_once(wide_threads):
     """Two batches stepped in the wide form on two streams at the same time
     (each caller stream gets its own second stream from the library): each
     ends with the bits of its run alone on the default stream."""
@@ -194,11 +211,11 @@ def test_wide_calls_on_two_streams_at_once():
     b2 = WL.batched_riemann(ninst=12, nmin=300, nmax=3000, order=9, seed=52, nsteps=20)
     alone = []
     for b in (b1, b2):
-        sim = ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=600)
+        sim = ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=600, wide_threads=wide_threads)
         sim.run(b.nsteps)
         alone.append(_outputs(sim))
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
-    sims = [ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=600) for b in (b1, b2)]
+    sims = [ase.BatchedSimulation(b, DEV, nbins=3, wide_min_cells=600, wide_threads=wide_threads) for b in (b1, b2)]
     torch.cuda.synchronize()
     for _ in range(4):   # interleaved calls of 5 steps each
         for sim, st in zip(sims, (s1, s2)):
