@@ -361,8 +361,9 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
  * Plan and step call take the same value.
  *
  * ase_batched_plan_wide: HOST arrays.  Instances with ncells >= min_cells
- * and at least one full tile (min_cells <= 0: none) are cut into tiles of
- * that length: tile j of instance k starts at
+ * (min_cells <= 0: none) and, in the per-stage form, at least one full tile
+ * are cut into tiles of that length (the last one ragged; in the per-step
+ * form an instance shorter than a tile is one tile): tile j of instance k starts at
  * interior cell tile_i0[j]; tile_inst[j] = k; the tiles of k are
  * inst_tile0[k] .. inst_tile0[k] + inst_ntiles[k] - 1 (inst_tile0 -1 and
  * inst_ntiles 0 for the others).  The others are packed into nbins bins as

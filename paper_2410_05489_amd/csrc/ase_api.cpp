@@ -784,8 +784,10 @@ int ase_batched_plan_wide(int32_t ninst, const int32_t *ncells, int32_t min_cell
         return fail(ASE_ERR_ARG, "threads_wide must be 256 or 512, optionally with ASE_WIDE_STEP");
     const int T = (threads_wide & ASE_WIDE_STEP) ? wide_step_tile_cells(nt_lanes, (order - 1) / 2)
                                                  : wide_tile_cells(nt_lanes, (order - 1) / 2);
-    // an instance takes the wide form from one full tile up
-    auto wide = [&](int k) { return min_cells > 0 && ncells[k] >= min_cells && ncells[k] >= T; };
+    // an instance takes the per-stage wide form from one full tile up, the
+    // per-step form at any length
+    const int tmin = (threads_wide & ASE_WIDE_STEP) ? 1 : T;
+    auto wide = [&](int k) { return min_cells > 0 && ncells[k] >= min_cells && ncells[k] >= tmin; };
     std::vector<int> small;
     long long nt = 0;
     for (int k = 0; k < ninst; ++k) {

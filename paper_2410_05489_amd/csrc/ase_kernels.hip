@@ -1493,7 +1493,9 @@ __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
 // stage); on a periodic instance the window simply wraps round, and a tile
 // computes the wrapped cells itself from the same values the tile owning
 // them uses.  Cells of the window whose inputs reach beyond it are computed
-// from garbage and never used.  The state and the instance times alternate
+// from garbage and never used.  An instance shorter than a tile is one tile
+// whose window holds all of it and its ghost cells (periodic and wall
+// instances have at least ng cells, as everywhere).  The state and the instance times alternate
 // between two buffers from step to step (neighbouring tiles read the halo of
 // the step's input while others write the output), arranged so that the
 // call's last step writes U and t; the per-tile signal-speed maxima
@@ -1566,8 +1568,10 @@ __device__ __forceinline__ void step_sigma(Lds1D<R, T> &L, const double (&W)[3],
     if (tid + 1 < UX) L.sS[tid] = sigma_point(qa, qb);
 }
 
-// Bounded to five waves per SIMD (88 registers, no spills; unbounded it takes
-// 117 and runs four, 5 % slower; six spill).
+// Bounded to five waves per SIMD (83 registers, no spills).  The three
+// stages are unrolled: as a loop, the constants and branch masks the stage
+// code keeps in scalar registers across it spilled 109 of them into vector
+// lanes, and the step ran 5 % slower.
 template <int R, int NT>
 __global__ void __launch_bounds__(NT, 5) k_batched_wide_step(WideArgs a)
 {
@@ -1584,7 +1588,7 @@ __global__ void __launch_bounds__(NT, 5) k_batched_wide_step(WideArgs a)
     const int N = a.ncells[k], ng = a.ng;
     const long long off = a.offsets[k], P = a.total;
     const int t0 = a.inst_tile0[k], nt = a.inst_ntiles[k];
-    if (N < TS || off < 0 || off + N + 2LL * ng > P || i0 < 0 || i0 >= N || t0 < 0 || nt < 1 ||
+    if (N < 1 || off < 0 || off + N + 2LL * ng > P || i0 < 0 || i0 >= N || t0 < 0 || nt < 1 ||
         t0 + nt > a.ntiles || b < t0 || b >= t0 + nt || a.nsteps < 1)
         return;
     const bool first = b == t0;
@@ -1688,7 +1692,7 @@ __global__ void __launch_bounds__(NT, 5) k_batched_wide_step(WideArgs a)
     tl.wl = tl.wr = nullptr; tl.level = nullptr;
     tl.plane = P; tl.nx = 1 << 30; tl.ng = ng; tl.NX = 1 << 30; tl.nfaces = 1 << 30;
     tl.inv_dx = inv_dx; tl.dt = dt;
-#pragma unroll 1
+#pragma unroll
     for (int stg = 1; stg <= 3; ++stg) {
         if (stg > 1) {
             // ghost cells of the new stage values again, then the strengths

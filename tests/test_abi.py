@@ -151,6 +151,10 @@ def test_wide_plan_covers_each_large_instance_once(order, threads):
     nc[0], nc[1] = 4096, T   # one tile exactly
     start, lst, ti, t0, it0, itn = ase.batched_plan_wide(nc, 1500, order, threads, 7)
     wide = (nc >= 1500) & (nc >= T)
+    if threads & ase.WIDE_STEP:
+        # the per-step form tiles an instance of any length
+        _, lst1, ti1, _, it01, itn1 = ase.batched_plan_wide(nc, 1, order, threads, 7)
+        assert len(lst1) == 0 and np.all(it01 >= 0) and np.all(itn1 == -(-nc // T))
     assert sorted(lst.tolist()) == sorted(np.flatnonzero(~wide).tolist())
     assert start[0] == 0 and np.all(np.diff(start) >= 0) and start[-1] == len(lst)
     assert len(ti) == int(sum(-(-int(n) // T) for n in nc[wide]))

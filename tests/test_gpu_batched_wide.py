@@ -158,6 +158,21 @@ def test_wide_tile_edges(order, wide_threads):
     _assert_same(p, w, "edges")
 
 
+@pytest.mark.parametrize("order,wide_threads", [(9, 256 | WS), (5, 512 | WS), (3, 256 | WS)])
+def test_wide_step_tiles_every_instance(order, wide_threads):
+    """The per-step form with every instance tiled (min_cells 1): instances
+    from ng cells (one tile whose window holds the whole instance and its
+    ghost cells) to several tiles, under each boundary kind, over an odd
+    step count: the persistent launch's bits."""
+    ng = (order + 1) // 2
+    T = _tile(wide_threads, order)
+    sizes = [ng, ng + 1, 16, 40, T - 1, T, T + 1, 3 * T + 7]
+    sizes = [n for n in sizes for _ in range(3)]
+    b = WL.batched_mixed(order=order, seed=47, nsteps=7, sizes=sizes)
+    p, w = _pair(b, b.nsteps, 1, wide_threads, nbins=3)
+    _assert_same(p, w, "every instance tiled")
+
+
 def test_wide_full_size_against_the_oracle():
     """The 256-instance batch, 100 steps, instances of 768 cells and more in
     the wide form: the six largest instances the method keeps against the
