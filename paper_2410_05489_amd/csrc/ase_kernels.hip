@@ -1791,7 +1791,7 @@ struct AdjTile {
     double inv_dx;
 };
 
-template <int R, int T, int NT>
+template <int R, int T, int NT, bool UNROLL_V = false>
 __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const MethodConst &mc, LdsAdj<R, T> &L)
 {
     using LA = LdsAdj<R, T>;
@@ -1896,8 +1896,7 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
     __syncthreads();
 
     const bool first = i0 == 0, last = i0 + T >= a.N;
-#pragma unroll 1
-    for (int v = 0; v < 3; ++v) {
+    auto var_pass = [&](int v) {
         // this lane's first gather cell: its stage-combination terms, loaded
         // now and used after the tap phase
         double pa0 = 0.0, pa1 = 0.0, pa2 = 0.0;
@@ -1957,6 +1956,16 @@ __device__ __forceinline__ void adjoint1d_tile(const AdjTile &a, int i0, const M
             a.out[e] = G;
         }
         __syncthreads();
+    };
+    if constexpr (UNROLL_V) {
+        // straight-line: the tap phase's constants and branch masks are
+        // formed where they are used instead of living in scalar registers
+        // across a loop (which spilled them into vector lanes)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) var_pass(v);
+    } else {
+#pragma unroll 1
+        for (int v = 0; v < 3; ++v) var_pass(v);
     }
 }
 
@@ -2311,7 +2320,7 @@ __global__ void __launch_bounds__(NT, 4) k_adjoint_wide(AdjWideArgs a)
         adj_fetch<R, T, NT>(t, i0, w);
         adj_stage_window<R, T, NT>(w, L);
         __syncthreads();
-        adjoint1d_tile<R, T, NT>(t, i0, a.mc, L);   // ends with a barrier
+        adjoint1d_tile<R, T, NT, true>(t, i0, a.mc, L);   // ends with a barrier
     }
     if (local) {
         const int v = threadIdx.x >> 1, side = threadIdx.x & 1;
