@@ -69,15 +69,17 @@ def test_wide_reverse_equals_persistent_mixed_boundaries(order, adj_threads, wid
     assert np.array_equal(a, w, equal_nan=True)
 
 
-def test_wide_autograd_gradient_equals_persistent():
-    """The autograd wrapper with the wide forward and the wide reverse sweep
-    (overlapped tape recomputation, checkpoints every 3 steps) gives the
-    persistent wrapper's forward state and gradient bit for bit."""
+@pytest.mark.parametrize("wide_threads", [256, 256 | ase.WIDE_STEP])
+def test_wide_autograd_gradient_equals_persistent(wide_threads):
+    """The autograd wrapper with the wide forward (one launch per stage or
+    per step) and the wide reverse sweep (overlapped tape recomputation,
+    checkpoints every 3 steps) gives the persistent wrapper's forward state
+    and gradient bit for bit."""
     b = WL.batched_riemann(ninst=14, nmin=40, nmax=3000, order=9, seed=21, nsteps=11)
     outs = []
     for wide in (0, 800):
         run = A.BatchedAdjoint(b, DEV, nbins=5, every=3, adj_threads=512, wide_min_cells=wide,
-                               adj_wide_min_cells=wide)
+                               wide_threads=wide_threads, adj_wide_min_cells=wide)
         U0 = torch.tensor(b.U, device=DEV, requires_grad=True)
         UN = run.run(U0, b.nsteps)
         run.pressure(UN).sum().backward()
