@@ -1495,11 +1495,11 @@ __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
 // them uses.  Cells of the window whose inputs reach beyond it are computed
 // from garbage and never used.  An instance shorter than a tile is one tile
 // whose window holds all of it and its ghost cells (periodic and wall
-// instances have at least ng cells, as everywhere).  The state and the instance times alternate
-// between two buffers from step to step (neighbouring tiles read the halo of
-// the step's input while others write the output), arranged so that the
-// call's last step writes U and t; the per-tile signal-speed maxima
-// alternate likewise.  Every output equals the per-stage form's and the
+// instances have at least ng cells, as everywhere).  The state and the
+// instance times alternate between two buffers from step to step
+// (neighbouring tiles read the halo of the step's input while others write
+// the output), arranged so that the call's last step writes U and t; the
+// per-tile signal-speed maxima alternate likewise.  Every output equals the per-stage form's and the
 // persistent launch's bit for bit: each cell value is formed by the same
 // operations on the same operands.
 // ---------------------------------------------------------------------------
