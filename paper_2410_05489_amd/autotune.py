@@ -45,7 +45,9 @@ def _arch() -> str:
 
 
 def batched_key(batch) -> str:
-    return f"{_arch()}/batched2/r{batch.params.order}/n{batch.ninst}/c{batch.total}/s{batch.params.df_source}"
+    # the version field changes with the candidate forms (3: the per-step
+    # wide form), so that a cache tuned without them is not reused
+    return f"{_arch()}/batched3/r{batch.params.order}/n{batch.ninst}/c{batch.total}/s{batch.params.df_source}"
 
 
 def _load() -> Dict[str, dict]:
