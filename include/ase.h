@@ -358,7 +358,8 @@ int ase_step_batched(const ase_params_t *p, int32_t bc, const int32_t *bc_inst, 
  * running the three stages of the step in on-chip memory over a window that
  * reaches three stages' stencils beyond its cells; tiles are then
  * threads_wide - 3 (order + 1) cells long instead of threads_wide - order - 1.
- * Plan and step call take the same value.
+ * Plan and step call take the same value: the step's kernels skip an
+ * instance whose tiles do not fit their tile length (it does not advance).
  *
  * ase_batched_plan_wide: HOST arrays.  Instances with ncells >= min_cells
  * (min_cells <= 0: none) and, in the per-stage form, at least one full tile

@@ -1307,6 +1307,17 @@ struct WideArgs {
     MethodConst mc;
 };
 
+// The instance's tiles are those of a plan for this tile length T: tile b is
+// number b - t0 at j T, the last one at (nt - 1) T, and they cover the N
+// cells exactly once.  Every tile of an instance takes the same decision
+// from the last tile's entry (a plan for another length is skipped as a
+// whole: its instances do not advance).
+__device__ __forceinline__ bool wide_tiles_fit(const WideArgs &a, int b, int i0, int t0, int nt, int N, int T)
+{
+    const long long last = (long long)(nt - 1) * T;
+    return a.tile_i0[t0 + nt - 1] == last && last < N && N <= last + T && i0 == (long long)(b - t0) * T;
+}
+
 template <int NT>
 __device__ __forceinline__ double block_max(double v, double *red)
 {
@@ -1390,7 +1401,7 @@ __global__ void __launch_bounds__(NT) k_batched_wide(WideArgs a)
     const long long off = a.offsets[k], P = a.total;
     const int t0 = a.inst_tile0[k], nt = a.inst_ntiles[k];
     if (N < T || off < 0 || off + N + 2LL * ng > P || i0 < 0 || i0 >= N || t0 < 0 || nt < 1 ||
-        t0 + nt > a.ntiles || b < t0 || b >= t0 + nt)
+        t0 + nt > a.ntiles || b < t0 || b >= t0 + nt || !wide_tiles_fit(a, b, i0, t0, nt, N, T))
         return;
     const bool first = b == t0;
     const double inv_dx = 1.0 / a.dx[k];
@@ -1589,7 +1600,7 @@ __global__ void __launch_bounds__(NT, 5) k_batched_wide_step(WideArgs a)
     const long long off = a.offsets[k], P = a.total;
     const int t0 = a.inst_tile0[k], nt = a.inst_ntiles[k];
     if (N < 1 || off < 0 || off + N + 2LL * ng > P || i0 < 0 || i0 >= N || t0 < 0 || nt < 1 ||
-        t0 + nt > a.ntiles || b < t0 || b >= t0 + nt || a.nsteps < 1)
+        t0 + nt > a.ntiles || b < t0 || b >= t0 + nt || a.nsteps < 1 || !wide_tiles_fit(a, b, i0, t0, nt, N, TS))
         return;
     const bool first = b == t0;
     const double inv_dx = 1.0 / a.dx[k];

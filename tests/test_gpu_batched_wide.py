@@ -173,6 +173,31 @@ def test_wide_step_tiles_every_instance(order, wide_threads):
     _assert_same(p, w, "every instance tiled")
 
 
+@pytest.mark.parametrize("plan_threads,call_threads", [(256, 256 | WS), (256 | WS, 256), (512, 256)])
+def test_wide_plan_for_another_tile_length_is_skipped(plan_threads, call_threads):
+    """A step call whose tile length differs from the plan's leaves the
+    tiled instances as they were (no partial updates), while the binned
+    instances advance as in the persistent launch."""
+    b = WL.batched_mixed(ninst=9, nmin=16, nmax=2500, order=9, seed=53, nsteps=5)
+    sim = ase.BatchedSimulation(b, DEV, nbins=2, wide_min_cells=600, wide_threads=plan_threads)
+    tiled = sim.wide["inst_ntiles"].cpu().numpy() > 0
+    assert tiled.any() and not tiled.all()
+    U0 = sim.U.cpu().numpy().copy()
+    sim.wide = dict(sim.wide, threads=call_threads)
+    print(f"plan {plan_threads} call {call_threads} tiled {np.flatnonzero(tiled).tolist()}", flush=True)
+    sim.run(b.nsteps)
+    ref = ase.BatchedSimulation(b, DEV, nbins=2)
+    ref.run(b.nsteps)
+    out, exp = _outputs(sim), _outputs(ref)
+    for k in range(b.ninst):
+        o, n = int(b.offsets[k]), int(b.ncells[k])
+        cells = slice(o + b.ng, o + b.ng + n)
+        if tiled[k]:
+            assert np.array_equal(out["U"][:, cells], U0[:, cells]) and out["t"][k] == 0.0, k
+        else:
+            assert np.array_equal(out["U"][:, cells], exp["U"][:, cells]) and out["t"][k] == exp["t"][k], k
+
+
 def test_wide_full_size_against_the_oracle():
     """The 256-instance batch, 100 steps, instances of 768 cells and more in
     the wide form: the six largest instances the method keeps against the
