@@ -490,13 +490,13 @@ def measure_adjoint(nsteps=100, every=10, reps=3):
 
 def cpu_baseline(w):
     """The oracle as it stands (OpenMP over grid lines) on the host's
-    threads: three steps of the same grid from its initial state; and one
-    step on a single thread."""
+    threads: eight steps of the same grid from its initial state (about 3 s
+    on 16 threads); and two steps on a single thread (about 9 s)."""
     from oracle import oracle as O
     n = w.grid.ncells()
     nt = host_threads()
     rates = {}
-    for threads, k in ((nt, 3), (1, 1)):
+    for threads, k in ((nt, 8), (1, 2)):
         used = O.set_threads(threads)
         U = w.U.copy()
         sx, sy = O.sigma_init(w.grid, w.params, U)
@@ -508,7 +508,7 @@ def cpu_baseline(w):
     v1, _, k1, el1 = rates[1]
     return {"value": v, "unit": "Mcell-updates/s", "cores": used, "kind": "oracle",
             "sample": f"{k} steps of {w.name} ({n} cells) from its initial state, C oracle on {used} threads, "
-                      f"{el:.1f} s; 1 step on 1 thread, {el1:.1f} s",
+                      f"{el:.1f} s; {k1} steps on 1 thread, {el1:.1f} s",
             "single_thread": v1, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
