@@ -173,6 +173,22 @@ def test_wide_step_tiles_every_instance(order, wide_threads):
     _assert_same(p, w, "every instance tiled")
 
 
+@pytest.mark.parametrize("wide_threads", [256, 256 | WS])
+def test_wide_dt_cap(wide_threads):
+    """A cap on the time step that binds for some instances and steps (the
+    CFL step of the others is smaller): the persistent launch's bits."""
+    b = WL.batched_mixed(ninst=9, nmin=300, nmax=2500, order=9, seed=59, nsteps=9)
+    sim = ase.BatchedSimulation(b, DEV, nbins=2)
+    h = torch.zeros((1, b.ninst), dtype=torch.float64, device=DEV)
+    sim.run(1, dt_hist=h)
+    torch.cuda.synchronize()
+    b.params.dt_cap = float(np.median(h.cpu().numpy()))
+    p, w = _pair(b, b.nsteps, 500, wide_threads, nbins=2)
+    _assert_same(p, w, "dt_cap")
+    capped = np.isclose(p["dt_hist"], b.params.dt_cap, rtol=0, atol=0)
+    assert capped.any() and not capped.all()
+
+
 @pytest.mark.parametrize("plan_threads,call_threads", [(256, 256 | WS), (256 | WS, 256), (512, 256)])
 def test_wide_plan_for_another_tile_length_is_skipped(plan_threads, call_threads):
     """A step call whose tile length differs from the plan's leaves the
